@@ -1,0 +1,183 @@
+/*
+ * gtucker.h -- C ABI of the groupwise Tucker channel-compression library for MI355X (gfx950).
+ *
+ * The library fits the groupwise Tucker model of OFDM massive-MIMO channel tensors and
+ * evaluates per-subcarrier SINR directly from the compressed form (Zhang, Zhu & Zhang,
+ * "Compressing MIMO Channel Submatrices with Tucker Decomposition", Sections 3.2 and 3.3).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Complex data is interleaved (re, im) single precision ("c64", 8 bytes per element),
+ *    the layout of a torch.complex64 tensor.  Real outputs are float32.
+ *  - Every data pointer is device memory owned by the caller.  The library never allocates
+ *    device memory: scratch lives in a caller-allocated workspace whose size comes from
+ *    gt_plan_workspace_bytes and which gt_workspace_init must fill once before use.
+ *  - Calls are asynchronous on the given stream (a hipStream_t passed as void*; NULL is
+ *    the default stream).  Host-detectable errors return synchronously and launch nothing.
+ *    Numerical conditions found on the device are OR-ed into a per-channel int32 status
+ *    word (GT_DEV_*); the caller clears it and reads it after synchronising.
+ *  - No C++ exception crosses this boundary.  All functions are thread-compatible: a plan
+ *    is immutable after creation and may be shared; a workspace must not be used by two
+ *    calls that run concurrently.
+ *
+ * Per-channel layouts (row-major; each channel's block starts at the offsets given by
+ * gt_plan_offsets, in elements):
+ *    X     [nsc][nr][nt]      channel tensor: H_s is the s-th nr x nt slice
+ *    A     [nr][m]            mode-1 factor, orthonormal columns
+ *    B     [nt][n]            mode-2 factor in matrix form: H_s ~ A Ht_s B^H
+ *    C     [nsc][p]           row s of the group factor C_g of the group holding s;
+ *                             entries q >= p_g are zero
+ *    G     [groups][p][m][n]  core of each group, slice q is G_g[q]; slices q >= p_g zero
+ *    Ht    [nsc][m][n]        compressed channel Ht_s = sum_q C[s,q] G_g[q]
+ *    SINR  [n_snr][total_subcarriers][ns_max] float32, linear; the subcarriers of channel c
+ *          start at offsets.sc; streams r >= ns of that channel are written as 0
+ *  Groups: g(s) = s / group_size; the last group may be short; p_g = min(p, group size).
+ */
+#ifndef GTUCKER_H
+#define GTUCKER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GT_OK = 0,
+  GT_ERR_ARG = 1,         /* null pointer, bad enum, bad count */
+  GT_ERR_SHAPE = 2,       /* non-positive or unsupported dimension */
+  GT_ERR_RANK = 3,        /* rank larger than its dimension, ns > min(m, n), p > group size */
+  GT_ERR_WORKSPACE = 4,   /* workspace missing or smaller than gt_plan_workspace_bytes */
+  GT_ERR_UNSUPPORTED = 5, /* operation or option not provided */
+  GT_ERR_HIP = 6,         /* a HIP runtime call or kernel launch failed */
+  GT_ERR_NO_DEVICE = 7    /* no usable GPU */
+} gt_status;
+
+/* device status bits, OR-ed per channel */
+#define GT_DEV_NONFINITE 1u      /* a non-finite value entered an eigensolver or the SINR chain */
+#define GT_DEV_EIG_SWEEPS 2u     /* an eigensolver stopped at its sweep cap before converging */
+#define GT_DEV_CHOLESKY 4u       /* the MMSE covariance lost positive definiteness */
+#define GT_DEV_ZERO_STREAM 8u    /* sigma_r <= 1e-3 sigma_1 (FP32) for a requested stream: SINR_r := 0 */
+
+typedef enum { GT_C64 = 0 } gt_dtype;
+
+/* Contraction precision of the fit's mode-n products.  Only GT_TTM_FP32 is provided. */
+typedef enum { GT_TTM_FP32 = 0, GT_TTM_BF16 = 1, GT_TTM_FP16 = 2, GT_TTM_SPLIT_BF16 = 3 } gt_ttm_prec;
+
+#define GT_FIT_WARM_START 1u  /* A, B, C are read as the starting factors; the HOSVD step is skipped */
+
+/* One channel tensor and its compression shape (paper notation M=nr, N=nt, (m, n, p)). */
+typedef struct {
+  int32_t nr, nt, nsc;   /* receive antennas, transmit antennas, subcarriers */
+  int32_t group_size;    /* subcarriers per group */
+  int32_t m, n, p;       /* Tucker ranks: 1<=m<=nr, 1<=n<=nt, 1<=p<=group_size */
+  int32_t ns;            /* SVD-precoded streams evaluated by the SINR calls, 1<=ns<=min(m,n) */
+} gt_channel_desc;
+
+/* Element offsets of one channel inside packed batch buffers. */
+typedef struct {
+  int64_t x, a, b, c, g, ht;  /* complex elements */
+  int64_t sc;                 /* first subcarrier of the channel in the SINR layout */
+  int32_t n_groups;
+  int32_t reserved;
+} gt_offsets;
+
+typedef struct {
+  int32_t iters;       /* alternating sweeps S, >= 0 */
+  int32_t ttm_prec;    /* gt_ttm_prec */
+  int32_t eig_fp64;    /* 1: Gram eigensolves in FP64 */
+  uint32_t flags;      /* GT_FIT_* */
+} gt_fit_options;
+
+typedef struct gt_plan gt_plan;
+
+/* Validates the descriptors and builds an immutable host plan (sizes, offsets, device
+ * tables, workspace layout).  Errors: GT_ERR_ARG (null, n_channels<1), GT_ERR_SHAPE (a
+ * dimension out of range: nr<=16, nt<=256, group_size<=32, nsc>=1), GT_ERR_RANK (rank or
+ * ns out of range), GT_ERR_UNSUPPORTED (an option not provided).  On success *out owns the
+ * plan until gt_plan_destroy.  Pure host code: needs no GPU. */
+gt_status gt_plan_create(const gt_channel_desc* descs, int32_t n_channels,
+                         const gt_fit_options* opt, gt_plan** out);
+void gt_plan_destroy(gt_plan* plan);
+
+/* Offsets of channel `channel` (0 <= channel < n_channels).  Pure host code. */
+gt_status gt_plan_offsets(const gt_plan* plan, int32_t channel, gt_offsets* out);
+/* Total element counts of the packed buffers (x, a, b, c, g, ht in complex elements; sc in
+ * subcarriers; n_groups summed) and the largest ns over the batch.  Pure host code. */
+gt_status gt_plan_totals(const gt_plan* plan, gt_offsets* totals, int32_t* ns_max);
+/* Workspace bytes every device call of this plan needs.  Pure host code. */
+gt_status gt_plan_workspace_bytes(const gt_plan* plan, size_t* bytes);
+
+/* Writes the plan's device tables into the workspace (an asynchronous host-to-device copy
+ * from memory the plan owns).  Call once per workspace before any other device call. */
+gt_status gt_workspace_init(const gt_plan* plan, void* ws, size_t ws_bytes, void* stream);
+
+/* Groupwise Tucker compression (Algorithm "Groupwise Tucker compression algorithm" with the
+ * HOSVD initialisation of Section 3.2; factor updates of equations "update A/B/C"; core of
+ * equation "kernel").  Inputs: X.  Outputs: A, B, C, G.  obj_trace (device, double, may be
+ * NULL) receives per channel 1 + 3*iters values of the objective f of equation "MT_origin"
+ * after the initialisation and after each half-step, layout [n_channels][1 + 3*iters].
+ * dev_status: [n_channels] int32 device words (may be NULL).  With GT_FIT_WARM_START the
+ * initial A, B, C are read from the output buffers. */
+gt_status gt_tucker_fit(const gt_plan* plan, const void* X, void* A, void* B, void* C, void* G,
+                        double* obj_trace, int32_t* dev_status, void* ws, size_t ws_bytes,
+                        void* stream);
+
+/* Reconstruction from the compressed form (equation "compressed matrix SINR reduction" and
+ * the matrix factorisation of equation "three matrix factorization"): Ht_s = sum_q C[s,q]
+ * G_g[q] and Xhat_s = A Ht_s B^H.  Either output may be NULL. */
+gt_status gt_tucker_reconstruct(const gt_plan* plan, const void* A, const void* B, const void* C,
+                                const void* G, void* Ht, void* Xhat, void* ws, size_t ws_bytes,
+                                void* stream);
+
+/* Per-subcarrier SINR from the compressed form (Section 3.3): Ht_s from (C, G); SVD precoder
+ * (equation "precoding matrix"); covariance, MMSE filter and per-stream SINR (equations
+ * "covariance matrix", "MMSE receive filter", "s_r^ij", "SINR formula") on the m x m
+ * compressed covariance.  sigma2: host array of n_snr noise variances (1 <= n_snr <= 16).
+ * Output layout as above. */
+gt_status gt_sinr_eval(const gt_plan* plan, const void* C, const void* G, const float* sigma2,
+                       int32_t n_snr, float* sinr, int32_t* dev_status, void* ws, size_t ws_bytes,
+                       void* stream);
+
+/* The same chain on the uncompressed channel H_s (nr x nt) read from X (Section 2.2). */
+gt_status gt_sinr_eval_full(const gt_plan* plan, const void* X, const float* sigma2, int32_t n_snr,
+                            float* sinr, int32_t* dev_status, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/* Adjoint of gt_sinr_eval: given grad_sinr (dl/dSINR, same layout as the SINR output),
+ * writes grad_C and grad_G (layouts of C and G, overwritten) as dl/dRe + i dl/dIm.  The
+ * SVD and the Cholesky factor are recomputed, not stored. */
+gt_status gt_sinr_eval_backward(const gt_plan* plan, const void* C, const void* G,
+                                const float* sigma2, int32_t n_snr, const float* grad_sinr,
+                                void* grad_C, void* grad_G, int32_t* dev_status, void* ws,
+                                size_t ws_bytes, void* stream);
+
+/* Adjoint of gt_tucker_reconstruct.  grad_Ht or grad_Xhat may be NULL (treated as zero).
+ * Writes grad_A, grad_B, grad_C, grad_G (overwritten). */
+gt_status gt_tucker_reconstruct_backward(const gt_plan* plan, const void* A, const void* B,
+                                         const void* C, const void* G, const void* grad_Ht,
+                                         const void* grad_Xhat, void* grad_A, void* grad_B,
+                                         void* grad_C, void* grad_G, void* ws, size_t ws_bytes,
+                                         void* stream);
+
+/* The fit is an argmax over eigenvectors and is not differentiated: always returns
+ * GT_ERR_UNSUPPORTED. */
+gt_status gt_tucker_fit_backward(const gt_plan* plan);
+
+/* Static description of a status code. */
+const char* gt_status_string(gt_status s);
+/* Text of the last HIP error seen by this thread (empty if none). */
+const char* gt_last_error_detail(void);
+
+/* Kernel timing.  When enabled, every kernel the library launches is bracketed by HIP
+ * events on its stream; gt_profile_query synchronises those events and returns the summed
+ * duration and launch count of kernels whose name contains `name`. */
+gt_status gt_profile_enable(int32_t on);
+gt_status gt_profile_reset(void);
+gt_status gt_profile_query(const char* name, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GTUCKER_H */

@@ -1,0 +1,231 @@
+"""Python front end of libgtucker: a plan object over packed device buffers, and autograd
+wrappers.  torch supplies device memory and the stream; every step runs in the library."""
+
+from __future__ import annotations
+
+import ctypes as C
+from typing import Dict, Iterable, List, Optional, Sequence
+
+import torch
+
+from . import _binding as B
+from ._binding import ChannelDesc, FitOptions, Offsets, check, load
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _c64(t: torch.Tensor, n: int, name: str) -> torch.Tensor:
+    if t.dtype != torch.complex64:
+        raise TypeError(f"{name} must be complex64")
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return t
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """Immutable description of a batch of channels plus its device workspace.
+
+    descs: iterable of dicts with keys nr, nt, nsc, group_size, m, n, p, ns.
+    Packed buffers (1-D complex64): X, A, B, C, G, Ht with per-channel blocks at
+    `offsets(c)`; SINR output is float32 [n_snr][total_subcarriers][ns_max].
+    """
+
+    def __init__(self, descs: Iterable[dict], iters: int = 20, eig_fp64: bool = False,
+                 warm_start: bool = False, device="cuda"):
+        self.lib = load()
+        self.descs: List[dict] = [dict(d) for d in descs]
+        arr = (ChannelDesc * len(self.descs))()
+        for i, d in enumerate(self.descs):
+            arr[i] = ChannelDesc(d["nr"], d["nt"], d["nsc"], d["group_size"], d["m"], d["n"],
+                                 d["p"], d["ns"])
+        opt = FitOptions(int(iters), 0, 1 if eig_fp64 else 0,
+                         B.GT_FIT_WARM_START if warm_start else 0)
+        h = C.c_void_p()
+        check("gt_plan_create", self.lib.gt_plan_create(arr, len(self.descs), C.byref(opt),
+                                                        C.byref(h)))
+        self._h = h
+        self.iters = int(iters)
+        tot = Offsets()
+        nsm = C.c_int32()
+        check("gt_plan_totals", self.lib.gt_plan_totals(h, C.byref(tot), C.byref(nsm)))
+        self.totals = tot
+        self.ns_max = nsm.value
+        wsb = C.c_size_t()
+        check("gt_plan_workspace_bytes", self.lib.gt_plan_workspace_bytes(h, C.byref(wsb)))
+        self.ws_bytes = wsb.value
+        self.device = torch.device(device)
+        self.ws = None
+        if self.device.type == "cuda":
+            self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+            check("gt_workspace_init", self.lib.gt_workspace_init(h, _ptr(self.ws), self.ws_bytes,
+                                                                  _stream()))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                self.lib.gt_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    @property
+    def n_channels(self) -> int:
+        return len(self.descs)
+
+    def offsets(self, c: int) -> Offsets:
+        o = Offsets()
+        check("gt_plan_offsets", self.lib.gt_plan_offsets(self._h, c, C.byref(o)))
+        return o
+
+    # -- buffers ---------------------------------------------------------------------
+    def _new(self, n: int, dtype=torch.complex64) -> torch.Tensor:
+        return torch.zeros(n, dtype=dtype, device=self.device)
+
+    def empty_factors(self) -> Dict[str, torch.Tensor]:
+        t = self.totals
+        return dict(A=self._new(t.a), B=self._new(t.b), C=self._new(t.c), G=self._new(t.g))
+
+    # -- calls -----------------------------------------------------------------------
+    def fit(self, X: torch.Tensor, factors: Optional[Dict[str, torch.Tensor]] = None,
+            trace: bool = True) -> Dict[str, torch.Tensor]:
+        """Groupwise Tucker compression of every channel in X (packed)."""
+        t = self.totals
+        _c64(X, t.x, "X")
+        f = factors if factors is not None else self.empty_factors()
+        tr = (torch.zeros(self.n_channels * (1 + 3 * self.iters), dtype=torch.float64,
+                          device=self.device) if trace else None)
+        st = torch.zeros(self.n_channels, dtype=torch.int32, device=self.device)
+        check("gt_tucker_fit", self.lib.gt_tucker_fit(
+            self._h, _ptr(X), _ptr(f["A"]), _ptr(f["B"]), _ptr(f["C"]), _ptr(f["G"]), _ptr(tr),
+            _ptr(st), _ptr(self.ws), self.ws_bytes, _stream()))
+        out = dict(f)
+        out["status"] = st
+        if tr is not None:
+            out["trace"] = tr.view(self.n_channels, 1 + 3 * self.iters)
+        return out
+
+    def reconstruct(self, A, B_, C_, G, ht: bool = True, xhat: bool = True):
+        t = self.totals
+        Ht = self._new(t.ht) if ht else None
+        Xh = self._new(t.x) if xhat else None
+        check("gt_tucker_reconstruct", self.lib.gt_tucker_reconstruct(
+            self._h, _ptr(A), _ptr(B_), _ptr(C_), _ptr(G), _ptr(Ht), _ptr(Xh), _ptr(self.ws),
+            self.ws_bytes, _stream()))
+        return Ht, Xh
+
+    def _sigma2(self, sigma2: Sequence[float]):
+        s = [float(v) for v in sigma2]
+        return (C.c_float * len(s))(*s), len(s)
+
+    def sinr(self, C_, G, sigma2: Sequence[float], out: Optional[torch.Tensor] = None,
+             status: Optional[torch.Tensor] = None) -> torch.Tensor:
+        s2, k = self._sigma2(sigma2)
+        if out is None:
+            out = torch.empty((k, self.totals.sc, self.ns_max), dtype=torch.float32,
+                              device=self.device)
+        check("gt_sinr_eval", self.lib.gt_sinr_eval(
+            self._h, _ptr(C_), _ptr(G), s2, k, _ptr(out), _ptr(status), _ptr(self.ws),
+            self.ws_bytes, _stream()))
+        return out
+
+    def sinr_full(self, X, sigma2: Sequence[float], out: Optional[torch.Tensor] = None,
+                  status: Optional[torch.Tensor] = None) -> torch.Tensor:
+        s2, k = self._sigma2(sigma2)
+        if out is None:
+            out = torch.empty((k, self.totals.sc, self.ns_max), dtype=torch.float32,
+                              device=self.device)
+        check("gt_sinr_eval_full", self.lib.gt_sinr_eval_full(
+            self._h, _ptr(X), s2, k, _ptr(out), _ptr(status), _ptr(self.ws), self.ws_bytes,
+            _stream()))
+        return out
+
+    def sinr_backward(self, C_, G, sigma2, grad_sinr, status=None):
+        s2, k = self._sigma2(sigma2)
+        gC = torch.empty_like(C_)
+        gG = torch.empty_like(G)
+        gs = grad_sinr.contiguous().float()
+        check("gt_sinr_eval_backward", self.lib.gt_sinr_eval_backward(
+            self._h, _ptr(C_), _ptr(G), s2, k, _ptr(gs), _ptr(gC), _ptr(gG), _ptr(status),
+            _ptr(self.ws), self.ws_bytes, _stream()))
+        return gC, gG
+
+    def reconstruct_backward(self, A, B_, C_, G, grad_Ht=None, grad_Xhat=None):
+        gA, gB, gC, gG = (torch.empty_like(v) for v in (A, B_, C_, G))
+        check("gt_tucker_reconstruct_backward", self.lib.gt_tucker_reconstruct_backward(
+            self._h, _ptr(A), _ptr(B_), _ptr(C_), _ptr(G),
+            _ptr(grad_Ht.contiguous() if grad_Ht is not None else None),
+            _ptr(grad_Xhat.contiguous() if grad_Xhat is not None else None),
+            _ptr(gA), _ptr(gB), _ptr(gC), _ptr(gG), _ptr(self.ws), self.ws_bytes, _stream()))
+        return gA, gB, gC, gG
+
+
+# -- autograd ----------------------------------------------------------------------------
+
+class SinrFn(torch.autograd.Function):
+    """SINR of the compressed form as a differentiable function of (C, G)."""
+
+    @staticmethod
+    def forward(ctx, plan: Plan, C_, G, sigma2):
+        ctx.plan = plan
+        ctx.sigma2 = list(sigma2)
+        ctx.save_for_backward(C_, G)
+        return plan.sinr(C_.detach(), G.detach(), sigma2)
+
+    @staticmethod
+    def backward(ctx, grad):
+        C_, G = ctx.saved_tensors
+        gC, gG = ctx.plan.sinr_backward(C_.detach(), G.detach(), ctx.sigma2, grad)
+        return None, gC, gG, None
+
+
+class ReconstructFn(torch.autograd.Function):
+    """(Ht, Xhat) as a differentiable function of (A, B, C, G)."""
+
+    @staticmethod
+    def forward(ctx, plan: Plan, A, B_, C_, G):
+        ctx.plan = plan
+        ctx.save_for_backward(A, B_, C_, G)
+        Ht, Xh = plan.reconstruct(A.detach(), B_.detach(), C_.detach(), G.detach())
+        return Ht, Xh
+
+    @staticmethod
+    def backward(ctx, gHt, gX):
+        A, B_, C_, G = ctx.saved_tensors
+        gA, gB, gC, gG = ctx.plan.reconstruct_backward(A.detach(), B_.detach(), C_.detach(),
+                                                       G.detach(), gHt, gX)
+        return None, gA, gB, gC, gG
+
+
+# -- helpers -----------------------------------------------------------------------------
+
+def profile_enable(on: bool = True) -> None:
+    check("gt_profile_enable", load().gt_profile_enable(1 if on else 0))
+
+
+def profile_reset() -> None:
+    check("gt_profile_reset", load().gt_profile_reset())
+
+
+def profile_query(name: str):
+    ms = C.c_double()
+    cnt = C.c_int64()
+    check("gt_profile_query", load().gt_profile_query(name.encode(), C.byref(ms), C.byref(cnt)))
+    return ms.value, cnt.value
+
+
+def desc_from_config(cfg) -> dict:
+    return dict(nr=cfg.nr, nt=cfg.nt, nsc=cfg.nsc, group_size=cfg.group_size, m=cfg.m, n=cfg.n,
+                p=cfg.p, ns=cfg.ns)

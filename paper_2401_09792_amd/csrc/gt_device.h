@@ -1,0 +1,264 @@
+// Device-side helpers: complex arithmetic on (re, im) pairs, wave-level synchronisation and
+// reductions, and a wave-synchronous parallel Jacobi eigensolver for small Hermitian
+// matrices held in LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gt {
+
+template <typename T>
+struct Cx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// conj(a) * b
+template <typename T>
+__device__ __forceinline__ Cx<T> cmulc(Cx<T> a, Cx<T> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ void cfma(Cx<T>& acc, Cx<T> a, Cx<T> b) {  // acc += a*b
+  acc.re += a.re * b.re - a.im * b.im;
+  acc.im += a.re * b.im + a.im * b.re;
+}
+template <typename T>
+__device__ __forceinline__ void cfmac(Cx<T>& acc, Cx<T> a, Cx<T> b) {  // acc += conj(a)*b
+  acc.re += a.re * b.re + a.im * b.im;
+  acc.im += a.re * b.im - a.im * b.re;
+}
+
+__device__ __forceinline__ Cx<float> ld(const float2* p) {
+  float2 v = *p;
+  return {v.x, v.y};
+}
+__device__ __forceinline__ void st(float2* p, Cx<float> v) { *p = make_float2(v.re, v.im); }
+
+template <typename T>
+__device__ __forceinline__ T dsqrt(T x);
+template <>
+__device__ __forceinline__ float dsqrt<float>(float x) {
+  return __builtin_sqrtf(x);
+}
+template <>
+__device__ __forceinline__ double dsqrt<double>(double x) {
+  return __builtin_sqrt(x);
+}
+
+template <typename T>
+struct Num;
+template <>
+struct Num<float> {
+  static __device__ __forceinline__ float eps() { return 5.9604645e-08f; }
+  static __device__ __forceinline__ float big() { return 1.0e18f; }
+  static __device__ __forceinline__ float ninf() { return -__builtin_huge_valf(); }
+  // smallest sigma_r / sigma_1 a Gram-based FP32 SVD resolves (about sqrt(eps))
+  static __device__ __forceinline__ float zero_stream() { return 1.0e-3f; }
+};
+template <>
+struct Num<double> {
+  static __device__ __forceinline__ double eps() { return 1.1102230246251565e-16; }
+  static __device__ __forceinline__ double big() { return 1.0e150; }
+  static __device__ __forceinline__ double ninf() { return -__builtin_huge_val(); }
+  static __device__ __forceinline__ double zero_stream() { return 1.0e-6; }
+};
+
+// Orders the wave's LDS accesses: everything before is visible to every lane after.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sum over an aligned group of G lanes (G a power of two <= 64).
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ bool wave_all(bool p) { return __all(p ? 1 : 0) != 0; }
+
+// ---------------------------------------------------------------------------------------
+// Parallel cyclic Jacobi for Hermitian matrices of dimension d <= MP held in LDS.
+//
+// MP lanes (an aligned group inside one wave) cooperate on one matrix; lane r owns row r of
+// the matrix and of the eigenvector matrix.  A wave may hold 64/MP independent problems;
+// all of them follow the same rotation schedule (round-robin pairing: in step t the lanes
+// are paired so that every pair of indices meets once per sweep), which keeps the wave in
+// lockstep.  Rows and columns >= d must be zero; they stay zero.
+template <typename T, int MP>
+struct EigLds {
+  T kr[MP][MP + 1];
+  T ki[MP][MP + 1];
+  T vr[MP][MP + 1];
+  T vi[MP][MP + 1];
+  T rc[MP / 2], rsr[MP / 2], rsi[MP / 2];
+  int rp[MP / 2], rq[MP / 2];
+  T lam[MP];
+  int src[MP];
+};
+
+template <int MP>
+__device__ __forceinline__ void rr_pair(int t, int r, int& pos, int& partner) {
+  if (MP == 1) {
+    pos = 0;
+    partner = 0;
+    return;
+  }
+  constexpr int N1 = MP - 1;
+  pos = (r == 0) ? 0 : ((r - 1 - t + 2 * N1 * MP) % N1) + 1;
+  int ppos = MP - 1 - pos;
+  partner = (ppos == 0) ? 0 : ((ppos - 1 + t) % N1) + 1;
+}
+
+// Returns true if the off-diagonal part fell below eps relative to the diagonal within
+// max_sweeps sweeps.  On exit kr/ki is (nearly) diagonal and vr/vi holds the eigenvectors
+// as columns (row r in lane r).
+template <typename T, int MP>
+__device__ bool jacobi_herm(EigLds<T, MP>& L, int r, int max_sweeps) {
+  for (int j = 0; j < MP; ++j) {
+    L.vr[r][j] = (j == r) ? T(1) : T(0);
+    L.vi[r][j] = T(0);
+  }
+  wave_sync();
+  const T eps = Num<T>::eps();
+  bool conv = false;
+  for (int sw = 0; sw <= max_sweeps; ++sw) {
+    T off = 0, dg = 0;
+    for (int j = 0; j < MP; ++j) {
+      T a = L.kr[r][j], b = L.ki[r][j];
+      T v = a * a + b * b;
+      if (j == r)
+        dg += v;
+      else
+        off += v;
+    }
+    off = group_sum<MP>(off);
+    dg = group_sum<MP>(dg);
+    bool done = off <= T(4) * eps * eps * dg;
+    if (wave_all(done)) {
+      conv = true;
+      break;
+    }
+    if (sw == max_sweeps) break;
+    for (int t = 0; t < MP - 1; ++t) {
+      int pos, partner;
+      rr_pair<MP>(t, r, pos, partner);
+      const bool first = pos < MP / 2;
+      if (first) {
+        T a = L.kr[r][r], b = L.kr[partner][partner];
+        T cre = L.kr[r][partner], cim = L.ki[r][partner];
+        T ac = dsqrt(cre * cre + cim * cim);
+        T cs = 1, sre = 0, sim = 0;
+        if (ac > T(0) && ac > eps * T(0.5) * (__builtin_fabs(a) + __builtin_fabs(b))) {
+          T z = (b - a) / (T(2) * ac);
+          T az = __builtin_fabs(z);
+          T tt = (az > Num<T>::big()) ? T(0.5) / az : T(1) / (az + dsqrt(T(1) + az * az));
+          if (z >= T(0)) tt = -tt;
+          cs = T(1) / dsqrt(T(1) + tt * tt);
+          T sn = tt * cs;
+          sre = sn * cre / ac;
+          sim = sn * cim / ac;
+        }
+        L.rc[pos] = cs;
+        L.rsr[pos] = sre;
+        L.rsi[pos] = sim;
+        L.rp[pos] = r;
+        L.rq[pos] = partner;
+      }
+      wave_sync();
+      const int slot = first ? pos : (MP - 1 - pos);
+      const T csr = L.rc[slot];
+      const T srr = L.rsr[slot], sri = L.rsi[slot];
+      for (int k = 0; k < MP / 2; ++k) {
+        const int p = L.rp[k], q = L.rq[k];
+        const T cs = L.rc[k];
+        const Cx<T> s{L.rsr[k], L.rsi[k]};
+        Cx<T> x{L.kr[r][p], L.ki[r][p]}, y{L.kr[r][q], L.ki[r][q]};
+        Cx<T> xp{L.kr[partner][p], L.ki[partner][p]}, yp{L.kr[partner][q], L.ki[partner][q]};
+        Cx<T> Rx, Ry;
+        if (first) {  // row r = p of its pair: cs*row_p + s*row_q
+          Cx<T> sv{srr, sri};
+          Cx<T> a1 = cmul(sv, xp), a2 = cmul(sv, yp);
+          Rx = {csr * x.re + a1.re, csr * x.im + a1.im};
+          Ry = {csr * y.re + a2.re, csr * y.im + a2.im};
+        } else {      // row r = q of its pair: -conj(s)*row_p + cs*row_q
+          Cx<T> sv{srr, sri};
+          Cx<T> a1 = cmulc(sv, xp), a2 = cmulc(sv, yp);
+          Rx = {csr * x.re - a1.re, csr * x.im - a1.im};
+          Ry = {csr * y.re - a2.re, csr * y.im - a2.im};
+        }
+        // columns: (K J)[:,p] = K[:,p] cs + K[:,q] conj(s); (K J)[:,q] = -K[:,p] s + K[:,q] cs
+        Cx<T> b1 = cmulc(s, Ry);  // conj(s) * Ry
+        Cx<T> b2 = cmul(Rx, s);
+        Cx<T> nx{Rx.re * cs + b1.re, Rx.im * cs + b1.im};
+        Cx<T> ny{Ry.re * cs - b2.re, Ry.im * cs - b2.im};
+        if (r == p) ny = {T(0), T(0)};
+        if (r == q) nx = {T(0), T(0)};
+        Cx<T> vp{L.vr[r][p], L.vi[r][p]}, vq{L.vr[r][q], L.vi[r][q]};
+        Cx<T> c1 = cmulc(s, vq), c2 = cmul(vp, s);
+        Cx<T> nvp{vp.re * cs + c1.re, vp.im * cs + c1.im};
+        Cx<T> nvq{vq.re * cs - c2.re, vq.im * cs - c2.im};
+        wave_sync();
+        L.kr[r][p] = nx.re;
+        L.ki[r][p] = nx.im;
+        L.kr[r][q] = ny.re;
+        L.ki[r][q] = ny.im;
+        L.vr[r][p] = nvp.re;
+        L.vi[r][p] = nvp.im;
+        L.vr[r][q] = nvq.re;
+        L.vi[r][q] = nvq.im;
+      }
+      wave_sync();
+    }
+  }
+  return conv;
+}
+
+// After jacobi_herm: eigenvalues sorted descending over the first d indices (padding last).
+// L.src[j] = index of the j-th largest eigenvalue; L.lam[i] = eigenvalue i.
+template <typename T, int MP>
+__device__ void eig_sort_desc(EigLds<T, MP>& L, int r, int d) {
+  L.lam[r] = (r < d) ? L.kr[r][r] : Num<T>::ninf();
+  wave_sync();
+  const T me = L.lam[r];
+  int rank = 0;
+  for (int j = 0; j < MP; ++j) {
+    T o = L.lam[j];
+    rank += (o > me || (o == me && j < r)) ? 1 : 0;
+  }
+  L.src[rank] = r;
+  wave_sync();
+}
+
+// Phase of output column j (eigenvector src[j]) so that its largest-modulus entry among the
+// first d rows (lowest row on ties) becomes real positive.  Returns the multiplier
+// conj(v_k)/|v_k| in every lane of the group.
+template <typename T, int MP>
+__device__ Cx<T> canonical_phase(EigLds<T, MP>& L, int r, int d, int col) {
+  T vr = L.vr[r][col], vi = L.vi[r][col];
+  T mag = (r < d) ? vr * vr + vi * vi : T(-1);
+  int idx = r;
+#pragma unroll
+  for (int o = MP / 2; o > 0; o >>= 1) {
+    T om = __shfl_xor(mag, o, 64);
+    int oi = __shfl_xor(idx, o, 64);
+    if (om > mag || (om == mag && oi < idx)) {
+      mag = om;
+      idx = oi;
+    }
+  }
+  T pr = L.vr[idx][col], pi = L.vi[idx][col];
+  T a = dsqrt(pr * pr + pi * pi);
+  if (a > T(0)) return {pr / a, -pi / a};
+  return {T(1), T(0)};
+}
+
+}  // namespace gt

@@ -1,0 +1,619 @@
+// Groupwise Tucker fit on the GPU: HOSVD initialisation, alternating (Gauss-Seidel) factor
+// updates and the final cores (Section 3.2: equations "update A", "update B", "update C",
+// "kernel" and the groupwise compression algorithm).
+//
+// Matrix forms used by the kernels, for the subcarrier slices H_s of one group g:
+//   A-step   Z_q = sum_s conj(C[s,q]) H_s B,      S1 = sum_{g,q} Z_q Z_q^H        (nr x nr)
+//   B-step   Y_s = A^H H_s, W_q = sum_s conj(C[s,q]) Y_s,  S2 = sum_{g,q} W_q^H W_q (nt x nt)
+//   C-step   Yh_s = Y_s B,  S3_g[s,s'] = <Yh_s, Yh_s'>                          (gs x gs)
+//   core     G_g[q] = sum_s conj(C[s,q]) Yh_s
+// These are the unfolded Grams of the paper's tensor expressions with the mode-2 factor in
+// matrix form (B = conj of the tensor-form factor).  After each half-step the objective is
+// f = ||X||^2 - (sum of the kept eigenvalues), since ||G||^2 = tr(U^H S U) at the maximiser.
+#include <hip/hip_runtime.h>
+
+#include "gt_device.h"
+#include "gt_internal.h"
+
+namespace gt {
+
+#define CH_BEGIN(ch_index)                   \
+  const DevChan& ch = chans[(ch_index)];     \
+  (void)ch;
+
+__device__ __forceinline__ float2* wsp(char* ws, int64_t off) {
+  return reinterpret_cast<float2*>(ws + off);
+}
+__device__ __forceinline__ double* wsd(char* ws, int64_t off) {
+  return reinterpret_cast<double*>(ws + off);
+}
+
+// ---------------------------------------------------------------------------------------
+// Initial Grams of one group: S1 partial = sum_s H_s H_s^H, S3_g[s,s'] = <H_s, H_s'>, and
+// the group's squared norm.
+__global__ void __launch_bounds__(256) k_init_group(const DevChan* __restrict__ chans,
+                                                    const GroupItem* __restrict__ items,
+                                                    const float2* __restrict__ X, char* ws) {
+  const GroupItem it = items[blockIdx.x];
+  CH_BEGIN(it.ch);
+  const int s0 = it.g * ch.gs;
+  const int sz = min(ch.gs, ch.nsc - s0);
+  const int nr = ch.nr, nt = ch.nt;
+  const float2* Xg = X + ch.x + (int64_t)s0 * nr * nt;
+  // S1 partial
+  float2* S1 = wsp(ws, ch.w_S1p) + (int64_t)it.g * nr * nr;
+  for (int o = threadIdx.x; o < nr * nr; o += blockDim.x) {
+    const int i = o / nr, k = o % nr;
+    Cx<float> acc{0.f, 0.f};
+    for (int s = 0; s < sz; ++s)
+      for (int j = 0; j < nt; ++j) {
+        Cx<float> a = ld(Xg + ((int64_t)s * nr + i) * nt + j);
+        Cx<float> b = ld(Xg + ((int64_t)s * nr + k) * nt + j);
+        cfmac(acc, b, a);  // a * conj(b)
+      }
+    st(S1 + o, acc);
+  }
+  // S3 of the group
+  const int gs = ch.gs;
+  float2* S3 = wsp(ws, ch.w_S3) + (int64_t)it.g * gs * gs;
+  for (int o = threadIdx.x; o < gs * gs; o += blockDim.x) {
+    const int s = o / gs, t = o % gs;
+    Cx<float> acc{0.f, 0.f};
+    if (s < sz && t < sz) {
+      const float2* Hs = Xg + (int64_t)s * nr * nt;
+      const float2* Ht = Xg + (int64_t)t * nr * nt;
+      for (int e = 0; e < nr * nt; ++e) cfmac(acc, ld(Ht + e), ld(Hs + e));
+    }
+    st(S3 + o, acc);
+  }
+  // squared norm (double)
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < sz * nr * nt; e += blockDim.x) {
+    float2 v = Xg[e];
+    acc += (double)v.x * v.x + (double)v.y * v.y;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) wsd(ws, ch.w_lamg)[it.g] = red[0];
+}
+
+// Sum of the per-group norms: scal[0] = ||X||^2.
+__global__ void k_norm_total(const DevChan* __restrict__ chans, int n_channels, char* ws) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_channels) return;
+  CH_BEGIN(c);
+  const double* lg = wsd(ws, ch.w_lamg);
+  double s = 0.0;
+  for (int g = 0; g < ch.ngroups; ++g) s += lg[g];
+  wsd(ws, ch.w_scal)[0] = s;
+}
+
+// ---------------------------------------------------------------------------------------
+// Split-row Gram: partial[split][j][k] = sum over the split's rows of conj(M[row][j]) M[row][k].
+// which = 0: rows of X (nsc*nr rows of length nt).  which = 1: rows of W.
+__global__ void __launch_bounds__(256) k_gram_rows(const DevChan* __restrict__ chans,
+                                                   const float2* __restrict__ X, char* ws,
+                                                   int which) {
+  CH_BEGIN(blockIdx.z);
+  const int nt = ch.nt;
+  const int tiles = (nt + 15) / 16;
+  const int tj = blockIdx.x / tiles, tk = blockIdx.x % tiles;
+  if (tj >= tiles) return;
+  const int split = blockIdx.y;
+  if (split >= ch.nsplit) return;
+  const float2* M;
+  int64_t nrows;
+  if (which == 0) {
+    M = X + ch.x;
+    nrows = (int64_t)ch.nsc * ch.nr;
+  } else {
+    M = wsp(ws, ch.w_W);
+    nrows = (int64_t)ch.ngroups * ch.p * ch.m;
+  }
+  const int64_t chunk = (nrows + ch.nsplit - 1) / ch.nsplit;
+  const int64_t r0 = split * chunk;
+  const int64_t r1 = min(nrows, r0 + chunk);
+  __shared__ float2 a_t[16][17];
+  __shared__ float2 b_t[16][17];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int j = tj * 16 + ty, k = tk * 16 + tx;
+  Cx<float> acc{0.f, 0.f};
+  for (int64_t rb = r0; rb < r1; rb += 16) {
+    // load 16 rows x 16 cols for both column blocks
+    {
+      const int lr = threadIdx.x / 16, lc = threadIdx.x % 16;
+      const int64_t row = rb + lr;
+      float2 va = make_float2(0.f, 0.f), vb = make_float2(0.f, 0.f);
+      if (row < r1) {
+        if (tj * 16 + lc < nt) va = M[row * nt + tj * 16 + lc];
+        if (tk * 16 + lc < nt) vb = M[row * nt + tk * 16 + lc];
+      }
+      a_t[lr][lc] = va;
+      b_t[lr][lc] = vb;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) {
+      float2 a = a_t[rr][ty], b = b_t[rr][tx];
+      cfmac(acc, Cx<float>{a.x, a.y}, Cx<float>{b.x, b.y});
+    }
+    __syncthreads();
+  }
+  if (j < nt && k < nt) st(wsp(ws, ch.w_S2p) + ((int64_t)split * nt + j) * nt + k, acc);
+}
+
+// S2 = sum of the split partials (fixed order).
+__global__ void k_reduce_S2(const DevChan* __restrict__ chans, char* ws) {
+  CH_BEGIN(blockIdx.y);
+  const int nt = ch.nt;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nt * nt) return;
+  const float2* P = wsp(ws, ch.w_S2p);
+  Cx<float> acc{0.f, 0.f};
+  for (int sp = 0; sp < ch.nsplit; ++sp) {
+    float2 v = P[(int64_t)sp * nt * nt + e];
+    acc.re += v.x;
+    acc.im += v.y;
+  }
+  st(wsp(ws, ch.w_S2) + e, acc);
+}
+
+// ---------------------------------------------------------------------------------------
+// Eigen kernels: top eigenvectors (descending, canonical phase) of the mode-1 Gram (sum of
+// the per-group partials), the mode-2 Gram, and each group's mode-3 Gram.
+
+template <typename T, int MP>
+__device__ void eig_finish(EigLds<T, MP>& L, int r, int d, int rk, float2* dst, int ld,
+                           int rpad, double* lamsum, int32_t* status, bool conv) {
+  eig_sort_desc<T, MP>(L, r, d);
+  double ls = 0.0;
+  for (int j = 0; j < rpad; ++j) {
+    if (j < rk) {
+      const int col = L.src[j];
+      Cx<T> ph = canonical_phase<T, MP>(L, r, d, col);
+      if (r < d && dst) {
+        Cx<T> v{L.vr[r][col], L.vi[r][col]};
+        Cx<T> o = cmul(v, ph);
+        dst[(int64_t)r * ld + j] = make_float2((float)o.re, (float)o.im);
+      }
+      ls += (double)L.lam[col];
+    } else if (r < d && dst) {
+      dst[(int64_t)r * ld + j] = make_float2(0.f, 0.f);
+    }
+  }
+  if (r == 0) {
+    if (lamsum) *lamsum = ls;
+    if (status) {
+      uint32_t bits = conv ? 0u : GT_DEV_EIG_SWEEPS;
+      if (!(ls == ls) || ls > 1e300 || ls < -1e300) bits |= GT_DEV_NONFINITE;
+      if (bits) atomicOr(reinterpret_cast<unsigned int*>(status), bits);
+    }
+  }
+}
+
+// mode-1: one MP-lane group per channel
+template <typename T, int MP>
+__global__ void __launch_bounds__(64) k_eigA(const DevChan* __restrict__ chans, int n_channels,
+                                              char* ws, float2* A, int32_t* status,
+                                              int write_factor) {
+  constexpr int GPW = 64 / MP;
+  __shared__ EigLds<T, MP> lds[GPW];
+  const int grp = threadIdx.x / MP, r = threadIdx.x % MP;
+  const int c = blockIdx.x * GPW + grp;
+  EigLds<T, MP>& L = lds[grp];
+  const bool valid = c < n_channels;
+  const DevChan* chp = valid ? &chans[c] : nullptr;
+  const int d = valid ? chp->nr : 0;
+  for (int j = 0; j < MP; ++j) {
+    T sr = 0, si = 0;
+    if (r < d && j < d) {
+      const float2* P = wsp(ws, chp->w_S1p);
+      for (int g = 0; g < chp->ngroups; ++g) {
+        float2 v = P[((int64_t)g * d + r) * d + j];
+        sr += (T)v.x;
+        si += (T)v.y;
+      }
+    }
+    L.kr[r][j] = sr;
+    L.ki[r][j] = si;
+  }
+  wave_sync();
+  bool conv = jacobi_herm<T, MP>(L, r, sizeof(T) == 4 ? 12 : 20);
+  if (valid) {
+    double* ls = wsd(ws, chp->w_scal) + 1;
+    eig_finish<T, MP>(L, r, d, chp->m, write_factor ? A + chp->a : nullptr, chp->m, chp->m, ls,
+                      status ? status + c : nullptr, conv);
+  } else {
+    eig_sort_desc<T, MP>(L, r, 0);
+  }
+}
+
+// mode-2: one wave per channel, nt <= 64
+template <typename T>
+__global__ void __launch_bounds__(64) k_eigB(const DevChan* __restrict__ chans, char* ws,
+                                             float2* B, int32_t* status, int write_factor) {
+  constexpr int MP = 64;
+  __shared__ EigLds<T, MP> L;
+  const int r = threadIdx.x;
+  const int c = blockIdx.x;
+  const DevChan& ch = chans[c];
+  const int d = ch.nt;
+  const float2* S = wsp(ws, ch.w_S2);
+  for (int j = 0; j < MP; ++j) {
+    T sr = 0, si = 0;
+    if (r < d && j < d) {
+      float2 v = S[(int64_t)r * d + j];
+      sr = (T)v.x;
+      si = (T)v.y;
+    }
+    L.kr[r][j] = sr;
+    L.ki[r][j] = si;
+  }
+  wave_sync();
+  bool conv = jacobi_herm<T, MP>(L, r, sizeof(T) == 4 ? 12 : 20);
+  eig_finish<T, MP>(L, r, d, ch.n, write_factor ? B + ch.b : nullptr, ch.n, ch.n,
+                    wsd(ws, ch.w_scal) + 2, status ? status + c : nullptr, conv);
+}
+
+// mode-3: one MP-lane group per subcarrier group
+template <typename T, int MP>
+__global__ void __launch_bounds__(64) k_eigC(const DevChan* __restrict__ chans,
+                                              const GroupItem* __restrict__ items,
+                                              int total_groups, char* ws, float2* C,
+                                              int32_t* status, int write_factor) {
+  constexpr int GPW = 64 / MP;
+  __shared__ EigLds<T, MP> lds[GPW];
+  const int grp = threadIdx.x / MP, r = threadIdx.x % MP;
+  const int gi = blockIdx.x * GPW + grp;
+  EigLds<T, MP>& L = lds[grp];
+  const bool valid = gi < total_groups;
+  GroupItem it{0, 0};
+  if (valid) it = items[gi];
+  const DevChan& ch = chans[it.ch];
+  const int s0 = it.g * ch.gs;
+  const int d = valid ? min(ch.gs, ch.nsc - s0) : 0;
+  const float2* S = wsp(ws, ch.w_S3) + (int64_t)it.g * ch.gs * ch.gs;
+  for (int j = 0; j < MP; ++j) {
+    T sr = 0, si = 0;
+    if (r < d && j < d) {
+      float2 v = S[r * ch.gs + j];
+      sr = (T)v.x;
+      si = (T)v.y;
+    }
+    L.kr[r][j] = sr;
+    L.ki[r][j] = si;
+  }
+  wave_sync();
+  bool conv = jacobi_herm<T, MP>(L, r, sizeof(T) == 4 ? 12 : 20);
+  if (valid) {
+    const int pg = min(ch.p, d);
+    eig_finish<T, MP>(L, r, d, pg, write_factor ? C + ch.c + (int64_t)s0 * ch.p : nullptr, ch.p,
+                      ch.p, wsd(ws, ch.w_lamg) + it.g, status ? status + it.ch : nullptr, conv);
+  } else {
+    eig_sort_desc<T, MP>(L, r, 0);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Mode-n products of the sweep.
+
+// Y_s = A^H H_s  (m x nt), all subcarriers of a channel.
+__global__ void __launch_bounds__(256) k_Y(const DevChan* __restrict__ chans,
+                                           const float2* __restrict__ X,
+                                           const float2* __restrict__ A, char* ws) {
+  CH_BEGIN(blockIdx.y);
+  const int64_t total = (int64_t)ch.nsc * ch.m * ch.nt;
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= total) return;
+  const int j = (int)(o % ch.nt);
+  const int a = (int)((o / ch.nt) % ch.m);
+  const int64_t s = o / ((int64_t)ch.nt * ch.m);
+  const float2* Hs = X + ch.x + s * ch.nr * ch.nt;
+  const float2* Ac = A + ch.a;
+  Cx<float> acc{0.f, 0.f};
+  for (int i = 0; i < ch.nr; ++i) cfmac(acc, ld(Ac + i * ch.m + a), ld(Hs + (int64_t)i * ch.nt + j));
+  st(wsp(ws, ch.w_Y) + o, acc);
+}
+
+// W[g][q] = sum_{s in g} conj(C[s,q]) Y_s  (m x nt); zero for q >= p_g.
+__global__ void __launch_bounds__(256) k_W(const DevChan* __restrict__ chans,
+                                           const float2* __restrict__ C, char* ws) {
+  CH_BEGIN(blockIdx.y);
+  const int64_t per_g = (int64_t)ch.p * ch.m * ch.nt;
+  const int64_t total = per_g * ch.ngroups;
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= total) return;
+  const int g = (int)(o / per_g);
+  const int64_t rem = o % per_g;
+  const int q = (int)(rem / ((int64_t)ch.m * ch.nt));
+  const int64_t aj = rem % ((int64_t)ch.m * ch.nt);
+  const int s0 = g * ch.gs;
+  const int sz = min(ch.gs, ch.nsc - s0);
+  Cx<float> acc{0.f, 0.f};
+  if (q < min(ch.p, sz)) {
+    const float2* Y = wsp(ws, ch.w_Y);
+    for (int i = 0; i < sz; ++i)
+      cfmac(acc, ld(C + ch.c + (int64_t)(s0 + i) * ch.p + q),
+            ld(Y + (int64_t)(s0 + i) * ch.m * ch.nt + aj));
+  }
+  st(wsp(ws, ch.w_W) + o, acc);
+}
+
+// T_s = H_s B  (nr x n)
+__global__ void __launch_bounds__(256) k_T(const DevChan* __restrict__ chans,
+                                           const float2* __restrict__ X,
+                                           const float2* __restrict__ B, char* ws) {
+  CH_BEGIN(blockIdx.y);
+  const int64_t total = (int64_t)ch.nsc * ch.nr * ch.n;
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= total) return;
+  const int b = (int)(o % ch.n);
+  const int64_t si = o / ch.n;  // s*nr + i
+  const float2* Hrow = X + ch.x + si * ch.nt;
+  const float2* Bc = B + ch.b;
+  Cx<float> acc{0.f, 0.f};
+  for (int j = 0; j < ch.nt; ++j) cfma(acc, ld(Hrow + j), ld(Bc + (int64_t)j * ch.n + b));
+  st(wsp(ws, ch.w_T) + o, acc);
+}
+
+// Per group: Z_q = sum_s conj(C[s,q]) T_s, S1 partial = sum_q Z_q Z_q^H (one q at a time).
+__global__ void __launch_bounds__(256) k_stepA_group(const DevChan* __restrict__ chans,
+                                                     const GroupItem* __restrict__ items,
+                                                     const float2* __restrict__ C, char* ws) {
+  const GroupItem it = items[blockIdx.x];
+  CH_BEGIN(it.ch);
+  const int nr = ch.nr, n = ch.n;
+  const int s0 = it.g * ch.gs;
+  const int sz = min(ch.gs, ch.nsc - s0);
+  const int pg = min(ch.p, sz);
+  __shared__ float2 Z[kMaxNr * 64];  // [i][b] of one Z_q
+  const float2* T = wsp(ws, ch.w_T) + (int64_t)s0 * nr * n;
+  Cx<float> acc[1] = {{0.f, 0.f}};
+  const int o = threadIdx.x;  // output (i, k) of S1, nr*nr <= 256
+  for (int q = 0; q < pg; ++q) {
+    for (int e = threadIdx.x; e < nr * n; e += blockDim.x) {
+      Cx<float> z{0.f, 0.f};
+      for (int i = 0; i < sz; ++i)
+        cfmac(z, ld(C + ch.c + (int64_t)(s0 + i) * ch.p + q), ld(T + (int64_t)i * nr * n + e));
+      Z[e] = make_float2(z.re, z.im);
+    }
+    __syncthreads();
+    if (o < nr * nr) {
+      const int i = o / nr, k = o % nr;
+      for (int b = 0; b < n; ++b) {
+        float2 zi = Z[i * n + b], zk = Z[k * n + b];
+        cfmac(acc[0], Cx<float>{zk.x, zk.y}, Cx<float>{zi.x, zi.y});
+      }
+    }
+    __syncthreads();
+  }
+  if (o < nr * nr) st(wsp(ws, ch.w_S1p) + (int64_t)it.g * nr * nr + o, acc[0]);
+}
+
+// Yh_s = Y_s B  (m x n)
+__global__ void __launch_bounds__(256) k_Yh(const DevChan* __restrict__ chans,
+                                            const float2* __restrict__ B, char* ws) {
+  CH_BEGIN(blockIdx.y);
+  const int64_t total = (int64_t)ch.nsc * ch.m * ch.n;
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= total) return;
+  const int b = (int)(o % ch.n);
+  const int64_t sa = o / ch.n;
+  const float2* Yrow = wsp(ws, ch.w_Y) + sa * ch.nt;
+  const float2* Bc = B + ch.b;
+  Cx<float> acc{0.f, 0.f};
+  for (int j = 0; j < ch.nt; ++j) cfma(acc, ld(Yrow + j), ld(Bc + (int64_t)j * ch.n + b));
+  st(wsp(ws, ch.w_Yh) + o, acc);
+}
+
+// S3_g[s,t] = <Yh_s, Yh_t> for the subcarriers of each group
+__global__ void __launch_bounds__(256) k_S3(const DevChan* __restrict__ chans,
+                                            const GroupItem* __restrict__ items, char* ws) {
+  const GroupItem it = items[blockIdx.x];
+  CH_BEGIN(it.ch);
+  const int gs = ch.gs;
+  const int s0 = it.g * gs;
+  const int sz = min(gs, ch.nsc - s0);
+  const int mn = ch.m * ch.n;
+  const float2* Yh = wsp(ws, ch.w_Yh) + (int64_t)s0 * mn;
+  float2* S3 = wsp(ws, ch.w_S3) + (int64_t)it.g * gs * gs;
+  for (int o = threadIdx.x; o < gs * gs; o += blockDim.x) {
+    const int s = o / gs, t = o % gs;
+    Cx<float> acc{0.f, 0.f};
+    if (s < sz && t < sz)
+      for (int e = 0; e < mn; ++e) cfmac(acc, ld(Yh + (int64_t)t * mn + e), ld(Yh + (int64_t)s * mn + e));
+    st(S3 + o, acc);
+  }
+}
+
+// per group: sum_q c_q^H S3_g c_q with the current C (objective of given factors)
+__global__ void __launch_bounds__(64) k_objC(const DevChan* __restrict__ chans,
+                                             const GroupItem* __restrict__ items,
+                                             const float2* __restrict__ C, char* ws) {
+  const GroupItem it = items[blockIdx.x];
+  CH_BEGIN(it.ch);
+  const int gs = ch.gs;
+  const int s0 = it.g * gs;
+  const int sz = min(gs, ch.nsc - s0);
+  const int pg = min(ch.p, sz);
+  const float2* S3 = wsp(ws, ch.w_S3) + (int64_t)it.g * gs * gs;
+  __shared__ double red[64];
+  double acc = 0.0;
+  for (int o = threadIdx.x; o < pg * sz; o += blockDim.x) {
+    const int q = o / sz, s = o % sz;
+    // (S3 c)_s conj(c_s)
+    double re = 0.0, im = 0.0;
+    for (int t = 0; t < sz; ++t) {
+      float2 a = S3[s * gs + t];
+      float2 c = C[ch.c + (int64_t)(s0 + t) * ch.p + q];
+      re += (double)a.x * c.x - (double)a.y * c.y;
+      im += (double)a.x * c.y + (double)a.y * c.x;
+    }
+    float2 cs = C[ch.c + (int64_t)(s0 + s) * ch.p + q];
+    acc += (double)cs.x * re + (double)cs.y * im;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 32; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) wsd(ws, ch.w_lamg)[it.g] = red[0];
+}
+
+// objective entry: mode 0 = scal[1] (A step), 1 = scal[2] (B step), 2 = sum of group sums
+__global__ void k_trace(const DevChan* __restrict__ chans, int n_channels, char* ws,
+                        double* trace, int stride, int idx, int mode) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_channels) return;
+  CH_BEGIN(c);
+  const double* sc = wsd(ws, ch.w_scal);
+  double kept;
+  if (mode == 0)
+    kept = sc[1];
+  else if (mode == 1)
+    kept = sc[2];
+  else {
+    kept = 0.0;
+    const double* lg = wsd(ws, ch.w_lamg);
+    for (int g = 0; g < ch.ngroups; ++g) kept += lg[g];
+  }
+  trace[(int64_t)c * stride + idx] = sc[0] - kept;
+}
+
+// G_g[q] = sum_s conj(C[s,q]) Yh_s; zero for q >= p_g
+__global__ void __launch_bounds__(256) k_core(const DevChan* __restrict__ chans,
+                                              const float2* __restrict__ C, float2* G, char* ws) {
+  CH_BEGIN(blockIdx.y);
+  const int mn = ch.m * ch.n;
+  const int64_t per_g = (int64_t)ch.p * mn;
+  const int64_t total = per_g * ch.ngroups;
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= total) return;
+  const int g = (int)(o / per_g);
+  const int q = (int)((o % per_g) / mn);
+  const int e = (int)(o % mn);
+  const int s0 = g * ch.gs;
+  const int sz = min(ch.gs, ch.nsc - s0);
+  Cx<float> acc{0.f, 0.f};
+  if (q < min(ch.p, sz)) {
+    const float2* Yh = wsp(ws, ch.w_Yh);
+    for (int i = 0; i < sz; ++i)
+      cfmac(acc, ld(C + ch.c + (int64_t)(s0 + i) * ch.p + q), ld(Yh + (int64_t)(s0 + i) * mn + e));
+  }
+  st(G + ch.g + o, acc);
+}
+
+// ---------------------------------------------------------------------------------------
+// Host side
+
+#define GT_LAUNCH(name, grid, block, ...)                        \
+  do {                                                           \
+    prof_begin(#name, L.stream);                                 \
+    hipLaunchKernelGGL(name, grid, block, 0, L.stream, __VA_ARGS__); \
+    prof_end(L.stream);                                          \
+    hipError_t e_ = hipGetLastError();                           \
+    if (e_ != hipSuccess) {                                      \
+      set_error_detail(#name, e_);                               \
+      return GT_ERR_HIP;                                         \
+    }                                                            \
+  } while (0)
+
+static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+template <typename T>
+static gt_status eig_all(const LaunchCtx& L, int which, float2* A, float2* B, float2* C,
+                         int32_t* status, int write) {
+  if (which == 0) {
+    GT_LAUNCH((k_eigA<T, 16>), dim3(cdiv(L.n_channels, 4)), dim3(64), L.d_chans, L.n_channels,
+              L.ws, A, status, write);
+  } else if (which == 1) {
+    GT_LAUNCH((k_eigB<T>), dim3(L.n_channels), dim3(64), L.d_chans, L.ws, B, status, write);
+  } else {
+    if (L.max_gs <= 16) {
+      GT_LAUNCH((k_eigC<T, 16>), dim3(cdiv(L.total_groups, 4)), dim3(64), L.d_chans, L.d_groups,
+                L.total_groups, L.ws, C, status, write);
+    } else {
+      GT_LAUNCH((k_eigC<T, 32>), dim3(cdiv(L.total_groups, 2)), dim3(64), L.d_chans, L.d_groups,
+                L.total_groups, L.ws, C, status, write);
+    }
+  }
+  return GT_OK;
+}
+
+static gt_status eig_dispatch(const LaunchCtx& L, int which, float2* A, float2* B, float2* C,
+                              int32_t* status, int write) {
+  return L.eig_fp64 ? eig_all<double>(L, which, A, B, C, status, write)
+                    : eig_all<float>(L, which, A, B, C, status, write);
+}
+
+gt_status launch_fit(const LaunchCtx& L, const float2* X, float2* A, float2* B, float2* C,
+                     float2* G, double* trace, int32_t* status, int iters, bool warm) {
+  const int nch = L.n_channels;
+  const int stride = 1 + 3 * iters;
+  const dim3 b256(256);
+  const unsigned gY = cdiv((int64_t)L.max_nsc * L.max_m * L.max_nt, 256);
+  const unsigned gW = cdiv((int64_t)L.max_groups * L.max_p * L.max_m * L.max_nt, 256);
+  const unsigned gT = cdiv((int64_t)L.max_nsc * L.max_nr * L.max_n, 256);
+  const unsigned gYh = cdiv((int64_t)L.max_nsc * L.max_m * L.max_n, 256);
+  const unsigned gCore = cdiv((int64_t)L.max_groups * L.max_p * L.max_m * L.max_n, 256);
+  const int tiles = (L.max_nt + 15) / 16;
+  const dim3 gGram(tiles * tiles, L.max_nsplit, nch);
+  const dim3 gRed(cdiv((int64_t)L.max_nt * L.max_nt, 256), nch);
+
+  // initialisation: Grams of the unfoldings, norms
+  GT_LAUNCH(k_init_group, dim3(L.total_groups), b256, L.d_chans, L.d_groups, X, L.ws);
+  GT_LAUNCH(k_norm_total, dim3(cdiv(nch, 64)), dim3(64), L.d_chans, nch, L.ws);
+  if (!warm) {
+    GT_LAUNCH(k_gram_rows, gGram, b256, L.d_chans, X, L.ws, 0);
+    GT_LAUNCH(k_reduce_S2, gRed, b256, L.d_chans, L.ws);
+    gt_status st;
+    if ((st = eig_dispatch(L, 0, A, B, C, status, 1)) != GT_OK) return st;
+    if ((st = eig_dispatch(L, 1, A, B, C, status, 1)) != GT_OK) return st;
+    if ((st = eig_dispatch(L, 2, A, B, C, status, 1)) != GT_OK) return st;
+  }
+  // objective of the starting factors
+  GT_LAUNCH(k_Y, dim3(gY, nch), b256, L.d_chans, X, A, L.ws);
+  GT_LAUNCH(k_Yh, dim3(gYh, nch), b256, L.d_chans, B, L.ws);
+  if (trace) {
+    GT_LAUNCH(k_S3, dim3(L.total_groups), b256, L.d_chans, L.d_groups, L.ws);
+    GT_LAUNCH(k_objC, dim3(L.total_groups), dim3(64), L.d_chans, L.d_groups, C, L.ws);
+    GT_LAUNCH(k_trace, dim3(cdiv(nch, 64)), dim3(64), L.d_chans, nch, L.ws, trace, stride, 0, 2);
+  }
+  for (int it = 0; it < iters; ++it) {
+    gt_status st;
+    // A-step (uses B, C of the previous sweep)
+    GT_LAUNCH(k_T, dim3(gT, nch), b256, L.d_chans, X, B, L.ws);
+    GT_LAUNCH(k_stepA_group, dim3(L.total_groups), b256, L.d_chans, L.d_groups, C, L.ws);
+    if ((st = eig_dispatch(L, 0, A, B, C, status, 1)) != GT_OK) return st;
+    if (trace)
+      GT_LAUNCH(k_trace, dim3(cdiv(nch, 64)), dim3(64), L.d_chans, nch, L.ws, trace, stride,
+                1 + 3 * it, 0);
+    // B-step (new A, C of the previous sweep)
+    GT_LAUNCH(k_Y, dim3(gY, nch), b256, L.d_chans, X, A, L.ws);
+    GT_LAUNCH(k_W, dim3(gW, nch), b256, L.d_chans, C, L.ws);
+    GT_LAUNCH(k_gram_rows, gGram, b256, L.d_chans, X, L.ws, 1);
+    GT_LAUNCH(k_reduce_S2, gRed, b256, L.d_chans, L.ws);
+    if ((st = eig_dispatch(L, 1, A, B, C, status, 1)) != GT_OK) return st;
+    if (trace)
+      GT_LAUNCH(k_trace, dim3(cdiv(nch, 64)), dim3(64), L.d_chans, nch, L.ws, trace, stride,
+                2 + 3 * it, 1);
+    // C-step (new A, B)
+    GT_LAUNCH(k_Yh, dim3(gYh, nch), b256, L.d_chans, B, L.ws);
+    GT_LAUNCH(k_S3, dim3(L.total_groups), b256, L.d_chans, L.d_groups, L.ws);
+    if ((st = eig_dispatch(L, 2, A, B, C, status, 1)) != GT_OK) return st;
+    if (trace)
+      GT_LAUNCH(k_trace, dim3(cdiv(nch, 64)), dim3(64), L.d_chans, nch, L.ws, trace, stride,
+                3 + 3 * it, 2);
+  }
+  // cores from the last Yh (computed with the final A and B)
+  GT_LAUNCH(k_core, dim3(gCore, nch), b256, L.d_chans, C, G, L.ws);
+  return GT_OK;
+}
+
+}  // namespace gt

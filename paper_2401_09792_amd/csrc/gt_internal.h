@@ -1,0 +1,67 @@
+// Internal types shared by the host plan code and the HIP kernels of libgtucker.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gtucker.h"
+
+namespace gt {
+
+// Upper bounds on shapes (checked at plan creation; the kernels size LDS by them).
+constexpr int kMaxNr = 16;        // receive antennas, also bounds m
+constexpr int kMaxNt = 64;        // transmit antennas handled by the Jacobi mode-2 eigensolver
+constexpr int kMaxGroup = 32;     // subcarriers per group, also bounds p
+constexpr int kMaxSnr = 16;
+
+// Per-channel descriptor as the kernels see it (lives in the workspace).
+struct DevChan {
+  int32_t nr, nt, nsc, gs, m, n, p, ns;
+  int32_t ngroups, nsplit;         // groups; row splits of the mode-2 Gram reduction
+  int32_t gfirst, pad0;            // index of the channel's first group in the group table
+  int64_t x, a, b, c, g, ht, sc;   // data offsets (complex elements; sc in subcarriers)
+  // workspace byte offsets of this channel's scratch
+  int64_t w_Y;     // [nsc][m][nt]        c64   A^H H_s
+  int64_t w_W;     // [ngroups][p][m][nt] c64   sum_s conj(C[s,q]) Y_s
+  int64_t w_T;     // [nsc][nr][n]        c64   H_s B
+  int64_t w_Yh;    // [nsc][m][n]         c64   A^H H_s B
+  int64_t w_S1p;   // [ngroups][nr][nr]   c64   per-group mode-1 Gram
+  int64_t w_S2p;   // [nsplit][nt][nt]    c64   split partials of the mode-2 Gram
+  int64_t w_S2;    // [nt][nt]            c64   mode-2 Gram
+  int64_t w_S3;    // [ngroups][gs][gs]   c64   per-group mode-3 Gram
+  int64_t w_lamg;  // [ngroups] double          per-group sums (norms, eigenvalue sums)
+  int64_t w_scal;  // [8] double                ||X||^2, eigenvalue sums of the A and B steps
+  int64_t w_gH;    // [nsc][m][n]         c64   per-subcarrier gradient of Ht
+  int64_t w_gAp;   // [ngroups][nr][m]    c64   per-group partial gradient of A
+  int64_t w_gBp;   // [ngroups][nt][n]    c64   per-group partial gradient of B
+};
+
+struct GroupItem {
+  int32_t ch, g;
+};
+
+// Workspace header: where the tables sit.
+struct WsLayout {
+  int64_t chans;   // DevChan[n_channels]
+  int64_t groups;  // GroupItem[total_groups]
+  int64_t total;   // bytes
+};
+
+// Host-side launch helpers implemented in gt_plan.cpp.
+struct LaunchCtx {
+  hipStream_t stream;
+  char* ws;
+  const DevChan* d_chans;     // device pointer into ws
+  const GroupItem* d_groups;  // device pointer into ws
+  int n_channels;
+  int total_groups;
+  int max_nr, max_nt, max_nsc, max_gs, max_m, max_n, max_p, max_ns, max_groups, max_nsplit;
+  int eig_fp64;
+};
+
+// kernel timing hooks (no-ops unless profiling is on)
+void prof_begin(const char* name, hipStream_t s);
+void prof_end(hipStream_t s);
+void set_error_detail(const char* where, hipError_t e);
+
+}  // namespace gt

@@ -1,0 +1,404 @@
+// Host side of libgtucker: plan creation and validation, packed-buffer offsets, workspace
+// layout, the C ABI entry points, status strings and kernel timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gt_internal.h"
+#include "gtucker.h"
+
+namespace gt {
+gt_status launch_fit(const LaunchCtx& L, const float2* X, float2* A, float2* B, float2* C, float2* G,
+                     double* trace, int32_t* status, int iters, bool warm);
+gt_status launch_reconstruct(const LaunchCtx& L, int64_t total_sc, const float2* A, const float2* B,
+                             const float2* C, const float2* G, float2* Ht, float2* Xhat);
+gt_status launch_reconstruct_bwd(const LaunchCtx& L, int64_t total_sc, const float2* A,
+                                 const float2* B, const float2* C, const float2* G,
+                                 const float2* gHt, const float2* gX, float2* gA, float2* gB,
+                                 float2* gC, float2* gG);
+gt_status launch_sinr(const LaunchCtx& L, int64_t total_sc, bool full, const float2* X,
+                      const float2* C, const float2* G, const float* s2, int n_snr, float* out,
+                      int ns_max, int32_t* status);
+gt_status launch_sinr_bwd(const LaunchCtx& L, int64_t total_sc, const float2* C, const float2* G,
+                          const float* s2, int n_snr, const float* gsinr, float2* gC, float2* gG,
+                          int ns_max, int32_t* status);
+
+// ---------------------------------------------------------------------------------------
+// error detail and kernel timing
+
+static thread_local std::string g_detail;
+
+void set_error_detail(const char* where, hipError_t e) {
+  g_detail = std::string(where) + ": " + hipGetErrorString(e);
+}
+
+struct ProfRec {
+  std::string name;
+  hipEvent_t start, stop;
+};
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<ProfRec> g_prof;
+static thread_local int g_prof_open = -1;
+
+void prof_begin(const char* name, hipStream_t s) {
+  if (!g_prof_on) return;
+  ProfRec r;
+  r.name = name;
+  if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.stop) != hipSuccess) return;
+  hipEventRecord(r.start, s);
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof.push_back(r);
+  g_prof_open = (int)g_prof.size() - 1;
+}
+
+void prof_end(hipStream_t s) {
+  if (!g_prof_on || g_prof_open < 0) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  hipEventRecord(g_prof[g_prof_open].stop, s);
+  g_prof_open = -1;
+}
+
+static void prof_clear_locked() {
+  for (auto& r : g_prof) {
+    hipEventDestroy(r.start);
+    hipEventDestroy(r.stop);
+  }
+  g_prof.clear();
+}
+
+}  // namespace gt
+
+using namespace gt;
+
+struct gt_plan {
+  std::vector<gt_channel_desc> desc;
+  std::vector<DevChan> chans;
+  std::vector<GroupItem> groups;
+  gt_fit_options opt;
+  WsLayout lay;
+  std::vector<char> blob;  // device tables, copied into the workspace by gt_workspace_init
+  gt_offsets totals;
+  int ns_max;
+  int max_nr, max_nt, max_nsc, max_gs, max_m, max_n, max_p, max_ns, max_groups, max_nsplit;
+};
+
+static int64_t align256(int64_t v) { return (v + 255) & ~int64_t(255); }
+
+extern "C" {
+
+const char* gt_status_string(gt_status s) {
+  switch (s) {
+    case GT_OK: return "ok";
+    case GT_ERR_ARG: return "invalid argument";
+    case GT_ERR_SHAPE: return "unsupported or invalid shape";
+    case GT_ERR_RANK: return "rank or stream count out of range";
+    case GT_ERR_WORKSPACE: return "workspace missing or too small";
+    case GT_ERR_UNSUPPORTED: return "operation not supported";
+    case GT_ERR_HIP: return "HIP runtime error";
+    case GT_ERR_NO_DEVICE: return "no GPU device";
+  }
+  return "unknown status";
+}
+
+const char* gt_last_error_detail(void) { return g_detail.c_str(); }
+
+static gt_status validate(const gt_channel_desc& d) {
+  if (d.nr < 1 || d.nt < 1 || d.nsc < 1 || d.group_size < 1) return GT_ERR_SHAPE;
+  if (d.nr > kMaxNr || d.nt > 256 || d.group_size > kMaxGroup) return GT_ERR_SHAPE;
+  if (d.m < 1 || d.m > d.nr || d.n < 1 || d.n > d.nt || d.n > 64) return GT_ERR_RANK;
+  if (d.p < 1 || d.p > d.group_size) return GT_ERR_RANK;
+  if (d.ns < 1 || d.ns > std::min(d.m, d.n)) return GT_ERR_RANK;
+  return GT_OK;
+}
+
+gt_status gt_plan_create(const gt_channel_desc* descs, int32_t n_channels, const gt_fit_options* opt,
+                         gt_plan** out) {
+  if (!descs || !out || n_channels < 1) return GT_ERR_ARG;
+  *out = nullptr;
+  gt_fit_options o{};
+  if (opt) o = *opt;
+  if (o.iters < 0 || o.eig_fp64 < 0 || o.eig_fp64 > 1) return GT_ERR_ARG;
+  if (o.ttm_prec < GT_TTM_FP32 || o.ttm_prec > GT_TTM_SPLIT_BF16) return GT_ERR_ARG;
+  if (o.ttm_prec != GT_TTM_FP32) return GT_ERR_UNSUPPORTED;
+  if (o.flags & ~GT_FIT_WARM_START) return GT_ERR_ARG;
+  for (int c = 0; c < n_channels; ++c) {
+    gt_status st = validate(descs[c]);
+    if (st != GT_OK) return st;
+  }
+  gt_plan* p = new (std::nothrow) gt_plan();
+  if (!p) return GT_ERR_ARG;
+  p->desc.assign(descs, descs + n_channels);
+  p->opt = o;
+  p->chans.resize(n_channels);
+  int64_t ox = 0, oa = 0, ob = 0, oc = 0, og = 0, oht = 0, osc = 0;
+  int gfirst = 0;
+  p->max_nr = p->max_nt = p->max_nsc = p->max_gs = p->max_m = p->max_n = p->max_p = p->max_ns = 0;
+  p->max_groups = p->max_nsplit = 0;
+  for (int c = 0; c < n_channels; ++c) {
+    const gt_channel_desc& d = descs[c];
+    DevChan& ch = p->chans[c];
+    std::memset(&ch, 0, sizeof(ch));
+    ch.nr = d.nr;
+    ch.nt = d.nt;
+    ch.nsc = d.nsc;
+    ch.gs = d.group_size;
+    ch.m = d.m;
+    ch.n = d.n;
+    ch.p = d.p;
+    ch.ns = d.ns;
+    ch.ngroups = (d.nsc + d.group_size - 1) / d.group_size;
+    ch.nsplit = std::min(ch.ngroups, 32);
+    ch.gfirst = gfirst;
+    ch.x = ox;
+    ch.a = oa;
+    ch.b = ob;
+    ch.c = oc;
+    ch.g = og;
+    ch.ht = oht;
+    ch.sc = osc;
+    ox += (int64_t)d.nsc * d.nr * d.nt;
+    oa += (int64_t)d.nr * d.m;
+    ob += (int64_t)d.nt * d.n;
+    oc += (int64_t)d.nsc * d.p;
+    og += (int64_t)ch.ngroups * d.p * d.m * d.n;
+    oht += (int64_t)d.nsc * d.m * d.n;
+    osc += d.nsc;
+    for (int g = 0; g < ch.ngroups; ++g) p->groups.push_back(GroupItem{c, g});
+    gfirst += ch.ngroups;
+    p->max_nr = std::max(p->max_nr, d.nr);
+    p->max_nt = std::max(p->max_nt, d.nt);
+    p->max_nsc = std::max(p->max_nsc, d.nsc);
+    p->max_gs = std::max(p->max_gs, d.group_size);
+    p->max_m = std::max(p->max_m, d.m);
+    p->max_n = std::max(p->max_n, d.n);
+    p->max_p = std::max(p->max_p, d.p);
+    p->max_ns = std::max(p->max_ns, d.ns);
+    p->max_groups = std::max(p->max_groups, ch.ngroups);
+    p->max_nsplit = std::max(p->max_nsplit, ch.nsplit);
+  }
+  p->totals = gt_offsets{ox, oa, ob, oc, og, oht, osc, gfirst, 0};
+  p->ns_max = p->max_ns;
+  // workspace: tables then per-channel scratch
+  int64_t off = 0;
+  p->lay.chans = off;
+  off = align256(off + (int64_t)sizeof(DevChan) * n_channels);
+  p->lay.groups = off;
+  off = align256(off + (int64_t)sizeof(GroupItem) * gfirst);
+  const int64_t c8 = 8;
+  for (int c = 0; c < n_channels; ++c) {
+    DevChan& ch = p->chans[c];
+    auto take = [&](int64_t bytes) {
+      int64_t at = off;
+      off = align256(off + std::max<int64_t>(bytes, 8));
+      return at;
+    };
+    ch.w_Y = take(c8 * ch.nsc * ch.m * ch.nt);
+    ch.w_W = take(c8 * ch.ngroups * ch.p * ch.m * ch.nt);
+    ch.w_T = take(c8 * ch.nsc * ch.nr * ch.n);
+    ch.w_Yh = take(c8 * ch.nsc * ch.m * ch.n);
+    ch.w_S1p = take(c8 * ch.ngroups * ch.nr * ch.nr);
+    ch.w_S2p = take(c8 * ch.nsplit * ch.nt * ch.nt);
+    ch.w_S2 = take(c8 * ch.nt * ch.nt);
+    ch.w_S3 = take(c8 * ch.ngroups * ch.gs * ch.gs);
+    ch.w_lamg = take(8 * (int64_t)ch.ngroups);
+    ch.w_scal = take(8 * 8);
+    ch.w_gH = take(c8 * ch.nsc * ch.m * ch.n);
+    ch.w_gAp = take(c8 * ch.ngroups * ch.nr * ch.m);
+    ch.w_gBp = take(c8 * ch.ngroups * ch.nt * ch.n);
+  }
+  p->lay.total = off;
+  p->blob.assign((size_t)p->lay.groups + sizeof(GroupItem) * gfirst, 0);
+  std::memcpy(p->blob.data() + p->lay.chans, p->chans.data(), sizeof(DevChan) * n_channels);
+  std::memcpy(p->blob.data() + p->lay.groups, p->groups.data(), sizeof(GroupItem) * gfirst);
+  *out = p;
+  return GT_OK;
+}
+
+void gt_plan_destroy(gt_plan* plan) { delete plan; }
+
+gt_status gt_plan_offsets(const gt_plan* plan, int32_t channel, gt_offsets* out) {
+  if (!plan || !out) return GT_ERR_ARG;
+  if (channel < 0 || channel >= (int32_t)plan->chans.size()) return GT_ERR_ARG;
+  const DevChan& ch = plan->chans[channel];
+  *out = gt_offsets{ch.x, ch.a, ch.b, ch.c, ch.g, ch.ht, ch.sc, ch.ngroups, 0};
+  return GT_OK;
+}
+
+gt_status gt_plan_totals(const gt_plan* plan, gt_offsets* totals, int32_t* ns_max) {
+  if (!plan) return GT_ERR_ARG;
+  if (totals) *totals = plan->totals;
+  if (ns_max) *ns_max = plan->ns_max;
+  return GT_OK;
+}
+
+gt_status gt_plan_workspace_bytes(const gt_plan* plan, size_t* bytes) {
+  if (!plan || !bytes) return GT_ERR_ARG;
+  *bytes = (size_t)plan->lay.total;
+  return GT_OK;
+}
+
+static gt_status check_ws(const gt_plan* plan, void* ws, size_t ws_bytes) {
+  if (!plan) return GT_ERR_ARG;
+  if (!ws || ws_bytes < (size_t)plan->lay.total) return GT_ERR_WORKSPACE;
+  return GT_OK;
+}
+
+static LaunchCtx make_ctx(const gt_plan* p, void* ws, void* stream) {
+  LaunchCtx L;
+  L.stream = reinterpret_cast<hipStream_t>(stream);
+  L.ws = reinterpret_cast<char*>(ws);
+  L.d_chans = reinterpret_cast<const DevChan*>(L.ws + p->lay.chans);
+  L.d_groups = reinterpret_cast<const GroupItem*>(L.ws + p->lay.groups);
+  L.n_channels = (int)p->chans.size();
+  L.total_groups = (int)p->groups.size();
+  L.max_nr = p->max_nr;
+  L.max_nt = p->max_nt;
+  L.max_nsc = p->max_nsc;
+  L.max_gs = p->max_gs;
+  L.max_m = p->max_m;
+  L.max_n = p->max_n;
+  L.max_p = p->max_p;
+  L.max_ns = p->max_ns;
+  L.max_groups = p->max_groups;
+  L.max_nsplit = p->max_nsplit;
+  L.eig_fp64 = p->opt.eig_fp64;
+  return L;
+}
+
+gt_status gt_workspace_init(const gt_plan* plan, void* ws, size_t ws_bytes, void* stream) {
+  gt_status st = check_ws(plan, ws, ws_bytes);
+  if (st != GT_OK) return st;
+  hipError_t e = hipMemcpyAsync(ws, plan->blob.data(), plan->blob.size(), hipMemcpyHostToDevice,
+                                reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) {
+    set_error_detail("gt_workspace_init", e);
+    return GT_ERR_HIP;
+  }
+  return GT_OK;
+}
+
+gt_status gt_tucker_fit(const gt_plan* plan, const void* X, void* A, void* B, void* C, void* G,
+                        double* obj_trace, int32_t* dev_status, void* ws, size_t ws_bytes,
+                        void* stream) {
+  gt_status st = check_ws(plan, ws, ws_bytes);
+  if (st != GT_OK) return st;
+  if (!X || !A || !B || !C || !G) return GT_ERR_ARG;
+  if (plan->max_nt > kMaxNt) return GT_ERR_UNSUPPORTED;
+  LaunchCtx L = make_ctx(plan, ws, stream);
+  return launch_fit(L, (const float2*)X, (float2*)A, (float2*)B, (float2*)C, (float2*)G, obj_trace,
+                    dev_status, plan->opt.iters, (plan->opt.flags & GT_FIT_WARM_START) != 0);
+}
+
+gt_status gt_tucker_reconstruct(const gt_plan* plan, const void* A, const void* B, const void* C,
+                                const void* G, void* Ht, void* Xhat, void* ws, size_t ws_bytes,
+                                void* stream) {
+  gt_status st = check_ws(plan, ws, ws_bytes);
+  if (st != GT_OK) return st;
+  if (!C || !G || (Xhat && (!A || !B))) return GT_ERR_ARG;
+  if (!Ht && !Xhat) return GT_OK;
+  LaunchCtx L = make_ctx(plan, ws, stream);
+  return launch_reconstruct(L, plan->totals.sc, (const float2*)A, (const float2*)B,
+                            (const float2*)C, (const float2*)G, (float2*)Ht, (float2*)Xhat);
+}
+
+static gt_status check_snr(const float* sigma2, int32_t n_snr) {
+  if (!sigma2 || n_snr < 1 || n_snr > kMaxSnr) return GT_ERR_ARG;
+  for (int k = 0; k < n_snr; ++k)
+    if (!(sigma2[k] >= 0.f) || sigma2[k] > 3e38f) return GT_ERR_ARG;
+  return GT_OK;
+}
+
+gt_status gt_sinr_eval(const gt_plan* plan, const void* C, const void* G, const float* sigma2,
+                       int32_t n_snr, float* sinr, int32_t* dev_status, void* ws, size_t ws_bytes,
+                       void* stream) {
+  gt_status st = check_ws(plan, ws, ws_bytes);
+  if (st != GT_OK) return st;
+  if ((st = check_snr(sigma2, n_snr)) != GT_OK) return st;
+  if (!C || !G || !sinr) return GT_ERR_ARG;
+  LaunchCtx L = make_ctx(plan, ws, stream);
+  return launch_sinr(L, plan->totals.sc, false, nullptr, (const float2*)C, (const float2*)G, sigma2,
+                     n_snr, sinr, plan->ns_max, dev_status);
+}
+
+gt_status gt_sinr_eval_full(const gt_plan* plan, const void* X, const float* sigma2, int32_t n_snr,
+                            float* sinr, int32_t* dev_status, void* ws, size_t ws_bytes,
+                            void* stream) {
+  gt_status st = check_ws(plan, ws, ws_bytes);
+  if (st != GT_OK) return st;
+  if ((st = check_snr(sigma2, n_snr)) != GT_OK) return st;
+  if (!X || !sinr) return GT_ERR_ARG;
+  LaunchCtx L = make_ctx(plan, ws, stream);
+  return launch_sinr(L, plan->totals.sc, true, (const float2*)X, nullptr, nullptr, sigma2, n_snr,
+                     sinr, plan->ns_max, dev_status);
+}
+
+gt_status gt_sinr_eval_backward(const gt_plan* plan, const void* C, const void* G,
+                                const float* sigma2, int32_t n_snr, const float* grad_sinr,
+                                void* grad_C, void* grad_G, int32_t* dev_status, void* ws,
+                                size_t ws_bytes, void* stream) {
+  gt_status st = check_ws(plan, ws, ws_bytes);
+  if (st != GT_OK) return st;
+  if ((st = check_snr(sigma2, n_snr)) != GT_OK) return st;
+  if (!C || !G || !grad_sinr || !grad_C || !grad_G) return GT_ERR_ARG;
+  LaunchCtx L = make_ctx(plan, ws, stream);
+  return launch_sinr_bwd(L, plan->totals.sc, (const float2*)C, (const float2*)G, sigma2, n_snr,
+                         grad_sinr, (float2*)grad_C, (float2*)grad_G, plan->ns_max, dev_status);
+}
+
+gt_status gt_tucker_reconstruct_backward(const gt_plan* plan, const void* A, const void* B,
+                                         const void* C, const void* G, const void* grad_Ht,
+                                         const void* grad_Xhat, void* grad_A, void* grad_B,
+                                         void* grad_C, void* grad_G, void* ws, size_t ws_bytes,
+                                         void* stream) {
+  gt_status st = check_ws(plan, ws, ws_bytes);
+  if (st != GT_OK) return st;
+  if (!A || !B || !C || !G || !grad_A || !grad_B || !grad_C || !grad_G) return GT_ERR_ARG;
+  LaunchCtx L = make_ctx(plan, ws, stream);
+  return launch_reconstruct_bwd(L, plan->totals.sc, (const float2*)A, (const float2*)B,
+                                (const float2*)C, (const float2*)G, (const float2*)grad_Ht,
+                                (const float2*)grad_Xhat, (float2*)grad_A, (float2*)grad_B,
+                                (float2*)grad_C, (float2*)grad_G);
+}
+
+gt_status gt_tucker_fit_backward(const gt_plan* plan) {
+  (void)plan;
+  return GT_ERR_UNSUPPORTED;
+}
+
+gt_status gt_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+  return GT_OK;
+}
+
+gt_status gt_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  prof_clear_locked();
+  return GT_OK;
+}
+
+gt_status gt_profile_query(const char* name, double* total_ms, int64_t* launches) {
+  if (!name || !total_ms || !launches) return GT_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  double tot = 0.0;
+  int64_t cnt = 0;
+  for (auto& r : g_prof) {
+    if (r.name.find(name) == std::string::npos) continue;
+    if (hipEventSynchronize(r.stop) != hipSuccess) return GT_ERR_HIP;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess) return GT_ERR_HIP;
+    tot += ms;
+    ++cnt;
+  }
+  *total_ms = tot;
+  *launches = cnt;
+  return GT_OK;
+}
+
+}  // extern "C"
