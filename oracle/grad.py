@@ -58,7 +58,7 @@ def sinr_grad(C: np.ndarray, G: np.ndarray, gs: int, sigma2_list, ns: int,
     Gt = torch.tensor(G, dtype=torch.complex128, requires_grad=True)
     y = sinr_compressed_t(Ct, Gt, gs, sigma2_list, ns)
     y.backward(torch.as_tensor(grad_sinr, dtype=torch.float64))
-    return Ct.grad.numpy().copy(), Gt.grad.numpy().copy()
+    return Ct.grad.resolve_conj().numpy().copy(), Gt.grad.resolve_conj().numpy().copy()
 
 
 def sinr_grad_closed_form(C, G, gs, sigma2_list, ns, grad_sinr):
@@ -100,5 +100,6 @@ def reconstruct_grad(A, B, C, G, gs, grad_Ht, grad_Xhat):
         outs.append(Xhat)
         grads.append(torch.as_tensor(grad_Xhat, dtype=torch.complex128))
     torch.autograd.backward(outs, grads)
-    return [t.grad.numpy().copy() if t.grad is not None else np.zeros(t.shape, np.complex128)
+    return [t.grad.resolve_conj().numpy().copy() if t.grad is not None
+            else np.zeros(t.shape, np.complex128)
             for t in ts]

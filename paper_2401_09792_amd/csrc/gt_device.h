@@ -118,32 +118,76 @@ __device__ __forceinline__ void rr_pair(int t, int r, int& pos, int& partner) {
   partner = (ppos == 0) ? 0 : ((ppos - 1 + t) % N1) + 1;
 }
 
-// Returns true if the off-diagonal part fell below eps relative to the diagonal within
-// max_sweeps sweeps.  On exit kr/ki is (nearly) diagonal and vr/vi holds the eigenvectors
-// as columns (row r in lane r).
-template <typename T, int MP>
-__device__ bool jacobi_herm(EigLds<T, MP>& L, int r, int max_sweeps) {
-  for (int j = 0; j < MP; ++j) {
-    L.vr[r][j] = (j == r) ? T(1) : T(0);
-    L.vi[r][j] = T(0);
+// Synchronisation for the Jacobi step: a wave-level fence when one wave owns the matrix, a
+// block barrier when NW waves share it.
+template <int NW>
+__device__ __forceinline__ void jsync() {
+  if (NW == 1)
+    wave_sync();
+  else
+    __syncthreads();
+}
+
+// Cyclic Jacobi sweeps on L.kr/ki.  Lane r (0 <= r < MP) of every cooperating wave owns row
+// r.  With NW > 1 (MP == 64 only) the NW waves of the block share one matrix: wave w applies
+// the rotations of pairs k = w, w + NW, ... to both the matrix and the eigenvectors; the
+// column sets of different pairs are disjoint, so waves only meet at two barriers per step.
+// With NW == 1 a wave may hold 64/MP matrices.  If `preset_v` is false V starts as the
+// identity, otherwise the caller has stored a starting basis in vr/vi (the rotations are then
+// accumulated onto it).  Returns true once the off-diagonal Frobenius norm is below
+// 2 eps times the diagonal norm for every matrix of the wave (or block).
+template <typename T, int MP, int NW>
+__device__ bool jacobi_herm(EigLds<T, MP>& L, int r, int wave, int max_sweeps,
+                            bool preset_v = false) {
+  static_assert(NW == 1 || MP == 64, "multi-wave Jacobi needs MP == 64");
+  constexpr int KP = MP / 2;
+  constexpr int KW = KP / NW;
+  constexpr int KC = (sizeof(T) == 4) ? (KW < 8 ? KW : 8) : (KW < 4 ? KW : 4);
+  static_assert(KW % KC == 0, "chunk must divide the pairs per wave");
+  if (!preset_v && wave == 0) {
+    for (int j = 0; j < MP; ++j) {
+      L.vr[r][j] = (j == r) ? T(1) : T(0);
+      L.vi[r][j] = T(0);
+    }
   }
-  wave_sync();
+  jsync<NW>();
   const T eps = Num<T>::eps();
   bool conv = false;
   for (int sw = 0; sw <= max_sweeps; ++sw) {
-    T off = 0, dg = 0;
-    for (int j = 0; j < MP; ++j) {
-      T a = L.kr[r][j], b = L.ki[r][j];
-      T v = a * a + b * b;
-      if (j == r)
-        dg += v;
-      else
-        off += v;
+    bool done;
+    if (NW == 1) {
+      T off = 0, dg = 0;
+      for (int j = 0; j < MP; ++j) {
+        T a = L.kr[r][j], b = L.ki[r][j];
+        T v = a * a + b * b;
+        if (j == r)
+          dg += v;
+        else
+          off += v;
+      }
+      off = group_sum<MP>(off);
+      dg = group_sum<MP>(dg);
+      done = wave_all(off <= T(4) * eps * eps * dg);
+    } else {
+      if (wave == 0) {
+        T off = 0, dg = 0;
+        for (int j = 0; j < MP; ++j) {
+          T a = L.kr[r][j], b = L.ki[r][j];
+          T v = a * a + b * b;
+          if (j == r)
+            dg += v;
+          else
+            off += v;
+        }
+        off = group_sum<MP>(off);
+        dg = group_sum<MP>(dg);
+        if (r == 0) L.src[0] = (off <= T(4) * eps * eps * dg) ? 1 : 0;
+      }
+      __syncthreads();
+      done = L.src[0] != 0;
+      __syncthreads();
     }
-    off = group_sum<MP>(off);
-    dg = group_sum<MP>(dg);
-    bool done = off <= T(4) * eps * eps * dg;
-    if (wave_all(done)) {
+    if (done) {
       conv = true;
       break;
     }
@@ -152,7 +196,7 @@ __device__ bool jacobi_herm(EigLds<T, MP>& L, int r, int max_sweeps) {
       int pos, partner;
       rr_pair<MP>(t, r, pos, partner);
       const bool first = pos < MP / 2;
-      if (first) {
+      if (first && wave == 0) {
         T a = L.kr[r][r], b = L.kr[partner][partner];
         T cre = L.kr[r][partner], cim = L.ki[r][partner];
         T ac = dsqrt(cre * cre + cim * cim);
@@ -173,50 +217,62 @@ __device__ bool jacobi_herm(EigLds<T, MP>& L, int r, int max_sweeps) {
         L.rp[pos] = r;
         L.rq[pos] = partner;
       }
-      wave_sync();
+      jsync<NW>();
       const int slot = first ? pos : (MP - 1 - pos);
       const T csr = L.rc[slot];
-      const T srr = L.rsr[slot], sri = L.rsi[slot];
-      for (int k = 0; k < MP / 2; ++k) {
-        const int p = L.rp[k], q = L.rq[k];
-        const T cs = L.rc[k];
-        const Cx<T> s{L.rsr[k], L.rsi[k]};
-        Cx<T> x{L.kr[r][p], L.ki[r][p]}, y{L.kr[r][q], L.ki[r][q]};
-        Cx<T> xp{L.kr[partner][p], L.ki[partner][p]}, yp{L.kr[partner][q], L.ki[partner][q]};
-        Cx<T> Rx, Ry;
-        if (first) {  // row r = p of its pair: cs*row_p + s*row_q
-          Cx<T> sv{srr, sri};
-          Cx<T> a1 = cmul(sv, xp), a2 = cmul(sv, yp);
-          Rx = {csr * x.re + a1.re, csr * x.im + a1.im};
-          Ry = {csr * y.re + a2.re, csr * y.im + a2.im};
-        } else {      // row r = q of its pair: -conj(s)*row_p + cs*row_q
-          Cx<T> sv{srr, sri};
-          Cx<T> a1 = cmulc(sv, xp), a2 = cmulc(sv, yp);
-          Rx = {csr * x.re - a1.re, csr * x.im - a1.im};
-          Ry = {csr * y.re - a2.re, csr * y.im - a2.im};
+      const Cx<T> sv{L.rsr[slot], L.rsi[slot]};
+#pragma unroll
+      for (int kb = 0; kb < KW; kb += KC) {
+        Cx<T> x[KC], y[KC], xp[KC], yp[KC], vp[KC], vq[KC];
+        int pk[KC], qk[KC];
+#pragma unroll
+        for (int c = 0; c < KC; ++c) {
+          const int k = wave + NW * (kb + c);
+          const int p = L.rp[k], q = L.rq[k];
+          pk[c] = p;
+          qk[c] = q;
+          x[c] = {L.kr[r][p], L.ki[r][p]};
+          y[c] = {L.kr[r][q], L.ki[r][q]};
+          xp[c] = {L.kr[partner][p], L.ki[partner][p]};
+          yp[c] = {L.kr[partner][q], L.ki[partner][q]};
+          vp[c] = {L.vr[r][p], L.vi[r][p]};
+          vq[c] = {L.vr[r][q], L.vi[r][q]};
         }
-        // columns: (K J)[:,p] = K[:,p] cs + K[:,q] conj(s); (K J)[:,q] = -K[:,p] s + K[:,q] cs
-        Cx<T> b1 = cmulc(s, Ry);  // conj(s) * Ry
-        Cx<T> b2 = cmul(Rx, s);
-        Cx<T> nx{Rx.re * cs + b1.re, Rx.im * cs + b1.im};
-        Cx<T> ny{Ry.re * cs - b2.re, Ry.im * cs - b2.im};
-        if (r == p) ny = {T(0), T(0)};
-        if (r == q) nx = {T(0), T(0)};
-        Cx<T> vp{L.vr[r][p], L.vi[r][p]}, vq{L.vr[r][q], L.vi[r][q]};
-        Cx<T> c1 = cmulc(s, vq), c2 = cmul(vp, s);
-        Cx<T> nvp{vp.re * cs + c1.re, vp.im * cs + c1.im};
-        Cx<T> nvq{vq.re * cs - c2.re, vq.im * cs - c2.im};
         wave_sync();
-        L.kr[r][p] = nx.re;
-        L.ki[r][p] = nx.im;
-        L.kr[r][q] = ny.re;
-        L.ki[r][q] = ny.im;
-        L.vr[r][p] = nvp.re;
-        L.vi[r][p] = nvp.im;
-        L.vr[r][q] = nvq.re;
-        L.vi[r][q] = nvq.im;
+#pragma unroll
+        for (int c = 0; c < KC; ++c) {
+          const int k = wave + NW * (kb + c);
+          const int p = pk[c], q = qk[c];
+          const T cs = L.rc[k];
+          const Cx<T> s{L.rsr[k], L.rsi[k]};
+          Cx<T> Rx, Ry;
+          if (first) {  // row r = p of its pair: cs*row_p + s*row_q
+            Cx<T> a1 = cmul(sv, xp[c]), a2 = cmul(sv, yp[c]);
+            Rx = {csr * x[c].re + a1.re, csr * x[c].im + a1.im};
+            Ry = {csr * y[c].re + a2.re, csr * y[c].im + a2.im};
+          } else {      // row r = q of its pair: -conj(s)*row_p + cs*row_q
+            Cx<T> a1 = cmulc(sv, xp[c]), a2 = cmulc(sv, yp[c]);
+            Rx = {csr * x[c].re - a1.re, csr * x[c].im - a1.im};
+            Ry = {csr * y[c].re - a2.re, csr * y[c].im - a2.im};
+          }
+          // (K J)[:,p] = K[:,p] cs + K[:,q] conj(s);  (K J)[:,q] = -K[:,p] s + K[:,q] cs
+          Cx<T> b1 = cmulc(s, Ry), b2 = cmul(Rx, s);
+          Cx<T> nx{Rx.re * cs + b1.re, Rx.im * cs + b1.im};
+          Cx<T> ny{Ry.re * cs - b2.re, Ry.im * cs - b2.im};
+          if (r == p) ny = {T(0), T(0)};
+          if (r == q) nx = {T(0), T(0)};
+          Cx<T> c1 = cmulc(s, vq[c]), c2 = cmul(vp[c], s);
+          L.kr[r][p] = nx.re;
+          L.ki[r][p] = nx.im;
+          L.kr[r][q] = ny.re;
+          L.ki[r][q] = ny.im;
+          L.vr[r][p] = vp[c].re * cs + c1.re;
+          L.vi[r][p] = vp[c].im * cs + c1.im;
+          L.vr[r][q] = vq[c].re * cs - c2.re;
+          L.vi[r][q] = vq[c].im * cs - c2.im;
+        }
       }
-      wave_sync();
+      jsync<NW>();
     }
   }
   return conv;

@@ -147,6 +147,30 @@ __global__ void __launch_bounds__(256) k_gram_rows(const DevChan* __restrict__ c
   if (j < nt && k < nt) st(wsp(ws, ch.w_S2p) + ((int64_t)split * nt + j) * nt + k, acc);
 }
 
+// S1 = sum of the per-group partials (fixed order, four independent accumulators).
+__global__ void k_reduce_S1(const DevChan* __restrict__ chans, char* ws) {
+  CH_BEGIN(blockIdx.y);
+  const int nn = ch.nr * ch.nr;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nn) return;
+  const float2* P = wsp(ws, ch.w_S1p);
+  float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
+  int g = 0;
+  for (; g + 4 <= ch.ngroups; g += 4)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      float2 v = P[(int64_t)(g + u) * nn + e];
+      ar[u] += v.x;
+      ai[u] += v.y;
+    }
+  for (; g < ch.ngroups; ++g) {
+    float2 v = P[(int64_t)g * nn + e];
+    ar[0] += v.x;
+    ai[0] += v.y;
+  }
+  st(wsp(ws, ch.w_S1) + e, Cx<float>{(ar[0] + ar[1]) + (ar[2] + ar[3]), (ai[0] + ai[1]) + (ai[2] + ai[3])});
+}
+
 // S2 = sum of the split partials (fixed order).
 __global__ void k_reduce_S2(const DevChan* __restrict__ chans, char* ws) {
   CH_BEGIN(blockIdx.y);
@@ -212,18 +236,15 @@ __global__ void __launch_bounds__(64) k_eigA(const DevChan* __restrict__ chans, 
   for (int j = 0; j < MP; ++j) {
     T sr = 0, si = 0;
     if (r < d && j < d) {
-      const float2* P = wsp(ws, chp->w_S1p);
-      for (int g = 0; g < chp->ngroups; ++g) {
-        float2 v = P[((int64_t)g * d + r) * d + j];
-        sr += (T)v.x;
-        si += (T)v.y;
-      }
+      float2 v = wsp(ws, chp->w_S1)[(int64_t)r * d + j];
+      sr = (T)v.x;
+      si = (T)v.y;
     }
     L.kr[r][j] = sr;
     L.ki[r][j] = si;
   }
   wave_sync();
-  bool conv = jacobi_herm<T, MP>(L, r, sizeof(T) == 4 ? 12 : 20);
+  bool conv = jacobi_herm<T, MP, 1>(L, r, 0, sizeof(T) == 4 ? 12 : 20);
   if (valid) {
     double* ls = wsd(ws, chp->w_scal) + 1;
     eig_finish<T, MP>(L, r, d, chp->m, write_factor ? A + chp->a : nullptr, chp->m, chp->m, ls,
@@ -233,31 +254,33 @@ __global__ void __launch_bounds__(64) k_eigA(const DevChan* __restrict__ chans, 
   }
 }
 
-// mode-2: one wave per channel, nt <= 64
-template <typename T>
-__global__ void __launch_bounds__(64) k_eigB(const DevChan* __restrict__ chans, char* ws,
-                                             float2* B, int32_t* status, int write_factor) {
+// mode-2: one block of NW waves per channel, nt <= 64
+template <typename T, int NW>
+__global__ void __launch_bounds__(64 * NW) k_eigB(const DevChan* __restrict__ chans, char* ws,
+                                                  float2* B, int32_t* status, int write_factor) {
   constexpr int MP = 64;
   __shared__ EigLds<T, MP> L;
-  const int r = threadIdx.x;
+  const int r = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int c = blockIdx.x;
   const DevChan& ch = chans[c];
   const int d = ch.nt;
   const float2* S = wsp(ws, ch.w_S2);
-  for (int j = 0; j < MP; ++j) {
+  for (int e = threadIdx.x; e < MP * MP; e += 64 * NW) {
+    const int i = e / MP, j = e % MP;
     T sr = 0, si = 0;
-    if (r < d && j < d) {
-      float2 v = S[(int64_t)r * d + j];
+    if (i < d && j < d) {
+      float2 v = S[(int64_t)i * d + j];
       sr = (T)v.x;
       si = (T)v.y;
     }
-    L.kr[r][j] = sr;
-    L.ki[r][j] = si;
+    L.kr[i][j] = sr;
+    L.ki[i][j] = si;
   }
-  wave_sync();
-  bool conv = jacobi_herm<T, MP>(L, r, sizeof(T) == 4 ? 12 : 20);
-  eig_finish<T, MP>(L, r, d, ch.n, write_factor ? B + ch.b : nullptr, ch.n, ch.n,
-                    wsd(ws, ch.w_scal) + 2, status ? status + c : nullptr, conv);
+  __syncthreads();
+  bool conv = jacobi_herm<T, MP, NW>(L, r, wave, sizeof(T) == 4 ? 12 : 20);
+  if (wave == 0)
+    eig_finish<T, MP>(L, r, d, ch.n, write_factor ? B + ch.b : nullptr, ch.n, ch.n,
+                      wsd(ws, ch.w_scal) + 2, status ? status + c : nullptr, conv);
 }
 
 // mode-3: one MP-lane group per subcarrier group
@@ -289,7 +312,7 @@ __global__ void __launch_bounds__(64) k_eigC(const DevChan* __restrict__ chans,
     L.ki[r][j] = si;
   }
   wave_sync();
-  bool conv = jacobi_herm<T, MP>(L, r, sizeof(T) == 4 ? 12 : 20);
+  bool conv = jacobi_herm<T, MP, 1>(L, r, 0, sizeof(T) == 4 ? 12 : 20);
   if (valid) {
     const int pg = min(ch.p, d);
     eig_finish<T, MP>(L, r, d, pg, write_factor ? C + ch.c + (int64_t)s0 * ch.p : nullptr, ch.p,
@@ -530,10 +553,13 @@ template <typename T>
 static gt_status eig_all(const LaunchCtx& L, int which, float2* A, float2* B, float2* C,
                          int32_t* status, int write) {
   if (which == 0) {
+    GT_LAUNCH(k_reduce_S1, dim3(cdiv(L.max_nr * L.max_nr, 256), L.n_channels), dim3(256), L.d_chans,
+              L.ws);
     GT_LAUNCH((k_eigA<T, 16>), dim3(cdiv(L.n_channels, 4)), dim3(64), L.d_chans, L.n_channels,
               L.ws, A, status, write);
   } else if (which == 1) {
-    GT_LAUNCH((k_eigB<T>), dim3(L.n_channels), dim3(64), L.d_chans, L.ws, B, status, write);
+    constexpr int NW = sizeof(T) == 4 ? 4 : 8;
+    GT_LAUNCH((k_eigB<T, NW>), dim3(L.n_channels), dim3(64 * NW), L.d_chans, L.ws, B, status, write);
   } else {
     if (L.max_gs <= 16) {
       GT_LAUNCH((k_eigC<T, 16>), dim3(cdiv(L.total_groups, 4)), dim3(64), L.d_chans, L.d_groups,

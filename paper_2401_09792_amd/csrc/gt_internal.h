@@ -26,6 +26,7 @@ struct DevChan {
   int64_t w_T;     // [nsc][nr][n]        c64   H_s B
   int64_t w_Yh;    // [nsc][m][n]         c64   A^H H_s B
   int64_t w_S1p;   // [ngroups][nr][nr]   c64   per-group mode-1 Gram
+  int64_t w_S1;    // [nr][nr]            c64   mode-1 Gram
   int64_t w_S2p;   // [nsplit][nt][nt]    c64   split partials of the mode-2 Gram
   int64_t w_S2;    // [nt][nt]            c64   mode-2 Gram
   int64_t w_S3;    // [ngroups][gs][gs]   c64   per-group mode-3 Gram

@@ -203,6 +203,7 @@ gt_status gt_plan_create(const gt_channel_desc* descs, int32_t n_channels, const
     ch.w_T = take(c8 * ch.nsc * ch.nr * ch.n);
     ch.w_Yh = take(c8 * ch.nsc * ch.m * ch.n);
     ch.w_S1p = take(c8 * ch.ngroups * ch.nr * ch.nr);
+    ch.w_S1 = take(c8 * ch.nr * ch.nr);
     ch.w_S2p = take(c8 * ch.nsplit * ch.nt * ch.nt);
     ch.w_S2 = take(c8 * ch.nt * ch.nt);
     ch.w_S3 = take(c8 * ch.ngroups * ch.gs * ch.gs);

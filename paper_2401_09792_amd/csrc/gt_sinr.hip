@@ -238,7 +238,7 @@ __global__ void __launch_bounds__(64) k_sinr(const DevChan* __restrict__ chans, 
   const int64_t s = gsc - ch.sc;
   int M, N;
   build_gram<T, MP, NMAX, FULL>(S, r, valid, ch, s, X, C, G, M, N);
-  bool conv = jacobi_herm<T, MP>(S.e, r, sizeof(T) == 4 ? 12 : 20);
+  bool conv = jacobi_herm<T, MP, 1>(S.e, r, 0, sizeof(T) == 4 ? 12 : 20);
   uint32_t bits = conv ? 0u : GT_DEV_EIG_SWEEPS;
   const int ns = valid ? ch.ns : 0;
   singular_setup<T, MP, NMAX>(S, r, M, ns, bits);
@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(64) k_sinr_bwd(const DevChan* __restrict__ cha
   const int64_t s = gsc - ch.sc;
   int M, N;
   build_gram<T, MP, NMAX, false>(S, r, valid, ch, s, nullptr, C, G, M, N);
-  bool conv = jacobi_herm<T, MP>(S.e, r, sizeof(T) == 4 ? 12 : 20);
+  bool conv = jacobi_herm<T, MP, 1>(S.e, r, 0, sizeof(T) == 4 ? 12 : 20);
   uint32_t bits = conv ? 0u : GT_DEV_EIG_SWEEPS;
   const int ns = valid ? ch.ns : 0;
   singular_setup<T, MP, NMAX>(S, r, M, ns, bits);

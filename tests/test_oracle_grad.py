@@ -57,3 +57,31 @@ def test_reconstruct_gradcheck_fd():
     ts = [torch.tensor(v, requires_grad=True) for v in (A, B, C, G)]
     f = lambda a, b, c, g: grad.reconstruct_t(a, b, c, g, 4)
     assert torch.autograd.gradcheck(f, tuple(ts), eps=1e-6, atol=1e-6, rtol=1e-5)
+
+
+def test_reconstruct_grad_directional_fd():
+    # l = Re<gHt, Ht> + Re<gX, Xhat>; its derivative along a random direction equals
+    # Re sum conj(grad) * direction for each of A, B, C, G (central differences, FP64)
+    rng = np.random.default_rng(6)
+    C, G = _small_compressed(seed=7, m=2, n=3, p=2, gs=4, nsc=6)
+    A = synthgen.random_unitary(rng, 3, 2)
+    Bm = synthgen.random_unitary(rng, 5, 3)
+    gHt = rng.standard_normal((6, 2, 3)) + 1j * rng.standard_normal((6, 2, 3))
+    gX = rng.standard_normal((6, 3, 5)) + 1j * rng.standard_normal((6, 3, 5))
+    grads = grad.reconstruct_grad(A, Bm, C, G, 4, gHt, gX)
+
+    def loss(a, b, c, g):
+        Ht, Xh = tucker.reconstruct(a, b, c, g, 4)
+        return float(np.real(np.sum(np.conj(gHt) * Ht) + np.sum(np.conj(gX) * Xh)))
+
+    args = [A, Bm, C, G]
+    h = 1e-6
+    for i, gr in enumerate(grads):
+        d = rng.standard_normal(args[i].shape) + 1j * rng.standard_normal(args[i].shape)
+        up = list(args)
+        dn = list(args)
+        up[i] = args[i] + h * d
+        dn[i] = args[i] - h * d
+        fd = (loss(*up) - loss(*dn)) / (2 * h)
+        an = float(np.real(np.sum(np.conj(gr) * d)))
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (i, fd, an)
