@@ -278,6 +278,204 @@ __device__ bool jacobi_herm(EigLds<T, MP>& L, int r, int wave, int max_sweeps,
   return conv;
 }
 
+// Warm start: K <- V^H K V, with the starting basis V already in L.vr/vi (one MP-lane group
+// per matrix, lane r owns row r).  tr/ti is scratch of the matrix's shape.  After this the
+// Jacobi sweeps run with preset_v = true and accumulate their rotations onto V.
+template <typename T, int MP>
+__device__ void rotate_into_basis(EigLds<T, MP>& L, T (*tr)[MP + 1], T (*ti)[MP + 1], int r) {
+  for (int j = 0; j < MP; ++j) {  // (K V)[r][j]
+    T ar = 0, ai = 0;
+    for (int k = 0; k < MP; ++k) {
+      T kr = L.kr[r][k], ki = L.ki[r][k], vr = L.vr[k][j], vi = L.vi[k][j];
+      ar += kr * vr - ki * vi;
+      ai += kr * vi + ki * vr;
+    }
+    tr[r][j] = ar;
+    ti[r][j] = ai;
+  }
+  wave_sync();
+  for (int j = 0; j < MP; ++j) {  // (V^H (K V))[r][j]
+    T ar = 0, ai = 0;
+    for (int k = 0; k < MP; ++k) {
+      T vr = L.vr[k][r], vi = L.vi[k][r], xr = tr[k][j], xi = ti[k][j];
+      ar += vr * xr + vi * xi;
+      ai += vr * xi - vi * xr;
+    }
+    L.kr[r][j] = ar;
+    L.ki[r][j] = ai;
+  }
+  wave_sync();
+}
+
+// One Newton-Schulz step V <- V (3 I - V^H V) / 2 on the starting basis in L.vr/vi: bases
+// carried from call to call in FP32 slowly lose orthonormality under many rotations, and the
+// step squares that error.  Uses L.kr/ki and tr/ti as scratch, so it runs before the matrix
+// is loaded.
+template <typename T, int MP>
+__device__ void reorthonormalize(EigLds<T, MP>& L, T (*tr)[MP + 1], T (*ti)[MP + 1], int r) {
+  for (int j = 0; j < MP; ++j) {  // E = V^H V, row r
+    T ar = 0, ai = 0;
+    for (int k = 0; k < MP; ++k) {
+      T xr = L.vr[k][r], xi = L.vi[k][r], yr = L.vr[k][j], yi = L.vi[k][j];
+      ar += xr * yr + xi * yi;
+      ai += xr * yi - xi * yr;
+    }
+    tr[r][j] = ar;
+    ti[r][j] = ai;
+  }
+  wave_sync();
+  for (int j = 0; j < MP; ++j) {  // row r of 1.5 V - 0.5 V E
+    T ar = 0, ai = 0;
+    for (int k = 0; k < MP; ++k) {
+      T xr = L.vr[r][k], xi = L.vi[r][k], yr = tr[k][j], yi = ti[k][j];
+      ar += xr * yr - xi * yi;
+      ai += xr * yi + xi * yr;
+    }
+    L.kr[r][j] = T(1.5) * L.vr[r][j] - T(0.5) * ar;
+    L.ki[r][j] = T(1.5) * L.vi[r][j] - T(0.5) * ai;
+  }
+  wave_sync();
+  for (int j = 0; j < MP; ++j) {
+    L.vr[r][j] = L.kr[r][j];
+    L.vi[r][j] = L.ki[r][j];
+  }
+  wave_sync();
+}
+
+// Block version for MP = 64 and 256 threads.
+template <typename T>
+__device__ void reorthonormalize64(EigLds<T, 64>& L, T (*tr)[65], T (*ti)[65]) {
+  const int t = threadIdx.x;
+  const int bi = (t / 16) * 4, bj = (t % 16) * 4;
+  T ar[4][4], ai[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) ar[a][b] = ai[a][b] = 0;
+  for (int k = 0; k < 64; ++k) {  // E = V^H V
+    T xr[4], xi[4], yr[4], yi[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      xr[a] = L.vr[k][bi + a];
+      xi[a] = -L.vi[k][bi + a];
+      yr[a] = L.vr[k][bj + a];
+      yi[a] = L.vi[k][bj + a];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        ar[a][b] += xr[a] * yr[b] - xi[a] * yi[b];
+        ai[a][b] += xr[a] * yi[b] + xi[a] * yr[b];
+      }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      tr[bi + a][bj + b] = ar[a][b];
+      ti[bi + a][bj + b] = ai[a][b];
+      ar[a][b] = ai[a][b] = 0;
+    }
+  __syncthreads();
+  for (int k = 0; k < 64; ++k) {  // V E
+    T xr[4], xi[4], yr[4], yi[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      xr[a] = L.vr[bi + a][k];
+      xi[a] = L.vi[bi + a][k];
+      yr[a] = tr[k][bj + a];
+      yi[a] = ti[k][bj + a];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        ar[a][b] += xr[a] * yr[b] - xi[a] * yi[b];
+        ai[a][b] += xr[a] * yi[b] + xi[a] * yr[b];
+      }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      L.kr[bi + a][bj + b] = T(1.5) * L.vr[bi + a][bj + b] - T(0.5) * ar[a][b];
+      L.ki[bi + a][bj + b] = T(1.5) * L.vi[bi + a][bj + b] - T(0.5) * ai[a][b];
+    }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      L.vr[bi + a][bj + b] = L.kr[bi + a][bj + b];
+      L.vi[bi + a][bj + b] = L.ki[bi + a][bj + b];
+    }
+  __syncthreads();
+}
+
+// The same for MP = 64 shared by a block of 256 threads (4 x 4 output tile per thread).
+template <typename T>
+__device__ void rotate_into_basis64(EigLds<T, 64>& L, T (*tr)[65], T (*ti)[65]) {
+  const int t = threadIdx.x;
+  const int bi = (t / 16) * 4, bj = (t % 16) * 4;
+  T ar[4][4], ai[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) ar[a][b] = ai[a][b] = 0;
+  for (int k = 0; k < 64; ++k) {
+    T xr[4], xi[4], yr[4], yi[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      xr[a] = L.kr[bi + a][k];
+      xi[a] = L.ki[bi + a][k];
+      yr[a] = L.vr[k][bj + a];
+      yi[a] = L.vi[k][bj + a];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        ar[a][b] += xr[a] * yr[b] - xi[a] * yi[b];
+        ai[a][b] += xr[a] * yi[b] + xi[a] * yr[b];
+      }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      tr[bi + a][bj + b] = ar[a][b];
+      ti[bi + a][bj + b] = ai[a][b];
+      ar[a][b] = ai[a][b] = 0;
+    }
+  __syncthreads();
+  for (int k = 0; k < 64; ++k) {
+    T xr[4], xi[4], yr[4], yi[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      xr[a] = L.vr[k][bi + a];  // conj(V[k][i])
+      xi[a] = -L.vi[k][bi + a];
+      yr[a] = tr[k][bj + a];
+      yi[a] = ti[k][bj + a];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        ar[a][b] += xr[a] * yr[b] - xi[a] * yi[b];
+        ai[a][b] += xr[a] * yi[b] + xi[a] * yr[b];
+      }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      L.kr[bi + a][bj + b] = ar[a][b];
+      L.ki[bi + a][bj + b] = ai[a][b];
+    }
+  __syncthreads();
+}
+
 // After jacobi_herm: eigenvalues sorted descending over the first d indices (padding last).
 // L.src[j] = index of the j-th largest eigenvalue; L.lam[i] = eigenvalue i.
 template <typename T, int MP>

@@ -220,19 +220,49 @@ __device__ void eig_finish(EigLds<T, MP>& L, int r, int d, int rk, float2* dst, 
   }
 }
 
+// Warm starts (FP32 eigensolves only): every eigen kernel stores its full eigenbasis in the
+// workspace; the next call on the same Gram family rotates the new Gram into that basis
+// before the sweeps, so only the change since the last call remains to be diagonalised.
+
+template <typename T, int MP>
+__device__ void load_basis(EigLds<T, MP>& L, const float2* V, int r) {
+  for (int j = 0; j < MP; ++j) {
+    float2 v = V[r * MP + j];
+    L.vr[r][j] = (T)v.x;
+    L.vi[r][j] = (T)v.y;
+  }
+}
+
+template <typename T, int MP>
+__device__ void store_basis(const EigLds<T, MP>& L, float2* V, int r) {
+  for (int j = 0; j < MP; ++j) V[r * MP + j] = make_float2((float)L.vr[r][j], (float)L.vi[r][j]);
+}
+
 // mode-1: one MP-lane group per channel
 template <typename T, int MP>
 __global__ void __launch_bounds__(64) k_eigA(const DevChan* __restrict__ chans, int n_channels,
-                                              char* ws, float2* A, int32_t* status,
-                                              int write_factor) {
+                                              char* ws, float2* A, int32_t* status, int warm) {
   constexpr int GPW = 64 / MP;
   __shared__ EigLds<T, MP> lds[GPW];
+  __shared__ T tr[GPW][MP][MP + 1], ti[GPW][MP][MP + 1];
   const int grp = threadIdx.x / MP, r = threadIdx.x % MP;
   const int c = blockIdx.x * GPW + grp;
   EigLds<T, MP>& L = lds[grp];
   const bool valid = c < n_channels;
   const DevChan* chp = valid ? &chans[c] : nullptr;
   const int d = valid ? chp->nr : 0;
+  const bool use_warm = warm && sizeof(T) == 4;
+  if (use_warm) {
+    if (valid)
+      load_basis<T, MP>(L, wsp(ws, chp->w_VA), r);
+    else
+      for (int j = 0; j < MP; ++j) {
+        L.vr[r][j] = (j == r) ? T(1) : T(0);
+        L.vi[r][j] = T(0);
+      }
+    wave_sync();
+    reorthonormalize<T, MP>(L, tr[grp], ti[grp], r);
+  }
   for (int j = 0; j < MP; ++j) {
     T sr = 0, si = 0;
     if (r < d && j < d) {
@@ -244,10 +274,13 @@ __global__ void __launch_bounds__(64) k_eigA(const DevChan* __restrict__ chans, 
     L.ki[r][j] = si;
   }
   wave_sync();
-  bool conv = jacobi_herm<T, MP, 1>(L, r, 0, sizeof(T) == 4 ? 12 : 20);
+  if (use_warm) rotate_into_basis<T, MP>(L, tr[grp], ti[grp], r);
+  wave_sync();
+  bool conv = jacobi_herm<T, MP, 1>(L, r, 0, sizeof(T) == 4 ? 12 : 20, use_warm);
   if (valid) {
+    if (sizeof(T) == 4) store_basis<T, MP>(L, wsp(ws, chp->w_VA), r);
     double* ls = wsd(ws, chp->w_scal) + 1;
-    eig_finish<T, MP>(L, r, d, chp->m, write_factor ? A + chp->a : nullptr, chp->m, chp->m, ls,
+    eig_finish<T, MP>(L, r, d, chp->m, A + chp->a, chp->m, chp->m, ls,
                       status ? status + c : nullptr, conv);
   } else {
     eig_sort_desc<T, MP>(L, r, 0);
@@ -257,14 +290,27 @@ __global__ void __launch_bounds__(64) k_eigA(const DevChan* __restrict__ chans, 
 // mode-2: one block of NW waves per channel, nt <= 64
 template <typename T, int NW>
 __global__ void __launch_bounds__(64 * NW) k_eigB(const DevChan* __restrict__ chans, char* ws,
-                                                  float2* B, int32_t* status, int write_factor) {
+                                                  float2* B, int32_t* status, int warm) {
   constexpr int MP = 64;
+  constexpr bool kWarmOk = sizeof(T) == 4 && NW == 4;
   __shared__ EigLds<T, MP> L;
+  __shared__ T tr[kWarmOk ? MP : 1][MP + 1], ti[kWarmOk ? MP : 1][MP + 1];
   const int r = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int c = blockIdx.x;
   const DevChan& ch = chans[c];
   const int d = ch.nt;
   const float2* S = wsp(ws, ch.w_S2);
+  float2* VB = wsp(ws, ch.w_VB);
+  const bool use_warm = kWarmOk && warm;
+  if (use_warm) {
+    for (int e = threadIdx.x; e < MP * MP; e += 64 * NW) {
+      float2 v = VB[e];
+      L.vr[e / MP][e % MP] = (T)v.x;
+      L.vi[e / MP][e % MP] = (T)v.y;
+    }
+    __syncthreads();
+    if (kWarmOk) reorthonormalize64<T>(L, reinterpret_cast<T(*)[65]>(tr), reinterpret_cast<T(*)[65]>(ti));
+  }
   for (int e = threadIdx.x; e < MP * MP; e += 64 * NW) {
     const int i = e / MP, j = e % MP;
     T sr = 0, si = 0;
@@ -277,10 +323,15 @@ __global__ void __launch_bounds__(64 * NW) k_eigB(const DevChan* __restrict__ ch
     L.ki[i][j] = si;
   }
   __syncthreads();
-  bool conv = jacobi_herm<T, MP, NW>(L, r, wave, sizeof(T) == 4 ? 12 : 20);
+  if (kWarmOk && use_warm) rotate_into_basis64<T>(L, reinterpret_cast<T(*)[65]>(tr),
+                                                  reinterpret_cast<T(*)[65]>(ti));
+  bool conv = jacobi_herm<T, MP, NW>(L, r, wave, sizeof(T) == 4 ? 12 : 20, use_warm);
+  if (sizeof(T) == 4)
+    for (int e = threadIdx.x; e < MP * MP; e += 64 * NW)
+      VB[e] = make_float2((float)L.vr[e / MP][e % MP], (float)L.vi[e / MP][e % MP]);
   if (wave == 0)
-    eig_finish<T, MP>(L, r, d, ch.n, write_factor ? B + ch.b : nullptr, ch.n, ch.n,
-                      wsd(ws, ch.w_scal) + 2, status ? status + c : nullptr, conv);
+    eig_finish<T, MP>(L, r, d, ch.n, B + ch.b, ch.n, ch.n, wsd(ws, ch.w_scal) + 2,
+                      status ? status + c : nullptr, conv);
 }
 
 // mode-3: one MP-lane group per subcarrier group
@@ -288,9 +339,10 @@ template <typename T, int MP>
 __global__ void __launch_bounds__(64) k_eigC(const DevChan* __restrict__ chans,
                                               const GroupItem* __restrict__ items,
                                               int total_groups, char* ws, float2* C,
-                                              int32_t* status, int write_factor) {
+                                              int32_t* status, int warm) {
   constexpr int GPW = 64 / MP;
   __shared__ EigLds<T, MP> lds[GPW];
+  __shared__ T tr[GPW][MP][MP + 1], ti[GPW][MP][MP + 1];
   const int grp = threadIdx.x / MP, r = threadIdx.x % MP;
   const int gi = blockIdx.x * GPW + grp;
   EigLds<T, MP>& L = lds[grp];
@@ -301,6 +353,19 @@ __global__ void __launch_bounds__(64) k_eigC(const DevChan* __restrict__ chans,
   const int s0 = it.g * ch.gs;
   const int d = valid ? min(ch.gs, ch.nsc - s0) : 0;
   const float2* S = wsp(ws, ch.w_S3) + (int64_t)it.g * ch.gs * ch.gs;
+  float2* VC = wsp(ws, ch.w_VC) + (int64_t)it.g * MP * MP;
+  const bool use_warm = warm && sizeof(T) == 4;
+  if (use_warm) {
+    if (valid)
+      load_basis<T, MP>(L, VC, r);
+    else
+      for (int j = 0; j < MP; ++j) {
+        L.vr[r][j] = (j == r) ? T(1) : T(0);
+        L.vi[r][j] = T(0);
+      }
+    wave_sync();
+    reorthonormalize<T, MP>(L, tr[grp], ti[grp], r);
+  }
   for (int j = 0; j < MP; ++j) {
     T sr = 0, si = 0;
     if (r < d && j < d) {
@@ -312,11 +377,14 @@ __global__ void __launch_bounds__(64) k_eigC(const DevChan* __restrict__ chans,
     L.ki[r][j] = si;
   }
   wave_sync();
-  bool conv = jacobi_herm<T, MP, 1>(L, r, 0, sizeof(T) == 4 ? 12 : 20);
+  if (use_warm) rotate_into_basis<T, MP>(L, tr[grp], ti[grp], r);
+  wave_sync();
+  bool conv = jacobi_herm<T, MP, 1>(L, r, 0, sizeof(T) == 4 ? 12 : 20, use_warm);
   if (valid) {
+    if (sizeof(T) == 4) store_basis<T, MP>(L, VC, r);
     const int pg = min(ch.p, d);
-    eig_finish<T, MP>(L, r, d, pg, write_factor ? C + ch.c + (int64_t)s0 * ch.p : nullptr, ch.p,
-                      ch.p, wsd(ws, ch.w_lamg) + it.g, status ? status + it.ch : nullptr, conv);
+    eig_finish<T, MP>(L, r, d, pg, C + ch.c + (int64_t)s0 * ch.p, ch.p, ch.p,
+                      wsd(ws, ch.w_lamg) + it.g, status ? status + it.ch : nullptr, conv);
   } else {
     eig_sort_desc<T, MP>(L, r, 0);
   }
@@ -551,32 +619,38 @@ static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1
 
 template <typename T>
 static gt_status eig_all(const LaunchCtx& L, int which, float2* A, float2* B, float2* C,
-                         int32_t* status, int write) {
+                         int32_t* status, int warm) {
   if (which == 0) {
     GT_LAUNCH(k_reduce_S1, dim3(cdiv(L.max_nr * L.max_nr, 256), L.n_channels), dim3(256), L.d_chans,
               L.ws);
     GT_LAUNCH((k_eigA<T, 16>), dim3(cdiv(L.n_channels, 4)), dim3(64), L.d_chans, L.n_channels,
-              L.ws, A, status, write);
+              L.ws, A, status, warm);
   } else if (which == 1) {
     constexpr int NW = sizeof(T) == 4 ? 4 : 8;
-    GT_LAUNCH((k_eigB<T, NW>), dim3(L.n_channels), dim3(64 * NW), L.d_chans, L.ws, B, status, write);
+    GT_LAUNCH((k_eigB<T, NW>), dim3(L.n_channels), dim3(64 * NW), L.d_chans, L.ws, B, status, warm);
   } else {
     if (L.max_gs <= 16) {
       GT_LAUNCH((k_eigC<T, 16>), dim3(cdiv(L.total_groups, 4)), dim3(64), L.d_chans, L.d_groups,
-                L.total_groups, L.ws, C, status, write);
+                L.total_groups, L.ws, C, status, warm);
     } else {
       GT_LAUNCH((k_eigC<T, 32>), dim3(cdiv(L.total_groups, 2)), dim3(64), L.d_chans, L.d_groups,
-                L.total_groups, L.ws, C, status, write);
+                L.total_groups, L.ws, C, status, warm);
     }
   }
   return GT_OK;
 }
 
 static gt_status eig_dispatch(const LaunchCtx& L, int which, float2* A, float2* B, float2* C,
-                              int32_t* status, int write) {
-  return L.eig_fp64 ? eig_all<double>(L, which, A, B, C, status, write)
-                    : eig_all<float>(L, which, A, B, C, status, write);
+                              int32_t* status, int warm) {
+  return L.eig_fp64 ? eig_all<double>(L, which, A, B, C, status, warm)
+                    : eig_all<float>(L, which, A, B, C, status, warm);
 }
+
+bool fused_fit_ok(const LaunchCtx& L);
+gt_status launch_fused_t(const LaunchCtx& L, const float2* X, const float2* A, const float2* B,
+                         int do_c);
+gt_status launch_fused_z(const LaunchCtx& L, const float2* C, float2* G, int do_a, int do_core);
+gt_status launch_fused_b(const LaunchCtx& L, const float2* X, const float2* A, const float2* C);
 
 gt_status launch_fit(const LaunchCtx& L, const float2* X, float2* A, float2* B, float2* C,
                      float2* G, double* trace, int32_t* status, int iters, bool warm) {
@@ -599,24 +673,58 @@ gt_status launch_fit(const LaunchCtx& L, const float2* X, float2* A, float2* B, 
     GT_LAUNCH(k_gram_rows, gGram, b256, L.d_chans, X, L.ws, 0);
     GT_LAUNCH(k_reduce_S2, gRed, b256, L.d_chans, L.ws);
     gt_status st;
-    if ((st = eig_dispatch(L, 0, A, B, C, status, 1)) != GT_OK) return st;
-    if ((st = eig_dispatch(L, 1, A, B, C, status, 1)) != GT_OK) return st;
-    if ((st = eig_dispatch(L, 2, A, B, C, status, 1)) != GT_OK) return st;
+    if ((st = eig_dispatch(L, 0, A, B, C, status, 0)) != GT_OK) return st;
+    if ((st = eig_dispatch(L, 1, A, B, C, status, 0)) != GT_OK) return st;
+    if ((st = eig_dispatch(L, 2, A, B, C, status, 0)) != GT_OK) return st;
   }
-  // objective of the starting factors
-  GT_LAUNCH(k_Y, dim3(gY, nch), b256, L.d_chans, X, A, L.ws);
-  GT_LAUNCH(k_Yh, dim3(gYh, nch), b256, L.d_chans, B, L.ws);
+  // objective of the starting factors (the generic path also needs Yh for the cores)
+  const bool fused = fused_fit_ok(L);
+  if (trace || !fused) {
+    GT_LAUNCH(k_Y, dim3(gY, nch), b256, L.d_chans, X, A, L.ws);
+    GT_LAUNCH(k_Yh, dim3(gYh, nch), b256, L.d_chans, B, L.ws);
+  }
   if (trace) {
     GT_LAUNCH(k_S3, dim3(L.total_groups), b256, L.d_chans, L.d_groups, L.ws);
     GT_LAUNCH(k_objC, dim3(L.total_groups), dim3(64), L.d_chans, L.d_groups, C, L.ws);
     GT_LAUNCH(k_trace, dim3(cdiv(nch, 64)), dim3(64), L.d_chans, nch, L.ws, trace, stride, 0, 2);
+  }
+  if (fused) {
+    // per sweep: eigA, [W + Gram], eigB, [T, Yh, S3], eigC, [Z + S1 or cores]; the first
+    // A-step Gram comes from [T] and [Z] with the starting factors
+    gt_status st;
+    if ((st = launch_fused_t(L, X, A, B, 0)) != GT_OK) return st;
+    if ((st = launch_fused_z(L, C, G, iters > 0 ? 1 : 0, 0)) != GT_OK) return st;
+    if (iters == 0) {
+      if ((st = launch_fused_t(L, X, A, B, 1)) != GT_OK) return st;
+      return launch_fused_z(L, C, G, 0, 1);
+    }
+    for (int it = 0; it < iters; ++it) {
+      const int w = (warm && it == 0) ? 0 : 1;
+      if ((st = eig_dispatch(L, 0, A, B, C, status, w)) != GT_OK) return st;
+      if (trace)
+        GT_LAUNCH(k_trace, dim3(cdiv(nch, 64)), dim3(64), L.d_chans, nch, L.ws, trace, stride,
+                  1 + 3 * it, 0);
+      if ((st = launch_fused_b(L, X, A, C)) != GT_OK) return st;
+      if ((st = eig_dispatch(L, 1, A, B, C, status, w)) != GT_OK) return st;
+      if (trace)
+        GT_LAUNCH(k_trace, dim3(cdiv(nch, 64)), dim3(64), L.d_chans, nch, L.ws, trace, stride,
+                  2 + 3 * it, 1);
+      const bool last = it == iters - 1;
+      if ((st = launch_fused_t(L, X, A, B, 1)) != GT_OK) return st;
+      if ((st = eig_dispatch(L, 2, A, B, C, status, w)) != GT_OK) return st;
+      if (trace)
+        GT_LAUNCH(k_trace, dim3(cdiv(nch, 64)), dim3(64), L.d_chans, nch, L.ws, trace, stride,
+                  3 + 3 * it, 2);
+      if ((st = launch_fused_z(L, C, G, last ? 0 : 1, last ? 1 : 0)) != GT_OK) return st;
+    }
+    return GT_OK;
   }
   for (int it = 0; it < iters; ++it) {
     gt_status st;
     // A-step (uses B, C of the previous sweep)
     GT_LAUNCH(k_T, dim3(gT, nch), b256, L.d_chans, X, B, L.ws);
     GT_LAUNCH(k_stepA_group, dim3(L.total_groups), b256, L.d_chans, L.d_groups, C, L.ws);
-    if ((st = eig_dispatch(L, 0, A, B, C, status, 1)) != GT_OK) return st;
+    if ((st = eig_dispatch(L, 0, A, B, C, status, (warm && it == 0) ? 0 : 1)) != GT_OK) return st;
     if (trace)
       GT_LAUNCH(k_trace, dim3(cdiv(nch, 64)), dim3(64), L.d_chans, nch, L.ws, trace, stride,
                 1 + 3 * it, 0);
@@ -625,14 +733,14 @@ gt_status launch_fit(const LaunchCtx& L, const float2* X, float2* A, float2* B, 
     GT_LAUNCH(k_W, dim3(gW, nch), b256, L.d_chans, C, L.ws);
     GT_LAUNCH(k_gram_rows, gGram, b256, L.d_chans, X, L.ws, 1);
     GT_LAUNCH(k_reduce_S2, gRed, b256, L.d_chans, L.ws);
-    if ((st = eig_dispatch(L, 1, A, B, C, status, 1)) != GT_OK) return st;
+    if ((st = eig_dispatch(L, 1, A, B, C, status, (warm && it == 0) ? 0 : 1)) != GT_OK) return st;
     if (trace)
       GT_LAUNCH(k_trace, dim3(cdiv(nch, 64)), dim3(64), L.d_chans, nch, L.ws, trace, stride,
                 2 + 3 * it, 1);
     // C-step (new A, B)
     GT_LAUNCH(k_Yh, dim3(gYh, nch), b256, L.d_chans, B, L.ws);
     GT_LAUNCH(k_S3, dim3(L.total_groups), b256, L.d_chans, L.d_groups, L.ws);
-    if ((st = eig_dispatch(L, 2, A, B, C, status, 1)) != GT_OK) return st;
+    if ((st = eig_dispatch(L, 2, A, B, C, status, (warm && it == 0) ? 0 : 1)) != GT_OK) return st;
     if (trace)
       GT_LAUNCH(k_trace, dim3(cdiv(nch, 64)), dim3(64), L.d_chans, nch, L.ws, trace, stride,
                 3 + 3 * it, 2);

@@ -30,6 +30,9 @@ struct DevChan {
   int64_t w_S2p;   // [nsplit][nt][nt]    c64   split partials of the mode-2 Gram
   int64_t w_S2;    // [nt][nt]            c64   mode-2 Gram
   int64_t w_S3;    // [ngroups][gs][gs]   c64   per-group mode-3 Gram
+  int64_t w_VA;    // [16][16]            c64   last mode-1 eigenbasis (padded)
+  int64_t w_VB;    // [64][64]            c64   last mode-2 eigenbasis (padded)
+  int64_t w_VC;    // [ngroups][32][32]   c64   last mode-3 eigenbases (padded)
   int64_t w_lamg;  // [ngroups] double          per-group sums (norms, eigenvalue sums)
   int64_t w_scal;  // [8] double                ||X||^2, eigenvalue sums of the A and B steps
   int64_t w_gH;    // [nsc][m][n]         c64   per-subcarrier gradient of Ht

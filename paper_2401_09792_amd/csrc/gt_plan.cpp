@@ -204,9 +204,12 @@ gt_status gt_plan_create(const gt_channel_desc* descs, int32_t n_channels, const
     ch.w_Yh = take(c8 * ch.nsc * ch.m * ch.n);
     ch.w_S1p = take(c8 * ch.ngroups * ch.nr * ch.nr);
     ch.w_S1 = take(c8 * ch.nr * ch.nr);
-    ch.w_S2p = take(c8 * ch.nsplit * ch.nt * ch.nt);
+    ch.w_S2p = take(std::max<int64_t>(c8 * ch.nsplit * ch.nt * ch.nt, 4LL * ch.nsplit * 128 * 128));
     ch.w_S2 = take(c8 * ch.nt * ch.nt);
     ch.w_S3 = take(c8 * ch.ngroups * ch.gs * ch.gs);
+    ch.w_VA = take(c8 * 16 * 16);
+    ch.w_VB = take(c8 * 64 * 64);
+    ch.w_VC = take(c8 * ch.ngroups * 32 * 32);
     ch.w_lamg = take(8 * (int64_t)ch.ngroups);
     ch.w_scal = take(8 * 8);
     ch.w_gH = take(c8 * ch.nsc * ch.m * ch.n);

@@ -263,6 +263,289 @@ __global__ void __launch_bounds__(64) k_sinr(const DevChan* __restrict__ chans, 
 }
 
 // ---------------------------------------------------------------------------------------
+// Register-resident variant for compressed channels with m <= M (M = 4 or 8): one lane per
+// subcarrier, every matrix in registers with compile-time indices, cyclic Jacobi on the
+// m x m Gram, then the same MMSE chain.  Rows i >= m are zero and stay zero.
+
+template <int M>
+struct LaneHerm {  // Hermitian M x M: diagonal d[i], upper entries (ur[i][j], ui[i][j]), i < j
+  float d[M];
+  float ur[M][M], ui[M][M];
+};
+
+template <int M, int NS>
+__global__ void __launch_bounds__(64) k_sinr_lane(const DevChan* __restrict__ chans, int n_channels,
+                                                   int64_t total_sc, const float2* __restrict__ C,
+                                                   const float2* __restrict__ G, SnrArgs snr,
+                                                   float* __restrict__ out, int ns_max,
+                                                   int32_t* status) {
+  const int64_t gsc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = gsc < total_sc;
+  const int c = valid ? find_channel(chans, n_channels, gsc) : 0;
+  const DevChan& ch = chans[c];
+  const int64_t s = valid ? gsc - ch.sc : 0;
+  const int m = ch.m, n = ch.n;
+  const int ns = valid ? ch.ns : 0;
+  const int g = (int)(s / ch.gs);
+  const int pg = min(ch.p, min(ch.gs, ch.nsc - g * ch.gs));
+  const float2* Cs = C + ch.c + s * ch.p;
+  const float2* Gg = G + ch.g + (int64_t)g * ch.p * m * n;
+  uint32_t bits = 0;
+
+  // K = Ht Ht^H, one column of Ht at a time
+  LaneHerm<M> K;
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    K.d[i] = 0.f;
+#pragma unroll
+    for (int j = 0; j < M; ++j) K.ur[i][j] = K.ui[i][j] = 0.f;
+  }
+  if (valid) {
+    for (int j = 0; j < n; ++j) {
+      float hr[M], hi[M];
+#pragma unroll
+      for (int i = 0; i < M; ++i) hr[i] = hi[i] = 0.f;
+      for (int q = 0; q < pg; ++q) {
+        const float2 cq = Cs[q];
+        const float2* Gq = Gg + (int64_t)q * m * n + j;
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          if (i < m) {
+            const float2 gv = Gq[(int64_t)i * n];
+            hr[i] += cq.x * gv.x - cq.y * gv.y;
+            hi[i] += cq.x * gv.y + cq.y * gv.x;
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        K.d[i] += hr[i] * hr[i] + hi[i] * hi[i];
+#pragma unroll
+        for (int k = i + 1; k < M; ++k) {  // h_i conj(h_k)
+          K.ur[i][k] += hr[i] * hr[k] + hi[i] * hi[k];
+          K.ui[i][k] += hi[i] * hr[k] - hr[i] * hi[k];
+        }
+      }
+    }
+  }
+
+  // cyclic Jacobi with eigenvectors V (columns)
+  float vr[M][M], vi[M][M];
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      vr[i][j] = (i == j) ? 1.f : 0.f;
+      vi[i][j] = 0.f;
+    }
+  const float eps = 5.9604645e-08f;
+  bool conv = false;
+  for (int sw = 0; sw <= 10; ++sw) {
+    float off = 0.f, dg = 0.f;
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      dg += K.d[i] * K.d[i];
+#pragma unroll
+      for (int k = i + 1; k < M; ++k) off += K.ur[i][k] * K.ur[i][k] + K.ui[i][k] * K.ui[i][k];
+    }
+    if (__all((2.f * off <= 4.f * eps * eps * dg) ? 1 : 0)) {
+      conv = true;
+      break;
+    }
+    if (sw == 10) break;
+#pragma unroll
+    for (int p = 0; p < M - 1; ++p) {
+#pragma unroll
+      for (int q = p + 1; q < M; ++q) {
+        const float a = K.d[p], b = K.d[q];
+        const float cre = K.ur[p][q], cim = K.ui[p][q];
+        const float ac = __builtin_sqrtf(cre * cre + cim * cim);
+        float cs = 1.f, sre = 0.f, sim = 0.f, tac = 0.f;
+        if (ac > 0.f && ac > eps * 0.5f * (__builtin_fabsf(a) + __builtin_fabsf(b))) {
+          const float z = (b - a) / (2.f * ac);
+          const float az = __builtin_fabsf(z);
+          float tt = (az > 1.0e18f) ? 0.5f / az : 1.f / (az + __builtin_sqrtf(1.f + az * az));
+          if (z >= 0.f) tt = -tt;
+          cs = 1.f / __builtin_sqrtf(1.f + tt * tt);
+          const float sn = tt * cs;
+          sre = sn * cre / ac;
+          sim = sn * cim / ac;
+          tac = tt * ac;
+        }
+        // rows p and q against every other index k
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+          if (k == p || k == q) continue;
+          // K[p][k], K[q][k] from upper storage
+          float pkr, pki, qkr, qki;
+          if (p < k) { pkr = K.ur[p][k]; pki = K.ui[p][k]; } else { pkr = K.ur[k][p]; pki = -K.ui[k][p]; }
+          if (q < k) { qkr = K.ur[q][k]; qki = K.ui[q][k]; } else { qkr = K.ur[k][q]; qki = -K.ui[k][q]; }
+          // new row p: cs K[p][k] + s K[q][k];  new row q: -conj(s) K[p][k] + cs K[q][k]
+          const float npr = cs * pkr + (sre * qkr - sim * qki);
+          const float npi = cs * pki + (sre * qki + sim * qkr);
+          const float nqr = cs * qkr - (sre * pkr + sim * pki);
+          const float nqi = cs * qki - (sre * pki - sim * pkr);
+          if (p < k) { K.ur[p][k] = npr; K.ui[p][k] = npi; } else { K.ur[k][p] = npr; K.ui[k][p] = -npi; }
+          if (q < k) { K.ur[q][k] = nqr; K.ui[q][k] = nqi; } else { K.ur[k][q] = nqr; K.ui[k][q] = -nqi; }
+        }
+        K.d[p] = a + tac;
+        K.d[q] = b - tac;
+        K.ur[p][q] = 0.f;
+        K.ui[p][q] = 0.f;
+        // V <- V J: column p = V_p cs + V_q conj(s), column q = -V_p s + V_q cs
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+          const float xr = vr[k][p], xi = vi[k][p], yr = vr[k][q], yi = vi[k][q];
+          vr[k][p] = xr * cs + (yr * sre + yi * sim);
+          vi[k][p] = xi * cs + (yi * sre - yr * sim);
+          vr[k][q] = yr * cs - (xr * sre - xi * sim);
+          vi[k][q] = yi * cs - (xr * sim + xi * sre);
+        }
+      }
+    }
+  }
+  if (!conv) bits |= GT_DEV_EIG_SWEEPS;
+
+  // descending order over the first m eigenvalues; HV = U_ns Sigma_ns
+  int rank[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    const float li = (i < m) ? K.d[i] : -3.0e38f;
+    int rk = 0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const float lj = (j < m) ? K.d[j] : -3.0e38f;
+      rk += (lj > li || (lj == li && j < i)) ? 1 : 0;
+    }
+    rank[i] = rk;
+  }
+  float sig[NS], hvr[M][NS], hvi[M][NS];
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    float l = 0.f;
+#pragma unroll
+    for (int j = 0; j < M; ++j) l = (rank[j] == r) ? K.d[j] : l;
+    sig[r] = __builtin_sqrtf(l > 0.f ? l : 0.f);
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      float ur = 0.f, ui = 0.f;
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        ur = (rank[j] == r) ? vr[i][j] : ur;
+        ui = (rank[j] == r) ? vi[i][j] : ui;
+      }
+      const bool on = r < ns && i < m;
+      hvr[i][r] = on ? sig[r] * ur : 0.f;
+      hvi[i][r] = on ? sig[r] * ui : 0.f;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NS; ++r)
+    if (r < ns && !(sig[r] > 1.0e-3f * sig[0])) bits |= GT_DEV_ZERO_STREAM;
+
+  for (int kk = 0; kk < snr.n; ++kk) {
+    const float s2 = snr.s2[kk];
+    // Cholesky of Q = HV HV^H + s2 I (lower L, real diagonal)
+    float lr[M][M], li[M][M], ld_[M];
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      float dj = s2;
+#pragma unroll
+      for (int r = 0; r < NS; ++r) dj += hvr[j][r] * hvr[j][r] + hvi[j][r] * hvi[j][r];
+#pragma unroll
+      for (int k = 0; k < j; ++k) dj -= lr[j][k] * lr[j][k] + li[j][k] * li[j][k];
+      ok = ok && (dj > 0.f);
+      const float djs = __builtin_sqrtf(dj > 0.f ? dj : 1.f);
+      ld_[j] = djs;
+      const float inv = 1.f / djs;
+#pragma unroll
+      for (int i = j + 1; i < M; ++i) {
+        // Q[i][j] = sum_r hv[i][r] conj(hv[j][r])
+        float qr = 0.f, qi = 0.f;
+#pragma unroll
+        for (int r = 0; r < NS; ++r) {
+          qr += hvr[i][r] * hvr[j][r] + hvi[i][r] * hvi[j][r];
+          qi += hvi[i][r] * hvr[j][r] - hvr[i][r] * hvi[j][r];
+        }
+#pragma unroll
+        for (int k = 0; k < j; ++k) {  // L[i][k] conj(L[j][k])
+          qr -= lr[i][k] * lr[j][k] + li[i][k] * li[j][k];
+          qi -= li[i][k] * lr[j][k] - lr[i][k] * li[j][k];
+        }
+        lr[i][j] = qr * inv;
+        li[i][j] = qi * inv;
+      }
+    }
+    // W = Q^{-1} HV, column by column
+    float wr[M][NS], wi[M][NS];
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+#pragma unroll
+      for (int i = 0; i < M; ++i) {  // L y = hv_r
+        float ar = hvr[i][r], ai = hvi[i][r];
+#pragma unroll
+        for (int j = 0; j < i; ++j) {
+          ar -= lr[i][j] * wr[j][r] - li[i][j] * wi[j][r];
+          ai -= lr[i][j] * wi[j][r] + li[i][j] * wr[j][r];
+        }
+        wr[i][r] = ar / ld_[i];
+        wi[i][r] = ai / ld_[i];
+      }
+#pragma unroll
+      for (int i = M - 1; i >= 0; --i) {  // L^H w = y
+        float ar = wr[i][r], ai = wi[i][r];
+#pragma unroll
+        for (int j = i + 1; j < M; ++j) {
+          ar -= lr[j][i] * wr[j][r] + li[j][i] * wi[j][r];
+          ai -= lr[j][i] * wi[j][r] - li[j][i] * wr[j][r];
+        }
+        wr[i][r] = ar / ld_[i];
+        wi[i][r] = ai / ld_[i];
+      }
+    }
+    if (!ok) bits |= GT_DEV_CHOLESKY;
+    float res[NS];
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+      float sig_p = 0.f, den = 0.f, nw = 0.f;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        float cr = 0.f, ci = 0.f;
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          cr += wr[i][r] * hvr[i][k] + wi[i][r] * hvi[i][k];
+          ci += wr[i][r] * hvi[i][k] - wi[i][r] * hvr[i][k];
+        }
+        const float pw = cr * cr + ci * ci;
+        if (k == r)
+          sig_p = pw;
+        else
+          den += pw;
+      }
+#pragma unroll
+      for (int i = 0; i < M; ++i) nw += wr[i][r] * wr[i][r] + wi[i][r] * wi[i][r];
+      den += s2 * nw;
+      float v = sig_p / den;
+      if (!ok || r >= ns || !(sig[r] > 1.0e-3f * sig[0])) v = 0.f;
+      if (!(v == v) || v > 3.0e38f) {
+        v = 0.f;
+        bits |= GT_DEV_NONFINITE;
+      }
+      res[r] = v;
+    }
+    if (valid) {
+      float* o = out + ((int64_t)kk * total_sc + gsc) * ns_max;
+#pragma unroll
+      for (int r = 0; r < NS; ++r)
+        if (r < ns_max) o[r] = res[r];
+      for (int r = NS; r < ns_max; ++r) o[r] = 0.f;
+    }
+  }
+  if (valid && status && bits) atomicOr(reinterpret_cast<unsigned int*>(status + c), bits);
+}
+
+// ---------------------------------------------------------------------------------------
 // Adjoint.  Per subcarrier: recompute Ht, its SVD and, per noise level, the Cholesky factor
 // and W; back-propagate dl/dSINR through SINR = s/d, s_r = |c_rr|^2, d_r = s2 ||w_r||^2 +
 // sum_{k != r} |c_rk|^2 (c = W^H HV), W = Q^{-1} HV and Q = HV HV^H + s2 I to dl/dHV; then
@@ -621,6 +904,24 @@ gt_status launch_sinr(const LaunchCtx& L, int64_t total_sc, bool full, const flo
   for (int k = 0; k < n_snr; ++k) a.s2[k] = s2[k];
   const int M = full ? L.max_nr : L.max_m;
   const int N = full ? L.max_nt : L.max_n;
+  if (!full && M <= 8) {
+    const unsigned grid = (unsigned)((total_sc + 63) / 64);
+    if (M <= 4) {
+      if (L.max_ns <= 2)
+        GT_LAUNCH((k_sinr_lane<4, 2>), dim3(grid), dim3(64), L.d_chans, L.n_channels, total_sc, C, G, a,
+                  out, ns_max, status);
+      else
+        GT_LAUNCH((k_sinr_lane<4, 4>), dim3(grid), dim3(64), L.d_chans, L.n_channels, total_sc, C, G, a,
+                  out, ns_max, status);
+    } else if (L.max_ns <= 4) {
+      GT_LAUNCH((k_sinr_lane<8, 4>), dim3(grid), dim3(64), L.d_chans, L.n_channels, total_sc, C, G, a,
+                out, ns_max, status);
+    } else {
+      GT_LAUNCH((k_sinr_lane<8, 8>), dim3(grid), dim3(64), L.d_chans, L.n_channels, total_sc, C, G, a,
+                out, ns_max, status);
+    }
+    return GT_OK;
+  }
   if (full) {
     if (M <= 4) return sinr_launch_t<4, 1, true>(L, total_sc, X, C, G, a, out, ns_max, status);
     if (M <= 8) return sinr_launch_t<8, 1, true>(L, total_sc, X, C, G, a, out, ns_max, status);
