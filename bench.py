@@ -136,7 +136,7 @@ def main():
              "k_init_group", "k_Y", "k_W", "k_T", "k_stepA_group", "k_Yh", "k_S3", "k_core",
              "k_objC", "k_trace", "k_norm_total", "k_fused_t", "k_fused_z", "k_fused_b",
              "k_reconstruct",
-             "k_sinr_lane", "k_sinr<", "k_sinr_bwd<", "k_sinr_bwd_reduce"]
+             "k_sinr_lane", "k_sinr<", "k_sinr_bwd_lane", "k_sinr_bwd<", "k_sinr_bwd_reduce"]
     kern = {}
     for nm in names:
         ms, cnt = api.profile_query(nm)

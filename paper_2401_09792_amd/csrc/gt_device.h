@@ -135,7 +135,7 @@ __device__ __forceinline__ void jsync() {
 // With NW == 1 a wave may hold 64/MP matrices.  If `preset_v` is false V starts as the
 // identity, otherwise the caller has stored a starting basis in vr/vi (the rotations are then
 // accumulated onto it).  Returns true once the off-diagonal Frobenius norm is below
-// 2 eps times the diagonal norm for every matrix of the wave (or block).
+// 8 eps times the diagonal norm for every matrix of the wave (or block).
 template <typename T, int MP, int NW>
 __device__ bool jacobi_herm(EigLds<T, MP>& L, int r, int wave, int max_sweeps,
                             bool preset_v = false) {
@@ -167,7 +167,7 @@ __device__ bool jacobi_herm(EigLds<T, MP>& L, int r, int wave, int max_sweeps,
       }
       off = group_sum<MP>(off);
       dg = group_sum<MP>(dg);
-      done = wave_all(off <= T(4) * eps * eps * dg);
+      done = wave_all(off <= T(64) * eps * eps * dg);
     } else {
       if (wave == 0) {
         T off = 0, dg = 0;
@@ -181,7 +181,7 @@ __device__ bool jacobi_herm(EigLds<T, MP>& L, int r, int wave, int max_sweeps,
         }
         off = group_sum<MP>(off);
         dg = group_sum<MP>(dg);
-        if (r == 0) L.src[0] = (off <= T(4) * eps * eps * dg) ? 1 : 0;
+        if (r == 0) L.src[0] = (off <= T(64) * eps * eps * dg) ? 1 : 0;
       }
       __syncthreads();
       done = L.src[0] != 0;

@@ -30,56 +30,68 @@ __device__ __forceinline__ double* wsd(char* ws, int64_t off) {
 
 // ---------------------------------------------------------------------------------------
 // Initial Grams of one group: S1 partial = sum_s H_s H_s^H, S3_g[s,s'] = <H_s, H_s'>, and
-// the group's squared norm.
+// the group's squared norm.  The group's slices are staged through LDS in chunks.
 __global__ void __launch_bounds__(256) k_init_group(const DevChan* __restrict__ chans,
                                                     const GroupItem* __restrict__ items,
                                                     const float2* __restrict__ X, char* ws) {
+  constexpr int CHUNK = 4096;  // complex elements staged at a time (32 KB)
+  __shared__ float2 xs[CHUNK];
+  __shared__ double red[256];
   const GroupItem it = items[blockIdx.x];
   CH_BEGIN(it.ch);
   const int s0 = it.g * ch.gs;
   const int sz = min(ch.gs, ch.nsc - s0);
-  const int nr = ch.nr, nt = ch.nt;
-  const float2* Xg = X + ch.x + (int64_t)s0 * nr * nt;
-  // S1 partial
-  float2* S1 = wsp(ws, ch.w_S1p) + (int64_t)it.g * nr * nr;
-  for (int o = threadIdx.x; o < nr * nr; o += blockDim.x) {
-    const int i = o / nr, k = o % nr;
-    Cx<float> acc{0.f, 0.f};
-    for (int s = 0; s < sz; ++s)
-      for (int j = 0; j < nt; ++j) {
-        Cx<float> a = ld(Xg + ((int64_t)s * nr + i) * nt + j);
-        Cx<float> b = ld(Xg + ((int64_t)s * nr + k) * nt + j);
-        cfmac(acc, b, a);  // a * conj(b)
-      }
-    st(S1 + o, acc);
-  }
-  // S3 of the group
-  const int gs = ch.gs;
-  float2* S3 = wsp(ws, ch.w_S3) + (int64_t)it.g * gs * gs;
-  for (int o = threadIdx.x; o < gs * gs; o += blockDim.x) {
-    const int s = o / gs, t = o % gs;
-    Cx<float> acc{0.f, 0.f};
-    if (s < sz && t < sz) {
-      const float2* Hs = Xg + (int64_t)s * nr * nt;
-      const float2* Ht = Xg + (int64_t)t * nr * nt;
-      for (int e = 0; e < nr * nt; ++e) cfmac(acc, ld(Ht + e), ld(Hs + e));
+  const int nr = ch.nr, nt = ch.nt, gs = ch.gs;
+  const int slice = nr * nt;
+  const float2* Xg = X + ch.x + (int64_t)s0 * slice;
+  const int tid = threadIdx.x;
+  // outputs of this thread: S1 entries o1 = tid (nr*nr <= 256) and S3 entries tid, tid+256, ...
+  Cx<float> a1{0.f, 0.f};
+  Cx<float> a3[4] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
+  double nrm = 0.0;
+  // columns j are chunked so that sz * nr * jc <= CHUNK
+  const int jc = max(1, min(nt, CHUNK / (sz * nr)));
+  for (int j0 = 0; j0 < nt; j0 += jc) {
+    const int jw = min(jc, nt - j0);
+    __syncthreads();
+    for (int e = tid; e < sz * nr * jw; e += 256) {
+      const int j = e % jw, si = e / jw;
+      const float2 v = Xg[(int64_t)si * nt + j0 + j];
+      xs[e] = v;
+      nrm += (double)v.x * v.x + (double)v.y * v.y;
     }
-    st(S3 + o, acc);
+    __syncthreads();
+    if (tid < nr * nr) {
+      const int i = tid / nr, k = tid % nr;
+      for (int s = 0; s < sz; ++s)
+        for (int j = 0; j < jw; ++j)  // H[i][j] conj(H[k][j])
+          cfmac(a1, ld(xs + (s * nr + k) * jw + j), ld(xs + (s * nr + i) * jw + j));
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int o = tid + 256 * u;
+      if (o < gs * gs) {
+        const int s = o / gs, t = o % gs;
+        if (s < sz && t < sz)
+          for (int e = 0; e < nr * jw; ++e)  // H_s conj(H_t)
+            cfmac(a3[u], ld(xs + t * nr * jw + e), ld(xs + s * nr * jw + e));
+      }
+    }
   }
-  // squared norm (double)
-  __shared__ double red[256];
-  double acc = 0.0;
-  for (int e = threadIdx.x; e < sz * nr * nt; e += blockDim.x) {
-    float2 v = Xg[e];
-    acc += (double)v.x * v.x + (double)v.y * v.y;
+  if (tid < nr * nr) st(wsp(ws, ch.w_S1p) + (int64_t)it.g * nr * nr + tid, a1);
+  float2* S3 = wsp(ws, ch.w_S3) + (int64_t)it.g * gs * gs;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int o = tid + 256 * u;
+    if (o < gs * gs) st(S3 + o, a3[u]);
   }
-  red[threadIdx.x] = acc;
+  red[tid] = nrm;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    if (tid < o) red[tid] += red[tid + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) wsd(ws, ch.w_lamg)[it.g] = red[0];
+  if (tid == 0) wsd(ws, ch.w_lamg)[it.g] = red[0];
 }
 
 // Sum of the per-group norms: scal[0] = ||X||^2.

@@ -153,7 +153,7 @@ gt_status gt_plan_create(const gt_channel_desc* descs, int32_t n_channels, const
     ch.p = d.p;
     ch.ns = d.ns;
     ch.ngroups = (d.nsc + d.group_size - 1) / d.group_size;
-    ch.nsplit = std::min(ch.ngroups, 32);
+    ch.nsplit = std::min(ch.ngroups, 16);
     ch.gfirst = gfirst;
     ch.x = ox;
     ch.a = oa;
