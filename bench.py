@@ -15,6 +15,7 @@ rate of the SINR kernel is reported beside it.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -64,6 +65,42 @@ def sinr_unit_bytes(m, n, p, gs, n_snr, ns):
     return (8 * m * n * p / gs + 8 * p) / n_snr + 4 * ns
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy of known size), or None when the
+    summary is absent or was taken on a different revision of the kernel's source file."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_rb273_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for ln in fh:
+            if ":" in ln and not ln.startswith(" "):
+                k, v = ln.split(":", 1)
+                fields[k.strip()] = v.strip()
+    src = fields.get("source")
+    if not src or "traffic_bytes_per_launch" not in fields:
+        return None
+    with open(os.path.join(ROOT, src), "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest() != fields.get("source_sha256"):
+            return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
+def copy_calibration(mib: int) -> None:
+    """Plain device copy of a known size, the reference for scaling HBM byte counters."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "copies": 3}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,13 +108,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=64, help="channels per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1, help="channels timed on the oracle")
+    ap.add_argument("--cpu-sample", type=int, default=4, help="channels timed on the oracle")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run three plain copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     import torch
 
@@ -133,10 +175,10 @@ def main():
 
     # live per-kernel durations over the timed region
     names = ["k_eigA", "k_eigB", "k_eigC", "k_gram_rows", "k_reduce_S1", "k_reduce_S2",
-             "k_init_group", "k_Y", "k_W", "k_T", "k_stepA_group", "k_Yh", "k_S3", "k_core",
-             "k_objC", "k_trace", "k_norm_total", "k_fused_t", "k_fused_z", "k_fused_b",
-             "k_reconstruct",
-             "k_sinr_lane", "k_sinr<", "k_sinr_bwd_lane", "k_sinr_bwd<", "k_sinr_bwd_reduce"]
+             "k_reduce_S2_mfma", "k_init_group", "k_Y", "k_W", "k_T", "k_stepA_group", "k_Yh",
+             "k_S3", "k_core", "k_objC", "k_trace", "k_norm_total", "k_fused_t",
+             "k_fused_t_mfma", "k_fused_z", "k_fused_b", "k_fused_b_mfma", "k_reconstruct",
+             "k_sinr_lane", "k_sinr", "k_sinr_bwd_lane", "k_sinr_bwd", "k_sinr_bwd_reduce"]
     kern = {}
     for nm in names:
         ms, cnt = api.profile_query(nm)
@@ -154,21 +196,23 @@ def main():
     nr, nt, m, n, p, gs = cfg.nr, cfg.nt, cfg.m, cfg.n, cfg.p, cfg.group_size
     models = {
         # per launch: B channels x ng groups
-        "k_fused_b": B * ng * CMAC * (gs * m * nr * nt + p * gs * m * nt + p * m * nt * nt / 2),
+        "k_fused_b_mfma": B * ng * CMAC * (gs * m * nr * nt + p * gs * m * nt
+                                           + p * m * nt * nt / 2),
         "k_sinr_lane": sinr_units * sinr_unit_flops(m, n, p, cfg.ns, n_snr),
-        "k_sinr<": sinr_units * sinr_unit_flops(m, n, p, cfg.ns, n_snr),
+        "k_sinr": sinr_units * sinr_unit_flops(m, n, p, cfg.ns, n_snr),
         "k_gram_rows": B * gram_rows_flops(ng, p, m, nt),
     }
+    bounds = {"k_fused_b_mfma": "mfma", "k_gram_rows": "mfma"}
     ranked = sorted(((v["total_ms"], k) for k, v in kern.items() if k in models), reverse=True)
     roof = None
     if ranked:
         dom = ranked[0][1]
         ach = models[dom] / (kern[dom]["avg_us"] * 1e-6) / 1e12
-        roof = dict(kernel=dom, bound="alu", achieved=ach, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                    frac=ach / PEAK_FP32_TFLOPS, traffic=None,
+        roof = dict(kernel=dom, bound=bounds.get(dom, "alu"), achieved=ach, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                    frac=ach / PEAK_FP32_TFLOPS, traffic=measured_traffic(dom),
                     algorithmic_flops_per_launch=models[dom],
                     share_of_step=kern[dom]["total_ms"] / ms_step)
-    sinr_k = kern.get("k_sinr_lane") or kern.get("k_sinr<")
+    sinr_k = kern.get("k_sinr_lane") or kern.get("k_sinr")
     sinr_rate = sinr_units / (sinr_k["avg_us"] * 1e-6) if sinr_k else None
 
     # accuracy of this step's output on channel 0 against the oracle, and the CPU baseline

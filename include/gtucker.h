@@ -172,7 +172,8 @@ const char* gt_last_error_detail(void);
 
 /* Kernel timing.  When enabled, every kernel the library launches is bracketed by HIP
  * events on its stream; gt_profile_query synchronises those events and returns the summed
- * duration and launch count of kernels whose name contains `name`. */
+ * duration and launch count of the kernels whose base name (identifier without template
+ * arguments) equals `name`, or starts with it when `name` ends in '*'. */
 gt_status gt_profile_enable(int32_t on);
 gt_status gt_profile_reset(void);
 gt_status gt_profile_query(const char* name, double* total_ms, int64_t* launches);

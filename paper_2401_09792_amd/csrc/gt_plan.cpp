@@ -392,8 +392,17 @@ gt_status gt_profile_query(const char* name, double* total_ms, int64_t* launches
   std::lock_guard<std::mutex> lk(g_prof_mu);
   double tot = 0.0;
   int64_t cnt = 0;
+  std::string pat(name);
+  const bool prefix = !pat.empty() && pat.back() == '*';
+  if (prefix) pat.pop_back();
   for (auto& r : g_prof) {
-    if (r.name.find(name) == std::string::npos) continue;
+    // base name: the kernel's identifier without the parentheses and template arguments
+    // that the launch macros record
+    std::string base = r.name;
+    if (!base.empty() && base[0] == '(') base.erase(0, 1);
+    const size_t lt = base.find_first_of("<)");
+    if (lt != std::string::npos) base.resize(lt);
+    if (prefix ? base.compare(0, pat.size(), pat) != 0 : base != pat) continue;
     if (hipEventSynchronize(r.stop) != hipSuccess) return GT_ERR_HIP;
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess) return GT_ERR_HIP;
