@@ -1,0 +1,418 @@
+// Mode-2 eigensolve for wide transmit arrays (nt > 64): the n leading eigenvectors of the
+// nt x nt Hermitian Gram S2 of equation "update B" (and of the HOSVD initialisation,
+// Section 2.3) by subspace iteration with Rayleigh-Ritz projection on a block of 64 vectors:
+//
+//   Y = S2 V,  H = V^H Y,  H = U diag(theta) U^H  (parallel Jacobi, theta descending),
+//   V <- V U,  Y <- Y U                           (Ritz vectors and S2 times them),
+//   stop once ||Y_j - theta_j V_j|| <= tol theta_0 for every kept column j < n,
+//   otherwise V <- orth(Y) by classical Gram-Schmidt applied twice, and repeat.
+//
+// One 256-thread block per channel.  V, Y and a third buffer live in the workspace as
+// column blocks [64][nt] (column k contiguous), so the passes over them read whole rows.
+// The final Ritz basis stays in the workspace and starts the next call on the same channel
+// (warm start inside the alternating sweeps); a cold start uses V = orth(S2 Omega) with a
+// fixed pseudo-random unimodular Omega.
+#include <hip/hip_runtime.h>
+
+#include "gt_device.h"
+#include "gt_internal.h"
+
+namespace gt {
+
+namespace {
+
+constexpr int KB = 64;    // Ritz block size
+constexpr int NTH = 256;  // threads per block; nt <= NTH so each thread owns one row
+constexpr float kTol = 5.0e-6f;
+
+__device__ __forceinline__ float2* wsp_s(char* ws, int64_t off) {
+  return reinterpret_cast<float2*>(ws + off);
+}
+__device__ __forceinline__ double* wsd_s(char* ws, int64_t off) {
+  return reinterpret_cast<double*>(ws + off);
+}
+
+// Fixed pseudo-random start entries in {1, i, -1, -i} (integer hash of the position).
+__device__ __forceinline__ float2 omega(int k, int j) {
+  uint32_t h = (uint32_t)k * 0x9E3779B1u ^ (uint32_t)j * 0x85EBCA77u;
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 12;
+  switch (h & 3u) {
+    case 0: return make_float2(1.f, 0.f);
+    case 1: return make_float2(0.f, 1.f);
+    case 2: return make_float2(-1.f, 0.f);
+    default: return make_float2(0.f, -1.f);
+  }
+}
+
+struct SubLds {
+  EigLds<float, KB> e;    // Rayleigh quotient and its eigenvectors
+  float2 sa[64][33];      // staging tile: 64 rows x 32
+  float2 sb[32][65];      // staging tile: 32 x 64 columns
+  float red[4][KB][2];    // per-wave partial sums of the Gram-Schmidt coefficients
+  float rs[KB];           // residual norms of the Ritz pairs
+  float ph[KB][2];        // output phases
+  float bsum[4];
+};
+
+// Sum of v over the block (every thread gets the result).
+__device__ float block_sum(SubLds& L, float v) {
+  v = group_sum<64>(v);
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  __syncthreads();
+  if (lane == 0) L.bsum[wave] = v;
+  __syncthreads();
+  return (L.bsum[0] + L.bsum[1]) + (L.bsum[2] + L.bsum[3]);
+}
+
+// Y[k][i] = sum_j S[i][j] Vin[k][j]  (Vin == nullptr: the start block Omega)
+__device__ void apply_gram(SubLds& L, const float2* __restrict__ S, const float2* Vin, float2* Y,
+                           int nt) {
+  const int t = threadIdx.x;
+  const int bi = (t / 16) * 4, bk = (t % 16) * 4;
+  for (int i0 = 0; i0 < nt; i0 += 64) {
+    float ar[4][4], ai[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) ar[a][b] = ai[a][b] = 0.f;
+    for (int j0 = 0; j0 < nt; j0 += 32) {
+      __syncthreads();
+      for (int e = t; e < 64 * 32; e += NTH) {
+        const int r = e / 32, c = e % 32, i = i0 + r, j = j0 + c;
+        L.sa[r][c] = (i < nt && j < nt) ? S[(int64_t)i * nt + j] : make_float2(0.f, 0.f);
+      }
+      for (int e = t; e < 64 * 32; e += NTH) {
+        const int k = e / 32, c = e % 32, j = j0 + c;
+        float2 v = make_float2(0.f, 0.f);
+        if (j < nt) v = Vin ? Vin[(int64_t)k * nt + j] : omega(k, j);
+        L.sb[c][k] = v;
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int c = 0; c < 32; ++c) {
+        float2 x[4], y[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) x[a] = L.sa[bi + a][c];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) y[b] = L.sb[c][bk + b];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            ar[a][b] += x[a].x * y[b].x - x[a].y * y[b].y;
+            ai[a][b] += x[a].x * y[b].y + x[a].y * y[b].x;
+          }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int i = i0 + bi + a;
+      if (i < nt)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) Y[(int64_t)(bk + b) * nt + i] = make_float2(ar[a][b], ai[a][b]);
+    }
+  }
+  __syncthreads();
+}
+
+// H = V^H Y into L.e.kr/ki (Hermitian part)
+__device__ void rayleigh(SubLds& L, const float2* V, const float2* Y, int nt) {
+  const int t = threadIdx.x;
+  const int ba = (t / 16) * 4, bb = (t % 16) * 4;
+  float ar[4][4], ai[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) ar[a][b] = ai[a][b] = 0.f;
+  for (int i0 = 0; i0 < nt; i0 += 32) {
+    __syncthreads();
+    for (int e = t; e < 64 * 32; e += NTH) {
+      const int k = e / 32, c = e % 32, i = i0 + c;
+      const bool ok = i < nt;
+      L.sa[k][c] = ok ? V[(int64_t)k * nt + i] : make_float2(0.f, 0.f);
+      L.sb[c][k] = ok ? Y[(int64_t)k * nt + i] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int c = 0; c < 32; ++c) {
+      float2 x[4], y[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) x[a] = L.sa[ba + a][c];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) y[b] = L.sb[c][bb + b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {  // conj(x) y
+          ar[a][b] += x[a].x * y[b].x + x[a].y * y[b].y;
+          ai[a][b] += x[a].x * y[b].y - x[a].y * y[b].x;
+        }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      L.e.kr[ba + a][bb + b] = ar[a][b];
+      L.e.ki[ba + a][bb + b] = ai[a][b];
+    }
+  __syncthreads();
+  // Hermitian part: (H + H^H) / 2
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      ar[a][b] = 0.5f * (ar[a][b] + L.e.kr[bb + b][ba + a]);
+      ai[a][b] = 0.5f * (ai[a][b] - L.e.ki[bb + b][ba + a]);
+    }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      L.e.kr[ba + a][bb + b] = ar[a][b];
+      L.e.ki[ba + a][bb + b] = ai[a][b];
+    }
+  __syncthreads();
+}
+
+// Out[j][i] = sum_a In[a][i] U[a][src[j]]  (U = the Rayleigh quotient's eigenvectors)
+__device__ void rotate_block(SubLds& L, const float2* In, float2* Out, int nt) {
+  const int t = threadIdx.x;
+  const int bi = (t / 16) * 4, bj = (t % 16) * 4;
+  int cj[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) cj[b] = L.e.src[bj + b];
+  for (int i0 = 0; i0 < nt; i0 += 64) {
+    float ar[4][4], ai[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) ar[a][b] = ai[a][b] = 0.f;
+    for (int a0 = 0; a0 < KB; a0 += 32) {
+      __syncthreads();
+      for (int e = t; e < 64 * 32; e += NTH) {
+        const int c = e / 64, r = e % 64, i = i0 + r;
+        L.sa[r][c] = (i < nt) ? In[(int64_t)(a0 + c) * nt + i] : make_float2(0.f, 0.f);
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int c = 0; c < 32; ++c) {
+        float2 x[4];
+        float ur[4], ui[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) x[a] = L.sa[bi + a][c];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          ur[b] = L.e.vr[a0 + c][cj[b]];
+          ui[b] = L.e.vi[a0 + c][cj[b]];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            ar[a][b] += x[a].x * ur[b] - x[a].y * ui[b];
+            ai[a][b] += x[a].x * ui[b] + x[a].y * ur[b];
+          }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int i = i0 + bi + a;
+      if (i < nt)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) Out[(int64_t)(bj + b) * nt + i] = make_float2(ar[a][b], ai[a][b]);
+    }
+  }
+  __syncthreads();
+}
+
+// Dst = orthonormal basis of the columns of Src, column by column (classical Gram-Schmidt,
+// two passes).  A column that keeps less than 1e-4 of its norm is replaced by the matching
+// column of Fb (or of Omega when Fb is null), then by unit vectors, until one survives.
+__device__ void orthonormalize(SubLds& L, const float2* Src, const float2* Fb, float2* Dst,
+                               int nt) {
+  const int i = threadIdx.x, wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const bool live = i < nt;
+  for (int j = 0; j < KB; ++j) {
+    float2 y = live ? Src[(int64_t)j * nt + i] : make_float2(0.f, 0.f);
+    float n0 = block_sum(L, y.x * y.x + y.y * y.y);
+    float n1 = 0.f;
+    for (int attempt = 0;; ++attempt) {
+      for (int pass = 0; pass < 2; ++pass) {
+        if (j > 0) {
+          for (int k = 0; k < j; ++k) {
+            float2 q = live ? Dst[(int64_t)k * nt + i] : make_float2(0.f, 0.f);
+            float pr = q.x * y.x + q.y * y.y, pi = q.x * y.y - q.y * y.x;  // conj(q) y
+            pr = group_sum<64>(pr);
+            pi = group_sum<64>(pi);
+            if (lane == 0) {
+              L.red[wave][k][0] = pr;
+              L.red[wave][k][1] = pi;
+            }
+          }
+          __syncthreads();
+          for (int k = 0; k < j; ++k) {
+            const float cr = (L.red[0][k][0] + L.red[1][k][0]) + (L.red[2][k][0] + L.red[3][k][0]);
+            const float ci = (L.red[0][k][1] + L.red[1][k][1]) + (L.red[2][k][1] + L.red[3][k][1]);
+            if (live) {
+              float2 q = Dst[(int64_t)k * nt + i];
+              y.x -= q.x * cr - q.y * ci;
+              y.y -= q.x * ci + q.y * cr;
+            }
+          }
+          __syncthreads();
+        }
+      }
+      n1 = block_sum(L, y.x * y.x + y.y * y.y);
+      if ((n1 > 1.0e-8f * n0 && n1 > 1.0e-36f) || attempt > nt + 1) break;
+      // replacement candidate
+      if (attempt == 0)
+        y = live ? (Fb ? Fb[(int64_t)j * nt + i] : omega(j, i)) : make_float2(0.f, 0.f);
+      else
+        y = (i == (j + attempt - 1) % nt) ? make_float2(1.f, 0.f) : make_float2(0.f, 0.f);
+      n0 = block_sum(L, y.x * y.x + y.y * y.y);
+    }
+    const float s = (n1 > 0.f) ? 1.0f / __builtin_sqrtf(n1) : 0.f;
+    if (live) Dst[(int64_t)j * nt + i] = make_float2(y.x * s, y.y * s);
+  }
+  __syncthreads();
+}
+
+// Largest relative residual ||W_j - theta_j Z_j|| / theta_0 over the kept columns j < n.
+__device__ float max_residual(SubLds& L, const float2* Z, const float2* W, int nt, int n) {
+  const int t = threadIdx.x;
+  const int j = t / 4, part = t % 4;
+  const float th = L.e.lam[L.e.src[j]];
+  float acc = 0.f;
+  for (int i = part; i < nt; i += 4) {
+    float2 z = Z[(int64_t)j * nt + i], w = W[(int64_t)j * nt + i];
+    const float dr = w.x - th * z.x, di = w.y - th * z.y;
+    acc += dr * dr + di * di;
+  }
+  acc += __shfl_xor(acc, 1, 64);
+  acc += __shfl_xor(acc, 2, 64);
+  __syncthreads();
+  if (part == 0) L.rs[j] = acc;
+  __syncthreads();
+  const float th0 = L.e.lam[L.e.src[0]];
+  float m = 0.f;
+  for (int k = 0; k < n; ++k) m = fmaxf(m, L.rs[k]);
+  // NaN propagates: comparisons below fail and the caller stops at the cap
+  const float den = th0 * th0;
+  return (den > 0.f) ? __builtin_sqrtf(m / den) : (m > 0.f ? 1.0f : 0.0f);
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(NTH) k_eigB_sub(const DevChan* __restrict__ chans, char* ws,
+                                                   float2* B, int32_t* status, int warm,
+                                                   int max_iter) {
+  __shared__ SubLds L;
+  const DevChan& ch = chans[blockIdx.x];
+  const int nt = ch.nt, n = ch.n;
+  if (nt <= 64) return;  // handled by the in-LDS Jacobi kernel
+  const int t = threadIdx.x, r = t % 64, wave = t / 64;
+  const float2* S = wsp_s(ws, ch.w_S2);
+  float2* P0 = wsp_s(ws, ch.w_VB);
+  float2* P1 = wsp_s(ws, ch.w_VS);
+  float2* P2 = P1 + (int64_t)KB * nt;
+
+  // starting orthonormal block in V
+  float2 *V, *Y, *F;
+  if (warm) {
+    orthonormalize(L, P0, nullptr, P1, nt);
+    V = P1;
+    Y = P2;
+    F = P0;
+  } else {
+    apply_gram(L, S, nullptr, P1, nt);
+    orthonormalize(L, P1, nullptr, P0, nt);
+    V = P0;
+    Y = P1;
+    F = P2;
+  }
+  bool conv = false, jconv = true;
+  float res = 0.f;
+  float2* Z = F;
+  for (int it = 0; it < max_iter; ++it) {
+    apply_gram(L, S, V, Y, nt);
+    rayleigh(L, V, Y, nt);
+    jconv = jacobi_herm<float, KB, 4>(L.e, r, wave, 12, false) && jconv;
+    __syncthreads();
+    if (wave == 0) eig_sort_desc<float, KB>(L.e, r, KB);
+    __syncthreads();
+    Z = F;
+    rotate_block(L, V, Z, nt);  // Ritz vectors
+    rotate_block(L, Y, V, nt);  // S2 times the Ritz vectors (V's storage is free now)
+    res = max_residual(L, Z, V, nt, n);
+    if (res <= kTol) {
+      conv = true;
+      break;
+    }
+    if (it == max_iter - 1) break;
+    orthonormalize(L, V, Z, Y, nt);  // next block, in Y's storage
+    float2* nv = Y;
+    Y = V;
+    F = Z;
+    V = nv;
+  }
+
+  // keep the Ritz basis for the next call
+  if (Z != P0) {
+    for (int e = t; e < KB * nt; e += NTH) P0[e] = Z[e];
+    __syncthreads();
+    Z = P0;
+  }
+  // canonical phase of each kept column: its largest-modulus entry (lowest row on ties)
+  // becomes real positive
+  if (t < n) {
+    float best = -1.f;
+    float2 bv = make_float2(1.f, 0.f);
+    for (int i = 0; i < nt; ++i) {
+      const float2 v = Z[(int64_t)t * nt + i];
+      const float mag = v.x * v.x + v.y * v.y;
+      if (mag > best) {
+        best = mag;
+        bv = v;
+      }
+    }
+    const float a = __builtin_sqrtf(bv.x * bv.x + bv.y * bv.y);
+    L.ph[t][0] = (a > 0.f) ? bv.x / a : 1.f;
+    L.ph[t][1] = (a > 0.f) ? -bv.y / a : 0.f;
+  }
+  __syncthreads();
+  float2* Bc = B + ch.b;
+  for (int e = t; e < nt * n; e += NTH) {
+    const int i = e / n, j = e % n;
+    const float2 v = Z[(int64_t)j * nt + i];
+    const float pr = L.ph[j][0], pi = L.ph[j][1];
+    Bc[e] = make_float2(v.x * pr - v.y * pi, v.x * pi + v.y * pr);
+  }
+  if (t == 0) {
+    double ls = 0.0;
+    for (int j = 0; j < n; ++j) ls += (double)L.e.lam[L.e.src[j]];
+    wsd_s(ws, ch.w_scal)[2] = ls;
+    uint32_t bits = (conv && jconv) ? 0u : GT_DEV_EIG_SWEEPS;
+    if (!(ls == ls) || !(res == res) || ls > 1e300 || ls < -1e300) bits |= GT_DEV_NONFINITE;
+    if (bits && status) atomicOr(reinterpret_cast<unsigned int*>(status + blockIdx.x), bits);
+  }
+}
+
+gt_status launch_eigB_sub(const LaunchCtx& L, float2* B, int32_t* status, int warm) {
+  const int max_iter = warm ? 40 : 100;
+  prof_begin("k_eigB_sub", L.stream);
+  hipLaunchKernelGGL(k_eigB_sub, dim3(L.n_channels), dim3(NTH), 0, L.stream, L.d_chans, L.ws, B,
+                     status, warm, max_iter);
+  prof_end(L.stream);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error_detail("k_eigB_sub", e);
+    return GT_ERR_HIP;
+  }
+  return GT_OK;
+}
+
+}  // namespace gt

@@ -311,6 +311,7 @@ __global__ void __launch_bounds__(64 * NW) k_eigB(const DevChan* __restrict__ ch
   const int c = blockIdx.x;
   const DevChan& ch = chans[c];
   const int d = ch.nt;
+  if (d > MP) return;  // wide arrays: subspace-iteration kernel
   const float2* S = wsp(ws, ch.w_S2);
   float2* VB = wsp(ws, ch.w_VB);
   const bool use_warm = kWarmOk && warm;
@@ -629,6 +630,8 @@ __global__ void __launch_bounds__(256) k_core(const DevChan* __restrict__ chans,
 
 static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
+gt_status launch_eigB_sub(const LaunchCtx& L, float2* B, int32_t* status, int warm);
+
 template <typename T>
 static gt_status eig_all(const LaunchCtx& L, int which, float2* A, float2* B, float2* C,
                          int32_t* status, int warm) {
@@ -639,7 +642,12 @@ static gt_status eig_all(const LaunchCtx& L, int which, float2* A, float2* B, fl
               L.ws, A, status, warm);
   } else if (which == 1) {
     constexpr int NW = sizeof(T) == 4 ? 4 : 8;
-    GT_LAUNCH((k_eigB<T, NW>), dim3(L.n_channels), dim3(64 * NW), L.d_chans, L.ws, B, status, warm);
+    if (L.min_nt <= 64)
+      GT_LAUNCH((k_eigB<T, NW>), dim3(L.n_channels), dim3(64 * NW), L.d_chans, L.ws, B, status, warm);
+    if (L.max_nt > 64) {
+      gt_status st = launch_eigB_sub(L, B, status, warm);
+      if (st != GT_OK) return st;
+    }
   } else {
     if (L.max_gs <= 16) {
       GT_LAUNCH((k_eigC<T, 16>), dim3(cdiv(L.total_groups, 4)), dim3(64), L.d_chans, L.d_groups,
@@ -659,6 +667,7 @@ static gt_status eig_dispatch(const LaunchCtx& L, int which, float2* A, float2* 
 }
 
 bool fused_fit_ok(const LaunchCtx& L);
+gt_status launch_eigB_sub(const LaunchCtx& L, float2* B, int32_t* status, int warm);
 gt_status launch_fused_t(const LaunchCtx& L, const float2* X, const float2* A, const float2* B,
                          int do_c);
 gt_status launch_fused_z(const LaunchCtx& L, const float2* C, float2* G, int do_a, int do_core);

@@ -31,7 +31,9 @@ struct DevChan {
   int64_t w_S2;    // [nt][nt]            c64   mode-2 Gram
   int64_t w_S3;    // [ngroups][gs][gs]   c64   per-group mode-3 Gram
   int64_t w_VA;    // [16][16]            c64   last mode-1 eigenbasis (padded)
-  int64_t w_VB;    // [64][64]            c64   last mode-2 eigenbasis (padded)
+  int64_t w_VB;    // [64][max(64,nt)]    c64   last mode-2 eigenbasis (padded; for nt > 64 the
+                   //                           64-column Ritz block, column-major)
+  int64_t w_VS;    // [2][64][nt]         c64   subspace-iteration buffers (nt > 64 only)
   int64_t w_VC;    // [ngroups][32][32]   c64   last mode-3 eigenbases (padded)
   int64_t w_lamg;  // [ngroups] double          per-group sums (norms, eigenvalue sums)
   int64_t w_scal;  // [8] double                ||X||^2, eigenvalue sums of the A and B steps
@@ -60,6 +62,7 @@ struct LaunchCtx {
   int n_channels;
   int total_groups;
   int max_nr, max_nt, max_nsc, max_gs, max_m, max_n, max_p, max_ns, max_groups, max_nsplit;
+  int min_nt;
   int eig_fp64;
 };
 

@@ -86,6 +86,7 @@ struct gt_plan {
   gt_offsets totals;
   int ns_max;
   int max_nr, max_nt, max_nsc, max_gs, max_m, max_n, max_p, max_ns, max_groups, max_nsplit;
+  int min_nt;
 };
 
 static int64_t align256(int64_t v) { return (v + 255) & ~int64_t(255); }
@@ -140,6 +141,7 @@ gt_status gt_plan_create(const gt_channel_desc* descs, int32_t n_channels, const
   int gfirst = 0;
   p->max_nr = p->max_nt = p->max_nsc = p->max_gs = p->max_m = p->max_n = p->max_p = p->max_ns = 0;
   p->max_groups = p->max_nsplit = 0;
+  p->min_nt = descs[0].nt;
   for (int c = 0; c < n_channels; ++c) {
     const gt_channel_desc& d = descs[c];
     DevChan& ch = p->chans[c];
@@ -173,6 +175,7 @@ gt_status gt_plan_create(const gt_channel_desc* descs, int32_t n_channels, const
     gfirst += ch.ngroups;
     p->max_nr = std::max(p->max_nr, d.nr);
     p->max_nt = std::max(p->max_nt, d.nt);
+    p->min_nt = std::min(p->min_nt, d.nt);
     p->max_nsc = std::max(p->max_nsc, d.nsc);
     p->max_gs = std::max(p->max_gs, d.group_size);
     p->max_m = std::max(p->max_m, d.m);
@@ -208,7 +211,8 @@ gt_status gt_plan_create(const gt_channel_desc* descs, int32_t n_channels, const
     ch.w_S2 = take(c8 * ch.nt * ch.nt);
     ch.w_S3 = take(c8 * ch.ngroups * ch.gs * ch.gs);
     ch.w_VA = take(c8 * 16 * 16);
-    ch.w_VB = take(c8 * 64 * 64);
+    ch.w_VB = take(c8 * 64 * std::max(64, ch.nt));
+    ch.w_VS = take(ch.nt > 64 ? c8 * 2 * 64 * ch.nt : 8);
     ch.w_VC = take(c8 * ch.ngroups * 32 * 32);
     ch.w_lamg = take(8 * (int64_t)ch.ngroups);
     ch.w_scal = take(8 * 8);
@@ -271,6 +275,7 @@ static LaunchCtx make_ctx(const gt_plan* p, void* ws, void* stream) {
   L.max_ns = p->max_ns;
   L.max_groups = p->max_groups;
   L.max_nsplit = p->max_nsplit;
+  L.min_nt = p->min_nt;
   L.eig_fp64 = p->opt.eig_fp64;
   return L;
 }
@@ -293,7 +298,8 @@ gt_status gt_tucker_fit(const gt_plan* plan, const void* X, void* A, void* B, vo
   gt_status st = check_ws(plan, ws, ws_bytes);
   if (st != GT_OK) return st;
   if (!X || !A || !B || !C || !G) return GT_ERR_ARG;
-  if (plan->max_nt > kMaxNt) return GT_ERR_UNSUPPORTED;
+  // wide arrays (nt > 64) use the FP32 subspace-iteration eigensolver only
+  if (plan->max_nt > kMaxNt && plan->opt.eig_fp64) return GT_ERR_UNSUPPORTED;
   LaunchCtx L = make_ctx(plan, ws, stream);
   return launch_fit(L, (const float2*)X, (float2*)A, (float2*)B, (float2*)C, (float2*)G, obj_trace,
                     dev_status, plan->opt.iters, (plan->opt.flags & GT_FIT_WARM_START) != 0);

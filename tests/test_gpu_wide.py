@@ -1,0 +1,104 @@
+"""Fit parity for wide transmit arrays (nt > 64), where the mode-2 eigensolve runs as
+subspace iteration with Rayleigh-Ritz projection instead of the in-LDS Jacobi.
+
+Reduced-subcarrier versions of the 16 x 256 and 8 x 128 workloads are checked against the
+FP64 oracle with the same bars as the other fit tests (NMSE within 1e-5 relative, X-hat
+within 1e-4 of ||X||, objective trace within 1e-5 of ||X||^2, orthonormal factors).  The
+full 16 x 256 x 3276 size is checked through properties that hold at any size.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import synthgen
+from oracle import metrics, tucker
+from tests.gpu_util import announce, crandn, desc, dev_c64, host, unpack
+from tests.test_gpu_parity import _gpu_fit_and_check
+
+pytestmark = pytest.mark.gpu
+
+
+def _generator_channel(seed, nr, nt, nsc, n_paths, k_db):
+    rng = np.random.default_rng(seed)
+    pp = synthgen.draw_paths(rng, n_paths, k_db)
+    return synthgen.build_channel(pp, nr, nt, nsc)
+
+
+@pytest.mark.parametrize("case", [
+    # (nsc, nr, nt, gs, m, n, p, iters, seed)
+    (40, 4, 96, 12, 3, 12, 6, 4, 31),     # decaying spectrum, ragged last group of 4
+    (30, 6, 128, 8, 4, 20, 5, 3, 37),     # short last group of 6
+])
+def test_fit_wide_lossy_random(gpu_lib, case):
+    nsc, nr, nt, gs, m, n, p, iters, seed = case
+    announce(f"fit wide lossy {case}")
+    rng = np.random.default_rng(seed)
+    X = crandn(rng, nsc, nr, nt)
+    X = X * (0.7 ** np.arange(nr))[None, :, None] * (0.93 ** np.arange(nt))[None, None, :]
+    _gpu_fit_and_check(gpu_lib, X, gs, m, n, p, 2, iters, xhat_tol=1e-4)
+
+
+@pytest.mark.parametrize("case", [
+    # (nr, nt, nsc, paths, K dB, gs, m, n, p, ns, iters, seed)
+    (16, 256, 96, 16, 3.0, 12, 12, 32, 12, 8, 6, 41),   # 16 x 256 array, 8 groups
+    (8, 128, 100, 32, 3.0, 12, 8, 24, 12, 4, 6, 43),    # 8 x 128, lossy in mode 2, short group
+])
+def test_fit_wide_generator(gpu_lib, case):
+    nr, nt, nsc, L, k_db, gs, m, n, p, ns, iters, seed = case
+    announce(f"fit wide generator {case}")
+    X = _generator_channel(seed, nr, nt, nsc, L, k_db)
+    _gpu_fit_and_check(gpu_lib, X, gs, m, n, p, ns, iters, xhat_tol=1e-4)
+
+
+def test_fit_batch_mixed_widths(gpu_lib):
+    # one channel on the Jacobi mode-2 path and one on the subspace path, in one plan
+    announce("fit batch nt 32 + nt 128")
+    X0 = _generator_channel(51, 4, 32, 36, 4, 6.0)
+    X1 = _generator_channel(52, 8, 128, 48, 12, 3.0)
+    d0 = desc(4, 32, 36, 12, 4, 8, 6, 2)
+    d1 = desc(8, 128, 48, 12, 6, 16, 8, 4)
+    plan = gpu_lib.Plan([d0, d1], iters=4)
+    res = plan.fit(dev_c64(np.concatenate([X0.reshape(-1), X1.reshape(-1)])))
+    _, xh = plan.reconstruct(res["A"], res["B"], res["C"], res["G"])
+    xh = host(xh)
+    assert np.all(host(res["status"]) == 0)
+    for c, (X, d) in enumerate(((X0, d0), (X1, d1))):
+        orc = tucker.fit(X, d["group_size"], d["m"], d["n"], d["p"], 4)
+        _, Xh_o = tucker.reconstruct(orc["A"], orc["B"], orc["C"], orc["G"], d["group_size"])
+        Xh = unpack(plan, c, xh, "x")
+        assert np.linalg.norm(Xh - Xh_o) <= 1e-4 * np.linalg.norm(X)
+        assert abs(metrics.nmse(X, Xh) - metrics.nmse(X, Xh_o)) <= 1e-5 * metrics.nmse(X, Xh_o) + 1e-10
+
+
+def test_fit_wide_full_size_properties(gpu_lib):
+    # 16 x 256 x 3276, groups of 12, ranks (12, 32, 12), 20 sweeps: properties that hold at
+    # any size (the FP64 oracle needs minutes here)
+    cfg = synthgen.CONFIGS["wide"]
+    announce("fit wide full size properties")
+    X = synthgen.make_channel(cfg, 0)
+    plan = gpu_lib.Plan([gpu_lib.desc_from_config(cfg)], iters=cfg.iters)
+    Xd = dev_c64(X)
+    res = plan.fit(Xd)
+    _, xh = plan.reconstruct(res["A"], res["B"], res["C"], res["G"])
+    torch.cuda.synchronize()
+    assert int(res["status"].item()) == 0
+    A = unpack(plan, 0, host(res["A"]), "a")
+    Bm = unpack(plan, 0, host(res["B"]), "b")
+    Cm = unpack(plan, 0, host(res["C"]), "c")
+    assert np.abs(A.conj().T @ A - np.eye(cfg.m)).max() < 1e-5
+    assert np.abs(Bm.conj().T @ Bm - np.eye(cfg.n)).max() < 1e-5
+    starts, sizes = tucker.group_layout(cfg.nsc, cfg.group_size)
+    for s0, sz in zip(starts, sizes):
+        Cg = Cm[s0:s0 + sz, :min(cfg.p, sz)]
+        assert np.abs(Cg.conj().T @ Cg - np.eye(Cg.shape[1])).max() < 1e-5
+    nx = float(np.sum(np.abs(X) ** 2))
+    tr = host(res["trace"])[0]
+    # the alternating objective never increases (FP32 tolerance)
+    assert np.all(np.diff(tr) <= 1e-5 * nx), np.diff(tr).max() / nx
+    # optimal-core identity: the last objective equals the explicit residual
+    Xh = unpack(plan, 0, host(xh), "x")
+    resid = float(np.sum(np.abs(X - Xh) ** 2))
+    assert abs(resid - tr[-1]) <= 1e-5 * nx, (resid / nx, tr[-1] / nx)
+    # the 16-path channel is nearly representable at ranks (12, 32, 12)
+    assert metrics.nmse(X, Xh) < 0.05
