@@ -177,7 +177,7 @@ def main():
     names = ["k_eigA", "k_eigB", "k_eigC", "k_gram_rows", "k_reduce_S1", "k_reduce_S2",
              "k_reduce_S2_mfma", "k_init_group", "k_Y", "k_W", "k_T", "k_stepA_group", "k_Yh",
              "k_S3", "k_core", "k_objC", "k_trace", "k_norm_total", "k_fused_t",
-             "k_fused_t_mfma", "k_fused_z", "k_fused_b", "k_fused_b_mfma", "k_reconstruct",
+             "k_fused_t_mfma", "k_fused_z", "k_fused_b", "k_fused_b_mfma", "k_fused_b_mm", "k_eigB_sub", "k_reconstruct",
              "k_sinr_lane", "k_sinr", "k_sinr_bwd_lane", "k_sinr_bwd", "k_sinr_bwd_reduce"]
     kern = {}
     for nm in names:
@@ -198,11 +198,13 @@ def main():
         # per launch: B channels x ng groups
         "k_fused_b_mfma": B * ng * CMAC * (gs * m * nr * nt + p * gs * m * nt
                                            + p * m * nt * nt / 2),
+        "k_fused_b_mm": B * ng * CMAC * (gs * m * nr * nt + p * gs * m * nt
+                                         + p * m * nt * nt / 2),
         "k_sinr_lane": sinr_units * sinr_unit_flops(m, n, p, cfg.ns, n_snr),
         "k_sinr": sinr_units * sinr_unit_flops(m, n, p, cfg.ns, n_snr),
         "k_gram_rows": B * gram_rows_flops(ng, p, m, nt),
     }
-    bounds = {"k_fused_b_mfma": "mfma", "k_gram_rows": "mfma"}
+    bounds = {"k_fused_b_mfma": "mfma", "k_fused_b_mm": "mfma", "k_gram_rows": "mfma"}
     ranked = sorted(((v["total_ms"], k) for k, v in kern.items() if k in models), reverse=True)
     roof = None
     if ranked:

@@ -185,19 +185,37 @@ __global__ void __launch_bounds__(256) k_fused_t_mfma(const DevChan* __restrict_
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[u][r] = 0.f;
   const int half = lane / 32, col = lane % 32;
+  // K order: with nt % 4 == 0 and 16-byte aligned rows, step 4 u + v takes real index
+  // k' = 8 u + 4 half + v in lane half, so each lane reads 16 contiguous bytes per four steps
+  // (the same permutation indexes Bt); otherwise k' = 2 j + half.
+  const bool vec4 = (nt % 4) == 0 && ((reinterpret_cast<uintptr_t>(Xf) & 15) == 0);
 #pragma unroll
   for (int u = 0; u < TPW; ++u) {
     const int tile = wave + 4 * u;
     if (tile < ntile) {
       const int row = tile * 32 + col;
       const bool rv = row < rows;
-      const float* xrow = Xf + (int64_t)(rv ? row : 0) * 2 * nt + half;
-      const float* bcol = Bt + half * 32 + col;
+      if (vec4) {
+        const float4* xrow4 = reinterpret_cast<const float4*>(Xf + (int64_t)(rv ? row : 0) * 2 * nt);
+        const float* bcol = Bt + 4 * half * 32 + col;
+#pragma unroll 2
+        for (int w = 0; w < nt / 4; ++w) {
+          const float4 a4 = rv ? xrow4[2 * w + half] : make_float4(0.f, 0.f, 0.f, 0.f);
+          const float* bw = bcol + 8 * w * 32;
+          acc[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, bw[0], acc[u], 0, 0, 0);
+          acc[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, bw[32], acc[u], 0, 0, 0);
+          acc[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, bw[64], acc[u], 0, 0, 0);
+          acc[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, bw[96], acc[u], 0, 0, 0);
+        }
+      } else {
+        const float* xrow = Xf + (int64_t)(rv ? row : 0) * 2 * nt + half;
+        const float* bcol = Bt + half * 32 + col;
 #pragma unroll 8
-      for (int j = 0; j < nt; ++j) {
-        const float av = rv ? xrow[2 * j] : 0.f;
-        const float bv = bcol[j * 64];
-        acc[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[u], 0, 0, 0);
+        for (int j = 0; j < nt; ++j) {
+          const float av = rv ? xrow[2 * j] : 0.f;
+          const float bv = bcol[j * 64];
+          acc[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[u], 0, 0, 0);
+        }
       }
     }
   }
@@ -581,6 +599,221 @@ __global__ void __launch_bounds__(256) k_fused_b_mfma(const DevChan* __restrict_
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// B-step pass with all three contractions on FP32 matrix cores, 8 waves per block.  Per
+// group, in real form (each complex product split into re/im rows and columns):
+//   1. Hc_q = sum_s conj(C[s,q]) H_s for q < p_g: rows (q, re/im), K over (s, re/im), N over
+//      the nr nt entries (i, j) of a slice.  Those are contiguous in X, so the B operand is
+//      read straight from HBM, coalesced.
+//   2. W_q = A^H Hc_q: rows (a, re/im), K over (i, re/im), N over j (two 32-column tiles,
+//      zero beyond nt).  Each wave takes whole q's and overwrites Hc_q by W_q (planar).
+//   3. The real Gram R^T R of R = [Re W | Im W] on the 10 upper 32 x 32 tiles (two tiles
+//      for waves 0 and 1, one for the others), accumulated over the block's groups.
+// LDS holds one slot per q of max(2 nr nt, 2 m 64) floats and the step-2 A operand.
+__host__ __device__ __forceinline__ int bmm_slot(int nr, int nt, int m) {
+  const int a = 2 * nr * nt, b = 2 * m * 64;
+  return a > b ? a : b;
+}
+
+// upper 32 x 32 tile k of the 128 x 128 real Gram: (0,0) (0,1) (0,2) (0,3) (1,1) (1,2) (1,3)
+// (2,2) (2,3) (3,3)
+__device__ __forceinline__ void gram_tile(int k, int& I, int& J) {
+  I = k < 4 ? 0 : (k < 7 ? 1 : (k < 9 ? 2 : 3));
+  J = k < 4 ? k : (k < 7 ? k - 3 : (k < 9 ? k - 5 : 3));
+}
+
+// Step-1 operands of group g for this lane, loaded one group ahead: the real (h = 0) or
+// imaginary (h = 1) part of slice s at column c = 32 (wave + 8 u) + lane % 32, and the
+// component of C[s, q] that the A operand of row (q, part) = lane % 32 at K index (s, h)
+// needs (its sign is applied at use).  Indices are clamped into the group so that every load
+// is unconditional (no wait is forced inside the prefetch); rows q >= p_g, columns beyond
+// nr nt and slices s >= size_g only reach outputs that are never stored or MFMAs that are
+// skipped.
+template <int NT1W, int SMAX>
+__device__ __forceinline__ void bmm_prefetch(float (&xp)[SMAX][NT1W], float (&cp)[SMAX],
+                                             const float2* __restrict__ X,
+                                             const float2* __restrict__ C, const DevChan& ch,
+                                             int g, int nrnt, int wave, int col, int h) {
+  const int s0 = g * ch.gs, sz = min(ch.gs, ch.nsc - s0);
+  const int pg = min(ch.p, sz);
+  const float* xg = reinterpret_cast<const float*>(X + ch.x + (int64_t)s0 * nrnt) + h;
+  const int q = min(col >> 1, pg - 1), part = col & 1;
+  const float* cg = reinterpret_cast<const float*>(C + ch.c + (int64_t)s0 * ch.p + q) + (part ^ h);
+#pragma unroll
+  for (int s = 0; s < SMAX; ++s) {
+    const int sc = min(s, sz - 1);
+#pragma unroll
+    for (int u = 0; u < NT1W; ++u) {
+      const int c = min(32 * (wave + 8 * u) + col, nrnt - 1);
+      xp[s][u] = xg[2 * ((int64_t)sc * nrnt + c)];
+    }
+    cp[s] = cg[2 * (int64_t)sc * ch.p];
+  }
+}
+
+template <int NT1W, int SMAX>
+__global__ void __launch_bounds__(512, 2) k_fused_b_mm(const DevChan* __restrict__ chans,
+                                                       const float2* __restrict__ X,
+                                                       const float2* __restrict__ A,
+                                                       const float2* __restrict__ C, char* ws) {
+  extern __shared__ float smf[];
+  const DevChan& ch = chans[blockIdx.y];
+  const int split = blockIdx.x;
+  if (split >= ch.nsplit) return;
+  const int nr = ch.nr, nt = ch.nt, m = ch.m, p = ch.p;
+  const int nrnt = nr * nt;
+  const int SL = bmm_slot(nr, nt, m);
+  float* aop = smf + p * SL;  // [nr][64] step-2 A operand
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int h = lane / 32, col = lane % 32;
+  // step-2 A operand of lane l at K step i: row l % 32 = (a, re/im), k = (i, l / 32)
+  for (int e = tid; e < nr * 64; e += 512) {
+    const int i = e / 64, l = e % 64, a = (l % 32) >> 1, part = l & 1, hh = l / 32;
+    float v = 0.f;
+    if (a < m) {
+      const float2 av = A[ch.a + i * m + a];
+      v = part == 0 ? (hh == 0 ? av.x : av.y) : (hh == 0 ? -av.y : av.x);
+    }
+    aop[e] = v;
+  }
+  // Gram tiles of this wave: wave and, for waves 0 and 1, wave + 8
+  const int nt2 = wave < 2 ? 2 : 1;
+  int offa[2], offb[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    int I, J;
+    gram_tile(t == 0 ? wave : wave + 8, I, J);
+    const int ca = 32 * I + col, cb = 32 * J + col;
+    offa[t] = ca < 64 ? ca : m * 64 + (ca - 64);
+    offb[t] = cb < 64 ? cb : m * 64 + (cb - 64);
+  }
+  f32x16 gacc[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) gacc[t][r] = 0.f;
+  const int g0 = (int)((int64_t)split * ch.ngroups / ch.nsplit);
+  const int g1 = (int)((int64_t)(split + 1) * ch.ngroups / ch.nsplit);
+  float xp[SMAX][NT1W], cp[SMAX];
+  if (g0 < g1) bmm_prefetch<NT1W, SMAX>(xp, cp, X, C, ch, g0, nrnt, wave, col, h);
+  __syncthreads();
+  for (int g = g0; g < g1; ++g) {
+    const int s0 = g * ch.gs;
+    const int sz = min(ch.gs, ch.nsc - s0);
+    const int pg = min(p, sz);
+    // 1. Hc: this wave's 32-column tiles c = 32 (wave + 8 u) + col
+    {
+      f32x16 acc1[NT1W];
+#pragma unroll
+      for (int u = 0; u < NT1W; ++u)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc1[u][r] = 0.f;
+      // A[(q, part)][(s, h)] = part 0: (Re C, Im C)[h], part 1: (-Im C, Re C)[h]
+      const float csign = ((col & 1) == 1 && h == 0) ? -1.f : 1.f;
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s)
+        if (s < sz) {
+          const float av = csign * cp[s];
+#pragma unroll
+          for (int u = 0; u < NT1W; ++u)
+            acc1[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, xp[s][u], acc1[u], 0, 0, 0);
+        }
+      // register pair (r, r + 1), r % 4 in {0, 2}, holds (re, im) of q = row / 2
+#pragma unroll
+      for (int u = 0; u < NT1W; ++u) {
+        const int c = 32 * (wave + 8 * u) + col;
+        if (c < nrnt)
+#pragma unroll
+          for (int r = 0; r < 16; r += 2) {
+            const int q = 4 * (r / 4) + 2 * h + ((r % 4) >> 1);
+            if (q < pg)
+              *reinterpret_cast<float2*>(smf + q * SL + 2 * c) = make_float2(acc1[u][r], acc1[u][r + 1]);
+          }
+      }
+    }
+    if (g + 1 < g1) bmm_prefetch<NT1W, SMAX>(xp, cp, X, C, ch, g + 1, nrnt, wave, col, h);
+    __syncthreads();
+    // 2. W_q = A^H Hc_q, in place
+    // both column tiles are read before either is written back; loads are unconditional
+    // (clamped) and out-of-range operands are zeroed by selects, four K steps per batch
+    for (int q = wave; q < pg; q += 8) {
+      float* slot = smf + q * SL;
+      f32x16 acc2[2];
+#pragma unroll
+      for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc2[jt][r] = 0.f;
+      const int j0 = min(col, nt - 1), j1 = min(32 + col, nt - 1);
+      const bool jv0 = col < nt, jv1 = 32 + col < nt;
+      for (int i0 = 0; i0 < nr; i0 += 4) {
+        float av[4], b0[4], b1[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          const int i = min(i0 + d, nr - 1);
+          const bool iv = i0 + d < nr;
+          const float x = aop[i * 64 + lane];
+          const float y0 = slot[2 * (i * nt + j0) + h], y1 = slot[2 * (i * nt + j1) + h];
+          av[d] = iv ? x : 0.f;
+          b0[d] = jv0 ? y0 : 0.f;
+          b1[d] = jv1 ? y1 : 0.f;
+        }
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          acc2[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[d], b0[d], acc2[0], 0, 0, 0);
+          acc2[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[d], b1[d], acc2[1], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = 8 * (r / 4) + 4 * h + (r % 4);
+          const int a = row >> 1;
+          if (a < m) slot[((row & 1) ? m * 64 : 0) + a * 64 + 32 * jt + col] = acc2[jt][r];
+        }
+    }
+    __syncthreads();
+    // 3. Gram over the rows (q, a) of W, q < p_g, two rows a0 + h of one q per step (an
+    // odd m pads each q with a zero row); two steps per batch, loads unconditional
+    for (int q = 0; q < pg; ++q) {
+      const float* qb = smf + q * SL;
+      for (int a0 = 0; a0 < m; a0 += 4) {
+        const int ra = a0 + h, rb2 = a0 + 2 + h;
+        const float sa = ra < m ? 1.f : 0.f, sb = rb2 < m ? 1.f : 0.f;
+        const float* p0 = qb + min(ra, m - 1) * 64;
+        const float* p1 = qb + min(rb2, m - 1) * 64;
+        if (nt2 == 2) {
+          const float x00 = p0[offa[0]], y00 = p0[offb[0]], x01 = p0[offa[1]], y01 = p0[offb[1]];
+          const float x10 = p1[offa[0]], y10 = p1[offb[0]], x11 = p1[offa[1]], y11 = p1[offb[1]];
+          gacc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(sa * x00, y00, gacc[0], 0, 0, 0);
+          gacc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(sa * x01, y01, gacc[1], 0, 0, 0);
+          gacc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(sb * x10, y10, gacc[0], 0, 0, 0);
+          gacc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(sb * x11, y11, gacc[1], 0, 0, 0);
+        } else {
+          const float x00 = p0[offa[0]], y00 = p0[offb[0]];
+          const float x10 = p1[offa[0]], y10 = p1[offb[0]];
+          gacc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(sa * x00, y00, gacc[0], 0, 0, 0);
+          gacc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(sb * x10, y10, gacc[0], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  float* P = reinterpret_cast<float*>(ws + ch.w_S2p) + (int64_t)split * 128 * 128;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    if (t < nt2) {
+      int I, J;
+      gram_tile(t == 0 ? wave : wave + 8, I, J);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 32 * I + 8 * (r / 4) + 4 * h + (r % 4);
+        P[row * 128 + 32 * J + col] = gacc[t][r];
+      }
+    }
+  }
+}
+
 // S2 = sum over splits of the complex Gram assembled from the real blocks of R^T R
 // (upper 32 x 32 tiles stored; lower entries by symmetry).
 __global__ void k_reduce_S2_mfma(const DevChan* __restrict__ chans, char* ws) {
@@ -676,7 +909,36 @@ bool fused_b_mfma_ok(const LaunchCtx& L) {
          bm_bytes(L) <= 64 * 1024;
 }
 
+static size_t bmm_bytes(const LaunchCtx& L) {
+  return sizeof(float) * ((size_t)L.max_p * bmm_slot(L.max_nr, L.max_nt, L.max_m) + (size_t)L.max_nr * 64);
+}
+
+// All-matrix-core variant: p, m <= 16 (32 real rows of steps 1 and 2), nt <= 64, a group's
+// step-1 operands of this wave's column tiles (32 NT1W per wave) held in SMAX x NT1W registers.
+static int bmm_variant(const LaunchCtx& L) {
+  if (!(L.max_nt <= 64 && L.max_nr <= 16 && L.max_p <= 16 && L.max_m <= 16 &&
+        bmm_bytes(L) <= 72 * 1024))
+    return 0;
+  const int n1 = (L.max_nr * L.max_nt + 31) / 32;
+  if (L.max_gs <= 12) return n1 <= 8 ? 1 : (n1 <= 16 ? 2 : 0);
+  if (L.max_gs <= 24) return n1 <= 8 ? 3 : 0;
+  return 0;
+}
+
 gt_status launch_fused_b(const LaunchCtx& L, const float2* X, const float2* A, const float2* C) {
+  const int v = bmm_variant(L);
+  if (v) {
+    const dim3 grid(L.max_nsplit, L.n_channels);
+    const size_t sh = bmm_bytes(L);
+    switch (v) {
+      case 1: GT_LAUNCH_SH((k_fused_b_mm<1, 12>), grid, dim3(512), sh, L.d_chans, X, A, C, L.ws); break;
+      case 2: GT_LAUNCH_SH((k_fused_b_mm<2, 12>), grid, dim3(512), sh, L.d_chans, X, A, C, L.ws); break;
+      default: GT_LAUNCH_SH((k_fused_b_mm<1, 24>), grid, dim3(512), sh, L.d_chans, X, A, C, L.ws); break;
+    }
+    GT_LAUNCH_SH(k_reduce_S2_mfma, dim3((L.max_nt * L.max_nt + 255) / 256, L.n_channels), dim3(256), 0,
+                 L.d_chans, L.ws);
+    return GT_OK;
+  }
   if (fused_b_mfma_ok(L)) {
     if (L.max_p <= 4)
       GT_LAUNCH_SH((k_fused_b_mfma<2, 4>), dim3(L.max_nsplit, L.n_channels), dim3(256), bm_bytes(L),
