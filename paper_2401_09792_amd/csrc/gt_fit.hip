@@ -716,7 +716,7 @@ gt_status launch_fit(const LaunchCtx& L, const float2* X, float2* A, float2* B, 
     if ((st = launch_fused_t(L, X, A, B, 0)) != GT_OK) return st;
     if ((st = launch_fused_z(L, C, G, iters > 0 ? 1 : 0, 0)) != GT_OK) return st;
     if (iters == 0) {
-      if ((st = launch_fused_t(L, X, A, B, 1)) != GT_OK) return st;
+      if ((st = launch_fused_t(L, X, A, B, 2)) != GT_OK) return st;
       return launch_fused_z(L, C, G, 0, 1);
     }
     for (int it = 0; it < iters; ++it) {
@@ -731,7 +731,8 @@ gt_status launch_fit(const LaunchCtx& L, const float2* X, float2* A, float2* B, 
         GT_LAUNCH(k_trace, dim3(cdiv(nch, 64)), dim3(64), L.d_chans, nch, L.ws, trace, stride,
                   2 + 3 * it, 1);
       const bool last = it == iters - 1;
-      if ((st = launch_fused_t(L, X, A, B, 1)) != GT_OK) return st;
+      // the C-step pass of the last sweep also keeps Yh for the cores
+      if ((st = launch_fused_t(L, X, A, B, last ? 2 : 1)) != GT_OK) return st;
       if ((st = eig_dispatch(L, 2, A, B, C, status, w)) != GT_OK) return st;
       if (trace)
         GT_LAUNCH(k_trace, dim3(cdiv(nch, 64)), dim3(64), L.d_chans, nch, L.ws, trace, stride,

@@ -52,6 +52,8 @@ __device__ __forceinline__ double* wsd2(char* ws, int64_t off) {
 
 // k_fused_t, one block per group: T_s = H_s B for the group's subcarriers (to the workspace)
 // and, for a C-step, Yh_s = A^H T_s and the group's Gram S3[s,t] = <Yh_s, Yh_t>.
+// do_c: 0 = T only; 1 = also Yh (in LDS) and S3; 2 = as 1 and Yh to the workspace (the
+// cores of the last sweep read it).
 __global__ void __launch_bounds__(256) k_fused_t(const DevChan* __restrict__ chans,
                                                   const GroupItem* __restrict__ items,
                                                   const float2* __restrict__ X,
@@ -132,7 +134,7 @@ __global__ void __launch_bounds__(256) k_fused_t(const DevChan* __restrict__ cha
     for (int i = 0; i < nr; ++i) cfmac(acc, ld(As + i * m + a), ld(Ts + (s * nr + i) * n + b));
     const float2 v = make_float2(acc.re, acc.im);
     Yh[o] = v;
-    Yg[o] = v;
+    if (do_c == 2) Yg[o] = v;
   }
   __syncthreads();
   group_gram_s3(Yh, wsp2(ws, ch.w_S3) + (int64_t)it.g * ch.gs * ch.gs, ch.gs, sz, m * n, tid);
@@ -165,37 +167,78 @@ __global__ void __launch_bounds__(256) k_fused_t_mfma(const DevChan* __restrict_
   float2* As = smem + nt * 32;                        // nr x m
   float2* Ts = As + nr * m;                           // sz x nr x n
   float2* Yh = Ts + ch.gs * nr * n;                   // sz x m x n
-  for (int e = tid; e < 2 * nt * 32; e += 256) {
-    const int kk = e / 32, c = e % 32, j = kk / 2, part = kk % 2;
-    float v = 0.f;
-    if (c < 2 * n) {
-      const float2 b = B[ch.b + j * n + (c < n ? c : c - n)];
-      v = (part == 0) ? (c < n ? b.x : b.y) : (c < n ? -b.y : b.x);
-    }
-    Bt[e] = v;
-  }
-  for (int e = tid; e < nr * m; e += 256) As[e] = A[ch.a + e];
-  __syncthreads();
   const int rows = sz * nr;
   const int ntile = (rows + 31) / 32;
   const float* Xf = reinterpret_cast<const float*>(X + ch.x + (int64_t)s0 * nr * nt);
-  f32x16 acc[TPW];
-#pragma unroll
-  for (int u = 0; u < TPW; ++u)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc[u][r] = 0.f;
   const int half = lane / 32, col = lane % 32;
   // K order: with nt % 4 == 0 and 16-byte aligned rows, step 4 u + v takes real index
   // k' = 8 u + 4 half + v in lane half, so each lane reads 16 contiguous bytes per four steps
   // (the same permutation indexes Bt); otherwise k' = 2 j + half.
   const bool vec4 = (nt % 4) == 0 && ((reinterpret_cast<uintptr_t>(Xf) & 15) == 0);
+  // nt = 64, one tile per wave: the lane's whole half-row (16 x 16 bytes) is requested first,
+  // so that its latency overlaps the staging of B
+  const bool whole = TPW == 1 && vec4 && nt == 64;
+  float4 a4[16];
+  if (whole) {
+    const int row = min(wave * 32 + col, rows - 1);
+    const float4* xrow4 = reinterpret_cast<const float4*>(Xf + (int64_t)row * 2 * nt);
+#pragma unroll
+    for (int w = 0; w < 16; ++w) a4[w] = xrow4[2 * w + half];
+  }
+  {
+    // all loads of the real-form B are issued before any is used (clamped indices)
+    constexpr int NE = 2 * 64 * 32 / 256;
+    float2 bv[NE];
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+      const int e = tid + 256 * k, kk = e / 32, c = e % 32;
+      const int j = min(kk / 2, nt - 1), cc = min(c < n ? c : c - n, n - 1);
+      bv[k] = B[ch.b + j * n + max(cc, 0)];
+    }
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+      const int e = tid + 256 * k, kk = e / 32, c = e % 32, part = kk % 2;
+      float v = (part == 0) ? (c < n ? bv[k].x : bv[k].y) : (c < n ? -bv[k].y : bv[k].x);
+      if (c >= 2 * n) v = 0.f;
+      if (e < 2 * nt * 32) Bt[e] = v;
+    }
+  }
+  for (int e = tid; e < nr * m; e += 256) As[e] = A[ch.a + e];
+  __syncthreads();
+  f32x16 acc[TPW];
+#pragma unroll
+  for (int u = 0; u < TPW; ++u)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[u][r] = 0.f;
 #pragma unroll
   for (int u = 0; u < TPW; ++u) {
     const int tile = wave + 4 * u;
     if (tile < ntile) {
       const int row = tile * 32 + col;
       const bool rv = row < rows;
-      if (vec4) {
+      if (whole) {
+        // products alternate between two accumulators
+        const float* bcol = Bt + 4 * half * 32 + col;
+        f32x16 acc_b;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc_b[r] = 0.f;
+#pragma unroll
+        for (int w = 0; w < 16; w += 2) {
+          const float* bw = bcol + 8 * w * 32;
+          const float4 x0 = rv ? a4[w] : make_float4(0.f, 0.f, 0.f, 0.f);
+          const float4 x1 = rv ? a4[w + 1] : make_float4(0.f, 0.f, 0.f, 0.f);
+          acc[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.x, bw[0], acc[u], 0, 0, 0);
+          acc_b = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.x, bw[256], acc_b, 0, 0, 0);
+          acc[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.y, bw[32], acc[u], 0, 0, 0);
+          acc_b = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.y, bw[288], acc_b, 0, 0, 0);
+          acc[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.z, bw[64], acc[u], 0, 0, 0);
+          acc_b = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.z, bw[320], acc_b, 0, 0, 0);
+          acc[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.w, bw[96], acc[u], 0, 0, 0);
+          acc_b = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.w, bw[352], acc_b, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[u][r] += acc_b[r];
+      } else if (vec4) {
         const float4* xrow4 = reinterpret_cast<const float4*>(Xf + (int64_t)(rv ? row : 0) * 2 * nt);
         const float* bcol = Bt + 4 * half * 32 + col;
 #pragma unroll 2
@@ -241,19 +284,59 @@ __global__ void __launch_bounds__(256) k_fused_t_mfma(const DevChan* __restrict_
   }
   if (!do_c) return;
   __syncthreads();
+  // Yh_s = A^H T_s: a thread owns column b of one T_s (in registers) and forms all m rows
   float2* Yg = wsp2(ws, ch.w_Yh) + (int64_t)s0 * m * n;
-  for (int o = tid; o < sz * m * n; o += 256) {
-    const int b = o % n;
-    const int a = (o / n) % m;
-    const int s = o / (m * n);
-    Cx<float> acc2{0.f, 0.f};
-    for (int i = 0; i < nr; ++i) cfmac(acc2, ld(As + i * m + a), ld(Ts + (s * nr + i) * n + b));
-    const float2 v = make_float2(acc2.re, acc2.im);
-    Yh[o] = v;
-    Yg[o] = v;
+  for (int sb = tid; sb < sz * n; sb += 256) {
+    const int s = sb / n, b = sb - s * n;
+    float2 tc[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      tc[i] = i < nr ? Ts[(s * nr + i) * n + b] : make_float2(0.f, 0.f);
+    for (int a = 0; a < m; ++a) {
+      float yr = 0.f, yi = 0.f;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        if (i < nr) {
+          const float2 av = As[i * m + a];
+          yr += av.x * tc[i].x + av.y * tc[i].y;
+          yi += av.x * tc[i].y - av.y * tc[i].x;
+        }
+      }
+      const int o = (s * m + a) * n + b;
+      Yh[o] = make_float2(yr, yi);
+      if (do_c == 2) Yg[o] = make_float2(yr, yi);
+    }
   }
   __syncthreads();
-  group_gram_s3(Yh, wsp2(ws, ch.w_S3) + (int64_t)it.g * ch.gs * ch.gs, ch.gs, sz, m * n, tid);
+  // S3[s][t] = <Yh_s, Yh_t> on the upper triangle (16 lanes per entry), mirrored below
+  {
+    const int gs = ch.gs, mn = m * n, l16 = tid % 16;
+    float2* S3 = wsp2(ws, ch.w_S3) + (int64_t)it.g * gs * gs;
+    for (int k = tid / 16; k < gs * (gs + 1) / 2; k += 16) {
+      int s = 0, rem = k;
+      while (rem >= gs - s) {
+        rem -= gs - s;
+        ++s;
+      }
+      const int t = s + rem;
+      float ar = 0.f, ai = 0.f;
+      if (t < sz)
+        for (int e = l16; e < mn; e += 16) {
+          const float2 x = Yh[s * mn + e], y = Yh[t * mn + e];
+          ar += x.x * y.x + x.y * y.y;
+          ai += x.y * y.x - x.x * y.y;
+        }
+#pragma unroll
+      for (int d = 8; d > 0; d >>= 1) {
+        ar += __shfl_xor(ar, d, 64);
+        ai += __shfl_xor(ai, d, 64);
+      }
+      if (l16 == 0) {
+        S3[s * gs + t] = make_float2(ar, ai);
+        if (t != s) S3[t * gs + s] = make_float2(ar, -ai);
+      }
+    }
+  }
 }
 
 // k_fused_z, one block per group, after the mode-3 eigensolve: the A-step partial Gram
@@ -651,8 +734,11 @@ __device__ __forceinline__ void bmm_prefetch(float (&xp)[SMAX][NT1W], float (&cp
   }
 }
 
-template <int NT1W, int SMAX>
-__global__ void __launch_bounds__(512, 2) k_fused_b_mm(const DevChan* __restrict__ chans,
+// PF: the next group's step-1 operands are loaded while the current group's steps 2 and 3
+// run (more registers, one block per CU); otherwise they are loaded at the start of step 1
+// and latency is hidden by a second resident block.
+template <int NT1W, int SMAX, bool PF>
+__global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* __restrict__ chans,
                                                        const float2* __restrict__ X,
                                                        const float2* __restrict__ A,
                                                        const float2* __restrict__ C, char* ws) {
@@ -695,43 +781,37 @@ __global__ void __launch_bounds__(512, 2) k_fused_b_mm(const DevChan* __restrict
   const int g0 = (int)((int64_t)split * ch.ngroups / ch.nsplit);
   const int g1 = (int)((int64_t)(split + 1) * ch.ngroups / ch.nsplit);
   float xp[SMAX][NT1W], cp[SMAX];
-  if (g0 < g1) bmm_prefetch<NT1W, SMAX>(xp, cp, X, C, ch, g0, nrnt, wave, col, h);
+  if (PF && g0 < g1) bmm_prefetch<NT1W, SMAX>(xp, cp, X, C, ch, g0, nrnt, wave, col, h);
   __syncthreads();
   for (int g = g0; g < g1; ++g) {
     const int s0 = g * ch.gs;
     const int sz = min(ch.gs, ch.nsc - s0);
     const int pg = min(p, sz);
-    // 1. Hc: this wave's 32-column tiles c = 32 (wave + 8 u) + col
+    if (!PF) bmm_prefetch<NT1W, SMAX>(xp, cp, X, C, ch, g, nrnt, wave, col, h);
+    // 1. Hc: this wave's 32-column tiles c = 32 (wave + 8 u) + col, one tile at a time
+    // A[(q, part)][(s, h)] = part 0: (Re C, Im C)[h], part 1: (-Im C, Re C)[h]
     {
-      f32x16 acc1[NT1W];
-#pragma unroll
-      for (int u = 0; u < NT1W; ++u)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc1[u][r] = 0.f;
-      // A[(q, part)][(s, h)] = part 0: (Re C, Im C)[h], part 1: (-Im C, Re C)[h]
       const float csign = ((col & 1) == 1 && h == 0) ? -1.f : 1.f;
 #pragma unroll
-      for (int s = 0; s < SMAX; ++s)
-        if (s < sz) {
-          const float av = csign * cp[s];
-#pragma unroll
-          for (int u = 0; u < NT1W; ++u)
-            acc1[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, xp[s][u], acc1[u], 0, 0, 0);
-        }
-      // register pair (r, r + 1), r % 4 in {0, 2}, holds (re, im) of q = row / 2
-#pragma unroll
       for (int u = 0; u < NT1W; ++u) {
+        f32x16 acc1;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc1[r] = 0.f;
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s)
+          if (s < sz) acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(csign * cp[s], xp[s][u], acc1, 0, 0, 0);
+        // register pair (r, r + 1), r % 4 in {0, 2}, holds (re, im) of q = row / 2
         const int c = 32 * (wave + 8 * u) + col;
         if (c < nrnt)
 #pragma unroll
           for (int r = 0; r < 16; r += 2) {
             const int q = 4 * (r / 4) + 2 * h + ((r % 4) >> 1);
             if (q < pg)
-              *reinterpret_cast<float2*>(smf + q * SL + 2 * c) = make_float2(acc1[u][r], acc1[u][r + 1]);
+              *reinterpret_cast<float2*>(smf + q * SL + 2 * c) = make_float2(acc1[r], acc1[r + 1]);
           }
       }
     }
-    if (g + 1 < g1) bmm_prefetch<NT1W, SMAX>(xp, cp, X, C, ch, g + 1, nrnt, wave, col, h);
+    if (PF && g + 1 < g1) bmm_prefetch<NT1W, SMAX>(xp, cp, X, C, ch, g + 1, nrnt, wave, col, h);
     __syncthreads();
     // 2. W_q = A^H Hc_q, in place
     // both column tiles are read before either is written back; loads are unconditional
@@ -931,9 +1011,9 @@ gt_status launch_fused_b(const LaunchCtx& L, const float2* X, const float2* A, c
     const dim3 grid(L.max_nsplit, L.n_channels);
     const size_t sh = bmm_bytes(L);
     switch (v) {
-      case 1: GT_LAUNCH_SH((k_fused_b_mm<1, 12>), grid, dim3(512), sh, L.d_chans, X, A, C, L.ws); break;
-      case 2: GT_LAUNCH_SH((k_fused_b_mm<2, 12>), grid, dim3(512), sh, L.d_chans, X, A, C, L.ws); break;
-      default: GT_LAUNCH_SH((k_fused_b_mm<1, 24>), grid, dim3(512), sh, L.d_chans, X, A, C, L.ws); break;
+      case 1: GT_LAUNCH_SH((k_fused_b_mm<1, 12, false>), grid, dim3(512), sh, L.d_chans, X, A, C, L.ws); break;
+      case 2: GT_LAUNCH_SH((k_fused_b_mm<2, 12, false>), grid, dim3(512), sh, L.d_chans, X, A, C, L.ws); break;
+      default: GT_LAUNCH_SH((k_fused_b_mm<1, 24, false>), grid, dim3(512), sh, L.d_chans, X, A, C, L.ws); break;
     }
     GT_LAUNCH_SH(k_reduce_S2_mfma, dim3((L.max_nt * L.max_nt + 255) / 256, L.n_channels), dim3(256), 0,
                  L.d_chans, L.ws);
