@@ -16,6 +16,7 @@
 
 namespace gt {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __global__ void k_reduce_S2(const DevChan* __restrict__ chans, char* ws);
@@ -749,26 +750,43 @@ __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* _
   const int nr = ch.nr, nt = ch.nt, m = ch.m, p = ch.p;
   const int nrnt = nr * nt;
   const int SL = bmm_slot(nr, nt, m);
-  float* aop = smf + p * SL;  // [nr][64] step-2 A operand
+  float* aop = smf + max(p * SL, 2048);  // [nr][64] step-2 A operand
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int h = lane / 32, col = lane % 32;
-  // step-2 A operand of lane l at K step i: row l % 32 = (a, re/im), k = (i, l / 32)
+  // step-2 A operand.  m <= 8 (16 real rows) uses 16 x 16 x 4 products: lane l at K step t
+  // holds row l % 16 = (a, re/im) and k' = 4 t + l / 16 = (i, re/im).  Otherwise 32 x 32 x 2:
+  // lane l at K step i holds row l % 32 = (a, re/im) and k = (i, l / 32).
+  const bool w16 = m <= 8;
   for (int e = tid; e < nr * 64; e += 512) {
-    const int i = e / 64, l = e % 64, a = (l % 32) >> 1, part = l & 1, hh = l / 32;
+    const int st = e / 64, l = e % 64;
+    int a, part, i, kp;
+    if (w16) {
+      a = (l % 16) >> 1;
+      part = l & 1;
+      const int kk = 4 * st + l / 16;
+      i = kk >> 1;
+      kp = kk & 1;
+    } else {
+      a = (l % 32) >> 1;
+      part = l & 1;
+      i = st;
+      kp = l / 32;
+    }
     float v = 0.f;
-    if (a < m) {
+    if (a < m && i < nr) {
       const float2 av = A[ch.a + i * m + a];
-      v = part == 0 ? (hh == 0 ? av.x : av.y) : (hh == 0 ? -av.y : av.x);
+      v = part == 0 ? (kp == 0 ? av.x : av.y) : (kp == 0 ? -av.y : av.x);
     }
     aop[e] = v;
   }
-  // Gram tiles of this wave: wave and, for waves 0 and 1, wave + 8
-  const int nt2 = wave < 2 ? 2 : 1;
+  // Gram tiles: wave w owns tile w; tiles 8 and 9 are shared, waves 0 and 1 taking them over
+  // even q and waves 2 and 3 over odd q, so that each SIMD carries two and a half tiles
+  const int nt2 = wave < 4 ? 2 : 1;
   int offa[2], offb[2];
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     int I, J;
-    gram_tile(t == 0 ? wave : wave + 8, I, J);
+    gram_tile(t == 0 ? wave : 8 + (wave & 1), I, J);
     const int ca = 32 * I + col, cb = 32 * J + col;
     offa[t] = ca < 64 ? ca : m * 64 + (ca - 64);
     offb[t] = cb < 64 ? cb : m * 64 + (cb - 64);
@@ -816,6 +834,56 @@ __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* _
     // 2. W_q = A^H Hc_q, in place
     // both column tiles are read before either is written back; loads are unconditional
     // (clamped) and out-of-range operands are zeroed by selects, four K steps per batch
+    if (w16) {
+      // rows (a, re/im) < 16, four 16-column tiles of j, K = (i, re/im) in steps of 4
+      const int r16 = lane % 16, k4 = lane / 16;
+      for (int q = wave; q < pg; q += 8) {
+        float* slot = smf + q * SL;
+        f32x4 acc4[4];
+#pragma unroll
+        for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc4[jt][r] = 0.f;
+        int jc[4];
+        bool jv[4];
+#pragma unroll
+        for (int jt = 0; jt < 4; ++jt) {
+          jc[jt] = min(16 * jt + r16, nt - 1);
+          jv[jt] = 16 * jt + r16 < nt;
+        }
+        const int nst = (nr + 1) / 2;
+        for (int t0 = 0; t0 < nst; t0 += 2) {
+          float av[2], bv[2][4];
+#pragma unroll
+          for (int d = 0; d < 2; ++d) {
+            const int t = min(t0 + d, nst - 1);
+            const bool tv = t0 + d < nst;
+            const int kk = 4 * t + k4, i = min(kk >> 1, nr - 1);
+            const bool iv = tv && (kk >> 1) < nr;
+            const float x = aop[t * 64 + lane];
+            av[d] = tv ? x : 0.f;
+#pragma unroll
+            for (int jt = 0; jt < 4; ++jt) {
+              const float y = slot[2 * (i * nt + jc[jt]) + (kk & 1)];
+              bv[d][jt] = (iv && jv[jt]) ? y : 0.f;
+            }
+          }
+#pragma unroll
+          for (int d = 0; d < 2; ++d)
+#pragma unroll
+            for (int jt = 0; jt < 4; ++jt)
+              acc4[jt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[d], bv[d][jt], acc4[jt], 0, 0, 0);
+        }
+        // accumulator (lane l, register r) = row 4 (l / 16) + r, column 16 jt + l % 16
+#pragma unroll
+        for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 4 * k4 + r, a = row >> 1;
+            if (a < m) slot[((row & 1) ? m * 64 : 0) + a * 64 + 16 * jt + r16] = acc4[jt][r];
+          }
+      }
+    } else
     for (int q = wave; q < pg; q += 8) {
       float* slot = smf + q * SL;
       f32x16 acc2[2];
@@ -857,12 +925,13 @@ __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* _
     // odd m pads each q with a zero row); two steps per batch, loads unconditional
     for (int q = 0; q < pg; ++q) {
       const float* qb = smf + q * SL;
+      const bool two = nt2 == 2 && (q & 1) == (wave >> 1);
       for (int a0 = 0; a0 < m; a0 += 4) {
         const int ra = a0 + h, rb2 = a0 + 2 + h;
         const float sa = ra < m ? 1.f : 0.f, sb = rb2 < m ? 1.f : 0.f;
         const float* p0 = qb + min(ra, m - 1) * 64;
         const float* p1 = qb + min(rb2, m - 1) * 64;
-        if (nt2 == 2) {
+        if (two) {
           const float x00 = p0[offa[0]], y00 = p0[offb[0]], x01 = p0[offa[1]], y01 = p0[offb[1]];
           const float x10 = p1[offa[0]], y10 = p1[offb[0]], x11 = p1[offa[1]], y11 = p1[offb[1]];
           gacc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(sa * x00, y00, gacc[0], 0, 0, 0);
@@ -879,12 +948,20 @@ __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* _
     }
     __syncthreads();
   }
+  // waves 2 and 3 hand their odd-q parts of tiles 8 and 9 to waves 0 and 1 through LDS
+  if (wave == 2 || wave == 3)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) smf[(wave - 2) * 1024 + lane * 16 + r] = gacc[1][r];
+  __syncthreads();
+  if (wave < 2)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) gacc[1][r] += smf[wave * 1024 + lane * 16 + r];
   float* P = reinterpret_cast<float*>(ws + ch.w_S2p) + (int64_t)split * 128 * 128;
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
-    if (t < nt2) {
+    if (t == 0 || wave < 2) {
       int I, J;
-      gram_tile(t == 0 ? wave : wave + 8, I, J);
+      gram_tile(t == 0 ? wave : 8 + wave, I, J);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int row = 32 * I + 8 * (r / 4) + 4 * h + (r % 4);
@@ -990,7 +1067,8 @@ bool fused_b_mfma_ok(const LaunchCtx& L) {
 }
 
 static size_t bmm_bytes(const LaunchCtx& L) {
-  return sizeof(float) * ((size_t)L.max_p * bmm_slot(L.max_nr, L.max_nt, L.max_m) + (size_t)L.max_nr * 64);
+  return sizeof(float) * (std::max<size_t>((size_t)L.max_p * bmm_slot(L.max_nr, L.max_nt, L.max_m), 2048) +
+                          (size_t)L.max_nr * 64);
 }
 
 // All-matrix-core variant: p, m <= 16 (32 real rows of steps 1 and 2), nt <= 64, a group's
