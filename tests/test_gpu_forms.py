@@ -1,0 +1,89 @@
+"""The batched and differentiation forms on the GPU: graph capture and replay of a whole fit +
+SINR evaluation, and SINR-aware refinement of the cores through the hand-written adjoint."""
+
+import numpy as np
+import pytest
+import torch
+
+import synthgen
+from oracle import grad as ograd, sinr as osinr, tucker
+from tests.gpu_util import announce, desc, dev_c64, host
+
+pytestmark = pytest.mark.gpu
+
+
+def test_fit_and_sinr_graph_replay(gpu_lib):
+    # two 8 x 64 x 3276 channels: eager run, then a captured graph replayed three times with
+    # eager work in between; every replay must reproduce the eager outputs bit for bit
+    cfg = synthgen.CONFIGS["rb273"]
+    announce("graph capture fit + sinr, 2 x rb273")
+    X = torch.cat([dev_c64(synthgen.make_channel(cfg, c)) for c in range(2)])
+    plan = gpu_lib.Plan([gpu_lib.desc_from_config(cfg)] * 2, iters=cfg.iters)
+    s2 = [float(v) for v in synthgen.snr_to_sigma2(cfg.snr_db)]
+    f_eager = plan.empty_factors()
+    r = plan.fit(X, factors=f_eager, trace=False)
+    sg_eager = plan.sinr(r["C"], r["G"], s2).clone()
+    eager = {k: v.clone() for k, v in r.items()}
+    torch.cuda.synchronize()
+
+    f_graph = plan.empty_factors()
+    sg_out = torch.empty_like(sg_eager)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up outside the capture
+        plan.fit(X, factors=f_graph, trace=False)
+        plan.sinr(f_graph["C"], f_graph["G"], s2, out=sg_out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        rg = plan.fit(X, factors=f_graph, trace=False)
+        plan.sinr(f_graph["C"], f_graph["G"], s2, out=sg_out)
+    for rep in range(3):
+        for v in f_graph.values():
+            v.zero_()
+        sg_out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        for k in ("A", "B", "C", "G"):
+            assert torch.equal(f_graph[k], eager[k]), (rep, k)
+        assert torch.equal(rg["status"], eager["status"])
+        assert torch.equal(sg_out, sg_eager), rep
+        # unrelated eager work between replays
+        plan.reconstruct(eager["A"], eager["B"], eager["C"], eager["G"])
+        torch.cuda.synchronize()
+
+
+def test_sinr_aware_refinement(gpu_lib):
+    # 8 x 128 channel with 32 paths compressed at mode-2 rank 24 (lossy): refine (C, G) with
+    # Adam on the squared dB error of the compressed SINR against the full-channel SINR; the
+    # gradient comes from the library's adjoint through SinrFn
+    announce("sinr-aware refinement 8 x 128 x 96")
+    rng = np.random.default_rng(61)
+    nr, nt, nsc, L = 8, 128, 96, 32
+    X = synthgen.build_channel(synthgen.draw_paths(rng, L, 3.0), nr, nt, nsc)
+    gs, m, n, p, ns = 12, 8, 24, 12, 4
+    s2 = [0.1]
+    orc = tucker.fit(X, gs, m, n, p, 10)
+    target = torch.tensor(10.0 * np.log10(osinr.sinr(X, s2, ns)), dtype=torch.float32,
+                          device="cuda")
+    plan = gpu_lib.Plan([desc(nr, nt, nsc, gs, m, n, p, ns)], iters=10)
+    Ct = dev_c64(orc["C"]).requires_grad_(True)
+    Gt = dev_c64(orc["G"]).requires_grad_(True)
+    # loss at the oracle's starting point, the same quantity in FP64 on the CPU
+    y0 = ograd.sinr_compressed_t(torch.tensor(orc["C"]), torch.tensor(orc["G"]), gs, s2, ns)
+    loss0_ref = float(((10 * torch.log10(y0) - target.double().cpu()) ** 2).mean())
+    opt = torch.optim.Adam([Ct, Gt], lr=3e-3)
+    losses = []
+    for it in range(50):
+        y = gpu_lib.SinrFn.apply(plan, Ct, Gt, s2)[:, :, :ns]
+        loss = ((10 * torch.log10(y) - target) ** 2).mean()
+        losses.append(float(loss.detach()))
+        opt.zero_grad()
+        loss.backward()
+        opt.step()
+    assert abs(losses[0] - loss0_ref) <= 1e-3 * loss0_ref + 1e-7, (losses[0], loss0_ref)
+    assert losses[-1] < 0.1 * losses[0], losses[::10]
+    y = host(gpu_lib.SinrFn.apply(plan, Ct, Gt, s2)[:, :, :ns].detach())
+    err = np.abs(10 * np.log10(y) - host(target))
+    assert err.max() < 0.1, err.max()
