@@ -87,3 +87,47 @@ def test_sinr_aware_refinement(gpu_lib):
     y = host(gpu_lib.SinrFn.apply(plan, Ct, Gt, s2)[:, :, :ns].detach())
     err = np.abs(10 * np.log10(y) - host(target))
     assert err.max() < 0.1, err.max()
+
+
+def test_heterogeneous_batch(gpu_lib):
+    # 48 channels of uneven antenna counts (4..16 x 32..256), subcarrier counts (624..3276),
+    # group sizes (12, 24) and ranks in one plan: properties on every channel, FP64 oracle
+    # parity on the three smallest
+    announce("heterogeneous batch of 48 channels")
+    specs = synthgen.heterogeneous_batch(48)
+    iters = 6
+    descs = [dict(nr=d["nr"], nt=d["nt"], nsc=d["nsc"], group_size=d["group_size"], m=d["m"],
+                  n=d["n"], p=d["p"], ns=d["ns"]) for d in specs]
+    X = torch.cat([synthgen.build_channel_torch(d["paths"], d["nr"], d["nt"], d["nsc"],
+                                                torch.device("cuda"),
+                                                dtype=torch.complex64).reshape(-1)
+                   for d in specs])
+    plan = gpu_lib.Plan(descs, iters=iters)
+    res = plan.fit(X)
+    _, xh = plan.reconstruct(res["A"], res["B"], res["C"], res["G"], ht=False)
+    torch.cuda.synchronize()
+    assert np.all(host(res["status"]) == 0)
+    tr = host(res["trace"])
+    Xh_all = host(xh)
+    X_all = host(X)
+    sizes = []
+    for c, d in enumerate(descs):
+        o = plan.offsets(c)
+        nx = d["nsc"] * d["nr"] * d["nt"]
+        Xc = X_all[o.x:o.x + nx].astype(np.complex128)
+        Xhc = Xh_all[o.x:o.x + nx].astype(np.complex128)
+        n2 = float(np.sum(np.abs(Xc) ** 2))
+        A = host(res["A"])[o.a:o.a + d["nr"] * d["m"]].reshape(d["nr"], d["m"])
+        Bm = host(res["B"])[o.b:o.b + d["nt"] * d["n"]].reshape(d["nt"], d["n"])
+        assert np.abs(A.conj().T @ A - np.eye(d["m"])).max() < 1e-4, c
+        assert np.abs(Bm.conj().T @ Bm - np.eye(d["n"])).max() < 1e-4, c
+        assert np.all(np.diff(tr[c]) <= 1e-5 * n2), (c, np.diff(tr[c]).max() / n2)
+        resid = float(np.sum(np.abs(Xc - Xhc) ** 2))
+        assert abs(resid - tr[c, -1]) <= 1e-5 * n2, (c, resid / n2, tr[c, -1] / n2)
+        sizes.append((nx, c))
+    for _, c in sorted(sizes)[:3]:
+        d = specs[c]
+        Xo = synthgen.build_channel(d["paths"], d["nr"], d["nt"], d["nsc"])
+        orc = tucker.fit(Xo, d["group_size"], d["m"], d["n"], d["p"], iters)
+        n2 = float(np.sum(np.abs(Xo) ** 2))
+        assert np.abs(tr[c] - orc["trace"]).max() <= 1e-5 * n2, c
