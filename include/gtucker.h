@@ -62,7 +62,13 @@ typedef enum {
 
 typedef enum { GT_C64 = 0 } gt_dtype;
 
-/* Contraction precision of the fit's mode-n products.  Only GT_TTM_FP32 is provided. */
+/* Contraction precision of the fit's mode-n products H_s B and C_g^H H_s (the tensor-times-
+ * matrix contractions of the A- and B-steps).  BF16 and FP16 round both operands to 16 bits;
+ * SPLIT_BF16 writes each operand as hi + lo (two BF16 numbers) and sums the products hi hi,
+ * hi lo and lo hi.  Products always accumulate in FP32; the Grams, eigensolves, cores and
+ * the SINR chain stay in FP32.  The 16-bit forms are provided for plans whose channels all
+ * run the fused per-group passes (nt <= 64 and a multiple of 4, group_size * nr <= 128, p and
+ * m <= 16); gt_tucker_fit returns GT_ERR_UNSUPPORTED otherwise. */
 typedef enum { GT_TTM_FP32 = 0, GT_TTM_BF16 = 1, GT_TTM_FP16 = 2, GT_TTM_SPLIT_BF16 = 3 } gt_ttm_prec;
 
 #define GT_FIT_WARM_START 1u  /* A, B, C are read as the starting factors; the HOSVD step is skipped */
@@ -119,7 +125,8 @@ gt_status gt_workspace_init(const gt_plan* plan, void* ws, size_t ws_bytes, void
  * NULL) receives per channel 1 + 3*iters values of the objective f of equation "MT_origin"
  * after the initialisation and after each half-step, layout [n_channels][1 + 3*iters].
  * dev_status: [n_channels] int32 device words (may be NULL).  With GT_FIT_WARM_START the
- * initial A, B, C are read from the output buffers. */
+ * initial A, B, C are read from the output buffers.  GT_ERR_UNSUPPORTED: eig_fp64 with some
+ * nt > 64, or a 16-bit ttm_prec on a plan outside the fused passes (see gt_ttm_prec). */
 gt_status gt_tucker_fit(const gt_plan* plan, const void* X, void* A, void* B, void* C, void* G,
                         double* obj_trace, int32_t* dev_status, void* ws, size_t ws_bytes,
                         void* stream);

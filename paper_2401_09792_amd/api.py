@@ -42,15 +42,17 @@ class Plan:
     `offsets(c)`; SINR output is float32 [n_snr][total_subcarriers][ns_max].
     """
 
+    TTM_PREC = {"fp32": 0, "bf16": 1, "fp16": 2, "split_bf16": 3}
+
     def __init__(self, descs: Iterable[dict], iters: int = 20, eig_fp64: bool = False,
-                 warm_start: bool = False, device="cuda"):
+                 warm_start: bool = False, ttm_prec: str = "fp32", device="cuda"):
         self.lib = load()
         self.descs: List[dict] = [dict(d) for d in descs]
         arr = (ChannelDesc * len(self.descs))()
         for i, d in enumerate(self.descs):
             arr[i] = ChannelDesc(d["nr"], d["nt"], d["nsc"], d["group_size"], d["m"], d["n"],
                                  d["p"], d["ns"])
-        opt = FitOptions(int(iters), 0, 1 if eig_fp64 else 0,
+        opt = FitOptions(int(iters), self.TTM_PREC[ttm_prec], 1 if eig_fp64 else 0,
                          B.GT_FIT_WARM_START if warm_start else 0)
         h = C.c_void_p()
         check("gt_plan_create", self.lib.gt_plan_create(arr, len(self.descs), C.byref(opt),

@@ -667,6 +667,7 @@ static gt_status eig_dispatch(const LaunchCtx& L, int which, float2* A, float2* 
 }
 
 bool fused_fit_ok(const LaunchCtx& L);
+gt_status launch_convert_x(const LaunchCtx& L, const float2* X);
 gt_status launch_eigB_sub(const LaunchCtx& L, float2* B, int32_t* status, int warm);
 gt_status launch_fused_t(const LaunchCtx& L, const float2* X, const float2* A, const float2* B,
                          int do_c);
@@ -713,6 +714,7 @@ gt_status launch_fit(const LaunchCtx& L, const float2* X, float2* A, float2* B, 
     // per sweep: eigA, [W + Gram], eigB, [T, Yh, S3], eigC, [Z + S1 or cores]; the first
     // A-step Gram comes from [T] and [Z] with the starting factors
     gt_status st;
+    if (L.ttm_prec != GT_TTM_FP32 && (st = launch_convert_x(L, X)) != GT_OK) return st;
     if ((st = launch_fused_t(L, X, A, B, 0)) != GT_OK) return st;
     if ((st = launch_fused_z(L, C, G, iters > 0 ? 1 : 0, 0)) != GT_OK) return st;
     if (iters == 0) {

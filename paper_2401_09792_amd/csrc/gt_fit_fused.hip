@@ -141,6 +141,93 @@ __global__ void __launch_bounds__(256) k_fused_t(const DevChan* __restrict__ cha
   group_gram_s3(Yh, wsp2(ws, ch.w_S3) + (int64_t)it.g * ch.gs * ch.gs, ch.gs, sz, m * n, tid);
 }
 
+// The part of the T pass after the product: T (accumulators of 32 x 32 tiles over rows (s, i)
+// and the 2 n real columns) to LDS and the workspace, then for a C-step Yh = A^H T and the
+// group's mode-3 Gram.
+template <int TPW>
+__device__ __forceinline__ void fused_t_finish(const DevChan& ch, const GroupItem& it, int s0, int sz,
+                                               int rows, int ntile, float2* Ts, float2* Yh,
+                                               const float2* As, char* ws, int do_c,
+                                               f32x16 (&acc)[TPW], int wave, int half, int col,
+                                               int tid) {
+  const int nr = ch.nr, m = ch.m, n = ch.n;
+  // accumulator element (row 8 (r / 4) + 4 half + r % 4, column col) of tile -> T
+  float2* Tg = wsp2(ws, ch.w_T) + (int64_t)s0 * nr * n;
+  float* Tsf = reinterpret_cast<float*>(Ts);
+  float* Tgf = reinterpret_cast<float*>(Tg);
+#pragma unroll
+  for (int u = 0; u < TPW; ++u) {
+    const int tile = wave + 4 * u;
+    if (tile < ntile && col < 2 * n) {
+      const int c = col < n ? col : col - n;
+      const int part = col < n ? 0 : 1;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = tile * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+        if (row < rows) {
+          Tsf[2 * (row * n + c) + part] = acc[u][r];
+          Tgf[2 * (row * n + c) + part] = acc[u][r];
+        }
+      }
+    }
+  }
+  if (!do_c) return;
+  __syncthreads();
+  // Yh_s = A^H T_s: a thread owns column b of one T_s (in registers) and forms all m rows
+  float2* Yg = wsp2(ws, ch.w_Yh) + (int64_t)s0 * m * n;
+  for (int sb = tid; sb < sz * n; sb += 256) {
+    const int s = sb / n, b = sb - s * n;
+    float2 tc[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      tc[i] = i < nr ? Ts[(s * nr + i) * n + b] : make_float2(0.f, 0.f);
+    for (int a = 0; a < m; ++a) {
+      float yr = 0.f, yi = 0.f;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        if (i < nr) {
+          const float2 av = As[i * m + a];
+          yr += av.x * tc[i].x + av.y * tc[i].y;
+          yi += av.x * tc[i].y - av.y * tc[i].x;
+        }
+      }
+      const int o = (s * m + a) * n + b;
+      Yh[o] = make_float2(yr, yi);
+      if (do_c == 2) Yg[o] = make_float2(yr, yi);
+    }
+  }
+  __syncthreads();
+  // S3[s][t] = <Yh_s, Yh_t> on the upper triangle (16 lanes per entry), mirrored below
+  {
+    const int gs = ch.gs, mn = m * n, l16 = tid % 16;
+    float2* S3 = wsp2(ws, ch.w_S3) + (int64_t)it.g * gs * gs;
+    for (int k = tid / 16; k < gs * (gs + 1) / 2; k += 16) {
+      int s = 0, rem = k;
+      while (rem >= gs - s) {
+        rem -= gs - s;
+        ++s;
+      }
+      const int t = s + rem;
+      float ar = 0.f, ai = 0.f;
+      if (t < sz)
+        for (int e = l16; e < mn; e += 16) {
+          const float2 x = Yh[s * mn + e], y = Yh[t * mn + e];
+          ar += x.x * y.x + x.y * y.y;
+          ai += x.y * y.x - x.x * y.y;
+        }
+#pragma unroll
+      for (int d = 8; d > 0; d >>= 1) {
+        ar += __shfl_xor(ar, d, 64);
+        ai += __shfl_xor(ai, d, 64);
+      }
+      if (l16 == 0) {
+        S3[s * gs + t] = make_float2(ar, ai);
+        if (t != s) S3[t * gs + s] = make_float2(ar, -ai);
+      }
+    }
+  }
+}
+
 // Matrix-core variant of k_fused_t.  Stacking the group's rows (s, i) of H gives
 // T = H B as one complex (sz nr) x nt by nt x n product.  In real form the K index runs over
 // (j, re/im) pairs, k' = 2 j + part, which matches the interleaved storage of H, and
@@ -263,81 +350,140 @@ __global__ void __launch_bounds__(256) k_fused_t_mfma(const DevChan* __restrict_
       }
     }
   }
-  // accumulator element (row 8 (r / 4) + 4 half + r % 4, column col) of tile -> T
-  float2* Tg = wsp2(ws, ch.w_T) + (int64_t)s0 * nr * n;
-  float* Tsf = reinterpret_cast<float*>(Ts);
-  float* Tgf = reinterpret_cast<float*>(Tg);
-#pragma unroll
-  for (int u = 0; u < TPW; ++u) {
-    const int tile = wave + 4 * u;
-    if (tile < ntile && col < 2 * n) {
-      const int c = col < n ? col : col - n;
-      const int part = col < n ? 0 : 1;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = tile * 32 + 8 * (r / 4) + 4 * half + (r % 4);
-        if (row < rows) {
-          Tsf[2 * (row * n + c) + part] = acc[u][r];
-          Tgf[2 * (row * n + c) + part] = acc[u][r];
-        }
-      }
-    }
+  fused_t_finish<TPW>(ch, it, s0, sz, rows, ntile, Ts, Yh, As, ws, do_c, acc, wave, half, col, tid);
+}
+
+// ---------------------------------------------------------------------------------------
+// 16-bit contraction operands (precision form).  PREC 1: BF16, 2: FP16, 3: split BF16
+// (x = hi + lo with hi = bf16(x), lo = bf16(x - hi); products hi hi + hi lo + lo hi).  The
+// products accumulate in FP32 on 32 x 32 x 8 matrix cores; operand lane layout: lane l holds
+// A[l % 32][4 (l / 32) + v] and B[4 (l / 32) + v][l % 32], v = 0..3.
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short f2bf(float x) {  // round to nearest even
+  unsigned u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
+__device__ __forceinline__ unsigned short f2h(float x) {
+  return __builtin_bit_cast(unsigned short, (_Float16)x);
+}
+template <int PREC>
+__device__ __forceinline__ unsigned short q_hi(float x) { return PREC == 2 ? f2h(x) : f2bf(x); }
+template <int PREC>
+__device__ __forceinline__ unsigned short q_lo(float x) {
+  return PREC == 3 ? f2bf(x - bf2f(f2bf(x))) : (unsigned short)0;
+}
+
+template <int PREC>
+__device__ __forceinline__ f32x16 mfma16(s16x4 a, s16x4 b, f32x16 c) {
+  if constexpr (PREC == 2)
+    return __builtin_amdgcn_mfma_f32_32x32x8f16(__builtin_bit_cast(f16x4, a), __builtin_bit_cast(f16x4, b),
+                                                 c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ s16x4 pack4(unsigned short a, unsigned short b, unsigned short c,
+                                       unsigned short d) {
+  s16x4 v;
+  v[0] = (short)a;
+  v[1] = (short)b;
+  v[2] = (short)c;
+  v[3] = (short)d;
+  return v;
+}
+
+// 16-bit copy of each channel's X in the workspace, same element order (hi, then lo for the
+// split form).
+template <int PREC>
+__global__ void __launch_bounds__(256) k_convert_x(const DevChan* __restrict__ chans,
+                                                   const float2* __restrict__ X, char* ws) {
+  const DevChan& ch = chans[blockIdx.y];
+  const int64_t total = (int64_t)ch.nsc * ch.nr * ch.nt;
+  unsigned short* hi = reinterpret_cast<unsigned short*>(ws + ch.w_Xq);
+  unsigned short* lo = hi + 2 * total;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const float2 v = X[ch.x + e];
+    const unsigned short hr = q_hi<PREC>(v.x), hm = q_hi<PREC>(v.y);
+    *reinterpret_cast<ushort2*>(hi + 2 * e) = make_ushort2(hr, hm);
+    if (PREC == 3) *reinterpret_cast<ushort2*>(lo + 2 * e) = make_ushort2(q_lo<PREC>(v.x), q_lo<PREC>(v.y));
   }
-  if (!do_c) return;
+}
+
+// Precision-form T pass: T = H B on 16-bit operands (one 32-row tile per wave, nt % 4 == 0),
+// then the same finish as the FP32 pass.  B is staged in LDS in real form as [32 c][2 nt k'].
+template <int PREC>
+__global__ void __launch_bounds__(256) k_fused_t_lp(const DevChan* __restrict__ chans,
+                                                    const GroupItem* __restrict__ items,
+                                                    const float2* __restrict__ A,
+                                                    const float2* __restrict__ B, char* ws,
+                                                    int do_c) {
+  extern __shared__ float2 smem[];
+  const GroupItem it = items[blockIdx.x];
+  const DevChan& ch = chans[it.ch];
+  const int nr = ch.nr, nt = ch.nt, m = ch.m, n = ch.n;
+  const int s0 = it.g * ch.gs;
+  const int sz = min(ch.gs, ch.nsc - s0);
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int half = lane / 32, col = lane % 32;
+  constexpr int NQ = PREC == 3 ? 2 : 1;
+  unsigned short* Bq = reinterpret_cast<unsigned short*>(smem);  // [NQ][32][2 nt]
+  float2* As = smem + NQ * 32 * 2 * nt * 2 / 8;                 // nr x m
+  float2* Ts = As + nr * m;
+  float2* Yh = Ts + ch.gs * nr * n;
+  const int rows = sz * nr;
+  const int ntile = (rows + 31) / 32;
+  const int64_t xtot = (int64_t)ch.nsc * nr * nt;
+  const unsigned short* Xh = reinterpret_cast<const unsigned short*>(ws + ch.w_Xq);
+  const int K8 = 2 * nt / 8;  // K steps of 8 real indices
+  // the lane's half-row: K index k' = 8 t + 4 half + v, 8 contiguous bytes per step
+  const int row = min(wave * 32 + col, rows - 1);
+  const bool rv = wave * 32 + col < rows;
+  const uint2* xr = reinterpret_cast<const uint2*>(Xh + 2 * ((int64_t)s0 * nr * nt + (int64_t)row * nt));
+  uint2 ah[16], al[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    ah[t] = t < K8 ? xr[2 * t + half] : make_uint2(0u, 0u);
+    if (PREC == 3) al[t] = t < K8 ? xr[2 * t + half + xtot / 2] : make_uint2(0u, 0u);
+  }
+  for (int e = tid; e < 32 * 2 * nt; e += 256) {
+    const int c = e / (2 * nt), kk = e % (2 * nt), j = kk / 2, part = kk % 2;
+    float v = 0.f;
+    if (c < 2 * n) {
+      const float2 b = B[ch.b + j * n + (c < n ? c : c - n)];
+      v = (part == 0) ? (c < n ? b.x : b.y) : (c < n ? -b.y : b.x);
+    }
+    Bq[e] = q_hi<PREC>(v);
+    if (PREC == 3) Bq[32 * 2 * nt + e] = q_lo<PREC>(v);
+  }
+  for (int e = tid; e < nr * m; e += 256) As[e] = A[ch.a + e];
   __syncthreads();
-  // Yh_s = A^H T_s: a thread owns column b of one T_s (in registers) and forms all m rows
-  float2* Yg = wsp2(ws, ch.w_Yh) + (int64_t)s0 * m * n;
-  for (int sb = tid; sb < sz * n; sb += 256) {
-    const int s = sb / n, b = sb - s * n;
-    float2 tc[16];
+  f32x16 acc[1];
 #pragma unroll
-    for (int i = 0; i < 16; ++i)
-      tc[i] = i < nr ? Ts[(s * nr + i) * n + b] : make_float2(0.f, 0.f);
-    for (int a = 0; a < m; ++a) {
-      float yr = 0.f, yi = 0.f;
+  for (int r = 0; r < 16; ++r) acc[0][r] = 0.f;
+  if (wave < ntile) {
+    const uint2* bq = reinterpret_cast<const uint2*>(Bq + col * 2 * nt) + half;
+    const uint2* bl = reinterpret_cast<const uint2*>(Bq + 32 * 2 * nt + col * 2 * nt) + half;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        if (i < nr) {
-          const float2 av = As[i * m + a];
-          yr += av.x * tc[i].x + av.y * tc[i].y;
-          yi += av.x * tc[i].y - av.y * tc[i].x;
+    for (int t = 0; t < 16; ++t) {
+      if (t < K8) {
+        const uint2 a2 = rv ? ah[t] : make_uint2(0u, 0u);
+        const uint2 b2 = bq[2 * t];
+        const s16x4 a = __builtin_bit_cast(s16x4, a2), b = __builtin_bit_cast(s16x4, b2);
+        acc[0] = mfma16<PREC>(a, b, acc[0]);
+        if (PREC == 3) {
+          const uint2 a2l = rv ? al[t] : make_uint2(0u, 0u);
+          const uint2 b2l = bl[2 * t];
+          acc[0] = mfma16<PREC>(a, __builtin_bit_cast(s16x4, b2l), acc[0]);
+          acc[0] = mfma16<PREC>(__builtin_bit_cast(s16x4, a2l), b, acc[0]);
         }
-      }
-      const int o = (s * m + a) * n + b;
-      Yh[o] = make_float2(yr, yi);
-      if (do_c == 2) Yg[o] = make_float2(yr, yi);
-    }
-  }
-  __syncthreads();
-  // S3[s][t] = <Yh_s, Yh_t> on the upper triangle (16 lanes per entry), mirrored below
-  {
-    const int gs = ch.gs, mn = m * n, l16 = tid % 16;
-    float2* S3 = wsp2(ws, ch.w_S3) + (int64_t)it.g * gs * gs;
-    for (int k = tid / 16; k < gs * (gs + 1) / 2; k += 16) {
-      int s = 0, rem = k;
-      while (rem >= gs - s) {
-        rem -= gs - s;
-        ++s;
-      }
-      const int t = s + rem;
-      float ar = 0.f, ai = 0.f;
-      if (t < sz)
-        for (int e = l16; e < mn; e += 16) {
-          const float2 x = Yh[s * mn + e], y = Yh[t * mn + e];
-          ar += x.x * y.x + x.y * y.y;
-          ai += x.y * y.x - x.x * y.y;
-        }
-#pragma unroll
-      for (int d = 8; d > 0; d >>= 1) {
-        ar += __shfl_xor(ar, d, 64);
-        ai += __shfl_xor(ai, d, 64);
-      }
-      if (l16 == 0) {
-        S3[s * gs + t] = make_float2(ar, ai);
-        if (t != s) S3[t * gs + s] = make_float2(ar, -ai);
       }
     }
   }
+  fused_t_finish<1>(ch, it, s0, sz, rows, ntile, Ts, Yh, As, ws, do_c, acc, wave, half, col, tid);
 }
 
 // k_fused_z, one block per group, after the mode-3 eigensolve: the A-step partial Gram
@@ -735,10 +881,51 @@ __device__ __forceinline__ void bmm_prefetch(float (&xp)[SMAX][NT1W], float (&cp
   }
 }
 
+// Step-1 operands of group g on 16-bit data: B operand (slices 4 t + 2 h and 4 t + 2 h + 1, re
+// and im, column c) from the 16-bit copy of X, A operand from C quantised here; indices
+// clamped into the group, A zeroed for slices beyond the group or rows q >= p_g.
+template <int NT1W, int SMAX, int PREC>
+__device__ __forceinline__ void bmm_prefetch_lp(uint2 (&xq)[PREC == 3 ? 2 : 1][(2 * SMAX + 7) / 8][NT1W],
+                                                uint2 (&cq)[PREC == 3 ? 2 : 1][(2 * SMAX + 7) / 8],
+                                                const float2* __restrict__ C, const char* ws,
+                                                const DevChan& ch, int g, int nrnt, int wave,
+                                                int col, int h) {
+  constexpr int S8 = (2 * SMAX + 7) / 8;
+  const int s0 = g * ch.gs, sz = min(ch.gs, ch.nsc - s0);
+  const int pg = min(ch.p, sz);
+  const int64_t total = (int64_t)ch.nsc * nrnt;
+  const unsigned* xg = reinterpret_cast<const unsigned*>(ws + ch.w_Xq) + (int64_t)s0 * nrnt;
+  const int q = col >> 1, po = col & 1;
+  const int qc = min(q, pg - 1);
+#pragma unroll
+  for (int t = 0; t < S8; ++t) {
+    const int sa = 4 * t + 2 * h, sb = sa + 1;
+    const int sac = min(sa, sz - 1), sbc = min(sb, sz - 1);
+#pragma unroll
+    for (int u = 0; u < NT1W; ++u) {
+      const int c = min(32 * (wave + 8 * u) + col, nrnt - 1);
+      xq[0][t][u] = make_uint2(xg[(int64_t)sac * nrnt + c], xg[(int64_t)sbc * nrnt + c]);
+      if (PREC == 3)
+        xq[PREC == 3 ? 1 : 0][t][u] = make_uint2(xg[total + (int64_t)sac * nrnt + c],
+                                                 xg[total + (int64_t)sbc * nrnt + c]);
+    }
+    const float2 ca = C[ch.c + (int64_t)(s0 + sac) * ch.p + qc];
+    const float2 cb = C[ch.c + (int64_t)(s0 + sbc) * ch.p + qc];
+    const bool va = sa < sz && q < pg, vb = sb < sz && q < pg;
+    // A[(q, po)][(s, pi)]: po 0: (Re C, Im C)[pi]; po 1: (-Im C, Re C)[pi]
+    const float a0 = va ? (po == 0 ? ca.x : -ca.y) : 0.f, a1 = va ? (po == 0 ? ca.y : ca.x) : 0.f;
+    const float b0 = vb ? (po == 0 ? cb.x : -cb.y) : 0.f, b1 = vb ? (po == 0 ? cb.y : cb.x) : 0.f;
+    cq[0][t] = __builtin_bit_cast(uint2, pack4(q_hi<PREC>(a0), q_hi<PREC>(a1), q_hi<PREC>(b0), q_hi<PREC>(b1)));
+    if (PREC == 3)
+      cq[PREC == 3 ? 1 : 0][t] =
+          __builtin_bit_cast(uint2, pack4(q_lo<PREC>(a0), q_lo<PREC>(a1), q_lo<PREC>(b0), q_lo<PREC>(b1)));
+  }
+}
+
 // PF: the next group's step-1 operands are loaded while the current group's steps 2 and 3
 // run (more registers, one block per CU); otherwise they are loaded at the start of step 1
 // and latency is hidden by a second resident block.
-template <int NT1W, int SMAX, bool PF>
+template <int NT1W, int SMAX, bool PF, int PREC>
 __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* __restrict__ chans,
                                                        const float2* __restrict__ X,
                                                        const float2* __restrict__ A,
@@ -805,6 +992,37 @@ __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* _
     const int s0 = g * ch.gs;
     const int sz = min(ch.gs, ch.nsc - s0);
     const int pg = min(p, sz);
+    if (PREC != 0) {
+      // 1. Hc on 16-bit operands, K steps of 8 = two subcarriers x (re, im) per lane half
+      constexpr int S8 = (2 * SMAX + 7) / 8;
+      constexpr int NQ = PREC == 3 ? 2 : 1;
+      uint2 xq[NQ][S8][NT1W], cq[NQ][S8];
+      bmm_prefetch_lp<NT1W, SMAX, PREC>(xq, cq, C, ws, ch, g, nrnt, wave, col, h);
+#pragma unroll
+      for (int u = 0; u < NT1W; ++u) {
+        f32x16 acc1;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc1[r] = 0.f;
+#pragma unroll
+        for (int t = 0; t < S8; ++t)
+          if (8 * t < 2 * sz) {
+            const s16x4 a = __builtin_bit_cast(s16x4, cq[0][t]), b = __builtin_bit_cast(s16x4, xq[0][t][u]);
+            acc1 = mfma16<PREC>(a, b, acc1);
+            if (PREC == 3) {
+              acc1 = mfma16<PREC>(a, __builtin_bit_cast(s16x4, xq[NQ - 1][t][u]), acc1);
+              acc1 = mfma16<PREC>(__builtin_bit_cast(s16x4, cq[NQ - 1][t]), b, acc1);
+            }
+          }
+        const int c = 32 * (wave + 8 * u) + col;
+        if (c < nrnt)
+#pragma unroll
+          for (int r = 0; r < 16; r += 2) {
+            const int q = 4 * (r / 4) + 2 * h + ((r % 4) >> 1);
+            if (q < pg)
+              *reinterpret_cast<float2*>(smf + q * SL + 2 * c) = make_float2(acc1[r], acc1[r + 1]);
+          }
+      }
+    } else {
     if (!PF) bmm_prefetch<NT1W, SMAX>(xp, cp, X, C, ch, g, nrnt, wave, col, h);
     // 1. Hc: this wave's 32-column tiles c = 32 (wave + 8 u) + col, one tile at a time
     // A[(q, part)][(s, h)] = part 0: (Re C, Im C)[h], part 1: (-Im C, Re C)[h]
@@ -830,6 +1048,7 @@ __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* _
       }
     }
     if (PF && g + 1 < g1) bmm_prefetch<NT1W, SMAX>(xp, cp, X, C, ch, g + 1, nrnt, wave, col, h);
+    }
     __syncthreads();
     // 2. W_q = A^H Hc_q, in place
     // both column tiles are read before either is written back; loads are unconditional
@@ -1030,8 +1249,51 @@ static size_t tm_bytes(const LaunchCtx& L) {
                            (size_t)L.max_gs * L.max_nr * L.max_n + (size_t)L.max_gs * L.max_m * L.max_n);
 }
 
+static size_t tlp_bytes(const LaunchCtx& L) {
+  const size_t nq = L.ttm_prec == GT_TTM_SPLIT_BF16 ? 2 : 1;
+  return nq * 32 * 2 * L.max_nt * sizeof(unsigned short) +
+         sizeof(float2) * ((size_t)L.max_nr * L.max_m + (size_t)L.max_gs * L.max_nr * L.max_n +
+                           (size_t)L.max_gs * L.max_m * L.max_n);
+}
+
+static int bmm_variant(const LaunchCtx& L);
+
+// The precision form runs on the fused passes with the matrix-core B-step kernel and one
+// 32-row tile per wave in the T pass (every channel's nt a multiple of 4, checked by the plan).
+bool fused_lowp_ok(const LaunchCtx& L) {
+  return fused_fit_ok(L) && bmm_variant(L) != 0 && L.max_gs * L.max_nr <= 128 &&
+         tlp_bytes(L) <= 64 * 1024;
+}
+
+gt_status launch_convert_x(const LaunchCtx& L, const float2* X) {
+  const int64_t per = (int64_t)L.max_nsc * L.max_nr * L.max_nt;
+  const dim3 grid((unsigned)std::min<int64_t>((per + 255) / 256, 2048), L.n_channels);
+  switch (L.ttm_prec) {
+    case GT_TTM_BF16: GT_LAUNCH_SH((k_convert_x<1>), grid, dim3(256), 0, L.d_chans, X, L.ws); break;
+    case GT_TTM_FP16: GT_LAUNCH_SH((k_convert_x<2>), grid, dim3(256), 0, L.d_chans, X, L.ws); break;
+    default: GT_LAUNCH_SH((k_convert_x<3>), grid, dim3(256), 0, L.d_chans, X, L.ws); break;
+  }
+  return GT_OK;
+}
+
 gt_status launch_fused_t(const LaunchCtx& L, const float2* X, const float2* A, const float2* B,
                          int do_c) {
+  if (L.ttm_prec != GT_TTM_FP32) {
+    const dim3 grid(L.total_groups);
+    const size_t sh = tlp_bytes(L);
+    switch (L.ttm_prec) {
+      case GT_TTM_BF16:
+        GT_LAUNCH_SH((k_fused_t_lp<1>), grid, dim3(256), sh, L.d_chans, L.d_groups, A, B, L.ws, do_c);
+        break;
+      case GT_TTM_FP16:
+        GT_LAUNCH_SH((k_fused_t_lp<2>), grid, dim3(256), sh, L.d_chans, L.d_groups, A, B, L.ws, do_c);
+        break;
+      default:
+        GT_LAUNCH_SH((k_fused_t_lp<3>), grid, dim3(256), sh, L.d_chans, L.d_groups, A, B, L.ws, do_c);
+        break;
+    }
+    return GT_OK;
+  }
   // matrix cores when the real output fits one column tile and at most 8 row tiles
   if (L.max_n <= 16 && L.max_gs * L.max_nr <= 256 && tm_bytes(L) <= 64 * 1024) {
     if (L.max_gs * L.max_nr <= 128)
@@ -1088,11 +1350,22 @@ gt_status launch_fused_b(const LaunchCtx& L, const float2* X, const float2* A, c
   if (v) {
     const dim3 grid(L.max_nsplit, L.n_channels);
     const size_t sh = bmm_bytes(L);
+#define GT_BMM(NT1W, SMAX, PREC) \
+  GT_LAUNCH_SH((k_fused_b_mm<NT1W, SMAX, false, PREC>), grid, dim3(512), sh, L.d_chans, X, A, C, L.ws)
+#define GT_BMM_PREC(NT1W, SMAX)                          \
+  switch (L.ttm_prec) {                                  \
+    case GT_TTM_BF16: GT_BMM(NT1W, SMAX, 1); break;      \
+    case GT_TTM_FP16: GT_BMM(NT1W, SMAX, 2); break;      \
+    case GT_TTM_SPLIT_BF16: GT_BMM(NT1W, SMAX, 3); break; \
+    default: GT_BMM(NT1W, SMAX, 0); break;               \
+  }
     switch (v) {
-      case 1: GT_LAUNCH_SH((k_fused_b_mm<1, 12, false>), grid, dim3(512), sh, L.d_chans, X, A, C, L.ws); break;
-      case 2: GT_LAUNCH_SH((k_fused_b_mm<2, 12, false>), grid, dim3(512), sh, L.d_chans, X, A, C, L.ws); break;
-      default: GT_LAUNCH_SH((k_fused_b_mm<1, 24, false>), grid, dim3(512), sh, L.d_chans, X, A, C, L.ws); break;
+      case 1: GT_BMM_PREC(1, 12); break;
+      case 2: GT_BMM_PREC(2, 12); break;
+      default: GT_BMM_PREC(1, 24); break;
     }
+#undef GT_BMM_PREC
+#undef GT_BMM
     GT_LAUNCH_SH(k_reduce_S2_mfma, dim3((L.max_nt * L.max_nt + 255) / 256, L.n_channels), dim3(256), 0,
                  L.d_chans, L.ws);
     return GT_OK;

@@ -34,6 +34,7 @@ struct DevChan {
   int64_t w_VB;    // [64][max(64,nt)]    c64   last mode-2 eigenbasis (padded; for nt > 64 the
                    //                           64-column Ritz block, column-major)
   int64_t w_VS;    // [2][64][nt]         c64   subspace-iteration buffers (nt > 64 only)
+  int64_t w_Xq;    // [2][nsc][nr][nt][2] u16   16-bit copy of X (hi, lo) for the precision form
   int64_t w_VC;    // [ngroups][32][32]   c64   last mode-3 eigenbases (padded)
   int64_t w_lamg;  // [ngroups] double          per-group sums (norms, eigenvalue sums)
   int64_t w_scal;  // [8] double                ||X||^2, eigenvalue sums of the A and B steps
@@ -64,6 +65,7 @@ struct LaunchCtx {
   int max_nr, max_nt, max_nsc, max_gs, max_m, max_n, max_p, max_ns, max_groups, max_nsplit;
   int min_nt;
   int eig_fp64;
+  int ttm_prec;  // gt_ttm_prec of the plan
 };
 
 // kernel timing hooks (no-ops unless profiling is on)

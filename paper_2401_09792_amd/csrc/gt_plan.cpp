@@ -15,6 +15,7 @@
 namespace gt {
 gt_status launch_fit(const LaunchCtx& L, const float2* X, float2* A, float2* B, float2* C, float2* G,
                      double* trace, int32_t* status, int iters, bool warm);
+bool fused_lowp_ok(const LaunchCtx& L);
 gt_status launch_reconstruct(const LaunchCtx& L, int64_t total_sc, const float2* A, const float2* B,
                              const float2* C, const float2* G, float2* Ht, float2* Xhat);
 gt_status launch_reconstruct_bwd(const LaunchCtx& L, int64_t total_sc, const float2* A,
@@ -126,7 +127,6 @@ gt_status gt_plan_create(const gt_channel_desc* descs, int32_t n_channels, const
   if (opt) o = *opt;
   if (o.iters < 0 || o.eig_fp64 < 0 || o.eig_fp64 > 1) return GT_ERR_ARG;
   if (o.ttm_prec < GT_TTM_FP32 || o.ttm_prec > GT_TTM_SPLIT_BF16) return GT_ERR_ARG;
-  if (o.ttm_prec != GT_TTM_FP32) return GT_ERR_UNSUPPORTED;
   if (o.flags & ~GT_FIT_WARM_START) return GT_ERR_ARG;
   for (int c = 0; c < n_channels; ++c) {
     gt_status st = validate(descs[c]);
@@ -213,6 +213,8 @@ gt_status gt_plan_create(const gt_channel_desc* descs, int32_t n_channels, const
     ch.w_VA = take(c8 * 16 * 16);
     ch.w_VB = take(c8 * 64 * std::max(64, ch.nt));
     ch.w_VS = take(ch.nt > 64 ? c8 * 2 * 64 * ch.nt : 8);
+    ch.w_Xq = take(o.ttm_prec == GT_TTM_FP32 ? 8
+                   : (o.ttm_prec == GT_TTM_SPLIT_BF16 ? 8 : 4) * (int64_t)ch.nsc * ch.nr * ch.nt);
     ch.w_VC = take(c8 * ch.ngroups * 32 * 32);
     ch.w_lamg = take(8 * (int64_t)ch.ngroups);
     ch.w_scal = take(8 * 8);
@@ -276,6 +278,7 @@ static LaunchCtx make_ctx(const gt_plan* p, void* ws, void* stream) {
   L.max_groups = p->max_groups;
   L.max_nsplit = p->max_nsplit;
   L.min_nt = p->min_nt;
+  L.ttm_prec = p->opt.ttm_prec;
   L.eig_fp64 = p->opt.eig_fp64;
   return L;
 }
@@ -301,6 +304,12 @@ gt_status gt_tucker_fit(const gt_plan* plan, const void* X, void* A, void* B, vo
   // wide arrays (nt > 64) use the FP32 subspace-iteration eigensolver only
   if (plan->max_nt > kMaxNt && plan->opt.eig_fp64) return GT_ERR_UNSUPPORTED;
   LaunchCtx L = make_ctx(plan, ws, stream);
+  // 16-bit contractions exist for the fused per-group passes only
+  if (plan->opt.ttm_prec != GT_TTM_FP32) {
+    bool nt4 = true;
+    for (const auto& d : plan->desc) nt4 = nt4 && d.nt % 4 == 0;
+    if (!nt4 || !fused_lowp_ok(L)) return GT_ERR_UNSUPPORTED;
+  }
   return launch_fit(L, (const float2*)X, (float2*)A, (float2*)B, (float2*)C, (float2*)G, obj_trace,
                     dev_status, plan->opt.iters, (plan->opt.flags & GT_FIT_WARM_START) != 0);
 }

@@ -60,7 +60,11 @@ def test_plan_validation(lib):
     for d, code in bad.items():
         st, h = _plan(lib, [d])
         assert st == code, (d, st)
-    assert _plan(lib, [ok], ttm=1)[0] == 5      # BF16 contractions not provided
+    for ttm in (1, 2, 3):                       # 16-bit contraction forms are accepted
+        st, h = _plan(lib, [ok], ttm=ttm)
+        assert st == 0, ttm
+        lib.gt_plan_destroy(h)
+    assert _plan(lib, [ok], ttm=4)[0] == 1      # unknown precision
     assert _plan(lib, [ok], iters=-1)[0] == 1
     assert _plan(lib, [ok], flags=4)[0] == 1
     h = C.c_void_p()

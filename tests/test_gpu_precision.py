@@ -1,0 +1,74 @@
+"""The precision form: the fit's tensor-times-matrix contractions on 16-bit operands (BF16,
+FP16, split BF16) with FP32 accumulation, against the FP64 oracle.
+
+Bars: SINR within 0.1 dB for BF16 and FP16, 0.05 dB for split BF16 (the plain FP32 bar);
+reconstruction within 2e-2 (BF16), 5e-3 (FP16) and 1e-4 (split BF16) of ||X|| on a lossy
+tensor, and the objective trace within the same fractions of ||X||^2.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import synthgen
+from oracle import metrics, sinr as osinr, tucker
+from paper_2401_09792_amd._binding import GtError
+from tests.gpu_util import announce, crandn, db, desc, dev_c64, host, unpack
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"bf16": (0.1, 2e-2), "fp16": (0.1, 5e-3), "split_bf16": (0.05, 1e-4)}
+
+
+@pytest.fixture(scope="module")
+def rb273_oracle():
+    cfg = synthgen.CONFIGS["rb273"]
+    X = synthgen.make_channel(cfg, 0)
+    orc = tucker.fit(X, cfg.group_size, cfg.m, cfg.n, cfg.p, cfg.iters)
+    Ht, _ = tucker.reconstruct(orc["A"], orc["B"], orc["C"], orc["G"], cfg.group_size)
+    s2 = synthgen.snr_to_sigma2(cfg.snr_db)
+    return cfg, X, orc, osinr.sinr(Ht, s2, cfg.ns), s2
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "split_bf16"])
+def test_precision_rb273_sinr(gpu_lib, rb273_oracle, prec):
+    cfg, X, orc, ref, s2 = rb273_oracle
+    announce(f"precision {prec} rb273 fit + sinr")
+    plan = gpu_lib.Plan([gpu_lib.desc_from_config(cfg)], iters=cfg.iters, ttm_prec=prec)
+    res = plan.fit(dev_c64(X))
+    sg = host(plan.sinr(res["C"], res["G"], s2))
+    assert int(res["status"].item()) == 0
+    err = np.abs(db(sg[:, :, :cfg.ns]) - db(ref))
+    print(f"[precision] {prec}: max SINR error {err.max():.3e} dB, mean {err.mean():.3e} dB")
+    assert err.max() <= TOL[prec][0], err.max()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "split_bf16"])
+def test_precision_lossy_fit(gpu_lib, prec):
+    announce(f"precision {prec} lossy fit")
+    rng = np.random.default_rng(71)
+    nsc, nr, nt, gs, m, n, p, iters = 40, 8, 32, 12, 4, 8, 6, 5
+    X = crandn(rng, nsc, nr, nt)
+    X = X * (0.6 ** np.arange(nr))[None, :, None] * (0.85 ** np.arange(nt))[None, None, :]
+    plan = gpu_lib.Plan([desc(nr, nt, nsc, gs, m, n, p, 2)], iters=iters, ttm_prec=prec)
+    res = plan.fit(dev_c64(X))
+    _, xh = plan.reconstruct(res["A"], res["B"], res["C"], res["G"])
+    Xh = unpack(plan, 0, host(xh), "x")
+    orc = tucker.fit(X, gs, m, n, p, iters)
+    _, Xh_o = tucker.reconstruct(orc["A"], orc["B"], orc["C"], orc["G"], gs)
+    nx = float(np.sum(np.abs(X) ** 2))
+    rel = np.linalg.norm(Xh - Xh_o) / np.sqrt(nx)
+    tr_err = np.abs(host(res["trace"])[0] - orc["trace"]).max() / nx
+    print(f"[precision] {prec}: X-hat {rel:.3e} of ||X||, trace {tr_err:.3e} of ||X||^2, "
+          f"NMSE {metrics.nmse(X, Xh):.4e} vs {metrics.nmse(X, Xh_o):.4e}")
+    assert int(res["status"].item()) == 0
+    assert rel <= TOL[prec][1], rel
+    assert tr_err <= TOL[prec][1], tr_err
+
+
+def test_precision_outside_fused_path_is_rejected(gpu_lib):
+    # nt = 128 runs the generic passes, where no 16-bit form exists
+    plan = gpu_lib.Plan([desc(4, 128, 24, 12, 2, 8, 4, 2)], iters=2, ttm_prec="bf16")
+    X = dev_c64(crandn(np.random.default_rng(1), 24, 4, 128))
+    with pytest.raises(GtError, match="GT_ERR_UNSUPPORTED"):
+        plan.fit(X)
