@@ -101,6 +101,101 @@ def copy_calibration(mib: int) -> None:
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "copies": 3}))
 
 
+def time_forms(api, synthgen, cfg, X, B, s2, ms_fp32, sg_fp32, torch, steps):
+    """The precision, batched (graph replay) and differentiation forms on the same GPU:
+    throughput of fit + SINR (eager FP32 first, as the reference) and SINR error against the
+    plain FP32 step's output."""
+    import numpy as np
+
+    forms = {}
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    def db_err(a, b):
+        a = a[:, :cfg.nsc * B, :cfg.ns].cpu().numpy()
+        b = b[:, :cfg.nsc * B, :cfg.ns].cpu().numpy()
+        live = (a > 0) & (b > 0)
+        return float(np.abs(10 * np.log10(a[live]) - 10 * np.log10(b[live])).max())
+
+    for prec in ("fp32", "bf16", "fp16", "split_bf16"):
+        plan = api.Plan([api.desc_from_config(cfg)] * B, iters=cfg.iters, ttm_prec=prec)
+        f = plan.empty_factors()
+        out = {}
+
+        def step_p():
+            r = plan.fit(X, factors=f, trace=False)
+            out["sg"] = plan.sinr(r["C"], r["G"], s2)
+
+        ms = timed(step_p, steps)
+        forms[prec] = dict(fits_per_s=B / (ms / 1e3), ms_per_fit_batch=ms,
+                           max_sinr_err_db_vs_fp32=db_err(out["sg"], sg_fp32))
+        del plan, f
+    # batched form: the whole FP32 fit + SINR captured once and replayed
+    plan = api.Plan([api.desc_from_config(cfg)] * B, iters=cfg.iters)
+    f = plan.empty_factors()
+    sg_out = torch.empty_like(sg_fp32)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.fit(X, factors=f, trace=False)
+        plan.sinr(f["C"], f["G"], s2, out=sg_out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.fit(X, factors=f, trace=False)
+        plan.sinr(f["C"], f["G"], s2, out=sg_out)
+    ms = timed(g.replay, steps)
+    forms["graph_replay_fp32"] = dict(fits_per_s=B / (ms / 1e3), ms_per_fit_batch=ms,
+                                      max_sinr_err_db_vs_fp32=db_err(sg_out, sg_fp32))
+    del g, plan, f
+    # differentiation form: SINR-aware refinement steps of (C, G) on the 8 x 128 x 1632
+    # workload (64 channels, ranks (8, 24, 12), 4 streams, 10 dB)
+    gcfg = synthgen.CONFIGS["grad"]
+    dev = torch.device("cuda:0")
+    xs = []
+    for c in range(gcfg.n_channels):
+        pp = synthgen.draw_paths(synthgen.channel_rng(gcfg.seed_index, c), gcfg.n_paths, gcfg.k_db)
+        xs.append(synthgen.build_channel_torch(pp, gcfg.nr, gcfg.nt, gcfg.nsc, dev,
+                                               dtype=torch.complex64).reshape(-1))
+    Xg = torch.cat(xs)
+    del xs
+    plan = api.Plan([api.desc_from_config(gcfg)] * gcfg.n_channels, iters=gcfg.iters)
+    gs2 = [float(v) for v in synthgen.snr_to_sigma2(gcfg.snr_db)]
+    r = plan.fit(Xg, trace=False)
+    target = 10 * torch.log10(plan.sinr_full(Xg, gs2).clamp_min(1e-30))
+    Ct = r["C"].clone().requires_grad_(True)
+    Gt = r["G"].clone().requires_grad_(True)
+    opt = torch.optim.Adam([Ct, Gt], lr=3e-3)
+    losses = []
+
+    def refine():
+        y = api.SinrFn.apply(plan, Ct, Gt, gs2)
+        live = target > -299.0
+        loss = ((10 * torch.log10(y.clamp_min(1e-30)) - target)[live] ** 2).mean()
+        opt.zero_grad()
+        loss.backward()
+        opt.step()
+        losses.append(loss.detach())
+
+    ms = timed(refine, 50)
+    forms["sinr_aware_refinement"] = dict(
+        workload="64 x (8 x 128 x 1632), ranks (8, 24, 12), Ns 4, 10 dB, Adam lr 3e-3",
+        steps_per_s=1e3 / ms, ms_per_step=ms, loss_first=float(losses[0]),
+        loss_last=float(losses[-1]))
+    return forms
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +204,8 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="channels per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=4, help="channels timed on the oracle")
+    ap.add_argument("--forms", action="store_true",
+                    help="also time the precision, graph-replay and refinement forms")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run three plain copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -252,6 +349,10 @@ def main():
                    nmse_gpu=metrics.nmse(Xc, xh0))
         del htg
 
+    forms = None
+    if args.forms:
+        forms = time_forms(api, synthgen, cfg, X, B, s2, ms_step, sg, torch, max(args.steps, 2))
+
     line = {
         "metric": "subcarrier SINR evals/sec + Tucker fits/sec at <=0.1 dB err vs FP64 oracle",
         "value": fits_per_s,
@@ -273,6 +374,7 @@ def main():
         "cpu_baseline": cpu,
         "accuracy": acc,
         "kernels": kern,
+        "forms": forms,
         "wall_s": wall,
     }
     print(json.dumps(line))
