@@ -94,6 +94,77 @@ __global__ void __launch_bounds__(256) k_init_group(const DevChan* __restrict__ 
   if (tid == 0) wsd(ws, ch.w_lamg)[it.g] = red[0];
 }
 
+// The same for groups of at most 8192 complex entries, staged whole: 16 lanes per output over
+// the upper triangles of S1 (over (s, j)) and S3 (over (i, j)), mirrored below.
+__global__ void __launch_bounds__(256) k_init_group_lds(const DevChan* __restrict__ chans,
+                                                        const GroupItem* __restrict__ items,
+                                                        const float2* __restrict__ X, char* ws) {
+  __shared__ float2 xs[8192];
+  __shared__ double red[256];
+  const GroupItem it = items[blockIdx.x];
+  CH_BEGIN(it.ch);
+  const int s0 = it.g * ch.gs;
+  const int sz = min(ch.gs, ch.nsc - s0);
+  const int nr = ch.nr, nt = ch.nt, gs = ch.gs;
+  const int slice = nr * nt, tot = sz * slice;
+  const float2* Xg = X + ch.x + (int64_t)s0 * slice;
+  const int tid = threadIdx.x, l16 = tid % 16;
+  double nrm = 0.0;
+  for (int e = tid; e < tot; e += 256) {
+    const float2 v = Xg[e];
+    xs[e] = v;
+    nrm += (double)v.x * v.x + (double)v.y * v.y;
+  }
+  __syncthreads();
+  const int n1 = nr * (nr + 1) / 2, n3 = gs * (gs + 1) / 2;
+  float2* S1 = wsp(ws, ch.w_S1p) + (int64_t)it.g * nr * nr;
+  float2* S3 = wsp(ws, ch.w_S3) + (int64_t)it.g * gs * gs;
+  for (int k = tid / 16; k < n1 + n3; k += 16) {
+    const bool one = k < n1;
+    const int dim = one ? nr : gs;
+    int a = 0, rem = one ? k : k - n1;
+    while (rem >= dim - a) {
+      rem -= dim - a;
+      ++a;
+    }
+    const int b = a + rem;
+    float ar = 0.f, ai = 0.f;
+    if (one) {
+      // S1[a][b] = sum_{s, j} H_s[a][j] conj(H_s[b][j])
+      for (int s = 0; s < sz; ++s)
+        for (int j = l16; j < nt; j += 16) {
+          const float2 x = xs[s * slice + a * nt + j], y = xs[s * slice + b * nt + j];
+          ar += x.x * y.x + x.y * y.y;
+          ai += x.y * y.x - x.x * y.y;
+        }
+    } else if (b < sz) {
+      // S3[a][b] = <H_a, H_b> = sum_e H_a[e] conj(H_b[e])
+      for (int e = l16; e < slice; e += 16) {
+        const float2 x = xs[a * slice + e], y = xs[b * slice + e];
+        ar += x.x * y.x + x.y * y.y;
+        ai += x.y * y.x - x.x * y.y;
+      }
+    }
+#pragma unroll
+    for (int d = 8; d > 0; d >>= 1) {
+      ar += __shfl_xor(ar, d, 64);
+      ai += __shfl_xor(ai, d, 64);
+    }
+    if (l16 == 0) {
+      float2* S = one ? S1 : S3;
+      S[a * dim + b] = make_float2(ar, ai);
+      if (a != b) S[b * dim + a] = make_float2(ar, -ai);
+    }
+  }
+  red[tid] = nrm;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) wsd(ws, ch.w_lamg)[it.g] = red[0];
+}
+
 // Sum of the per-group norms: scal[0] = ||X||^2.
 __global__ void k_norm_total(const DevChan* __restrict__ chans, int n_channels, char* ws) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -668,6 +739,7 @@ static gt_status eig_dispatch(const LaunchCtx& L, int which, float2* A, float2* 
 
 bool fused_fit_ok(const LaunchCtx& L);
 gt_status launch_convert_x(const LaunchCtx& L, const float2* X);
+gt_status launch_gram_x(const LaunchCtx& L, const float2* X);
 gt_status launch_eigB_sub(const LaunchCtx& L, float2* B, int32_t* status, int warm);
 gt_status launch_fused_t(const LaunchCtx& L, const float2* X, const float2* A, const float2* B,
                          int do_c);
@@ -689,12 +761,19 @@ gt_status launch_fit(const LaunchCtx& L, const float2* X, float2* A, float2* B, 
   const dim3 gRed(cdiv((int64_t)L.max_nt * L.max_nt, 256), nch);
 
   // initialisation: Grams of the unfoldings, norms
-  GT_LAUNCH(k_init_group, dim3(L.total_groups), b256, L.d_chans, L.d_groups, X, L.ws);
+  if ((int64_t)L.max_gs * L.max_nr * L.max_nt <= 8192)
+    GT_LAUNCH(k_init_group_lds, dim3(L.total_groups), b256, L.d_chans, L.d_groups, X, L.ws);
+  else
+    GT_LAUNCH(k_init_group, dim3(L.total_groups), b256, L.d_chans, L.d_groups, X, L.ws);
   GT_LAUNCH(k_norm_total, dim3(cdiv(nch, 64)), dim3(64), L.d_chans, nch, L.ws);
   if (!warm) {
-    GT_LAUNCH(k_gram_rows, gGram, b256, L.d_chans, X, L.ws, 0);
-    GT_LAUNCH(k_reduce_S2, gRed, b256, L.d_chans, L.ws);
     gt_status st;
+    if (L.max_nt <= 64) {
+      if ((st = launch_gram_x(L, X)) != GT_OK) return st;
+    } else {
+      GT_LAUNCH(k_gram_rows, gGram, b256, L.d_chans, X, L.ws, 0);
+      GT_LAUNCH(k_reduce_S2, gRed, b256, L.d_chans, L.ws);
+    }
     if ((st = eig_dispatch(L, 0, A, B, C, status, 0)) != GT_OK) return st;
     if ((st = eig_dispatch(L, 1, A, B, C, status, 0)) != GT_OK) return st;
     if ((st = eig_dispatch(L, 2, A, B, C, status, 0)) != GT_OK) return st;
