@@ -137,7 +137,7 @@ __device__ __forceinline__ void jsync() {
 // accumulated onto it).  Returns true once the off-diagonal Frobenius norm is below
 // 8 eps times the diagonal norm for every matrix of the wave (or block).
 template <typename T, int MP, int NW>
-__device__ bool jacobi_herm(EigLds<T, MP>& L, int r, int wave, int max_sweeps,
+__device__ __forceinline__ bool jacobi_herm(EigLds<T, MP>& L, int r, int wave, int max_sweeps,
                             bool preset_v = false) {
   static_assert(NW == 1 || MP == 64, "multi-wave Jacobi needs MP == 64");
   constexpr int KP = MP / 2;
@@ -282,7 +282,7 @@ __device__ bool jacobi_herm(EigLds<T, MP>& L, int r, int wave, int max_sweeps,
 // per matrix, lane r owns row r).  tr/ti is scratch of the matrix's shape.  After this the
 // Jacobi sweeps run with preset_v = true and accumulate their rotations onto V.
 template <typename T, int MP>
-__device__ void rotate_into_basis(EigLds<T, MP>& L, T (*tr)[MP + 1], T (*ti)[MP + 1], int r) {
+__device__ __forceinline__ void rotate_into_basis(EigLds<T, MP>& L, T (*tr)[MP + 1], T (*ti)[MP + 1], int r) {
   for (int j = 0; j < MP; ++j) {  // (K V)[r][j]
     T ar = 0, ai = 0;
     for (int k = 0; k < MP; ++k) {
@@ -312,7 +312,7 @@ __device__ void rotate_into_basis(EigLds<T, MP>& L, T (*tr)[MP + 1], T (*ti)[MP 
 // step squares that error.  Uses L.kr/ki and tr/ti as scratch, so it runs before the matrix
 // is loaded.
 template <typename T, int MP>
-__device__ void reorthonormalize(EigLds<T, MP>& L, T (*tr)[MP + 1], T (*ti)[MP + 1], int r) {
+__device__ __forceinline__ void reorthonormalize(EigLds<T, MP>& L, T (*tr)[MP + 1], T (*ti)[MP + 1], int r) {
   for (int j = 0; j < MP; ++j) {  // E = V^H V, row r
     T ar = 0, ai = 0;
     for (int k = 0; k < MP; ++k) {
@@ -342,9 +342,87 @@ __device__ void reorthonormalize(EigLds<T, MP>& L, T (*tr)[MP + 1], T (*ti)[MP +
   wave_sync();
 }
 
+// Register-row variants of the two warm-start steps above for one MP-lane group: the
+// intermediate rows live in registers and in the matrix arrays, so no scratch matrix is needed.
+template <typename T, int MP>
+__device__ __forceinline__ void rotate_into_basis_r(EigLds<T, MP>& L, int r) {
+  T xr[MP], xi[MP];
+#pragma unroll
+  for (int j = 0; j < MP; ++j) {  // (K V)[r][j]; only row r of K is read by lane r
+    T ar = 0, ai = 0;
+    for (int k = 0; k < MP; ++k) {
+      T kr = L.kr[r][k], ki = L.ki[r][k], vr = L.vr[k][j], vi = L.vi[k][j];
+      ar += kr * vr - ki * vi;
+      ai += kr * vi + ki * vr;
+    }
+    xr[j] = ar;
+    xi[j] = ai;
+  }
+#pragma unroll
+  for (int j = 0; j < MP; ++j) {
+    L.kr[r][j] = xr[j];
+    L.ki[r][j] = xi[j];
+  }
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < MP; ++j) {  // (V^H (K V))[r][j]
+    T ar = 0, ai = 0;
+    for (int k = 0; k < MP; ++k) {
+      T vr = L.vr[k][r], vi = L.vi[k][r], yr = L.kr[k][j], yi = L.ki[k][j];
+      ar += vr * yr + vi * yi;
+      ai += vr * yi - vi * yr;
+    }
+    xr[j] = ar;
+    xi[j] = ai;
+  }
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < MP; ++j) {
+    L.kr[r][j] = xr[j];
+    L.ki[r][j] = xi[j];
+  }
+  wave_sync();
+}
+
+// Newton-Schulz step with E = V^H V held in the (still unused) matrix arrays.
+template <typename T, int MP>
+__device__ __forceinline__ void reorthonormalize_r(EigLds<T, MP>& L, int r) {
+  T xr[MP], xi[MP];
+#pragma unroll
+  for (int j = 0; j < MP; ++j) {  // E = V^H V, row r
+    T ar = 0, ai = 0;
+    for (int k = 0; k < MP; ++k) {
+      T yr = L.vr[k][r], yi = L.vi[k][r], zr = L.vr[k][j], zi = L.vi[k][j];
+      ar += yr * zr + yi * zi;
+      ai += yr * zi - yi * zr;
+    }
+    L.kr[r][j] = ar;
+    L.ki[r][j] = ai;
+  }
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < MP; ++j) {  // row r of 1.5 V - 0.5 V E
+    T ar = 0, ai = 0;
+    for (int k = 0; k < MP; ++k) {
+      T yr = L.vr[r][k], yi = L.vi[r][k], zr = L.kr[k][j], zi = L.ki[k][j];
+      ar += yr * zr - yi * zi;
+      ai += yr * zi + yi * zr;
+    }
+    xr[j] = T(1.5) * L.vr[r][j] - T(0.5) * ar;
+    xi[j] = T(1.5) * L.vi[r][j] - T(0.5) * ai;
+  }
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < MP; ++j) {
+    L.vr[r][j] = xr[j];
+    L.vi[r][j] = xi[j];
+  }
+  wave_sync();
+}
+
 // Block version for MP = 64 and 256 threads.
 template <typename T>
-__device__ void reorthonormalize64(EigLds<T, 64>& L, T (*tr)[65], T (*ti)[65]) {
+__device__ __forceinline__ void reorthonormalize64(EigLds<T, 64>& L, T (*tr)[65], T (*ti)[65]) {
   const int t = threadIdx.x;
   const int bi = (t / 16) * 4, bj = (t % 16) * 4;
   T ar[4][4], ai[4][4];
@@ -415,7 +493,7 @@ __device__ void reorthonormalize64(EigLds<T, 64>& L, T (*tr)[65], T (*ti)[65]) {
 
 // The same for MP = 64 shared by a block of 256 threads (4 x 4 output tile per thread).
 template <typename T>
-__device__ void rotate_into_basis64(EigLds<T, 64>& L, T (*tr)[65], T (*ti)[65]) {
+__device__ __forceinline__ void rotate_into_basis64(EigLds<T, 64>& L, T (*tr)[65], T (*ti)[65]) {
   const int t = threadIdx.x;
   const int bi = (t / 16) * 4, bj = (t % 16) * 4;
   T ar[4][4], ai[4][4];
@@ -479,7 +557,7 @@ __device__ void rotate_into_basis64(EigLds<T, 64>& L, T (*tr)[65], T (*ti)[65]) 
 // After jacobi_herm: eigenvalues sorted descending over the first d indices (padding last).
 // L.src[j] = index of the j-th largest eigenvalue; L.lam[i] = eigenvalue i.
 template <typename T, int MP>
-__device__ void eig_sort_desc(EigLds<T, MP>& L, int r, int d) {
+__device__ __forceinline__ void eig_sort_desc(EigLds<T, MP>& L, int r, int d) {
   L.lam[r] = (r < d) ? L.kr[r][r] : Num<T>::ninf();
   wave_sync();
   const T me = L.lam[r];
@@ -496,7 +574,7 @@ __device__ void eig_sort_desc(EigLds<T, MP>& L, int r, int d) {
 // first d rows (lowest row on ties) becomes real positive.  Returns the multiplier
 // conj(v_k)/|v_k| in every lane of the group.
 template <typename T, int MP>
-__device__ Cx<T> canonical_phase(EigLds<T, MP>& L, int r, int d, int col) {
+__device__ __forceinline__ Cx<T> canonical_phase(EigLds<T, MP>& L, int r, int d, int col) {
   T vr = L.vr[r][col], vi = L.vi[r][col];
   T mag = (r < d) ? vr * vr + vi * vi : T(-1);
   int idx = r;

@@ -275,7 +275,7 @@ __global__ void k_reduce_S2(const DevChan* __restrict__ chans, char* ws) {
 // the per-group partials), the mode-2 Gram, and each group's mode-3 Gram.
 
 template <typename T, int MP>
-__device__ void eig_finish(EigLds<T, MP>& L, int r, int d, int rk, float2* dst, int ld,
+__device__ __forceinline__ void eig_finish(EigLds<T, MP>& L, int r, int d, int rk, float2* dst, int ld,
                            int rpad, double* lamsum, int32_t* status, bool conv) {
   eig_sort_desc<T, MP>(L, r, d);
   double ls = 0.0;
@@ -308,7 +308,7 @@ __device__ void eig_finish(EigLds<T, MP>& L, int r, int d, int rk, float2* dst, 
 // before the sweeps, so only the change since the last call remains to be diagonalised.
 
 template <typename T, int MP>
-__device__ void load_basis(EigLds<T, MP>& L, const float2* V, int r) {
+__device__ __forceinline__ void load_basis(EigLds<T, MP>& L, const float2* V, int r) {
   for (int j = 0; j < MP; ++j) {
     float2 v = V[r * MP + j];
     L.vr[r][j] = (T)v.x;
@@ -317,17 +317,16 @@ __device__ void load_basis(EigLds<T, MP>& L, const float2* V, int r) {
 }
 
 template <typename T, int MP>
-__device__ void store_basis(const EigLds<T, MP>& L, float2* V, int r) {
+__device__ __forceinline__ void store_basis(const EigLds<T, MP>& L, float2* V, int r) {
   for (int j = 0; j < MP; ++j) V[r * MP + j] = make_float2((float)L.vr[r][j], (float)L.vi[r][j]);
 }
 
 // mode-1: one MP-lane group per channel
 template <typename T, int MP>
-__global__ void __launch_bounds__(64) k_eigA(const DevChan* __restrict__ chans, int n_channels,
+__global__ void __launch_bounds__(64, (sizeof(T) == 4 && MP == 16) ? 2 : 1) k_eigA(const DevChan* __restrict__ chans, int n_channels,
                                               char* ws, float2* A, int32_t* status, int warm) {
   constexpr int GPW = 64 / MP;
   __shared__ EigLds<T, MP> lds[GPW];
-  __shared__ T tr[GPW][MP][MP + 1], ti[GPW][MP][MP + 1];
   const int grp = threadIdx.x / MP, r = threadIdx.x % MP;
   const int c = blockIdx.x * GPW + grp;
   EigLds<T, MP>& L = lds[grp];
@@ -344,7 +343,7 @@ __global__ void __launch_bounds__(64) k_eigA(const DevChan* __restrict__ chans, 
         L.vi[r][j] = T(0);
       }
     wave_sync();
-    reorthonormalize<T, MP>(L, tr[grp], ti[grp], r);
+    reorthonormalize_r<T, MP>(L, r);
   }
   for (int j = 0; j < MP; ++j) {
     T sr = 0, si = 0;
@@ -357,7 +356,7 @@ __global__ void __launch_bounds__(64) k_eigA(const DevChan* __restrict__ chans, 
     L.ki[r][j] = si;
   }
   wave_sync();
-  if (use_warm) rotate_into_basis<T, MP>(L, tr[grp], ti[grp], r);
+  if (use_warm) rotate_into_basis_r<T, MP>(L, r);
   wave_sync();
   bool conv = jacobi_herm<T, MP, 1>(L, r, 0, sizeof(T) == 4 ? 12 : 20, use_warm);
   if (valid) {
@@ -420,13 +419,12 @@ __global__ void __launch_bounds__(64 * NW) k_eigB(const DevChan* __restrict__ ch
 
 // mode-3: one MP-lane group per subcarrier group
 template <typename T, int MP>
-__global__ void __launch_bounds__(64) k_eigC(const DevChan* __restrict__ chans,
+__global__ void __launch_bounds__(64, (sizeof(T) == 4 && MP == 16) ? 2 : 1) k_eigC(const DevChan* __restrict__ chans,
                                               const GroupItem* __restrict__ items,
                                               int total_groups, char* ws, float2* C,
                                               int32_t* status, int warm) {
   constexpr int GPW = 64 / MP;
   __shared__ EigLds<T, MP> lds[GPW];
-  __shared__ T tr[GPW][MP][MP + 1], ti[GPW][MP][MP + 1];
   const int grp = threadIdx.x / MP, r = threadIdx.x % MP;
   const int gi = blockIdx.x * GPW + grp;
   EigLds<T, MP>& L = lds[grp];
@@ -448,7 +446,7 @@ __global__ void __launch_bounds__(64) k_eigC(const DevChan* __restrict__ chans,
         L.vi[r][j] = T(0);
       }
     wave_sync();
-    reorthonormalize<T, MP>(L, tr[grp], ti[grp], r);
+    reorthonormalize_r<T, MP>(L, r);
   }
   for (int j = 0; j < MP; ++j) {
     T sr = 0, si = 0;
@@ -461,7 +459,7 @@ __global__ void __launch_bounds__(64) k_eigC(const DevChan* __restrict__ chans,
     L.ki[r][j] = si;
   }
   wave_sync();
-  if (use_warm) rotate_into_basis<T, MP>(L, tr[grp], ti[grp], r);
+  if (use_warm) rotate_into_basis_r<T, MP>(L, r);
   wave_sync();
   bool conv = jacobi_herm<T, MP, 1>(L, r, 0, sizeof(T) == 4 ? 12 : 20, use_warm);
   if (valid) {
