@@ -251,10 +251,13 @@ __global__ void __launch_bounds__(256) k_fused_t_mfma(const DevChan* __restrict_
   const int sz = min(ch.gs, ch.nsc - s0);
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
-  float* Bt = reinterpret_cast<float*>(smem);        // [2 nt][32]
-  float2* As = smem + nt * 32;                        // nr x m
+  // region 0 holds the real-form B ([2 nt][32] floats) for the product and Yh (sz x m x n)
+  // afterwards
+  const int reg0 = max(nt * 32, ch.gs * m * n);
+  float* Bt = reinterpret_cast<float*>(smem);
+  float2* Yh = smem;
+  float2* As = smem + reg0;                           // nr x m
   float2* Ts = As + nr * m;                           // sz x nr x n
-  float2* Yh = Ts + ch.gs * nr * n;                   // sz x m x n
   const int rows = sz * nr;
   const int ntile = (rows + 31) / 32;
   const float* Xf = reinterpret_cast<const float*>(X + ch.x + (int64_t)s0 * nr * nt);
@@ -1314,8 +1317,8 @@ bool fused_fit_ok(const LaunchCtx& L) {
 }
 
 static size_t tm_bytes(const LaunchCtx& L) {
-  return sizeof(float2) * ((size_t)L.max_nt * 32 + (size_t)L.max_nr * L.max_m +
-                           (size_t)L.max_gs * L.max_nr * L.max_n + (size_t)L.max_gs * L.max_m * L.max_n);
+  return sizeof(float2) * (std::max<size_t>((size_t)L.max_nt * 32, (size_t)L.max_gs * L.max_m * L.max_n) +
+                           (size_t)L.max_nr * L.max_m + (size_t)L.max_gs * L.max_nr * L.max_n);
 }
 
 static size_t tlp_bytes(const LaunchCtx& L) {
