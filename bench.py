@@ -172,6 +172,11 @@ def time_forms(api, synthgen, cfg, X, B, s2, ms_fp32, sg_fp32, torch, steps):
     del xs
     plan = api.Plan([api.desc_from_config(gcfg)] * gcfg.n_channels, iters=gcfg.iters)
     gs2 = [float(v) for v in synthgen.snr_to_sigma2(gcfg.snr_db)]
+    fg = plan.empty_factors()
+    ms_fit = timed(lambda: plan.fit(Xg, factors=fg, trace=False), 2)
+    forms["fit_8x128x1632"] = dict(
+        workload="64 x (8 x 128 x 1632), 32 paths, groups of 12, ranks (8, 24, 12), 20 sweeps",
+        fits_per_s=gcfg.n_channels / (ms_fit / 1e3), ms_per_fit_batch=ms_fit)
     r = plan.fit(Xg, trace=False)
     target = 10 * torch.log10(plan.sinr_full(Xg, gs2).clamp_min(1e-30))
     Ct = r["C"].clone().requires_grad_(True)
@@ -193,6 +198,22 @@ def time_forms(api, synthgen, cfg, X, B, s2, ms_fp32, sg_fp32, torch, steps):
         workload="64 x (8 x 128 x 1632), ranks (8, 24, 12), Ns 4, 10 dB, Adam lr 3e-3",
         steps_per_s=1e3 / ms, ms_per_step=ms, loss_first=float(losses[0]),
         loss_last=float(losses[-1]))
+    # the 16 x 256 x 3276 workload (ranks (12, 32, 12)): 8 channels per batch
+    wcfg = synthgen.CONFIGS["wide"]
+    nw = 8
+    xs = []
+    for c in range(nw):
+        pp = synthgen.draw_paths(synthgen.channel_rng(wcfg.seed_index, c), wcfg.n_paths, wcfg.k_db)
+        xs.append(synthgen.build_channel_torch(pp, wcfg.nr, wcfg.nt, wcfg.nsc, dev,
+                                               dtype=torch.complex64).reshape(-1))
+    Xw = torch.cat(xs)
+    del xs
+    planw = api.Plan([api.desc_from_config(wcfg)] * nw, iters=wcfg.iters)
+    fw = planw.empty_factors()
+    ms_w = timed(lambda: planw.fit(Xw, factors=fw, trace=False), 1)
+    forms["fit_16x256x3276"] = dict(
+        workload="8 x (16 x 256 x 3276), 16 paths, groups of 12, ranks (12, 32, 12), 20 sweeps",
+        fits_per_s=nw / (ms_w / 1e3), ms_per_fit_batch=ms_w)
     return forms
 
 

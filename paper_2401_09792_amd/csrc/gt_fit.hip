@@ -517,23 +517,6 @@ __global__ void __launch_bounds__(256) k_W(const DevChan* __restrict__ chans,
   st(wsp(ws, ch.w_W) + o, acc);
 }
 
-// T_s = H_s B  (nr x n)
-__global__ void __launch_bounds__(256) k_T(const DevChan* __restrict__ chans,
-                                           const float2* __restrict__ X,
-                                           const float2* __restrict__ B, char* ws) {
-  CH_BEGIN(blockIdx.y);
-  const int64_t total = (int64_t)ch.nsc * ch.nr * ch.n;
-  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= total) return;
-  const int b = (int)(o % ch.n);
-  const int64_t si = o / ch.n;  // s*nr + i
-  const float2* Hrow = X + ch.x + si * ch.nt;
-  const float2* Bc = B + ch.b;
-  Cx<float> acc{0.f, 0.f};
-  for (int j = 0; j < ch.nt; ++j) cfma(acc, ld(Hrow + j), ld(Bc + (int64_t)j * ch.n + b));
-  st(wsp(ws, ch.w_T) + o, acc);
-}
-
 // Per group: Z_q = sum_s conj(C[s,q]) T_s, S1 partial = sum_q Z_q Z_q^H (one q at a time).
 __global__ void __launch_bounds__(256) k_stepA_group(const DevChan* __restrict__ chans,
                                                      const GroupItem* __restrict__ items,
@@ -566,22 +549,6 @@ __global__ void __launch_bounds__(256) k_stepA_group(const DevChan* __restrict__
     __syncthreads();
   }
   if (o < nr * nr) st(wsp(ws, ch.w_S1p) + (int64_t)it.g * nr * nr + o, acc[0]);
-}
-
-// Yh_s = Y_s B  (m x n)
-__global__ void __launch_bounds__(256) k_Yh(const DevChan* __restrict__ chans,
-                                            const float2* __restrict__ B, char* ws) {
-  CH_BEGIN(blockIdx.y);
-  const int64_t total = (int64_t)ch.nsc * ch.m * ch.n;
-  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= total) return;
-  const int b = (int)(o % ch.n);
-  const int64_t sa = o / ch.n;
-  const float2* Yrow = wsp(ws, ch.w_Y) + sa * ch.nt;
-  const float2* Bc = B + ch.b;
-  Cx<float> acc{0.f, 0.f};
-  for (int j = 0; j < ch.nt; ++j) cfma(acc, ld(Yrow + j), ld(Bc + (int64_t)j * ch.n + b));
-  st(wsp(ws, ch.w_Yh) + o, acc);
 }
 
 // S3_g[s,t] = <Yh_s, Yh_t> for the subcarriers of each group
@@ -738,6 +705,8 @@ static gt_status eig_dispatch(const LaunchCtx& L, int which, float2* A, float2* 
 bool fused_fit_ok(const LaunchCtx& L);
 gt_status launch_convert_x(const LaunchCtx& L, const float2* X);
 gt_status launch_gram_x(const LaunchCtx& L, const float2* X);
+gt_status launch_gram_rows_big(const LaunchCtx& L, const float2* X, int which);
+gt_status launch_rows_times_b(const LaunchCtx& L, const float2* X, const float2* B, int which);
 gt_status launch_eigB_sub(const LaunchCtx& L, float2* B, int32_t* status, int warm);
 gt_status launch_fused_t(const LaunchCtx& L, const float2* X, const float2* A, const float2* B,
                          int do_c);
@@ -751,8 +720,6 @@ gt_status launch_fit(const LaunchCtx& L, const float2* X, float2* A, float2* B, 
   const dim3 b256(256);
   const unsigned gY = cdiv((int64_t)L.max_nsc * L.max_m * L.max_nt, 256);
   const unsigned gW = cdiv((int64_t)L.max_groups * L.max_p * L.max_m * L.max_nt, 256);
-  const unsigned gT = cdiv((int64_t)L.max_nsc * L.max_nr * L.max_n, 256);
-  const unsigned gYh = cdiv((int64_t)L.max_nsc * L.max_m * L.max_n, 256);
   const unsigned gCore = cdiv((int64_t)L.max_groups * L.max_p * L.max_m * L.max_n, 256);
   const int tiles = (L.max_nt + 15) / 16;
   const dim3 gGram(tiles * tiles, L.max_nsplit, nch);
@@ -769,8 +736,7 @@ gt_status launch_fit(const LaunchCtx& L, const float2* X, float2* A, float2* B, 
     if (L.max_nt <= 64) {
       if ((st = launch_gram_x(L, X)) != GT_OK) return st;
     } else {
-      GT_LAUNCH(k_gram_rows, gGram, b256, L.d_chans, X, L.ws, 0);
-      GT_LAUNCH(k_reduce_S2, gRed, b256, L.d_chans, L.ws);
+      if ((st = launch_gram_rows_big(L, X, 0)) != GT_OK) return st;
     }
     if ((st = eig_dispatch(L, 0, A, B, C, status, 0)) != GT_OK) return st;
     if ((st = eig_dispatch(L, 1, A, B, C, status, 0)) != GT_OK) return st;
@@ -780,7 +746,8 @@ gt_status launch_fit(const LaunchCtx& L, const float2* X, float2* A, float2* B, 
   const bool fused = fused_fit_ok(L);
   if (trace || !fused) {
     GT_LAUNCH(k_Y, dim3(gY, nch), b256, L.d_chans, X, A, L.ws);
-    GT_LAUNCH(k_Yh, dim3(gYh, nch), b256, L.d_chans, B, L.ws);
+    gt_status st;
+    if ((st = launch_rows_times_b(L, X, B, 1)) != GT_OK) return st;
   }
   if (trace) {
     GT_LAUNCH(k_S3, dim3(L.total_groups), b256, L.d_chans, L.d_groups, L.ws);
@@ -823,7 +790,7 @@ gt_status launch_fit(const LaunchCtx& L, const float2* X, float2* A, float2* B, 
   for (int it = 0; it < iters; ++it) {
     gt_status st;
     // A-step (uses B, C of the previous sweep)
-    GT_LAUNCH(k_T, dim3(gT, nch), b256, L.d_chans, X, B, L.ws);
+    if ((st = launch_rows_times_b(L, X, B, 0)) != GT_OK) return st;
     GT_LAUNCH(k_stepA_group, dim3(L.total_groups), b256, L.d_chans, L.d_groups, C, L.ws);
     if ((st = eig_dispatch(L, 0, A, B, C, status, (warm && it == 0) ? 0 : 1)) != GT_OK) return st;
     if (trace)
@@ -832,14 +799,18 @@ gt_status launch_fit(const LaunchCtx& L, const float2* X, float2* A, float2* B, 
     // B-step (new A, C of the previous sweep)
     GT_LAUNCH(k_Y, dim3(gY, nch), b256, L.d_chans, X, A, L.ws);
     GT_LAUNCH(k_W, dim3(gW, nch), b256, L.d_chans, C, L.ws);
-    GT_LAUNCH(k_gram_rows, gGram, b256, L.d_chans, X, L.ws, 1);
-    GT_LAUNCH(k_reduce_S2, gRed, b256, L.d_chans, L.ws);
+    if (L.max_nt > 64) {
+      if ((st = launch_gram_rows_big(L, X, 1)) != GT_OK) return st;
+    } else {
+      GT_LAUNCH(k_gram_rows, gGram, b256, L.d_chans, X, L.ws, 1);
+      GT_LAUNCH(k_reduce_S2, gRed, b256, L.d_chans, L.ws);
+    }
     if ((st = eig_dispatch(L, 1, A, B, C, status, (warm && it == 0) ? 0 : 1)) != GT_OK) return st;
     if (trace)
       GT_LAUNCH(k_trace, dim3(cdiv(nch, 64)), dim3(64), L.d_chans, nch, L.ws, trace, stride,
                 2 + 3 * it, 1);
     // C-step (new A, B)
-    GT_LAUNCH(k_Yh, dim3(gYh, nch), b256, L.d_chans, B, L.ws);
+    if ((st = launch_rows_times_b(L, X, B, 1)) != GT_OK) return st;
     GT_LAUNCH(k_S3, dim3(L.total_groups), b256, L.d_chans, L.d_groups, L.ws);
     if ((st = eig_dispatch(L, 2, A, B, C, status, (warm && it == 0) ? 0 : 1)) != GT_OK) return st;
     if (trace)

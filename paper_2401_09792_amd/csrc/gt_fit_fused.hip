@@ -1262,6 +1262,190 @@ __global__ void __launch_bounds__(512) k_gram_x_mfma(const DevChan* __restrict__
   }
 }
 
+// Mode-2 Gram of long row stacks for any nt <= 256: rows of X (which = 0: (s, i) rows of the
+// channel tensor) or of W (which = 1: (g, q, a) rows from the B-step), each a contiguous row of
+// nt complex values.  With R = [Re rows | Im rows] (real column c < nt: Re of column c, else
+// Im of column c - nt), R^T R is accumulated on its upper 32 x 32 tiles (T = ceil(2 nt / 32)
+// tile rows, T (T + 1) / 2 tiles), eight tiles per 256-thread block (two per wave), one block
+// per (tile octet, row split, channel); operands straight from the rows in memory.
+__device__ __forceinline__ void upper_tile(int k, int T, int& I, int& J) {
+  I = 0;
+  while (k >= T - I) {
+    k -= T - I;
+    ++I;
+  }
+  J = I + k;
+}
+
+__global__ void __launch_bounds__(256) k_gram_rows_mfma(const DevChan* __restrict__ chans,
+                                                        const float2* __restrict__ X, char* ws,
+                                                        int which, int noct_max) {
+  const DevChan& ch = chans[blockIdx.y];
+  const int nt = ch.nt;
+  const int T = (2 * nt + 31) / 32, npairs = T * (T + 1) / 2, noct = (npairs + 7) / 8;
+  const int oct = blockIdx.x % noct_max, split = blockIdx.x / noct_max;
+  if (oct >= noct || split >= ch.nsplit) return;
+  const float* M;
+  int64_t nrows;
+  if (which == 0) {
+    M = reinterpret_cast<const float*>(X + ch.x);
+    nrows = (int64_t)ch.nsc * ch.nr;
+  } else {
+    M = reinterpret_cast<const float*>(ws + ch.w_W);
+    nrows = (int64_t)ch.ngroups * ch.p * ch.m;
+  }
+  const int64_t r0 = split * nrows / ch.nsplit, r1 = (split + 1) * nrows / ch.nsplit;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, h = lane / 32, col = lane % 32;
+  int tI[2], tJ[2], oa[2], ob[2];
+  bool ok[2], va[2], vb[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int k = 8 * oct + 2 * wave + t;
+    ok[t] = k < npairs;
+    upper_tile(ok[t] ? k : 0, T, tI[t], tJ[t]);
+    const int ca = 32 * tI[t] + col, cb = 32 * tJ[t] + col;
+    va[t] = ca < 2 * nt;
+    vb[t] = cb < 2 * nt;
+    const int ja = ca < nt ? ca : ca - nt, jb = cb < nt ? cb : cb - nt;
+    oa[t] = 2 * min(max(ja, 0), nt - 1) + (ca >= nt ? 1 : 0);
+    ob[t] = 2 * min(max(jb, 0), nt - 1) + (cb >= nt ? 1 : 0);
+  }
+  f32x16 acc[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
+  if (ok[0] || ok[1]) {
+    for (int64_t k0 = r0; k0 < r1; k0 += 16) {
+      float a0[8], b0[8], a1[8], b1[8];
+#pragma unroll
+      for (int d = 0; d < 8; ++d) {
+        const int64_t row = k0 + 2 * d + h;
+        const bool rv = row < r1;
+        const float* rp = M + min(row, r1 - 1) * 2 * nt;
+        const float x0 = rp[oa[0]], y0 = rp[ob[0]], x1 = rp[oa[1]], y1 = rp[ob[1]];
+        a0[d] = (rv && va[0]) ? x0 : 0.f;
+        b0[d] = (rv && vb[0]) ? y0 : 0.f;
+        a1[d] = (rv && va[1]) ? x1 : 0.f;
+        b1[d] = (rv && vb[1]) ? y1 : 0.f;
+      }
+#pragma unroll
+      for (int d = 0; d < 8; ++d) {
+        acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[d], b0[d], acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[d], b1[d], acc[1], 0, 0, 0);
+      }
+    }
+  }
+  const int W = 32 * T;
+  float* P = reinterpret_cast<float*>(ws + ch.w_S2p) + (int64_t)split * W * W;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    if (ok[t])
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 32 * tI[t] + 8 * (r / 4) + 4 * h + (r % 4);
+        P[(int64_t)row * W + 32 * tJ[t] + col] = acc[t][r];
+      }
+  }
+}
+
+// S2 (nt x nt complex) = sum over splits of the blocks of the real Gram in the layout above:
+// Re S2 = R_re^T R_re + R_im^T R_im, Im S2 = R_re^T R_im - R_im^T R_re (lower tiles by symmetry).
+__global__ void k_reduce_S2_big(const DevChan* __restrict__ chans, char* ws) {
+  const DevChan& ch = chans[blockIdx.y];
+  const int nt = ch.nt;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nt * nt) return;
+  const int j = e / nt, k = e % nt;
+  const int W = 32 * ((2 * nt + 31) / 32);
+  const float* P = reinterpret_cast<const float*>(ws + ch.w_S2p);
+  auto at = [&](const float* Q, int a, int b) {
+    return ((a >> 5) <= (b >> 5)) ? Q[(int64_t)a * W + b] : Q[(int64_t)b * W + a];
+  };
+  float re = 0.f, im = 0.f;
+  for (int sp = 0; sp < ch.nsplit; ++sp) {
+    const float* Q = P + (int64_t)sp * W * W;
+    re += at(Q, j, k) + at(Q, nt + j, nt + k);
+    im += at(Q, j, nt + k) - at(Q, nt + j, k);
+  }
+  reinterpret_cast<float2*>(ws + ch.w_S2)[e] = make_float2(re, im);
+}
+
+// Row products for wide arrays: out[row] = in[row] B for the rows of X (which = 0: T_s = H_s B,
+// rows (s, i)) or of Y (which = 1: Yh_s = Y_s B, rows (s, a)), each row nt complex, B nt x n.
+// Real form as in the T pass, K index k' = 2 j + part of the interleaved input row; one 32-wide
+// tile of the 2 n real output columns ([Re | Im]) per block with its real-form B slice in LDS
+// ([2 nt][32] floats, k'-major); each wave takes 32-row tiles.  With nt % 8 == 0 and 16-byte
+// aligned rows, step 4 u + v takes k' = 8 u + 4 half + v in lane half (16 contiguous bytes per
+// lane per four steps); otherwise step t takes k' = 2 t + half.
+__global__ void __launch_bounds__(256) k_rows_times_b(const DevChan* __restrict__ chans,
+                                                      const float2* __restrict__ X,
+                                                      const float2* __restrict__ B, char* ws,
+                                                      int which, int tiles_per_block) {
+  extern __shared__ float bts[];  // [2 nt][32]
+  const DevChan& ch = chans[blockIdx.z];
+  const int nt = ch.nt, n = ch.n;
+  const int ctile = blockIdx.y;
+  if (32 * ctile >= 2 * n) return;
+  const int64_t nrows = which == 0 ? (int64_t)ch.nsc * ch.nr : (int64_t)ch.nsc * ch.m;
+  const int64_t rtiles = (nrows + 31) / 32;
+  const int64_t t0 = (int64_t)blockIdx.x * tiles_per_block;
+  if (t0 >= rtiles) return;
+  const float* in = which == 0 ? reinterpret_cast<const float*>(X + ch.x)
+                               : reinterpret_cast<const float*>(ws + ch.w_Y);
+  float2* out = reinterpret_cast<float2*>(ws + (which == 0 ? ch.w_T : ch.w_Yh));
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, half = lane / 32, col = lane % 32;
+  for (int e = tid; e < 2 * nt * 32; e += 256) {
+    const int kk = e / 32, c = 32 * ctile + e % 32, j = kk / 2, part = kk % 2;
+    float v = 0.f;
+    if (c < 2 * n) {
+      const float2 b = B[ch.b + (int64_t)j * n + (c < n ? c : c - n)];
+      v = (part == 0) ? (c < n ? b.x : b.y) : (c < n ? -b.y : b.x);
+    }
+    bts[e] = v;
+  }
+  __syncthreads();
+  const int oc = 32 * ctile + col;  // real output column of this lane
+  const bool ocv = oc < 2 * n;
+  const int ob = oc < n ? oc : oc - n, opart = oc < n ? 0 : 1;
+  const bool vec8 = (nt % 8) == 0 && ((reinterpret_cast<uintptr_t>(in) & 15) == 0);
+  const int64_t tend = min(rtiles, t0 + tiles_per_block);
+  for (int64_t rt = t0 + wave; rt < tend; rt += 4) {
+    const int64_t row = min(rt * 32 + col, nrows - 1);
+    const float* xr = in + row * 2 * nt;
+    f32x16 acc, accb;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = accb[r] = 0.f;
+    if (vec8) {
+      const float4* xr4 = reinterpret_cast<const float4*>(xr);
+      const float* bcol = bts + 4 * half * 32 + col;
+      for (int w = 0; w < nt / 4; w += 2) {
+        const float4 x0 = xr4[2 * w + half], x1 = xr4[2 * (w + 1) + half];
+        const float* bw = bcol + 8 * w * 32;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.x, bw[0], acc, 0, 0, 0);
+        accb = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.x, bw[256], accb, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.y, bw[32], acc, 0, 0, 0);
+        accb = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.y, bw[288], accb, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.z, bw[64], acc, 0, 0, 0);
+        accb = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.z, bw[320], accb, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.w, bw[96], acc, 0, 0, 0);
+        accb = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.w, bw[352], accb, 0, 0, 0);
+      }
+    } else {
+      for (int t = 0; t < nt; ++t)
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(xr[2 * t + half], bts[(2 * t + half) * 32 + col],
+                                                   acc, 0, 0, 0);
+    }
+    if (ocv)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t orow = rt * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+        if (orow < nrows)
+          reinterpret_cast<float*>(out + orow * n + ob)[opart] = acc[r] + accb[r];
+      }
+  }
+}
+
 // S2 = sum over splits of the complex Gram assembled from the real blocks of R^T R
 // (upper 32 x 32 tiles stored; lower entries by symmetry).
 __global__ void k_reduce_S2_mfma(const DevChan* __restrict__ chans, char* ws) {
@@ -1335,6 +1519,27 @@ static int bmm_variant(const LaunchCtx& L);
 bool fused_lowp_ok(const LaunchCtx& L) {
   return fused_fit_ok(L) && bmm_variant(L) != 0 && L.max_gs * L.max_nr <= 128 &&
          tlp_bytes(L) <= 64 * 1024;
+}
+
+// T = H B (which = 0) or Yh = Y B (which = 1) over all rows, for plans with some nt > 64.
+gt_status launch_rows_times_b(const LaunchCtx& L, const float2* X, const float2* B, int which) {
+  const int64_t rows = (int64_t)L.max_nsc * (which == 0 ? L.max_nr : L.max_m);
+  const int64_t rtiles = (rows + 31) / 32;
+  const int tpb = 16;
+  const dim3 grid((unsigned)((rtiles + tpb - 1) / tpb), (2 * L.max_n + 31) / 32, L.n_channels);
+  GT_LAUNCH_SH(k_rows_times_b, grid, dim3(256), sizeof(float) * 2 * L.max_nt * 32, L.d_chans, X, B,
+               L.ws, which, tpb);
+  return GT_OK;
+}
+
+// Mode-2 Gram of X rows (which = 0) or W rows (which = 1) for plans with some nt > 64.
+gt_status launch_gram_rows_big(const LaunchCtx& L, const float2* X, int which) {
+  const int T = (2 * L.max_nt + 31) / 32, noct = (T * (T + 1) / 2 + 7) / 8;
+  GT_LAUNCH_SH(k_gram_rows_mfma, dim3(noct * L.max_nsplit, L.n_channels), dim3(256), 0, L.d_chans, X,
+               L.ws, which, noct);
+  GT_LAUNCH_SH(k_reduce_S2_big, dim3((L.max_nt * L.max_nt + 255) / 256, L.n_channels), dim3(256), 0,
+               L.d_chans, L.ws);
+  return GT_OK;
 }
 
 gt_status launch_gram_x(const LaunchCtx& L, const float2* X) {
