@@ -475,48 +475,6 @@ __global__ void __launch_bounds__(64, (sizeof(T) == 4 && MP == 16) ? 2 : 1) k_ei
 // ---------------------------------------------------------------------------------------
 // Mode-n products of the sweep.
 
-// Y_s = A^H H_s  (m x nt), all subcarriers of a channel.
-__global__ void __launch_bounds__(256) k_Y(const DevChan* __restrict__ chans,
-                                           const float2* __restrict__ X,
-                                           const float2* __restrict__ A, char* ws) {
-  CH_BEGIN(blockIdx.y);
-  const int64_t total = (int64_t)ch.nsc * ch.m * ch.nt;
-  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= total) return;
-  const int j = (int)(o % ch.nt);
-  const int a = (int)((o / ch.nt) % ch.m);
-  const int64_t s = o / ((int64_t)ch.nt * ch.m);
-  const float2* Hs = X + ch.x + s * ch.nr * ch.nt;
-  const float2* Ac = A + ch.a;
-  Cx<float> acc{0.f, 0.f};
-  for (int i = 0; i < ch.nr; ++i) cfmac(acc, ld(Ac + i * ch.m + a), ld(Hs + (int64_t)i * ch.nt + j));
-  st(wsp(ws, ch.w_Y) + o, acc);
-}
-
-// W[g][q] = sum_{s in g} conj(C[s,q]) Y_s  (m x nt); zero for q >= p_g.
-__global__ void __launch_bounds__(256) k_W(const DevChan* __restrict__ chans,
-                                           const float2* __restrict__ C, char* ws) {
-  CH_BEGIN(blockIdx.y);
-  const int64_t per_g = (int64_t)ch.p * ch.m * ch.nt;
-  const int64_t total = per_g * ch.ngroups;
-  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= total) return;
-  const int g = (int)(o / per_g);
-  const int64_t rem = o % per_g;
-  const int q = (int)(rem / ((int64_t)ch.m * ch.nt));
-  const int64_t aj = rem % ((int64_t)ch.m * ch.nt);
-  const int s0 = g * ch.gs;
-  const int sz = min(ch.gs, ch.nsc - s0);
-  Cx<float> acc{0.f, 0.f};
-  if (q < min(ch.p, sz)) {
-    const float2* Y = wsp(ws, ch.w_Y);
-    for (int i = 0; i < sz; ++i)
-      cfmac(acc, ld(C + ch.c + (int64_t)(s0 + i) * ch.p + q),
-            ld(Y + (int64_t)(s0 + i) * ch.m * ch.nt + aj));
-  }
-  st(wsp(ws, ch.w_W) + o, acc);
-}
-
 // Per group: Z_q = sum_s conj(C[s,q]) T_s, S1 partial = sum_q Z_q Z_q^H (one q at a time).
 __global__ void __launch_bounds__(256) k_stepA_group(const DevChan* __restrict__ chans,
                                                      const GroupItem* __restrict__ items,
@@ -706,7 +664,9 @@ bool fused_fit_ok(const LaunchCtx& L);
 gt_status launch_convert_x(const LaunchCtx& L, const float2* X);
 gt_status launch_gram_x(const LaunchCtx& L, const float2* X);
 gt_status launch_gram_rows_big(const LaunchCtx& L, const float2* X, int which);
-gt_status launch_rows_times_b(const LaunchCtx& L, const float2* X, const float2* B, int which);
+gt_status launch_rows_times_b(const LaunchCtx& L, const float2* X, const float2* B);
+gt_status launch_w_rows(const LaunchCtx& L, const float2* X, const float2* A, const float2* C);
+gt_status launch_yh_from_t(const LaunchCtx& L, const float2* A);
 gt_status launch_eigB_sub(const LaunchCtx& L, float2* B, int32_t* status, int warm);
 gt_status launch_fused_t(const LaunchCtx& L, const float2* X, const float2* A, const float2* B,
                          int do_c);
@@ -718,8 +678,6 @@ gt_status launch_fit(const LaunchCtx& L, const float2* X, float2* A, float2* B, 
   const int nch = L.n_channels;
   const int stride = 1 + 3 * iters;
   const dim3 b256(256);
-  const unsigned gY = cdiv((int64_t)L.max_nsc * L.max_m * L.max_nt, 256);
-  const unsigned gW = cdiv((int64_t)L.max_groups * L.max_p * L.max_m * L.max_nt, 256);
   const unsigned gCore = cdiv((int64_t)L.max_groups * L.max_p * L.max_m * L.max_n, 256);
   const int tiles = (L.max_nt + 15) / 16;
   const dim3 gGram(tiles * tiles, L.max_nsplit, nch);
@@ -745,9 +703,10 @@ gt_status launch_fit(const LaunchCtx& L, const float2* X, float2* A, float2* B, 
   // objective of the starting factors (the generic path also needs Yh for the cores)
   const bool fused = fused_fit_ok(L);
   if (trace || !fused) {
-    GT_LAUNCH(k_Y, dim3(gY, nch), b256, L.d_chans, X, A, L.ws);
+    // T = H B (kept for the first A-step of the generic path), Yh = A^H T
     gt_status st;
-    if ((st = launch_rows_times_b(L, X, B, 1)) != GT_OK) return st;
+    if ((st = launch_rows_times_b(L, X, B)) != GT_OK) return st;
+    if ((st = launch_yh_from_t(L, A)) != GT_OK) return st;
   }
   if (trace) {
     GT_LAUNCH(k_S3, dim3(L.total_groups), b256, L.d_chans, L.d_groups, L.ws);
@@ -787,18 +746,18 @@ gt_status launch_fit(const LaunchCtx& L, const float2* X, float2* A, float2* B, 
     }
     return GT_OK;
   }
+  // per sweep: [Z + S1] from T = H B of the previous C-step, eigA, [W rows, Gram], eigB,
+  // [T = H B, Yh = A^H T, S3], eigC
   for (int it = 0; it < iters; ++it) {
     gt_status st;
-    // A-step (uses B, C of the previous sweep)
-    if ((st = launch_rows_times_b(L, X, B, 0)) != GT_OK) return st;
+    // A-step (B, C of the previous sweep)
     GT_LAUNCH(k_stepA_group, dim3(L.total_groups), b256, L.d_chans, L.d_groups, C, L.ws);
     if ((st = eig_dispatch(L, 0, A, B, C, status, (warm && it == 0) ? 0 : 1)) != GT_OK) return st;
     if (trace)
       GT_LAUNCH(k_trace, dim3(cdiv(nch, 64)), dim3(64), L.d_chans, nch, L.ws, trace, stride,
                 1 + 3 * it, 0);
     // B-step (new A, C of the previous sweep)
-    GT_LAUNCH(k_Y, dim3(gY, nch), b256, L.d_chans, X, A, L.ws);
-    GT_LAUNCH(k_W, dim3(gW, nch), b256, L.d_chans, C, L.ws);
+    if ((st = launch_w_rows(L, X, A, C)) != GT_OK) return st;
     if (L.max_nt > 64) {
       if ((st = launch_gram_rows_big(L, X, 1)) != GT_OK) return st;
     } else {
@@ -809,8 +768,9 @@ gt_status launch_fit(const LaunchCtx& L, const float2* X, float2* A, float2* B, 
     if (trace)
       GT_LAUNCH(k_trace, dim3(cdiv(nch, 64)), dim3(64), L.d_chans, nch, L.ws, trace, stride,
                 2 + 3 * it, 1);
-    // C-step (new A, B)
-    if ((st = launch_rows_times_b(L, X, B, 1)) != GT_OK) return st;
+    // C-step (new A, B); T = H B also serves the next sweep's A-step
+    if ((st = launch_rows_times_b(L, X, B)) != GT_OK) return st;
+    if ((st = launch_yh_from_t(L, A)) != GT_OK) return st;
     GT_LAUNCH(k_S3, dim3(L.total_groups), b256, L.d_chans, L.d_groups, L.ws);
     if ((st = eig_dispatch(L, 2, A, B, C, status, (warm && it == 0) ? 0 : 1)) != GT_OK) return st;
     if (trace)

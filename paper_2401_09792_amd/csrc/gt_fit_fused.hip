@@ -1371,29 +1371,27 @@ __global__ void k_reduce_S2_big(const DevChan* __restrict__ chans, char* ws) {
   reinterpret_cast<float2*>(ws + ch.w_S2)[e] = make_float2(re, im);
 }
 
-// Row products for wide arrays: out[row] = in[row] B for the rows of X (which = 0: T_s = H_s B,
-// rows (s, i)) or of Y (which = 1: Yh_s = Y_s B, rows (s, a)), each row nt complex, B nt x n.
-// Real form as in the T pass, K index k' = 2 j + part of the interleaved input row; one 32-wide
-// tile of the 2 n real output columns ([Re | Im]) per block with its real-form B slice in LDS
-// ([2 nt][32] floats, k'-major); each wave takes 32-row tiles.  With nt % 8 == 0 and 16-byte
-// aligned rows, step 4 u + v takes k' = 8 u + 4 half + v in lane half (16 contiguous bytes per
-// lane per four steps); otherwise step t takes k' = 2 t + half.
+// T_s = H_s B (nr x n) for all subcarriers, as a product over the rows (s, i) of X, each row
+// nt complex.  Real form as in the T pass, K index k' = 2 j + part of the interleaved row; one
+// 32-wide tile of the 2 n real output columns ([Re | Im]) per block with its real-form B slice
+// in LDS ([2 nt][32] floats, k'-major); each wave takes 32-row tiles.  With nt % 8 == 0 and
+// 16-byte aligned rows, step 4 u + v takes k' = 8 u + 4 half + v in lane half (16 contiguous
+// bytes per lane per four steps); otherwise step t takes k' = 2 t + half.
 __global__ void __launch_bounds__(256) k_rows_times_b(const DevChan* __restrict__ chans,
                                                       const float2* __restrict__ X,
                                                       const float2* __restrict__ B, char* ws,
-                                                      int which, int tiles_per_block) {
+                                                      int tiles_per_block) {
   extern __shared__ float bts[];  // [2 nt][32]
   const DevChan& ch = chans[blockIdx.z];
   const int nt = ch.nt, n = ch.n;
   const int ctile = blockIdx.y;
   if (32 * ctile >= 2 * n) return;
-  const int64_t nrows = which == 0 ? (int64_t)ch.nsc * ch.nr : (int64_t)ch.nsc * ch.m;
+  const int64_t nrows = (int64_t)ch.nsc * ch.nr;
   const int64_t rtiles = (nrows + 31) / 32;
   const int64_t t0 = (int64_t)blockIdx.x * tiles_per_block;
   if (t0 >= rtiles) return;
-  const float* in = which == 0 ? reinterpret_cast<const float*>(X + ch.x)
-                               : reinterpret_cast<const float*>(ws + ch.w_Y);
-  float2* out = reinterpret_cast<float2*>(ws + (which == 0 ? ch.w_T : ch.w_Yh));
+  const float* in = reinterpret_cast<const float*>(X + ch.x);
+  float2* out = reinterpret_cast<float2*>(ws + ch.w_T);
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, half = lane / 32, col = lane % 32;
   for (int e = tid; e < 2 * nt * 32; e += 256) {
     const int kk = e / 32, c = 32 * ctile + e % 32, j = kk / 2, part = kk % 2;
@@ -1444,6 +1442,131 @@ __global__ void __launch_bounds__(256) k_rows_times_b(const DevChan* __restrict_
           reinterpret_cast<float*>(out + orow * n + ob)[opart] = acc[r] + accb[r];
       }
   }
+}
+
+// B-step rows for wide arrays: W_q = A^H (sum_s conj(C[s,q]) H_s) for one group and a chunk of
+// 32 transmit columns per block, written to the workspace as rows (g, q, a) of nt complex for
+// the mode-2 Gram.  Step 1 contracts the subcarriers first, Hc_q = sum_s conj(C[s,q]) H_s,
+// for up to 16 q at a time (one 32-row real tile (q, re/im) x K (s, re/im) x 32 columns j
+// per antenna i), into LDS as separate re and im planes [q][i][32]; step 2 takes per q the
+// product with A^H (rows (a, re/im), K (i, re/im)).  Rows q >= p_g of a short group come out
+// zero through zero coefficients.
+template <int SMAX>
+__global__ void __launch_bounds__(256) k_w_rows(const DevChan* __restrict__ chans,
+                                                const float2* __restrict__ X,
+                                                const float2* __restrict__ A,
+                                                const float2* __restrict__ C, char* ws,
+                                                int nchunk_max, int qcap) {
+  extern __shared__ float hcs[];  // [2][qcap][nr][32]
+  const DevChan& ch = chans[blockIdx.y];
+  const int g = blockIdx.x / nchunk_max, jc = blockIdx.x % nchunk_max;
+  const int nr = ch.nr, nt = ch.nt, m = ch.m, p = ch.p;
+  if (g >= ch.ngroups || 32 * jc >= nt) return;
+  const int s0 = g * ch.gs, sz = min(ch.gs, ch.nsc - s0), pg = min(p, sz);
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, h = lane / 32, col = lane % 32;
+  const int j = 32 * jc + col;
+  const bool jv = j < nt;
+  const int jcl = min(j, nt - 1);
+  const int plane = qcap * nr * 32;
+  const int rq = col >> 1, po = col & 1;  // MFMA row of this lane: (q or a, re/im)
+  // step-2 A operand for K step i: po 0: (Re, Im)[h] of A[i][a], po 1: (-Im, Re)[h]
+  float aco[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const float2 av = A[ch.a + min(i, nr - 1) * m + min(rq, m - 1)];
+    const float v = po == 0 ? (h == 0 ? av.x : av.y) : (h == 0 ? -av.y : av.x);
+    aco[i] = (i < nr && rq < m) ? v : 0.f;
+  }
+  const float* xg = reinterpret_cast<const float*>(X + ch.x + (int64_t)s0 * nr * nt) + h;
+  float2* Wg = reinterpret_cast<float2*>(ws + ch.w_W) + (int64_t)g * p * m * nt;
+  const float csign = (po == 1 && h == 0) ? -1.f : 1.f;
+  for (int q0 = 0; q0 < p; q0 += qcap) {
+    const int q = q0 + rq;
+    const bool qv = q < pg && rq < qcap;
+    const float* cg = reinterpret_cast<const float*>(C + ch.c + (int64_t)s0 * p + min(q, p - 1)) + (po ^ h);
+    float cp[SMAX];
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {
+      const float c = cg[2 * (int64_t)min(s, sz - 1) * p];
+      cp[s] = (qv && s < sz) ? csign * c : 0.f;
+    }
+    if (q0 > 0) __syncthreads();  // the previous q tile's step 2 has read the planes
+    // 1. NI antenna tiles i0 + 4 k per pass, all loads issued before the products
+    constexpr int NI = SMAX <= 12 ? 2 : 1;
+    for (int i0 = wave; i0 < nr; i0 += 4 * NI) {
+      float xa[NI][SMAX];
+#pragma unroll
+      for (int k = 0; k < NI; ++k) {
+        const int ic = min(i0 + 4 * k, nr - 1);
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) {
+          const int64_t sc = min(s, sz - 1);
+          xa[k][s] = xg[2 * ((sc * nr + ic) * nt + jcl)];
+        }
+      }
+      f32x16 acc[NI];
+#pragma unroll
+      for (int k = 0; k < NI; ++k)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[k][r] = 0.f;
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s)
+        if (s < sz)
+#pragma unroll
+          for (int k = 0; k < NI; ++k)
+            acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(cp[s], xa[k][s], acc[k], 0, 0, 0);
+      // accumulator (lane, r): row 8 (r / 4) + 4 h + r % 4 = (q - q0, re/im), column j
+#pragma unroll
+      for (int k = 0; k < NI; ++k)
+        if (i0 + 4 * k < nr)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int row = 8 * (r / 4) + 4 * h + (r % 4), ql = row >> 1;
+            if (ql < qcap) hcs[(row & 1) * plane + (ql * nr + i0 + 4 * k) * 32 + col] = acc[k][r];
+          }
+    }
+    __syncthreads();
+    // 2. W_q = A^H Hc_q: rows (a, re/im), K = (i, re/im) with the lane half choosing the plane
+    for (int ql = wave; ql < min(qcap, p - q0); ql += 4) {
+      const float* hq = hcs + h * plane + ql * nr * 32 + col;
+      f32x16 acc;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (i < nr) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(aco[i], hq[i * 32], acc, 0, 0, 0);
+      float2* wq = Wg + (int64_t)(q0 + ql) * m * nt + j;
+      if (jv)
+#pragma unroll
+        for (int r = 0; r < 16; r += 2) {
+          const int a = (8 * (r / 4) + 4 * h + (r % 4)) >> 1;
+          if (a < m) wq[(int64_t)a * nt] = make_float2(acc[r], acc[r + 1]);
+        }
+    }
+  }
+}
+
+// Yh_s = A^H T_s (m x n) from T = H B, one output per thread.
+__global__ void __launch_bounds__(256) k_yh_from_t(const DevChan* __restrict__ chans,
+                                                   const float2* __restrict__ A, char* ws) {
+  const DevChan& ch = chans[blockIdx.y];
+  const int nr = ch.nr, m = ch.m, n = ch.n;
+  const int64_t total = (int64_t)ch.nsc * m * n;
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= total) return;
+  const int b = (int)(o % n);
+  const int64_t sa = o / n;
+  const int a = (int)(sa % m);
+  const int64_t s = sa / m;
+  const float2* T = reinterpret_cast<const float2*>(ws + ch.w_T) + s * nr * n + b;
+  const float2* Ac = A + ch.a + a;
+  float re = 0.f, im = 0.f;
+  for (int i = 0; i < nr; ++i) {
+    const float2 x = Ac[i * m], t = T[(int64_t)i * n];
+    re += x.x * t.x + x.y * t.y;
+    im += x.x * t.y - x.y * t.x;
+  }
+  reinterpret_cast<float2*>(ws + ch.w_Yh)[o] = make_float2(re, im);
 }
 
 // S2 = sum over splits of the complex Gram assembled from the real blocks of R^T R
@@ -1521,14 +1644,35 @@ bool fused_lowp_ok(const LaunchCtx& L) {
          tlp_bytes(L) <= 64 * 1024;
 }
 
-// T = H B (which = 0) or Yh = Y B (which = 1) over all rows, for plans with some nt > 64.
-gt_status launch_rows_times_b(const LaunchCtx& L, const float2* X, const float2* B, int which) {
-  const int64_t rows = (int64_t)L.max_nsc * (which == 0 ? L.max_nr : L.max_m);
-  const int64_t rtiles = (rows + 31) / 32;
+// T = H B over all rows of X (generic path).
+gt_status launch_rows_times_b(const LaunchCtx& L, const float2* X, const float2* B) {
+  const int64_t rtiles = ((int64_t)L.max_nsc * L.max_nr + 31) / 32;
   const int tpb = 16;
   const dim3 grid((unsigned)((rtiles + tpb - 1) / tpb), (2 * L.max_n + 31) / 32, L.n_channels);
   GT_LAUNCH_SH(k_rows_times_b, grid, dim3(256), sizeof(float) * 2 * L.max_nt * 32, L.d_chans, X, B,
-               L.ws, which, tpb);
+               L.ws, tpb);
+  return GT_OK;
+}
+
+// W rows of the B-step for plans with some nt > 64.
+gt_status launch_w_rows(const LaunchCtx& L, const float2* X, const float2* A, const float2* C) {
+  const int nchunk = (L.max_nt + 31) / 32;
+  const int qcap = std::min(16, L.max_p);
+  const dim3 grid((unsigned)(L.max_groups * nchunk), L.n_channels);
+  const size_t sh = sizeof(float) * 2 * qcap * L.max_nr * 32;
+  if (L.max_gs <= 12)
+    GT_LAUNCH_SH((k_w_rows<12>), grid, dim3(256), sh, L.d_chans, X, A, C, L.ws, nchunk, qcap);
+  else if (L.max_gs <= 24)
+    GT_LAUNCH_SH((k_w_rows<24>), grid, dim3(256), sh, L.d_chans, X, A, C, L.ws, nchunk, qcap);
+  else
+    GT_LAUNCH_SH((k_w_rows<32>), grid, dim3(256), sh, L.d_chans, X, A, C, L.ws, nchunk, qcap);
+  return GT_OK;
+}
+
+gt_status launch_yh_from_t(const LaunchCtx& L, const float2* A) {
+  const int64_t total = (int64_t)L.max_nsc * L.max_m * L.max_n;
+  GT_LAUNCH_SH(k_yh_from_t, dim3((unsigned)((total + 255) / 256), L.n_channels), dim3(256), 0,
+               L.d_chans, A, L.ws);
   return GT_OK;
 }
 

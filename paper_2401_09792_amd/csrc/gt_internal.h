@@ -21,8 +21,7 @@ struct DevChan {
   int32_t gfirst, pad0;            // index of the channel's first group in the group table
   int64_t x, a, b, c, g, ht, sc;   // data offsets (complex elements; sc in subcarriers)
   // workspace byte offsets of this channel's scratch
-  int64_t w_Y;     // [nsc][m][nt]        c64   A^H H_s
-  int64_t w_W;     // [ngroups][p][m][nt] c64   sum_s conj(C[s,q]) Y_s
+  int64_t w_W;     // [ngroups][p][m][nt] c64   A^H sum_s conj(C[s,q]) H_s
   int64_t w_T;     // [nsc][nr][n]        c64   H_s B
   int64_t w_Yh;    // [nsc][m][n]         c64   A^H H_s B
   int64_t w_S1p;   // [ngroups][nr][nr]   c64   per-group mode-1 Gram

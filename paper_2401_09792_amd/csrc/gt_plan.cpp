@@ -201,7 +201,6 @@ gt_status gt_plan_create(const gt_channel_desc* descs, int32_t n_channels, const
       off = align256(off + std::max<int64_t>(bytes, 8));
       return at;
     };
-    ch.w_Y = take(c8 * ch.nsc * ch.m * ch.nt);
     ch.w_W = take(c8 * ch.ngroups * ch.p * ch.m * ch.nt);
     ch.w_T = take(c8 * ch.nsc * ch.nr * ch.n);
     ch.w_Yh = take(c8 * ch.nsc * ch.m * ch.n);
