@@ -281,6 +281,86 @@ __device__ void orthonormalize(SubLds& L, const float2* Src, const float2* Fb, f
   __syncthreads();
 }
 
+// Cholesky factorisation Src^H Src = R^H R of the Gram block in L.e.kr/ki (upper triangle,
+// overwritten by R, on wave 0), then R^{-1} column by column (lane j solves R x = e_j by back
+// substitution) into L.e.vr/vi with the identity column order in L.e.src, so that
+// rotate_block applies R^{-1}.  Returns false in every thread when a pivot falls below
+// kPiv times its diagonal entry of the Gram (a column nearly dependent on the ones before).
+constexpr float kPiv = 1.0e-5f;
+
+__device__ bool chol_inv(SubLds& L) {
+  const int t = threadIdx.x;
+  if (t < KB) {
+    const int j = t;
+    L.rs[j] = L.e.kr[j][j];
+    wave_sync();
+    bool ok = true;
+    for (int k = 0; k < KB; ++k) {
+      const float d = L.e.kr[k][k];
+      const bool good = d > kPiv * L.rs[k] && d > 1.0e-30f;
+      ok = ok && good;
+      const float rinv = good ? 1.0f / __builtin_sqrtf(d) : 1.0f;
+      wave_sync();
+      float gr = 0.f, gi = 0.f;
+      if (j >= k) {
+        gr = (j == k) ? d * rinv : L.e.kr[k][j] * rinv;
+        gi = (j == k) ? 0.f : L.e.ki[k][j] * rinv;
+        L.e.kr[k][j] = gr;
+        L.e.ki[k][j] = gi;
+      }
+      wave_sync();
+      // G[i][j] -= conj(R[k][i]) R[k][j] for k < i <= j
+      for (int i = k + 1; i <= j; ++i) {
+        const float ar = L.e.kr[k][i], ai = L.e.ki[k][i];
+        L.e.kr[i][j] -= ar * gr + ai * gi;
+        L.e.ki[i][j] -= ar * gi - ai * gr;
+      }
+      wave_sync();
+    }
+    // column j of R^{-1}: x_j = 1 / R_jj, x_i = -(sum_{i < k <= j} R_ik x_k) / R_ii
+    for (int i = KB - 1; i > j; --i) {
+      L.e.vr[i][j] = 0.f;
+      L.e.vi[i][j] = 0.f;
+    }
+    L.e.vr[j][j] = 1.0f / L.e.kr[j][j];
+    L.e.vi[j][j] = 0.f;
+    for (int i = j - 1; i >= 0; --i) {
+      float sr = 0.f, si = 0.f;
+      for (int k = i + 1; k <= j; ++k) {
+        const float rr = L.e.kr[i][k], ri = L.e.ki[i][k];
+        const float xr = L.e.vr[k][j], xi = L.e.vi[k][j];
+        sr += rr * xr - ri * xi;
+        si += rr * xi + ri * xr;
+      }
+      const float dinv = -1.0f / L.e.kr[i][i];
+      L.e.vr[i][j] = sr * dinv;
+      L.e.vi[i][j] = si * dinv;
+    }
+    L.e.src[j] = j;
+    if (j == 0) L.bsum[0] = ok ? 1.f : 0.f;
+  }
+  __syncthreads();
+  return L.bsum[0] != 0.f;
+}
+
+// Dst = orthonormal basis of the columns of Src: Cholesky-QR (passes 1 or 2, the second
+// in place on Dst), falling back to Gram-Schmidt with column replacement when the block is
+// too close to rank deficient for the Cholesky factorisation.
+__device__ void orth_block(SubLds& L, const float2* Src, const float2* Fb, float2* Dst, int nt,
+                           int passes) {
+  rayleigh(L, Src, Src, nt);
+  bool ok = chol_inv(L);
+  if (ok) {
+    rotate_block(L, Src, Dst, nt);
+    if (passes > 1) {
+      rayleigh(L, Dst, Dst, nt);
+      ok = chol_inv(L);
+      if (ok) rotate_block(L, Dst, Dst, nt);
+    }
+  }
+  if (!ok) orthonormalize(L, Src, Fb, Dst, nt);
+}
+
 // Largest relative residual ||W_j - theta_j Z_j|| / theta_0 over the kept columns j < n.
 __device__ float max_residual(SubLds& L, const float2* Z, const float2* W, int nt, int n) {
   const int t = threadIdx.x;
@@ -323,13 +403,13 @@ __global__ void __launch_bounds__(NTH) k_eigB_sub(const DevChan* __restrict__ ch
   // starting orthonormal block in V
   float2 *V, *Y, *F;
   if (warm) {
-    orthonormalize(L, P0, nullptr, P1, nt);
+    orth_block(L, P0, nullptr, P1, nt, 1);  // the previous Ritz basis, orthonormal to rounding
     V = P1;
     Y = P2;
     F = P0;
   } else {
     apply_gram(L, S, nullptr, P1, nt);
-    orthonormalize(L, P1, nullptr, P0, nt);
+    orth_block(L, P1, nullptr, P0, nt, 2);
     V = P0;
     Y = P1;
     F = P2;
@@ -353,7 +433,7 @@ __global__ void __launch_bounds__(NTH) k_eigB_sub(const DevChan* __restrict__ ch
       break;
     }
     if (it == max_iter - 1) break;
-    orthonormalize(L, V, Z, Y, nt);  // next block, in Y's storage
+    orth_block(L, V, Z, Y, nt, 2);  // next block, in Y's storage
     float2* nv = Y;
     Y = V;
     F = Z;
