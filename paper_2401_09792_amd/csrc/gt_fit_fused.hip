@@ -1277,14 +1277,29 @@ __device__ __forceinline__ void upper_tile(int k, int T, int& I, int& J) {
   J = I + k;
 }
 
-__global__ void __launch_bounds__(256) k_gram_rows_mfma(const DevChan* __restrict__ chans,
-                                                        const float2* __restrict__ X, char* ws,
-                                                        int which, int noct_max) {
+// Mode-2 Gram for wide arrays from the rows of X (which = 0: rows (s, i)) or of W (which = 1:
+// rows (g, q, a)), each row nt complex read as 2 nt interleaved reals (re, im).  The real Gram
+// P = R^T R of the rows r0..r1 of one split is accumulated in 128 x 128 super-tiles of the
+// upper triangle, one per block; wave w computes the 2 x 2 tiles of 32 at rows 2 (w / 2) + {0, 1}
+// and columns 2 (w % 2) + {0, 1} of its super-tile.  Chunks of 16 rows are staged in LDS
+// column-major ([128 columns][16 rows + pad], double-buffered) so that a lane reads four
+// consecutive rows at once: step 4 u + v takes row 8 u + 4 h + v in lane half h.  The next
+// chunk's global loads (clamped, zeroed past the split or the row end) are in flight during
+// the current chunk's products.
+constexpr int kGK = 16, kGP = 20;  // rows per chunk, LDS column stride (conflict-free b128 reads)
+
+__global__ void __launch_bounds__(256) k_gram_rows_st(const DevChan* __restrict__ chans,
+                                                      const float2* __restrict__ X, char* ws,
+                                                      int which, int nst_max) {
+  __shared__ float4 sbuf4[2 * 2 * 128 * kGP / 4];  // [buffer][A, B][column][row]
+  float* sbuf = reinterpret_cast<float*>(sbuf4);
   const DevChan& ch = chans[blockIdx.y];
-  const int nt = ch.nt;
-  const int T = (2 * nt + 31) / 32, npairs = T * (T + 1) / 2, noct = (npairs + 7) / 8;
-  const int oct = blockIdx.x % noct_max, split = blockIdx.x / noct_max;
-  if (oct >= noct || split >= ch.nsplit) return;
+  const int nt = ch.nt, nc = 2 * nt;
+  const int S = (nc + 127) / 128, nst = S * (S + 1) / 2;
+  const int st = blockIdx.x % nst_max, split = blockIdx.x / nst_max;
+  if (st >= nst || split >= ch.nsplit) return;
+  int SI, SJ;
+  upper_tile(st, S, SI, SJ);
   const float* M;
   int64_t nrows;
   if (which == 0) {
@@ -1295,78 +1310,121 @@ __global__ void __launch_bounds__(256) k_gram_rows_mfma(const DevChan* __restric
     nrows = (int64_t)ch.ngroups * ch.p * ch.m;
   }
   const int64_t r0 = split * nrows / ch.nsplit, r1 = (split + 1) * nrows / ch.nsplit;
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, h = lane / 32, col = lane % 32;
-  int tI[2], tJ[2], oa[2], ob[2];
-  bool ok[2], va[2], vb[2];
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, h = lane / 32, col = lane % 32;
+  const bool vec = (nt % 2) == 0 && ((reinterpret_cast<uintptr_t>(M) & 15) == 0);
+  // staging role of this thread: element e = tid + 256 k, matrix e / 512 (A rows of SI, B of
+  // SJ), row (e / 32) % 16 of the chunk, columns 4 (e % 32) .. + 3 of the 128
+  int cb[4], lds[4], rowk[4];
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const int k = 8 * oct + 2 * wave + t;
-    ok[t] = k < npairs;
-    upper_tile(ok[t] ? k : 0, T, tI[t], tJ[t]);
-    const int ca = 32 * tI[t] + col, cb = 32 * tJ[t] + col;
-    va[t] = ca < 2 * nt;
-    vb[t] = cb < 2 * nt;
-    const int ja = ca < nt ? ca : ca - nt, jb = cb < nt ? cb : cb - nt;
-    oa[t] = 2 * min(max(ja, 0), nt - 1) + (ca >= nt ? 1 : 0);
-    ob[t] = 2 * min(max(jb, 0), nt - 1) + (cb >= nt ? 1 : 0);
+  for (int k = 0; k < 4; ++k) {
+    const int e = tid + 256 * k, mat = e >> 9, cq = e & 31;
+    rowk[k] = (e >> 5) & 15;
+    cb[k] = 128 * (mat ? SJ : SI) + 4 * cq;
+    lds[k] = mat * 128 * kGP + 4 * cq * kGP + rowk[k];
   }
-  f32x16 acc[2];
+  float4 pf[4];
+  auto load = [&](int64_t rc) {
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
-  if (ok[0] || ok[1]) {
-    for (int64_t k0 = r0; k0 < r1; k0 += 16) {
-      float a0[8], b0[8], a1[8], b1[8];
-#pragma unroll
-      for (int d = 0; d < 8; ++d) {
-        const int64_t row = k0 + 2 * d + h;
-        const bool rv = row < r1;
-        const float* rp = M + min(row, r1 - 1) * 2 * nt;
-        const float x0 = rp[oa[0]], y0 = rp[ob[0]], x1 = rp[oa[1]], y1 = rp[ob[1]];
-        a0[d] = (rv && va[0]) ? x0 : 0.f;
-        b0[d] = (rv && vb[0]) ? y0 : 0.f;
-        a1[d] = (rv && va[1]) ? x1 : 0.f;
-        b1[d] = (rv && vb[1]) ? y1 : 0.f;
+    for (int k = 0; k < 4; ++k) {
+      const int64_t rr = rc + rowk[k];
+      const bool ok = rr < r1;
+      const float* rp = M + min(rr, r1 - 1) * nc;
+      const int c = cb[k];
+      float4 v;
+      if (vec) {  // nc % 4 == 0: the quad is wholly inside or wholly outside the row
+        v = *reinterpret_cast<const float4*>(rp + min(c, nc - 4));
+        if (c >= nc) v = make_float4(0.f, 0.f, 0.f, 0.f);
+      } else {
+        const float x0 = rp[min(c, nc - 1)], x1 = rp[min(c + 1, nc - 1)];
+        const float x2 = rp[min(c + 2, nc - 1)], x3 = rp[min(c + 3, nc - 1)];
+        v = make_float4(c < nc ? x0 : 0.f, c + 1 < nc ? x1 : 0.f, c + 2 < nc ? x2 : 0.f,
+                        c + 3 < nc ? x3 : 0.f);
       }
-#pragma unroll
-      for (int d = 0; d < 8; ++d) {
-        acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[d], b0[d], acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[d], b1[d], acc[1], 0, 0, 0);
-      }
+      pf[k] = ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
     }
+  };
+  auto store = [&](int buf) {
+    float* d = sbuf + buf * 2 * 128 * kGP;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      d[lds[k]] = pf[k].x;
+      d[lds[k] + kGP] = pf[k].y;
+      d[lds[k] + 2 * kGP] = pf[k].z;
+      d[lds[k] + 3 * kGP] = pf[k].w;
+    }
+  };
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+  const int ti0 = 2 * (wave >> 1), tj0 = 2 * (wave & 1);
+  const int nchunk = (int)((r1 - r0 + kGK - 1) / kGK);
+  if (nchunk > 0) {
+    load(r0);
+    store(0);
   }
-  const int W = 32 * T;
+  __syncthreads();
+  for (int c = 0; c < nchunk; ++c) {
+    if (c + 1 < nchunk) load(r0 + (int64_t)(c + 1) * kGK);
+    const float* sA = sbuf + (c & 1) * 2 * 128 * kGP;
+    const float* sB = sA + 128 * kGP;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      float4 av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+        av[a] = *reinterpret_cast<const float4*>(sA + (32 * (ti0 + a) + col) * kGP + 8 * u + 4 * h);
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        bv[b] = *reinterpret_cast<const float4*>(sB + (32 * (tj0 + b) + col) * kGP + 8 * u + 4 * h);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a].x, bv[b].x, acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a].y, bv[b].y, acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a].z, bv[b].z, acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a].w, bv[b].w, acc[a][b], 0, 0, 0);
+        }
+    }
+    if (c + 1 < nchunk) store((c + 1) & 1);
+    __syncthreads();
+  }
+  const int W = 128 * S;
   float* P = reinterpret_cast<float*>(ws + ch.w_S2p) + (int64_t)split * W * W;
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    if (ok[t])
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int row = 32 * tI[t] + 8 * (r / 4) + 4 * h + (r % 4);
-        P[(int64_t)row * W + 32 * tJ[t] + col] = acc[t][r];
+        const int row = 128 * SI + 32 * (ti0 + a) + 8 * (r / 4) + 4 * h + (r % 4);
+        P[(int64_t)row * W + 128 * SJ + 32 * (tj0 + b) + col] = acc[a][b][r];
       }
-  }
 }
 
-// S2 (nt x nt complex) = sum over splits of the blocks of the real Gram in the layout above:
-// Re S2 = R_re^T R_re + R_im^T R_im, Im S2 = R_re^T R_im - R_im^T R_re (lower tiles by symmetry).
-__global__ void k_reduce_S2_big(const DevChan* __restrict__ chans, char* ws) {
+// S2 (nt x nt complex) = sum over splits of the interleaved real Gram above (super-tiles of the
+// lower triangle by symmetry): Re S2[j][k] = P[2j][2k] + P[2j+1][2k+1],
+// Im S2[j][k] = P[2j][2k+1] - P[2j+1][2k].
+__global__ void k_reduce_S2_st(const DevChan* __restrict__ chans, char* ws) {
   const DevChan& ch = chans[blockIdx.y];
   const int nt = ch.nt;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nt * nt) return;
   const int j = e / nt, k = e % nt;
-  const int W = 32 * ((2 * nt + 31) / 32);
+  const int W = 128 * ((2 * nt + 127) / 128);
   const float* P = reinterpret_cast<const float*>(ws + ch.w_S2p);
   auto at = [&](const float* Q, int a, int b) {
-    return ((a >> 5) <= (b >> 5)) ? Q[(int64_t)a * W + b] : Q[(int64_t)b * W + a];
+    return ((a >> 7) <= (b >> 7)) ? Q[(int64_t)a * W + b] : Q[(int64_t)b * W + a];
   };
   float re = 0.f, im = 0.f;
   for (int sp = 0; sp < ch.nsplit; ++sp) {
     const float* Q = P + (int64_t)sp * W * W;
-    re += at(Q, j, k) + at(Q, nt + j, nt + k);
-    im += at(Q, j, nt + k) - at(Q, nt + j, k);
+    re += at(Q, 2 * j, 2 * k) + at(Q, 2 * j + 1, 2 * k + 1);
+    im += at(Q, 2 * j, 2 * k + 1) - at(Q, 2 * j + 1, 2 * k);
   }
   reinterpret_cast<float2*>(ws + ch.w_S2)[e] = make_float2(re, im);
 }
@@ -1678,10 +1736,10 @@ gt_status launch_yh_from_t(const LaunchCtx& L, const float2* A) {
 
 // Mode-2 Gram of X rows (which = 0) or W rows (which = 1) for plans with some nt > 64.
 gt_status launch_gram_rows_big(const LaunchCtx& L, const float2* X, int which) {
-  const int T = (2 * L.max_nt + 31) / 32, noct = (T * (T + 1) / 2 + 7) / 8;
-  GT_LAUNCH_SH(k_gram_rows_mfma, dim3(noct * L.max_nsplit, L.n_channels), dim3(256), 0, L.d_chans, X,
-               L.ws, which, noct);
-  GT_LAUNCH_SH(k_reduce_S2_big, dim3((L.max_nt * L.max_nt + 255) / 256, L.n_channels), dim3(256), 0,
+  const int S = (2 * L.max_nt + 127) / 128, nst = S * (S + 1) / 2;
+  GT_LAUNCH_SH(k_gram_rows_st, dim3(nst * L.max_nsplit, L.n_channels), dim3(256), 0, L.d_chans, X,
+               L.ws, which, nst);
+  GT_LAUNCH_SH(k_reduce_S2_st, dim3((L.max_nt * L.max_nt + 255) / 256, L.n_channels), dim3(256), 0,
                L.d_chans, L.ws);
   return GT_OK;
 }

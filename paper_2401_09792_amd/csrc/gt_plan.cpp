@@ -206,8 +206,8 @@ gt_status gt_plan_create(const gt_channel_desc* descs, int32_t n_channels, const
     ch.w_Yh = take(c8 * ch.nsc * ch.m * ch.n);
     ch.w_S1p = take(c8 * ch.ngroups * ch.nr * ch.nr);
     ch.w_S1 = take(c8 * ch.nr * ch.nr);
-    {  // split partials: complex nt x nt (VALU Gram) or the real Gram of [Re | Im] in 32-wide tiles
-      const int64_t wr = 32 * ((2 * (int64_t)std::max(ch.nt, 64) + 31) / 32);
+    {  // split partials: complex nt x nt (VALU Gram) or the real Gram in 128-wide super-tiles
+      const int64_t wr = 128 * ((2 * (int64_t)std::max(ch.nt, 64) + 127) / 128);
       ch.w_S2p = take(std::max<int64_t>(c8 * ch.nsplit * ch.nt * ch.nt, 4LL * ch.nsplit * wr * wr));
     }
     ch.w_S2 = take(c8 * ch.nt * ch.nt);
