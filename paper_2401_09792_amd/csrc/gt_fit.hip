@@ -661,6 +661,7 @@ static gt_status eig_dispatch(const LaunchCtx& L, int which, float2* A, float2* 
 }
 
 bool fused_fit_ok(const LaunchCtx& L);
+bool fused_lowp_ok(const LaunchCtx& L);
 gt_status launch_convert_x(const LaunchCtx& L, const float2* X);
 gt_status launch_gram_x(const LaunchCtx& L, const float2* X);
 gt_status launch_gram_rows_big(const LaunchCtx& L, const float2* X, int which);
@@ -701,7 +702,13 @@ gt_status launch_fit(const LaunchCtx& L, const float2* X, float2* A, float2* B, 
     if ((st = eig_dispatch(L, 2, A, B, C, status, 0)) != GT_OK) return st;
   }
   // objective of the starting factors (the generic path also needs Yh for the cores)
-  const bool fused = fused_fit_ok(L);
+  // the fused per-group passes need their own limits for 16-bit contractions; the generic
+  // row passes take any shape
+  const bool fused = fused_fit_ok(L) && (L.ttm_prec == GT_TTM_FP32 || fused_lowp_ok(L));
+  if (L.ttm_prec != GT_TTM_FP32) {  // 16-bit copy of X for the contractions below
+    gt_status st;
+    if ((st = launch_convert_x(L, X)) != GT_OK) return st;
+  }
   if (trace || !fused) {
     // T = H B (kept for the first A-step of the generic path), Yh = A^H T
     gt_status st;
@@ -717,7 +724,6 @@ gt_status launch_fit(const LaunchCtx& L, const float2* X, float2* A, float2* B, 
     // per sweep: eigA, [W + Gram], eigB, [T, Yh, S3], eigC, [Z + S1 or cores]; the first
     // A-step Gram comes from [T] and [Z] with the starting factors
     gt_status st;
-    if (L.ttm_prec != GT_TTM_FP32 && (st = launch_convert_x(L, X)) != GT_OK) return st;
     if ((st = launch_fused_t(L, X, A, B, 0)) != GT_OK) return st;
     if ((st = launch_fused_z(L, C, G, iters > 0 ? 1 : 0, 0)) != GT_OK) return st;
     if (iters == 0) {

@@ -1502,6 +1502,104 @@ __global__ void __launch_bounds__(256) k_rows_times_b(const DevChan* __restrict_
   }
 }
 
+// Precision form of the generic T pass: T = H B on 16-bit operands from the 16-bit copy of X
+// (nt % 4 == 0).  B's real-form slice for one 32-wide output tile is staged in LDS as
+// [32 c][2 nt + 4] 16-bit values (hi, then lo for the split form; the pad keeps the lanes'
+// 8-byte reads on distinct banks).  K steps of 8 real indices; pairs of steps 2 u, 2 u + 1 take
+// k' = 16 u + 8 h + 4 w + v in lane half h (16 contiguous bytes of the row per lane), a last
+// single step (nt % 8 == 4) takes k' = 8 t + 4 h + v.
+template <int PREC>
+__global__ void __launch_bounds__(256) k_rows_times_b_lp(const DevChan* __restrict__ chans,
+                                                         const float2* __restrict__ B, char* ws,
+                                                         int tiles_per_block) {
+  extern __shared__ unsigned short bq[];  // [NQ][32][2 nt + 4]
+  constexpr int NQ = PREC == 3 ? 2 : 1;
+  const DevChan& ch = chans[blockIdx.z];
+  const int nt = ch.nt, n = ch.n, nc = 2 * nt, sd = nc + 4;
+  const int ctile = blockIdx.y;
+  if (32 * ctile >= 2 * n) return;
+  const int64_t nrows = (int64_t)ch.nsc * ch.nr;
+  const int64_t rtiles = (nrows + 31) / 32;
+  const int64_t t0 = (int64_t)blockIdx.x * tiles_per_block;
+  if (t0 >= rtiles) return;
+  const unsigned short* Xh = reinterpret_cast<const unsigned short*>(ws + ch.w_Xq);
+  const int64_t xtot = nrows * nt;
+  float2* out = reinterpret_cast<float2*>(ws + ch.w_T);
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, half = lane / 32, col = lane % 32;
+  for (int e = tid; e < 32 * nc; e += 256) {
+    const int c = e / nc, kk = e % nc, j = kk / 2, part = kk % 2;
+    const int oc = 32 * ctile + c;
+    float v = 0.f;
+    if (oc < 2 * n) {
+      const float2 b = B[ch.b + (int64_t)j * n + (oc < n ? oc : oc - n)];
+      v = (part == 0) ? (oc < n ? b.x : b.y) : (oc < n ? -b.y : b.x);
+    }
+    bq[c * sd + kk] = q_hi<PREC>(v);
+    if (PREC == 3) bq[32 * sd + c * sd + kk] = q_lo<PREC>(v);
+  }
+  __syncthreads();
+  const int oc = 32 * ctile + col;
+  const bool ocv = oc < 2 * n;
+  const int ob = oc < n ? oc : oc - n, opart = oc < n ? 0 : 1;
+  const unsigned short* bh = bq + col * sd;
+  const unsigned short* bl = bq + 32 * sd + col * sd;
+  const int K16 = nt / 8;          // pairs of steps
+  const bool tail = (nt % 8) != 0;  // one more step of 8
+  const int64_t tend = min(rtiles, t0 + tiles_per_block);
+  for (int64_t rt = t0 + wave; rt < tend; rt += 4) {
+    const int64_t row = min(rt * 32 + col, nrows - 1);
+    const unsigned short* xr = Xh + 2 * row * nt;
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    for (int u0 = 0; u0 < K16; u0 += 4) {
+      uint4 a[4], al[4];
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const int u = min(u0 + d, K16 - 1);
+        a[d] = *reinterpret_cast<const uint4*>(xr + 16 * u + 8 * half);
+        if (PREC == 3) al[d] = *reinterpret_cast<const uint4*>(xr + 2 * xtot + 16 * u + 8 * half);
+      }
+#pragma unroll
+      for (int d = 0; d < 4; ++d)
+        if (u0 + d < K16) {
+          const int u = u0 + d;
+#pragma unroll
+          for (int w = 0; w < 2; ++w) {
+            const uint2 a2 = w == 0 ? make_uint2(a[d].x, a[d].y) : make_uint2(a[d].z, a[d].w);
+            const uint2 b2 = *reinterpret_cast<const uint2*>(bh + 16 * u + 8 * half + 4 * w);
+            const s16x4 av = __builtin_bit_cast(s16x4, a2), bv = __builtin_bit_cast(s16x4, b2);
+            acc = mfma16<PREC>(av, bv, acc);
+            if (PREC == 3) {
+              const uint2 a2l = w == 0 ? make_uint2(al[d].x, al[d].y) : make_uint2(al[d].z, al[d].w);
+              const uint2 b2l = *reinterpret_cast<const uint2*>(bl + 16 * u + 8 * half + 4 * w);
+              acc = mfma16<PREC>(av, __builtin_bit_cast(s16x4, b2l), acc);
+              acc = mfma16<PREC>(__builtin_bit_cast(s16x4, a2l), bv, acc);
+            }
+          }
+        }
+    }
+    if (tail) {
+      const int k0 = 16 * K16 + 4 * half;
+      const s16x4 av = __builtin_bit_cast(s16x4, *reinterpret_cast<const uint2*>(xr + k0));
+      const s16x4 bv = __builtin_bit_cast(s16x4, *reinterpret_cast<const uint2*>(bh + k0));
+      acc = mfma16<PREC>(av, bv, acc);
+      if (PREC == 3) {
+        const s16x4 avl = __builtin_bit_cast(s16x4, *reinterpret_cast<const uint2*>(xr + 2 * xtot + k0));
+        const s16x4 bvl = __builtin_bit_cast(s16x4, *reinterpret_cast<const uint2*>(bl + k0));
+        acc = mfma16<PREC>(av, bvl, acc);
+        acc = mfma16<PREC>(avl, bv, acc);
+      }
+    }
+    if (ocv)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t orow = rt * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+        if (orow < nrows) reinterpret_cast<float*>(out + orow * n + ob)[opart] = acc[r];
+      }
+  }
+}
+
 // B-step rows for wide arrays: W_q = A^H (sum_s conj(C[s,q]) H_s) for one group and a chunk of
 // 32 transmit columns per block, written to the workspace as rows (g, q, a) of nt complex for
 // the mode-2 Gram.  Step 1 contracts the subcarriers first, Hc_q = sum_s conj(C[s,q]) H_s,
@@ -1509,7 +1607,7 @@ __global__ void __launch_bounds__(256) k_rows_times_b(const DevChan* __restrict_
 // per antenna i), into LDS as separate re and im planes [q][i][32]; step 2 takes per q the
 // product with A^H (rows (a, re/im), K (i, re/im)).  Rows q >= p_g of a short group come out
 // zero through zero coefficients.
-template <int SMAX>
+template <int SMAX, int PREC>
 __global__ void __launch_bounds__(256) k_w_rows(const DevChan* __restrict__ chans,
                                                 const float2* __restrict__ X,
                                                 const float2* __restrict__ A,
@@ -1542,13 +1640,67 @@ __global__ void __launch_bounds__(256) k_w_rows(const DevChan* __restrict__ chan
     const int q = q0 + rq;
     const bool qv = q < pg && rq < qcap;
     const float* cg = reinterpret_cast<const float*>(C + ch.c + (int64_t)s0 * p + min(q, p - 1)) + (po ^ h);
-    float cp[SMAX];
+    float cp[PREC == 0 ? SMAX : 1];
+    if constexpr (PREC == 0)
 #pragma unroll
-    for (int s = 0; s < SMAX; ++s) {
-      const float c = cg[2 * (int64_t)min(s, sz - 1) * p];
-      cp[s] = (qv && s < sz) ? csign * c : 0.f;
-    }
+      for (int s = 0; s < SMAX; ++s) {
+        const float c = cg[2 * (int64_t)min(s, sz - 1) * p];
+        cp[s] = (qv && s < sz) ? csign * c : 0.f;
+      }
     if (q0 > 0) __syncthreads();  // the previous q tile's step 2 has read the planes
+    if constexpr (PREC != 0) {
+      // 1. on 16-bit operands: K step t covers subcarriers 4 t .. 4 t + 3, lane half h holding
+      // k = (s, re/im) for s = 4 t + 2 h and 4 t + 2 h + 1 (the v order re, im, re, im)
+      constexpr int SQ = (SMAX + 3) / 4;
+      constexpr int NQ = PREC == 3 ? 2 : 1;
+      uint2 aq[NQ][SQ];
+#pragma unroll
+      for (int t = 0; t < SQ; ++t) {
+        const int sa = 4 * t + 2 * h, sb = sa + 1;
+        const float sga = (po == 1) ? -1.f : 1.f;  // sign of the pi = 0 entry of row po
+        const float2 cva = C[ch.c + (int64_t)(s0 + min(sa, sz - 1)) * p + min(q, p - 1)];
+        const float2 cvb = C[ch.c + (int64_t)(s0 + min(sb, sz - 1)) * p + min(q, p - 1)];
+        const bool va = qv && sa < sz, vb = qv && sb < sz;
+        // row po 0: (Re C, Im C)[pi]; row po 1: (-Im C, Re C)[pi]
+        const float a0 = va ? (po == 0 ? cva.x : sga * cva.y) : 0.f;
+        const float a1 = va ? (po == 0 ? cva.y : cva.x) : 0.f;
+        const float b0 = vb ? (po == 0 ? cvb.x : sga * cvb.y) : 0.f;
+        const float b1 = vb ? (po == 0 ? cvb.y : cvb.x) : 0.f;
+        aq[0][t] = __builtin_bit_cast(uint2, pack4(q_hi<PREC>(a0), q_hi<PREC>(a1), q_hi<PREC>(b0), q_hi<PREC>(b1)));
+        if (PREC == 3)
+          aq[NQ - 1][t] = __builtin_bit_cast(uint2, pack4(q_lo<PREC>(a0), q_lo<PREC>(a1), q_lo<PREC>(b0), q_lo<PREC>(b1)));
+      }
+      const int64_t xtot = (int64_t)ch.nsc * nr * nt;
+      const unsigned* xq = reinterpret_cast<const unsigned*>(ws + ch.w_Xq) + (int64_t)s0 * nr * nt;
+      for (int i = wave; i < nr; i += 4) {
+        uint2 xv[NQ][SQ];
+#pragma unroll
+        for (int t = 0; t < SQ; ++t) {
+          const int64_t sa = min(4 * t + 2 * h, sz - 1), sb = min(4 * t + 2 * h + 1, sz - 1);
+          const int64_t oa = (sa * nr + i) * nt + jcl, ob = (sb * nr + i) * nt + jcl;
+          xv[0][t] = make_uint2(xq[oa], xq[ob]);
+          if (PREC == 3) xv[NQ - 1][t] = make_uint2(xq[xtot + oa], xq[xtot + ob]);
+        }
+        f32x16 acc;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+#pragma unroll
+        for (int t = 0; t < SQ; ++t)
+          if (4 * t < sz) {
+            const s16x4 a = __builtin_bit_cast(s16x4, aq[0][t]), b = __builtin_bit_cast(s16x4, xv[0][t]);
+            acc = mfma16<PREC>(a, b, acc);
+            if (PREC == 3) {
+              acc = mfma16<PREC>(a, __builtin_bit_cast(s16x4, xv[NQ - 1][t]), acc);
+              acc = mfma16<PREC>(__builtin_bit_cast(s16x4, aq[NQ - 1][t]), b, acc);
+            }
+          }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = 8 * (r / 4) + 4 * h + (r % 4), ql = row >> 1;
+          if (ql < qcap) hcs[(row & 1) * plane + (ql * nr + i) * 32 + col] = acc[r];
+        }
+      }
+    } else {
     // 1. NI antenna tiles i0 + 4 k per pass, all loads issued before the products
     constexpr int NI = SMAX <= 12 ? 2 : 1;
     for (int i0 = wave; i0 < nr; i0 += 4 * NI) {
@@ -1582,6 +1734,7 @@ __global__ void __launch_bounds__(256) k_w_rows(const DevChan* __restrict__ chan
             const int row = 8 * (r / 4) + 4 * h + (r % 4), ql = row >> 1;
             if (ql < qcap) hcs[(row & 1) * plane + (ql * nr + i0 + 4 * k) * 32 + col] = acc[k][r];
           }
+    }
     }
     __syncthreads();
     // 2. W_q = A^H Hc_q: rows (a, re/im), K = (i, re/im) with the lane half choosing the plane
@@ -1707,8 +1860,18 @@ gt_status launch_rows_times_b(const LaunchCtx& L, const float2* X, const float2*
   const int64_t rtiles = ((int64_t)L.max_nsc * L.max_nr + 31) / 32;
   const int tpb = 16;
   const dim3 grid((unsigned)((rtiles + tpb - 1) / tpb), (2 * L.max_n + 31) / 32, L.n_channels);
-  GT_LAUNCH_SH(k_rows_times_b, grid, dim3(256), sizeof(float) * 2 * L.max_nt * 32, L.d_chans, X, B,
-               L.ws, tpb);
+  if (L.ttm_prec == GT_TTM_FP32) {
+    GT_LAUNCH_SH(k_rows_times_b, grid, dim3(256), sizeof(float) * 2 * L.max_nt * 32, L.d_chans, X,
+                 B, L.ws, tpb);
+    return GT_OK;
+  }
+  const int nq = L.ttm_prec == GT_TTM_SPLIT_BF16 ? 2 : 1;
+  const size_t sh = sizeof(unsigned short) * nq * 32 * (2 * L.max_nt + 4);
+  switch (L.ttm_prec) {
+    case GT_TTM_BF16: GT_LAUNCH_SH((k_rows_times_b_lp<1>), grid, dim3(256), sh, L.d_chans, B, L.ws, tpb); break;
+    case GT_TTM_FP16: GT_LAUNCH_SH((k_rows_times_b_lp<2>), grid, dim3(256), sh, L.d_chans, B, L.ws, tpb); break;
+    default: GT_LAUNCH_SH((k_rows_times_b_lp<3>), grid, dim3(256), sh, L.d_chans, B, L.ws, tpb); break;
+  }
   return GT_OK;
 }
 
@@ -1718,12 +1881,24 @@ gt_status launch_w_rows(const LaunchCtx& L, const float2* X, const float2* A, co
   const int qcap = std::min(16, L.max_p);
   const dim3 grid((unsigned)(L.max_groups * nchunk), L.n_channels);
   const size_t sh = sizeof(float) * 2 * qcap * L.max_nr * 32;
-  if (L.max_gs <= 12)
-    GT_LAUNCH_SH((k_w_rows<12>), grid, dim3(256), sh, L.d_chans, X, A, C, L.ws, nchunk, qcap);
-  else if (L.max_gs <= 24)
-    GT_LAUNCH_SH((k_w_rows<24>), grid, dim3(256), sh, L.d_chans, X, A, C, L.ws, nchunk, qcap);
-  else
-    GT_LAUNCH_SH((k_w_rows<32>), grid, dim3(256), sh, L.d_chans, X, A, C, L.ws, nchunk, qcap);
+#define GT_WROWS(SM, PR) \
+  GT_LAUNCH_SH((k_w_rows<SM, PR>), grid, dim3(256), sh, L.d_chans, X, A, C, L.ws, nchunk, qcap)
+#define GT_WROWS_P(SM)                                     \
+  switch (L.ttm_prec) {                                    \
+    case GT_TTM_FP32: GT_WROWS(SM, 0); break;              \
+    case GT_TTM_BF16: GT_WROWS(SM, 1); break;              \
+    case GT_TTM_FP16: GT_WROWS(SM, 2); break;              \
+    default: GT_WROWS(SM, 3); break;                       \
+  }
+  if (L.max_gs <= 12) {
+    GT_WROWS_P(12)
+  } else if (L.max_gs <= 24) {
+    GT_WROWS_P(24)
+  } else {
+    GT_WROWS_P(32)
+  }
+#undef GT_WROWS_P
+#undef GT_WROWS
   return GT_OK;
 }
 

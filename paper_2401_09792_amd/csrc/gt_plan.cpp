@@ -306,11 +306,10 @@ gt_status gt_tucker_fit(const gt_plan* plan, const void* X, void* A, void* B, vo
   // wide arrays (nt > 64) use the FP32 subspace-iteration eigensolver only
   if (plan->max_nt > kMaxNt && plan->opt.eig_fp64) return GT_ERR_UNSUPPORTED;
   LaunchCtx L = make_ctx(plan, ws, stream);
-  // 16-bit contractions exist for the fused per-group passes only
+  // 16-bit contractions take K steps of 8 reals: every nt a multiple of 4
   if (plan->opt.ttm_prec != GT_TTM_FP32) {
-    bool nt4 = true;
-    for (const auto& d : plan->desc) nt4 = nt4 && d.nt % 4 == 0;
-    if (!nt4 || !fused_lowp_ok(L)) return GT_ERR_UNSUPPORTED;
+    for (const auto& d : plan->desc)
+      if (d.nt % 4 != 0) return GT_ERR_UNSUPPORTED;
   }
   return launch_fit(L, (const float2*)X, (float2*)A, (float2*)B, (float2*)C, (float2*)G, obj_trace,
                     dev_status, plan->opt.iters, (plan->opt.flags & GT_FIT_WARM_START) != 0);

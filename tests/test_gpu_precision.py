@@ -66,9 +66,59 @@ def test_precision_lossy_fit(gpu_lib, prec):
     assert tr_err <= TOL[prec][1], tr_err
 
 
-def test_precision_outside_fused_path_is_rejected(gpu_lib):
-    # nt = 128 runs the generic passes, where no 16-bit form exists
-    plan = gpu_lib.Plan([desc(4, 128, 24, 12, 2, 8, 4, 2)], iters=2, ttm_prec="bf16")
-    X = dev_c64(crandn(np.random.default_rng(1), 24, 4, 128))
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "split_bf16"])
+def test_precision_wide_lossy_fit(gpu_lib, prec):
+    # nt = 96 runs the generic row passes (16-bit T = H B and subcarrier contraction of W)
+    announce(f"precision {prec} wide lossy fit")
+    rng = np.random.default_rng(73)
+    nsc, nr, nt, gs, m, n, p, iters = 40, 8, 96, 12, 4, 12, 6, 5
+    X = crandn(rng, nsc, nr, nt)
+    X = X * (0.6 ** np.arange(nr))[None, :, None] * (0.93 ** np.arange(nt))[None, None, :]
+    plan = gpu_lib.Plan([desc(nr, nt, nsc, gs, m, n, p, 2)], iters=iters, ttm_prec=prec)
+    res = plan.fit(dev_c64(X))
+    _, xh = plan.reconstruct(res["A"], res["B"], res["C"], res["G"])
+    Xh = unpack(plan, 0, host(xh), "x")
+    orc = tucker.fit(X, gs, m, n, p, iters)
+    _, Xh_o = tucker.reconstruct(orc["A"], orc["B"], orc["C"], orc["G"], gs)
+    nx = float(np.sum(np.abs(X) ** 2))
+    rel = np.linalg.norm(Xh - Xh_o) / np.sqrt(nx)
+    tr_err = np.abs(host(res["trace"])[0] - orc["trace"]).max() / nx
+    print(f"[precision] wide {prec}: X-hat {rel:.3e} of ||X||, trace {tr_err:.3e} of ||X||^2")
+    assert int(res["status"].item()) == 0
+    assert rel <= TOL[prec][1], rel
+    assert tr_err <= TOL[prec][1], tr_err
+
+
+@pytest.fixture(scope="module")
+def wide_oracle():
+    # the 16 x 256 precision workload (16 paths, K = 3 dB, ranks (12, 32, 12), Ns = 8 at 10 dB)
+    # on its first 96 subcarriers
+    cfg = synthgen.CONFIGS["wide"]
+    rng = synthgen.channel_rng(cfg.seed_index, 0)
+    X = synthgen.build_channel(synthgen.draw_paths(rng, cfg.n_paths, cfg.k_db), cfg.nr, cfg.nt, 96)
+    orc = tucker.fit(X, cfg.group_size, cfg.m, cfg.n, cfg.p, cfg.iters)
+    Ht, _ = tucker.reconstruct(orc["A"], orc["B"], orc["C"], orc["G"], cfg.group_size)
+    s2 = synthgen.snr_to_sigma2(cfg.snr_db)
+    return cfg, X, osinr.sinr(Ht, s2, cfg.ns), s2
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "split_bf16"])
+def test_precision_wide_sinr(gpu_lib, wide_oracle, prec):
+    cfg, X, ref, s2 = wide_oracle
+    announce(f"precision {prec} 16 x 256 x 96 fit + sinr")
+    plan = gpu_lib.Plan([desc(cfg.nr, cfg.nt, 96, cfg.group_size, cfg.m, cfg.n, cfg.p, cfg.ns)],
+                        iters=cfg.iters, ttm_prec=prec)
+    res = plan.fit(dev_c64(X))
+    sg = host(plan.sinr(res["C"], res["G"], s2))
+    assert int(res["status"].item()) == 0
+    err = np.abs(db(sg[:, :, :cfg.ns]) - db(ref))
+    print(f"[precision] wide {prec}: max SINR error {err.max():.3e} dB, mean {err.mean():.3e} dB")
+    assert err.max() <= TOL[prec][0], err.max()
+
+
+def test_precision_needs_nt_multiple_of_4(gpu_lib):
+    # 16-bit contractions take K steps of 8 reals
+    plan = gpu_lib.Plan([desc(4, 30, 24, 12, 2, 8, 4, 2)], iters=2, ttm_prec="bf16")
+    X = dev_c64(crandn(np.random.default_rng(1), 24, 4, 30))
     with pytest.raises(GtError, match="GT_ERR_UNSUPPORTED"):
         plan.fit(X)
