@@ -7,8 +7,10 @@
 //   stop once ||Y_j - theta_j V_j|| <= tol theta_0 for every kept column j < n,
 //   otherwise V <- orth(Y) by classical Gram-Schmidt applied twice, and repeat.
 //
-// One 256-thread block per channel.  V, Y and a third buffer live in the workspace as
-// column blocks [64][nt] (column k contiguous), so the passes over them read whole rows.
+// One 256-thread block per channel, in FP32 or (the FP64 eigensolve option) FP64 throughout:
+// the Gram itself is the FP32-accumulated S2, promoted on load.  V, Y and a third buffer live
+// in the workspace as column blocks [64][nt] (column k contiguous), so the passes over them
+// read whole rows.
 // The final Ritz basis stays in the workspace and starts the next call on the same channel
 // (warm start inside the alternating sweeps); a cold start uses V = orth(S2 Omega) with a
 // fixed pseudo-random unimodular Omega.
@@ -23,41 +25,82 @@ namespace {
 
 constexpr int KB = 64;    // Ritz block size
 constexpr int NTH = 256;  // threads per block; nt <= NTH so each thread owns one row
-constexpr float kTol = 5.0e-6f;
 
-__device__ __forceinline__ float2* wsp_s(char* ws, int64_t off) {
-  return reinterpret_cast<float2*>(ws + off);
+template <typename T>
+struct V2T;
+template <>
+struct V2T<float> {
+  using type = float2;
+};
+template <>
+struct V2T<double> {
+  using type = double2;
+};
+template <typename T>
+using V2 = typename V2T<T>::type;
+
+template <typename T>
+__device__ __forceinline__ V2<T> mk(T a, T b) {
+  V2<T> v;
+  v.x = a;
+  v.y = b;
+  return v;
 }
-__device__ __forceinline__ double* wsd_s(char* ws, int64_t off) {
-  return reinterpret_cast<double*>(ws + off);
-}
+
+// Per-precision constants: staging chunk width, stopping tolerance on the relative residual,
+// eigenvalue floor (relative to the largest) below which a kept pair is not held to the
+// tolerance, Cholesky pivot floor, Gram-Schmidt survival threshold (squared norm ratio) and
+// floor.  The Gram is accumulated in FP32, so in the FP64 form eigenpairs below about 1e-6 of
+// the largest eigenvalue lie in its rounding noise: their vectors are any orthonormal
+// completion and are not iterated to the FP64 tolerance.
+template <typename T>
+struct SubP;
+template <>
+struct SubP<float> {
+  static constexpr int KC = 32;
+  static constexpr float tol = 5.0e-6f, floor = 0.0f, piv = 1.0e-5f, keep = 1.0e-8f, tiny = 1.0e-36f;
+};
+template <>
+struct SubP<double> {
+  static constexpr int KC = 8;
+  static constexpr double tol = 1.0e-10, floor = 1.0e-6, piv = 1.0e-10, keep = 1.0e-16, tiny = 1.0e-300;
+};
+
+__device__ __forceinline__ float rsqrt_t(float x) { return 1.0f / __builtin_sqrtf(x); }
+__device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / __builtin_sqrt(x); }
+__device__ __forceinline__ float sqrt_t(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ double sqrt_t(double x) { return __builtin_sqrt(x); }
 
 // Fixed pseudo-random start entries in {1, i, -1, -i} (integer hash of the position).
-__device__ __forceinline__ float2 omega(int k, int j) {
+template <typename T>
+__device__ __forceinline__ V2<T> omega(int k, int j) {
   uint32_t h = (uint32_t)k * 0x9E3779B1u ^ (uint32_t)j * 0x85EBCA77u;
   h ^= h >> 15;
   h *= 0x2C1B3C6Du;
   h ^= h >> 12;
   switch (h & 3u) {
-    case 0: return make_float2(1.f, 0.f);
-    case 1: return make_float2(0.f, 1.f);
-    case 2: return make_float2(-1.f, 0.f);
-    default: return make_float2(0.f, -1.f);
+    case 0: return mk<T>(1, 0);
+    case 1: return mk<T>(0, 1);
+    case 2: return mk<T>(-1, 0);
+    default: return mk<T>(0, -1);
   }
 }
 
+template <typename T>
 struct SubLds {
-  EigLds<float, KB> e;    // Rayleigh quotient and its eigenvectors
-  float2 sa[64][33];      // staging tile: 64 rows x 32
-  float2 sb[32][65];      // staging tile: 32 x 64 columns
-  float red[4][KB][2];    // per-wave partial sums of the Gram-Schmidt coefficients
-  float rs[KB];           // residual norms of the Ritz pairs
-  float ph[KB][2];        // output phases
-  float bsum[4];
+  static constexpr int KC = SubP<T>::KC;
+  EigLds<T, KB> e;        // Rayleigh quotient, Cholesky factor and their eigenvectors / inverse
+  V2<T> sa[64][KC + 1];   // staging tile: 64 rows x KC
+  V2<T> sb[KC][65];       // staging tile: KC x 64 columns
+  T red[4][KB][2];        // per-wave partial sums of the Gram-Schmidt coefficients
+  T rs[KB];               // residual norms of the Ritz pairs / Gram diagonal
+  T ph[KB][2];            // output phases
+  T bsum[4];
 };
 
 // Sum of v over the block (every thread gets the result).
-__device__ float block_sum(SubLds& L, float v) {
+template <typename T>
+__device__ T block_sum(SubLds<T>& L, T v) {
   v = group_sum<64>(v);
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   __syncthreads();
@@ -67,32 +110,35 @@ __device__ float block_sum(SubLds& L, float v) {
 }
 
 // Y[k][i] = sum_j S[i][j] Vin[k][j]  (Vin == nullptr: the start block Omega)
-__device__ void apply_gram(SubLds& L, const float2* __restrict__ S, const float2* Vin, float2* Y,
+template <typename T>
+__device__ void apply_gram(SubLds<T>& L, const float2* __restrict__ S, const V2<T>* Vin, V2<T>* Y,
                            int nt) {
+  constexpr int KC = SubP<T>::KC;
   const int t = threadIdx.x;
   const int bi = (t / 16) * 4, bk = (t % 16) * 4;
   for (int i0 = 0; i0 < nt; i0 += 64) {
-    float ar[4][4], ai[4][4];
+    T ar[4][4], ai[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) ar[a][b] = ai[a][b] = 0.f;
-    for (int j0 = 0; j0 < nt; j0 += 32) {
+      for (int b = 0; b < 4; ++b) ar[a][b] = ai[a][b] = 0;
+    for (int j0 = 0; j0 < nt; j0 += KC) {
       __syncthreads();
-      for (int e = t; e < 64 * 32; e += NTH) {
-        const int r = e / 32, c = e % 32, i = i0 + r, j = j0 + c;
-        L.sa[r][c] = (i < nt && j < nt) ? S[(int64_t)i * nt + j] : make_float2(0.f, 0.f);
+      for (int e = t; e < 64 * KC; e += NTH) {
+        const int r = e / KC, c = e % KC, i = i0 + r, j = j0 + c;
+        const float2 v = (i < nt && j < nt) ? S[(int64_t)i * nt + j] : make_float2(0.f, 0.f);
+        L.sa[r][c] = mk<T>((T)v.x, (T)v.y);
       }
-      for (int e = t; e < 64 * 32; e += NTH) {
-        const int k = e / 32, c = e % 32, j = j0 + c;
-        float2 v = make_float2(0.f, 0.f);
-        if (j < nt) v = Vin ? Vin[(int64_t)k * nt + j] : omega(k, j);
+      for (int e = t; e < 64 * KC; e += NTH) {
+        const int k = e / KC, c = e % KC, j = j0 + c;
+        V2<T> v = mk<T>(0, 0);
+        if (j < nt) v = Vin ? Vin[(int64_t)k * nt + j] : omega<T>(k, j);
         L.sb[c][k] = v;
       }
       __syncthreads();
 #pragma unroll 4
-      for (int c = 0; c < 32; ++c) {
-        float2 x[4], y[4];
+      for (int c = 0; c < KC; ++c) {
+        V2<T> x[4], y[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) x[a] = L.sa[bi + a][c];
 #pragma unroll
@@ -111,33 +157,35 @@ __device__ void apply_gram(SubLds& L, const float2* __restrict__ S, const float2
       const int i = i0 + bi + a;
       if (i < nt)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) Y[(int64_t)(bk + b) * nt + i] = make_float2(ar[a][b], ai[a][b]);
+        for (int b = 0; b < 4; ++b) Y[(int64_t)(bk + b) * nt + i] = mk<T>(ar[a][b], ai[a][b]);
     }
   }
   __syncthreads();
 }
 
 // H = V^H Y into L.e.kr/ki (Hermitian part)
-__device__ void rayleigh(SubLds& L, const float2* V, const float2* Y, int nt) {
+template <typename T>
+__device__ void rayleigh(SubLds<T>& L, const V2<T>* V, const V2<T>* Y, int nt) {
+  constexpr int KC = SubP<T>::KC;
   const int t = threadIdx.x;
   const int ba = (t / 16) * 4, bb = (t % 16) * 4;
-  float ar[4][4], ai[4][4];
+  T ar[4][4], ai[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) ar[a][b] = ai[a][b] = 0.f;
-  for (int i0 = 0; i0 < nt; i0 += 32) {
+    for (int b = 0; b < 4; ++b) ar[a][b] = ai[a][b] = 0;
+  for (int i0 = 0; i0 < nt; i0 += KC) {
     __syncthreads();
-    for (int e = t; e < 64 * 32; e += NTH) {
-      const int k = e / 32, c = e % 32, i = i0 + c;
+    for (int e = t; e < 64 * KC; e += NTH) {
+      const int k = e / KC, c = e % KC, i = i0 + c;
       const bool ok = i < nt;
-      L.sa[k][c] = ok ? V[(int64_t)k * nt + i] : make_float2(0.f, 0.f);
-      L.sb[c][k] = ok ? Y[(int64_t)k * nt + i] : make_float2(0.f, 0.f);
+      L.sa[k][c] = ok ? V[(int64_t)k * nt + i] : mk<T>(0, 0);
+      L.sb[c][k] = ok ? Y[(int64_t)k * nt + i] : mk<T>(0, 0);
     }
     __syncthreads();
 #pragma unroll 4
-    for (int c = 0; c < 32; ++c) {
-      float2 x[4], y[4];
+    for (int c = 0; c < KC; ++c) {
+      V2<T> x[4], y[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) x[a] = L.sa[ba + a][c];
 #pragma unroll
@@ -164,8 +212,8 @@ __device__ void rayleigh(SubLds& L, const float2* V, const float2* Y, int nt) {
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      ar[a][b] = 0.5f * (ar[a][b] + L.e.kr[bb + b][ba + a]);
-      ai[a][b] = 0.5f * (ai[a][b] - L.e.ki[bb + b][ba + a]);
+      ar[a][b] = T(0.5) * (ar[a][b] + L.e.kr[bb + b][ba + a]);
+      ai[a][b] = T(0.5) * (ai[a][b] - L.e.ki[bb + b][ba + a]);
     }
   __syncthreads();
 #pragma unroll
@@ -178,30 +226,33 @@ __device__ void rayleigh(SubLds& L, const float2* V, const float2* Y, int nt) {
   __syncthreads();
 }
 
-// Out[j][i] = sum_a In[a][i] U[a][src[j]]  (U = the Rayleigh quotient's eigenvectors)
-__device__ void rotate_block(SubLds& L, const float2* In, float2* Out, int nt) {
+// Out[j][i] = sum_a In[a][i] U[a][src[j]]  (U = L.e.vr/vi: eigenvectors or R^{-1}); In may
+// equal Out (every row block is read completely before it is written)
+template <typename T>
+__device__ void rotate_block(SubLds<T>& L, const V2<T>* In, V2<T>* Out, int nt) {
+  constexpr int KC = SubP<T>::KC;
   const int t = threadIdx.x;
   const int bi = (t / 16) * 4, bj = (t % 16) * 4;
   int cj[4];
 #pragma unroll
   for (int b = 0; b < 4; ++b) cj[b] = L.e.src[bj + b];
   for (int i0 = 0; i0 < nt; i0 += 64) {
-    float ar[4][4], ai[4][4];
+    T ar[4][4], ai[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) ar[a][b] = ai[a][b] = 0.f;
-    for (int a0 = 0; a0 < KB; a0 += 32) {
+      for (int b = 0; b < 4; ++b) ar[a][b] = ai[a][b] = 0;
+    for (int a0 = 0; a0 < KB; a0 += KC) {
       __syncthreads();
-      for (int e = t; e < 64 * 32; e += NTH) {
+      for (int e = t; e < 64 * KC; e += NTH) {
         const int c = e / 64, r = e % 64, i = i0 + r;
-        L.sa[r][c] = (i < nt) ? In[(int64_t)(a0 + c) * nt + i] : make_float2(0.f, 0.f);
+        L.sa[r][c] = (i < nt) ? In[(int64_t)(a0 + c) * nt + i] : mk<T>(0, 0);
       }
       __syncthreads();
 #pragma unroll 4
-      for (int c = 0; c < 32; ++c) {
-        float2 x[4];
-        float ur[4], ui[4];
+      for (int c = 0; c < KC; ++c) {
+        V2<T> x[4];
+        T ur[4], ui[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) x[a] = L.sa[bi + a][c];
 #pragma unroll
@@ -218,34 +269,36 @@ __device__ void rotate_block(SubLds& L, const float2* In, float2* Out, int nt) {
           }
       }
     }
+    __syncthreads();
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       const int i = i0 + bi + a;
       if (i < nt)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) Out[(int64_t)(bj + b) * nt + i] = make_float2(ar[a][b], ai[a][b]);
+        for (int b = 0; b < 4; ++b) Out[(int64_t)(bj + b) * nt + i] = mk<T>(ar[a][b], ai[a][b]);
     }
   }
   __syncthreads();
 }
 
 // Dst = orthonormal basis of the columns of Src, column by column (classical Gram-Schmidt,
-// two passes).  A column that keeps less than 1e-4 of its norm is replaced by the matching
+// two passes).  A column that keeps too little of its norm is replaced by the matching
 // column of Fb (or of Omega when Fb is null), then by unit vectors, until one survives.
-__device__ void orthonormalize(SubLds& L, const float2* Src, const float2* Fb, float2* Dst,
+template <typename T>
+__device__ void orthonormalize(SubLds<T>& L, const V2<T>* Src, const V2<T>* Fb, V2<T>* Dst,
                                int nt) {
   const int i = threadIdx.x, wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const bool live = i < nt;
   for (int j = 0; j < KB; ++j) {
-    float2 y = live ? Src[(int64_t)j * nt + i] : make_float2(0.f, 0.f);
-    float n0 = block_sum(L, y.x * y.x + y.y * y.y);
-    float n1 = 0.f;
+    V2<T> y = live ? Src[(int64_t)j * nt + i] : mk<T>(0, 0);
+    T n0 = block_sum<T>(L, y.x * y.x + y.y * y.y);
+    T n1 = 0;
     for (int attempt = 0;; ++attempt) {
       for (int pass = 0; pass < 2; ++pass) {
         if (j > 0) {
           for (int k = 0; k < j; ++k) {
-            float2 q = live ? Dst[(int64_t)k * nt + i] : make_float2(0.f, 0.f);
-            float pr = q.x * y.x + q.y * y.y, pi = q.x * y.y - q.y * y.x;  // conj(q) y
+            V2<T> q = live ? Dst[(int64_t)k * nt + i] : mk<T>(0, 0);
+            T pr = q.x * y.x + q.y * y.y, pi = q.x * y.y - q.y * y.x;  // conj(q) y
             pr = group_sum<64>(pr);
             pi = group_sum<64>(pi);
             if (lane == 0) {
@@ -255,10 +308,10 @@ __device__ void orthonormalize(SubLds& L, const float2* Src, const float2* Fb, f
           }
           __syncthreads();
           for (int k = 0; k < j; ++k) {
-            const float cr = (L.red[0][k][0] + L.red[1][k][0]) + (L.red[2][k][0] + L.red[3][k][0]);
-            const float ci = (L.red[0][k][1] + L.red[1][k][1]) + (L.red[2][k][1] + L.red[3][k][1]);
+            const T cr = (L.red[0][k][0] + L.red[1][k][0]) + (L.red[2][k][0] + L.red[3][k][0]);
+            const T ci = (L.red[0][k][1] + L.red[1][k][1]) + (L.red[2][k][1] + L.red[3][k][1]);
             if (live) {
-              float2 q = Dst[(int64_t)k * nt + i];
+              V2<T> q = Dst[(int64_t)k * nt + i];
               y.x -= q.x * cr - q.y * ci;
               y.y -= q.x * ci + q.y * cr;
             }
@@ -266,17 +319,17 @@ __device__ void orthonormalize(SubLds& L, const float2* Src, const float2* Fb, f
           __syncthreads();
         }
       }
-      n1 = block_sum(L, y.x * y.x + y.y * y.y);
-      if ((n1 > 1.0e-8f * n0 && n1 > 1.0e-36f) || attempt > nt + 1) break;
+      n1 = block_sum<T>(L, y.x * y.x + y.y * y.y);
+      if ((n1 > SubP<T>::keep * n0 && n1 > SubP<T>::tiny) || attempt > nt + 1) break;
       // replacement candidate
       if (attempt == 0)
-        y = live ? (Fb ? Fb[(int64_t)j * nt + i] : omega(j, i)) : make_float2(0.f, 0.f);
+        y = live ? (Fb ? Fb[(int64_t)j * nt + i] : omega<T>(j, i)) : mk<T>(0, 0);
       else
-        y = (i == (j + attempt - 1) % nt) ? make_float2(1.f, 0.f) : make_float2(0.f, 0.f);
-      n0 = block_sum(L, y.x * y.x + y.y * y.y);
+        y = (i == (j + attempt - 1) % nt) ? mk<T>(1, 0) : mk<T>(0, 0);
+      n0 = block_sum<T>(L, y.x * y.x + y.y * y.y);
     }
-    const float s = (n1 > 0.f) ? 1.0f / __builtin_sqrtf(n1) : 0.f;
-    if (live) Dst[(int64_t)j * nt + i] = make_float2(y.x * s, y.y * s);
+    const T s = (n1 > 0) ? rsqrt_t(n1) : T(0);
+    if (live) Dst[(int64_t)j * nt + i] = mk<T>(y.x * s, y.y * s);
   }
   __syncthreads();
 }
@@ -284,11 +337,11 @@ __device__ void orthonormalize(SubLds& L, const float2* Src, const float2* Fb, f
 // Cholesky factorisation Src^H Src = R^H R of the Gram block in L.e.kr/ki (upper triangle,
 // overwritten by R, on wave 0), then R^{-1} column by column (lane j solves R x = e_j by back
 // substitution) into L.e.vr/vi with the identity column order in L.e.src, so that
-// rotate_block applies R^{-1}.  Returns false in every thread when a pivot falls below
-// kPiv times its diagonal entry of the Gram (a column nearly dependent on the ones before).
-constexpr float kPiv = 1.0e-5f;
-
-__device__ bool chol_inv(SubLds& L) {
+// rotate_block applies R^{-1}.  Returns false in every thread when a pivot falls below the
+// pivot floor times its diagonal entry of the Gram (a column nearly dependent on the ones
+// before).
+template <typename T>
+__device__ bool chol_inv(SubLds<T>& L) {
   const int t = threadIdx.x;
   if (t < KB) {
     const int j = t;
@@ -296,22 +349,22 @@ __device__ bool chol_inv(SubLds& L) {
     wave_sync();
     bool ok = true;
     for (int k = 0; k < KB; ++k) {
-      const float d = L.e.kr[k][k];
-      const bool good = d > kPiv * L.rs[k] && d > 1.0e-30f;
+      const T d = L.e.kr[k][k];
+      const bool good = d > SubP<T>::piv * L.rs[k] && d > SubP<T>::tiny;
       ok = ok && good;
-      const float rinv = good ? 1.0f / __builtin_sqrtf(d) : 1.0f;
+      const T rinv = good ? rsqrt_t(d) : T(1);
       wave_sync();
-      float gr = 0.f, gi = 0.f;
+      T gr = 0, gi = 0;
       if (j >= k) {
         gr = (j == k) ? d * rinv : L.e.kr[k][j] * rinv;
-        gi = (j == k) ? 0.f : L.e.ki[k][j] * rinv;
+        gi = (j == k) ? T(0) : L.e.ki[k][j] * rinv;
         L.e.kr[k][j] = gr;
         L.e.ki[k][j] = gi;
       }
       wave_sync();
       // G[i][j] -= conj(R[k][i]) R[k][j] for k < i <= j
       for (int i = k + 1; i <= j; ++i) {
-        const float ar = L.e.kr[k][i], ai = L.e.ki[k][i];
+        const T ar = L.e.kr[k][i], ai = L.e.ki[k][i];
         L.e.kr[i][j] -= ar * gr + ai * gi;
         L.e.ki[i][j] -= ar * gi - ai * gr;
       }
@@ -319,57 +372,60 @@ __device__ bool chol_inv(SubLds& L) {
     }
     // column j of R^{-1}: x_j = 1 / R_jj, x_i = -(sum_{i < k <= j} R_ik x_k) / R_ii
     for (int i = KB - 1; i > j; --i) {
-      L.e.vr[i][j] = 0.f;
-      L.e.vi[i][j] = 0.f;
+      L.e.vr[i][j] = 0;
+      L.e.vi[i][j] = 0;
     }
-    L.e.vr[j][j] = 1.0f / L.e.kr[j][j];
-    L.e.vi[j][j] = 0.f;
+    L.e.vr[j][j] = T(1) / L.e.kr[j][j];
+    L.e.vi[j][j] = 0;
     for (int i = j - 1; i >= 0; --i) {
-      float sr = 0.f, si = 0.f;
+      T sr = 0, si = 0;
       for (int k = i + 1; k <= j; ++k) {
-        const float rr = L.e.kr[i][k], ri = L.e.ki[i][k];
-        const float xr = L.e.vr[k][j], xi = L.e.vi[k][j];
+        const T rr = L.e.kr[i][k], ri = L.e.ki[i][k];
+        const T xr = L.e.vr[k][j], xi = L.e.vi[k][j];
         sr += rr * xr - ri * xi;
         si += rr * xi + ri * xr;
       }
-      const float dinv = -1.0f / L.e.kr[i][i];
+      const T dinv = T(-1) / L.e.kr[i][i];
       L.e.vr[i][j] = sr * dinv;
       L.e.vi[i][j] = si * dinv;
     }
     L.e.src[j] = j;
-    if (j == 0) L.bsum[0] = ok ? 1.f : 0.f;
+    if (j == 0) L.bsum[0] = ok ? T(1) : T(0);
   }
   __syncthreads();
-  return L.bsum[0] != 0.f;
+  return L.bsum[0] != T(0);
 }
 
 // Dst = orthonormal basis of the columns of Src: Cholesky-QR (passes 1 or 2, the second
 // in place on Dst), falling back to Gram-Schmidt with column replacement when the block is
 // too close to rank deficient for the Cholesky factorisation.
-__device__ void orth_block(SubLds& L, const float2* Src, const float2* Fb, float2* Dst, int nt,
+template <typename T>
+__device__ void orth_block(SubLds<T>& L, const V2<T>* Src, const V2<T>* Fb, V2<T>* Dst, int nt,
                            int passes) {
-  rayleigh(L, Src, Src, nt);
-  bool ok = chol_inv(L);
+  rayleigh<T>(L, Src, Src, nt);
+  bool ok = chol_inv<T>(L);
   if (ok) {
-    rotate_block(L, Src, Dst, nt);
+    rotate_block<T>(L, Src, Dst, nt);
     if (passes > 1) {
-      rayleigh(L, Dst, Dst, nt);
-      ok = chol_inv(L);
-      if (ok) rotate_block(L, Dst, Dst, nt);
+      rayleigh<T>(L, Dst, Dst, nt);
+      ok = chol_inv<T>(L);
+      if (ok) rotate_block<T>(L, Dst, Dst, nt);
     }
   }
-  if (!ok) orthonormalize(L, Src, Fb, Dst, nt);
+  if (!ok) orthonormalize<T>(L, Src, Fb, Dst, nt);
 }
 
-// Largest relative residual ||W_j - theta_j Z_j|| / theta_0 over the kept columns j < n.
-__device__ float max_residual(SubLds& L, const float2* Z, const float2* W, int nt, int n) {
+// Largest relative residual ||W_j - theta_j Z_j|| / theta_0 over the kept columns j < n with
+// theta_j above the eigenvalue floor.
+template <typename T>
+__device__ T max_residual(SubLds<T>& L, const V2<T>* Z, const V2<T>* W, int nt, int n) {
   const int t = threadIdx.x;
   const int j = t / 4, part = t % 4;
-  const float th = L.e.lam[L.e.src[j]];
-  float acc = 0.f;
+  const T th = L.e.lam[L.e.src[j]];
+  T acc = 0;
   for (int i = part; i < nt; i += 4) {
-    float2 z = Z[(int64_t)j * nt + i], w = W[(int64_t)j * nt + i];
-    const float dr = w.x - th * z.x, di = w.y - th * z.y;
+    V2<T> z = Z[(int64_t)j * nt + i], w = W[(int64_t)j * nt + i];
+    const T dr = w.x - th * z.x, di = w.y - th * z.y;
     acc += dr * dr + di * di;
   }
   acc += __shfl_xor(acc, 1, 64);
@@ -377,64 +433,66 @@ __device__ float max_residual(SubLds& L, const float2* Z, const float2* W, int n
   __syncthreads();
   if (part == 0) L.rs[j] = acc;
   __syncthreads();
-  const float th0 = L.e.lam[L.e.src[0]];
-  float m = 0.f;
-  for (int k = 0; k < n; ++k) m = fmaxf(m, L.rs[k]);
+  const T th0 = L.e.lam[L.e.src[0]];
+  T m = 0;
+  for (int k = 0; k < n; ++k)
+    if (!(L.e.lam[L.e.src[k]] <= SubP<T>::floor * th0)) m = fmax(m, L.rs[k]);
   // NaN propagates: comparisons below fail and the caller stops at the cap
-  const float den = th0 * th0;
-  return (den > 0.f) ? __builtin_sqrtf(m / den) : (m > 0.f ? 1.0f : 0.0f);
+  const T den = th0 * th0;
+  return (den > 0) ? sqrt_t(m / den) : (m > 0 ? T(1) : T(0));
 }
 
 }  // namespace
 
+template <typename T>
 __global__ void __launch_bounds__(NTH) k_eigB_sub(const DevChan* __restrict__ chans, char* ws,
                                                    float2* B, int32_t* status, int warm,
                                                    int max_iter) {
-  __shared__ SubLds L;
+  __shared__ SubLds<T> L;
   const DevChan& ch = chans[blockIdx.x];
   const int nt = ch.nt, n = ch.n;
   if (nt <= 64) return;  // handled by the in-LDS Jacobi kernel
   const int t = threadIdx.x, r = t % 64, wave = t / 64;
-  const float2* S = wsp_s(ws, ch.w_S2);
-  float2* P0 = wsp_s(ws, ch.w_VB);
-  float2* P1 = wsp_s(ws, ch.w_VS);
-  float2* P2 = P1 + (int64_t)KB * nt;
+  const float2* S = reinterpret_cast<const float2*>(ws + ch.w_S2);
+  V2<T>* P0 = reinterpret_cast<V2<T>*>(ws + ch.w_VB);
+  V2<T>* P1 = reinterpret_cast<V2<T>*>(ws + ch.w_VS);
+  V2<T>* P2 = P1 + (int64_t)KB * nt;
 
   // starting orthonormal block in V
-  float2 *V, *Y, *F;
+  V2<T> *V, *Y, *F;
   if (warm) {
-    orth_block(L, P0, nullptr, P1, nt, 1);  // the previous Ritz basis, orthonormal to rounding
+    orth_block<T>(L, P0, nullptr, P1, nt, 1);  // the previous Ritz basis, orthonormal to rounding
     V = P1;
     Y = P2;
     F = P0;
   } else {
-    apply_gram(L, S, nullptr, P1, nt);
-    orth_block(L, P1, nullptr, P0, nt, 2);
+    apply_gram<T>(L, S, nullptr, P1, nt);
+    orth_block<T>(L, P1, nullptr, P0, nt, 2);
     V = P0;
     Y = P1;
     F = P2;
   }
   bool conv = false, jconv = true;
-  float res = 0.f;
-  float2* Z = F;
+  T res = 0;
+  V2<T>* Z = F;
   for (int it = 0; it < max_iter; ++it) {
-    apply_gram(L, S, V, Y, nt);
-    rayleigh(L, V, Y, nt);
-    jconv = jacobi_herm<float, KB, 4>(L.e, r, wave, 12, false) && jconv;
+    apply_gram<T>(L, S, V, Y, nt);
+    rayleigh<T>(L, V, Y, nt);
+    jconv = jacobi_herm<T, KB, 4>(L.e, r, wave, sizeof(T) == 4 ? 12 : 20, false) && jconv;
     __syncthreads();
-    if (wave == 0) eig_sort_desc<float, KB>(L.e, r, KB);
+    if (wave == 0) eig_sort_desc<T, KB>(L.e, r, KB);
     __syncthreads();
     Z = F;
-    rotate_block(L, V, Z, nt);  // Ritz vectors
-    rotate_block(L, Y, V, nt);  // S2 times the Ritz vectors (V's storage is free now)
-    res = max_residual(L, Z, V, nt, n);
-    if (res <= kTol) {
+    rotate_block<T>(L, V, Z, nt);  // Ritz vectors
+    rotate_block<T>(L, Y, V, nt);  // S2 times the Ritz vectors (V's storage is free now)
+    res = max_residual<T>(L, Z, V, nt, n);
+    if (res <= SubP<T>::tol) {
       conv = true;
       break;
     }
     if (it == max_iter - 1) break;
-    orth_block(L, V, Z, Y, nt, 2);  // next block, in Y's storage
-    float2* nv = Y;
+    orth_block<T>(L, V, Z, Y, nt, 2);  // next block, in Y's storage
+    V2<T>* nv = Y;
     Y = V;
     F = Z;
     V = nv;
@@ -449,32 +507,32 @@ __global__ void __launch_bounds__(NTH) k_eigB_sub(const DevChan* __restrict__ ch
   // canonical phase of each kept column: its largest-modulus entry (lowest row on ties)
   // becomes real positive
   if (t < n) {
-    float best = -1.f;
-    float2 bv = make_float2(1.f, 0.f);
+    T best = -1;
+    V2<T> bv = mk<T>(1, 0);
     for (int i = 0; i < nt; ++i) {
-      const float2 v = Z[(int64_t)t * nt + i];
-      const float mag = v.x * v.x + v.y * v.y;
+      const V2<T> v = Z[(int64_t)t * nt + i];
+      const T mag = v.x * v.x + v.y * v.y;
       if (mag > best) {
         best = mag;
         bv = v;
       }
     }
-    const float a = __builtin_sqrtf(bv.x * bv.x + bv.y * bv.y);
-    L.ph[t][0] = (a > 0.f) ? bv.x / a : 1.f;
-    L.ph[t][1] = (a > 0.f) ? -bv.y / a : 0.f;
+    const T a = sqrt_t(bv.x * bv.x + bv.y * bv.y);
+    L.ph[t][0] = (a > 0) ? bv.x / a : T(1);
+    L.ph[t][1] = (a > 0) ? -bv.y / a : T(0);
   }
   __syncthreads();
   float2* Bc = B + ch.b;
   for (int e = t; e < nt * n; e += NTH) {
     const int i = e / n, j = e % n;
-    const float2 v = Z[(int64_t)j * nt + i];
-    const float pr = L.ph[j][0], pi = L.ph[j][1];
-    Bc[e] = make_float2(v.x * pr - v.y * pi, v.x * pi + v.y * pr);
+    const V2<T> v = Z[(int64_t)j * nt + i];
+    const T pr = L.ph[j][0], pi = L.ph[j][1];
+    Bc[e] = make_float2((float)(v.x * pr - v.y * pi), (float)(v.x * pi + v.y * pr));
   }
   if (t == 0) {
     double ls = 0.0;
     for (int j = 0; j < n; ++j) ls += (double)L.e.lam[L.e.src[j]];
-    wsd_s(ws, ch.w_scal)[2] = ls;
+    reinterpret_cast<double*>(ws + ch.w_scal)[2] = ls;
     uint32_t bits = (conv && jconv) ? 0u : GT_DEV_EIG_SWEEPS;
     if (!(ls == ls) || !(res == res) || ls > 1e300 || ls < -1e300) bits |= GT_DEV_NONFINITE;
     if (bits && status) atomicOr(reinterpret_cast<unsigned int*>(status + blockIdx.x), bits);
@@ -484,8 +542,12 @@ __global__ void __launch_bounds__(NTH) k_eigB_sub(const DevChan* __restrict__ ch
 gt_status launch_eigB_sub(const LaunchCtx& L, float2* B, int32_t* status, int warm) {
   const int max_iter = warm ? 40 : 100;
   prof_begin("k_eigB_sub", L.stream);
-  hipLaunchKernelGGL(k_eigB_sub, dim3(L.n_channels), dim3(NTH), 0, L.stream, L.d_chans, L.ws, B,
-                     status, warm, max_iter);
+  if (L.eig_fp64)
+    hipLaunchKernelGGL(k_eigB_sub<double>, dim3(L.n_channels), dim3(NTH), 0, L.stream, L.d_chans,
+                       L.ws, B, status, warm, max_iter);
+  else
+    hipLaunchKernelGGL(k_eigB_sub<float>, dim3(L.n_channels), dim3(NTH), 0, L.stream, L.d_chans,
+                       L.ws, B, status, warm, max_iter);
   prof_end(L.stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {

@@ -31,8 +31,10 @@ struct DevChan {
   int64_t w_S3;    // [ngroups][gs][gs]   c64   per-group mode-3 Gram
   int64_t w_VA;    // [16][16]            c64   last mode-1 eigenbasis (padded)
   int64_t w_VB;    // [64][max(64,nt)]    c64   last mode-2 eigenbasis (padded; for nt > 64 the
-                   //                           64-column Ritz block, column-major)
-  int64_t w_VS;    // [2][64][nt]         c64   subspace-iteration buffers (nt > 64 only)
+                   //                           64-column Ritz block, column-major, c128 under
+                   //                           the FP64 eigensolve)
+  int64_t w_VS;    // [2][64][nt]         c64   subspace-iteration buffers (nt > 64 only; c128
+                   //                           under the FP64 eigensolve)
   int64_t w_Xq;    // [2][nsc][nr][nt][2] u16   16-bit copy of X (hi, lo) for the precision form
   int64_t w_VC;    // [ngroups][32][32]   c64   last mode-3 eigenbases (padded)
   int64_t w_lamg;  // [ngroups] double          per-group sums (norms, eigenvalue sums)

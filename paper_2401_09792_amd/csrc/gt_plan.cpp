@@ -213,8 +213,11 @@ gt_status gt_plan_create(const gt_channel_desc* descs, int32_t n_channels, const
     ch.w_S2 = take(c8 * ch.nt * ch.nt);
     ch.w_S3 = take(c8 * ch.ngroups * ch.gs * ch.gs);
     ch.w_VA = take(c8 * 16 * 16);
-    ch.w_VB = take(c8 * 64 * std::max(64, ch.nt));
-    ch.w_VS = take(ch.nt > 64 ? c8 * 2 * 64 * ch.nt : 8);
+    {  // eigenbasis buffers: complex FP32, or FP64 for the subspace iteration's FP64 form
+      const int64_t cv = (ch.nt > 64 && o.eig_fp64) ? 16 : 8;
+      ch.w_VB = take(cv * 64 * std::max(64, ch.nt));
+      ch.w_VS = take(ch.nt > 64 ? cv * 2 * 64 * ch.nt : 8);
+    }
     ch.w_Xq = take(o.ttm_prec == GT_TTM_FP32 ? 8
                    : (o.ttm_prec == GT_TTM_SPLIT_BF16 ? 8 : 4) * (int64_t)ch.nsc * ch.nr * ch.nt);
     ch.w_VC = take(c8 * ch.ngroups * 32 * 32);
@@ -303,8 +306,6 @@ gt_status gt_tucker_fit(const gt_plan* plan, const void* X, void* A, void* B, vo
   gt_status st = check_ws(plan, ws, ws_bytes);
   if (st != GT_OK) return st;
   if (!X || !A || !B || !C || !G) return GT_ERR_ARG;
-  // wide arrays (nt > 64) use the FP32 subspace-iteration eigensolver only
-  if (plan->max_nt > kMaxNt && plan->opt.eig_fp64) return GT_ERR_UNSUPPORTED;
   LaunchCtx L = make_ctx(plan, ws, stream);
   // 16-bit contractions take K steps of 8 reals: every nt a multiple of 4
   if (plan->opt.ttm_prec != GT_TTM_FP32) {

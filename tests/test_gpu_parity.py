@@ -66,9 +66,9 @@ def test_reconstruct_matches_oracle(gpu_lib, small_case):
     assert np.linalg.norm(xh - Xh) <= 1e-5 * np.linalg.norm(Xh)
 
 
-def _gpu_fit_and_check(api, X, gs, m, n, p, ns, iters, orc=None, xhat_tol=1e-4):
+def _gpu_fit_and_check(api, X, gs, m, n, p, ns, iters, orc=None, xhat_tol=1e-4, **plan_kw):
     nsc, nr, nt = X.shape
-    plan = _plan(api, [desc(nr, nt, nsc, gs, m, n, p, ns)], iters=iters)
+    plan = _plan(api, [desc(nr, nt, nsc, gs, m, n, p, ns)], iters=iters, **plan_kw)
     res = plan.fit(dev_c64(X))
     torch.cuda.synchronize()
     ht, xh = plan.reconstruct(res["A"], res["B"], res["C"], res["G"])

@@ -12,7 +12,7 @@ import pytest
 import torch
 
 import synthgen
-from oracle import metrics, tucker
+from oracle import metrics, sinr as osinr, tucker
 from tests.gpu_util import announce, crandn, desc, dev_c64, host, unpack
 from tests.test_gpu_parity import _gpu_fit_and_check
 
@@ -102,3 +102,25 @@ def test_fit_wide_full_size_properties(gpu_lib):
     assert abs(resid - tr[-1]) <= 1e-5 * nx, (resid / nx, tr[-1] / nx)
     # the 16-path channel is nearly representable at ranks (12, 32, 12)
     assert metrics.nmse(X, Xh) < 0.05
+
+
+@pytest.mark.parametrize("shape", [
+    # (nr, nt, nsc, paths, K dB, gs, m, n, p, ns, iters, seed)
+    (8, 64, 60, 8, 6.0, 12, 8, 16, 12, 4, 6, 81),      # Jacobi mode-2 eigensolve in FP64
+    (16, 256, 96, 16, 3.0, 12, 12, 32, 12, 8, 6, 83),  # subspace iteration in FP64
+])
+def test_fit_eig_fp64(gpu_lib, shape):
+    # the FP64 Gram eigensolve option against the FP64 oracle: the fit bars, and compressed
+    # SINR within 0.05 dB of the oracle's
+    nr, nt, nsc, L, k_db, gs, m, n, p, ns, iters, seed = shape
+    announce(f"fit eig fp64 {shape}")
+    X = _generator_channel(seed, nr, nt, nsc, L, k_db)
+    plan, res, orc = _gpu_fit_and_check(gpu_lib, X, gs, m, n, p, ns, iters, xhat_tol=1e-4,
+                                        eig_fp64=True)
+    s2 = synthgen.snr_to_sigma2([10.0])
+    Ht_o, _ = tucker.reconstruct(orc["A"], orc["B"], orc["C"], orc["G"], gs)
+    ref = osinr.sinr(Ht_o, s2, ns)
+    sg = host(plan.sinr(res["C"], res["G"], s2))[:, :, :ns]
+    err = np.abs(10 * np.log10(sg) - 10 * np.log10(ref))
+    print(f"[eig fp64] {shape[:3]}: max SINR error {err.max():.3e} dB")
+    assert err.max() <= 0.05, err.max()
