@@ -198,7 +198,9 @@ def time_forms(api, synthgen, cfg, X, B, s2, ms_fp32, sg_fp32, torch, steps):
         workload="64 x (8 x 128 x 1632), ranks (8, 24, 12), Ns 4, 10 dB, Adam lr 3e-3",
         steps_per_s=1e3 / ms, ms_per_step=ms, loss_first=float(losses[0]),
         loss_last=float(losses[-1]))
-    # the 16 x 256 x 3276 workload (ranks (12, 32, 12)): 8 channels per batch
+    # precision form on the 16 x 256 x 3276 workload (16 paths, ranks (12, 32, 12), Ns 8 at
+    # 10 dB), 8 channels per batch: fit + SINR for FP32, the three 16-bit contraction forms and
+    # the FP64 Gram eigensolve, SINR error against the plain FP32 output of the same batch
     wcfg = synthgen.CONFIGS["wide"]
     nw = 8
     xs = []
@@ -208,12 +210,72 @@ def time_forms(api, synthgen, cfg, X, B, s2, ms_fp32, sg_fp32, torch, steps):
                                                dtype=torch.complex64).reshape(-1))
     Xw = torch.cat(xs)
     del xs
-    planw = api.Plan([api.desc_from_config(wcfg)] * nw, iters=wcfg.iters)
-    fw = planw.empty_factors()
-    ms_w = timed(lambda: planw.fit(Xw, factors=fw, trace=False), 1)
-    forms["fit_16x256x3276"] = dict(
-        workload="8 x (16 x 256 x 3276), 16 paths, groups of 12, ranks (12, 32, 12), 20 sweeps",
-        fits_per_s=nw / (ms_w / 1e3), ms_per_fit_batch=ms_w)
+    ws2 = [float(v) for v in synthgen.snr_to_sigma2(wcfg.snr_db)]
+    wide = {}
+    sg_ref = None
+    for name, kw in (("fp32", {}), ("bf16", dict(ttm_prec="bf16")), ("fp16", dict(ttm_prec="fp16")),
+                     ("split_bf16", dict(ttm_prec="split_bf16")), ("fp32_eig_fp64", dict(eig_fp64=True))):
+        planw = api.Plan([api.desc_from_config(wcfg)] * nw, iters=wcfg.iters, **kw)
+        fw = planw.empty_factors()
+        outw = {}
+
+        def step_w():
+            r = planw.fit(Xw, factors=fw, trace=False)
+            outw["sg"] = planw.sinr(r["C"], r["G"], ws2)
+            outw["st"] = r["status"]
+
+        ms_w = timed(step_w, 2)
+        sgw = outw["sg"][:, :, :wcfg.ns].cpu().numpy()
+        if sg_ref is None:
+            sg_ref = sgw
+        live = (sgw > 0) & (sg_ref > 0)
+        wide[name] = dict(fits_per_s=nw / (ms_w / 1e3), ms_per_fit_batch=ms_w,
+                          max_sinr_err_db_vs_fp32=float(np.abs(10 * np.log10(sgw[live])
+                                                               - 10 * np.log10(sg_ref[live])).max()),
+                          status_ok=bool((outw["st"] == 0).all()))
+        del planw, fw
+    forms["precision_16x256x3276"] = dict(
+        workload="8 x (16 x 256 x 3276), 16 paths, K 3 dB, groups of 12, ranks (12, 32, 12), "
+                 "20 sweeps, fit + SINR (Ns 8, 10 dB)", **wide)
+    del Xw
+    # batched form: 512 channels of uneven shapes (nr 4/8/16, nt 32..256, nsc 624..3276, groups
+    # of 12 or 24, ranks up to (nr, nt / 4, 12)) in one plan, fit + SINR captured in one graph
+    specs = synthgen.heterogeneous_batch(512)
+    descs = [dict(nr=d["nr"], nt=d["nt"], nsc=d["nsc"], group_size=d["group_size"], m=d["m"],
+                  n=d["n"], p=d["p"], ns=d["ns"]) for d in specs]
+    Xb = torch.cat([synthgen.build_channel_torch(d["paths"], d["nr"], d["nt"], d["nsc"], dev,
+                                                 dtype=torch.complex64).reshape(-1) for d in specs])
+    del specs
+    planb = api.Plan(descs, iters=20)
+    fb = planb.empty_factors()
+    bs2 = [float(v) for v in synthgen.snr_to_sigma2([10.0])]
+    sgb = torch.empty((1, planb.totals.sc, planb.ns_max), dtype=torch.float32, device=dev)
+    stb = {}
+
+    def step_b():
+        r = planb.fit(Xb, factors=fb, trace=False)
+        planb.sinr(fb["C"], fb["G"], bs2, out=sgb)
+        stb["st"] = r["status"]
+
+    ms_eager = timed(step_b, 2)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step_b()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    gb = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gb):
+        step_b()
+    ms_graph = timed(gb.replay, 2)
+    forms["batch_512_heterogeneous"] = dict(
+        workload="512 channels, nr {4,8,16}, nt {32,64,128,256}, nsc {624,1632,3276}, 4..16 paths, "
+                 "groups of 12/24, ranks up to (nr, nt/4, 12), 20 sweeps, fit + SINR (10 dB)",
+        fits_per_s_graph=512 / (ms_graph / 1e3), ms_per_batch_graph=ms_graph,
+        fits_per_s_eager=512 / (ms_eager / 1e3), ms_per_batch_eager=ms_eager,
+        subcarriers=int(planb.totals.sc), x_bytes=int(Xb.numel() * 8),
+        status_ok=bool((stb["st"] == 0).all()))
+    del gb, planb, fb, Xb
     return forms
 
 
@@ -293,10 +355,12 @@ def main():
 
     # live per-kernel durations over the timed region
     names = ["k_eigA", "k_eigB", "k_eigC", "k_gram_rows", "k_reduce_S1", "k_reduce_S2",
-             "k_reduce_S2_mfma", "k_init_group", "k_init_group_lds", "k_gram_x_mfma", "k_Y", "k_W", "k_T", "k_stepA_group", "k_Yh",
-             "k_S3", "k_core", "k_objC", "k_trace", "k_norm_total", "k_fused_t",
-             "k_fused_t_mfma", "k_fused_z", "k_fused_b", "k_fused_b_mfma", "k_fused_b_mm", "k_eigB_sub", "k_reconstruct",
-             "k_sinr_lane", "k_sinr", "k_sinr_bwd_lane", "k_sinr_bwd", "k_sinr_bwd_reduce"]
+             "k_reduce_S2_mfma", "k_init_group", "k_init_group_lds", "k_gram_x_mfma",
+             "k_stepA_group", "k_S3", "k_core", "k_objC", "k_trace", "k_norm_total", "k_fused_t",
+             "k_fused_t_mfma", "k_fused_z", "k_fused_b", "k_fused_b_mfma", "k_fused_b_mm",
+             "k_eigB_sub", "k_rows_times_b", "k_w_rows", "k_yh_from_t", "k_gram_rows_st",
+             "k_reduce_S2_st", "k_reconstruct", "k_sinr_lane", "k_sinr", "k_sinr_bwd_lane",
+             "k_sinr_bwd", "k_sinr_bwd_reduce"]
     kern = {}
     for nm in names:
         ms, cnt = api.profile_query(nm)
