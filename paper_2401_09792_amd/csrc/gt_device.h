@@ -68,6 +68,29 @@ struct Num<double> {
   static __device__ __forceinline__ double zero_stream() { return 1.0e-6; }
 };
 
+// Channel of block b in a compact grid: the c with off[c] <= b < off[c + 1] (off holds the
+// prefix sums of the channels' block counts, off[0] = 0).
+__device__ __forceinline__ int tile_channel(const int32_t* __restrict__ off, int n_channels, int b) {
+  int lo = 0, hi = n_channels;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= b)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Workgroups are dealt to the chip's 8 XCDs round-robin by block index; this order hands each
+// XCD a contiguous range of logical tiles (total of them, grid 8 ceil(total / 8)), so that
+// neighbouring tiles sharing input rows meet in one XCD's L2.  Returns -1 for the padding.
+__device__ __forceinline__ int xcd_tile(int b, int total) {
+  const int per = (total + 7) / 8;
+  const int t = (b % 8) * per + b / 8;
+  return t < total ? t : -1;
+}
+
 // Orders the wave's LDS accesses: everything before is visible to every lane after.
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -15,6 +15,8 @@
 #include "gt_device.h"
 #include "gt_internal.h"
 
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
 namespace gt {
 
 #define CH_BEGIN(ch_index)                   \
@@ -509,23 +511,72 @@ __global__ void __launch_bounds__(256) k_stepA_group(const DevChan* __restrict__
   if (o < nr * nr) st(wsp(ws, ch.w_S1p) + (int64_t)it.g * nr * nr + o, acc[0]);
 }
 
-// S3_g[s,t] = <Yh_s, Yh_t> for the subcarriers of each group
+// S3_g[s][t] = sum_e conj(Yh_t[e]) Yh_s[e] over the subcarriers of each group, on matrix cores:
+// rows s (one 32-row tile), columns (t, re/im) in one or two 32-wide tiles, K = (e, re/im)
+// with e over the m n entries; the K range is split over the four waves and their partial
+// tiles are summed in a fixed order.  Row s, column (t, 0) takes Re, (t, 1) Im: B operand
+// (Re, Im)[k] of Yh_t[e] for part 0 and (-Im, Re)[k] for part 1.
 __global__ void __launch_bounds__(256) k_S3(const DevChan* __restrict__ chans,
                                             const GroupItem* __restrict__ items, char* ws) {
+  __shared__ float part[4][2][1024];
   const GroupItem it = items[blockIdx.x];
-  CH_BEGIN(it.ch);
+  const DevChan& ch = chans[it.ch];
   const int gs = ch.gs;
   const int s0 = it.g * gs;
   const int sz = min(gs, ch.nsc - s0);
   const int mn = ch.m * ch.n;
-  const float2* Yh = wsp(ws, ch.w_Yh) + (int64_t)s0 * mn;
+  const float* Yh = reinterpret_cast<const float*>(wsp(ws, ch.w_Yh) + (int64_t)s0 * mn);
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, h = lane / 32, c32 = lane % 32;
+  const int nct = gs <= 16 ? 1 : 2;
+  const bool rv = c32 < sz;
+  const float* ya = Yh + (int64_t)min(c32, sz - 1) * 2 * mn + h;
+  const float* yb[2];
+  float bsgn[2];
+  bool bv[2];
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct) {
+    const int c = 32 * ct + c32, t = c >> 1, pt = c & 1;
+    bv[ct] = t < sz;
+    bsgn[ct] = (pt == 1 && h == 0) ? -1.f : 1.f;
+    yb[ct] = Yh + (int64_t)min(t, sz - 1) * 2 * mn + (pt ^ h);
+  }
+  f32x16 acc[2];
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[ct][r] = 0.f;
+  const int kq = (mn + 3) / 4, e0 = wave * kq, e1 = min(mn, e0 + kq);
+  for (int e = e0; e < e1; e += 4) {
+    float av[4], b0[4], b1[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const int ee = min(e + d, e1 - 1);
+      const bool ok = e + d < e1;
+      const float x = ya[2 * ee], y0 = yb[0][2 * ee], y1 = yb[1][2 * ee];
+      av[d] = (ok && rv) ? x : 0.f;
+      b0[d] = (ok && bv[0]) ? bsgn[0] * y0 : 0.f;
+      b1[d] = (ok && bv[1]) ? bsgn[1] * y1 : 0.f;
+    }
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[d], b0[d], acc[0], 0, 0, 0);
+      if (nct == 2) acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[d], b1[d], acc[1], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct)
+    if (ct < nct)
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        part[wave][ct][(8 * (r / 4) + 4 * h + (r % 4)) * 32 + c32] = acc[ct][r];
+  __syncthreads();
   float2* S3 = wsp(ws, ch.w_S3) + (int64_t)it.g * gs * gs;
-  for (int o = threadIdx.x; o < gs * gs; o += blockDim.x) {
-    const int s = o / gs, t = o % gs;
-    Cx<float> acc{0.f, 0.f};
-    if (s < sz && t < sz)
-      for (int e = 0; e < mn; ++e) cfmac(acc, ld(Yh + (int64_t)t * mn + e), ld(Yh + (int64_t)s * mn + e));
-    st(S3 + o, acc);
+  for (int o = tid; o < gs * gs; o += 256) {
+    const int si = o / gs, t = o % gs, ct = t >> 4, col = (2 * t) & 31;
+    const int ix = si * 32 + col;
+    const float re = (part[0][ct][ix] + part[1][ct][ix]) + (part[2][ct][ix] + part[3][ct][ix]);
+    const float im = (part[0][ct][ix + 1] + part[1][ct][ix + 1]) + (part[2][ct][ix + 1] + part[3][ct][ix + 1]);
+    S3[o] = make_float2(re, im);
   }
 }
 
@@ -643,13 +694,14 @@ static gt_status eig_all(const LaunchCtx& L, int which, float2* A, float2* B, fl
       if (st != GT_OK) return st;
     }
   } else {
-    if (L.max_gs <= 16) {
-      GT_LAUNCH((k_eigC<T, 16>), dim3(cdiv(L.total_groups, 4)), dim3(64), L.d_chans, L.d_groups,
-                L.total_groups, L.ws, C, status, warm);
-    } else {
-      GT_LAUNCH((k_eigC<T, 32>), dim3(cdiv(L.total_groups, 2)), dim3(64), L.d_chans, L.d_groups,
-                L.total_groups, L.ws, C, status, warm);
-    }
+    // groups of up to 16 subcarriers on 16-lane solvers, larger ones on 32-lane solvers
+    const int ns = L.n_small_groups, nl = L.total_groups - L.n_small_groups;
+    if (ns > 0)
+      GT_LAUNCH((k_eigC<T, 16>), dim3(cdiv(ns, 4)), dim3(64), L.d_chans, L.d_groups_by_size, ns,
+                L.ws, C, status, warm);
+    if (nl > 0)
+      GT_LAUNCH((k_eigC<T, 32>), dim3(cdiv(nl, 2)), dim3(64), L.d_chans, L.d_groups_by_size + ns, nl,
+                L.ws, C, status, warm);
   }
   return GT_OK;
 }

@@ -1289,15 +1289,17 @@ __device__ __forceinline__ void upper_tile(int k, int T, int& I, int& J) {
 constexpr int kGK = 16, kGP = 20;  // rows per chunk, LDS column stride (conflict-free b128 reads)
 
 __global__ void __launch_bounds__(256) k_gram_rows_st(const DevChan* __restrict__ chans,
-                                                      const float2* __restrict__ X, char* ws,
-                                                      int which, int nst_max) {
+                                                      const int32_t* __restrict__ toff,
+                                                      int n_channels, const float2* __restrict__ X,
+                                                      char* ws, int which) {
   __shared__ float4 sbuf4[2 * 2 * 128 * kGP / 4];  // [buffer][A, B][column][row]
   float* sbuf = reinterpret_cast<float*>(sbuf4);
-  const DevChan& ch = chans[blockIdx.y];
+  const int cidx = tile_channel(toff, n_channels, blockIdx.x);
+  const int local = blockIdx.x - toff[cidx];
+  const DevChan& ch = chans[cidx];
   const int nt = ch.nt, nc = 2 * nt;
   const int S = (nc + 127) / 128, nst = S * (S + 1) / 2;
-  const int st = blockIdx.x % nst_max, split = blockIdx.x / nst_max;
-  if (st >= nst || split >= ch.nsplit) return;
+  const int st = local % nst, split = local / nst;
   int SI, SJ;
   upper_tile(st, S, SI, SJ);
   const float* M;
@@ -1406,27 +1408,32 @@ __global__ void __launch_bounds__(256) k_gram_rows_st(const DevChan* __restrict_
       }
 }
 
-// S2 (nt x nt complex) = sum over splits of the interleaved real Gram above (super-tiles of the
-// lower triangle by symmetry): Re S2[j][k] = P[2j][2k] + P[2j+1][2k+1],
-// Im S2[j][k] = P[2j][2k+1] - P[2j+1][2k].
-__global__ void k_reduce_S2_st(const DevChan* __restrict__ chans, char* ws) {
-  const DevChan& ch = chans[blockIdx.y];
+// S2 (nt x nt complex) = sum over splits of the interleaved real Gram above:
+// Re S2[j][k] = P[2j][2k] + P[2j+1][2k+1], Im S2[j][k] = P[2j][2k+1] - P[2j+1][2k].  Only
+// entries whose real rows lie in a super-tile row at or above their columns' are read (the
+// computed part of P, row-contiguous); the entries below are written as the conjugates.
+__global__ void k_reduce_S2_st(const DevChan* __restrict__ chans, const int32_t* __restrict__ toff,
+                               int n_channels, char* ws) {
+  const int cidx = tile_channel(toff, n_channels, blockIdx.x);
+  const DevChan& ch = chans[cidx];
   const int nt = ch.nt;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = (blockIdx.x - toff[cidx]) * blockDim.x + threadIdx.x;
   if (e >= nt * nt) return;
   const int j = e / nt, k = e % nt;
+  if ((j >> 6) > (k >> 6)) return;  // super-tile row of 2 j below that of 2 k
   const int W = 128 * ((2 * nt + 127) / 128);
   const float* P = reinterpret_cast<const float*>(ws + ch.w_S2p);
-  auto at = [&](const float* Q, int a, int b) {
-    return ((a >> 7) <= (b >> 7)) ? Q[(int64_t)a * W + b] : Q[(int64_t)b * W + a];
-  };
   float re = 0.f, im = 0.f;
   for (int sp = 0; sp < ch.nsplit; ++sp) {
     const float* Q = P + (int64_t)sp * W * W;
-    re += at(Q, 2 * j, 2 * k) + at(Q, 2 * j + 1, 2 * k + 1);
-    im += at(Q, 2 * j, 2 * k + 1) - at(Q, 2 * j + 1, 2 * k);
+    const float2 r0 = *reinterpret_cast<const float2*>(Q + (int64_t)(2 * j) * W + 2 * k);
+    const float2 r1 = *reinterpret_cast<const float2*>(Q + (int64_t)(2 * j + 1) * W + 2 * k);
+    re += r0.x + r1.y;
+    im += r0.y - r1.x;
   }
-  reinterpret_cast<float2*>(ws + ch.w_S2)[e] = make_float2(re, im);
+  float2* S2 = reinterpret_cast<float2*>(ws + ch.w_S2);
+  S2[e] = make_float2(re, im);
+  if ((j >> 6) < (k >> 6)) S2[(int64_t)k * nt + j] = make_float2(re, -im);
 }
 
 // T_s = H_s B (nr x n) for all subcarriers, as a product over the rows (s, i) of X, each row
@@ -1436,18 +1443,22 @@ __global__ void k_reduce_S2_st(const DevChan* __restrict__ chans, char* ws) {
 // 16-byte aligned rows, step 4 u + v takes k' = 8 u + 4 half + v in lane half (16 contiguous
 // bytes per lane per four steps); otherwise step t takes k' = 2 t + half.
 __global__ void __launch_bounds__(256) k_rows_times_b(const DevChan* __restrict__ chans,
-                                                      const float2* __restrict__ X,
-                                                      const float2* __restrict__ B, char* ws,
-                                                      int tiles_per_block) {
+                                                      const int32_t* __restrict__ toff,
+                                                      int n_channels, const float2* __restrict__ X,
+                                                      const float2* __restrict__ B, char* ws) {
   extern __shared__ float bts[];  // [2 nt][32]
-  const DevChan& ch = chans[blockIdx.z];
+  constexpr int tiles_per_block = kTRowTiles;
+  const int bt = xcd_tile(blockIdx.x, toff[n_channels]);  // column tiles of a row block together
+  if (bt < 0) return;
+  const int cidx = tile_channel(toff, n_channels, bt);
+  const int local = bt - toff[cidx];
+  const DevChan& ch = chans[cidx];
   const int nt = ch.nt, n = ch.n;
-  const int ctile = blockIdx.y;
-  if (32 * ctile >= 2 * n) return;
+  const int nct = (2 * n + 31) / 32;
+  const int ctile = local % nct;
   const int64_t nrows = (int64_t)ch.nsc * ch.nr;
   const int64_t rtiles = (nrows + 31) / 32;
-  const int64_t t0 = (int64_t)blockIdx.x * tiles_per_block;
-  if (t0 >= rtiles) return;
+  const int64_t t0 = (int64_t)(local / nct) * tiles_per_block;
   const float* in = reinterpret_cast<const float*>(X + ch.x);
   float2* out = reinterpret_cast<float2*>(ws + ch.w_T);
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, half = lane / 32, col = lane % 32;
@@ -1510,18 +1521,23 @@ __global__ void __launch_bounds__(256) k_rows_times_b(const DevChan* __restrict_
 // single step (nt % 8 == 4) takes k' = 8 t + 4 h + v.
 template <int PREC>
 __global__ void __launch_bounds__(256) k_rows_times_b_lp(const DevChan* __restrict__ chans,
-                                                         const float2* __restrict__ B, char* ws,
-                                                         int tiles_per_block) {
+                                                         const int32_t* __restrict__ toff,
+                                                         int n_channels,
+                                                         const float2* __restrict__ B, char* ws) {
   extern __shared__ unsigned short bq[];  // [NQ][32][2 nt + 4]
   constexpr int NQ = PREC == 3 ? 2 : 1;
-  const DevChan& ch = chans[blockIdx.z];
+  constexpr int tiles_per_block = kTRowTiles;
+  const int bt = xcd_tile(blockIdx.x, toff[n_channels]);  // column tiles of a row block together
+  if (bt < 0) return;
+  const int cidx = tile_channel(toff, n_channels, bt);
+  const int local = bt - toff[cidx];
+  const DevChan& ch = chans[cidx];
   const int nt = ch.nt, n = ch.n, nc = 2 * nt, sd = nc + 4;
-  const int ctile = blockIdx.y;
-  if (32 * ctile >= 2 * n) return;
+  const int nct = (2 * n + 31) / 32;
+  const int ctile = local % nct;
   const int64_t nrows = (int64_t)ch.nsc * ch.nr;
   const int64_t rtiles = (nrows + 31) / 32;
-  const int64_t t0 = (int64_t)blockIdx.x * tiles_per_block;
-  if (t0 >= rtiles) return;
+  const int64_t t0 = (int64_t)(local / nct) * tiles_per_block;
   const unsigned short* Xh = reinterpret_cast<const unsigned short*>(ws + ch.w_Xq);
   const int64_t xtot = nrows * nt;
   float2* out = reinterpret_cast<float2*>(ws + ch.w_T);
@@ -1612,12 +1628,15 @@ __global__ void __launch_bounds__(256) k_w_rows(const DevChan* __restrict__ chan
                                                 const float2* __restrict__ X,
                                                 const float2* __restrict__ A,
                                                 const float2* __restrict__ C, char* ws,
-                                                int nchunk_max, int qcap) {
+                                                const int32_t* __restrict__ toff, int n_channels,
+                                                int qcap) {
   extern __shared__ float hcs[];  // [2][qcap][nr][32]
-  const DevChan& ch = chans[blockIdx.y];
-  const int g = blockIdx.x / nchunk_max, jc = blockIdx.x % nchunk_max;
+  const int cidx = tile_channel(toff, n_channels, blockIdx.x);
+  const int local = blockIdx.x - toff[cidx];
+  const DevChan& ch = chans[cidx];
   const int nr = ch.nr, nt = ch.nt, m = ch.m, p = ch.p;
-  if (g >= ch.ngroups || 32 * jc >= nt) return;
+  const int nchunk = (nt + 31) / 32;
+  const int g = local / nchunk, jc = local % nchunk;
   const int s0 = g * ch.gs, sz = min(ch.gs, ch.nsc - s0), pg = min(p, sz);
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, h = lane / 32, col = lane % 32;
   const int j = 32 * jc + col;
@@ -1759,11 +1778,13 @@ __global__ void __launch_bounds__(256) k_w_rows(const DevChan* __restrict__ chan
 
 // Yh_s = A^H T_s (m x n) from T = H B, one output per thread.
 __global__ void __launch_bounds__(256) k_yh_from_t(const DevChan* __restrict__ chans,
+                                                   const int32_t* __restrict__ toff, int n_channels,
                                                    const float2* __restrict__ A, char* ws) {
-  const DevChan& ch = chans[blockIdx.y];
+  const int cidx = tile_channel(toff, n_channels, blockIdx.x);
+  const DevChan& ch = chans[cidx];
   const int nr = ch.nr, m = ch.m, n = ch.n;
   const int64_t total = (int64_t)ch.nsc * m * n;
-  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t o = (int64_t)(blockIdx.x - toff[cidx]) * blockDim.x + threadIdx.x;
   if (o >= total) return;
   const int b = (int)(o % n);
   const int64_t sa = o / n;
@@ -1803,6 +1824,10 @@ __global__ void k_reduce_S2_mfma(const DevChan* __restrict__ chans, char* ws) {
 
 // ---------------------------------------------------------------------------------------
 // host side
+
+static const int32_t* tiles_of(const LaunchCtx& L, TileKind k) {
+  return L.d_tiles + (size_t)k * (L.n_channels + 1);
+}
 
 #define GT_LAUNCH_SH(name, grid, block, shm, ...)                       \
   do {                                                                  \
@@ -1857,32 +1882,40 @@ bool fused_lowp_ok(const LaunchCtx& L) {
 
 // T = H B over all rows of X (generic path).
 gt_status launch_rows_times_b(const LaunchCtx& L, const float2* X, const float2* B) {
-  const int64_t rtiles = ((int64_t)L.max_nsc * L.max_nr + 31) / 32;
-  const int tpb = 16;
-  const dim3 grid((unsigned)((rtiles + tpb - 1) / tpb), (2 * L.max_n + 31) / 32, L.n_channels);
+  if (L.tiles_total[TK_TROWS] == 0) return GT_OK;
+  const dim3 grid(8 * ((L.tiles_total[TK_TROWS] + 7) / 8));
+  const int32_t* toff = tiles_of(L, TK_TROWS);
   if (L.ttm_prec == GT_TTM_FP32) {
-    GT_LAUNCH_SH(k_rows_times_b, grid, dim3(256), sizeof(float) * 2 * L.max_nt * 32, L.d_chans, X,
-                 B, L.ws, tpb);
+    GT_LAUNCH_SH(k_rows_times_b, grid, dim3(256), sizeof(float) * 2 * L.max_nt * 32, L.d_chans,
+                 toff, L.n_channels, X, B, L.ws);
     return GT_OK;
   }
   const int nq = L.ttm_prec == GT_TTM_SPLIT_BF16 ? 2 : 1;
   const size_t sh = sizeof(unsigned short) * nq * 32 * (2 * L.max_nt + 4);
   switch (L.ttm_prec) {
-    case GT_TTM_BF16: GT_LAUNCH_SH((k_rows_times_b_lp<1>), grid, dim3(256), sh, L.d_chans, B, L.ws, tpb); break;
-    case GT_TTM_FP16: GT_LAUNCH_SH((k_rows_times_b_lp<2>), grid, dim3(256), sh, L.d_chans, B, L.ws, tpb); break;
-    default: GT_LAUNCH_SH((k_rows_times_b_lp<3>), grid, dim3(256), sh, L.d_chans, B, L.ws, tpb); break;
+    case GT_TTM_BF16:
+      GT_LAUNCH_SH((k_rows_times_b_lp<1>), grid, dim3(256), sh, L.d_chans, toff, L.n_channels, B, L.ws);
+      break;
+    case GT_TTM_FP16:
+      GT_LAUNCH_SH((k_rows_times_b_lp<2>), grid, dim3(256), sh, L.d_chans, toff, L.n_channels, B, L.ws);
+      break;
+    default:
+      GT_LAUNCH_SH((k_rows_times_b_lp<3>), grid, dim3(256), sh, L.d_chans, toff, L.n_channels, B, L.ws);
+      break;
   }
   return GT_OK;
 }
 
 // W rows of the B-step for plans with some nt > 64.
 gt_status launch_w_rows(const LaunchCtx& L, const float2* X, const float2* A, const float2* C) {
-  const int nchunk = (L.max_nt + 31) / 32;
   const int qcap = std::min(16, L.max_p);
-  const dim3 grid((unsigned)(L.max_groups * nchunk), L.n_channels);
+  const dim3 grid(L.tiles_total[TK_WROWS]);
+  if (grid.x == 0) return GT_OK;
+  const int32_t* toff = tiles_of(L, TK_WROWS);
   const size_t sh = sizeof(float) * 2 * qcap * L.max_nr * 32;
-#define GT_WROWS(SM, PR) \
-  GT_LAUNCH_SH((k_w_rows<SM, PR>), grid, dim3(256), sh, L.d_chans, X, A, C, L.ws, nchunk, qcap)
+#define GT_WROWS(SM, PR)                                                                       \
+  GT_LAUNCH_SH((k_w_rows<SM, PR>), grid, dim3(256), sh, L.d_chans, X, A, C, L.ws, toff, \
+               L.n_channels, qcap)
 #define GT_WROWS_P(SM)                                     \
   switch (L.ttm_prec) {                                    \
     case GT_TTM_FP32: GT_WROWS(SM, 0); break;              \
@@ -1903,19 +1936,20 @@ gt_status launch_w_rows(const LaunchCtx& L, const float2* X, const float2* A, co
 }
 
 gt_status launch_yh_from_t(const LaunchCtx& L, const float2* A) {
-  const int64_t total = (int64_t)L.max_nsc * L.max_m * L.max_n;
-  GT_LAUNCH_SH(k_yh_from_t, dim3((unsigned)((total + 255) / 256), L.n_channels), dim3(256), 0,
-               L.d_chans, A, L.ws);
+  if (L.tiles_total[TK_YH] > 0)
+    GT_LAUNCH_SH(k_yh_from_t, dim3(L.tiles_total[TK_YH]), dim3(256), 0, L.d_chans,
+                 tiles_of(L, TK_YH), L.n_channels, A, L.ws);
   return GT_OK;
 }
 
 // Mode-2 Gram of X rows (which = 0) or W rows (which = 1) for plans with some nt > 64.
 gt_status launch_gram_rows_big(const LaunchCtx& L, const float2* X, int which) {
-  const int S = (2 * L.max_nt + 127) / 128, nst = S * (S + 1) / 2;
-  GT_LAUNCH_SH(k_gram_rows_st, dim3(nst * L.max_nsplit, L.n_channels), dim3(256), 0, L.d_chans, X,
-               L.ws, which, nst);
-  GT_LAUNCH_SH(k_reduce_S2_st, dim3((L.max_nt * L.max_nt + 255) / 256, L.n_channels), dim3(256), 0,
-               L.d_chans, L.ws);
+  if (L.tiles_total[TK_GRAM] > 0)
+    GT_LAUNCH_SH(k_gram_rows_st, dim3(L.tiles_total[TK_GRAM]), dim3(256), 0, L.d_chans,
+                 tiles_of(L, TK_GRAM), L.n_channels, X, L.ws, which);
+  if (L.tiles_total[TK_RED2] > 0)
+    GT_LAUNCH_SH(k_reduce_S2_st, dim3(L.tiles_total[TK_RED2]), dim3(256), 0, L.d_chans,
+                 tiles_of(L, TK_RED2), L.n_channels, L.ws);
   return GT_OK;
 }
 

@@ -48,10 +48,25 @@ struct GroupItem {
   int32_t ch, g;
 };
 
+// Compact launch grids for the generic row passes: block b of a pass belongs to the channel c
+// with tiles[kind][c] <= b < tiles[kind][c + 1] (prefix sums of the channel's block counts),
+// so that uneven batches launch no empty blocks.
+enum TileKind {
+  TK_WROWS = 0,  // W rows: ngroups x ceil(nt / 32)
+  TK_TROWS,      // T = H B: ceil(ceil(nsc nr / 32) / kTRowTiles) x ceil(2 n / 32)
+  TK_GRAM,       // mode-2 Gram super-tiles: S (S + 1) / 2 x nsplit, S = ceil(2 nt / 128)
+  TK_RED2,       // Gram reduction: ceil(nt^2 / 256)
+  TK_YH,         // Yh = A^H T: ceil(nsc m n / 256)
+  TK_COUNT
+};
+constexpr int kTRowTiles = 16;  // 32-row tiles per block of the T pass
+
 // Workspace header: where the tables sit.
 struct WsLayout {
   int64_t chans;   // DevChan[n_channels]
   int64_t groups;  // GroupItem[total_groups]
+  int64_t groups_by_size;  // GroupItem[total_groups]: groups of size <= 16 first, then the rest
+  int64_t tiles;   // int32[TK_COUNT][n_channels + 1]
   int64_t total;   // bytes
 };
 
@@ -61,8 +76,12 @@ struct LaunchCtx {
   char* ws;
   const DevChan* d_chans;     // device pointer into ws
   const GroupItem* d_groups;  // device pointer into ws
+  const GroupItem* d_groups_by_size;  // groups of size <= 16, then larger ones
+  const int32_t* d_tiles;     // [TK_COUNT][n_channels + 1] block prefix sums
+  int tiles_total[TK_COUNT];
   int n_channels;
   int total_groups;
+  int n_small_groups;         // groups of size <= 16
   int max_nr, max_nt, max_nsc, max_gs, max_m, max_n, max_p, max_ns, max_groups, max_nsplit;
   int min_nt;
   int eig_fp64;

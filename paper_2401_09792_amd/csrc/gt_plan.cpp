@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -88,6 +89,9 @@ struct gt_plan {
   int ns_max;
   int max_nr, max_nt, max_nsc, max_gs, max_m, max_n, max_p, max_ns, max_groups, max_nsplit;
   int min_nt;
+  std::vector<GroupItem> groups_by_size;
+  int n_small_groups;
+  std::vector<int32_t> tiles;  // [TK_COUNT][n_channels + 1]
 };
 
 static int64_t align256(int64_t v) { return (v + 255) & ~int64_t(255); }
@@ -193,6 +197,38 @@ gt_status gt_plan_create(const gt_channel_desc* descs, int32_t n_channels, const
   off = align256(off + (int64_t)sizeof(DevChan) * n_channels);
   p->lay.groups = off;
   off = align256(off + (int64_t)sizeof(GroupItem) * gfirst);
+  // groups ordered by size class (the mode-3 eigensolve takes 16- and 32-lane groups)
+  p->groups_by_size.clear();
+  for (const GroupItem& it : p->groups)
+    if (p->chans[it.ch].gs <= 16) p->groups_by_size.push_back(it);
+  p->n_small_groups = (int)p->groups_by_size.size();
+  for (const GroupItem& it : p->groups)
+    if (p->chans[it.ch].gs > 16) p->groups_by_size.push_back(it);
+  p->lay.groups_by_size = off;
+  off = align256(off + (int64_t)sizeof(GroupItem) * gfirst);
+  // block prefix sums of the compact grids
+  p->tiles.assign((size_t)TK_COUNT * (n_channels + 1), 0);
+  for (int c = 0; c < n_channels; ++c) {
+    const DevChan& ch = p->chans[c];
+    const int64_t rtiles = ((int64_t)ch.nsc * ch.nr + 31) / 32;
+    const int64_t S = (2 * (int64_t)ch.nt + 127) / 128;
+    const int64_t cnt[TK_COUNT] = {
+        (int64_t)ch.ngroups * ((ch.nt + 31) / 32),
+        ((rtiles + kTRowTiles - 1) / kTRowTiles) * ((2 * ch.n + 31) / 32),
+        S * (S + 1) / 2 * ch.nsplit,
+        ((int64_t)ch.nt * ch.nt + 255) / 256,
+        ((int64_t)ch.nsc * ch.m * ch.n + 255) / 256};
+    for (int k = 0; k < TK_COUNT; ++k) {
+      const int64_t v = p->tiles[(size_t)k * (n_channels + 1) + c] + cnt[k];
+      if (v > INT32_MAX) {
+        delete p;
+        return GT_ERR_SHAPE;
+      }
+      p->tiles[(size_t)k * (n_channels + 1) + c + 1] = (int32_t)v;
+    }
+  }
+  p->lay.tiles = off;
+  off = align256(off + (int64_t)sizeof(int32_t) * p->tiles.size());
   const int64_t c8 = 8;
   for (int c = 0; c < n_channels; ++c) {
     DevChan& ch = p->chans[c];
@@ -228,9 +264,12 @@ gt_status gt_plan_create(const gt_channel_desc* descs, int32_t n_channels, const
     ch.w_gBp = take(c8 * ch.ngroups * ch.nt * ch.n);
   }
   p->lay.total = off;
-  p->blob.assign((size_t)p->lay.groups + sizeof(GroupItem) * gfirst, 0);
+  p->blob.assign((size_t)p->lay.tiles + sizeof(int32_t) * p->tiles.size(), 0);
   std::memcpy(p->blob.data() + p->lay.chans, p->chans.data(), sizeof(DevChan) * n_channels);
   std::memcpy(p->blob.data() + p->lay.groups, p->groups.data(), sizeof(GroupItem) * gfirst);
+  std::memcpy(p->blob.data() + p->lay.groups_by_size, p->groups_by_size.data(),
+              sizeof(GroupItem) * gfirst);
+  std::memcpy(p->blob.data() + p->lay.tiles, p->tiles.data(), sizeof(int32_t) * p->tiles.size());
   *out = p;
   return GT_OK;
 }
@@ -270,8 +309,13 @@ static LaunchCtx make_ctx(const gt_plan* p, void* ws, void* stream) {
   L.ws = reinterpret_cast<char*>(ws);
   L.d_chans = reinterpret_cast<const DevChan*>(L.ws + p->lay.chans);
   L.d_groups = reinterpret_cast<const GroupItem*>(L.ws + p->lay.groups);
+  L.d_groups_by_size = reinterpret_cast<const GroupItem*>(L.ws + p->lay.groups_by_size);
+  L.d_tiles = reinterpret_cast<const int32_t*>(L.ws + p->lay.tiles);
   L.n_channels = (int)p->chans.size();
+  for (int k = 0; k < TK_COUNT; ++k)
+    L.tiles_total[k] = p->tiles[(size_t)k * (L.n_channels + 1) + L.n_channels];
   L.total_groups = (int)p->groups.size();
+  L.n_small_groups = p->n_small_groups;
   L.max_nr = p->max_nr;
   L.max_nt = p->max_nt;
   L.max_nsc = p->max_nsc;
