@@ -16,6 +16,8 @@
 // fixed pseudo-random unimodular Omega.
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
+
 #include "gt_device.h"
 #include "gt_internal.h"
 
@@ -112,11 +114,11 @@ __device__ T block_sum(SubLds<T>& L, T v) {
 // Y[k][i] = sum_j S[i][j] Vin[k][j]  (Vin == nullptr: the start block Omega)
 template <typename T>
 __device__ void apply_gram(SubLds<T>& L, const float2* __restrict__ S, const V2<T>* Vin, V2<T>* Y,
-                           int nt) {
+                           int nt, int i_lo = 0, int i_hi = 1 << 30) {
   constexpr int KC = SubP<T>::KC;
   const int t = threadIdx.x;
   const int bi = (t / 16) * 4, bk = (t % 16) * 4;
-  for (int i0 = 0; i0 < nt; i0 += 64) {
+  for (int i0 = i_lo; i0 < min(nt, i_hi); i0 += 64) {
     T ar[4][4], ai[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -165,7 +167,8 @@ __device__ void apply_gram(SubLds<T>& L, const float2* __restrict__ S, const V2<
 
 // H = V^H Y into L.e.kr/ki (Hermitian part)
 template <typename T>
-__device__ void rayleigh(SubLds<T>& L, const V2<T>* V, const V2<T>* Y, int nt) {
+__device__ void rayleigh(SubLds<T>& L, const V2<T>* V, const V2<T>* Y, int nt, int i_lo = 0,
+                         int i_hi = 1 << 30) {
   constexpr int KC = SubP<T>::KC;
   const int t = threadIdx.x;
   const int ba = (t / 16) * 4, bb = (t % 16) * 4;
@@ -174,11 +177,12 @@ __device__ void rayleigh(SubLds<T>& L, const V2<T>* V, const V2<T>* Y, int nt) {
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) ar[a][b] = ai[a][b] = 0;
-  for (int i0 = 0; i0 < nt; i0 += KC) {
+  const int iend = min(nt, i_hi);
+  for (int i0 = i_lo; i0 < iend; i0 += KC) {
     __syncthreads();
     for (int e = t; e < 64 * KC; e += NTH) {
       const int k = e / KC, c = e % KC, i = i0 + c;
-      const bool ok = i < nt;
+      const bool ok = i < iend;
       L.sa[k][c] = ok ? V[(int64_t)k * nt + i] : mk<T>(0, 0);
       L.sb[c][k] = ok ? Y[(int64_t)k * nt + i] : mk<T>(0, 0);
     }
@@ -229,14 +233,15 @@ __device__ void rayleigh(SubLds<T>& L, const V2<T>* V, const V2<T>* Y, int nt) {
 // Out[j][i] = sum_a In[a][i] U[a][src[j]]  (U = L.e.vr/vi: eigenvectors or R^{-1}); In may
 // equal Out (every row block is read completely before it is written)
 template <typename T>
-__device__ void rotate_block(SubLds<T>& L, const V2<T>* In, V2<T>* Out, int nt) {
+__device__ void rotate_block(SubLds<T>& L, const V2<T>* In, V2<T>* Out, int nt, int i_lo = 0,
+                             int i_hi = 1 << 30) {
   constexpr int KC = SubP<T>::KC;
   const int t = threadIdx.x;
   const int bi = (t / 16) * 4, bj = (t % 16) * 4;
   int cj[4];
 #pragma unroll
   for (int b = 0; b < 4; ++b) cj[b] = L.e.src[bj + b];
-  for (int i0 = 0; i0 < nt; i0 += 64) {
+  for (int i0 = i_lo; i0 < min(nt, i_hi); i0 += 64) {
     T ar[4][4], ai[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -444,10 +449,24 @@ __device__ T max_residual(SubLds<T>& L, const V2<T>* Z, const V2<T>* W, int nt, 
 
 }  // namespace
 
+// Workspace of the multi-block first step (float offsets from w_SP, wide channels): slice
+// partials of H = V^H S2 V and M = V^H V, then Q = R^{-1} U (M = R^H R, U the eigenvectors of
+// R^{-H} H R^{-1}), the sorted Ritz values, the slice partials of the residual norms, and the
+// flags (Cholesky accepted, Jacobi converged).
+constexpr int kSlices = 4;  // 64-row slices of nt <= 256
+struct SubWs {
+  static constexpr int part = 0;                        // [4][2][64][64] complex
+  static constexpr int q = kSlices * 2 * 64 * 64 * 2;   // [64][64] complex, column-major order
+  static constexpr int lam = q + 64 * 64 * 2;           // [64]
+  static constexpr int res = lam + 64;                  // [4][64]
+  static constexpr int flags = res + kSlices * 64;      // [2]
+  static constexpr int total = flags + 2;
+};
+
 template <typename T>
 __global__ void __launch_bounds__(NTH) k_eigB_sub(const DevChan* __restrict__ chans, char* ws,
                                                    float2* B, int32_t* status, int warm,
-                                                   int max_iter) {
+                                                   int max_iter, int resume) {
   __shared__ SubLds<T> L;
   const DevChan& ch = chans[blockIdx.x];
   const int nt = ch.nt, n = ch.n;
@@ -458,9 +477,49 @@ __global__ void __launch_bounds__(NTH) k_eigB_sub(const DevChan* __restrict__ ch
   V2<T>* P1 = reinterpret_cast<V2<T>*>(ws + ch.w_VS);
   V2<T>* P2 = P1 + (int64_t)KB * nt;
 
-  // starting orthonormal block in V
+  bool conv = false, jconv = true, done = false;
+  T res = 0;
+  V2<T>* Z = P1;
   V2<T> *V, *Y, *F;
-  if (warm) {
+  if (resume) {
+    // the multi-block first step left Ritz vectors Z in P1, S2 Z in P2, the Ritz values and
+    // the residual partials
+    const float* sp = reinterpret_cast<const float*>(ws + ch.w_SP);
+    const bool chol_ok = sp[SubWs::flags] != 0.f;
+    jconv = sp[SubWs::flags + 1] != 0.f;
+    if (t < KB) {
+      L.e.lam[t] = (T)sp[SubWs::lam + t];
+      L.e.src[t] = t;
+      T acc = 0;
+      for (int sl = 0; sl < (nt + 63) / 64; ++sl) acc += (T)sp[SubWs::res + 64 * sl + t];
+      L.rs[t] = acc;
+    }
+    __syncthreads();
+    if (chol_ok) {
+      const T th0 = L.e.lam[0];
+      T m = 0;
+      for (int k = 0; k < n; ++k)
+        if (!(L.e.lam[k] <= SubP<T>::floor * th0)) m = fmax(m, L.rs[k]);
+      const T den = th0 * th0;
+      res = (den > 0) ? sqrt_t(m / den) : (m > 0 ? T(1) : T(0));
+      if (res <= SubP<T>::tol) {
+        conv = done = true;
+        Z = P1;
+      } else {
+        orth_block<T>(L, P2, P1, P0, nt, 2);  // next block from S2 Z
+        V = P0;
+        Y = P2;
+        F = P1;
+      }
+    } else {  // the old basis was not accepted: the single-block warm start
+      jconv = true;
+      orth_block<T>(L, P0, nullptr, P1, nt, 1);
+      V = P1;
+      Y = P2;
+      F = P0;
+    }
+  } else if (warm) {
+    // starting orthonormal block in V
     orth_block<T>(L, P0, nullptr, P1, nt, 1);  // the previous Ritz basis, orthonormal to rounding
     V = P1;
     Y = P2;
@@ -472,10 +531,8 @@ __global__ void __launch_bounds__(NTH) k_eigB_sub(const DevChan* __restrict__ ch
     Y = P1;
     F = P2;
   }
-  bool conv = false, jconv = true;
-  T res = 0;
-  V2<T>* Z = F;
-  for (int it = 0; it < max_iter; ++it) {
+  if (!done) Z = F;
+  for (int it = 0; it < (done ? 0 : max_iter); ++it) {
     apply_gram<T>(L, S, V, Y, nt);
     rayleigh<T>(L, V, Y, nt);
     jconv = jacobi_herm<T, KB, 4>(L.e, r, wave, sizeof(T) == 4 ? 12 : 20, false) && jconv;
@@ -539,15 +596,222 @@ __global__ void __launch_bounds__(NTH) k_eigB_sub(const DevChan* __restrict__ ch
   }
 }
 
+// Multi-block first step of a warm FP32 call (four blocks per wide channel, one per 64-row
+// slice): Rayleigh-Ritz on the previous Ritz basis V without orthonormalising it first, as the
+// generalised problem H x = theta M x with M = V^H V = R^H R (so that V R^{-1} is the
+// orthonormal basis), then the Ritz vectors Z = V Q and S2 Z with Q = R^{-1} U.
+
+// Block (channel, slice): Y = S2 V on the slice's rows into P2, then the slice's partials of H
+// and M.
+__global__ void __launch_bounds__(NTH) k_sub_prod(const DevChan* __restrict__ chans, char* ws) {
+  __shared__ SubLds<float> L;
+  const DevChan& ch = chans[blockIdx.x / kSlices];
+  const int slice = blockIdx.x % kSlices, nt = ch.nt;
+  if (nt <= 64 || 64 * slice >= nt) return;
+  const float2* S = reinterpret_cast<const float2*>(ws + ch.w_S2);
+  const float2* P0 = reinterpret_cast<const float2*>(ws + ch.w_VB);
+  float2* P2 = reinterpret_cast<float2*>(ws + ch.w_VS) + (int64_t)KB * nt;
+  float* part = reinterpret_cast<float*>(ws + ch.w_SP) + SubWs::part + slice * 2 * 64 * 64 * 2;
+  const int lo = 64 * slice, hi = lo + 64;
+  apply_gram<float>(L, S, P0, P2, nt, lo, hi);
+  for (int w = 0; w < 2; ++w) {
+    rayleigh<float>(L, P0, w == 0 ? P2 : P0, nt, lo, hi);
+    float* dst = part + w * 64 * 64 * 2;
+    for (int e = threadIdx.x; e < 64 * 64; e += NTH) {
+      dst[2 * e] = L.e.kr[e / 64][e % 64];
+      dst[2 * e + 1] = L.e.ki[e / 64][e % 64];
+    }
+  }
+}
+
+// One block per wide channel: sums the partials, factors M = R^H R, forms H' = R^{-H} H R^{-1},
+// diagonalises it (Jacobi, eigenvalues descending) and stores Q = R^{-1} U, the Ritz values
+// and the flags.
+__global__ void __launch_bounds__(NTH) k_sub_rr(const DevChan* __restrict__ chans, char* ws) {
+  __shared__ SubLds<float> L;
+  const DevChan& ch = chans[blockIdx.x];
+  if (ch.nt <= 64) return;
+  const int t = threadIdx.x, r = t % 64, wave = t / 64;
+  float* sp = reinterpret_cast<float*>(ws + ch.w_SP);
+  const int nsl = (ch.nt + 63) / 64;
+  // M into kr/ki, H kept in registers: thread t owns entries e = t + 256 u
+  float hr[16], hi[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = t + 256 * u;
+    float ar = 0.f, ai = 0.f, mr = 0.f, mi = 0.f;
+    for (int sl = 0; sl < nsl; ++sl) {
+      const float* pp = sp + SubWs::part + sl * 2 * 64 * 64 * 2;
+      ar += pp[2 * e];
+      ai += pp[2 * e + 1];
+      mr += pp[64 * 64 * 2 + 2 * e];
+      mi += pp[64 * 64 * 2 + 2 * e + 1];
+    }
+    hr[u] = ar;
+    hi[u] = ai;
+    L.e.kr[e / 64][e % 64] = mr;
+    L.e.ki[e / 64][e % 64] = mi;
+  }
+  __syncthreads();
+  const bool chol_ok = chol_inv<float>(L);  // R^{-1} in vr/vi
+  // R^{-1} to the staging tiles, used as one [2][64][64] float area (sb follows sa)
+  static_assert(offsetof(SubLds<float>, sb) == offsetof(SubLds<float>, sa) + sizeof(L.sa) &&
+                    sizeof(L.sa) + sizeof(L.sb) >= 2 * 64 * 64 * sizeof(float),
+                "staging tiles too small for R^{-1}");
+  float* rr_ = reinterpret_cast<float*>(&L.sa[0][0]);
+  float* ri_ = rr_ + 64 * 64;
+  for (int e = t; e < 64 * 64; e += NTH) {
+    rr_[e] = L.e.vr[e / 64][e % 64];
+    ri_[e] = L.e.vi[e / 64][e % 64];
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = t + 256 * u;
+    L.e.kr[e / 64][e % 64] = hr[u];
+    L.e.ki[e / 64][e % 64] = hi[u];
+  }
+  __syncthreads();
+  // X = H R^{-1} into vr/vi
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = t + 256 * u, a = e / 64, b = e % 64;
+    float xr = 0.f, xi = 0.f;
+    for (int k = 0; k <= b; ++k) {  // R^{-1} is upper triangular
+      const float h1 = L.e.kr[a][k], h2 = L.e.ki[a][k], q1 = rr_[k * 64 + b], q2 = ri_[k * 64 + b];
+      xr += h1 * q1 - h2 * q2;
+      xi += h1 * q2 + h2 * q1;
+    }
+    hr[u] = xr;
+    hi[u] = xi;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = t + 256 * u;
+    L.e.vr[e / 64][e % 64] = hr[u];
+    L.e.vi[e / 64][e % 64] = hi[u];
+  }
+  __syncthreads();
+  // H' = R^{-H} X, Hermitian part, into kr/ki
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = t + 256 * u, a = e / 64, b = e % 64;
+    float xr = 0.f, xi = 0.f;
+    for (int k = 0; k <= a; ++k) {  // conj(R^{-1}[k][a]) X[k][b]
+      const float q1 = rr_[k * 64 + a], q2 = ri_[k * 64 + a], x1 = L.e.vr[k][b], x2 = L.e.vi[k][b];
+      xr += q1 * x1 + q2 * x2;
+      xi += q1 * x2 - q2 * x1;
+    }
+    hr[u] = xr;
+    hi[u] = xi;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = t + 256 * u;
+    L.e.kr[e / 64][e % 64] = hr[u];
+    L.e.ki[e / 64][e % 64] = hi[u];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = t + 256 * u, a = e / 64, b = e % 64;
+    hr[u] = 0.5f * (hr[u] + L.e.kr[b][a]);
+    hi[u] = 0.5f * (hi[u] - L.e.ki[b][a]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = t + 256 * u;
+    L.e.kr[e / 64][e % 64] = hr[u];
+    L.e.ki[e / 64][e % 64] = hi[u];
+  }
+  __syncthreads();
+  const bool jc = jacobi_herm<float, KB, 4>(L.e, r, wave, 12, false);
+  __syncthreads();
+  if (wave == 0) eig_sort_desc<float, KB>(L.e, r, KB);
+  __syncthreads();
+  // Q[:, j] = R^{-1} U[:, src[j]], stored column-major ([j][a])
+  float* q = sp + SubWs::q;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = t + 256 * u, j = e / 64, a = e % 64, cj = L.e.src[j];
+    float xr = 0.f, xi = 0.f;
+    for (int k = a; k < 64; ++k) {
+      const float q1 = rr_[a * 64 + k], q2 = ri_[a * 64 + k], u1 = L.e.vr[k][cj], u2 = L.e.vi[k][cj];
+      xr += q1 * u1 - q2 * u2;
+      xi += q1 * u2 + q2 * u1;
+    }
+    q[2 * e] = xr;
+    q[2 * e + 1] = xi;
+  }
+  if (t < KB) sp[SubWs::lam + t] = L.e.lam[L.e.src[t]];
+  if (t == 0) {
+    sp[SubWs::flags] = chol_ok ? 1.f : 0.f;
+    sp[SubWs::flags + 1] = jc ? 1.f : 0.f;
+  }
+}
+
+// Block (channel, slice): Z = V Q into P1 and S2 Z = Y Q in place in P2 on the slice's rows,
+// and the slice's partial residual norms ||S2 z_j - theta_j z_j||^2.
+__global__ void __launch_bounds__(NTH) k_sub_rot(const DevChan* __restrict__ chans, char* ws) {
+  __shared__ SubLds<float> L;
+  const DevChan& ch = chans[blockIdx.x / kSlices];
+  const int slice = blockIdx.x % kSlices, nt = ch.nt;
+  if (nt <= 64 || 64 * slice >= nt) return;
+  const int t = threadIdx.x;
+  float* sp = reinterpret_cast<float*>(ws + ch.w_SP);
+  if (sp[SubWs::flags] == 0.f) return;  // the resume kernel redoes the step on one block
+  const float* q = sp + SubWs::q;
+  for (int e = t; e < 64 * 64; e += NTH) {
+    L.e.vr[e % 64][e / 64] = q[2 * e];  // vr[a][j]
+    L.e.vi[e % 64][e / 64] = q[2 * e + 1];
+  }
+  if (t < KB) {
+    L.e.src[t] = t;
+    L.e.lam[t] = sp[SubWs::lam + t];
+  }
+  __syncthreads();
+  const float2* P0 = reinterpret_cast<const float2*>(ws + ch.w_VB);
+  float2* P1 = reinterpret_cast<float2*>(ws + ch.w_VS);
+  float2* P2 = P1 + (int64_t)KB * nt;
+  const int lo = 64 * slice, hi = min(nt, lo + 64);
+  rotate_block<float>(L, P0, P1, nt, lo, hi);
+  rotate_block<float>(L, P2, P2, nt, lo, hi);
+  const int j = t / 4, pt = t % 4;
+  const float th = L.e.lam[j];
+  float acc = 0.f;
+  for (int i = lo + pt; i < hi; i += 4) {
+    const float2 z = P1[(int64_t)j * nt + i], w = P2[(int64_t)j * nt + i];
+    const float dr = w.x - th * z.x, di = w.y - th * z.y;
+    acc += dr * dr + di * di;
+  }
+  acc += __shfl_xor(acc, 1, 64);
+  acc += __shfl_xor(acc, 2, 64);
+  if (pt == 0) sp[SubWs::res + 64 * slice + j] = acc;
+}
+
 gt_status launch_eigB_sub(const LaunchCtx& L, float2* B, int32_t* status, int warm) {
   const int max_iter = warm ? 40 : 100;
+  const bool multi = warm && !L.eig_fp64;
+  if (multi) {
+    prof_begin("k_sub_prod", L.stream);
+    hipLaunchKernelGGL(k_sub_prod, dim3(kSlices * L.n_channels), dim3(NTH), 0, L.stream, L.d_chans, L.ws);
+    prof_end(L.stream);
+    prof_begin("k_sub_rr", L.stream);
+    hipLaunchKernelGGL(k_sub_rr, dim3(L.n_channels), dim3(NTH), 0, L.stream, L.d_chans, L.ws);
+    prof_end(L.stream);
+    prof_begin("k_sub_rot", L.stream);
+    hipLaunchKernelGGL(k_sub_rot, dim3(kSlices * L.n_channels), dim3(NTH), 0, L.stream, L.d_chans, L.ws);
+    prof_end(L.stream);
+  }
   prof_begin("k_eigB_sub", L.stream);
   if (L.eig_fp64)
     hipLaunchKernelGGL(k_eigB_sub<double>, dim3(L.n_channels), dim3(NTH), 0, L.stream, L.d_chans,
-                       L.ws, B, status, warm, max_iter);
+                       L.ws, B, status, warm, max_iter, 0);
   else
     hipLaunchKernelGGL(k_eigB_sub<float>, dim3(L.n_channels), dim3(NTH), 0, L.stream, L.d_chans,
-                       L.ws, B, status, warm, max_iter);
+                       L.ws, B, status, warm, max_iter, multi ? 1 : 0);
   prof_end(L.stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {

@@ -35,6 +35,8 @@ struct DevChan {
                    //                           the FP64 eigensolve)
   int64_t w_VS;    // [2][64][nt]         c64   subspace-iteration buffers (nt > 64 only; c128
                    //                           under the FP64 eigensolve)
+  int64_t w_SP;    // f32 partials and small matrices of the multi-block subspace step
+                   //                           (nt > 64 only)
   int64_t w_Xq;    // [2][nsc][nr][nt][2] u16   16-bit copy of X (hi, lo) for the precision form
   int64_t w_VC;    // [ngroups][32][32]   c64   last mode-3 eigenbases (padded)
   int64_t w_lamg;  // [ngroups] double          per-group sums (norms, eigenvalue sums)
