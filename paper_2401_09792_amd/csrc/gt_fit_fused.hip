@@ -1652,20 +1652,28 @@ __global__ void __launch_bounds__(256) k_w_rows(const DevChan* __restrict__ chan
     const float v = po == 0 ? (h == 0 ? av.x : av.y) : (h == 0 ? -av.y : av.x);
     aco[i] = (i < nr && rq < m) ? v : 0.f;
   }
-  const float* xg = reinterpret_cast<const float*>(X + ch.x + (int64_t)s0 * nr * nt) + h;
+  const float2* xg = X + ch.x + (int64_t)s0 * nr * nt;
   float2* Wg = reinterpret_cast<float2*>(ws + ch.w_W) + (int64_t)g * p * m * nt;
-  const float csign = (po == 1 && h == 0) ? -1.f : 1.f;
+  // FP32 step 1 in K steps of 4: step 4 u + v takes k = (s, re/im) with s = 4 u + 2 h + v / 2
+  // and part v % 2 in lane half h, so that a lane reads whole complex entries of two
+  // subcarriers
+  constexpr int SU = (SMAX + 3) / 4;
   for (int q0 = 0; q0 < p; q0 += qcap) {
     const int q = q0 + rq;
     const bool qv = q < pg && rq < qcap;
-    const float* cg = reinterpret_cast<const float*>(C + ch.c + (int64_t)s0 * p + min(q, p - 1)) + (po ^ h);
-    float cp[PREC == 0 ? SMAX : 1];
+    float cpp[PREC == 0 ? SU : 1][4];
     if constexpr (PREC == 0)
 #pragma unroll
-      for (int s = 0; s < SMAX; ++s) {
-        const float c = cg[2 * (int64_t)min(s, sz - 1) * p];
-        cp[s] = (qv && s < sz) ? csign * c : 0.f;
-      }
+      for (int u = 0; u < SU; ++u)
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+          const int sc = 4 * u + 2 * h + w;
+          const float2 c = C[ch.c + (int64_t)(s0 + min(sc, sz - 1)) * p + min(q, p - 1)];
+          const bool ok = qv && sc < sz;
+          // row po 0: (Re C, Im C)[pi]; row po 1: (-Im C, Re C)[pi]
+          cpp[u][2 * w] = ok ? (po == 0 ? c.x : -c.y) : 0.f;
+          cpp[u][2 * w + 1] = ok ? (po == 0 ? c.y : c.x) : 0.f;
+        }
     if (q0 > 0) __syncthreads();  // the previous q tile's step 2 has read the planes
     if constexpr (PREC != 0) {
       // 1. on 16-bit operands: K step t covers subcarriers 4 t .. 4 t + 3, lane half h holding
@@ -1723,15 +1731,17 @@ __global__ void __launch_bounds__(256) k_w_rows(const DevChan* __restrict__ chan
     // 1. NI antenna tiles i0 + 4 k per pass, all loads issued before the products
     constexpr int NI = SMAX <= 12 ? 2 : 1;
     for (int i0 = wave; i0 < nr; i0 += 4 * NI) {
-      float xa[NI][SMAX];
+      float2 xa[NI][SU][2];
 #pragma unroll
       for (int k = 0; k < NI; ++k) {
         const int ic = min(i0 + 4 * k, nr - 1);
 #pragma unroll
-        for (int s = 0; s < SMAX; ++s) {
-          const int64_t sc = min(s, sz - 1);
-          xa[k][s] = xg[2 * ((sc * nr + ic) * nt + jcl)];
-        }
+        for (int u = 0; u < SU; ++u)
+#pragma unroll
+          for (int w = 0; w < 2; ++w) {
+            const int64_t sc = min(4 * u + 2 * h + w, sz - 1);
+            xa[k][u][w] = xg[(sc * nr + ic) * nt + jcl];
+          }
       }
       f32x16 acc[NI];
 #pragma unroll
@@ -1739,11 +1749,15 @@ __global__ void __launch_bounds__(256) k_w_rows(const DevChan* __restrict__ chan
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[k][r] = 0.f;
 #pragma unroll
-      for (int s = 0; s < SMAX; ++s)
-        if (s < sz)
+      for (int u = 0; u < SU; ++u)
+        if (4 * u < sz)
 #pragma unroll
-          for (int k = 0; k < NI; ++k)
-            acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(cp[s], xa[k][s], acc[k], 0, 0, 0);
+          for (int k = 0; k < NI; ++k) {
+            acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(cpp[u][0], xa[k][u][0].x, acc[k], 0, 0, 0);
+            acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(cpp[u][1], xa[k][u][0].y, acc[k], 0, 0, 0);
+            acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(cpp[u][2], xa[k][u][1].x, acc[k], 0, 0, 0);
+            acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(cpp[u][3], xa[k][u][1].y, acc[k], 0, 0, 0);
+          }
       // accumulator (lane, r): row 8 (r / 4) + 4 h + r % 4 = (q - q0, re/im), column j
 #pragma unroll
       for (int k = 0; k < NI; ++k)
