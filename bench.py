@@ -10,6 +10,11 @@ One step = one pass of the whole path over a batch of channels resident in HBM:
     per-subcarrier SINR at 4 SNRs  ->  adjoint of the SINR with respect to (C, G).
 Prints one JSON line.  `value` is Tucker fits/s of the whole step; the SINR-evaluation
 rate of the SINR kernel is reported beside it.
+
+`--workload wide` times the same step on channels of 16 x 256 x 3276 (16 paths, K = 3 dB,
+ranks (12, 32, 12), 8 streams at 10 dB), 8 channels per step, for the profiles of the
+wide-array passes; the default run is the workload above.  `--forms` adds the precision,
+graph-replay, differentiation and heterogeneous-batch forms to the default run's line.
 """
 
 from __future__ import annotations
@@ -65,11 +70,11 @@ def sinr_unit_bytes(m, n, p, gs, n_snr, ns):
     return (8 * m * n * p / gs + 8 * p) / n_snr + 4 * ns
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, workload: str = "rb273"):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy of known size), or None when the
     summary is absent or was taken on a different revision of the kernel's source file."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_rb273_traffic.txt")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -284,7 +289,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=64, help="channels per step")
+    ap.add_argument("--workload", choices=("rb273", "wide"), default="rb273",
+                    help="rb273: 8x64x3276 channels (the headline); wide: 16x256x3276 channels")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="channels per step (default 64 for rb273, 8 for wide)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=4, help="channels timed on the oracle")
     ap.add_argument("--forms", action="store_true",
@@ -306,9 +314,10 @@ def main():
     import synthgen
     from paper_2401_09792_amd import api
 
-    cfg = synthgen.CONFIGS["rb273"]
+    cfg = synthgen.CONFIGS[args.workload]
+    wide = args.workload == "wide"
     dev = torch.device("cuda:0")
-    B = args.batch
+    B = args.batch or (8 if wide else 64)
     s2 = [float(v) for v in synthgen.snr_to_sigma2(cfg.snr_db)]
     n_snr = len(s2)
 
@@ -376,7 +385,15 @@ def main():
 
     # dominant kernel with an algorithmic work model, and its roofline
     nr, nt, m, n, p, gs = cfg.nr, cfg.nt, cfg.m, cfg.n, cfg.p, cfg.group_size
+    n_sweeps = cfg.iters
     models = {
+        # wide path, per launch over the B channels: the mode-2 Gram (one launch on the rows of
+        # X for the initialisation, one per sweep on the W rows: the average over the
+        # 1 + sweeps launches), T = H B, and the W rows of the B-step
+        "k_gram_rows_st": B * CMAC * nt * (nt + 1) / 2
+        * (cfg.nsc * nr + n_sweeps * ng * p * m) / (1 + n_sweeps),
+        "k_rows_times_b": B * CMAC * cfg.nsc * nr * nt * n,
+        "k_w_rows": B * CMAC * ng * (p * gs * nr * nt + p * m * nr * nt),
         # per launch: B channels x ng groups
         "k_fused_b_mfma": B * ng * CMAC * (gs * m * nr * nt + p * gs * m * nt
                                            + p * m * nt * nt / 2),
@@ -386,14 +403,15 @@ def main():
         "k_sinr": sinr_units * sinr_unit_flops(m, n, p, cfg.ns, n_snr),
         "k_gram_rows": B * gram_rows_flops(ng, p, m, nt),
     }
-    bounds = {"k_fused_b_mfma": "mfma", "k_fused_b_mm": "mfma", "k_gram_rows": "mfma"}
+    bounds = {"k_fused_b_mfma": "mfma", "k_fused_b_mm": "mfma", "k_gram_rows": "mfma",
+              "k_gram_rows_st": "mfma", "k_rows_times_b": "mfma", "k_w_rows": "mfma"}
     ranked = sorted(((v["total_ms"], k) for k, v in kern.items() if k in models), reverse=True)
     roof = None
     if ranked:
         dom = ranked[0][1]
         ach = models[dom] / (kern[dom]["avg_us"] * 1e-6) / 1e12
         roof = dict(kernel=dom, bound=bounds.get(dom, "alu"), achieved=ach, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                    frac=ach / PEAK_FP32_TFLOPS, traffic=measured_traffic(dom),
+                    frac=ach / PEAK_FP32_TFLOPS, traffic=measured_traffic(dom, args.workload),
                     algorithmic_flops_per_launch=models[dom],
                     share_of_step=kern[dom]["total_ms"] / ms_step)
     sinr_k = kern.get("k_sinr_lane") or kern.get("k_sinr")
@@ -407,7 +425,25 @@ def main():
 
         from oracle import metrics, sinr as osinr, tucker
 
-        nsamp = max(1, args.cpu_sample)
+        info = threadpoolctl.threadpool_info()
+        threads = max([i.get("num_threads", 1) for i in info] + [1])
+        if wide:
+            # a bounded sample: the first 540 subcarriers (45 groups) of channel 0, scaled to
+            # channels of 3276 subcarriers
+            nsub = 540
+            rng = synthgen.channel_rng(cfg.seed_index, 0)
+            Xs = synthgen.build_channel(synthgen.draw_paths(rng, cfg.n_paths, cfg.k_db),
+                                        cfg.nr, cfg.nt, nsub)
+            t = time.perf_counter()
+            orc = tucker.fit(Xs, cfg.group_size, cfg.m, cfg.n, cfg.p, cfg.iters)
+            Ht_o, _ = tucker.reconstruct(orc["A"], orc["B"], orc["C"], orc["G"], cfg.group_size)
+            osinr.sinr(Ht_o, s2, cfg.ns)
+            cpu_s = time.perf_counter() - t
+            cpu = dict(value=(nsub / cfg.nsc) / cpu_s, unit="fits/s", cores=threads, kind="oracle",
+                       sample=f"first {nsub} of {cfg.nsc} subcarriers of one channel: fit + Ht + "
+                              f"SINR (no adjoint), {cpu_s:.1f} s, scaled by {nsub}/{cfg.nsc}; "
+                              "complex128 NumPy/LAPACK")
+        nsamp = 0 if wide else max(1, args.cpu_sample)
         t = time.perf_counter()
         orc0 = None
         for c in range(nsamp):
@@ -417,12 +453,14 @@ def main():
             sg_o = osinr.sinr(Ht_o, s2, cfg.ns)
             if orc0 is None:
                 orc0 = (Xc, orc, sg_o)
-        cpu_s = time.perf_counter() - t
-        info = threadpoolctl.threadpool_info()
-        threads = max([i.get("num_threads", 1) for i in info] + [1])
-        cpu = dict(value=nsamp / cpu_s, unit="fits/s", cores=threads, kind="oracle",
-                   sample=f"{nsamp} channel(s) of the workload: fit + Ht + SINR at 4 SNRs "
-                          f"(no adjoint), {cpu_s:.1f} s, complex128 NumPy/LAPACK")
+        if not wide:
+            cpu_s = time.perf_counter() - t
+            cpu = dict(value=nsamp / cpu_s, unit="fits/s", cores=threads, kind="oracle",
+                       sample=f"{nsamp} channel(s) of the workload: fit + Ht + SINR at 4 SNRs "
+                              f"(no adjoint), {cpu_s:.1f} s, complex128 NumPy/LAPACK")
+    if not args.no_cpu_baseline and not wide:
+        from oracle import metrics
+
         Xc, orc, sg_o = orc0
         sg0 = sg[:, :cfg.nsc, :cfg.ns].cpu().numpy()
         err = metrics.db_error(sg0, sg_o)
@@ -435,7 +473,7 @@ def main():
         del htg
 
     forms = None
-    if args.forms:
+    if args.forms and not wide:
         forms = time_forms(api, synthgen, cfg, X, B, s2, ms_step, sg, torch, max(args.steps, 2))
 
     line = {
@@ -451,8 +489,10 @@ def main():
         "vs_baseline": None,
         "dtype": "c64",
         "data": "synthetic",
-        "config": {"workload": "rb273: 8x64x3276 channels, groups of 12, ranks (8,16,12), "
-                               "20 sweeps, Ns=4, SNR -5/0/10/20 dB",
+        "config": {"workload": ("wide: 16x256x3276 channels, 16 paths, groups of 12, ranks "
+                                "(12,32,12), 20 sweeps, Ns=8, SNR 10 dB") if wide else
+                               ("rb273: 8x64x3276 channels, groups of 12, ranks (8,16,12), "
+                                "20 sweeps, Ns=4, SNR -5/0/10/20 dB"),
                    "channels_per_step": B, "parallelism": "single GPU"},
         "sinr_evals_per_s": sinr_rate,
         "roofline": roof,
