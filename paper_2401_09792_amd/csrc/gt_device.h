@@ -177,7 +177,10 @@ __device__ __forceinline__ bool jacobi_herm(EigLds<T, MP>& L, int r, int wave, i
   const T eps = Num<T>::eps();
   bool conv = false;
   for (int sw = 0; sw <= max_sweeps; ++sw) {
-    bool done;
+    // done: every matrix of the wave (block) has converged; gdone: this lane's matrix has.  A
+    // converged matrix takes identity rotations while the others finish, so that its result
+    // does not depend on the matrices it shares a wave with.
+    bool done, gdone;
     if (NW == 1) {
       T off = 0, dg = 0;
       for (int j = 0; j < MP; ++j) {
@@ -190,7 +193,8 @@ __device__ __forceinline__ bool jacobi_herm(EigLds<T, MP>& L, int r, int wave, i
       }
       off = group_sum<MP>(off);
       dg = group_sum<MP>(dg);
-      done = wave_all(off <= T(64) * eps * eps * dg);
+      gdone = off <= T(64) * eps * eps * dg;  // the same in every lane of the group
+      done = wave_all(gdone);
     } else {
       if (wave == 0) {
         T off = 0, dg = 0;
@@ -208,13 +212,17 @@ __device__ __forceinline__ bool jacobi_herm(EigLds<T, MP>& L, int r, int wave, i
       }
       __syncthreads();
       done = L.src[0] != 0;
+      gdone = done;
       __syncthreads();
     }
     if (done) {
       conv = true;
       break;
     }
-    if (sw == max_sweeps) break;
+    if (sw == max_sweeps) {
+      conv = gdone;
+      break;
+    }
     for (int t = 0; t < MP - 1; ++t) {
       int pos, partner;
       rr_pair<MP>(t, r, pos, partner);
@@ -224,7 +232,7 @@ __device__ __forceinline__ bool jacobi_herm(EigLds<T, MP>& L, int r, int wave, i
         T cre = L.kr[r][partner], cim = L.ki[r][partner];
         T ac = dsqrt(cre * cre + cim * cim);
         T cs = 1, sre = 0, sim = 0;
-        if (ac > T(0) && ac > eps * T(0.5) * (__builtin_fabs(a) + __builtin_fabs(b))) {
+        if (!gdone && ac > T(0) && ac > eps * T(0.5) * (__builtin_fabs(a) + __builtin_fabs(b))) {
           T z = (b - a) / (T(2) * ac);
           T az = __builtin_fabs(z);
           T tt = (az > Num<T>::big()) ? T(0.5) / az : T(1) / (az + dsqrt(T(1) + az * az));

@@ -673,6 +673,19 @@ __global__ void __launch_bounds__(256) k_core(const DevChan* __restrict__ chans,
     }                                                            \
   } while (0)
 
+// the same on the stream of another context
+#define GT_LAUNCH2(ctx, name, grid, block, ...)                      \
+  do {                                                               \
+    prof_begin(#name, (ctx).stream);                                 \
+    hipLaunchKernelGGL(name, grid, block, 0, (ctx).stream, __VA_ARGS__); \
+    prof_end((ctx).stream);                                          \
+    hipError_t e_ = hipGetLastError();                               \
+    if (e_ != hipSuccess) {                                          \
+      set_error_detail(#name, e_);                                   \
+      return GT_ERR_HIP;                                             \
+    }                                                                \
+  } while (0)
+
 static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 gt_status launch_eigB_sub(const LaunchCtx& L, float2* B, int32_t* status, int warm);
@@ -726,8 +739,24 @@ gt_status launch_fused_t(const LaunchCtx& L, const float2* X, const float2* A, c
 gt_status launch_fused_z(const LaunchCtx& L, const float2* C, float2* G, int do_a, int do_core);
 gt_status launch_fused_b(const LaunchCtx& L, const float2* X, const float2* A, const float2* C);
 
-gt_status launch_fit(const LaunchCtx& L, const float2* X, float2* A, float2* B, float2* C,
-                     float2* G, double* trace, int32_t* status, int iters, bool warm) {
+static gt_status split_fork(const LaunchCtx& L, const SplitCtx& S) {
+  if (hipEventRecord(S.fork, L.stream) != hipSuccess) return GT_ERR_HIP;
+  for (int k = 1; k < S.n; ++k)
+    if (hipStreamWaitEvent(S.parts[k].stream, S.fork, 0) != hipSuccess) return GT_ERR_HIP;
+  return GT_OK;
+}
+
+static gt_status split_join(const LaunchCtx& L, const SplitCtx& S) {
+  for (int k = 1; k < S.n; ++k) {
+    if (hipEventRecord(S.join[k - 1], S.parts[k].stream) != hipSuccess) return GT_ERR_HIP;
+    if (hipStreamWaitEvent(L.stream, S.join[k - 1], 0) != hipSuccess) return GT_ERR_HIP;
+  }
+  return GT_OK;
+}
+
+gt_status launch_fit(const LaunchCtx& L, const SplitCtx* split, const float2* X, float2* A,
+                     float2* B, float2* C, float2* G, double* trace, int32_t* status, int iters,
+                     bool warm) {
   const int nch = L.n_channels;
   const int stride = 1 + 3 * iters;
   const dim3 b256(256);
@@ -781,6 +810,52 @@ gt_status launch_fit(const LaunchCtx& L, const float2* X, float2* A, float2* B, 
     if (iters == 0) {
       if ((st = launch_fused_t(L, X, A, B, 2)) != GT_OK) return st;
       return launch_fused_z(L, C, G, 0, 1);
+    }
+    if (split) {
+      // The B-step pass runs over the whole batch; the rest of each sweep (mode-2 eigensolve,
+      // T pass, mode-3 eigensolves, Z pass, next mode-1 eigensolve) runs per part on its own
+      // stream, so that the small eigensolve launches of one part overlap the other parts'
+      // passes.
+      auto part_sweep = [&](int it, bool with_bc) -> gt_status {
+        gt_status s2;
+        if ((s2 = split_fork(L, *split)) != GT_OK) return s2;
+        for (int k = 0; k < split->n; ++k) {
+          const LaunchCtx& P = split->parts[k];
+          const int pn = P.n_channels;
+          int32_t* ps = status ? status + P.c0 : nullptr;
+          double* pt = trace ? trace + (int64_t)P.c0 * stride : nullptr;
+          const bool last = it == iters - 1;
+          const int w = (warm && it == 0) ? 0 : 1;
+          if (with_bc) {
+            if ((s2 = eig_dispatch(P, 1, A, B, C, ps, w)) != GT_OK) return s2;
+            if (pt)
+              GT_LAUNCH2(P, k_trace, dim3(cdiv(pn, 64)), dim3(64), P.d_chans, pn, P.ws, pt,
+                         stride, 2 + 3 * it, 1);
+            if ((s2 = launch_fused_t(P, X, A, B, last ? 2 : 1)) != GT_OK) return s2;
+            if ((s2 = eig_dispatch(P, 2, A, B, C, ps, w)) != GT_OK) return s2;
+            if (pt)
+              GT_LAUNCH2(P, k_trace, dim3(cdiv(pn, 64)), dim3(64), P.d_chans, pn, P.ws, pt,
+                         stride, 3 + 3 * it, 2);
+            if ((s2 = launch_fused_z(P, C, G, last ? 0 : 1, last ? 1 : 0)) != GT_OK) return s2;
+          }
+          // mode-1 eigensolve of the next sweep (of sweep 0 when called before the loop)
+          const int na = with_bc ? it + 1 : 0;
+          if (na < iters) {
+            const int wa = (warm && na == 0) ? 0 : 1;
+            if ((s2 = eig_dispatch(P, 0, A, B, C, ps, wa)) != GT_OK) return s2;
+            if (pt)
+              GT_LAUNCH2(P, k_trace, dim3(cdiv(pn, 64)), dim3(64), P.d_chans, pn, P.ws, pt,
+                         stride, 1 + 3 * na, 0);
+          }
+        }
+        return split_join(L, *split);
+      };
+      if ((st = part_sweep(0, false)) != GT_OK) return st;
+      for (int it = 0; it < iters; ++it) {
+        if ((st = launch_fused_b(L, X, A, C)) != GT_OK) return st;
+        if ((st = part_sweep(it, true)) != GT_OK) return st;
+      }
+      return GT_OK;
     }
     for (int it = 0; it < iters; ++it) {
       const int w = (warm && it == 0) ? 0 : 1;

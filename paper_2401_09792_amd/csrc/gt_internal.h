@@ -88,6 +88,17 @@ struct LaunchCtx {
   int min_nt;
   int eig_fp64;
   int ttm_prec;  // gt_ttm_prec of the plan
+  int c0 = 0;    // first channel of this context in the caller's channel numbering
+};
+
+// A fit whose batch is split into parts of consecutive channels: the parts' contexts (their
+// own tables over the same per-channel workspace, part 0 on the caller's stream) and the
+// events that fork the side streams from the caller's stream and join them back.
+struct SplitCtx {
+  int n;
+  const LaunchCtx* parts;
+  hipEvent_t fork;
+  hipEvent_t join[3];
 };
 
 // kernel timing hooks (no-ops unless profiling is on)

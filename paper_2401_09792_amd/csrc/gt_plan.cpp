@@ -14,9 +14,11 @@
 #include "gtucker.h"
 
 namespace gt {
-gt_status launch_fit(const LaunchCtx& L, const float2* X, float2* A, float2* B, float2* C, float2* G,
-                     double* trace, int32_t* status, int iters, bool warm);
+gt_status launch_fit(const LaunchCtx& L, const SplitCtx* split, const float2* X, float2* A,
+                     float2* B, float2* C, float2* G, double* trace, int32_t* status, int iters,
+                     bool warm);
 bool fused_lowp_ok(const LaunchCtx& L);
+bool fused_fit_ok(const LaunchCtx& L);
 gt_status launch_reconstruct(const LaunchCtx& L, int64_t total_sc, const float2* A, const float2* B,
                              const float2* C, const float2* G, float2* Ht, float2* Xhat);
 gt_status launch_reconstruct_bwd(const LaunchCtx& L, int64_t total_sc, const float2* A,
@@ -92,7 +94,29 @@ struct gt_plan {
   std::vector<GroupItem> groups_by_size;
   int n_small_groups;
   std::vector<int32_t> tiles;  // [TK_COUNT][n_channels + 1]
+  // The fit of a batch of 8 or more channels on the fused per-group passes runs most of each
+  // sweep as parts of consecutive channels on concurrent streams.  A part is a view: its own
+  // tables (channels, groups, grids) in a workspace region after this plan's, over the same
+  // per-channel workspace; side streams and events are made on the first fit.
+  std::vector<gt_plan*> parts;
+  std::vector<int32_t> part_c0;
+  std::vector<int64_t> part_ws;
+  int64_t ws_total = 0;
+  std::mutex side_mu;
+  bool side_tried = false, side_ok = false;
+  hipStream_t side[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr, ev_join[3] = {nullptr, nullptr, nullptr};
+  ~gt_plan();
 };
+
+gt_plan::~gt_plan() {
+  for (gt_plan* c : parts) delete c;
+  for (hipStream_t& st : side)
+    if (st) (void)hipStreamDestroy(st);
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  for (hipEvent_t& e : ev_join)
+    if (e) (void)hipEventDestroy(e);
+}
 
 static int64_t align256(int64_t v) { return (v + 255) & ~int64_t(255); }
 
@@ -123,8 +147,17 @@ static gt_status validate(const gt_channel_desc& d) {
   return GT_OK;
 }
 
+static LaunchCtx make_ctx(const gt_plan* p, void* ws, void* stream);
+static gt_status plan_build(const gt_channel_desc* descs, int32_t n_channels,
+                            const gt_fit_options* opt, bool allow_split, gt_plan** out);
+
 gt_status gt_plan_create(const gt_channel_desc* descs, int32_t n_channels, const gt_fit_options* opt,
                          gt_plan** out) {
+  return plan_build(descs, n_channels, opt, true, out);
+}
+
+static gt_status plan_build(const gt_channel_desc* descs, int32_t n_channels,
+                            const gt_fit_options* opt, bool allow_split, gt_plan** out) {
   if (!descs || !out || n_channels < 1) return GT_ERR_ARG;
   *out = nullptr;
   gt_fit_options o{};
@@ -273,6 +306,68 @@ gt_status gt_plan_create(const gt_channel_desc* descs, int32_t n_channels, const
   std::memcpy(p->blob.data() + p->lay.groups_by_size, p->groups_by_size.data(),
               sizeof(GroupItem) * gfirst);
   std::memcpy(p->blob.data() + p->lay.tiles, p->tiles.data(), sizeof(int32_t) * p->tiles.size());
+  p->ws_total = p->lay.total;
+  // batch split of the fit (fused passes, 8 or more channels): views over parts
+  if (allow_split && n_channels >= 8 && fused_fit_ok(make_ctx(p, nullptr, nullptr))) {
+    const int k = n_channels >= 16 ? 4 : 2;
+    int64_t woff = align256(p->lay.total);
+    for (int i = 0; i < k; ++i) {
+      const int c0 = (int)((int64_t)i * n_channels / k), c1 = (int)((int64_t)(i + 1) * n_channels / k);
+      const int nc = c1 - c0;
+      gt_plan* v = new (std::nothrow) gt_plan();
+      if (!v) {
+        delete p;
+        return GT_ERR_ARG;
+      }
+      v->desc.assign(descs + c0, descs + c1);
+      v->opt = o;
+      v->chans.assign(p->chans.begin() + c0, p->chans.begin() + c1);
+      for (const GroupItem& it : p->groups)
+        if (it.ch >= c0 && it.ch < c1) v->groups.push_back(GroupItem{it.ch - c0, it.g});
+      for (const GroupItem& it : v->groups)
+        if (v->chans[it.ch].gs <= 16) v->groups_by_size.push_back(it);
+      v->n_small_groups = (int)v->groups_by_size.size();
+      for (const GroupItem& it : v->groups)
+        if (v->chans[it.ch].gs > 16) v->groups_by_size.push_back(it);
+      v->tiles.assign((size_t)TK_COUNT * (nc + 1), 0);
+      for (int t = 0; t < TK_COUNT; ++t)
+        for (int c = 0; c <= nc; ++c)
+          v->tiles[(size_t)t * (nc + 1) + c] = p->tiles[(size_t)t * (n_channels + 1) + c0 + c] -
+                                               p->tiles[(size_t)t * (n_channels + 1) + c0];
+      v->max_nr = p->max_nr;
+      v->max_nt = p->max_nt;
+      v->min_nt = p->min_nt;
+      v->max_nsc = p->max_nsc;
+      v->max_gs = p->max_gs;
+      v->max_m = p->max_m;
+      v->max_n = p->max_n;
+      v->max_p = p->max_p;
+      v->max_ns = p->max_ns;
+      v->max_groups = p->max_groups;
+      v->max_nsplit = p->max_nsplit;
+      v->ns_max = p->ns_max;
+      v->totals = p->totals;
+      // tables at absolute workspace offsets, one contiguous blob from lay.chans
+      const int64_t ng = (int64_t)v->groups.size();
+      v->lay.chans = woff;
+      v->lay.groups = align256(v->lay.chans + (int64_t)sizeof(DevChan) * nc);
+      v->lay.groups_by_size = align256(v->lay.groups + (int64_t)sizeof(GroupItem) * ng);
+      v->lay.tiles = align256(v->lay.groups_by_size + (int64_t)sizeof(GroupItem) * ng);
+      v->lay.total = v->lay.tiles + (int64_t)sizeof(int32_t) * v->tiles.size();
+      v->blob.assign((size_t)(v->lay.total - woff), 0);
+      std::memcpy(v->blob.data(), v->chans.data(), sizeof(DevChan) * nc);
+      std::memcpy(v->blob.data() + (v->lay.groups - woff), v->groups.data(), sizeof(GroupItem) * ng);
+      std::memcpy(v->blob.data() + (v->lay.groups_by_size - woff), v->groups_by_size.data(),
+                  sizeof(GroupItem) * ng);
+      std::memcpy(v->blob.data() + (v->lay.tiles - woff), v->tiles.data(),
+                  sizeof(int32_t) * v->tiles.size());
+      p->parts.push_back(v);
+      p->part_c0.push_back(c0);
+      p->part_ws.push_back(woff);
+      woff = align256(v->lay.total);
+    }
+    p->ws_total = woff;
+  }
   *out = p;
   return GT_OK;
 }
@@ -296,13 +391,13 @@ gt_status gt_plan_totals(const gt_plan* plan, gt_offsets* totals, int32_t* ns_ma
 
 gt_status gt_plan_workspace_bytes(const gt_plan* plan, size_t* bytes) {
   if (!plan || !bytes) return GT_ERR_ARG;
-  *bytes = (size_t)plan->lay.total;
+  *bytes = (size_t)plan->ws_total;
   return GT_OK;
 }
 
 static gt_status check_ws(const gt_plan* plan, void* ws, size_t ws_bytes) {
   if (!plan) return GT_ERR_ARG;
-  if (!ws || ws_bytes < (size_t)plan->lay.total) return GT_ERR_WORKSPACE;
+  if (!ws || ws_bytes < (size_t)plan->ws_total) return GT_ERR_WORKSPACE;
   return GT_OK;
 }
 
@@ -340,11 +435,29 @@ gt_status gt_workspace_init(const gt_plan* plan, void* ws, size_t ws_bytes, void
   if (st != GT_OK) return st;
   hipError_t e = hipMemcpyAsync(ws, plan->blob.data(), plan->blob.size(), hipMemcpyHostToDevice,
                                 reinterpret_cast<hipStream_t>(stream));
+  for (size_t i = 0; e == hipSuccess && i < plan->parts.size(); ++i)
+    e = hipMemcpyAsync(reinterpret_cast<char*>(ws) + plan->part_ws[i], plan->parts[i]->blob.data(),
+                       plan->parts[i]->blob.size(), hipMemcpyHostToDevice,
+                       reinterpret_cast<hipStream_t>(stream));
   if (e != hipSuccess) {
     set_error_detail("gt_workspace_init", e);
     return GT_ERR_HIP;
   }
   return GT_OK;
+}
+
+// Side streams (default priority) and events of a split plan, made once on the current device.
+static bool side_ready(gt_plan* p) {
+  std::lock_guard<std::mutex> lk(p->side_mu);
+  if (p->side_tried) return p->side_ok;
+  p->side_tried = true;
+  const size_t ns = p->parts.size() - 1;
+  bool ok = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) == hipSuccess;
+  for (size_t i = 0; ok && i < ns; ++i)
+    ok = hipStreamCreateWithFlags(&p->side[i], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&p->ev_join[i], hipEventDisableTiming) == hipSuccess;
+  p->side_ok = ok;
+  return ok;
 }
 
 gt_status gt_tucker_fit(const gt_plan* plan, const void* X, void* A, void* B, void* C, void* G,
@@ -359,8 +472,24 @@ gt_status gt_tucker_fit(const gt_plan* plan, const void* X, void* A, void* B, vo
     for (const auto& d : plan->desc)
       if (d.nt % 4 != 0) return GT_ERR_UNSUPPORTED;
   }
-  return launch_fit(L, (const float2*)X, (float2*)A, (float2*)B, (float2*)C, (float2*)G, obj_trace,
-                    dev_status, plan->opt.iters, (plan->opt.flags & GT_FIT_WARM_START) != 0);
+  const bool warm = (plan->opt.flags & GT_FIT_WARM_START) != 0;
+  gt_plan* mp = const_cast<gt_plan*>(plan);
+  if (plan->parts.empty() || !side_ready(mp))
+    return launch_fit(L, nullptr, (const float2*)X, (float2*)A, (float2*)B, (float2*)C,
+                      (float2*)G, obj_trace, dev_status, plan->opt.iters, warm);
+  // split batch: part 0 on the caller's stream, the others on side streams
+  LaunchCtx P[4];
+  SplitCtx S;
+  S.n = (int)plan->parts.size();
+  S.parts = P;
+  S.fork = mp->ev_fork;
+  for (int k = 0; k < S.n; ++k) {
+    P[k] = make_ctx(plan->parts[k], ws, k == 0 ? stream : (void*)mp->side[k - 1]);
+    P[k].c0 = plan->part_c0[k];
+    if (k > 0) S.join[k - 1] = mp->ev_join[k - 1];
+  }
+  return launch_fit(L, &S, (const float2*)X, (float2*)A, (float2*)B, (float2*)C, (float2*)G,
+                    obj_trace, dev_status, plan->opt.iters, warm);
 }
 
 gt_status gt_tucker_reconstruct(const gt_plan* plan, const void* A, const void* B, const void* C,

@@ -13,12 +13,13 @@ pytestmark = pytest.mark.gpu
 
 
 def test_fit_and_sinr_graph_replay(gpu_lib):
-    # two 8 x 64 x 3276 channels: eager run, then a captured graph replayed three times with
-    # eager work in between; every replay must reproduce the eager outputs bit for bit
+    # eight 8 x 64 x 3276 channels (a batch the fit splits over concurrent streams): eager run,
+    # then a captured graph replayed three times with eager work in between; every replay must
+    # reproduce the eager outputs bit for bit
     cfg = synthgen.CONFIGS["rb273"]
-    announce("graph capture fit + sinr, 2 x rb273")
-    X = torch.cat([dev_c64(synthgen.make_channel(cfg, c)) for c in range(2)])
-    plan = gpu_lib.Plan([gpu_lib.desc_from_config(cfg)] * 2, iters=cfg.iters)
+    announce("graph capture fit + sinr, 8 x rb273")
+    X = torch.cat([dev_c64(synthgen.make_channel(cfg, c)) for c in range(8)])
+    plan = gpu_lib.Plan([gpu_lib.desc_from_config(cfg)] * 8, iters=cfg.iters)
     s2 = [float(v) for v in synthgen.snr_to_sigma2(cfg.snr_db)]
     f_eager = plan.empty_factors()
     r = plan.fit(X, factors=f_eager, trace=False)
@@ -131,3 +132,25 @@ def test_heterogeneous_batch(gpu_lib):
         orc = tucker.fit(Xo, d["group_size"], d["m"], d["n"], d["p"], iters)
         n2 = float(np.sum(np.abs(Xo) ** 2))
         assert np.abs(tr[c] - orc["trace"]).max() <= 1e-5 * n2, c
+
+
+def test_split_batch_matches_single_channel_fits(gpu_lib):
+    # a batch of 16 channels runs as four parts on concurrent streams; every channel's factors,
+    # cores, objective trace and status must equal those of a plan holding that channel alone
+    announce("split batch of 16 vs single-channel plans")
+    rng = np.random.default_rng(91)
+    nr, nt, nsc = 8, 64, 240
+    Xs = [synthgen.build_channel(synthgen.draw_paths(rng, 8, 6.0), nr, nt, nsc) for _ in range(16)]
+    d = desc(nr, nt, nsc, 12, 8, 16, 12, 4)
+    plan = gpu_lib.Plan([d] * 16, iters=8)
+    res = plan.fit(torch.cat([dev_c64(x) for x in Xs]))
+    torch.cuda.synchronize()
+    for c, x in enumerate(Xs):
+        one = gpu_lib.Plan([d], iters=8).fit(dev_c64(x))
+        torch.cuda.synchronize()
+        o = plan.offsets(c)
+        for k, off, size in (("A", o.a, nr * 8), ("B", o.b, nt * 16), ("C", o.c, nsc * 12),
+                             ("G", o.g, one["G"].numel())):
+            assert torch.equal(res[k][off:off + size], one[k]), (c, k)
+        assert torch.equal(res["trace"][c], one["trace"][0]), c
+        assert int(res["status"][c].item()) == 0 and int(one["status"][0].item()) == 0
