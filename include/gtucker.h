@@ -17,8 +17,9 @@
  *    Numerical conditions found on the device are OR-ed into a per-channel int32 status
  *    word (GT_DEV_*); the caller clears it and reads it after synchronising.
  *  - No C++ exception crosses this boundary.  All functions are thread-compatible: a plan
- *    is immutable after creation and may be shared; a workspace must not be used by two
- *    calls that run concurrently.
+ *    is immutable after creation (apart from the side streams its first fit makes, under a
+ *    lock) and may be shared; a workspace must not be used by two calls that run
+ *    concurrently, and one plan's fits must not overlap.
  *
  * Per-channel layouts (row-major; each channel's block starts at the offsets given by
  * gt_plan_offsets, in elements):
@@ -66,9 +67,8 @@ typedef enum { GT_C64 = 0 } gt_dtype;
  * matrix contractions of the A- and B-steps).  BF16 and FP16 round both operands to 16 bits;
  * SPLIT_BF16 writes each operand as hi + lo (two BF16 numbers) and sums the products hi hi,
  * hi lo and lo hi.  Products always accumulate in FP32; the Grams, eigensolves, cores and
- * the SINR chain stay in FP32.  The 16-bit forms are provided for plans whose channels all
- * run the fused per-group passes (nt <= 64 and a multiple of 4, group_size * nr <= 128, p and
- * m <= 16); gt_tucker_fit returns GT_ERR_UNSUPPORTED otherwise. */
+ * the SINR chain stay in FP32.  The 16-bit forms need every nt to be a multiple of 4 (K steps
+ * of 8 reals); gt_tucker_fit returns GT_ERR_UNSUPPORTED otherwise. */
 typedef enum { GT_TTM_FP32 = 0, GT_TTM_BF16 = 1, GT_TTM_FP16 = 2, GT_TTM_SPLIT_BF16 = 3 } gt_ttm_prec;
 
 #define GT_FIT_WARM_START 1u  /* A, B, C are read as the starting factors; the HOSVD step is skipped */
@@ -92,7 +92,7 @@ typedef struct {
 typedef struct {
   int32_t iters;       /* alternating sweeps S, >= 0 */
   int32_t ttm_prec;    /* gt_ttm_prec */
-  int32_t eig_fp64;    /* 1: Gram eigensolves in FP64 */
+  int32_t eig_fp64;    /* 1: Gram eigensolves in FP64 (on the FP32-accumulated Grams) */
   uint32_t flags;      /* GT_FIT_* */
 } gt_fit_options;
 
@@ -125,8 +125,12 @@ gt_status gt_workspace_init(const gt_plan* plan, void* ws, size_t ws_bytes, void
  * NULL) receives per channel 1 + 3*iters values of the objective f of equation "MT_origin"
  * after the initialisation and after each half-step, layout [n_channels][1 + 3*iters].
  * dev_status: [n_channels] int32 device words (may be NULL).  With GT_FIT_WARM_START the
- * initial A, B, C are read from the output buffers.  GT_ERR_UNSUPPORTED: eig_fp64 with some
- * nt > 64, or a 16-bit ttm_prec on a plan outside the fused passes (see gt_ttm_prec). */
+ * initial A, B, C are read from the output buffers.  GT_ERR_UNSUPPORTED: a 16-bit ttm_prec
+ * with some nt not a multiple of 4 (see gt_ttm_prec).  A batch of 8 or more channels that
+ * runs the fused per-group passes spreads parts of each sweep over up to three side streams
+ * of its own (made on the plan's first fit, default priority), forked from and joined back
+ * into `stream` by events, so the call stays ordered on `stream` and can be captured in a
+ * graph; a channel's results do not depend on the batch it is fitted in. */
 gt_status gt_tucker_fit(const gt_plan* plan, const void* X, void* A, void* B, void* C, void* G,
                         double* obj_trace, int32_t* dev_status, void* ws, size_t ws_bytes,
                         void* stream);
