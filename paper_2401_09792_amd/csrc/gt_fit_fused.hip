@@ -1315,12 +1315,13 @@ __global__ void __launch_bounds__(256) k_gram_rows_st(const DevChan* __restrict_
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, h = lane / 32, col = lane % 32;
   const bool vec = (nt % 2) == 0 && ((reinterpret_cast<uintptr_t>(M) & 15) == 0);
   // staging role of this thread: element e = tid + 256 k, matrix e / 512 (A rows of SI, B of
-  // SJ), row (e / 32) % 16 of the chunk, columns 4 (e % 32) .. + 3 of the 128
+  // SJ), row e % 16 of the chunk, columns 4 ((e / 16) % 32) .. + 3 of the 128 (consecutive
+  // threads take consecutive rows, so that their column-major LDS writes hit distinct banks)
   int cb[4], lds[4], rowk[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int e = tid + 256 * k, mat = e >> 9, cq = e & 31;
-    rowk[k] = (e >> 5) & 15;
+    const int e = tid + 256 * k, mat = e >> 9, cq = (e >> 4) & 31;
+    rowk[k] = e & 15;
     cb[k] = 128 * (mat ? SJ : SI) + 4 * cq;
     lds[k] = mat * 128 * kGP + 4 * cq * kGP + rowk[k];
   }
