@@ -1485,19 +1485,34 @@ __global__ void __launch_bounds__(256) k_rows_times_b(const DevChan* __restrict_
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = accb[r] = 0.f;
     if (vec8) {
+      // batches of eight 16-byte loads (32 products); the next batch is requested before the
+      // current one's products (clamped to the row at its end)
       const float4* xr4 = reinterpret_cast<const float4*>(xr);
       const float* bcol = bts + 4 * half * 32 + col;
-      for (int w = 0; w < nt / 4; w += 2) {
-        const float4 x0 = xr4[2 * w + half], x1 = xr4[2 * (w + 1) + half];
-        const float* bw = bcol + 8 * w * 32;
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.x, bw[0], acc, 0, 0, 0);
-        accb = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.x, bw[256], accb, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.y, bw[32], acc, 0, 0, 0);
-        accb = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.y, bw[288], accb, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.z, bw[64], acc, 0, 0, 0);
-        accb = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.z, bw[320], accb, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.w, bw[96], acc, 0, 0, 0);
-        accb = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.w, bw[352], accb, 0, 0, 0);
+      const int nw = nt / 4;
+      float4 xa[8];
+#pragma unroll
+      for (int d = 0; d < 8; ++d) xa[d] = xr4[2 * min(d, nw - 1) + half];
+      for (int w0 = 0; w0 < nw; w0 += 8) {
+        float4 xn[8];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) xn[d] = xr4[2 * min(w0 + 8 + d, nw - 1) + half];
+#pragma unroll
+        for (int d = 0; d < 8; d += 2)
+          if (w0 + d < nw) {
+            const float4 x0 = xa[d], x1 = xa[d + 1];
+            const float* bw = bcol + 8 * (w0 + d) * 32;
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.x, bw[0], acc, 0, 0, 0);
+            accb = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.x, bw[256], accb, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.y, bw[32], acc, 0, 0, 0);
+            accb = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.y, bw[288], accb, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.z, bw[64], acc, 0, 0, 0);
+            accb = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.z, bw[320], accb, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.w, bw[96], acc, 0, 0, 0);
+            accb = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.w, bw[352], accb, 0, 0, 0);
+          }
+#pragma unroll
+        for (int d = 0; d < 8; ++d) xa[d] = xn[d];
       }
     } else {
       for (int t = 0; t < nt; ++t)
