@@ -477,38 +477,70 @@ __global__ void __launch_bounds__(64, (sizeof(T) == 4 && MP == 16) ? 2 : 1) k_ei
 // ---------------------------------------------------------------------------------------
 // Mode-n products of the sweep.
 
-// Per group: Z_q = sum_s conj(C[s,q]) T_s, S1 partial = sum_q Z_q Z_q^H (one q at a time).
+// Per group: Z_q = sum_s conj(C[s,q]) T_s for a chunk of q at once (a thread owns entries
+// (i, b) and reads each T_s entry once per chunk), then the S1 partial sum_q Z_q Z_q^H with
+// thr threads per output (i, k) splitting the (q, b) sum.  Dynamic LDS: C_g [gs][p], then Z
+// [qc][nr][n] with qc nr n <= kZLds.
+constexpr int kZLds = 8192;  // complex entries of Z held at once (64 KB)
+
+template <int SMAX>
 __global__ void __launch_bounds__(256) k_stepA_group(const DevChan* __restrict__ chans,
                                                      const GroupItem* __restrict__ items,
                                                      const float2* __restrict__ C, char* ws) {
+  extern __shared__ float2 sa_lds[];
   const GroupItem it = items[blockIdx.x];
   CH_BEGIN(it.ch);
-  const int nr = ch.nr, n = ch.n;
+  const int nr = ch.nr, n = ch.n, p = ch.p;
   const int s0 = it.g * ch.gs;
   const int sz = min(ch.gs, ch.nsc - s0);
-  const int pg = min(ch.p, sz);
-  __shared__ float2 Z[kMaxNr * 64];  // [i][b] of one Z_q
-  const float2* T = wsp(ws, ch.w_T) + (int64_t)s0 * nr * n;
-  Cx<float> acc[1] = {{0.f, 0.f}};
-  const int o = threadIdx.x;  // output (i, k) of S1, nr*nr <= 256
-  for (int q = 0; q < pg; ++q) {
-    for (int e = threadIdx.x; e < nr * n; e += blockDim.x) {
-      Cx<float> z{0.f, 0.f};
-      for (int i = 0; i < sz; ++i)
-        cfmac(z, ld(C + ch.c + (int64_t)(s0 + i) * ch.p + q), ld(T + (int64_t)i * nr * n + e));
-      Z[e] = make_float2(z.re, z.im);
-    }
-    __syncthreads();
-    if (o < nr * nr) {
-      const int i = o / nr, k = o % nr;
-      for (int b = 0; b < n; ++b) {
-        float2 zi = Z[i * n + b], zk = Z[k * n + b];
-        cfmac(acc[0], Cx<float>{zk.x, zk.y}, Cx<float>{zi.x, zi.y});
+  const int pg = min(p, sz);
+  const int ne = nr * n;
+  const int qc = max(1, min(pg, kZLds / ne));
+  float2* Cs = sa_lds;               // [gs][p]
+  float2* Z = sa_lds + ch.gs * p;    // [qc][nr][n]
+  for (int e = threadIdx.x; e < sz * p; e += blockDim.x) Cs[e] = C[ch.c + (int64_t)s0 * p + e];
+  const float2* T = wsp(ws, ch.w_T) + (int64_t)s0 * ne;
+  int thr = 1;
+  while (thr * 2 * nr * nr <= 256 && thr < 64) thr *= 2;
+  const int o = threadIdx.x / thr, part = threadIdx.x % thr;
+  float ar = 0.f, ai = 0.f;
+  for (int q0 = 0; q0 < pg; q0 += qc) {
+    const int q1 = min(pg, q0 + qc);
+    __syncthreads();  // C staged; the previous chunk's Z read
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+      float2 tv[SMAX];
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s) tv[s] = T[(int64_t)min(s, sz - 1) * ne + e];
+      for (int q = q0; q < q1; ++q) {
+        float zr = 0.f, zi = 0.f;
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s)
+          if (s < sz) {
+            const float2 c = Cs[s * p + q];  // conj(c) t
+            zr += c.x * tv[s].x + c.y * tv[s].y;
+            zi += c.x * tv[s].y - c.y * tv[s].x;
+          }
+        Z[(q - q0) * ne + e] = make_float2(zr, zi);
       }
     }
     __syncthreads();
+    // S1[i][k] += sum_{q in chunk, b} Z_q[i][b] conj(Z_q[k][b])
+    if (o < nr * nr) {
+      const int i = o / nr, k = o % nr;
+      for (int q = 0; q < q1 - q0; ++q)
+        for (int b = part; b < n; b += thr) {
+          const float2 zi = Z[q * ne + i * n + b], zk = Z[q * ne + k * n + b];
+          ar += zk.x * zi.x + zk.y * zi.y;
+          ai += zk.x * zi.y - zk.y * zi.x;
+        }
+    }
   }
-  if (o < nr * nr) st(wsp(ws, ch.w_S1p) + (int64_t)it.g * nr * nr + o, acc[0]);
+  for (int d = thr / 2; d > 0; d >>= 1) {
+    ar += __shfl_xor(ar, d, 64);
+    ai += __shfl_xor(ai, d, 64);
+  }
+  if (o < nr * nr && part == 0)
+    wsp(ws, ch.w_S1p)[(int64_t)it.g * nr * nr + o] = make_float2(ar, ai);
 }
 
 // S3_g[s][t] = sum_e conj(Yh_t[e]) Yh_s[e] over the subcarriers of each group, on matrix cores:
@@ -671,6 +703,19 @@ __global__ void __launch_bounds__(256) k_core(const DevChan* __restrict__ chans,
       set_error_detail(#name, e_);                               \
       return GT_ERR_HIP;                                         \
     }                                                            \
+  } while (0)
+
+// the same with dynamic LDS
+#define GT_LAUNCH_SH(name, grid, block, shm, ...)                       \
+  do {                                                                  \
+    prof_begin(#name, L.stream);                                        \
+    hipLaunchKernelGGL(name, grid, block, shm, L.stream, __VA_ARGS__);  \
+    prof_end(L.stream);                                                 \
+    hipError_t e_ = hipGetLastError();                                  \
+    if (e_ != hipSuccess) {                                             \
+      set_error_detail(#name, e_);                                      \
+      return GT_ERR_HIP;                                                \
+    }                                                                   \
   } while (0)
 
 // the same on the stream of another context
@@ -884,7 +929,16 @@ gt_status launch_fit(const LaunchCtx& L, const SplitCtx* split, const float2* X,
   for (int it = 0; it < iters; ++it) {
     gt_status st;
     // A-step (B, C of the previous sweep)
-    GT_LAUNCH(k_stepA_group, dim3(L.total_groups), b256, L.d_chans, L.d_groups, C, L.ws);
+    {
+      const size_t sh = sizeof(float2) * ((size_t)L.max_gs * L.max_p +
+                                          std::min<size_t>(kZLds, (size_t)L.max_p * L.max_nr * L.max_n));
+      if (L.max_gs <= 12)
+        GT_LAUNCH_SH((k_stepA_group<12>), dim3(L.total_groups), b256, sh, L.d_chans, L.d_groups, C, L.ws);
+      else if (L.max_gs <= 24)
+        GT_LAUNCH_SH((k_stepA_group<24>), dim3(L.total_groups), b256, sh, L.d_chans, L.d_groups, C, L.ws);
+      else
+        GT_LAUNCH_SH((k_stepA_group<32>), dim3(L.total_groups), b256, sh, L.d_chans, L.d_groups, C, L.ws);
+    }
     if ((st = eig_dispatch(L, 0, A, B, C, status, (warm && it == 0) ? 0 : 1)) != GT_OK) return st;
     if (trace)
       GT_LAUNCH(k_trace, dim3(cdiv(nch, 64)), dim3(64), L.d_chans, nch, L.ws, trace, stride,
