@@ -1806,29 +1806,35 @@ __global__ void __launch_bounds__(256) k_w_rows(const DevChan* __restrict__ chan
   }
 }
 
-// Yh_s = A^H T_s (m x n) from T = H B, one output per thread.
+// Yh_s = A^H T_s (m x n) from T = H B: a thread owns column b of one T_s (nr entries, read
+// once) and forms the m entries of that column of Yh_s.
 __global__ void __launch_bounds__(256) k_yh_from_t(const DevChan* __restrict__ chans,
                                                    const int32_t* __restrict__ toff, int n_channels,
                                                    const float2* __restrict__ A, char* ws) {
   const int cidx = tile_channel(toff, n_channels, blockIdx.x);
   const DevChan& ch = chans[cidx];
   const int nr = ch.nr, m = ch.m, n = ch.n;
-  const int64_t total = (int64_t)ch.nsc * m * n;
   const int64_t o = (int64_t)(blockIdx.x - toff[cidx]) * blockDim.x + threadIdx.x;
-  if (o >= total) return;
+  if (o >= (int64_t)ch.nsc * n) return;
   const int b = (int)(o % n);
-  const int64_t sa = o / n;
-  const int a = (int)(sa % m);
-  const int64_t s = sa / m;
+  const int64_t s = o / n;
   const float2* T = reinterpret_cast<const float2*>(ws + ch.w_T) + s * nr * n + b;
-  const float2* Ac = A + ch.a + a;
-  float re = 0.f, im = 0.f;
-  for (int i = 0; i < nr; ++i) {
-    const float2 x = Ac[i * m], t = T[(int64_t)i * n];
-    re += x.x * t.x + x.y * t.y;
-    im += x.x * t.y - x.y * t.x;
+  float2 tc[kMaxNr];
+#pragma unroll
+  for (int i = 0; i < kMaxNr; ++i) tc[i] = T[(int64_t)min(i, nr - 1) * n];
+  float2* Y = reinterpret_cast<float2*>(ws + ch.w_Yh) + s * m * n + b;
+  const float2* Ac = A + ch.a;
+  for (int a = 0; a < m; ++a) {
+    float re = 0.f, im = 0.f;
+#pragma unroll
+    for (int i = 0; i < kMaxNr; ++i)
+      if (i < nr) {
+        const float2 x = Ac[i * m + a];
+        re += x.x * tc[i].x + x.y * tc[i].y;
+        im += x.x * tc[i].y - x.y * tc[i].x;
+      }
+    Y[(int64_t)a * n] = make_float2(re, im);
   }
-  reinterpret_cast<float2*>(ws + ch.w_Yh)[o] = make_float2(re, im);
 }
 
 // S2 = sum over splits of the complex Gram assembled from the real blocks of R^T R

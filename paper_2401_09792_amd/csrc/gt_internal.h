@@ -58,7 +58,7 @@ enum TileKind {
   TK_TROWS,      // T = H B: ceil(ceil(nsc nr / 32) / kTRowTiles) x ceil(2 n / 32)
   TK_GRAM,       // mode-2 Gram super-tiles: S (S + 1) / 2 x nsplit, S = ceil(2 nt / 128)
   TK_RED2,       // Gram reduction: ceil(nt^2 / 256)
-  TK_YH,         // Yh = A^H T: ceil(nsc m n / 256)
+  TK_YH,         // Yh = A^H T: ceil(nsc n / 256)
   TK_COUNT
 };
 constexpr int kTRowTiles = 16;  // 32-row tiles per block of the T pass

@@ -250,7 +250,7 @@ static gt_status plan_build(const gt_channel_desc* descs, int32_t n_channels,
         ((rtiles + kTRowTiles - 1) / kTRowTiles) * ((2 * ch.n + 31) / 32),
         S * (S + 1) / 2 * ch.nsplit,
         ((int64_t)ch.nt * ch.nt + 255) / 256,
-        ((int64_t)ch.nsc * ch.m * ch.n + 255) / 256};
+        ((int64_t)ch.nsc * ch.n + 255) / 256};
     for (int k = 0; k < TK_COUNT; ++k) {
       const int64_t v = p->tiles[(size_t)k * (n_channels + 1) + c] + cnt[k];
       if (v > INT32_MAX) {
