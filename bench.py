@@ -204,8 +204,9 @@ def time_forms(api, synthgen, cfg, X, B, s2, ms_fp32, sg_fp32, torch, steps):
         steps_per_s=1e3 / ms, ms_per_step=ms, loss_first=float(losses[0]),
         loss_last=float(losses[-1]))
     # precision form on the 16 x 256 x 3276 workload (16 paths, ranks (12, 32, 12), Ns 8 at
-    # 10 dB), 8 channels per batch: fit + SINR for FP32, the three 16-bit contraction forms and
-    # the FP64 Gram eigensolve, SINR error against the plain FP32 output of the same batch
+    # 10 dB), 8 channels per batch: fit + SINR for FP32, the three 16-bit contraction forms,
+    # the FP64 Gram eigensolve, and the 16-bit forms with the FP64 eigensolve; SINR error
+    # against the plain FP32 output of the same batch
     wcfg = synthgen.CONFIGS["wide"]
     nw = 8
     xs = []
@@ -219,7 +220,10 @@ def time_forms(api, synthgen, cfg, X, B, s2, ms_fp32, sg_fp32, torch, steps):
     wide = {}
     sg_ref = None
     for name, kw in (("fp32", {}), ("bf16", dict(ttm_prec="bf16")), ("fp16", dict(ttm_prec="fp16")),
-                     ("split_bf16", dict(ttm_prec="split_bf16")), ("fp32_eig_fp64", dict(eig_fp64=True))):
+                     ("split_bf16", dict(ttm_prec="split_bf16")), ("fp32_eig_fp64", dict(eig_fp64=True)),
+                     ("bf16_eig_fp64", dict(ttm_prec="bf16", eig_fp64=True)),
+                     ("fp16_eig_fp64", dict(ttm_prec="fp16", eig_fp64=True)),
+                     ("split_bf16_eig_fp64", dict(ttm_prec="split_bf16", eig_fp64=True))):
         planw = api.Plan([api.desc_from_config(wcfg)] * nw, iters=wcfg.iters, **kw)
         fw = planw.empty_factors()
         outw = {}

@@ -449,7 +449,8 @@ __device__ T max_residual(SubLds<T>& L, const V2<T>* Z, const V2<T>* W, int nt, 
 
 }  // namespace
 
-// Workspace of the multi-block first step (float offsets from w_SP, wide channels): slice
+// Workspace of the multi-block first step (offsets in elements of the eigensolve's precision
+// from w_SP, wide channels): slice
 // partials of H = V^H S2 V and M = V^H V, then Q = R^{-1} U (M = R^H R, U the eigenvectors of
 // R^{-H} H R^{-1}), the sorted Ritz values, the slice partials of the residual norms, and the
 // flags (Cholesky accepted, Jacobi converged).
@@ -484,14 +485,14 @@ __global__ void __launch_bounds__(NTH) k_eigB_sub(const DevChan* __restrict__ ch
   if (resume) {
     // the multi-block first step left Ritz vectors Z in P1, S2 Z in P2, the Ritz values and
     // the residual partials
-    const float* sp = reinterpret_cast<const float*>(ws + ch.w_SP);
-    const bool chol_ok = sp[SubWs::flags] != 0.f;
-    jconv = sp[SubWs::flags + 1] != 0.f;
+    const T* sp = reinterpret_cast<const T*>(ws + ch.w_SP);
+    const bool chol_ok = sp[SubWs::flags] != T(0);
+    jconv = sp[SubWs::flags + 1] != T(0);
     if (t < KB) {
-      L.e.lam[t] = (T)sp[SubWs::lam + t];
+      L.e.lam[t] = sp[SubWs::lam + t];
       L.e.src[t] = t;
       T acc = 0;
-      for (int sl = 0; sl < (nt + 63) / 64; ++sl) acc += (T)sp[SubWs::res + 64 * sl + t];
+      for (int sl = 0; sl < (nt + 63) / 64; ++sl) acc += sp[SubWs::res + 64 * sl + t];
       L.rs[t] = acc;
     }
     __syncthreads();
@@ -596,27 +597,28 @@ __global__ void __launch_bounds__(NTH) k_eigB_sub(const DevChan* __restrict__ ch
   }
 }
 
-// Multi-block first step of a warm FP32 call (four blocks per wide channel, one per 64-row
+// Multi-block first step of a warm call (four blocks per wide channel, one per 64-row
 // slice): Rayleigh-Ritz on the previous Ritz basis V without orthonormalising it first, as the
 // generalised problem H x = theta M x with M = V^H V = R^H R (so that V R^{-1} is the
 // orthonormal basis), then the Ritz vectors Z = V Q and S2 Z with Q = R^{-1} U.
 
 // Block (channel, slice): Y = S2 V on the slice's rows into P2, then the slice's partials of H
 // and M.
+template <typename T>
 __global__ void __launch_bounds__(NTH) k_sub_prod(const DevChan* __restrict__ chans, char* ws) {
-  __shared__ SubLds<float> L;
+  __shared__ SubLds<T> L;
   const DevChan& ch = chans[blockIdx.x / kSlices];
   const int slice = blockIdx.x % kSlices, nt = ch.nt;
   if (nt <= 64 || 64 * slice >= nt) return;
   const float2* S = reinterpret_cast<const float2*>(ws + ch.w_S2);
-  const float2* P0 = reinterpret_cast<const float2*>(ws + ch.w_VB);
-  float2* P2 = reinterpret_cast<float2*>(ws + ch.w_VS) + (int64_t)KB * nt;
-  float* part = reinterpret_cast<float*>(ws + ch.w_SP) + SubWs::part + slice * 2 * 64 * 64 * 2;
+  const V2<T>* P0 = reinterpret_cast<const V2<T>*>(ws + ch.w_VB);
+  V2<T>* P2 = reinterpret_cast<V2<T>*>(ws + ch.w_VS) + (int64_t)KB * nt;
+  T* part = reinterpret_cast<T*>(ws + ch.w_SP) + SubWs::part + slice * 2 * 64 * 64 * 2;
   const int lo = 64 * slice, hi = lo + 64;
-  apply_gram<float>(L, S, P0, P2, nt, lo, hi);
+  apply_gram<T>(L, S, P0, P2, nt, lo, hi);
   for (int w = 0; w < 2; ++w) {
-    rayleigh<float>(L, P0, w == 0 ? P2 : P0, nt, lo, hi);
-    float* dst = part + w * 64 * 64 * 2;
+    rayleigh<T>(L, P0, w == 0 ? P2 : P0, nt, lo, hi);
+    T* dst = part + w * 64 * 64 * 2;
     for (int e = threadIdx.x; e < 64 * 64; e += NTH) {
       dst[2 * e] = L.e.kr[e / 64][e % 64];
       dst[2 * e + 1] = L.e.ki[e / 64][e % 64];
@@ -627,21 +629,22 @@ __global__ void __launch_bounds__(NTH) k_sub_prod(const DevChan* __restrict__ ch
 // One block per wide channel: sums the partials, factors M = R^H R, forms H' = R^{-H} H R^{-1},
 // diagonalises it (Jacobi, eigenvalues descending) and stores Q = R^{-1} U, the Ritz values
 // and the flags.
+template <typename T>
 __global__ void __launch_bounds__(NTH) k_sub_rr(const DevChan* __restrict__ chans, char* ws) {
-  __shared__ SubLds<float> L;
+  __shared__ SubLds<T> L;
   const DevChan& ch = chans[blockIdx.x];
   if (ch.nt <= 64) return;
   const int t = threadIdx.x, r = t % 64, wave = t / 64;
-  float* sp = reinterpret_cast<float*>(ws + ch.w_SP);
+  T* sp = reinterpret_cast<T*>(ws + ch.w_SP);
   const int nsl = (ch.nt + 63) / 64;
   // M into kr/ki, H kept in registers: thread t owns entries e = t + 256 u
-  float hr[16], hi[16];
+  T hr[16], hi[16];
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int e = t + 256 * u;
-    float ar = 0.f, ai = 0.f, mr = 0.f, mi = 0.f;
+    T ar = 0, ai = 0, mr = 0, mi = 0;
     for (int sl = 0; sl < nsl; ++sl) {
-      const float* pp = sp + SubWs::part + sl * 2 * 64 * 64 * 2;
+      const T* pp = sp + SubWs::part + sl * 2 * 64 * 64 * 2;
       ar += pp[2 * e];
       ai += pp[2 * e + 1];
       mr += pp[64 * 64 * 2 + 2 * e];
@@ -653,13 +656,14 @@ __global__ void __launch_bounds__(NTH) k_sub_rr(const DevChan* __restrict__ chan
     L.e.ki[e / 64][e % 64] = mi;
   }
   __syncthreads();
-  const bool chol_ok = chol_inv<float>(L);  // R^{-1} in vr/vi
-  // R^{-1} to the staging tiles, used as one [2][64][64] float area (sb follows sa)
-  static_assert(offsetof(SubLds<float>, sb) == offsetof(SubLds<float>, sa) + sizeof(L.sa) &&
-                    sizeof(L.sa) + sizeof(L.sb) >= 2 * 64 * 64 * sizeof(float),
+  const bool chol_ok = chol_inv<T>(L);  // R^{-1} in vr/vi
+  // R^{-1} as [2][64][64] (re, im planes): in FP32 on the staging tiles (sb follows sa), in
+  // FP64 on the workspace's partial area, whose sums have been read above
+  static_assert(offsetof(SubLds<float>, sb) == offsetof(SubLds<float>, sa) + sizeof(SubLds<float>::sa) &&
+                    sizeof(SubLds<float>::sa) + sizeof(SubLds<float>::sb) >= 2 * 64 * 64 * sizeof(float),
                 "staging tiles too small for R^{-1}");
-  float* rr_ = reinterpret_cast<float*>(&L.sa[0][0]);
-  float* ri_ = rr_ + 64 * 64;
+  T* rr_ = sizeof(T) == 4 ? reinterpret_cast<T*>(&L.sa[0][0]) : sp + SubWs::part;
+  T* ri_ = rr_ + 64 * 64;
   for (int e = t; e < 64 * 64; e += NTH) {
     rr_[e] = L.e.vr[e / 64][e % 64];
     ri_[e] = L.e.vi[e / 64][e % 64];
@@ -675,9 +679,9 @@ __global__ void __launch_bounds__(NTH) k_sub_rr(const DevChan* __restrict__ chan
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int e = t + 256 * u, a = e / 64, b = e % 64;
-    float xr = 0.f, xi = 0.f;
+    T xr = 0, xi = 0;
     for (int k = 0; k <= b; ++k) {  // R^{-1} is upper triangular
-      const float h1 = L.e.kr[a][k], h2 = L.e.ki[a][k], q1 = rr_[k * 64 + b], q2 = ri_[k * 64 + b];
+      const T h1 = L.e.kr[a][k], h2 = L.e.ki[a][k], q1 = rr_[k * 64 + b], q2 = ri_[k * 64 + b];
       xr += h1 * q1 - h2 * q2;
       xi += h1 * q2 + h2 * q1;
     }
@@ -696,9 +700,9 @@ __global__ void __launch_bounds__(NTH) k_sub_rr(const DevChan* __restrict__ chan
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int e = t + 256 * u, a = e / 64, b = e % 64;
-    float xr = 0.f, xi = 0.f;
+    T xr = 0, xi = 0;
     for (int k = 0; k <= a; ++k) {  // conj(R^{-1}[k][a]) X[k][b]
-      const float q1 = rr_[k * 64 + a], q2 = ri_[k * 64 + a], x1 = L.e.vr[k][b], x2 = L.e.vi[k][b];
+      const T q1 = rr_[k * 64 + a], q2 = ri_[k * 64 + a], x1 = L.e.vr[k][b], x2 = L.e.vi[k][b];
       xr += q1 * x1 + q2 * x2;
       xi += q1 * x2 - q2 * x1;
     }
@@ -716,8 +720,8 @@ __global__ void __launch_bounds__(NTH) k_sub_rr(const DevChan* __restrict__ chan
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int e = t + 256 * u, a = e / 64, b = e % 64;
-    hr[u] = 0.5f * (hr[u] + L.e.kr[b][a]);
-    hi[u] = 0.5f * (hi[u] - L.e.ki[b][a]);
+    hr[u] = T(0.5) * (hr[u] + L.e.kr[b][a]);
+    hi[u] = T(0.5) * (hi[u] - L.e.ki[b][a]);
   }
   __syncthreads();
 #pragma unroll
@@ -727,18 +731,18 @@ __global__ void __launch_bounds__(NTH) k_sub_rr(const DevChan* __restrict__ chan
     L.e.ki[e / 64][e % 64] = hi[u];
   }
   __syncthreads();
-  const bool jc = jacobi_herm<float, KB, 4>(L.e, r, wave, 12, false);
+  const bool jc = jacobi_herm<T, KB, 4>(L.e, r, wave, sizeof(T) == 4 ? 12 : 20, false);
   __syncthreads();
-  if (wave == 0) eig_sort_desc<float, KB>(L.e, r, KB);
+  if (wave == 0) eig_sort_desc<T, KB>(L.e, r, KB);
   __syncthreads();
   // Q[:, j] = R^{-1} U[:, src[j]], stored column-major ([j][a])
-  float* q = sp + SubWs::q;
+  T* q = sp + SubWs::q;
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int e = t + 256 * u, j = e / 64, a = e % 64, cj = L.e.src[j];
-    float xr = 0.f, xi = 0.f;
+    T xr = 0, xi = 0;
     for (int k = a; k < 64; ++k) {
-      const float q1 = rr_[a * 64 + k], q2 = ri_[a * 64 + k], u1 = L.e.vr[k][cj], u2 = L.e.vi[k][cj];
+      const T q1 = rr_[a * 64 + k], q2 = ri_[a * 64 + k], u1 = L.e.vr[k][cj], u2 = L.e.vi[k][cj];
       xr += q1 * u1 - q2 * u2;
       xi += q1 * u2 + q2 * u1;
     }
@@ -747,22 +751,23 @@ __global__ void __launch_bounds__(NTH) k_sub_rr(const DevChan* __restrict__ chan
   }
   if (t < KB) sp[SubWs::lam + t] = L.e.lam[L.e.src[t]];
   if (t == 0) {
-    sp[SubWs::flags] = chol_ok ? 1.f : 0.f;
-    sp[SubWs::flags + 1] = jc ? 1.f : 0.f;
+    sp[SubWs::flags] = chol_ok ? T(1) : T(0);
+    sp[SubWs::flags + 1] = jc ? T(1) : T(0);
   }
 }
 
 // Block (channel, slice): Z = V Q into P1 and S2 Z = Y Q in place in P2 on the slice's rows,
 // and the slice's partial residual norms ||S2 z_j - theta_j z_j||^2.
+template <typename T>
 __global__ void __launch_bounds__(NTH) k_sub_rot(const DevChan* __restrict__ chans, char* ws) {
-  __shared__ SubLds<float> L;
+  __shared__ SubLds<T> L;
   const DevChan& ch = chans[blockIdx.x / kSlices];
   const int slice = blockIdx.x % kSlices, nt = ch.nt;
   if (nt <= 64 || 64 * slice >= nt) return;
   const int t = threadIdx.x;
-  float* sp = reinterpret_cast<float*>(ws + ch.w_SP);
-  if (sp[SubWs::flags] == 0.f) return;  // the resume kernel redoes the step on one block
-  const float* q = sp + SubWs::q;
+  T* sp = reinterpret_cast<T*>(ws + ch.w_SP);
+  if (sp[SubWs::flags] == T(0)) return;  // the resume kernel redoes the step on one block
+  const T* q = sp + SubWs::q;
   for (int e = t; e < 64 * 64; e += NTH) {
     L.e.vr[e % 64][e / 64] = q[2 * e];  // vr[a][j]
     L.e.vi[e % 64][e / 64] = q[2 * e + 1];
@@ -772,18 +777,18 @@ __global__ void __launch_bounds__(NTH) k_sub_rot(const DevChan* __restrict__ cha
     L.e.lam[t] = sp[SubWs::lam + t];
   }
   __syncthreads();
-  const float2* P0 = reinterpret_cast<const float2*>(ws + ch.w_VB);
-  float2* P1 = reinterpret_cast<float2*>(ws + ch.w_VS);
-  float2* P2 = P1 + (int64_t)KB * nt;
+  const V2<T>* P0 = reinterpret_cast<const V2<T>*>(ws + ch.w_VB);
+  V2<T>* P1 = reinterpret_cast<V2<T>*>(ws + ch.w_VS);
+  V2<T>* P2 = P1 + (int64_t)KB * nt;
   const int lo = 64 * slice, hi = min(nt, lo + 64);
-  rotate_block<float>(L, P0, P1, nt, lo, hi);
-  rotate_block<float>(L, P2, P2, nt, lo, hi);
+  rotate_block<T>(L, P0, P1, nt, lo, hi);
+  rotate_block<T>(L, P2, P2, nt, lo, hi);
   const int j = t / 4, pt = t % 4;
-  const float th = L.e.lam[j];
-  float acc = 0.f;
+  const T th = L.e.lam[j];
+  T acc = 0;
   for (int i = lo + pt; i < hi; i += 4) {
-    const float2 z = P1[(int64_t)j * nt + i], w = P2[(int64_t)j * nt + i];
-    const float dr = w.x - th * z.x, di = w.y - th * z.y;
+    const V2<T> z = P1[(int64_t)j * nt + i], w = P2[(int64_t)j * nt + i];
+    const T dr = w.x - th * z.x, di = w.y - th * z.y;
     acc += dr * dr + di * di;
   }
   acc += __shfl_xor(acc, 1, 64);
@@ -793,22 +798,32 @@ __global__ void __launch_bounds__(NTH) k_sub_rot(const DevChan* __restrict__ cha
 
 gt_status launch_eigB_sub(const LaunchCtx& L, float2* B, int32_t* status, int warm) {
   const int max_iter = warm ? 40 : 100;
-  const bool multi = warm && !L.eig_fp64;
+  const bool multi = warm != 0;
   if (multi) {
+    const dim3 gs(kSlices * L.n_channels), gc(L.n_channels), b(NTH);
     prof_begin("k_sub_prod", L.stream);
-    hipLaunchKernelGGL(k_sub_prod, dim3(kSlices * L.n_channels), dim3(NTH), 0, L.stream, L.d_chans, L.ws);
+    if (L.eig_fp64)
+      hipLaunchKernelGGL(k_sub_prod<double>, gs, b, 0, L.stream, L.d_chans, L.ws);
+    else
+      hipLaunchKernelGGL(k_sub_prod<float>, gs, b, 0, L.stream, L.d_chans, L.ws);
     prof_end(L.stream);
     prof_begin("k_sub_rr", L.stream);
-    hipLaunchKernelGGL(k_sub_rr, dim3(L.n_channels), dim3(NTH), 0, L.stream, L.d_chans, L.ws);
+    if (L.eig_fp64)
+      hipLaunchKernelGGL(k_sub_rr<double>, gc, b, 0, L.stream, L.d_chans, L.ws);
+    else
+      hipLaunchKernelGGL(k_sub_rr<float>, gc, b, 0, L.stream, L.d_chans, L.ws);
     prof_end(L.stream);
     prof_begin("k_sub_rot", L.stream);
-    hipLaunchKernelGGL(k_sub_rot, dim3(kSlices * L.n_channels), dim3(NTH), 0, L.stream, L.d_chans, L.ws);
+    if (L.eig_fp64)
+      hipLaunchKernelGGL(k_sub_rot<double>, gs, b, 0, L.stream, L.d_chans, L.ws);
+    else
+      hipLaunchKernelGGL(k_sub_rot<float>, gs, b, 0, L.stream, L.d_chans, L.ws);
     prof_end(L.stream);
   }
   prof_begin("k_eigB_sub", L.stream);
   if (L.eig_fp64)
     hipLaunchKernelGGL(k_eigB_sub<double>, dim3(L.n_channels), dim3(NTH), 0, L.stream, L.d_chans,
-                       L.ws, B, status, warm, max_iter, 0);
+                       L.ws, B, status, warm, max_iter, multi ? 1 : 0);
   else
     hipLaunchKernelGGL(k_eigB_sub<float>, dim3(L.n_channels), dim3(NTH), 0, L.stream, L.d_chans,
                        L.ws, B, status, warm, max_iter, multi ? 1 : 0);

@@ -288,7 +288,7 @@ static gt_status plan_build(const gt_channel_desc* descs, int32_t n_channels,
       ch.w_VS = take(ch.nt > 64 ? cv * 2 * 64 * ch.nt : 8);
       // slice partials of two 64 x 64 complex blocks (4 slices), Q, Ritz values, residual
       // partials and two flags
-      ch.w_SP = take(ch.nt > 64 ? 4 * (4 * 2 * 64 * 64 * 2 + 64 * 64 * 2 + 64 + 4 * 64 + 2) : 8);
+      ch.w_SP = take(ch.nt > 64 ? (cv / 2) * (4 * 2 * 64 * 64 * 2 + 64 * 64 * 2 + 64 + 4 * 64 + 2) : 8);
     }
     ch.w_Xq = take(o.ttm_prec == GT_TTM_FP32 ? 8
                    : (o.ttm_prec == GT_TTM_SPLIT_BF16 ? 8 : 4) * (int64_t)ch.nsc * ch.nr * ch.nt);

@@ -102,17 +102,21 @@ def wide_oracle():
     return cfg, X, osinr.sinr(Ht, s2, cfg.ns), s2
 
 
+@pytest.mark.parametrize("eig_fp64", [False, True])
 @pytest.mark.parametrize("prec", ["bf16", "fp16", "split_bf16"])
-def test_precision_wide_sinr(gpu_lib, wide_oracle, prec):
+def test_precision_wide_sinr(gpu_lib, wide_oracle, prec, eig_fp64):
+    # with eig_fp64 this is the precision workload's own combination: 16-bit contractions and
+    # the FP64 Gram eigensolve
     cfg, X, ref, s2 = wide_oracle
-    announce(f"precision {prec} 16 x 256 x 96 fit + sinr")
+    announce(f"precision {prec} eig_fp64={eig_fp64} 16 x 256 x 96 fit + sinr")
     plan = gpu_lib.Plan([desc(cfg.nr, cfg.nt, 96, cfg.group_size, cfg.m, cfg.n, cfg.p, cfg.ns)],
-                        iters=cfg.iters, ttm_prec=prec)
+                        iters=cfg.iters, ttm_prec=prec, eig_fp64=eig_fp64)
     res = plan.fit(dev_c64(X))
     sg = host(plan.sinr(res["C"], res["G"], s2))
     assert int(res["status"].item()) == 0
     err = np.abs(db(sg[:, :, :cfg.ns]) - db(ref))
-    print(f"[precision] wide {prec}: max SINR error {err.max():.3e} dB, mean {err.mean():.3e} dB")
+    print(f"[precision] wide {prec} eig_fp64={eig_fp64}: max SINR error {err.max():.3e} dB, "
+          f"mean {err.mean():.3e} dB")
     assert err.max() <= TOL[prec][0], err.max()
 
 
