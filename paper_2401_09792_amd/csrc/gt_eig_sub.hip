@@ -16,8 +16,6 @@
 // fixed pseudo-random unimodular Omega.
 #include <hip/hip_runtime.h>
 
-#include <cstddef>
-
 #include "gt_device.h"
 #include "gt_internal.h"
 
@@ -65,7 +63,7 @@ struct SubP<float> {
 template <>
 struct SubP<double> {
   static constexpr int KC = 8;
-  static constexpr double tol = 1.0e-10, floor = 1.0e-6, piv = 1.0e-10, keep = 1.0e-16, tiny = 1.0e-300;
+  static constexpr double tol = 1.0e-8, floor = 1.0e-6, piv = 1.0e-10, keep = 1.0e-16, tiny = 1.0e-300;
 };
 
 __device__ __forceinline__ float rsqrt_t(float x) { return 1.0f / __builtin_sqrtf(x); }
@@ -656,18 +654,7 @@ __global__ void __launch_bounds__(NTH) k_sub_rr(const DevChan* __restrict__ chan
     L.e.ki[e / 64][e % 64] = mi;
   }
   __syncthreads();
-  const bool chol_ok = chol_inv<T>(L);  // R^{-1} in vr/vi
-  // R^{-1} as [2][64][64] (re, im planes): in FP32 on the staging tiles (sb follows sa), in
-  // FP64 on the workspace's partial area, whose sums have been read above
-  static_assert(offsetof(SubLds<float>, sb) == offsetof(SubLds<float>, sa) + sizeof(SubLds<float>::sa) &&
-                    sizeof(SubLds<float>::sa) + sizeof(SubLds<float>::sb) >= 2 * 64 * 64 * sizeof(float),
-                "staging tiles too small for R^{-1}");
-  T* rr_ = sizeof(T) == 4 ? reinterpret_cast<T*>(&L.sa[0][0]) : sp + SubWs::part;
-  T* ri_ = rr_ + 64 * 64;
-  for (int e = t; e < 64 * 64; e += NTH) {
-    rr_[e] = L.e.vr[e / 64][e % 64];
-    ri_[e] = L.e.vi[e / 64][e % 64];
-  }
+  const bool chol_ok = chol_inv<T>(L);  // R^{-1} in vr/vi (R in kr/ki is not needed again)
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int e = t + 256 * u;
@@ -675,13 +662,13 @@ __global__ void __launch_bounds__(NTH) k_sub_rr(const DevChan* __restrict__ chan
     L.e.ki[e / 64][e % 64] = hi[u];
   }
   __syncthreads();
-  // X = H R^{-1} into vr/vi
+  // X = H R^{-1} (R^{-1} upper triangular), into kr/ki once H is read
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int e = t + 256 * u, a = e / 64, b = e % 64;
     T xr = 0, xi = 0;
-    for (int k = 0; k <= b; ++k) {  // R^{-1} is upper triangular
-      const T h1 = L.e.kr[a][k], h2 = L.e.ki[a][k], q1 = rr_[k * 64 + b], q2 = ri_[k * 64 + b];
+    for (int k = 0; k <= b; ++k) {
+      const T h1 = L.e.kr[a][k], h2 = L.e.ki[a][k], q1 = L.e.vr[k][b], q2 = L.e.vi[k][b];
       xr += h1 * q1 - h2 * q2;
       xi += h1 * q2 + h2 * q1;
     }
@@ -692,17 +679,17 @@ __global__ void __launch_bounds__(NTH) k_sub_rr(const DevChan* __restrict__ chan
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int e = t + 256 * u;
-    L.e.vr[e / 64][e % 64] = hr[u];
-    L.e.vi[e / 64][e % 64] = hi[u];
+    L.e.kr[e / 64][e % 64] = hr[u];
+    L.e.ki[e / 64][e % 64] = hi[u];
   }
   __syncthreads();
-  // H' = R^{-H} X, Hermitian part, into kr/ki
+  // H' = R^{-H} X, then its Hermitian part, into kr/ki
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int e = t + 256 * u, a = e / 64, b = e % 64;
     T xr = 0, xi = 0;
     for (int k = 0; k <= a; ++k) {  // conj(R^{-1}[k][a]) X[k][b]
-      const T q1 = rr_[k * 64 + a], q2 = ri_[k * 64 + a], x1 = L.e.vr[k][b], x2 = L.e.vi[k][b];
+      const T q1 = L.e.vr[k][a], q2 = L.e.vi[k][a], x1 = L.e.kr[k][b], x2 = L.e.ki[k][b];
       xr += q1 * x1 + q2 * x2;
       xi += q1 * x2 - q2 * x1;
     }
@@ -731,23 +718,19 @@ __global__ void __launch_bounds__(NTH) k_sub_rr(const DevChan* __restrict__ chan
     L.e.ki[e / 64][e % 64] = hi[u];
   }
   __syncthreads();
-  const bool jc = jacobi_herm<T, KB, 4>(L.e, r, wave, sizeof(T) == 4 ? 12 : 20, false);
+  // Jacobi with its rotations accumulated onto R^{-1}: the eigenvector matrix it leaves is
+  // Q = R^{-1} U
+  const bool jc = jacobi_herm<T, KB, 4>(L.e, r, wave, sizeof(T) == 4 ? 12 : 20, true);
   __syncthreads();
   if (wave == 0) eig_sort_desc<T, KB>(L.e, r, KB);
   __syncthreads();
-  // Q[:, j] = R^{-1} U[:, src[j]], stored column-major ([j][a])
+  // Q[:, j] = column src[j], stored column-major ([j][a])
   T* q = sp + SubWs::q;
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int e = t + 256 * u, j = e / 64, a = e % 64, cj = L.e.src[j];
-    T xr = 0, xi = 0;
-    for (int k = a; k < 64; ++k) {
-      const T q1 = rr_[a * 64 + k], q2 = ri_[a * 64 + k], u1 = L.e.vr[k][cj], u2 = L.e.vi[k][cj];
-      xr += q1 * u1 - q2 * u2;
-      xi += q1 * u2 + q2 * u1;
-    }
-    q[2 * e] = xr;
-    q[2 * e + 1] = xi;
+    q[2 * e] = L.e.vr[a][cj];
+    q[2 * e + 1] = L.e.vi[a][cj];
   }
   if (t < KB) sp[SubWs::lam + t] = L.e.lam[L.e.src[t]];
   if (t == 0) {
