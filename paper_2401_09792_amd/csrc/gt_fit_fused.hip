@@ -1294,8 +1294,10 @@ __global__ void __launch_bounds__(256) k_gram_rows_st(const DevChan* __restrict_
                                                       char* ws, int which) {
   __shared__ float4 sbuf4[2 * 2 * 128 * kGP / 4];  // [buffer][A, B][column][row]
   float* sbuf = reinterpret_cast<float*>(sbuf4);
-  const int cidx = tile_channel(toff, n_channels, blockIdx.x);
-  const int local = blockIdx.x - toff[cidx];
+  const int bt = xcd_tile(blockIdx.x, toff[n_channels]);  // the super-tiles of a split together
+  if (bt < 0) return;
+  const int cidx = tile_channel(toff, n_channels, bt);
+  const int local = bt - toff[cidx];
   const DevChan& ch = chans[cidx];
   const int nt = ch.nt, nc = 2 * nt;
   const int S = (nc + 127) / 128, nst = S * (S + 1) / 2;
@@ -1981,7 +1983,7 @@ gt_status launch_yh_from_t(const LaunchCtx& L, const float2* A) {
 // Mode-2 Gram of X rows (which = 0) or W rows (which = 1) for plans with some nt > 64.
 gt_status launch_gram_rows_big(const LaunchCtx& L, const float2* X, int which) {
   if (L.tiles_total[TK_GRAM] > 0)
-    GT_LAUNCH_SH(k_gram_rows_st, dim3(L.tiles_total[TK_GRAM]), dim3(256), 0, L.d_chans,
+    GT_LAUNCH_SH(k_gram_rows_st, dim3(8 * ((L.tiles_total[TK_GRAM] + 7) / 8)), dim3(256), 0, L.d_chans,
                  tiles_of(L, TK_GRAM), L.n_channels, X, L.ws, which);
   if (L.tiles_total[TK_RED2] > 0)
     GT_LAUNCH_SH(k_reduce_S2_st, dim3(L.tiles_total[TK_RED2]), dim3(256), 0, L.d_chans,
