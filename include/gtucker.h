@@ -172,6 +172,28 @@ gt_status gt_tucker_reconstruct_backward(const gt_plan* plan, const void* A, con
                                          void* grad_C, void* grad_G, void* ws, size_t ws_bytes,
                                          void* stream);
 
+/* Autotuner of the fit's pass variants on a plan's own shapes and data.  Each tunable choice
+ * is timed in turn over short fits of X (HIP events, at most 3 sweeps, the other choices held
+ * at their current values) and the fastest is kept in the plan for its later fits:
+ *   bstep  B-step pass: 0 matrix-core kernel, 1 the same with the next group's operands
+ *          prefetched during the current group's Gram, 2 the older matrix-core kernel;
+ *   tpass  T pass: 0 matrix cores, 1 vector ALU;
+ *   split  fits of 8 or more channels split over concurrent streams: 0 off, 1 on.
+ * Choices that do not apply to the plan (no fused passes, 16-bit contractions for the
+ * prefetching variant) keep 0 and are not timed.  A, B, C, G receive the last probe's fit
+ * and are otherwise scratch.  Synchronises the stream and is not capturable: call it before
+ * capturing the fits in a graph.  `out` (may be NULL) receives the choices and the probe
+ * time of the kept configuration in ms. */
+typedef struct {
+  int32_t bstep, tpass, split;
+  float probe_ms;
+} gt_tune_result;
+gt_status gt_plan_autotune(gt_plan* plan, const void* X, void* A, void* B, void* C, void* G,
+                           void* ws, size_t ws_bytes, void* stream, gt_tune_result* out);
+/* Sets the choices directly (for instance ones an earlier autotune stored for the same
+ * shapes).  GT_ERR_ARG for a value out of range.  Pure host code. */
+gt_status gt_plan_set_tuning(gt_plan* plan, int32_t bstep, int32_t tpass, int32_t split);
+
 /* The fit is an argmax over eigenvectors and is not differentiated: always returns
  * GT_ERR_UNSUPPORTED. */
 gt_status gt_tucker_fit_backward(const gt_plan* plan);

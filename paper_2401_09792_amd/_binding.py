@@ -33,6 +33,11 @@ class FitOptions(C.Structure):
                 ("flags", C.c_uint32)]
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("bstep", C.c_int32), ("tpass", C.c_int32), ("split", C.c_int32),
+                ("probe_ms", C.c_float)]
+
+
 # exported symbol -> (restype, argtypes)
 SIGNATURES = {
     "gt_plan_create": (C.c_int, [C.POINTER(ChannelDesc), C.c_int32, C.POINTER(FitOptions),
@@ -61,6 +66,9 @@ SIGNATURES = {
     "gt_tucker_reconstruct_backward": (C.c_int, [C.c_void_p] * 11 + [C.c_void_p, C.c_size_t,
                                                                       C.c_void_p]),
     "gt_tucker_fit_backward": (C.c_int, [C.c_void_p]),
+    "gt_plan_autotune": (C.c_int, [C.c_void_p] * 7 + [C.c_size_t, C.c_void_p,
+                                                       C.POINTER(TuneResult)]),
+    "gt_plan_set_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
     "gt_status_string": (C.c_char_p, [C.c_int]),
     "gt_last_error_detail": (C.c_char_p, []),
     "gt_profile_enable": (C.c_int, [C.c_int32]),

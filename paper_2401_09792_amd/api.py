@@ -9,7 +9,7 @@ from typing import Dict, Iterable, List, Optional, Sequence
 import torch
 
 from . import _binding as B
-from ._binding import ChannelDesc, FitOptions, Offsets, check, load
+from ._binding import ChannelDesc, FitOptions, Offsets, TuneResult, check, load
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -118,6 +118,21 @@ class Plan:
         if tr is not None:
             out["trace"] = tr.view(self.n_channels, 1 + 3 * self.iters)
         return out
+
+    def autotune(self, X: torch.Tensor) -> Dict[str, float]:
+        """Times the fit's pass variants on X and keeps the fastest in the plan (synchronises;
+        call before capturing fits in a graph)."""
+        _c64(X, self.totals.x, "X")
+        f = self.empty_factors()
+        res = TuneResult()
+        check("gt_plan_autotune", self.lib.gt_plan_autotune(
+            self._h, _ptr(X), _ptr(f["A"]), _ptr(f["B"]), _ptr(f["C"]), _ptr(f["G"]),
+            _ptr(self.ws), self.ws_bytes, _stream(), C.byref(res)))
+        return dict(bstep=res.bstep, tpass=res.tpass, split=res.split, probe_ms=res.probe_ms)
+
+    def set_tuning(self, bstep: int = 0, tpass: int = 0, split: int = 1) -> None:
+        """Sets the fit's pass variants (the choices autotune makes)."""
+        check("gt_plan_set_tuning", self.lib.gt_plan_set_tuning(self._h, bstep, tpass, split))
 
     def reconstruct(self, A, B_, C_, G, ht: bool = True, xhat: bool = True):
         t = self.totals

@@ -1910,6 +1910,7 @@ static size_t tlp_bytes(const LaunchCtx& L) {
 }
 
 static int bmm_variant(const LaunchCtx& L);
+bool fused_b_mfma_ok(const LaunchCtx& L);
 
 // The precision form runs on the fused passes with the matrix-core B-step kernel and one
 // 32-row tile per wave in the T pass (every channel's nt a multiple of 4, checked by the plan).
@@ -2027,8 +2028,9 @@ gt_status launch_fused_t(const LaunchCtx& L, const float2* X, const float2* A, c
     }
     return GT_OK;
   }
-  // matrix cores when the real output fits one column tile and at most 8 row tiles
-  if (L.max_n <= 16 && L.max_gs * L.max_nr <= 256 && tm_bytes(L) <= 64 * 1024) {
+  // matrix cores when the real output fits one column tile and at most 8 row tiles (unless
+  // the tuned choice is the vector ALU kernel)
+  if (L.tune_tpass == 0 && L.max_n <= 16 && L.max_gs * L.max_nr <= 256 && tm_bytes(L) <= 64 * 1024) {
     if (L.max_gs * L.max_nr <= 128)
       GT_LAUNCH_SH((k_fused_t_mfma<1>), dim3(L.total_groups), dim3(256), tm_bytes(L), L.d_chans,
                    L.d_groups, X, A, B, L.ws, do_c);
@@ -2079,12 +2081,16 @@ static int bmm_variant(const LaunchCtx& L) {
 }
 
 gt_status launch_fused_b(const LaunchCtx& L, const float2* X, const float2* A, const float2* C) {
-  const int v = bmm_variant(L);
+  const int v = (L.tune_bstep == 2 && fused_b_mfma_ok(L)) ? 0 : bmm_variant(L);
   if (v) {
     const dim3 grid(L.max_nsplit, L.n_channels);
     const size_t sh = bmm_bytes(L);
-#define GT_BMM(NT1W, SMAX, PREC) \
-  GT_LAUNCH_SH((k_fused_b_mm<NT1W, SMAX, false, PREC>), grid, dim3(512), sh, L.d_chans, X, A, C, L.ws)
+    const bool pf = L.tune_bstep == 1 && L.ttm_prec == GT_TTM_FP32;
+#define GT_BMM(NT1W, SMAX, PREC)                                                                    \
+  if (PREC == 0 && pf)                                                                           \
+    GT_LAUNCH_SH((k_fused_b_mm<NT1W, SMAX, true, 0>), grid, dim3(512), sh, L.d_chans, X, A, C, L.ws); \
+  else                                                                                           \
+    GT_LAUNCH_SH((k_fused_b_mm<NT1W, SMAX, false, PREC>), grid, dim3(512), sh, L.d_chans, X, A, C, L.ws)
 #define GT_BMM_PREC(NT1W, SMAX)                          \
   switch (L.ttm_prec) {                                  \
     case GT_TTM_BF16: GT_BMM(NT1W, SMAX, 1); break;      \

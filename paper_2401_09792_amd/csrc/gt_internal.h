@@ -89,6 +89,8 @@ struct LaunchCtx {
   int eig_fp64;
   int ttm_prec;  // gt_ttm_prec of the plan
   int c0 = 0;    // first channel of this context in the caller's channel numbering
+  int tune_bstep = 0;  // B-step pass variant (see gt_plan_autotune)
+  int tune_tpass = 0;  // T pass variant
 };
 
 // A fit whose batch is split into parts of consecutive channels: the parts' contexts (their

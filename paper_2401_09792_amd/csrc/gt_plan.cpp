@@ -106,6 +106,8 @@ struct gt_plan {
   bool side_tried = false, side_ok = false;
   hipStream_t side[3] = {nullptr, nullptr, nullptr};
   hipEvent_t ev_fork = nullptr, ev_join[3] = {nullptr, nullptr, nullptr};
+  // pass variants chosen by gt_plan_autotune
+  int tune_bstep = 0, tune_tpass = 0, tune_split = 1;
   ~gt_plan();
 };
 
@@ -427,6 +429,8 @@ static LaunchCtx make_ctx(const gt_plan* p, void* ws, void* stream) {
   L.min_nt = p->min_nt;
   L.ttm_prec = p->opt.ttm_prec;
   L.eig_fp64 = p->opt.eig_fp64;
+  L.tune_bstep = p->tune_bstep;
+  L.tune_tpass = p->tune_tpass;
   return L;
 }
 
@@ -460,23 +464,16 @@ static bool side_ready(gt_plan* p) {
   return ok;
 }
 
-gt_status gt_tucker_fit(const gt_plan* plan, const void* X, void* A, void* B, void* C, void* G,
-                        double* obj_trace, int32_t* dev_status, void* ws, size_t ws_bytes,
-                        void* stream) {
-  gt_status st = check_ws(plan, ws, ws_bytes);
-  if (st != GT_OK) return st;
-  if (!X || !A || !B || !C || !G) return GT_ERR_ARG;
+// One fit of the plan's batch on `stream` with `iters` sweeps (split over the side streams when
+// the plan has parts and the split is on).
+static gt_status run_fit(const gt_plan* plan, const void* X, void* A, void* B, void* C, void* G,
+                         double* obj_trace, int32_t* dev_status, void* ws, void* stream, int iters) {
   LaunchCtx L = make_ctx(plan, ws, stream);
-  // 16-bit contractions take K steps of 8 reals: every nt a multiple of 4
-  if (plan->opt.ttm_prec != GT_TTM_FP32) {
-    for (const auto& d : plan->desc)
-      if (d.nt % 4 != 0) return GT_ERR_UNSUPPORTED;
-  }
   const bool warm = (plan->opt.flags & GT_FIT_WARM_START) != 0;
   gt_plan* mp = const_cast<gt_plan*>(plan);
-  if (plan->parts.empty() || !side_ready(mp))
+  if (plan->parts.empty() || !plan->tune_split || !side_ready(mp))
     return launch_fit(L, nullptr, (const float2*)X, (float2*)A, (float2*)B, (float2*)C,
-                      (float2*)G, obj_trace, dev_status, plan->opt.iters, warm);
+                      (float2*)G, obj_trace, dev_status, iters, warm);
   // split batch: part 0 on the caller's stream, the others on side streams
   LaunchCtx P[4];
   SplitCtx S;
@@ -486,10 +483,102 @@ gt_status gt_tucker_fit(const gt_plan* plan, const void* X, void* A, void* B, vo
   for (int k = 0; k < S.n; ++k) {
     P[k] = make_ctx(plan->parts[k], ws, k == 0 ? stream : (void*)mp->side[k - 1]);
     P[k].c0 = plan->part_c0[k];
+    P[k].tune_bstep = plan->tune_bstep;
+    P[k].tune_tpass = plan->tune_tpass;
     if (k > 0) S.join[k - 1] = mp->ev_join[k - 1];
   }
   return launch_fit(L, &S, (const float2*)X, (float2*)A, (float2*)B, (float2*)C, (float2*)G,
-                    obj_trace, dev_status, plan->opt.iters, warm);
+                    obj_trace, dev_status, iters, warm);
+}
+
+gt_status gt_tucker_fit(const gt_plan* plan, const void* X, void* A, void* B, void* C, void* G,
+                        double* obj_trace, int32_t* dev_status, void* ws, size_t ws_bytes,
+                        void* stream) {
+  gt_status st = check_ws(plan, ws, ws_bytes);
+  if (st != GT_OK) return st;
+  if (!X || !A || !B || !C || !G) return GT_ERR_ARG;
+  // 16-bit contractions take K steps of 8 reals: every nt a multiple of 4
+  if (plan->opt.ttm_prec != GT_TTM_FP32) {
+    for (const auto& d : plan->desc)
+      if (d.nt % 4 != 0) return GT_ERR_UNSUPPORTED;
+  }
+  return run_fit(plan, X, A, B, C, G, obj_trace, dev_status, ws, stream, plan->opt.iters);
+}
+
+gt_status gt_plan_set_tuning(gt_plan* plan, int32_t bstep, int32_t tpass, int32_t split) {
+  if (!plan || bstep < 0 || bstep > 2 || tpass < 0 || tpass > 1 || split < 0 || split > 1)
+    return GT_ERR_ARG;
+  plan->tune_bstep = bstep;
+  plan->tune_tpass = tpass;
+  plan->tune_split = split;
+  return GT_OK;
+}
+
+gt_status gt_plan_autotune(gt_plan* plan, const void* X, void* A, void* B, void* C, void* G,
+                           void* ws, size_t ws_bytes, void* stream, gt_tune_result* out) {
+  gt_status st = check_ws(plan, ws, ws_bytes);
+  if (st != GT_OK) return st;
+  if (!X || !A || !B || !C || !G) return GT_ERR_ARG;
+  if (plan->opt.ttm_prec != GT_TTM_FP32) {
+    for (const auto& d : plan->desc)
+      if (d.nt % 4 != 0) return GT_ERR_UNSUPPORTED;
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    set_error_detail("gt_plan_autotune", hipErrorOutOfMemory);
+    return GT_ERR_HIP;
+  }
+  const int iters = std::min(plan->opt.iters, 3);
+  // time of one probe fit (after one untimed run of the same configuration), or < 0 on error
+  auto probe = [&]() -> float {
+    if (run_fit(plan, X, A, B, C, G, nullptr, nullptr, ws, stream, iters) != GT_OK) return -1.f;
+    if (hipEventRecord(e0, s) != hipSuccess) return -1.f;
+    if (run_fit(plan, X, A, B, C, G, nullptr, nullptr, ws, stream, iters) != GT_OK) return -1.f;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.f;
+    float ms = -1.f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.f;
+    return ms;
+  };
+  const LaunchCtx L0 = make_ctx(plan, ws, stream);
+  const bool fused = fused_fit_ok(L0) && (L0.ttm_prec == GT_TTM_FP32 || fused_lowp_ok(L0));
+  float best = probe();
+  gt_status rc = best < 0.f ? GT_ERR_HIP : GT_OK;
+  // coordinate search: each choice in turn over its values, the others held
+  struct Knob {
+    int* field;
+    int nvals;
+  };
+  std::vector<Knob> knobs;
+  if (fused) {
+    knobs.push_back({&plan->tune_bstep, L0.ttm_prec == GT_TTM_FP32 ? 3 : 1});
+    knobs.push_back({&plan->tune_tpass, L0.ttm_prec == GT_TTM_FP32 ? 2 : 1});
+    if (!plan->parts.empty()) knobs.push_back({&plan->tune_split, 2});
+  }
+  for (const Knob& k : knobs) {
+    if (rc != GT_OK) break;
+    const int keep = *k.field;
+    int best_v = keep;
+    for (int v = 0; v < k.nvals; ++v) {
+      if (v == keep) continue;
+      *k.field = v;
+      const float ms = probe();
+      if (ms < 0.f) {
+        rc = GT_ERR_HIP;
+        break;
+      }
+      if (ms < best) {
+        best = ms;
+        best_v = v;
+      }
+    }
+    *k.field = best_v;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (out) *out = gt_tune_result{plan->tune_bstep, plan->tune_tpass, plan->tune_split, best};
+  return rc;
 }
 
 gt_status gt_tucker_reconstruct(const gt_plan* plan, const void* A, const void* B, const void* C,

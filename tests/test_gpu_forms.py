@@ -154,3 +154,41 @@ def test_split_batch_matches_single_channel_fits(gpu_lib):
             assert torch.equal(res[k][off:off + size], one[k]), (c, k)
         assert torch.equal(res["trace"][c], one["trace"][0]), c
         assert int(res["status"][c].item()) == 0 and int(one["status"][0].item()) == 0
+
+
+def test_autotune_keeps_a_valid_fit(gpu_lib):
+    # the autotuner times the pass variants on 16 rb273-shaped channels (fused passes, split
+    # batch); every variant it may keep must give the same fit up to FP32 rounding: the tuned
+    # plan's factors reconstruct X as well as the default plan's, the objective traces agree
+    announce("autotune 16 channels")
+    rng = np.random.default_rng(93)
+    nr, nt, nsc = 8, 64, 480
+    Xs = [synthgen.build_channel(synthgen.draw_paths(rng, 8, 6.0), nr, nt, nsc) for _ in range(16)]
+    X = torch.cat([dev_c64(x) for x in Xs])
+    d = desc(nr, nt, nsc, 12, 8, 16, 12, 4)
+    ref = gpu_lib.Plan([d] * 16, iters=6)
+    r0 = ref.fit(X)
+    tuned = gpu_lib.Plan([d] * 16, iters=6)
+    choice = tuned.autotune(X)
+    print(f"[autotune] {choice}")
+    assert choice["probe_ms"] > 0
+    r1 = tuned.fit(X)
+    torch.cuda.synchronize()
+    assert np.all(host(r1["status"]) == 0)
+    tr0, tr1 = host(r0["trace"]), host(r1["trace"])
+    for c, x in enumerate(Xs):
+        nx = float(np.sum(np.abs(x) ** 2))
+        assert np.abs(tr0[c] - tr1[c]).max() <= 1e-5 * nx, c
+    # every variant in turn gives the reference fit up to rounding
+    for bstep in (0, 1, 2):
+        for tpass in (0, 1):
+            for split in (0, 1):
+                p = gpu_lib.Plan([d] * 16, iters=6)
+                p.set_tuning(bstep=bstep, tpass=tpass, split=split)
+                r = p.fit(X)
+                torch.cuda.synchronize()
+                assert np.all(host(r["status"]) == 0), (bstep, tpass, split)
+                tr = host(r["trace"])
+                for c, x in enumerate(Xs):
+                    nx = float(np.sum(np.abs(x) ** 2))
+                    assert np.abs(tr0[c] - tr[c]).max() <= 1e-5 * nx, (bstep, tpass, split, c)
