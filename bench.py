@@ -145,6 +145,21 @@ def time_forms(api, synthgen, cfg, X, B, s2, ms_fp32, sg_fp32, torch, steps):
         forms[prec] = dict(fits_per_s=B / (ms / 1e3), ms_per_fit_batch=ms,
                            max_sinr_err_db_vs_fp32=db_err(out["sg"], sg_fp32))
         del plan, f
+    # the FP32 fit + SINR after the autotuner has picked the pass variants on this batch
+    plan = api.Plan([api.desc_from_config(cfg)] * B, iters=cfg.iters)
+    choice = plan.autotune(X)
+    f = plan.empty_factors()
+    out = {}
+
+    def step_t():
+        r = plan.fit(X, factors=f, trace=False)
+        out["sg"] = plan.sinr(r["C"], r["G"], s2)
+
+    ms = timed(step_t, steps)
+    forms["fp32_autotuned"] = dict(fits_per_s=B / (ms / 1e3), ms_per_fit_batch=ms,
+                                   max_sinr_err_db_vs_fp32=db_err(out["sg"], sg_fp32),
+                                   choice={k: v for k, v in choice.items() if k != "probe_ms"})
+    del plan, f
     # batched form: the whole FP32 fit + SINR captured once and replayed
     plan = api.Plan([api.desc_from_config(cfg)] * B, iters=cfg.iters)
     f = plan.empty_factors()
