@@ -29,6 +29,8 @@ def _generator_channel(seed, nr, nt, nsc, n_paths, k_db):
     # (nsc, nr, nt, gs, m, n, p, iters, seed)
     (40, 4, 96, 12, 3, 12, 6, 4, 31),     # decaying spectrum, ragged last group of 4
     (30, 6, 128, 8, 4, 20, 5, 3, 37),     # short last group of 6
+    (27, 5, 67, 12, 3, 17, 6, 3, 39),     # odd nt: scalar staging, ragged column chunk and tiles
+    (25, 3, 130, 7, 2, 33, 7, 3, 45),     # nt % 8 == 2, odd group size, p = group size
 ])
 def test_fit_wide_lossy_random(gpu_lib, case):
     nsc, nr, nt, gs, m, n, p, iters, seed = case
@@ -124,3 +126,32 @@ def test_fit_eig_fp64(gpu_lib, shape):
     err = np.abs(10 * np.log10(sg) - 10 * np.log10(ref))
     print(f"[eig fp64] {shape[:3]}: max SINR error {err.max():.3e} dB")
     assert err.max() <= 0.05, err.max()
+
+
+def test_fit_batch_misaligned_offsets(gpu_lib):
+    # three channels on the row passes whose packed offsets in X are odd (no 16-byte alignment of
+    # their rows): the first channel has 7 x 3 x 67 entries; each channel against the oracle
+    # (spectra decaying along every axis, so that the rank cuts have gaps)
+    announce("fit batch with odd channel offsets")
+    shapes = [(7, 3, 67, 4, 2, 9, 2), (17, 4, 96, 12, 3, 12, 6), (9, 2, 72, 8, 2, 10, 4)]
+    Xs, descs = [], []
+    for k, (nsc, nr, nt, gs, m, n, p) in enumerate(shapes):
+        rng = np.random.default_rng(60 + k)
+        X = crandn(rng, nsc, nr, nt) * (0.5 ** np.arange(nr))[None, :, None] \
+            * (0.8 ** np.arange(nt))[None, None, :] * (0.8 ** np.arange(nsc))[:, None, None]
+        Xs.append(X)
+        descs.append(desc(nr, nt, nsc, gs, m, n, p, 2))
+    plan = gpu_lib.Plan(descs, iters=3)
+    res = plan.fit(dev_c64(np.concatenate([x.reshape(-1) for x in Xs])))
+    _, xh = plan.reconstruct(res["A"], res["B"], res["C"], res["G"])
+    xh = host(xh)
+    assert np.all(host(res["status"]) == 0)
+    assert plan.offsets(1).x % 2 == 1
+    tr = host(res["trace"])
+    for c, (X, d) in enumerate(zip(Xs, descs)):
+        orc = tucker.fit(X, d["group_size"], d["m"], d["n"], d["p"], 3)
+        _, Xh_o = tucker.reconstruct(orc["A"], orc["B"], orc["C"], orc["G"], d["group_size"])
+        nx = float(np.sum(np.abs(X) ** 2))
+        Xh = unpack(plan, c, xh, "x")
+        assert np.linalg.norm(Xh - Xh_o) <= 1e-4 * np.sqrt(nx), c
+        assert np.abs(tr[c] - orc["trace"]).max() <= 1e-5 * nx, c
