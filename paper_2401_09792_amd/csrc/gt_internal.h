@@ -63,12 +63,27 @@ enum TileKind {
 };
 constexpr int kTRowTiles = 16;  // 32-row tiles per block of the T pass
 
+// SINR kernel classes of a channel, by its compressed shape: the per-lane kernel for
+// m <= 4 / 8 and ns <= 2 / 4 / 8, the cooperative kernel for m > 8 by n.  A batch that
+// mixes classes runs one launch per class over a compact subcarrier range.
+enum ScClass {
+  SC_LANE4_2 = 0,  // m <= 4, ns <= 2
+  SC_LANE4_4,      // m <= 4, ns <= 4
+  SC_LANE8_4,      // m <= 8, ns <= 4
+  SC_LANE8_8,      // m <= 8, ns <= 8
+  SC_COOP_32,      // m <= 16, n <= 32
+  SC_COOP_64,      // m <= 16, n <= 64
+  SC_COUNT
+};
+
 // Workspace header: where the tables sit.
 struct WsLayout {
   int64_t chans;   // DevChan[n_channels]
   int64_t groups;  // GroupItem[total_groups]
   int64_t groups_by_size;  // GroupItem[total_groups]: groups of size <= 16 first, then the rest
   int64_t tiles;   // int32[TK_COUNT][n_channels + 1]
+  int64_t sc_ch;   // int32[n_channels]: channels ordered by SINR kernel class
+  int64_t sc_off;  // int64[n_channels + 1]: subcarrier prefix sums in that order
   int64_t total;   // bytes
 };
 
@@ -91,6 +106,13 @@ struct LaunchCtx {
   int c0 = 0;    // first channel of this context in the caller's channel numbering
   int tune_bstep = 0;  // B-step pass variant (see gt_plan_autotune)
   int tune_tpass = 0;  // T pass variant
+  // SINR classes: channels in class order, subcarrier prefix sums in that order, and per class
+  // its first position, first subcarrier and largest n
+  const int32_t* d_sc_ch = nullptr;
+  const int64_t* d_sc_off = nullptr;
+  int sc_j[SC_COUNT + 1] = {};
+  int64_t sc_base[SC_COUNT + 1] = {};
+  int sc_maxn[SC_COUNT] = {};
 };
 
 // A fit whose batch is split into parts of consecutive channels: the parts' contexts (their

@@ -94,6 +94,13 @@ struct gt_plan {
   std::vector<GroupItem> groups_by_size;
   int n_small_groups;
   std::vector<int32_t> tiles;  // [TK_COUNT][n_channels + 1]
+  // SINR classes: channels in class order, their subcarrier prefix sums, and per class its
+  // first position, first subcarrier and largest n
+  std::vector<int32_t> sc_ch;
+  std::vector<int64_t> sc_off;
+  int sc_j[SC_COUNT + 1] = {};
+  int64_t sc_base[SC_COUNT + 1] = {};
+  int sc_maxn[SC_COUNT] = {};
   // The fit of a batch of 8 or more channels on the fused per-group passes runs most of each
   // sweep as parts of consecutive channels on concurrent streams.  A part is a view: its own
   // tables (channels, groups, grids) in a workspace region after this plan's, over the same
@@ -121,6 +128,13 @@ gt_plan::~gt_plan() {
 }
 
 static int64_t align256(int64_t v) { return (v + 255) & ~int64_t(255); }
+
+// SINR kernel class of a channel (compressed shape m x n, ns streams; ns <= m).
+static int sc_class(const DevChan& ch) {
+  if (ch.m <= 4) return ch.ns <= 2 ? SC_LANE4_2 : SC_LANE4_4;
+  if (ch.m <= 8) return ch.ns <= 4 ? SC_LANE8_4 : SC_LANE8_8;
+  return ch.n <= 32 ? SC_COOP_32 : SC_COOP_64;
+}
 
 extern "C" {
 
@@ -264,6 +278,26 @@ static gt_status plan_build(const gt_channel_desc* descs, int32_t n_channels,
   }
   p->lay.tiles = off;
   off = align256(off + (int64_t)sizeof(int32_t) * p->tiles.size());
+  // channels ordered by SINR class (stable), subcarriers numbered through that order
+  p->sc_ch.clear();
+  p->sc_off.assign(1, 0);
+  for (int k = 0; k < SC_COUNT; ++k) {
+    p->sc_j[k] = (int)p->sc_ch.size();
+    p->sc_base[k] = p->sc_off.back();
+    p->sc_maxn[k] = 0;
+    for (int c = 0; c < n_channels; ++c)
+      if (sc_class(p->chans[c]) == k) {
+        p->sc_ch.push_back(c);
+        p->sc_off.push_back(p->sc_off.back() + p->chans[c].nsc);
+        p->sc_maxn[k] = std::max(p->sc_maxn[k], p->chans[c].n);
+      }
+  }
+  p->sc_j[SC_COUNT] = n_channels;
+  p->sc_base[SC_COUNT] = p->sc_off.back();
+  p->lay.sc_ch = off;
+  off = align256(off + (int64_t)sizeof(int32_t) * n_channels);
+  p->lay.sc_off = off;
+  off = align256(off + (int64_t)sizeof(int64_t) * (n_channels + 1));
   const int64_t c8 = 8;
   for (int c = 0; c < n_channels; ++c) {
     DevChan& ch = p->chans[c];
@@ -302,12 +336,14 @@ static gt_status plan_build(const gt_channel_desc* descs, int32_t n_channels,
     ch.w_gBp = take(c8 * ch.ngroups * ch.nt * ch.n);
   }
   p->lay.total = off;
-  p->blob.assign((size_t)p->lay.tiles + sizeof(int32_t) * p->tiles.size(), 0);
+  p->blob.assign((size_t)p->lay.sc_off + sizeof(int64_t) * (n_channels + 1), 0);
   std::memcpy(p->blob.data() + p->lay.chans, p->chans.data(), sizeof(DevChan) * n_channels);
   std::memcpy(p->blob.data() + p->lay.groups, p->groups.data(), sizeof(GroupItem) * gfirst);
   std::memcpy(p->blob.data() + p->lay.groups_by_size, p->groups_by_size.data(),
               sizeof(GroupItem) * gfirst);
   std::memcpy(p->blob.data() + p->lay.tiles, p->tiles.data(), sizeof(int32_t) * p->tiles.size());
+  std::memcpy(p->blob.data() + p->lay.sc_ch, p->sc_ch.data(), sizeof(int32_t) * n_channels);
+  std::memcpy(p->blob.data() + p->lay.sc_off, p->sc_off.data(), sizeof(int64_t) * (n_channels + 1));
   p->ws_total = p->lay.total;
   // batch split of the fit (fused passes, 8 or more channels): views over parts
   if (allow_split && n_channels >= 8 && fused_fit_ok(make_ctx(p, nullptr, nullptr))) {
@@ -411,6 +447,15 @@ static LaunchCtx make_ctx(const gt_plan* p, void* ws, void* stream) {
   L.d_groups = reinterpret_cast<const GroupItem*>(L.ws + p->lay.groups);
   L.d_groups_by_size = reinterpret_cast<const GroupItem*>(L.ws + p->lay.groups_by_size);
   L.d_tiles = reinterpret_cast<const int32_t*>(L.ws + p->lay.tiles);
+  if (!p->sc_ch.empty()) {  // split views run no SINR and carry no class tables
+    L.d_sc_ch = reinterpret_cast<const int32_t*>(L.ws + p->lay.sc_ch);
+    L.d_sc_off = reinterpret_cast<const int64_t*>(L.ws + p->lay.sc_off);
+  }
+  for (int k = 0; k <= SC_COUNT; ++k) {
+    L.sc_j[k] = p->sc_j[k];
+    L.sc_base[k] = p->sc_base[k];
+  }
+  for (int k = 0; k < SC_COUNT; ++k) L.sc_maxn[k] = p->sc_maxn[k];
   L.n_channels = (int)p->chans.size();
   for (int k = 0; k < TK_COUNT; ++k)
     L.tiles_total[k] = p->tiles[(size_t)k * (L.n_channels + 1) + L.n_channels];

@@ -16,6 +16,8 @@
 // to one at high SNR.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "gt_device.h"
 #include "gt_internal.h"
 
@@ -38,21 +40,53 @@ struct SinrLds {
   T vr[MP][NMAX + 1], vi[MP][NMAX + 1];  // right singular vectors v_r as rows
 };
 
-__device__ __forceinline__ int find_channel(const DevChan* chans, int n_channels, int64_t gsc) {
-  int lo = 0, hi = n_channels - 1;
+// The forward chain's LDS: the staged channel rows are read only while the Gram is formed,
+// so HV and W take their place afterwards (less LDS per subcarrier, more waves per CU).
+template <typename T, int MP, int NMAX>
+struct SinrFwdLds {
+  EigLds<T, MP> e;
+  union {
+    struct {
+      T hr[MP][NMAX + 1], hi[MP][NMAX + 1];
+    };
+    struct {
+      T hvr[MP][MP + 1], hvi[MP][MP + 1];
+      T wr[MP][MP + 1], wi[MP][MP + 1];
+    };
+  };
+  T sig[MP];
+};
+
+// A compact range of subcarriers: the channels of one or more consecutive SINR kernel classes
+// (channels ordered by class, subcarriers numbered through that order).
+struct ScRange {
+  const int32_t* ch;   // channels of the range
+  const int64_t* off;  // first position of each in the class order (ascending)
+  int n;               // channels in the range (>= 1)
+  int64_t base;        // position of the range's first subcarrier in the class order
+  int64_t count;       // subcarriers in the range
+};
+
+// Channel and global subcarrier index of item i < R.count of the range.
+__device__ __forceinline__ int locate_sc(const ScRange& R, const DevChan* chans, int64_t i,
+                                         int64_t& gsc) {
+  const int64_t pos = R.base + i;
+  int lo = 0, hi = R.n - 1;
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
-    if (chans[mid].sc <= gsc)
+    if (R.off[mid] <= pos)
       lo = mid;
     else
       hi = mid - 1;
   }
-  return lo;
+  const int c = R.ch[lo];
+  gsc = chans[c].sc + (pos - R.off[lo]);
+  return c;
 }
 
 // Fills S.e.kr/ki with K = H H^H (padded) and, for the compressed form, stages Ht in S.hr/hi.
-template <typename T, int MP, int NMAX, bool FULL>
-__device__ void build_gram(SinrLds<T, MP, NMAX>& S, int r, bool valid, const DevChan& ch, int64_t s,
+template <typename T, int MP, int NMAX, bool FULL, typename Lds>
+__device__ void build_gram(Lds& S, int r, bool valid, const DevChan& ch, int64_t s,
                            const float2* __restrict__ X, const float2* __restrict__ C,
                            const float2* __restrict__ G, int& M, int& N) {
   M = valid ? (FULL ? ch.nr : ch.m) : 0;
@@ -99,8 +133,8 @@ __device__ void build_gram(SinrLds<T, MP, NMAX>& S, int r, bool valid, const Dev
 
 // After the eigensolve: singular values and HV = U_ns Sigma_ns.  Returns the number of
 // streams of this subcarrier (0 if invalid) and flags zero streams.
-template <typename T, int MP, int NMAX>
-__device__ int singular_setup(SinrLds<T, MP, NMAX>& S, int r, int M, int ns, uint32_t& bits) {
+template <typename T, int MP, int NMAX, typename Lds>
+__device__ int singular_setup(Lds& S, int r, int M, int ns, uint32_t& bits) {
   eig_sort_desc<T, MP>(S.e, r, M);
   if (r < ns) {
     T l = S.e.lam[S.e.src[r]];
@@ -125,8 +159,8 @@ __device__ int singular_setup(SinrLds<T, MP, NMAX>& S, int r, int M, int ns, uin
 
 // Cholesky of Q = HV HV^H + s2 I (lower, in S.e.kr/ki), then W = Q^{-1} HV by two triangular
 // solves (column r in lane r).  Returns false if Q is not numerically positive definite.
-template <typename T, int MP, int NMAX>
-__device__ bool mmse_filter(SinrLds<T, MP, NMAX>& S, int r, int M, int ns, T s2) {
+template <typename T, int MP, int NMAX, typename Lds>
+__device__ bool mmse_filter(Lds& S, int r, int M, int ns, T s2) {
   for (int j = 0; j < MP; ++j) {
     T qr = 0, qi = 0;
     if (r < M && j < M) {
@@ -197,8 +231,8 @@ __device__ bool mmse_filter(SinrLds<T, MP, NMAX>& S, int r, int M, int ns, T s2)
 }
 
 // SINR of stream r from W and HV; also returns s_r, d_r and the products c_rk = w_r^H hv_k
-template <typename T, int MP, int NMAX>
-__device__ T stream_sinr(SinrLds<T, MP, NMAX>& S, int r, int M, int ns, T s2, T& sr_out, T& dr_out) {
+template <typename T, int MP, int NMAX, typename Lds>
+__device__ T stream_sinr(Lds& S, int r, int M, int ns, T s2, T& sr_out, T& dr_out) {
   T sig = 0, den = 0, nw = 0;
   for (int k = 0; k < ns; ++k) {
     T cr = 0, ci = 0;
@@ -221,19 +255,20 @@ __device__ T stream_sinr(SinrLds<T, MP, NMAX>& S, int r, int M, int ns, T s2, T&
 }
 
 template <typename T, int MP, int NMAX, bool FULL>
-__global__ void __launch_bounds__(64) k_sinr(const DevChan* __restrict__ chans, int n_channels,
+__global__ void __launch_bounds__(64) k_sinr(const DevChan* __restrict__ chans, ScRange R,
                                               int64_t total_sc, const float2* __restrict__ X,
                                               const float2* __restrict__ C,
                                               const float2* __restrict__ G, SnrArgs snr,
                                               float* __restrict__ out, int ns_max,
                                               int32_t* status) {
   constexpr int SPB = 64 / MP;
-  __shared__ SinrLds<T, MP, NMAX> lds[SPB];
+  __shared__ SinrFwdLds<T, MP, NMAX> lds[SPB];
   const int grp = threadIdx.x / MP, r = threadIdx.x % MP;
-  SinrLds<T, MP, NMAX>& S = lds[grp];
-  const int64_t gsc = (int64_t)blockIdx.x * SPB + grp;
-  const bool valid = gsc < total_sc;
-  const int c = valid ? find_channel(chans, n_channels, gsc) : 0;
+  SinrFwdLds<T, MP, NMAX>& S = lds[grp];
+  const int64_t it = (int64_t)blockIdx.x * SPB + grp;
+  const bool valid = it < R.count;
+  int64_t gsc = 0;
+  const int c = valid ? locate_sc(R, chans, it, gsc) : 0;
   const DevChan& ch = chans[c];
   const int64_t s = gsc - ch.sc;
   int M, N;
@@ -441,14 +476,15 @@ __device__ __forceinline__ void lane_svd(bool valid, int m, int n, int ns, int p
 }
 
 template <int M, int NS>
-__global__ void __launch_bounds__(64) k_sinr_lane(const DevChan* __restrict__ chans, int n_channels,
+__global__ void __launch_bounds__(64) k_sinr_lane(const DevChan* __restrict__ chans, ScRange R,
                                                    int64_t total_sc, const float2* __restrict__ C,
                                                    const float2* __restrict__ G, SnrArgs snr,
                                                    float* __restrict__ out, int ns_max,
                                                    int32_t* status) {
-  const int64_t gsc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = gsc < total_sc;
-  const int c = valid ? find_channel(chans, n_channels, gsc) : 0;
+  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = it < R.count;
+  int64_t gsc = 0;
+  const int c = valid ? locate_sc(R, chans, it, gsc) : 0;
   const DevChan& ch = chans[c];
   const int64_t s = valid ? gsc - ch.sc : 0;
   const int m = ch.m, n = ch.n;
@@ -569,14 +605,15 @@ __global__ void __launch_bounds__(64) k_sinr_lane(const DevChan* __restrict__ ch
 // so the gradient is formed column by column from recomputed columns of Ht.
 template <int M, int NS>
 __global__ void __launch_bounds__(64) k_sinr_bwd_lane(const DevChan* __restrict__ chans,
-                                                       int n_channels, int64_t total_sc,
+                                                       ScRange R, int64_t total_sc,
                                                        const float2* __restrict__ C,
                                                        const float2* __restrict__ G, SnrArgs snr,
                                                        const float* __restrict__ gsinr, int ns_max,
                                                        char* ws, int32_t* status) {
-  const int64_t gsc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = gsc < total_sc;
-  const int c = valid ? find_channel(chans, n_channels, gsc) : 0;
+  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = it < R.count;
+  int64_t gsc = 0;
+  const int c = valid ? locate_sc(R, chans, it, gsc) : 0;
   const DevChan& ch = chans[c];
   const int64_t s = valid ? gsc - ch.sc : 0;
   const int m = ch.m, n = ch.n;
@@ -886,7 +923,7 @@ __global__ void __launch_bounds__(64) k_sinr_bwd_lane(const DevChan* __restrict_
 // dl/dHt per subcarrier goes to the workspace; k_sinr_bwd_reduce forms dl/dG and dl/dC.
 
 template <typename T, int MP, int NMAX>
-__global__ void __launch_bounds__(64) k_sinr_bwd(const DevChan* __restrict__ chans, int n_channels,
+__global__ void __launch_bounds__(64) k_sinr_bwd(const DevChan* __restrict__ chans, ScRange R,
                                                   int64_t total_sc, const float2* __restrict__ C,
                                                   const float2* __restrict__ G, SnrArgs snr,
                                                   const float* __restrict__ gsinr, int ns_max,
@@ -895,9 +932,10 @@ __global__ void __launch_bounds__(64) k_sinr_bwd(const DevChan* __restrict__ cha
   __shared__ SinrLds<T, MP, NMAX> lds[SPB];
   const int grp = threadIdx.x / MP, r = threadIdx.x % MP;
   SinrLds<T, MP, NMAX>& S = lds[grp];
-  const int64_t gsc = (int64_t)blockIdx.x * SPB + grp;
-  const bool valid = gsc < total_sc;
-  const int c = valid ? find_channel(chans, n_channels, gsc) : 0;
+  const int64_t it = (int64_t)blockIdx.x * SPB + grp;
+  const bool valid = it < R.count;
+  int64_t gsc = 0;
+  const int c = valid ? locate_sc(R, chans, it, gsc) : 0;
   const DevChan& ch = chans[c];
   const int64_t s = gsc - ch.sc;
   int M, N;
@@ -1211,105 +1249,133 @@ __global__ void __launch_bounds__(256) k_sinr_bwd_reduce(const DevChan* __restri
     }                                                                \
   } while (0)
 
+// Range of SINR classes [k0, k1) of the plan; count 0 when they hold no channel.
+static ScRange sc_range(const LaunchCtx& L, int k0, int k1) {
+  ScRange R;
+  const int j0 = L.sc_j[k0], j1 = L.sc_j[k1];
+  R.ch = L.d_sc_ch + j0;
+  R.off = L.d_sc_off + j0;
+  R.n = j1 - j0;
+  R.base = L.sc_base[k0];
+  R.count = L.sc_base[k1] - L.sc_base[k0];
+  return R;
+}
+
+static int sc_maxn(const LaunchCtx& L, int k0, int k1) {
+  int v = 0;
+  for (int k = k0; k < k1; ++k) v = std::max(v, L.sc_maxn[k]);
+  return v;
+}
+
 template <int MP, int NMAX, bool FULL>
-static gt_status sinr_launch_t(const LaunchCtx& L, int64_t total_sc, const float2* X,
-                               const float2* C, const float2* G, const SnrArgs& a, float* out,
-                               int ns_max, int32_t* status) {
+static gt_status sinr_launch_t(const LaunchCtx& L, const ScRange& R, int64_t total_sc,
+                               const float2* X, const float2* C, const float2* G, const SnrArgs& a,
+                               float* out, int ns_max, int32_t* status) {
   constexpr int SPB = 64 / MP;
-  const unsigned grid = (unsigned)((total_sc + SPB - 1) / SPB);
-  GT_LAUNCH((k_sinr<float, MP, NMAX, FULL>), dim3(grid), dim3(64), L.d_chans, L.n_channels, total_sc,
-            X, C, G, a, out, ns_max, status);
+  const unsigned grid = (unsigned)((R.count + SPB - 1) / SPB);
+  GT_LAUNCH((k_sinr<float, MP, NMAX, FULL>), dim3(grid), dim3(64), L.d_chans, R, total_sc, X, C, G,
+            a, out, ns_max, status);
   return GT_OK;
 }
 
+template <int M, int NS>
+static gt_status sinr_lane_t(const LaunchCtx& L, const ScRange& R, int64_t total_sc,
+                             const float2* C, const float2* G, const SnrArgs& a, float* out,
+                             int ns_max, int32_t* status) {
+  const unsigned grid = (unsigned)((R.count + 63) / 64);
+  GT_LAUNCH((k_sinr_lane<M, NS>), dim3(grid), dim3(64), L.d_chans, R, total_sc, C, G, a, out, ns_max,
+            status);
+  return GT_OK;
+}
+
+// One launch per non-empty SINR class: the per-lane kernel for m <= 8, the cooperative one
+// for larger m; the full-channel form runs one cooperative launch over every channel.
 gt_status launch_sinr(const LaunchCtx& L, int64_t total_sc, bool full, const float2* X,
                       const float2* C, const float2* G, const float* s2, int n_snr, float* out,
                       int ns_max, int32_t* status) {
   SnrArgs a{};
   a.n = n_snr;
   for (int k = 0; k < n_snr; ++k) a.s2[k] = s2[k];
-  const int M = full ? L.max_nr : L.max_m;
-  const int N = full ? L.max_nt : L.max_n;
-  if (!full && M <= 8) {
-    const unsigned grid = (unsigned)((total_sc + 63) / 64);
-    if (M <= 4) {
-      if (L.max_ns <= 2)
-        GT_LAUNCH((k_sinr_lane<4, 2>), dim3(grid), dim3(64), L.d_chans, L.n_channels, total_sc, C, G, a,
-                  out, ns_max, status);
-      else
-        GT_LAUNCH((k_sinr_lane<4, 4>), dim3(grid), dim3(64), L.d_chans, L.n_channels, total_sc, C, G, a,
-                  out, ns_max, status);
-    } else if (L.max_ns <= 4) {
-      GT_LAUNCH((k_sinr_lane<8, 4>), dim3(grid), dim3(64), L.d_chans, L.n_channels, total_sc, C, G, a,
-                out, ns_max, status);
-    } else {
-      GT_LAUNCH((k_sinr_lane<8, 8>), dim3(grid), dim3(64), L.d_chans, L.n_channels, total_sc, C, G, a,
-                out, ns_max, status);
-    }
-    return GT_OK;
-  }
   if (full) {
-    if (M <= 4) return sinr_launch_t<4, 1, true>(L, total_sc, X, C, G, a, out, ns_max, status);
-    if (M <= 8) return sinr_launch_t<8, 1, true>(L, total_sc, X, C, G, a, out, ns_max, status);
-    return sinr_launch_t<16, 1, true>(L, total_sc, X, C, G, a, out, ns_max, status);
+    const ScRange R = sc_range(L, 0, SC_COUNT);
+    const int M = L.max_nr;
+    if (M <= 4) return sinr_launch_t<4, 1, true>(L, R, total_sc, X, C, G, a, out, ns_max, status);
+    if (M <= 8) return sinr_launch_t<8, 1, true>(L, R, total_sc, X, C, G, a, out, ns_max, status);
+    return sinr_launch_t<16, 1, true>(L, R, total_sc, X, C, G, a, out, ns_max, status);
   }
-  if (M <= 4) {
-    if (N <= 16) return sinr_launch_t<4, 16, false>(L, total_sc, X, C, G, a, out, ns_max, status);
-    return sinr_launch_t<4, 64, false>(L, total_sc, X, C, G, a, out, ns_max, status);
+  for (int k = 0; k < SC_COUNT; ++k) {
+    const ScRange R = sc_range(L, k, k + 1);
+    if (R.count == 0) continue;
+    gt_status st = GT_OK;
+    switch (k) {
+      case SC_LANE4_2: st = sinr_lane_t<4, 2>(L, R, total_sc, C, G, a, out, ns_max, status); break;
+      case SC_LANE4_4: st = sinr_lane_t<4, 4>(L, R, total_sc, C, G, a, out, ns_max, status); break;
+      case SC_LANE8_4: st = sinr_lane_t<8, 4>(L, R, total_sc, C, G, a, out, ns_max, status); break;
+      case SC_LANE8_8: st = sinr_lane_t<8, 8>(L, R, total_sc, C, G, a, out, ns_max, status); break;
+      case SC_COOP_32:
+        st = sinr_launch_t<16, 32, false>(L, R, total_sc, X, C, G, a, out, ns_max, status);
+        break;
+      default:
+        st = sinr_launch_t<16, 64, false>(L, R, total_sc, X, C, G, a, out, ns_max, status);
+        break;
+    }
+    if (st != GT_OK) return st;
   }
-  if (M <= 8) {
-    if (N <= 16) return sinr_launch_t<8, 16, false>(L, total_sc, X, C, G, a, out, ns_max, status);
-    if (N <= 32) return sinr_launch_t<8, 32, false>(L, total_sc, X, C, G, a, out, ns_max, status);
-    return sinr_launch_t<8, 64, false>(L, total_sc, X, C, G, a, out, ns_max, status);
-  }
-  if (N <= 32) return sinr_launch_t<16, 32, false>(L, total_sc, X, C, G, a, out, ns_max, status);
-  return sinr_launch_t<16, 64, false>(L, total_sc, X, C, G, a, out, ns_max, status);
+  return GT_OK;
 }
 
 gt_status launch_grad_cg(const LaunchCtx& L, const float2* C, const float2* G, float2* gC, float2* gG);
 
 template <int MP, int NMAX>
-static gt_status sinr_bwd_t(const LaunchCtx& L, int64_t total_sc, const float2* C, const float2* G,
-                            const SnrArgs& a, const float* gs, int ns_max, int32_t* status) {
+static gt_status sinr_bwd_t(const LaunchCtx& L, const ScRange& R, int64_t total_sc, const float2* C,
+                            const float2* G, const SnrArgs& a, const float* gs, int ns_max,
+                            int32_t* status) {
   constexpr int SPB = 64 / MP;
-  const unsigned grid = (unsigned)((total_sc + SPB - 1) / SPB);
-  GT_LAUNCH((k_sinr_bwd<float, MP, NMAX>), dim3(grid), dim3(64), L.d_chans, L.n_channels, total_sc, C,
-            G, a, gs, ns_max, L.ws, status);
+  const unsigned grid = (unsigned)((R.count + SPB - 1) / SPB);
+  GT_LAUNCH((k_sinr_bwd<float, MP, NMAX>), dim3(grid), dim3(64), L.d_chans, R, total_sc, C, G, a, gs,
+            ns_max, L.ws, status);
   return GT_OK;
 }
 
+template <int M, int NS>
+static gt_status sinr_bwd_lane_t(const LaunchCtx& L, const ScRange& R, int64_t total_sc,
+                                 const float2* C, const float2* G, const SnrArgs& a, const float* gs,
+                                 int ns_max, int32_t* status) {
+  const unsigned grid = (unsigned)((R.count + 63) / 64);
+  GT_LAUNCH((k_sinr_bwd_lane<M, NS>), dim3(grid), dim3(64), L.d_chans, R, total_sc, C, G, a, gs,
+            ns_max, L.ws, status);
+  return GT_OK;
+}
+
+// The adjoint: the per-lane kernel for m <= 8 with ns <= 4, the cooperative one for the rest
+// (m <= 8 with ns > 4 on 8-lane groups sized by n), one launch per non-empty class, then the
+// per-group reduction into dl/dC and dl/dG.
 gt_status launch_sinr_bwd(const LaunchCtx& L, int64_t total_sc, const float2* C, const float2* G,
                           const float* s2, int n_snr, const float* gsinr, float2* gC, float2* gG,
                           int ns_max, int32_t* status) {
   SnrArgs a{};
   a.n = n_snr;
   for (int k = 0; k < n_snr; ++k) a.s2[k] = s2[k];
-  gt_status st;
-  const int M = L.max_m, N = L.max_n;
-  if (M <= 8 && L.max_ns <= 4) {
-    const unsigned grid = (unsigned)((total_sc + 63) / 64);
-    if (M <= 4 && L.max_ns <= 2)
-      GT_LAUNCH((k_sinr_bwd_lane<4, 2>), dim3(grid), dim3(64), L.d_chans, L.n_channels, total_sc, C, G,
-                a, gsinr, ns_max, L.ws, status);
-    else if (M <= 4)
-      GT_LAUNCH((k_sinr_bwd_lane<4, 4>), dim3(grid), dim3(64), L.d_chans, L.n_channels, total_sc, C, G,
-                a, gsinr, ns_max, L.ws, status);
-    else
-      GT_LAUNCH((k_sinr_bwd_lane<8, 4>), dim3(grid), dim3(64), L.d_chans, L.n_channels, total_sc, C, G,
-                a, gsinr, ns_max, L.ws, status);
-    return launch_grad_cg(L, C, G, gC, gG);
+  for (int k = 0; k < SC_COUNT; ++k) {
+    const ScRange R = sc_range(L, k, k + 1);
+    if (R.count == 0) continue;
+    gt_status st = GT_OK;
+    switch (k) {
+      case SC_LANE4_2: st = sinr_bwd_lane_t<4, 2>(L, R, total_sc, C, G, a, gsinr, ns_max, status); break;
+      case SC_LANE4_4: st = sinr_bwd_lane_t<4, 4>(L, R, total_sc, C, G, a, gsinr, ns_max, status); break;
+      case SC_LANE8_4: st = sinr_bwd_lane_t<8, 4>(L, R, total_sc, C, G, a, gsinr, ns_max, status); break;
+      case SC_LANE8_8: {
+        const int N = sc_maxn(L, k, k + 1);
+        st = N <= 16 ? sinr_bwd_t<8, 16>(L, R, total_sc, C, G, a, gsinr, ns_max, status)
+                     : (N <= 32 ? sinr_bwd_t<8, 32>(L, R, total_sc, C, G, a, gsinr, ns_max, status)
+                                : sinr_bwd_t<8, 64>(L, R, total_sc, C, G, a, gsinr, ns_max, status));
+        break;
+      }
+      case SC_COOP_32: st = sinr_bwd_t<16, 32>(L, R, total_sc, C, G, a, gsinr, ns_max, status); break;
+      default: st = sinr_bwd_t<16, 64>(L, R, total_sc, C, G, a, gsinr, ns_max, status); break;
+    }
+    if (st != GT_OK) return st;
   }
-  if (M <= 4)
-    st = N <= 16 ? sinr_bwd_t<4, 16>(L, total_sc, C, G, a, gsinr, ns_max, status)
-                 : sinr_bwd_t<4, 64>(L, total_sc, C, G, a, gsinr, ns_max, status);
-  else if (M <= 8)
-    st = N <= 16 ? sinr_bwd_t<8, 16>(L, total_sc, C, G, a, gsinr, ns_max, status)
-                 : (N <= 32 ? sinr_bwd_t<8, 32>(L, total_sc, C, G, a, gsinr, ns_max, status)
-                            : sinr_bwd_t<8, 64>(L, total_sc, C, G, a, gsinr, ns_max, status));
-  else
-    st = N <= 32 ? sinr_bwd_t<16, 32>(L, total_sc, C, G, a, gsinr, ns_max, status)
-                 : sinr_bwd_t<16, 64>(L, total_sc, C, G, a, gsinr, ns_max, status);
-  if (st != GT_OK) return st;
   return launch_grad_cg(L, C, G, gC, gG);
 }
 

@@ -10,7 +10,7 @@ import pytest
 import torch
 
 import synthgen
-from oracle import grad as ograd, tucker
+from oracle import grad as ograd, sinr as osinr, tucker
 from tests.gpu_util import announce, crandn, desc, dev_c64, host, unpack
 
 pytestmark = pytest.mark.gpu
@@ -85,3 +85,45 @@ def test_reconstruct_backward_matches_oracle(gpu_lib):
     for got, r, what in zip(outs2, ref2, ("a", "b", "c", "g")):
         g = unpack(plan, 0, host(got), what)
         assert np.abs(g - r).max() <= 1e-4 * max(np.abs(r).max(), 1e-30), what
+
+
+def test_sinr_mixed_kernel_classes(gpu_lib):
+    # one plan whose channels fall in every SINR kernel class (per-lane m <= 4 / 8 with
+    # ns <= 2 / 4 / 8, cooperative m > 8 with n <= 32 / 64), interleaved so that the per-class
+    # launches cover non-contiguous channels; forward and adjoint per channel against the oracle
+    shapes = [  # nsc, gs, m, n, p, ns
+        (24, 12, 2, 4, 3, 2), (26, 13, 10, 20, 4, 4), (30, 16, 6, 12, 4, 3),
+        (20, 10, 4, 8, 3, 3), (17, 8, 8, 16, 5, 6), (22, 11, 12, 40, 3, 4),
+        (9, 9, 3, 6, 2, 1)]
+    announce(f"sinr mixed kernel classes {shapes}")
+    plan = gpu_lib.Plan([desc(m, n, nsc, gs, m, n, p, ns) for nsc, gs, m, n, p, ns in shapes],
+                        iters=1)
+    Cb = np.zeros(plan.totals.c, np.complex128)
+    Gb = np.zeros(plan.totals.g, np.complex128)
+    parts = []
+    for i, (nsc, gs, m, n, p, ns) in enumerate(shapes):
+        rng, C, G = _compressed(40 + i, nsc, gs, m, n, p)
+        o = plan.offsets(i)
+        Cb[o.c:o.c + C.size] = C.reshape(-1)
+        Gb[o.g:o.g + G.size] = G.reshape(-1)
+        parts.append((C, G))
+    s2 = [0.05, 0.5]
+    sg = host(plan.sinr(dev_c64(Cb), dev_c64(Gb), s2))
+    gs_all = np.random.default_rng(3).standard_normal((2, plan.totals.sc, plan.ns_max))
+    gC, gG = plan.sinr_backward(dev_c64(Cb), dev_c64(Gb), s2,
+                                torch.as_tensor(gs_all, dtype=torch.float32).cuda())
+    gC, gG = host(gC), host(gG)
+    for i, ((nsc, gs, m, n, p, ns), (C, G)) in enumerate(zip(shapes, parts)):
+        o = plan.offsets(i)
+        Ht = ograd.compressed_channels_t(torch.as_tensor(C), torch.as_tensor(G), gs).numpy()
+        ref = osinr.sinr(Ht, s2, ns)
+        got = sg[:, o.sc:o.sc + nsc, :ns]
+        err = np.abs(10 * np.log10(got) - 10 * np.log10(ref)).max()
+        print(f"[mixed] channel {i} m={m} n={n} ns={ns}: max SINR error {err:.3e} dB", flush=True)
+        assert err <= 0.05, (i, err)
+        assert np.all(sg[:, o.sc:o.sc + nsc, ns:] == 0)
+        gC_o, gG_o = ograd.sinr_grad(C, G, gs, s2, ns, gs_all[:, o.sc:o.sc + nsc, :ns])
+        gCi = unpack(plan, i, gC, "c")
+        gGi = unpack(plan, i, gG, "g")
+        assert np.abs(gGi - gG_o).max() <= 2e-3 * np.abs(gG_o).max(), i
+        assert np.abs(gCi - gC_o).max() <= 2e-3 * np.abs(gC_o).max(), i
