@@ -927,8 +927,11 @@ __device__ __forceinline__ void bmm_prefetch_lp(uint2 (&xq)[PREC == 3 ? 2 : 1][(
 
 // PF: the next group's step-1 operands are loaded while the current group's steps 2 and 3
 // run (more registers, one block per CU); otherwise they are loaded at the start of step 1
-// and latency is hidden by a second resident block.
-template <int NT1W, int SMAX, bool PF, int PREC>
+// and latency is hidden by a second resident block.  SLC: the per-q LDS slot stride in
+// floats when every channel of the launch fits it (a compile-time stride turns the slot
+// offsets into instruction immediates instead of per-lane addresses held across the group
+// loop), or 0 for the channel's own stride.
+template <int NT1W, int SMAX, bool PF, int PREC, int SLC>
 __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* __restrict__ chans,
                                                        const float2* __restrict__ X,
                                                        const float2* __restrict__ A,
@@ -939,8 +942,10 @@ __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* _
   if (split >= ch.nsplit) return;
   const int nr = ch.nr, nt = ch.nt, m = ch.m, p = ch.p;
   const int nrnt = nr * nt;
-  const int SL = bmm_slot(nr, nt, m);
-  float* aop = smf + max(p * SL, 2048);  // [nr][64] step-2 A operand
+  const int SL = SLC ? SLC : bmm_slot(nr, nt, m);
+  // with a compile-time stride, all 16 q slots exist and step 1 stores its rows q >= p_g
+  // unconditionally (steps 2 and 3 read only q < p_g)
+  float* aop = smf + (SLC ? 16 * SLC : max(p * SL, 2048));  // [nr][64] step-2 A operand
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int h = lane / 32, col = lane % 32;
   // step-2 A operand.  m <= 8 (16 real rows) uses 16 x 16 x 4 products: lane l at K step t
@@ -972,15 +977,6 @@ __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* _
   // Gram tiles: wave w owns tile w; tiles 8 and 9 are shared, waves 0 and 1 taking them over
   // even q and waves 2 and 3 over odd q, so that each SIMD carries two and a half tiles
   const int nt2 = wave < 4 ? 2 : 1;
-  int offa[2], offb[2];
-#pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    int I, J;
-    gram_tile(t == 0 ? wave : 8 + (wave & 1), I, J);
-    const int ca = 32 * I + col, cb = 32 * J + col;
-    offa[t] = ca < 64 ? ca : m * 64 + (ca - 64);
-    offb[t] = cb < 64 ? cb : m * 64 + (cb - 64);
-  }
   f32x16 gacc[2];
 #pragma unroll
   for (int t = 0; t < 2; ++t)
@@ -995,6 +991,9 @@ __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* _
     const int s0 = g * ch.gs;
     const int sz = min(ch.gs, ch.nsc - s0);
     const int pg = min(p, sz);
+    int ol1 = lane;  // opaque copy: step 1's per-lane addresses are recomputed per group
+    asm volatile("" : "+v"(ol1));
+    const int h = ol1 / 32, col = ol1 % 32;
     if (PREC != 0) {
       // 1. Hc on 16-bit operands, K steps of 8 = two subcarriers x (re, im) per lane half
       constexpr int S8 = (2 * SMAX + 7) / 8;
@@ -1021,7 +1020,7 @@ __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* _
 #pragma unroll
           for (int r = 0; r < 16; r += 2) {
             const int q = 4 * (r / 4) + 2 * h + ((r % 4) >> 1);
-            if (q < pg)
+            if (SLC || q < pg)
               *reinterpret_cast<float2*>(smf + q * SL + 2 * c) = make_float2(acc1[r], acc1[r + 1]);
           }
       }
@@ -1045,7 +1044,7 @@ __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* _
 #pragma unroll
           for (int r = 0; r < 16; r += 2) {
             const int q = 4 * (r / 4) + 2 * h + ((r % 4) >> 1);
-            if (q < pg)
+            if (SLC || q < pg)
               *reinterpret_cast<float2*>(smf + q * SL + 2 * c) = make_float2(acc1[r], acc1[r + 1]);
           }
       }
@@ -1057,45 +1056,51 @@ __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* _
     // both column tiles are read before either is written back; loads are unconditional
     // (clamped) and out-of-range operands are zeroed by selects, four K steps per batch
     if (w16) {
-      // rows (a, re/im) < 16, four 16-column tiles of j, K = (i, re/im) in steps of 4
-      const int r16 = lane % 16, k4 = lane / 16;
+      // rows (a, re/im) < 16, four 16-column tiles of j, K = (i, re/im) in steps of 4; every
+      // operand of four K steps is loaded before their products (nr <= 16: at most 8).  Lane
+      // (k4, r16) at step t reads Hc[i = 2 t + k4 / 2][j = 16 jt + r16], part k4 % 2: one
+      // per-lane base plus a uniform step offset and an immediate tile offset.  Reads past row
+      // nr - 1 or column nt - 1 stay inside the block's LDS (the allocation is padded) and are
+      // zeroed by selects.
+      int ol = lane;  // opaque copy: the per-lane offsets below are recomputed per group
+      asm volatile("" : "+v"(ol));
+      const int r16 = ol % 16, k4 = ol / 16;
+      const int nst = (nr + 1) / 2;
+      const int lb = 2 * (k4 >> 1) * nt + 2 * r16 + (k4 & 1);
+      bool jv[4];
+#pragma unroll
+      for (int jt = 0; jt < 4; ++jt) jv[jt] = 16 * jt + r16 < nt;
       for (int q = wave; q < pg; q += 8) {
         float* slot = smf + q * SL;
+        const float* src = slot + lb;
         f32x4 acc4[4];
 #pragma unroll
         for (int jt = 0; jt < 4; ++jt)
 #pragma unroll
           for (int r = 0; r < 4; ++r) acc4[jt][r] = 0.f;
-        int jc[4];
-        bool jv[4];
 #pragma unroll
-        for (int jt = 0; jt < 4; ++jt) {
-          jc[jt] = min(16 * jt + r16, nt - 1);
-          jv[jt] = 16 * jt + r16 < nt;
-        }
-        const int nst = (nr + 1) / 2;
-        for (int t0 = 0; t0 < nst; t0 += 2) {
-          float av[2], bv[2][4];
+        for (int tb = 0; tb < 8; tb += 4)
+          if (tb < nst) {  // four K steps: all loads, then the products
+            float av[4], bv[4][4];
 #pragma unroll
-          for (int d = 0; d < 2; ++d) {
-            const int t = min(t0 + d, nst - 1);
-            const bool tv = t0 + d < nst;
-            const int kk = 4 * t + k4, i = min(kk >> 1, nr - 1);
-            const bool iv = tv && (kk >> 1) < nr;
-            const float x = aop[t * 64 + lane];
-            av[d] = tv ? x : 0.f;
+            for (int d = 0; d < 4; ++d)
+              if (tb + d < nst) {
+                const int t = tb + d;
+                const bool iv = 2 * t + (k4 >> 1) < nr;
+                av[d] = aop[t * 64 + lane];
 #pragma unroll
-            for (int jt = 0; jt < 4; ++jt) {
-              const float y = slot[2 * (i * nt + jc[jt]) + (kk & 1)];
-              bv[d][jt] = (iv && jv[jt]) ? y : 0.f;
-            }
+                for (int jt = 0; jt < 4; ++jt) {
+                  const float y = src[t * 4 * nt + 32 * jt];
+                  bv[d][jt] = (iv && jv[jt]) ? y : 0.f;
+                }
+              }
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+              if (tb + d < nst)
+#pragma unroll
+                for (int jt = 0; jt < 4; ++jt)
+                  acc4[jt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[d], bv[d][jt], acc4[jt], 0, 0, 0);
           }
-#pragma unroll
-          for (int d = 0; d < 2; ++d)
-#pragma unroll
-            for (int jt = 0; jt < 4; ++jt)
-              acc4[jt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[d], bv[d][jt], acc4[jt], 0, 0, 0);
-        }
         // accumulator (lane l, register r) = row 4 (l / 16) + r, column 16 jt + l % 16
 #pragma unroll
         for (int jt = 0; jt < 4; ++jt)
@@ -1145,26 +1150,44 @@ __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* _
     __syncthreads();
     // 3. Gram over the rows (q, a) of W, q < p_g, two rows a0 + h of one q per step (an
     // odd m pads each q with a zero row); two steps per batch, loads unconditional
-    for (int q = 0; q < pg; ++q) {
-      const float* qb = smf + q * SL;
-      const bool two = nt2 == 2 && (q & 1) == (wave >> 1);
-      for (int a0 = 0; a0 < m; a0 += 4) {
-        const int ra = a0 + h, rb2 = a0 + 2 + h;
-        const float sa = ra < m ? 1.f : 0.f, sb = rb2 < m ? 1.f : 0.f;
-        const float* p0 = qb + min(ra, m - 1) * 64;
-        const float* p1 = qb + min(rb2, m - 1) * 64;
-        if (two) {
-          const float x00 = p0[offa[0]], y00 = p0[offb[0]], x01 = p0[offa[1]], y01 = p0[offb[1]];
-          const float x10 = p1[offa[0]], y10 = p1[offb[0]], x11 = p1[offa[1]], y11 = p1[offb[1]];
-          gacc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(sa * x00, y00, gacc[0], 0, 0, 0);
-          gacc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(sa * x01, y01, gacc[1], 0, 0, 0);
-          gacc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(sb * x10, y10, gacc[0], 0, 0, 0);
-          gacc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(sb * x11, y11, gacc[1], 0, 0, 0);
-        } else {
-          const float x00 = p0[offa[0]], y00 = p0[offb[0]];
-          const float x10 = p1[offa[0]], y10 = p1[offb[0]];
-          gacc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(sa * x00, y00, gacc[0], 0, 0, 0);
-          gacc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(sb * x10, y10, gacc[0], 0, 0, 0);
+    {
+      // per-lane offsets are derived here from an opaque copy of the lane index, so that the
+      // compiler recomputes them per group instead of holding them across steps 1 and 2
+      int ol = lane;
+      asm volatile("" : "+v"(ol));
+      const int h = ol / 32, col = ol % 32;
+      int offa[2], offb[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        int I, J;
+        gram_tile(t == 0 ? wave : 8 + (wave & 1), I, J);
+        const int ca = 32 * I + col, cb = 32 * J + col;
+        offa[t] = ca < 64 ? ca : m * 64 + (ca - 64);
+        offb[t] = cb < 64 ? cb : m * 64 + (cb - 64);
+      }
+      const bool t2 = nt2 == 2;
+      const int par = wave >> 1;
+      for (int q = 0; q < pg; ++q) {
+        const float* qb = smf + q * SL;
+        const bool two = t2 && (q & 1) == par;
+        for (int a0 = 0; a0 < m; a0 += 4) {
+          const int ra = a0 + h, rb2 = a0 + 2 + h;
+          const float sa = ra < m ? 1.f : 0.f, sb = rb2 < m ? 1.f : 0.f;
+          const float* p0 = qb + min(ra, m - 1) * 64;
+          const float* p1 = qb + min(rb2, m - 1) * 64;
+          if (two) {
+            const float x00 = p0[offa[0]], y00 = p0[offb[0]], x01 = p0[offa[1]], y01 = p0[offb[1]];
+            const float x10 = p1[offa[0]], y10 = p1[offb[0]], x11 = p1[offa[1]], y11 = p1[offb[1]];
+            gacc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(sa * x00, y00, gacc[0], 0, 0, 0);
+            gacc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(sa * x01, y01, gacc[1], 0, 0, 0);
+            gacc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(sb * x10, y10, gacc[0], 0, 0, 0);
+            gacc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(sb * x11, y11, gacc[1], 0, 0, 0);
+          } else {
+            const float x00 = p0[offa[0]], y00 = p0[offb[0]];
+            const float x10 = p1[offa[0]], y10 = p1[offb[0]];
+            gacc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(sa * x00, y00, gacc[0], 0, 0, 0);
+            gacc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(sb * x10, y10, gacc[0], 0, 0, 0);
+          }
         }
       }
     }
@@ -2063,9 +2086,14 @@ bool fused_b_mfma_ok(const LaunchCtx& L) {
          bm_bytes(L) <= 64 * 1024;
 }
 
+// compile-time slot stride of the launch (0: per channel)
+static int bmm_slc(const LaunchCtx& L) { return bmm_slot(L.max_nr, L.max_nt, L.max_m) <= 1024 ? 1024 : 0; }
+
 static size_t bmm_bytes(const LaunchCtx& L) {
-  return sizeof(float) * (std::max<size_t>((size_t)L.max_p * bmm_slot(L.max_nr, L.max_nt, L.max_m), 2048) +
-                          (size_t)L.max_nr * 64);
+  // + 128 floats: step-2 operand reads run up to 127 floats past a slot's last row
+  const size_t slots = bmm_slc(L) ? (size_t)16 * bmm_slc(L)
+                                  : std::max<size_t>((size_t)L.max_p * bmm_slot(L.max_nr, L.max_nt, L.max_m), 2048);
+  return sizeof(float) * (slots + (size_t)L.max_nr * 64 + 128);
 }
 
 // All-matrix-core variant: p, m <= 16 (32 real rows of steps 1 and 2), nt <= 64, a group's
@@ -2086,11 +2114,18 @@ gt_status launch_fused_b(const LaunchCtx& L, const float2* X, const float2* A, c
     const dim3 grid(L.max_nsplit, L.n_channels);
     const size_t sh = bmm_bytes(L);
     const bool pf = L.tune_bstep == 1 && L.ttm_prec == GT_TTM_FP32;
-#define GT_BMM(NT1W, SMAX, PREC)                                                                    \
-  if (PREC == 0 && pf)                                                                           \
-    GT_LAUNCH_SH((k_fused_b_mm<NT1W, SMAX, true, 0>), grid, dim3(512), sh, L.d_chans, X, A, C, L.ws); \
-  else                                                                                           \
-    GT_LAUNCH_SH((k_fused_b_mm<NT1W, SMAX, false, PREC>), grid, dim3(512), sh, L.d_chans, X, A, C, L.ws)
+    const bool slc = bmm_slc(L) != 0;
+#define GT_BMM_S(NT1W, SMAX, PF, PREC)                                                                     \
+  if (slc)                                                                                                 \
+    GT_LAUNCH_SH((k_fused_b_mm<NT1W, SMAX, PF, PREC, 1024>), grid, dim3(512), sh, L.d_chans, X, A, C, L.ws); \
+  else                                                                                                     \
+    GT_LAUNCH_SH((k_fused_b_mm<NT1W, SMAX, PF, PREC, 0>), grid, dim3(512), sh, L.d_chans, X, A, C, L.ws)
+#define GT_BMM(NT1W, SMAX, PREC)   \
+  if (PREC == 0 && pf) {           \
+    GT_BMM_S(NT1W, SMAX, true, 0); \
+  } else {                         \
+    GT_BMM_S(NT1W, SMAX, false, PREC); \
+  }
 #define GT_BMM_PREC(NT1W, SMAX)                          \
   switch (L.ttm_prec) {                                  \
     case GT_TTM_BF16: GT_BMM(NT1W, SMAX, 1); break;      \
@@ -2105,6 +2140,7 @@ gt_status launch_fused_b(const LaunchCtx& L, const float2* X, const float2* A, c
     }
 #undef GT_BMM_PREC
 #undef GT_BMM
+#undef GT_BMM_S
     GT_LAUNCH_SH(k_reduce_S2_mfma, dim3((L.max_nt * L.max_nt + 255) / 256, L.n_channels), dim3(256), 0,
                  L.d_chans, L.ws);
     return GT_OK;
