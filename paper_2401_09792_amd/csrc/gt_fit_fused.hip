@@ -173,34 +173,78 @@ __device__ __forceinline__ void fused_t_finish(const DevChan& ch, const GroupIte
   }
   if (!do_c) return;
   __syncthreads();
-  // Yh_s = A^H T_s: a thread owns column b of one T_s (in registers) and forms all m rows
   float2* Yg = wsp2(ws, ch.w_Yh) + (int64_t)s0 * m * n;
-  for (int sb = tid; sb < sz * n; sb += 256) {
-    const int s = sb / n, b = sb - s * n;
-    float2 tc[16];
+  const int ys = m * n + 2;  // LDS stride of Yh_s (complex): consecutive subcarriers 4 banks apart
+  if (m <= 8 && n <= 16 && nr <= 16) {
+    // Yh_s = A^H T_s on 16 x 16 x 4 matrix cores, one subcarrier per wave at a time: rows
+    // (a, re/im), columns b, K = (i, re/im) in steps of 4 (lane l: row / column l % 16,
+    // k' = 4 t + l / 16); the A operand is the sign-arranged real form of A^H
+    const int lane = tid % 64, r16 = lane % 16, k4 = lane / 16;
+    const int nst = (nr + 1) / 2;
+    const float* Tsf = reinterpret_cast<const float*>(Ts);
+    float* Yhf = reinterpret_cast<float*>(Yh);
+    float* Ygf = reinterpret_cast<float*>(Yg);
+    float aop[8];
 #pragma unroll
-    for (int i = 0; i < 16; ++i)
-      tc[i] = i < nr ? Ts[(s * nr + i) * n + b] : make_float2(0.f, 0.f);
-    for (int a = 0; a < m; ++a) {
-      float yr = 0.f, yi = 0.f;
+    for (int t = 0; t < 8; ++t) {
+      const int kk = 4 * t + k4, i = kk >> 1, kp = kk & 1, a = r16 >> 1, pp = r16 & 1;
+      const float2 av = As[min(i, nr - 1) * m + min(a, m - 1)];
+      const float v = pp == 0 ? (kp == 0 ? av.x : av.y) : (kp == 0 ? -av.y : av.x);
+      aop[t] = (t < nst && a < m && i < nr) ? v : 0.f;
+    }
+    for (int s = wave; s < sz; s += 4) {
+      f32x4 acc4;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        if (i < nr) {
-          const float2 av = As[i * m + a];
-          yr += av.x * tc[i].x + av.y * tc[i].y;
-          yi += av.x * tc[i].y - av.y * tc[i].x;
+      for (int r = 0; r < 4; ++r) acc4[r] = 0.f;
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        if (t < nst) {
+          const int kk = 4 * t + k4, i = kk >> 1;
+          const float y = Tsf[2 * ((s * nr + min(i, nr - 1)) * n + min(r16, n - 1)) + (kk & 1)];
+          acc4 = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[t], (i < nr && r16 < n) ? y : 0.f, acc4, 0, 0, 0);
+        }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 4 * k4 + r, a = row >> 1;
+        if (a < m && r16 < n) {
+          const int o = 2 * ((s * m + a) * n + r16) + (row & 1);
+          Yhf[2 * s * ys + o - 2 * s * m * n] = acc4[r];
+          if (do_c == 2) Ygf[o] = acc4[r];
         }
       }
-      const int o = (s * m + a) * n + b;
-      Yh[o] = make_float2(yr, yi);
-      if (do_c == 2) Yg[o] = make_float2(yr, yi);
+    }
+  } else {
+    // a thread owns column b of one T_s (in registers) and forms all m rows
+    for (int sb = tid; sb < sz * n; sb += 256) {
+      const int s = sb / n, b = sb - s * n;
+      float2 tc[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        tc[i] = i < nr ? Ts[(s * nr + i) * n + b] : make_float2(0.f, 0.f);
+      for (int a = 0; a < m; ++a) {
+        float yr = 0.f, yi = 0.f;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          if (i < nr) {
+            const float2 av = As[i * m + a];
+            yr += av.x * tc[i].x + av.y * tc[i].y;
+            yi += av.x * tc[i].y - av.y * tc[i].x;
+          }
+        }
+        const int o = (s * m + a) * n + b;
+        Yh[s * ys + a * n + b] = make_float2(yr, yi);
+        if (do_c == 2) Yg[o] = make_float2(yr, yi);
+      }
     }
   }
   __syncthreads();
-  // S3[s][t] = <Yh_s, Yh_t> on the upper triangle (16 lanes per entry), mirrored below
+  // S3[s][t] = <Yh_s, Yh_t> on the upper triangle (16 lanes per entry), mirrored below (zero
+  // where t is past the group).  On matrix cores this Gram used two waves of the four and made
+  // the split fit slower; the vector form keeps all four busy.
+  const int gs = ch.gs, mn = m * n;
+  float2* S3 = wsp2(ws, ch.w_S3) + (int64_t)it.g * gs * gs;
   {
-    const int gs = ch.gs, mn = m * n, l16 = tid % 16;
-    float2* S3 = wsp2(ws, ch.w_S3) + (int64_t)it.g * gs * gs;
+    const int l16 = tid % 16;
     for (int k = tid / 16; k < gs * (gs + 1) / 2; k += 16) {
       int s = 0, rem = k;
       while (rem >= gs - s) {
@@ -211,7 +255,7 @@ __device__ __forceinline__ void fused_t_finish(const DevChan& ch, const GroupIte
       float ar = 0.f, ai = 0.f;
       if (t < sz)
         for (int e = l16; e < mn; e += 16) {
-          const float2 x = Yh[s * mn + e], y = Yh[t * mn + e];
+          const float2 x = Yh[s * ys + e], y = Yh[t * ys + e];
           ar += x.x * y.x + x.y * y.y;
           ai += x.y * y.x - x.x * y.y;
         }
@@ -253,7 +297,7 @@ __global__ void __launch_bounds__(256) k_fused_t_mfma(const DevChan* __restrict_
   const int wave = tid / 64, lane = tid % 64;
   // region 0 holds the real-form B ([2 nt][32] floats) for the product and Yh (sz x m x n)
   // afterwards
-  const int reg0 = max(nt * 32, ch.gs * m * n);
+  const int reg0 = max(nt * 32, ch.gs * (m * n + 2));
   float* Bt = reinterpret_cast<float*>(smem);
   float2* Yh = smem;
   float2* As = smem + reg0;                           // nr x m
@@ -1921,7 +1965,7 @@ bool fused_fit_ok(const LaunchCtx& L) {
 }
 
 static size_t tm_bytes(const LaunchCtx& L) {
-  return sizeof(float2) * (std::max<size_t>((size_t)L.max_nt * 32, (size_t)L.max_gs * L.max_m * L.max_n) +
+  return sizeof(float2) * (std::max<size_t>((size_t)L.max_nt * 32, (size_t)L.max_gs * (L.max_m * L.max_n + 2)) +
                            (size_t)L.max_nr * L.max_m + (size_t)L.max_gs * L.max_nr * L.max_n);
 }
 
@@ -1929,7 +1973,7 @@ static size_t tlp_bytes(const LaunchCtx& L) {
   const size_t nq = L.ttm_prec == GT_TTM_SPLIT_BF16 ? 2 : 1;
   return nq * 32 * 2 * L.max_nt * sizeof(unsigned short) +
          sizeof(float2) * ((size_t)L.max_nr * L.max_m + (size_t)L.max_gs * L.max_nr * L.max_n +
-                           (size_t)L.max_gs * L.max_m * L.max_n);
+                           (size_t)L.max_gs * (L.max_m * L.max_n + 2));
 }
 
 static int bmm_variant(const LaunchCtx& L);
