@@ -553,12 +553,25 @@ __global__ void __launch_bounds__(256) k_fused_z(const DevChan* __restrict__ cha
   for (int e = tid; e < sz * p; e += 256) Cs[e] = C[ch.c + (int64_t)s0 * p + e];
   __syncthreads();
   if (do_a) {
+    // a thread owns entry e of T_s for QC consecutive q: each T entry is read from memory once
+    // per chunk of q, not once per q
     const float2* Tg = wsp2(ws, ch.w_T) + (int64_t)s0 * nr * n;
-    for (int o = tid; o < pg * nr * n; o += 256) {
-      const int q = o / (nr * n), e = o % (nr * n);
-      Cx<float> z{0.f, 0.f};
-      for (int s = 0; s < sz; ++s) cfmac(z, ld(Cs + s * p + q), ld(Tg + s * nr * n + e));
-      Zs[o] = make_float2(z.re, z.im);
+    constexpr int QC = 6;
+    const int nrn = nr * n, nqc = (pg + QC - 1) / QC;
+    for (int o = tid; o < nqc * nrn; o += 256) {
+      const int qc = o / nrn, e = o - qc * nrn;
+      Cx<float> z[QC];
+#pragma unroll
+      for (int j = 0; j < QC; ++j) z[j] = Cx<float>{0.f, 0.f};
+      for (int s = 0; s < sz; ++s) {
+        const Cx<float> tv = ld(Tg + s * nrn + e);
+#pragma unroll
+        for (int j = 0; j < QC; ++j)
+          if (qc * QC + j < pg) cfmac(z[j], ld(Cs + s * p + qc * QC + j), tv);
+      }
+#pragma unroll
+      for (int j = 0; j < QC; ++j)
+        if (qc * QC + j < pg) Zs[(qc * QC + j) * nrn + e] = make_float2(z[j].re, z[j].im);
     }
     __syncthreads();
     // S1[i][k] = sum_{q, b} Z_q[i][b] conj(Z_q[k][b]); four threads per output split b
