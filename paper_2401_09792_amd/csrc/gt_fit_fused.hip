@@ -574,27 +574,26 @@ __global__ void __launch_bounds__(256) k_fused_z(const DevChan* __restrict__ cha
         if (qc * QC + j < pg) Zs[(qc * QC + j) * nrn + e] = make_float2(z[j].re, z[j].im);
     }
     __syncthreads();
-    // S1[i][k] = sum_{q, b} Z_q[i][b] conj(Z_q[k][b]); four threads per output split b
-    {
-      const int o = tid / 4, part = tid % 4;
+    // S1[i][k] = sum_{q, b} Z_q[i][b] conj(Z_q[k][b]); four threads per output split b, in
+    // passes of 64 outputs (nr up to 16: 256 outputs).  The four threads of an output are
+    // aligned lanes of one pass, so they stay active together for the shuffles.
+    for (int o4 = tid; o4 < 4 * nr * nr; o4 += 256) {
+      const int o = o4 / 4, part = o4 % 4;
+      const int i = o / nr, k = o % nr;
       float ar = 0.f, ai = 0.f;
-      if (o < nr * nr) {
-        const int i = o / nr, k = o % nr;
-        for (int q = 0; q < pg; ++q) {
-          const float2* zq = Zs + q * nr * n;
-          for (int b = part; b < n; b += 4) {
-            float2 zi = zq[i * n + b], zk = zq[k * n + b];
-            ar += zi.x * zk.x + zi.y * zk.y;
-            ai += zi.y * zk.x - zi.x * zk.y;
-          }
+      for (int q = 0; q < pg; ++q) {
+        const float2* zq = Zs + q * nr * n;
+        for (int b = part; b < n; b += 4) {
+          float2 zi = zq[i * n + b], zk = zq[k * n + b];
+          ar += zi.x * zk.x + zi.y * zk.y;
+          ai += zi.y * zk.x - zi.x * zk.y;
         }
       }
       ar += __shfl_xor(ar, 1, 64);
       ai += __shfl_xor(ai, 1, 64);
       ar += __shfl_xor(ar, 2, 64);
       ai += __shfl_xor(ai, 2, 64);
-      if (o < nr * nr && part == 0)
-        wsp2(ws, ch.w_S1p)[(int64_t)it.g * nr * nr + o] = make_float2(ar, ai);
+      if (part == 0) wsp2(ws, ch.w_S1p)[(int64_t)it.g * nr * nr + o] = make_float2(ar, ai);
     }
   }
   if (do_core) {

@@ -109,6 +109,9 @@ def test_fit_small_config(gpu_lib, small_case):
     (30, 6, 10, 8, 3, 4, 3, 6, 7),        # lossy, short last group of 6
     (40, 8, 16, 12, 4, 6, 6, 5, 11),      # last group of 4 < p: p_g = 4
     (25, 4, 32, 5, 2, 8, 2, 4, 13),       # many small groups
+    # m > 8: the B-step's 32 x 32 x 2 step 2 with a per-channel slot stride (1280 floats), and
+    # the T pass's vector-ALU Yh
+    (60, 12, 40, 12, 10, 8, 6, 5, 17),
 ])
 def test_fit_lossy_random(gpu_lib, case):
     nsc, nr, nt, gs, m, n, p, iters, seed = case
