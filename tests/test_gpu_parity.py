@@ -112,6 +112,12 @@ def test_fit_small_config(gpu_lib, small_case):
     # m > 8: the B-step's 32 x 32 x 2 step 2 with a per-channel slot stride (1280 floats), and
     # the T pass's vector-ALU Yh
     (60, 12, 40, 12, 10, 8, 6, 5, 17),
+    # groups of 24 (the B-step pass's 24-slice variant, two T tiles per wave), short last group
+    (70, 8, 32, 24, 4, 8, 10, 5, 29),
+    # groups of 32 (past the all-matrix-core B-step pass's limit)
+    (64, 4, 16, 32, 3, 6, 8, 5, 31),
+    # nr = 16, the largest receive array of the fused passes
+    (70, 16, 16, 12, 12, 6, 6, 5, 37),
 ])
 def test_fit_lossy_random(gpu_lib, case):
     nsc, nr, nt, gs, m, n, p, iters, seed = case
