@@ -188,3 +188,25 @@ def test_zero_stream_status(gpu_lib):
     out = host(plan.sinr(dev_c64(Cm), dev_c64(G), [0.5], status=st))
     assert int(st.item()) & 8
     assert np.all(out[..., 1:] == 0) and np.all(out[..., 0] > 0)
+
+
+def test_sinr_full_mixed_arrays(gpu_lib):
+    # the full-channel SINR on 4-, 8- and 16-lane groups (one plan per array size), and the
+    # three channels in one plan (16-lane groups for all), against the oracle per channel
+    announce("sinr full mixed arrays")
+    rng = np.random.default_rng(41)
+    shapes = [(4, 32, 20, 2), (6, 40, 18, 3), (12, 64, 16, 4)]  # nr, nt, nsc, ns
+    descs = [desc(nr, nt, nsc, 8, min(nr, 4), 8, 4, ns) for nr, nt, nsc, ns in shapes]
+    Xs = [crandn(rng, nsc, nr, nt) for nr, nt, nsc, _ in shapes]
+    s2 = synthgen.snr_to_sigma2(SNRS)
+    plans = [([d], [x]) for d, x in zip(descs, Xs)] + [(descs, Xs)]
+    for ds, xs in plans:
+        plan = _plan(gpu_lib, ds, iters=2)
+        out = host(plan.sinr_full(dev_c64(np.concatenate([x.reshape(-1) for x in xs])), s2))
+        for c, (d, X) in enumerate(zip(ds, xs)):
+            o = plan.offsets(c)
+            ref = osinr.sinr(X, s2, d["ns"])
+            got = out[:, o.sc:o.sc + d["nsc"], :d["ns"]]
+            err = np.abs(db(got) - db(ref)).max()
+            print(f"[sinr full] {len(ds)} channel(s), nr {d['nr']}: max error {err:.3e} dB", flush=True)
+            assert err <= 0.05, (len(ds), c, err)
