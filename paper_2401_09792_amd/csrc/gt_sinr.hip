@@ -1217,20 +1217,44 @@ __global__ void __launch_bounds__(256) k_sinr_bwd_reduce(const DevChan* __restri
   const float2* gH = reinterpret_cast<const float2*>(ws + ch.w_gH) + (int64_t)s0 * mn;
   const float2* Gg = G + ch.g + (int64_t)it.g * ch.p * mn;
   float2* gGg = gG + ch.g + (int64_t)it.g * ch.p * mn;
-  for (int o = threadIdx.x; o < ch.p * mn; o += blockDim.x) {
-    const int q = o / mn, e = o % mn;
-    Cx<float> acc{0.f, 0.f};
-    if (q < pg)
-      for (int i = 0; i < sz; ++i)
-        cfmac(acc, ld(C + ch.c + (int64_t)(s0 + i) * ch.p + q), ld(gH + (int64_t)i * mn + e));
-    st(gGg + o, acc);
+  // dl/dG: a thread owns entry e for QC consecutive q, so each dl/dHt entry is read once per
+  // chunk of q (rows q >= p_g are written as zero)
+  constexpr int QC = 8;
+  const int nqc = (ch.p + QC - 1) / QC;
+  for (int o = threadIdx.x; o < nqc * mn; o += blockDim.x) {
+    const int qc = o / mn, e = o - qc * mn;
+    Cx<float> acc[QC];
+#pragma unroll
+    for (int j = 0; j < QC; ++j) acc[j] = Cx<float>{0.f, 0.f};
+    for (int i = 0; i < sz; ++i) {
+      const Cx<float> h = ld(gH + (int64_t)i * mn + e);
+      const float2* Ci = C + ch.c + (int64_t)(s0 + i) * ch.p + qc * QC;
+#pragma unroll
+      for (int j = 0; j < QC; ++j)
+        if (qc * QC + j < pg) cfmac(acc[j], ld(Ci + j), h);
+    }
+#pragma unroll
+    for (int j = 0; j < QC; ++j)
+      if (qc * QC + j < ch.p) st(gGg + (int64_t)(qc * QC + j) * mn + e, acc[j]);
   }
-  for (int o = threadIdx.x; o < sz * ch.p; o += blockDim.x) {
+  // dl/dC: 16 lanes per (s, q) split the m n entries and reduce by shuffles; the 16 lanes of an
+  // output are aligned and run the same passes
+  const int l16 = threadIdx.x % 16;
+  for (int o = threadIdx.x / 16; o < sz * ch.p; o += blockDim.x / 16) {
     const int i = o / ch.p, q = o % ch.p;
-    Cx<float> acc{0.f, 0.f};
+    float ar = 0.f, ai = 0.f;
     if (q < pg)
-      for (int e = 0; e < mn; ++e) cfmac(acc, ld(Gg + (int64_t)q * mn + e), ld(gH + (int64_t)i * mn + e));
-    st(gC + ch.c + (int64_t)(s0 + i) * ch.p + q, acc);
+      for (int e = l16; e < mn; e += 16) {
+        const float2 g = Gg[(int64_t)q * mn + e], h = gH[(int64_t)i * mn + e];
+        ar += g.x * h.x + g.y * h.y;  // conj(g) h
+        ai += g.x * h.y - g.y * h.x;
+      }
+#pragma unroll
+    for (int d = 8; d > 0; d >>= 1) {
+      ar += __shfl_xor(ar, d, 64);
+      ai += __shfl_xor(ai, d, 64);
+    }
+    if (l16 == 0) gC[ch.c + (int64_t)(s0 + i) * ch.p + q] = make_float2(ar, ai);
   }
 }
 
