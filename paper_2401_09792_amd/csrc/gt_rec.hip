@@ -83,6 +83,40 @@ __global__ void __launch_bounds__(256) k_reconstruct(const DevChan* __restrict__
   }
 }
 
+// Ht only (no Xhat): one block per group; a thread owns entry e of Ht_s for SC consecutive
+// subcarriers, so each entry of G_g is read once per chunk of subcarriers rather than once per
+// subcarrier.  The sum over q runs in the same order as in stage_ht.
+__global__ void __launch_bounds__(256) k_reconstruct_ht(const DevChan* __restrict__ chans,
+                                                        const GroupItem* __restrict__ items,
+                                                        const float2* __restrict__ C,
+                                                        const float2* __restrict__ G, float2* Ht) {
+  const GroupItem it = items[blockIdx.x];
+  const DevChan& ch = chans[it.ch];
+  const int s0 = it.g * ch.gs;
+  const int sz = min(ch.gs, ch.nsc - s0);
+  const int pg = min(ch.p, sz);
+  const int mn = ch.m * ch.n;
+  const float2* Gg = G + ch.g + (int64_t)it.g * ch.p * mn;
+  constexpr int SC = 8;
+  const int nch = (sz + SC - 1) / SC;
+  for (int o = threadIdx.x; o < nch * mn; o += blockDim.x) {
+    const int sc = o / mn, e = o - sc * mn;
+    Cx<float> acc[SC];
+#pragma unroll
+    for (int j = 0; j < SC; ++j) acc[j] = Cx<float>{0.f, 0.f};
+    for (int q = 0; q < pg; ++q) {
+      const Cx<float> gv = ld(Gg + (int64_t)q * mn + e);
+#pragma unroll
+      for (int j = 0; j < SC; ++j)
+        if (sc * SC + j < sz) cfma(acc[j], ld(C + ch.c + (int64_t)(s0 + sc * SC + j) * ch.p + q), gv);
+    }
+#pragma unroll
+    for (int j = 0; j < SC; ++j)
+      if (sc * SC + j < sz)
+        Ht[ch.ht + (int64_t)(s0 + sc * SC + j) * mn + e] = make_float2(acc[j].re, acc[j].im);
+  }
+}
+
 // Adjoint, one block per subcarrier: dHt(total) into the workspace, and the per-subcarrier
 // contributions to dA and dB accumulated per group by k_rec_bwd_group.
 __global__ void __launch_bounds__(256) k_rec_bwd_sub(const DevChan* __restrict__ chans, int n_channels,
@@ -225,6 +259,10 @@ gt_status launch_grad_cg(const LaunchCtx& L, const float2* C, const float2* G, f
 
 gt_status launch_reconstruct(const LaunchCtx& L, int64_t total_sc, const float2* A, const float2* B,
                              const float2* C, const float2* G, float2* Ht, float2* Xhat) {
+  if (!Xhat) {
+    if (Ht) GT_LAUNCH(k_reconstruct_ht, dim3(L.total_groups), dim3(256), L.d_chans, L.d_groups, C, G, Ht);
+    return GT_OK;
+  }
   GT_LAUNCH(k_reconstruct, dim3((unsigned)total_sc), dim3(256), L.d_chans, L.n_channels, A, B, C, G, Ht,
             Xhat);
   return GT_OK;

@@ -210,3 +210,22 @@ def test_sinr_full_mixed_arrays(gpu_lib):
             err = np.abs(db(got) - db(ref)).max()
             print(f"[sinr full] {len(ds)} channel(s), nr {d['nr']}: max error {err:.3e} dB", flush=True)
             assert err <= 0.05, (len(ds), c, err)
+
+
+def test_reconstruct_ht_only_matches(gpu_lib):
+    # Ht alone (one block per group) against Ht from the per-subcarrier kernel that also forms
+    # Xhat: the same sums in the same order (the compiler may contract them into different fused
+    # multiply-adds, so rounding-level differences remain); uneven groups in a batch of two
+    announce("reconstruct Ht only")
+    rng = np.random.default_rng(43)
+    d0, d1 = desc(6, 16, 29, 12, 4, 6, 5, 2), desc(8, 32, 40, 8, 6, 10, 7, 3)
+    plan = _plan(gpu_lib, [d0, d1], iters=2)
+    t = plan.totals
+    A, Bm, C, G = (dev_c64(crandn(rng, k)) for k in (t.a, t.b, t.c, t.g))
+    ht_full, _ = plan.reconstruct(A, Bm, C, G, ht=True, xhat=True)
+    ht_only, xh = plan.reconstruct(A, Bm, C, G, ht=True, xhat=False)
+    assert xh is None
+    a, b = host(ht_only), host(ht_full)
+    err = np.abs(a - b).max() / np.abs(b).max()
+    print(f"[reconstruct] Ht only vs with Xhat: {err:.3e} of max |Ht|", flush=True)
+    assert err <= 1e-6, err
