@@ -35,7 +35,7 @@ import numpy as np  # noqa: E402
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 
-# algorithmic work per unit ("Measurement"): CMAC = 8 real flops
+# algorithmic work per unit of each timed kernel: CMAC = 8 real flops
 CMAC = 8.0
 
 
