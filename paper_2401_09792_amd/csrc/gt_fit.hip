@@ -97,12 +97,13 @@ __global__ void __launch_bounds__(256) k_init_group(const DevChan* __restrict__ 
 }
 
 // The same for groups of at most 8192 complex entries, staged whole: 16 lanes per output over
-// the upper triangles of S1 (over (s, j)) and S3 (over (i, j)), mirrored below.
-__global__ void __launch_bounds__(256) k_init_group_lds(const DevChan* __restrict__ chans,
+// the upper triangles of S1 (over (s, j)) and S3 (over (i, j)), mirrored below; 512 threads, so
+// that the two blocks per CU that the 64 KB stage allows keep 16 waves busy.
+__global__ void __launch_bounds__(512) k_init_group_lds(const DevChan* __restrict__ chans,
                                                         const GroupItem* __restrict__ items,
                                                         const float2* __restrict__ X, char* ws) {
   __shared__ float2 xs[8192];
-  __shared__ double red[256];
+  __shared__ double red[512];
   const GroupItem it = items[blockIdx.x];
   CH_BEGIN(it.ch);
   const int s0 = it.g * ch.gs;
@@ -112,7 +113,7 @@ __global__ void __launch_bounds__(256) k_init_group_lds(const DevChan* __restric
   const float2* Xg = X + ch.x + (int64_t)s0 * slice;
   const int tid = threadIdx.x, l16 = tid % 16;
   double nrm = 0.0;
-  for (int e = tid; e < tot; e += 256) {
+  for (int e = tid; e < tot; e += 512) {
     const float2 v = Xg[e];
     xs[e] = v;
     nrm += (double)v.x * v.x + (double)v.y * v.y;
@@ -121,7 +122,7 @@ __global__ void __launch_bounds__(256) k_init_group_lds(const DevChan* __restric
   const int n1 = nr * (nr + 1) / 2, n3 = gs * (gs + 1) / 2;
   float2* S1 = wsp(ws, ch.w_S1p) + (int64_t)it.g * nr * nr;
   float2* S3 = wsp(ws, ch.w_S3) + (int64_t)it.g * gs * gs;
-  for (int k = tid / 16; k < n1 + n3; k += 16) {
+  for (int k = tid / 16; k < n1 + n3; k += 32) {
     const bool one = k < n1;
     const int dim = one ? nr : gs;
     int a = 0, rem = one ? k : k - n1;
@@ -160,7 +161,7 @@ __global__ void __launch_bounds__(256) k_init_group_lds(const DevChan* __restric
   }
   red[tid] = nrm;
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
+  for (int o = 256; o > 0; o >>= 1) {
     if (tid < o) red[tid] += red[tid + o];
     __syncthreads();
   }
@@ -812,7 +813,7 @@ gt_status launch_fit(const LaunchCtx& L, const SplitCtx* split, const float2* X,
 
   // initialisation: Grams of the unfoldings, norms
   if ((int64_t)L.max_gs * L.max_nr * L.max_nt <= 8192)
-    GT_LAUNCH(k_init_group_lds, dim3(L.total_groups), b256, L.d_chans, L.d_groups, X, L.ws);
+    GT_LAUNCH(k_init_group_lds, dim3(L.total_groups), dim3(512), L.d_chans, L.d_groups, X, L.ws);
   else
     GT_LAUNCH(k_init_group, dim3(L.total_groups), b256, L.d_chans, L.d_groups, X, L.ws);
   GT_LAUNCH(k_norm_total, dim3(cdiv(nch, 64)), dim3(64), L.d_chans, nch, L.ws);

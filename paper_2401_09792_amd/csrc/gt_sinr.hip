@@ -1203,20 +1203,35 @@ __global__ void __launch_bounds__(64) k_sinr_bwd(const DevChan* __restrict__ cha
 }
 
 // dl/dG_g[q] = sum_{s in g} conj(C[s,q]) dl/dHt_s ;  dl/dC[s,q] = <dl/dHt_s, G_g[q]>
+// STAGE: dl/dHt_s of the group and G_g are first copied to LDS (when they fit), so that the two
+// contractions read them from LDS rather than through the caches once per q or per entry.
+template <bool STAGE>
 __global__ void __launch_bounds__(256) k_sinr_bwd_reduce(const DevChan* __restrict__ chans,
                                                          const GroupItem* __restrict__ items,
                                                          const float2* __restrict__ C,
                                                          const float2* __restrict__ G,
                                                          float2* gC, float2* gG, char* ws) {
+  extern __shared__ float2 sm[];
   const GroupItem it = items[blockIdx.x];
   const DevChan& ch = chans[it.ch];
   const int s0 = it.g * ch.gs;
   const int sz = min(ch.gs, ch.nsc - s0);
   const int pg = min(ch.p, sz);
   const int mn = ch.m * ch.n;
-  const float2* gH = reinterpret_cast<const float2*>(ws + ch.w_gH) + (int64_t)s0 * mn;
-  const float2* Gg = G + ch.g + (int64_t)it.g * ch.p * mn;
+  const float2* gHm = reinterpret_cast<const float2*>(ws + ch.w_gH) + (int64_t)s0 * mn;
+  const float2* Ggm = G + ch.g + (int64_t)it.g * ch.p * mn;
   float2* gGg = gG + ch.g + (int64_t)it.g * ch.p * mn;
+  const float2* gH = gHm;
+  const float2* Gg = Ggm;
+  if (STAGE) {
+    float2* sH = sm;
+    float2* sG = sm + sz * mn;
+    for (int e = threadIdx.x; e < sz * mn; e += blockDim.x) sH[e] = gHm[e];
+    for (int e = threadIdx.x; e < pg * mn; e += blockDim.x) sG[e] = Ggm[e];
+    __syncthreads();
+    gH = sH;
+    Gg = sG;
+  }
   // dl/dG: a thread owns entry e for QC consecutive q, so each dl/dHt entry is read once per
   // chunk of q (rows q >= p_g are written as zero)
   constexpr int QC = 8;
@@ -1404,8 +1419,21 @@ gt_status launch_sinr_bwd(const LaunchCtx& L, int64_t total_sc, const float2* C,
 }
 
 gt_status launch_grad_cg(const LaunchCtx& L, const float2* C, const float2* G, float2* gC, float2* gG) {
-  GT_LAUNCH(k_sinr_bwd_reduce, dim3(L.total_groups), dim3(256), L.d_chans, L.d_groups, C, G, gC, gG,
-            L.ws);
+  const size_t sh = sizeof(float2) * ((size_t)L.max_gs + L.max_p) * L.max_m * L.max_n;
+  if (sh <= 64 * 1024) {
+    prof_begin("k_sinr_bwd_reduce", L.stream);
+    hipLaunchKernelGGL((k_sinr_bwd_reduce<true>), dim3(L.total_groups), dim3(256), sh, L.stream, L.d_chans,
+                       L.d_groups, C, G, gC, gG, L.ws);
+    prof_end(L.stream);
+    hipError_t e_ = hipGetLastError();
+    if (e_ != hipSuccess) {
+      set_error_detail("k_sinr_bwd_reduce", e_);
+      return GT_ERR_HIP;
+    }
+    return GT_OK;
+  }
+  GT_LAUNCH((k_sinr_bwd_reduce<false>), dim3(L.total_groups), dim3(256), L.d_chans, L.d_groups, C, G, gC,
+            gG, L.ws);
   return GT_OK;
 }
 
