@@ -1920,23 +1920,61 @@ __global__ void __launch_bounds__(256) k_yh_from_t(const DevChan* __restrict__ c
 
 // S2 = sum over splits of the complex Gram assembled from the real blocks of R^T R
 // (upper 32 x 32 tiles stored; lower entries by symmetry).
-__global__ void k_reduce_S2_mfma(const DevChan* __restrict__ chans, char* ws) {
+__global__ void __launch_bounds__(256) k_reduce_S2_mfma(const DevChan* __restrict__ chans, char* ws) {
+  // One block per upper 32 x 32 tile (J, K) of S2 (J <= K) and channel.  With UL, UR, LR the
+  // quadrants of the real Gram of [Re W | Im W] (stored as its upper 32 x 32 tiles):
+  //   Re S2[j][k] = UL[j][k] + LR[j][k],  Im S2[j][k] = UR[j][k] - UR[k][j].
+  // Every partial is read in its stored orientation (coalesced); the UR[k][j] sums and the
+  // mirrored lower tile go through an LDS transpose.
   const DevChan& ch = chans[blockIdx.y];
   const int nt = ch.nt;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nt * nt) return;
-  const int j = e / nt, k = e % nt;
+  const int t = blockIdx.x;
+  const int J = t == 2 ? 1 : 0, K = t == 0 ? 0 : 1;
+  if (32 * K >= nt) return;
+  __shared__ float tra[32][33], trb[32][33];
   const float* P = reinterpret_cast<const float*>(ws + ch.w_S2p);
-  auto at = [&](const float* Q, int a, int b) {
-    return ((a >> 5) <= (b >> 5)) ? Q[a * 128 + b] : Q[b * 128 + a];
-  };
-  float re = 0.f, im = 0.f;
+  const int tid = threadIdx.x, col = tid % 32, r0 = tid / 32;
+  float re[4], ia[4], ib[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) re[u] = ia[u] = ib[u] = 0.f;
   for (int sp = 0; sp < ch.nsplit; ++sp) {
     const float* Q = P + (int64_t)sp * 128 * 128;
-    re += at(Q, j, k) + at(Q, 64 + j, 64 + k);
-    im += at(Q, j, 64 + k) - at(Q, 64 + j, k);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int row = r0 + 8 * u;
+      re[u] += Q[(32 * J + row) * 128 + 32 * K + col] + Q[(64 + 32 * J + row) * 128 + 64 + 32 * K + col];
+      ia[u] += Q[(32 * J + row) * 128 + 64 + 32 * K + col];  // UR[32 J + row][32 K + col]
+      ib[u] += Q[(32 * K + row) * 128 + 64 + 32 * J + col];  // UR[32 K + row][32 J + col]
+    }
   }
-  reinterpret_cast<float2*>(ws + ch.w_S2)[e] = make_float2(re, im);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) trb[r0 + 8 * u][col] = ib[u];
+  __syncthreads();
+  float2* S2 = reinterpret_cast<float2*>(ws + ch.w_S2);
+  float im[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int row = r0 + 8 * u;
+    im[u] = ia[u] - trb[col][row];  // UR[k][j] for j = 32 J + row, k = 32 K + col
+    const int j = 32 * J + row, k = 32 * K + col;
+    if (j < nt && k < nt) S2[j * nt + k] = make_float2(re[u], im[u]);
+  }
+  if (J == K) return;
+  // lower tile: S2[k][j] = conj(S2[j][k]), written row-major through a transpose (after every
+  // thread has read trb above)
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    tra[r0 + 8 * u][col] = re[u];
+    trb[r0 + 8 * u][col] = im[u];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int row = r0 + 8 * u;  // k - 32 K
+    const int k = 32 * K + row, j = 32 * J + col;
+    if (j < nt && k < nt) S2[k * nt + j] = make_float2(tra[col][row], -trb[col][row]);
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -2073,7 +2111,7 @@ gt_status launch_gram_rows_big(const LaunchCtx& L, const float2* X, int which) {
 
 gt_status launch_gram_x(const LaunchCtx& L, const float2* X) {
   GT_LAUNCH_SH(k_gram_x_mfma, dim3(L.max_nsplit, L.n_channels), dim3(512), 0, L.d_chans, X, L.ws);
-  GT_LAUNCH_SH(k_reduce_S2_mfma, dim3((L.max_nt * L.max_nt + 255) / 256, L.n_channels), dim3(256), 0,
+  GT_LAUNCH_SH(k_reduce_S2_mfma, dim3(3, L.n_channels), dim3(256), 0,
                L.d_chans, L.ws);
   return GT_OK;
 }
@@ -2197,7 +2235,7 @@ gt_status launch_fused_b(const LaunchCtx& L, const float2* X, const float2* A, c
 #undef GT_BMM_PREC
 #undef GT_BMM
 #undef GT_BMM_S
-    GT_LAUNCH_SH(k_reduce_S2_mfma, dim3((L.max_nt * L.max_nt + 255) / 256, L.n_channels), dim3(256), 0,
+    GT_LAUNCH_SH(k_reduce_S2_mfma, dim3(3, L.n_channels), dim3(256), 0,
                  L.d_chans, L.ws);
     return GT_OK;
   }
@@ -2214,7 +2252,7 @@ gt_status launch_fused_b(const LaunchCtx& L, const float2* X, const float2* A, c
     else
       GT_LAUNCH_SH((k_fused_b_mfma<2, 16>), dim3(L.max_nsplit, L.n_channels), dim3(256), bm_bytes(L),
                    L.d_chans, X, A, C, L.ws);
-    GT_LAUNCH_SH(k_reduce_S2_mfma, dim3((L.max_nt * L.max_nt + 255) / 256, L.n_channels), dim3(256), 0,
+    GT_LAUNCH_SH(k_reduce_S2_mfma, dim3(3, L.n_channels), dim3(256), 0,
                  L.d_chans, L.ws);
     return GT_OK;
   }
