@@ -234,27 +234,37 @@ __global__ void __launch_bounds__(256) k_gram_rows(const DevChan* __restrict__ c
 }
 
 // S1 = sum of the per-group partials (fixed order, four independent accumulators).
-__global__ void k_reduce_S1(const DevChan* __restrict__ chans, char* ws) {
+// S1 = sum of the per-group partials: the four waves of the block each sum a quarter of the
+// groups (four interleaved accumulators per entry), then the quarters are added in order.
+__global__ void __launch_bounds__(256) k_reduce_S1(const DevChan* __restrict__ chans, char* ws) {
   CH_BEGIN(blockIdx.y);
+  __shared__ float2 part[4][kMaxNr * kMaxNr];
   const int nn = ch.nr * ch.nr;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nn) return;
+  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  const int g0 = (int)((int64_t)w * ch.ngroups / 4), g1 = (int)((int64_t)(w + 1) * ch.ngroups / 4);
   const float2* P = wsp(ws, ch.w_S1p);
-  float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
-  int g = 0;
-  for (; g + 4 <= ch.ngroups; g += 4)
+  for (int e = l; e < nn; e += 64) {
+    float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
+    int g = g0;
+    for (; g + 4 <= g1; g += 4)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      float2 v = P[(int64_t)(g + u) * nn + e];
-      ar[u] += v.x;
-      ai[u] += v.y;
+      for (int u = 0; u < 4; ++u) {
+        float2 v = P[(int64_t)(g + u) * nn + e];
+        ar[u] += v.x;
+        ai[u] += v.y;
+      }
+    for (; g < g1; ++g) {
+      float2 v = P[(int64_t)g * nn + e];
+      ar[0] += v.x;
+      ai[0] += v.y;
     }
-  for (; g < ch.ngroups; ++g) {
-    float2 v = P[(int64_t)g * nn + e];
-    ar[0] += v.x;
-    ai[0] += v.y;
+    part[w][e] = make_float2((ar[0] + ar[1]) + (ar[2] + ar[3]), (ai[0] + ai[1]) + (ai[2] + ai[3]));
   }
-  st(wsp(ws, ch.w_S1) + e, Cx<float>{(ar[0] + ar[1]) + (ar[2] + ar[3]), (ai[0] + ai[1]) + (ai[2] + ai[3])});
+  __syncthreads();
+  for (int e = threadIdx.x; e < nn; e += 256) {
+    const float2 a0 = part[0][e], a1 = part[1][e], a2 = part[2][e], a3 = part[3][e];
+    st(wsp(ws, ch.w_S1) + e, Cx<float>{(a0.x + a1.x) + (a2.x + a3.x), (a0.y + a1.y) + (a2.y + a3.y)});
+  }
 }
 
 // S2 = sum of the split partials (fixed order).
@@ -740,7 +750,7 @@ template <typename T>
 static gt_status eig_all(const LaunchCtx& L, int which, float2* A, float2* B, float2* C,
                          int32_t* status, int warm) {
   if (which == 0) {
-    GT_LAUNCH(k_reduce_S1, dim3(cdiv(L.max_nr * L.max_nr, 256), L.n_channels), dim3(256), L.d_chans,
+    GT_LAUNCH(k_reduce_S1, dim3(1, L.n_channels), dim3(256), L.d_chans,
               L.ws);
     GT_LAUNCH((k_eigA<T, 16>), dim3(cdiv(L.n_channels, 4)), dim3(64), L.d_chans, L.n_channels,
               L.ws, A, status, warm);
