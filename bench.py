@@ -383,7 +383,7 @@ def main():
 
     # live per-kernel durations over the timed region
     names = ["k_eigA", "k_eigB", "k_eigC", "k_gram_rows", "k_reduce_S1", "k_reduce_S2",
-             "k_reduce_S2_mfma", "k_init_group", "k_init_group_lds", "k_gram_x_mfma",
+             "k_reduce_S2_mfma", "k_init_group", "k_init_group_lds",
              "k_stepA_group", "k_S3", "k_core", "k_objC", "k_trace", "k_norm_total", "k_fused_t",
              "k_fused_t_mfma", "k_fused_z", "k_fused_b", "k_fused_b_mfma", "k_fused_b_mm",
              "k_eigB_sub", "k_sub_prod", "k_sub_rr", "k_sub_rot", "k_rows_times_b", "k_w_rows", "k_yh_from_t", "k_gram_rows_st",

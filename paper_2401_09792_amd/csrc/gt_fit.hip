@@ -784,7 +784,6 @@ static gt_status eig_dispatch(const LaunchCtx& L, int which, float2* A, float2* 
 bool fused_fit_ok(const LaunchCtx& L);
 bool fused_lowp_ok(const LaunchCtx& L);
 gt_status launch_convert_x(const LaunchCtx& L, const float2* X);
-gt_status launch_gram_x(const LaunchCtx& L, const float2* X);
 gt_status launch_gram_rows_big(const LaunchCtx& L, const float2* X, int which);
 gt_status launch_rows_times_b(const LaunchCtx& L, const float2* X, const float2* B);
 gt_status launch_w_rows(const LaunchCtx& L, const float2* X, const float2* A, const float2* C);
@@ -829,11 +828,9 @@ gt_status launch_fit(const LaunchCtx& L, const SplitCtx* split, const float2* X,
   GT_LAUNCH(k_norm_total, dim3(cdiv(nch, 64)), dim3(64), L.d_chans, nch, L.ws);
   if (!warm) {
     gt_status st;
-    if (L.max_nt <= 64) {
-      if ((st = launch_gram_x(L, X)) != GT_OK) return st;
-    } else {
-      if ((st = launch_gram_rows_big(L, X, 0)) != GT_OK) return st;
-    }
+    // mode-2 Gram of the rows of X in 128 x 128 super-tiles (LDS-staged row chunks); for
+    // nt <= 64 one super-tile holds the whole real Gram
+    if ((st = launch_gram_rows_big(L, X, 0)) != GT_OK) return st;
     if ((st = eig_dispatch(L, 0, A, B, C, status, 0)) != GT_OK) return st;
     if ((st = eig_dispatch(L, 1, A, B, C, status, 0)) != GT_OK) return st;
     if ((st = eig_dispatch(L, 2, A, B, C, status, 0)) != GT_OK) return st;

@@ -1272,75 +1272,6 @@ __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* _
   }
 }
 
-// Mode-2 Gram of the channel tensor for the HOSVD initialisation, S2 = sum over the rows
-// (s, i) of X of row^H row, as the real Gram R^T R of R = [Re X | Im X] (2 nt <= 128 columns)
-// on the 10 upper 32 x 32 tiles, one block per (row split, channel).  Operands come straight
-// from X: lane (h, col) of a step reads row k0 + h at column 32 I + col, i.e. float 2 j + part
-// of a contiguous 8 nt-byte row.  Wave w owns tile w, waves 0 and 1 also tiles 8 and 9.
-__global__ void __launch_bounds__(512) k_gram_x_mfma(const DevChan* __restrict__ chans,
-                                                     const float2* __restrict__ X, char* ws) {
-  const DevChan& ch = chans[blockIdx.y];
-  const int split = blockIdx.x;
-  if (split >= ch.nsplit) return;
-  const int nt = ch.nt;
-  const int64_t nrows = (int64_t)ch.nsc * ch.nr;
-  const int64_t r0 = split * nrows / ch.nsplit, r1 = (split + 1) * nrows / ch.nsplit;
-  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
-  const int h = lane / 32, col = lane % 32;
-  const int nt2 = wave < 2 ? 2 : 1;
-  int oa[2], ob[2];
-  bool va[2], vb[2];
-#pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    int I, J;
-    gram_tile(t == 0 ? wave : 8 + wave, I, J);
-    const int ca = 32 * I + col, cb = 32 * J + col;
-    const int ja = ca & 63, jb = cb & 63;
-    va[t] = ja < nt;
-    vb[t] = jb < nt;
-    oa[t] = 2 * min(ja, nt - 1) + (ca >> 6);
-    ob[t] = 2 * min(jb, nt - 1) + (cb >> 6);
-  }
-  const float* Xf = reinterpret_cast<const float*>(X + ch.x);
-  f32x16 acc[2];
-#pragma unroll
-  for (int t = 0; t < 2; ++t)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
-  for (int64_t k0 = r0; k0 < r1; k0 += 16) {
-    float a0[8], b0[8], a1[8], b1[8];
-#pragma unroll
-    for (int d = 0; d < 8; ++d) {
-      const int64_t row = k0 + 2 * d + h;
-      const bool rv = row < r1;
-      const float* rp = Xf + min(row, r1 - 1) * 2 * nt;
-      const float x0 = rp[oa[0]], y0 = rp[ob[0]], x1 = rp[oa[1]], y1 = rp[ob[1]];
-      a0[d] = (rv && va[0]) ? x0 : 0.f;
-      b0[d] = (rv && vb[0]) ? y0 : 0.f;
-      a1[d] = (rv && va[1]) ? x1 : 0.f;
-      b1[d] = (rv && vb[1]) ? y1 : 0.f;
-    }
-#pragma unroll
-    for (int d = 0; d < 8; ++d) {
-      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[d], b0[d], acc[0], 0, 0, 0);
-      if (nt2 == 2) acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[d], b1[d], acc[1], 0, 0, 0);
-    }
-  }
-  float* P = reinterpret_cast<float*>(ws + ch.w_S2p) + (int64_t)split * 128 * 128;
-#pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    if (t < nt2) {
-      int I, J;
-      gram_tile(t == 0 ? wave : 8 + wave, I, J);
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = 32 * I + 8 * (r / 4) + 4 * h + (r % 4);
-        P[row * 128 + 32 * J + col] = acc[t][r];
-      }
-    }
-  }
-}
-
 // Mode-2 Gram of long row stacks for any nt <= 256: rows of X (which = 0: (s, i) rows of the
 // channel tensor) or of W (which = 1: (g, q, a) rows from the B-step), each a contiguous row of
 // nt complex values.  With R = [Re rows | Im rows] (real column c < nt: Re of column c, else
@@ -2106,13 +2037,6 @@ gt_status launch_gram_rows_big(const LaunchCtx& L, const float2* X, int which) {
   if (L.tiles_total[TK_RED2] > 0)
     GT_LAUNCH_SH(k_reduce_S2_st, dim3(L.tiles_total[TK_RED2]), dim3(256), 0, L.d_chans,
                  tiles_of(L, TK_RED2), L.n_channels, L.ws);
-  return GT_OK;
-}
-
-gt_status launch_gram_x(const LaunchCtx& L, const float2* X) {
-  GT_LAUNCH_SH(k_gram_x_mfma, dim3(L.max_nsplit, L.n_channels), dim3(512), 0, L.d_chans, X, L.ws);
-  GT_LAUNCH_SH(k_reduce_S2_mfma, dim3(3, L.n_channels), dim3(256), 0,
-               L.d_chans, L.ws);
   return GT_OK;
 }
 
