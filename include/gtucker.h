@@ -173,12 +173,14 @@ gt_status gt_tucker_reconstruct_backward(const gt_plan* plan, const void* A, con
                                          void* stream);
 
 /* Autotuner of the fit's pass variants on a plan's own shapes and data.  Each tunable choice
- * is timed in turn over short fits of X (HIP events, at most 3 sweeps, the other choices held
- * at their current values) and the fastest is kept in the plan for its later fits:
+ * is timed in turn over short fits of X (HIP events, the other choices held at their current
+ * values) and the fastest is kept in the plan for its later fits:
  *   bstep  B-step pass: 0 matrix-core kernel, 1 the same with the next group's operands
  *          prefetched during the current group's Gram, 2 the older matrix-core kernel;
  *   tpass  T pass: 0 matrix cores, 1 vector ALU;
  *   split  fits of 8 or more channels split over concurrent streams: 0 off, 1 on.
+ * Each configuration is timed as the faster of two fits of min(iters, 8) sweeps after an
+ * untimed one, and a choice replaces the current one only when it is more than 2 % faster.
  * Choices that do not apply to the plan (no fused passes, 16-bit contractions for the
  * prefetching variant) keep 0 and are not timed.  A, B, C, G receive the last probe's fit
  * and are otherwise scratch.  Synchronises the stream and is not capturable: call it before
