@@ -135,6 +135,7 @@ __global__ void __launch_bounds__(512) k_init_group_lds(const DevChan* __restric
     if (one) {
       // S1[a][b] = sum_{s, j} H_s[a][j] conj(H_s[b][j])
       for (int s = 0; s < sz; ++s)
+#pragma unroll 8
         for (int j = l16; j < nt; j += 16) {
           const float2 x = xs[s * slice + a * nt + j], y = xs[s * slice + b * nt + j];
           ar += x.x * y.x + x.y * y.y;
@@ -142,6 +143,7 @@ __global__ void __launch_bounds__(512) k_init_group_lds(const DevChan* __restric
         }
     } else if (b < sz) {
       // S3[a][b] = <H_a, H_b> = sum_e H_a[e] conj(H_b[e])
+#pragma unroll 8
       for (int e = l16; e < slice; e += 16) {
         const float2 x = xs[a * slice + e], y = xs[b * slice + e];
         ar += x.x * y.x + x.y * y.y;

@@ -253,12 +253,14 @@ __device__ __forceinline__ void fused_t_finish(const DevChan& ch, const GroupIte
       }
       const int t = s + rem;
       float ar = 0.f, ai = 0.f;
-      if (t < sz)
+      if (t < sz) {
+#pragma unroll 8
         for (int e = l16; e < mn; e += 16) {
           const float2 x = Yh[s * ys + e], y = Yh[t * ys + e];
           ar += x.x * y.x + x.y * y.y;
           ai += x.y * y.x - x.x * y.y;
         }
+      }
 #pragma unroll
       for (int d = 8; d > 0; d >>= 1) {
         ar += __shfl_xor(ar, d, 64);
