@@ -1258,12 +1258,14 @@ __global__ void __launch_bounds__(256) k_sinr_bwd_reduce(const DevChan* __restri
   for (int o = threadIdx.x / 16; o < sz * ch.p; o += blockDim.x / 16) {
     const int i = o / ch.p, q = o % ch.p;
     float ar = 0.f, ai = 0.f;
-    if (q < pg)
+    if (q < pg) {
+#pragma unroll 8
       for (int e = l16; e < mn; e += 16) {
         const float2 g = Gg[(int64_t)q * mn + e], h = gH[(int64_t)i * mn + e];
         ar += g.x * h.x + g.y * h.y;  // conj(g) h
         ai += g.x * h.y - g.y * h.x;
       }
+    }
 #pragma unroll
     for (int d = 8; d > 0; d >>= 1) {
       ar += __shfl_xor(ar, d, 64);
