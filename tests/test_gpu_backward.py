@@ -63,9 +63,15 @@ def test_sinr_autograd_function(gpu_lib):
     assert np.abs(host(Gt.grad).reshape(G.shape) - gG_o).max() <= 2e-3 * np.abs(gG_o).max()
 
 
-def test_reconstruct_backward_matches_oracle(gpu_lib):
-    announce("reconstruct backward")
-    nsc, gs, m, n, p, nr, nt = 20, 8, 3, 5, 4, 6, 12
+@pytest.mark.parametrize("shape", [
+    # nsc, gs, m, n, p, nr, nt
+    (20, 8, 3, 5, 4, 6, 12),
+    (30, 12, 10, 20, 6, 12, 64),     # m > 8, a short last group
+    (26, 12, 12, 32, 8, 16, 256),    # the largest arrays
+])
+def test_reconstruct_backward_matches_oracle(gpu_lib, shape):
+    announce(f"reconstruct backward {shape}")
+    nsc, gs, m, n, p, nr, nt = shape
     rng, C, G = _compressed(13, nsc, gs, m, n, p)
     A = synthgen.random_unitary(rng, nr, m)
     Bm = synthgen.random_unitary(rng, nt, n)

@@ -67,6 +67,30 @@ def test_precision_lossy_fit(gpu_lib, prec):
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16", "split_bf16"])
+def test_precision_lossy_fit_large_m(gpu_lib, prec):
+    # fused 16-bit passes at nr = 12, m = 10 (the B-step's 32 x 32 x 2 step 2 with a per-channel
+    # slot stride, the T pass's vector-ALU Yh, the A-step Gram past 64 entries)
+    announce(f"precision {prec} lossy fit, nr 12, m 10")
+    rng = np.random.default_rng(79)
+    nsc, nr, nt, gs, m, n, p, iters = 48, 12, 40, 8, 10, 8, 6, 5
+    X = crandn(rng, nsc, nr, nt)
+    X = X * (0.6 ** np.arange(nr))[None, :, None] * (0.85 ** np.arange(nt))[None, None, :]
+    plan = gpu_lib.Plan([desc(nr, nt, nsc, gs, m, n, p, 2)], iters=iters, ttm_prec=prec)
+    res = plan.fit(dev_c64(X))
+    _, xh = plan.reconstruct(res["A"], res["B"], res["C"], res["G"])
+    Xh = unpack(plan, 0, host(xh), "x")
+    orc = tucker.fit(X, gs, m, n, p, iters)
+    _, Xh_o = tucker.reconstruct(orc["A"], orc["B"], orc["C"], orc["G"], gs)
+    nx = float(np.sum(np.abs(X) ** 2))
+    rel = np.linalg.norm(Xh - Xh_o) / np.sqrt(nx)
+    tr_err = np.abs(host(res["trace"])[0] - orc["trace"]).max() / nx
+    print(f"[precision] nr 12 m 10 {prec}: X-hat {rel:.3e} of ||X||, trace {tr_err:.3e} of ||X||^2")
+    assert int(res["status"].item()) == 0
+    assert rel <= TOL[prec][1], rel
+    assert tr_err <= TOL[prec][1], tr_err
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "split_bf16"])
 def test_precision_wide_lossy_fit(gpu_lib, prec):
     # nt = 96 runs the generic row passes (16-bit T = H B and subcarrier contraction of W)
     announce(f"precision {prec} wide lossy fit")
