@@ -229,3 +229,31 @@ def test_reconstruct_ht_only_matches(gpu_lib):
     err = np.abs(a - b).max() / np.abs(b).max()
     print(f"[reconstruct] Ht only vs with Xhat: {err:.3e} of max |Ht|", flush=True)
     assert err <= 1e-6, err
+
+
+def test_fit_warm_start_resume(gpu_lib):
+    # GT_FIT_WARM_START: three sweeps resumed from the factors of a three-sweep fit follow the
+    # oracle's warm continuation (which the oracle pins equal to an uninterrupted six-sweep fit)
+    announce("fit warm start resume")
+    rng = np.random.default_rng(51)
+    nsc, nr, nt, gs, m, n, p = 40, 8, 16, 12, 4, 6, 6
+    X = crandn(rng, nsc, nr, nt)
+    X = X * (0.6 ** np.arange(nr))[None, :, None] * (0.8 ** np.arange(nt))[None, None, :]
+    d = desc(nr, nt, nsc, gs, m, n, p, 2)
+    r1 = _plan(gpu_lib, [d], iters=3).fit(dev_c64(X))
+    warm = _plan(gpu_lib, [d], iters=3, warm_start=True)
+    f = {k: r1[k].clone() for k in ("A", "B", "C", "G")}
+    r2 = warm.fit(dev_c64(X), factors=f)
+    _, xh = warm.reconstruct(r2["A"], r2["B"], r2["C"], r2["G"])
+    Xh = unpack(warm, 0, host(xh), "x")
+    half = tucker.fit(X, gs, m, n, p, 3)
+    rest = tucker.fit(X, gs, m, n, p, 3, warm=half)
+    _, Xh_o = tucker.reconstruct(rest["A"], rest["B"], rest["C"], rest["G"], gs)
+    nx = float(np.sum(np.abs(X) ** 2))
+    rel = np.linalg.norm(Xh - Xh_o) / np.sqrt(nx)
+    tr = host(r2["trace"])[0]
+    tr_err = np.abs(tr[1:] - rest["trace"][1:]).max() / nx
+    print(f"[warm] X-hat {rel:.3e} of ||X||, trace {tr_err:.3e} of ||X||^2", flush=True)
+    assert int(r2["status"].item()) == 0
+    assert rel <= 1e-4, rel
+    assert tr_err <= 1e-5, tr_err
