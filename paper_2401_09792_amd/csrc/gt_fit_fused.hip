@@ -281,9 +281,11 @@ __device__ __forceinline__ void fused_t_finish(const DevChan& ch, const GroupIte
 //   Bt[k'][c]    = part 0: (c < n: Re B[j][c], else Im B[j][c - n])
 //                  part 1: (c < n: -Im B[j][c], else Re B[j][c - n])
 // so that the real product A Bt is [Re T | Im T].  Output tiles are 32 x 32 over rows
-// (s, i) and the 2 n real columns (n <= 16: one column tile); tile r goes to wave r % 4.
+// (s, i) and the 2 n real columns (n <= 16: one column tile); tile r goes to wave r % 4.  The
+// bounds ask for four resident blocks per CU (at most 128 registers): without them the
+// accumulators went to 32 extra AGPRs, three blocks fitted, and the pass took 25 % longer.
 template <int TPW>
-__global__ void __launch_bounds__(256) k_fused_t_mfma(const DevChan* __restrict__ chans,
+__global__ void __launch_bounds__(256, 4) k_fused_t_mfma(const DevChan* __restrict__ chans,
                                                       const GroupItem* __restrict__ items,
                                                       const float2* __restrict__ X,
                                                       const float2* __restrict__ A,
