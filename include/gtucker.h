@@ -8,7 +8,9 @@
  * Conventions shared by every call
  * --------------------------------
  *  - Complex data is interleaved (re, im) single precision ("c64", 8 bytes per element),
- *    the layout of a torch.complex64 tensor.  Real outputs are float32.
+ *    the layout of a torch.complex64 tensor, and real outputs are float32; a plan created
+ *    with dtype GT_C128 takes double precision instead (16 bytes, torch.complex128, float64
+ *    outputs) on the calls that provide it (see gt_dtype).
  *  - Every data pointer is device memory owned by the caller.  The library never allocates
  *    device memory: scratch lives in a caller-allocated workspace whose size comes from
  *    gt_plan_workspace_bytes and which gt_workspace_init must fill once before use.
@@ -61,7 +63,16 @@ typedef enum {
 #define GT_DEV_CHOLESKY 4u       /* the MMSE covariance lost positive definiteness */
 #define GT_DEV_ZERO_STREAM 8u    /* sigma_r <= 1e-3 sigma_1 (FP32) for a requested stream: SINR_r := 0 */
 
-typedef enum { GT_C64 = 0 } gt_dtype;
+/* Element type of a plan's complex buffers.
+ *   GT_C64   interleaved FP32 (re, im), 8 bytes; real outputs (SINR, its gradient input) are
+ *            float32.  Every call is provided.
+ *   GT_C128  interleaved FP64 (re, im), 16 bytes; SINR outputs and grad_sinr are float64.
+ *            Provided for gt_sinr_eval, gt_sinr_eval_full and gt_sinr_eval_backward, which then
+ *            run the whole SVD / MMSE / SINR chain and its adjoint in FP64 on the GPU (for
+ *            validation and finite-difference gradient checks of the differentiation form, not
+ *            for throughput); the fit, reconstruction, their adjoints and the autotuner return
+ *            GT_ERR_UNSUPPORTED on such a plan.  sigma2 stays a float array. */
+typedef enum { GT_C64 = 0, GT_C128 = 1 } gt_dtype;
 
 /* Contraction precision of the fit's mode-n products H_s B and C_g^H H_s (the tensor-times-
  * matrix contractions of the A- and B-steps).  BF16 and FP16 round both operands to 16 bits;
@@ -91,9 +102,10 @@ typedef struct {
 
 typedef struct {
   int32_t iters;       /* alternating sweeps S, >= 0 */
-  int32_t ttm_prec;    /* gt_ttm_prec */
+  int32_t ttm_prec;    /* gt_ttm_prec (GT_TTM_FP32 on a GT_C128 plan) */
   int32_t eig_fp64;    /* 1: Gram eigensolves in FP64 (on the FP32-accumulated Grams) */
   uint32_t flags;      /* GT_FIT_* */
+  int32_t dtype;       /* gt_dtype of the plan's buffers (0 = GT_C64) */
 } gt_fit_options;
 
 typedef struct gt_plan gt_plan;
@@ -101,7 +113,8 @@ typedef struct gt_plan gt_plan;
 /* Validates the descriptors and builds an immutable host plan (sizes, offsets, device
  * tables, workspace layout).  Errors: GT_ERR_ARG (null, n_channels<1), GT_ERR_SHAPE (a
  * dimension out of range: nr<=16, nt<=256, group_size<=32, nsc>=1), GT_ERR_RANK (rank or
- * ns out of range), GT_ERR_UNSUPPORTED (an option not provided).  On success *out owns the
+ * ns out of range), GT_ERR_UNSUPPORTED (an option not provided, such as 16-bit contractions on
+ * a GT_C128 plan).  `opt` may be NULL (all options zero).  On success *out owns the
  * plan until gt_plan_destroy.  Pure host code: needs no GPU. */
 gt_status gt_plan_create(const gt_channel_desc* descs, int32_t n_channels,
                          const gt_fit_options* opt, gt_plan** out);
@@ -146,21 +159,21 @@ gt_status gt_tucker_reconstruct(const gt_plan* plan, const void* A, const void* 
  * (equation "precoding matrix"); covariance, MMSE filter and per-stream SINR (equations
  * "covariance matrix", "MMSE receive filter", "s_r^ij", "SINR formula") on the m x m
  * compressed covariance.  sigma2: host array of n_snr noise variances (1 <= n_snr <= 16).
- * Output layout as above. */
+ * Output layout as above: float32 on a GT_C64 plan, float64 on a GT_C128 plan. */
 gt_status gt_sinr_eval(const gt_plan* plan, const void* C, const void* G, const float* sigma2,
-                       int32_t n_snr, float* sinr, int32_t* dev_status, void* ws, size_t ws_bytes,
+                       int32_t n_snr, void* sinr, int32_t* dev_status, void* ws, size_t ws_bytes,
                        void* stream);
 
 /* The same chain on the uncompressed channel H_s (nr x nt) read from X (Section 2.2). */
 gt_status gt_sinr_eval_full(const gt_plan* plan, const void* X, const float* sigma2, int32_t n_snr,
-                            float* sinr, int32_t* dev_status, void* ws, size_t ws_bytes,
+                            void* sinr, int32_t* dev_status, void* ws, size_t ws_bytes,
                             void* stream);
 
-/* Adjoint of gt_sinr_eval: given grad_sinr (dl/dSINR, same layout as the SINR output),
- * writes grad_C and grad_G (layouts of C and G, overwritten) as dl/dRe + i dl/dIm.  The
- * SVD and the Cholesky factor are recomputed, not stored. */
+/* Adjoint of gt_sinr_eval: given grad_sinr (dl/dSINR, same layout and real type as the SINR
+ * output), writes grad_C and grad_G (layouts of C and G, overwritten) as dl/dRe + i dl/dIm.
+ * The SVD and the Cholesky factor are recomputed, not stored. */
 gt_status gt_sinr_eval_backward(const gt_plan* plan, const void* C, const void* G,
-                                const float* sigma2, int32_t n_snr, const float* grad_sinr,
+                                const float* sigma2, int32_t n_snr, const void* grad_sinr,
                                 void* grad_C, void* grad_G, int32_t* dev_status, void* ws,
                                 size_t ws_bytes, void* stream);
 
@@ -193,7 +206,10 @@ typedef struct {
 gt_status gt_plan_autotune(gt_plan* plan, const void* X, void* A, void* B, void* C, void* G,
                            void* ws, size_t ws_bytes, void* stream, gt_tune_result* out);
 /* Sets the choices directly (for instance ones an earlier autotune stored for the same
- * shapes).  GT_ERR_ARG for a value out of range.  Pure host code. */
+ * shapes).  GT_ERR_ARG for a value out of range; GT_ERR_UNSUPPORTED for bstep or tpass other
+ * than 0 on a plan with 16-bit contractions (those variants are FP32-only).  Pure host code.
+ * gt_plan_autotune and gt_plan_set_tuning change the plan: they must not run concurrently
+ * with any other call on the same plan. */
 gt_status gt_plan_set_tuning(gt_plan* plan, int32_t bstep, int32_t tpass, int32_t split);
 
 /* The fit is an argmax over eigenvectors and is not differentiated: always returns

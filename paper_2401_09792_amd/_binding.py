@@ -13,6 +13,7 @@ STATUS_NAMES = {0: "GT_OK", 1: "GT_ERR_ARG", 2: "GT_ERR_SHAPE", 3: "GT_ERR_RANK"
                 4: "GT_ERR_WORKSPACE", 5: "GT_ERR_UNSUPPORTED", 6: "GT_ERR_HIP",
                 7: "GT_ERR_NO_DEVICE"}
 GT_FIT_WARM_START = 1
+GT_C64, GT_C128 = 0, 1
 DEV_NONFINITE, DEV_EIG_SWEEPS, DEV_CHOLESKY, DEV_ZERO_STREAM = 1, 2, 4, 8
 
 
@@ -30,7 +31,7 @@ class Offsets(C.Structure):
 
 class FitOptions(C.Structure):
     _fields_ = [("iters", C.c_int32), ("ttm_prec", C.c_int32), ("eig_fp64", C.c_int32),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("dtype", C.c_int32)]
 
 
 class TuneResult(C.Structure):

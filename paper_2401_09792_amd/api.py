@@ -22,11 +22,23 @@ def _ptr(t: Optional[torch.Tensor]):
     return C.c_void_p(t.data_ptr())
 
 
-def _c64(t: torch.Tensor, n: int, name: str) -> torch.Tensor:
-    if t.dtype != torch.complex64:
-        raise TypeError(f"{name} must be complex64")
+def _buf(t: Optional[torch.Tensor], n: int, dtype: torch.dtype, name: str,
+         optional: bool = False) -> Optional[torch.Tensor]:
+    """Checks that a buffer handed to the library is a contiguous GPU tensor of the plan's
+    element type with exactly the number of elements the plan lays out for it (a smaller
+    buffer would let the kernels write past its end)."""
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
     if t.numel() != n:
         raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
     return t
 
 
@@ -38,22 +50,33 @@ class Plan:
     """Immutable description of a batch of channels plus its device workspace.
 
     descs: iterable of dicts with keys nr, nt, nsc, group_size, m, n, p, ns.
-    Packed buffers (1-D complex64): X, A, B, C, G, Ht with per-channel blocks at
-    `offsets(c)`; SINR output is float32 [n_snr][total_subcarriers][ns_max].
+    Packed buffers (1-D complex64, or complex128 on a "c128" plan): X, A, B, C, G, Ht with
+    per-channel blocks at `offsets(c)`; SINR output is float32 (float64 on a "c128" plan)
+    [n_snr][total_subcarriers][ns_max].  Every buffer is checked against the plan's sizes and
+    element type before the library sees its pointer.
     """
 
     TTM_PREC = {"fp32": 0, "bf16": 1, "fp16": 2, "split_bf16": 3}
+    DTYPES = {"c64": (B.GT_C64, torch.complex64, torch.float32),
+              "c128": (B.GT_C128, torch.complex128, torch.float64)}
 
     def __init__(self, descs: Iterable[dict], iters: int = 20, eig_fp64: bool = False,
-                 warm_start: bool = False, ttm_prec: str = "fp32", device="cuda"):
+                 warm_start: bool = False, ttm_prec: str = "fp32", device="cuda",
+                 dtype: str = "c64"):
+        """dtype "c128" makes a plan whose SINR calls (forward, full-channel and adjoint) run
+        in FP64 on complex128 buffers with float64 outputs; it provides no fit."""
         self.lib = load()
+        if dtype not in self.DTYPES:
+            raise ValueError(f"dtype must be one of {sorted(self.DTYPES)}")
+        code, self.cdtype, self.rdtype = self.DTYPES[dtype]
+        self.dtype = dtype
         self.descs: List[dict] = [dict(d) for d in descs]
         arr = (ChannelDesc * len(self.descs))()
         for i, d in enumerate(self.descs):
             arr[i] = ChannelDesc(d["nr"], d["nt"], d["nsc"], d["group_size"], d["m"], d["n"],
                                  d["p"], d["ns"])
         opt = FitOptions(int(iters), self.TTM_PREC[ttm_prec], 1 if eig_fp64 else 0,
-                         B.GT_FIT_WARM_START if warm_start else 0)
+                         B.GT_FIT_WARM_START if warm_start else 0, code)
         h = C.c_void_p()
         check("gt_plan_create", self.lib.gt_plan_create(arr, len(self.descs), C.byref(opt),
                                                         C.byref(h)))
@@ -93,8 +116,21 @@ class Plan:
         return o
 
     # -- buffers ---------------------------------------------------------------------
-    def _new(self, n: int, dtype=torch.complex64) -> torch.Tensor:
-        return torch.zeros(n, dtype=dtype, device=self.device)
+    def _new(self, n: int, dtype=None) -> torch.Tensor:
+        return torch.zeros(n, dtype=dtype or self.cdtype, device=self.device)
+
+    def _cx(self, t, what: str, name: str, optional: bool = False):
+        """A packed complex buffer of kind `what` (x, a, b, c, g or ht) at the plan's sizes."""
+        return _buf(t, getattr(self.totals, what), self.cdtype, name, optional)
+
+    def _sinr_shape(self, k: int):
+        return (k, self.totals.sc, self.ns_max)
+
+    def _real_out(self, t, k: int, name: str, optional: bool = False):
+        return _buf(t, k * self.totals.sc * self.ns_max, self.rdtype, name, optional)
+
+    def _status(self, t, optional: bool = True):
+        return _buf(t, self.n_channels, torch.int32, "status", optional)
 
     def empty_factors(self) -> Dict[str, torch.Tensor]:
         t = self.totals
@@ -104,9 +140,10 @@ class Plan:
     def fit(self, X: torch.Tensor, factors: Optional[Dict[str, torch.Tensor]] = None,
             trace: bool = True) -> Dict[str, torch.Tensor]:
         """Groupwise Tucker compression of every channel in X (packed)."""
-        t = self.totals
-        _c64(X, t.x, "X")
+        self._cx(X, "x", "X")
         f = factors if factors is not None else self.empty_factors()
+        for k in ("A", "B", "C", "G"):
+            self._cx(f.get(k), k.lower(), f"factors[{k!r}]")
         tr = (torch.zeros(self.n_channels * (1 + 3 * self.iters), dtype=torch.float64,
                           device=self.device) if trace else None)
         st = torch.zeros(self.n_channels, dtype=torch.int32, device=self.device)
@@ -122,7 +159,7 @@ class Plan:
     def autotune(self, X: torch.Tensor) -> Dict[str, float]:
         """Times the fit's pass variants on X and keeps the fastest in the plan (synchronises;
         call before capturing fits in a graph)."""
-        _c64(X, self.totals.x, "X")
+        self._cx(X, "x", "X")
         f = self.empty_factors()
         res = TuneResult()
         check("gt_plan_autotune", self.lib.gt_plan_autotune(
@@ -136,6 +173,10 @@ class Plan:
 
     def reconstruct(self, A, B_, C_, G, ht: bool = True, xhat: bool = True):
         t = self.totals
+        self._cx(A, "a", "A", optional=not xhat)
+        self._cx(B_, "b", "B", optional=not xhat)
+        self._cx(C_, "c", "C")
+        self._cx(G, "g", "G")
         Ht = self._new(t.ht) if ht else None
         Xh = self._new(t.x) if xhat else None
         check("gt_tucker_reconstruct", self.lib.gt_tucker_reconstruct(
@@ -150,9 +191,12 @@ class Plan:
     def sinr(self, C_, G, sigma2: Sequence[float], out: Optional[torch.Tensor] = None,
              status: Optional[torch.Tensor] = None) -> torch.Tensor:
         s2, k = self._sigma2(sigma2)
+        self._cx(C_, "c", "C")
+        self._cx(G, "g", "G")
+        self._status(status)
         if out is None:
-            out = torch.empty((k, self.totals.sc, self.ns_max), dtype=torch.float32,
-                              device=self.device)
+            out = torch.empty(self._sinr_shape(k), dtype=self.rdtype, device=self.device)
+        self._real_out(out, k, "out")
         check("gt_sinr_eval", self.lib.gt_sinr_eval(
             self._h, _ptr(C_), _ptr(G), s2, k, _ptr(out), _ptr(status), _ptr(self.ws),
             self.ws_bytes, _stream()))
@@ -161,9 +205,11 @@ class Plan:
     def sinr_full(self, X, sigma2: Sequence[float], out: Optional[torch.Tensor] = None,
                   status: Optional[torch.Tensor] = None) -> torch.Tensor:
         s2, k = self._sigma2(sigma2)
+        self._cx(X, "x", "X")
+        self._status(status)
         if out is None:
-            out = torch.empty((k, self.totals.sc, self.ns_max), dtype=torch.float32,
-                              device=self.device)
+            out = torch.empty(self._sinr_shape(k), dtype=self.rdtype, device=self.device)
+        self._real_out(out, k, "out")
         check("gt_sinr_eval_full", self.lib.gt_sinr_eval_full(
             self._h, _ptr(X), s2, k, _ptr(out), _ptr(status), _ptr(self.ws), self.ws_bytes,
             _stream()))
@@ -171,20 +217,30 @@ class Plan:
 
     def sinr_backward(self, C_, G, sigma2, grad_sinr, status=None):
         s2, k = self._sigma2(sigma2)
+        self._cx(C_, "c", "C")
+        self._cx(G, "g", "G")
+        self._status(status)
+        if not isinstance(grad_sinr, torch.Tensor) or tuple(grad_sinr.shape) != self._sinr_shape(k):
+            raise ValueError(f"grad_sinr must have shape {self._sinr_shape(k)}")
+        gs = grad_sinr.contiguous().to(self.rdtype)
         gC = torch.empty_like(C_)
         gG = torch.empty_like(G)
-        gs = grad_sinr.contiguous().float()
         check("gt_sinr_eval_backward", self.lib.gt_sinr_eval_backward(
             self._h, _ptr(C_), _ptr(G), s2, k, _ptr(gs), _ptr(gC), _ptr(gG), _ptr(status),
             _ptr(self.ws), self.ws_bytes, _stream()))
         return gC, gG
 
     def reconstruct_backward(self, A, B_, C_, G, grad_Ht=None, grad_Xhat=None):
+        for t, what in ((A, "a"), (B_, "b"), (C_, "c"), (G, "g")):
+            self._cx(t, what, what.upper())
+        if grad_Ht is not None:
+            grad_Ht = self._cx(grad_Ht.contiguous(), "ht", "grad_Ht")
+        if grad_Xhat is not None:
+            grad_Xhat = self._cx(grad_Xhat.contiguous(), "x", "grad_Xhat")
         gA, gB, gC, gG = (torch.empty_like(v) for v in (A, B_, C_, G))
         check("gt_tucker_reconstruct_backward", self.lib.gt_tucker_reconstruct_backward(
             self._h, _ptr(A), _ptr(B_), _ptr(C_), _ptr(G),
-            _ptr(grad_Ht.contiguous() if grad_Ht is not None else None),
-            _ptr(grad_Xhat.contiguous() if grad_Xhat is not None else None),
+            _ptr(grad_Ht), _ptr(grad_Xhat),
             _ptr(gA), _ptr(gB), _ptr(gC), _ptr(gG), _ptr(self.ws), self.ws_bytes, _stream()))
         return gA, gB, gC, gG
 

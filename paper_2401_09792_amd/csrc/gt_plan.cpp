@@ -31,6 +31,12 @@ gt_status launch_sinr(const LaunchCtx& L, int64_t total_sc, bool full, const flo
 gt_status launch_sinr_bwd(const LaunchCtx& L, int64_t total_sc, const float2* C, const float2* G,
                           const float* s2, int n_snr, const float* gsinr, float2* gC, float2* gG,
                           int ns_max, int32_t* status);
+gt_status launch_sinr_c128(const LaunchCtx& L, int64_t total_sc, bool full, const double2* X,
+                           const double2* C, const double2* G, const float* s2, int n_snr,
+                           double* out, int ns_max, int32_t* status);
+gt_status launch_sinr_bwd_c128(const LaunchCtx& L, int64_t total_sc, const double2* C,
+                               const double2* G, const float* s2, int n_snr, const double* gsinr,
+                               double2* gC, double2* gG, int ns_max, int32_t* status);
 
 // ---------------------------------------------------------------------------------------
 // error detail and kernel timing
@@ -181,6 +187,10 @@ static gt_status plan_build(const gt_channel_desc* descs, int32_t n_channels,
   if (o.iters < 0 || o.eig_fp64 < 0 || o.eig_fp64 > 1) return GT_ERR_ARG;
   if (o.ttm_prec < GT_TTM_FP32 || o.ttm_prec > GT_TTM_SPLIT_BF16) return GT_ERR_ARG;
   if (o.flags & ~GT_FIT_WARM_START) return GT_ERR_ARG;
+  if (o.dtype != GT_C64 && o.dtype != GT_C128) return GT_ERR_ARG;
+  // c128 plans evaluate the SINR chain and its adjoint in FP64; the contraction precision
+  // option belongs to the fit, which they do not run
+  if (o.dtype == GT_C128 && o.ttm_prec != GT_TTM_FP32) return GT_ERR_UNSUPPORTED;
   for (int c = 0; c < n_channels; ++c) {
     gt_status st = validate(descs[c]);
     if (st != GT_OK) return st;
@@ -331,7 +341,7 @@ static gt_status plan_build(const gt_channel_desc* descs, int32_t n_channels,
     ch.w_VC = take(c8 * ch.ngroups * 32 * 32);
     ch.w_lamg = take(8 * (int64_t)ch.ngroups);
     ch.w_scal = take(8 * 8);
-    ch.w_gH = take(c8 * ch.nsc * ch.m * ch.n);
+    ch.w_gH = take((o.dtype == GT_C128 ? 2 : 1) * c8 * ch.nsc * ch.m * ch.n);
     ch.w_gAp = take(c8 * ch.ngroups * ch.nr * ch.m);
     ch.w_gBp = take(c8 * ch.ngroups * ch.nt * ch.n);
   }
@@ -542,6 +552,7 @@ gt_status gt_tucker_fit(const gt_plan* plan, const void* X, void* A, void* B, vo
   gt_status st = check_ws(plan, ws, ws_bytes);
   if (st != GT_OK) return st;
   if (!X || !A || !B || !C || !G) return GT_ERR_ARG;
+  if (plan->opt.dtype != GT_C64) return GT_ERR_UNSUPPORTED;
   // 16-bit contractions take K steps of 8 reals: every nt a multiple of 4
   if (plan->opt.ttm_prec != GT_TTM_FP32) {
     for (const auto& d : plan->desc)
@@ -553,6 +564,9 @@ gt_status gt_tucker_fit(const gt_plan* plan, const void* X, void* A, void* B, vo
 gt_status gt_plan_set_tuning(gt_plan* plan, int32_t bstep, int32_t tpass, int32_t split) {
   if (!plan || bstep < 0 || bstep > 2 || tpass < 0 || tpass > 1 || split < 0 || split > 1)
     return GT_ERR_ARG;
+  // the prefetching and the older B-step kernels and the vector-ALU T pass are FP32-only: on a
+  // 16-bit plan they would run the contraction on the FP32 X
+  if (plan->opt.ttm_prec != GT_TTM_FP32 && (bstep != 0 || tpass != 0)) return GT_ERR_UNSUPPORTED;
   plan->tune_bstep = bstep;
   plan->tune_tpass = tpass;
   plan->tune_split = split;
@@ -564,6 +578,7 @@ gt_status gt_plan_autotune(gt_plan* plan, const void* X, void* A, void* B, void*
   gt_status st = check_ws(plan, ws, ws_bytes);
   if (st != GT_OK) return st;
   if (!X || !A || !B || !C || !G) return GT_ERR_ARG;
+  if (plan->opt.dtype != GT_C64) return GT_ERR_UNSUPPORTED;
   if (plan->opt.ttm_prec != GT_TTM_FP32) {
     for (const auto& d : plan->desc)
       if (d.nt % 4 != 0) return GT_ERR_UNSUPPORTED;
@@ -640,6 +655,7 @@ gt_status gt_tucker_reconstruct(const gt_plan* plan, const void* A, const void* 
   gt_status st = check_ws(plan, ws, ws_bytes);
   if (st != GT_OK) return st;
   if (!C || !G || (Xhat && (!A || !B))) return GT_ERR_ARG;
+  if (plan->opt.dtype != GT_C64) return GT_ERR_UNSUPPORTED;
   if (!Ht && !Xhat) return GT_OK;
   LaunchCtx L = make_ctx(plan, ws, stream);
   return launch_reconstruct(L, plan->totals.sc, (const float2*)A, (const float2*)B,
@@ -654,31 +670,37 @@ static gt_status check_snr(const float* sigma2, int32_t n_snr) {
 }
 
 gt_status gt_sinr_eval(const gt_plan* plan, const void* C, const void* G, const float* sigma2,
-                       int32_t n_snr, float* sinr, int32_t* dev_status, void* ws, size_t ws_bytes,
+                       int32_t n_snr, void* sinr, int32_t* dev_status, void* ws, size_t ws_bytes,
                        void* stream) {
   gt_status st = check_ws(plan, ws, ws_bytes);
   if (st != GT_OK) return st;
   if ((st = check_snr(sigma2, n_snr)) != GT_OK) return st;
   if (!C || !G || !sinr) return GT_ERR_ARG;
   LaunchCtx L = make_ctx(plan, ws, stream);
+  if (plan->opt.dtype == GT_C128)
+    return launch_sinr_c128(L, plan->totals.sc, false, nullptr, (const double2*)C, (const double2*)G,
+                            sigma2, n_snr, (double*)sinr, plan->ns_max, dev_status);
   return launch_sinr(L, plan->totals.sc, false, nullptr, (const float2*)C, (const float2*)G, sigma2,
-                     n_snr, sinr, plan->ns_max, dev_status);
+                     n_snr, (float*)sinr, plan->ns_max, dev_status);
 }
 
 gt_status gt_sinr_eval_full(const gt_plan* plan, const void* X, const float* sigma2, int32_t n_snr,
-                            float* sinr, int32_t* dev_status, void* ws, size_t ws_bytes,
+                            void* sinr, int32_t* dev_status, void* ws, size_t ws_bytes,
                             void* stream) {
   gt_status st = check_ws(plan, ws, ws_bytes);
   if (st != GT_OK) return st;
   if ((st = check_snr(sigma2, n_snr)) != GT_OK) return st;
   if (!X || !sinr) return GT_ERR_ARG;
   LaunchCtx L = make_ctx(plan, ws, stream);
+  if (plan->opt.dtype == GT_C128)
+    return launch_sinr_c128(L, plan->totals.sc, true, (const double2*)X, nullptr, nullptr, sigma2,
+                            n_snr, (double*)sinr, plan->ns_max, dev_status);
   return launch_sinr(L, plan->totals.sc, true, (const float2*)X, nullptr, nullptr, sigma2, n_snr,
-                     sinr, plan->ns_max, dev_status);
+                     (float*)sinr, plan->ns_max, dev_status);
 }
 
 gt_status gt_sinr_eval_backward(const gt_plan* plan, const void* C, const void* G,
-                                const float* sigma2, int32_t n_snr, const float* grad_sinr,
+                                const float* sigma2, int32_t n_snr, const void* grad_sinr,
                                 void* grad_C, void* grad_G, int32_t* dev_status, void* ws,
                                 size_t ws_bytes, void* stream) {
   gt_status st = check_ws(plan, ws, ws_bytes);
@@ -686,8 +708,13 @@ gt_status gt_sinr_eval_backward(const gt_plan* plan, const void* C, const void* 
   if ((st = check_snr(sigma2, n_snr)) != GT_OK) return st;
   if (!C || !G || !grad_sinr || !grad_C || !grad_G) return GT_ERR_ARG;
   LaunchCtx L = make_ctx(plan, ws, stream);
+  if (plan->opt.dtype == GT_C128)
+    return launch_sinr_bwd_c128(L, plan->totals.sc, (const double2*)C, (const double2*)G, sigma2,
+                                n_snr, (const double*)grad_sinr, (double2*)grad_C, (double2*)grad_G,
+                                plan->ns_max, dev_status);
   return launch_sinr_bwd(L, plan->totals.sc, (const float2*)C, (const float2*)G, sigma2, n_snr,
-                         grad_sinr, (float2*)grad_C, (float2*)grad_G, plan->ns_max, dev_status);
+                         (const float*)grad_sinr, (float2*)grad_C, (float2*)grad_G, plan->ns_max,
+                         dev_status);
 }
 
 gt_status gt_tucker_reconstruct_backward(const gt_plan* plan, const void* A, const void* B,
@@ -698,6 +725,7 @@ gt_status gt_tucker_reconstruct_backward(const gt_plan* plan, const void* A, con
   gt_status st = check_ws(plan, ws, ws_bytes);
   if (st != GT_OK) return st;
   if (!A || !B || !C || !G || !grad_A || !grad_B || !grad_C || !grad_G) return GT_ERR_ARG;
+  if (plan->opt.dtype != GT_C64) return GT_ERR_UNSUPPORTED;
   LaunchCtx L = make_ctx(plan, ws, stream);
   return launch_reconstruct_bwd(L, plan->totals.sc, (const float2*)A, (const float2*)B,
                                 (const float2*)C, (const float2*)G, (const float2*)grad_Ht,

@@ -28,6 +28,26 @@ struct SnrArgs {
   int n;
 };
 
+// Element storage of the complex buffers: interleaved FP32 (float2) for c64 plans, FP64
+// (double2) for c128 plans.  Loads convert to the arithmetic type T.
+template <typename E>
+struct Elem;
+template <>
+struct Elem<float2> {
+  using R = float;
+  static __device__ __forceinline__ float2 make(float re, float im) { return make_float2(re, im); }
+};
+template <>
+struct Elem<double2> {
+  using R = double;
+  static __device__ __forceinline__ double2 make(double re, double im) { return make_double2(re, im); }
+};
+template <typename T, typename E>
+__device__ __forceinline__ Cx<T> ldc(const E* p) {
+  const E v = *p;
+  return {(T)v.x, (T)v.y};
+}
+
 template <typename T, int MP, int NMAX>
 struct SinrLds {
   EigLds<T, MP> e;
@@ -85,21 +105,22 @@ __device__ __forceinline__ int locate_sc(const ScRange& R, const DevChan* chans,
 }
 
 // Fills S.e.kr/ki with K = H H^H (padded) and, for the compressed form, stages Ht in S.hr/hi.
-template <typename T, int MP, int NMAX, bool FULL, typename Lds>
+template <typename T, int MP, int NMAX, bool FULL, typename Lds, typename E>
 __device__ void build_gram(Lds& S, int r, bool valid, const DevChan& ch, int64_t s,
-                           const float2* __restrict__ X, const float2* __restrict__ C,
-                           const float2* __restrict__ G, int& M, int& N) {
+                           const E* __restrict__ X, const E* __restrict__ C,
+                           const E* __restrict__ G, int& M, int& N) {
   M = valid ? (FULL ? ch.nr : ch.m) : 0;
   N = valid ? (FULL ? ch.nt : ch.n) : 0;
   if (!FULL) {
     if (r < M) {
       const int g = (int)(s / ch.gs);
-      const float2* Cs = C + ch.c + s * ch.p;
-      const float2* Gg = G + ch.g + (int64_t)g * ch.p * ch.m * ch.n;
+      const E* Cs = C + ch.c + s * ch.p;
+      const E* Gg = G + ch.g + (int64_t)g * ch.p * ch.m * ch.n;
       const int pg = min(ch.p, min(ch.gs, ch.nsc - g * ch.gs));
       for (int j = 0; j < N; ++j) {
-        Cx<float> acc{0.f, 0.f};
-        for (int q = 0; q < pg; ++q) cfma(acc, ld(Cs + q), ld(Gg + ((int64_t)q * ch.m + r) * ch.n + j));
+        Cx<T> acc{T(0), T(0)};
+        for (int q = 0; q < pg; ++q)
+          cfma(acc, ldc<T>(Cs + q), ldc<T>(Gg + ((int64_t)q * ch.m + r) * ch.n + j));
         S.hr[r][j] = (T)acc.re;
         S.hi[r][j] = (T)acc.im;
       }
@@ -110,10 +131,10 @@ __device__ void build_gram(Lds& S, int r, bool valid, const DevChan& ch, int64_t
     T ar = 0, ai = 0;
     if (r < M && k < M) {
       if (FULL) {
-        const float2* Hi = X + ch.x + (s * ch.nr + r) * ch.nt;
-        const float2* Hk = X + ch.x + (s * ch.nr + k) * ch.nt;
+        const E* Hi = X + ch.x + (s * ch.nr + r) * ch.nt;
+        const E* Hk = X + ch.x + (s * ch.nr + k) * ch.nt;
         for (int j = 0; j < N; ++j) {
-          float2 a = Hi[j], b = Hk[j];
+          E a = Hi[j], b = Hk[j];
           ar += (T)a.x * (T)b.x + (T)a.y * (T)b.y;
           ai += (T)a.y * (T)b.x - (T)a.x * (T)b.y;
         }
@@ -254,14 +275,16 @@ __device__ T stream_sinr(Lds& S, int r, int M, int ns, T s2, T& sr_out, T& dr_ou
   return sig / den;
 }
 
-template <typename T, int MP, int NMAX, bool FULL>
+// SPB subcarriers per block of SPB * MP lanes (64 / MP for FP32; FP64 blocks hold one
+// subcarrier so that their LDS fits).
+template <typename T, int MP, int NMAX, bool FULL, typename E = float2, typename O = float,
+          int SPB = 64 / MP>
 __global__ void __launch_bounds__(64) k_sinr(const DevChan* __restrict__ chans, ScRange R,
-                                              int64_t total_sc, const float2* __restrict__ X,
-                                              const float2* __restrict__ C,
-                                              const float2* __restrict__ G, SnrArgs snr,
-                                              float* __restrict__ out, int ns_max,
+                                              int64_t total_sc, const E* __restrict__ X,
+                                              const E* __restrict__ C,
+                                              const E* __restrict__ G, SnrArgs snr,
+                                              O* __restrict__ out, int ns_max,
                                               int32_t* status) {
-  constexpr int SPB = 64 / MP;
   __shared__ SinrFwdLds<T, MP, NMAX> lds[SPB];
   const int grp = threadIdx.x / MP, r = threadIdx.x % MP;
   SinrFwdLds<T, MP, NMAX>& S = lds[grp];
@@ -292,7 +315,7 @@ __global__ void __launch_bounds__(64) k_sinr(const DevChan* __restrict__ chans, 
       }
     }
     if (!ok && r == 0) bits |= GT_DEV_CHOLESKY;
-    if (valid && r < ns_max) out[((int64_t)k * total_sc + gsc) * ns_max + r] = (float)val;
+    if (valid && r < ns_max) out[((int64_t)k * total_sc + gsc) * ns_max + r] = (O)val;
   }
   if (valid && status && bits && r == 0) atomicOr(reinterpret_cast<unsigned int*>(status + c), bits);
 }
@@ -922,13 +945,12 @@ __global__ void __launch_bounds__(64) k_sinr_bwd_lane(const DevChan* __restrict_
 // when sigma_a and sigma_b are numerically equal (the exact value for such S).
 // dl/dHt per subcarrier goes to the workspace; k_sinr_bwd_reduce forms dl/dG and dl/dC.
 
-template <typename T, int MP, int NMAX>
+template <typename T, int MP, int NMAX, typename E = float2, typename O = float, int SPB = 64 / MP>
 __global__ void __launch_bounds__(64) k_sinr_bwd(const DevChan* __restrict__ chans, ScRange R,
-                                                  int64_t total_sc, const float2* __restrict__ C,
-                                                  const float2* __restrict__ G, SnrArgs snr,
-                                                  const float* __restrict__ gsinr, int ns_max,
+                                                  int64_t total_sc, const E* __restrict__ C,
+                                                  const E* __restrict__ G, SnrArgs snr,
+                                                  const O* __restrict__ gsinr, int ns_max,
                                                   char* ws, int32_t* status) {
-  constexpr int SPB = 64 / MP;
   __shared__ SinrLds<T, MP, NMAX> lds[SPB];
   const int grp = threadIdx.x / MP, r = threadIdx.x % MP;
   SinrLds<T, MP, NMAX>& S = lds[grp];
@@ -939,7 +961,7 @@ __global__ void __launch_bounds__(64) k_sinr_bwd(const DevChan* __restrict__ cha
   const DevChan& ch = chans[c];
   const int64_t s = gsc - ch.sc;
   int M, N;
-  build_gram<T, MP, NMAX, false>(S, r, valid, ch, s, nullptr, C, G, M, N);
+  build_gram<T, MP, NMAX, false>(S, r, valid, ch, s, (const E*)nullptr, C, G, M, N);
   bool conv = jacobi_herm<T, MP, 1>(S.e, r, 0, sizeof(T) == 4 ? 12 : 20);
   uint32_t bits = conv ? 0u : GT_DEV_EIG_SWEEPS;
   const int ns = valid ? ch.ns : 0;
@@ -1181,7 +1203,7 @@ __global__ void __launch_bounds__(64) k_sinr_bwd(const DevChan* __restrict__ cha
   wave_sync();
   // dl/dHt[i][j] = sum_{a,b} u_a[i] D[a][b] conj(v_b[j]); lane i = row
   if (valid && r < M) {
-    float2* gH = reinterpret_cast<float2*>(ws + ch.w_gH) + s * ch.m * ch.n;
+    E* gH = reinterpret_cast<E*>(ws + ch.w_gH) + s * ch.m * ch.n;
     for (int j = 0; j < N; ++j) {
       T ar = 0, ai = 0;
       for (int a = 0; a < ns; ++a) {
@@ -1196,7 +1218,7 @@ __global__ void __launch_bounds__(64) k_sinr_bwd(const DevChan* __restrict__ cha
         ar += ur * tr - ui * ti;
         ai += ur * ti + ui * tr;
       }
-      gH[(int64_t)r * ch.n + j] = make_float2((float)ar, (float)ai);
+      gH[(int64_t)r * ch.n + j] = Elem<E>::make((typename Elem<E>::R)ar, (typename Elem<E>::R)ai);
     }
   }
   if (valid && status && bits && r == 0) atomicOr(reinterpret_cast<unsigned int*>(status + c), bits);
@@ -1205,27 +1227,29 @@ __global__ void __launch_bounds__(64) k_sinr_bwd(const DevChan* __restrict__ cha
 // dl/dG_g[q] = sum_{s in g} conj(C[s,q]) dl/dHt_s ;  dl/dC[s,q] = <dl/dHt_s, G_g[q]>
 // STAGE: dl/dHt_s of the group and G_g are first copied to LDS (when they fit), so that the two
 // contractions read them from LDS rather than through the caches once per q or per entry.
-template <bool STAGE>
+template <bool STAGE, typename E = float2>
 __global__ void __launch_bounds__(256) k_sinr_bwd_reduce(const DevChan* __restrict__ chans,
                                                          const GroupItem* __restrict__ items,
-                                                         const float2* __restrict__ C,
-                                                         const float2* __restrict__ G,
-                                                         float2* gC, float2* gG, char* ws) {
-  extern __shared__ float2 sm[];
+                                                         const E* __restrict__ C,
+                                                         const E* __restrict__ G,
+                                                         E* gC, E* gG, char* ws) {
+  using R = typename Elem<E>::R;
+  extern __shared__ __align__(16) char sm_raw[];
+  E* sm = reinterpret_cast<E*>(sm_raw);
   const GroupItem it = items[blockIdx.x];
   const DevChan& ch = chans[it.ch];
   const int s0 = it.g * ch.gs;
   const int sz = min(ch.gs, ch.nsc - s0);
   const int pg = min(ch.p, sz);
   const int mn = ch.m * ch.n;
-  const float2* gHm = reinterpret_cast<const float2*>(ws + ch.w_gH) + (int64_t)s0 * mn;
-  const float2* Ggm = G + ch.g + (int64_t)it.g * ch.p * mn;
-  float2* gGg = gG + ch.g + (int64_t)it.g * ch.p * mn;
-  const float2* gH = gHm;
-  const float2* Gg = Ggm;
+  const E* gHm = reinterpret_cast<const E*>(ws + ch.w_gH) + (int64_t)s0 * mn;
+  const E* Ggm = G + ch.g + (int64_t)it.g * ch.p * mn;
+  E* gGg = gG + ch.g + (int64_t)it.g * ch.p * mn;
+  const E* gH = gHm;
+  const E* Gg = Ggm;
   if (STAGE) {
-    float2* sH = sm;
-    float2* sG = sm + sz * mn;
+    E* sH = sm;
+    E* sG = sm + sz * mn;
     for (int e = threadIdx.x; e < sz * mn; e += blockDim.x) sH[e] = gHm[e];
     for (int e = threadIdx.x; e < pg * mn; e += blockDim.x) sG[e] = Ggm[e];
     __syncthreads();
@@ -1238,30 +1262,30 @@ __global__ void __launch_bounds__(256) k_sinr_bwd_reduce(const DevChan* __restri
   const int nqc = (ch.p + QC - 1) / QC;
   for (int o = threadIdx.x; o < nqc * mn; o += blockDim.x) {
     const int qc = o / mn, e = o - qc * mn;
-    Cx<float> acc[QC];
+    Cx<R> acc[QC];
 #pragma unroll
-    for (int j = 0; j < QC; ++j) acc[j] = Cx<float>{0.f, 0.f};
+    for (int j = 0; j < QC; ++j) acc[j] = Cx<R>{R(0), R(0)};
     for (int i = 0; i < sz; ++i) {
-      const Cx<float> h = ld(gH + (int64_t)i * mn + e);
-      const float2* Ci = C + ch.c + (int64_t)(s0 + i) * ch.p + qc * QC;
+      const Cx<R> h = ldc<R>(gH + (int64_t)i * mn + e);
+      const E* Ci = C + ch.c + (int64_t)(s0 + i) * ch.p + qc * QC;
 #pragma unroll
       for (int j = 0; j < QC; ++j)
-        if (qc * QC + j < pg) cfmac(acc[j], ld(Ci + j), h);
+        if (qc * QC + j < pg) cfmac(acc[j], ldc<R>(Ci + j), h);
     }
 #pragma unroll
     for (int j = 0; j < QC; ++j)
-      if (qc * QC + j < ch.p) st(gGg + (int64_t)(qc * QC + j) * mn + e, acc[j]);
+      if (qc * QC + j < ch.p) gGg[(int64_t)(qc * QC + j) * mn + e] = Elem<E>::make(acc[j].re, acc[j].im);
   }
   // dl/dC: 16 lanes per (s, q) split the m n entries and reduce by shuffles; the 16 lanes of an
   // output are aligned and run the same passes
   const int l16 = threadIdx.x % 16;
   for (int o = threadIdx.x / 16; o < sz * ch.p; o += blockDim.x / 16) {
     const int i = o / ch.p, q = o % ch.p;
-    float ar = 0.f, ai = 0.f;
+    R ar = 0, ai = 0;
     if (q < pg) {
 #pragma unroll 8
       for (int e = l16; e < mn; e += 16) {
-        const float2 g = Gg[(int64_t)q * mn + e], h = gH[(int64_t)i * mn + e];
+        const E g = Gg[(int64_t)q * mn + e], h = gH[(int64_t)i * mn + e];
         ar += g.x * h.x + g.y * h.y;  // conj(g) h
         ai += g.x * h.y - g.y * h.x;
       }
@@ -1271,7 +1295,7 @@ __global__ void __launch_bounds__(256) k_sinr_bwd_reduce(const DevChan* __restri
       ar += __shfl_xor(ar, d, 64);
       ai += __shfl_xor(ai, d, 64);
     }
-    if (l16 == 0) gC[ch.c + (int64_t)(s0 + i) * ch.p + q] = make_float2(ar, ai);
+    if (l16 == 0) gC[ch.c + (int64_t)(s0 + i) * ch.p + q] = Elem<E>::make(ar, ai);
   }
 }
 
@@ -1420,12 +1444,13 @@ gt_status launch_sinr_bwd(const LaunchCtx& L, int64_t total_sc, const float2* C,
   return launch_grad_cg(L, C, G, gC, gG);
 }
 
-gt_status launch_grad_cg(const LaunchCtx& L, const float2* C, const float2* G, float2* gC, float2* gG) {
-  const size_t sh = sizeof(float2) * ((size_t)L.max_gs + L.max_p) * L.max_m * L.max_n;
+template <typename E>
+static gt_status grad_cg_t(const LaunchCtx& L, const E* C, const E* G, E* gC, E* gG) {
+  const size_t sh = sizeof(E) * ((size_t)L.max_gs + L.max_p) * L.max_m * L.max_n;
   if (sh <= 64 * 1024) {
     prof_begin("k_sinr_bwd_reduce", L.stream);
-    hipLaunchKernelGGL((k_sinr_bwd_reduce<true>), dim3(L.total_groups), dim3(256), sh, L.stream, L.d_chans,
-                       L.d_groups, C, G, gC, gG, L.ws);
+    hipLaunchKernelGGL((k_sinr_bwd_reduce<true, E>), dim3(L.total_groups), dim3(256), sh, L.stream,
+                       L.d_chans, L.d_groups, C, G, gC, gG, L.ws);
     prof_end(L.stream);
     hipError_t e_ = hipGetLastError();
     if (e_ != hipSuccess) {
@@ -1434,9 +1459,104 @@ gt_status launch_grad_cg(const LaunchCtx& L, const float2* C, const float2* G, f
     }
     return GT_OK;
   }
-  GT_LAUNCH((k_sinr_bwd_reduce<false>), dim3(L.total_groups), dim3(256), L.d_chans, L.d_groups, C, G, gC,
-            gG, L.ws);
+  GT_LAUNCH((k_sinr_bwd_reduce<false, E>), dim3(L.total_groups), dim3(256), L.d_chans, L.d_groups, C, G,
+            gC, gG, L.ws);
   return GT_OK;
+}
+
+gt_status launch_grad_cg(const LaunchCtx& L, const float2* C, const float2* G, float2* gC, float2* gG) {
+  return grad_cg_t<float2>(L, C, G, gC, gG);
+}
+
+// ---------------------------------------------------------------------------------------
+// FP64 (c128 plans): every class on the cooperative kernels in double, one subcarrier per
+// block of MP lanes (MP = 4, 8 or 16 by the class's m; staged rows sized by its largest n).
+// This form exists for validation and gradient checks, not for throughput.
+
+template <int MP, int NMAX, bool FULL>
+static gt_status sinr64_t(const LaunchCtx& L, const ScRange& R, int64_t total_sc, const double2* X,
+                          const double2* C, const double2* G, const SnrArgs& a, double* out,
+                          int ns_max, int32_t* status) {
+  GT_LAUNCH((k_sinr<double, MP, NMAX, FULL, double2, double, 1>), dim3((unsigned)R.count), dim3(MP),
+            L.d_chans, R, total_sc, X, C, G, a, out, ns_max, status);
+  return GT_OK;
+}
+
+template <int MP>
+static gt_status sinr64_by_n(const LaunchCtx& L, const ScRange& R, int N, int64_t total_sc,
+                             const double2* C, const double2* G, const SnrArgs& a, double* out,
+                             int ns_max, int32_t* status) {
+  if (N <= 16) return sinr64_t<MP, 16, false>(L, R, total_sc, nullptr, C, G, a, out, ns_max, status);
+  if (N <= 32) return sinr64_t<MP, 32, false>(L, R, total_sc, nullptr, C, G, a, out, ns_max, status);
+  return sinr64_t<MP, 64, false>(L, R, total_sc, nullptr, C, G, a, out, ns_max, status);
+}
+
+static int class_mp(int k) {
+  return (k == SC_LANE4_2 || k == SC_LANE4_4) ? 4 : ((k == SC_LANE8_4 || k == SC_LANE8_8) ? 8 : 16);
+}
+
+gt_status launch_sinr_c128(const LaunchCtx& L, int64_t total_sc, bool full, const double2* X,
+                           const double2* C, const double2* G, const float* s2, int n_snr,
+                           double* out, int ns_max, int32_t* status) {
+  SnrArgs a{};
+  a.n = n_snr;
+  for (int k = 0; k < n_snr; ++k) a.s2[k] = s2[k];
+  if (full) {
+    const ScRange R = sc_range(L, 0, SC_COUNT);
+    if (R.count == 0) return GT_OK;
+    const int M = L.max_nr;
+    if (M <= 4) return sinr64_t<4, 1, true>(L, R, total_sc, X, C, G, a, out, ns_max, status);
+    if (M <= 8) return sinr64_t<8, 1, true>(L, R, total_sc, X, C, G, a, out, ns_max, status);
+    return sinr64_t<16, 1, true>(L, R, total_sc, X, C, G, a, out, ns_max, status);
+  }
+  for (int k = 0; k < SC_COUNT; ++k) {
+    const ScRange R = sc_range(L, k, k + 1);
+    if (R.count == 0) continue;
+    const int N = sc_maxn(L, k, k + 1);
+    const int mp = class_mp(k);
+    gt_status st = mp == 4 ? sinr64_by_n<4>(L, R, N, total_sc, C, G, a, out, ns_max, status)
+                 : mp == 8 ? sinr64_by_n<8>(L, R, N, total_sc, C, G, a, out, ns_max, status)
+                           : sinr64_by_n<16>(L, R, N, total_sc, C, G, a, out, ns_max, status);
+    if (st != GT_OK) return st;
+  }
+  return GT_OK;
+}
+
+template <int MP, int NMAX>
+static gt_status sinr64_bwd_t(const LaunchCtx& L, const ScRange& R, int64_t total_sc, const double2* C,
+                              const double2* G, const SnrArgs& a, const double* gs, int ns_max,
+                              int32_t* status) {
+  GT_LAUNCH((k_sinr_bwd<double, MP, NMAX, double2, double, 1>), dim3((unsigned)R.count), dim3(MP),
+            L.d_chans, R, total_sc, C, G, a, gs, ns_max, L.ws, status);
+  return GT_OK;
+}
+
+template <int MP>
+static gt_status sinr64_bwd_by_n(const LaunchCtx& L, const ScRange& R, int N, int64_t total_sc,
+                                 const double2* C, const double2* G, const SnrArgs& a,
+                                 const double* gs, int ns_max, int32_t* status) {
+  if (N <= 16) return sinr64_bwd_t<MP, 16>(L, R, total_sc, C, G, a, gs, ns_max, status);
+  if (N <= 32) return sinr64_bwd_t<MP, 32>(L, R, total_sc, C, G, a, gs, ns_max, status);
+  return sinr64_bwd_t<MP, 64>(L, R, total_sc, C, G, a, gs, ns_max, status);
+}
+
+gt_status launch_sinr_bwd_c128(const LaunchCtx& L, int64_t total_sc, const double2* C,
+                               const double2* G, const float* s2, int n_snr, const double* gsinr,
+                               double2* gC, double2* gG, int ns_max, int32_t* status) {
+  SnrArgs a{};
+  a.n = n_snr;
+  for (int k = 0; k < n_snr; ++k) a.s2[k] = s2[k];
+  for (int k = 0; k < SC_COUNT; ++k) {
+    const ScRange R = sc_range(L, k, k + 1);
+    if (R.count == 0) continue;
+    const int N = sc_maxn(L, k, k + 1);
+    const int mp = class_mp(k);
+    gt_status st = mp == 4 ? sinr64_bwd_by_n<4>(L, R, N, total_sc, C, G, a, gsinr, ns_max, status)
+                 : mp == 8 ? sinr64_bwd_by_n<8>(L, R, N, total_sc, C, G, a, gsinr, ns_max, status)
+                           : sinr64_bwd_by_n<16>(L, R, N, total_sc, C, G, a, gsinr, ns_max, status);
+    if (st != GT_OK) return st;
+  }
+  return grad_cg_t<double2>(L, C, G, gC, gG);
 }
 
 }  // namespace gt

@@ -24,3 +24,18 @@ def gpu_lib():
 
     api.load()  # raises if the shared library is missing
     return api
+
+
+@pytest.fixture(scope="session")
+def rb273_oracle():
+    """The 8 x 64 x 3276 channel (273 groups of 12, ranks (8, 16, 12), 20 sweeps) and the
+    FP64 oracle's fit, reconstruction and compressed SINR at its four SNRs."""
+    import synthgen
+    from oracle import sinr as osinr, tucker
+
+    cfg = synthgen.CONFIGS["rb273"]
+    X = synthgen.make_channel(cfg, 0)
+    orc = tucker.fit(X, cfg.group_size, cfg.m, cfg.n, cfg.p, cfg.iters)
+    Ht, Xh = tucker.reconstruct(orc["A"], orc["B"], orc["C"], orc["G"], cfg.group_size)
+    s2 = synthgen.snr_to_sigma2(cfg.snr_db)
+    return dict(cfg=cfg, X=X, orc=orc, Xh=Xh, sinr=osinr.sinr(Ht, s2, cfg.ns), s2=s2)

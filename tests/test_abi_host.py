@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def _plan(lib, descs, iters=3, flags=0, ttm=0, eig64=0):
     arr = (B.ChannelDesc * len(descs))(*[B.ChannelDesc(*d) for d in descs])
-    opt = B.FitOptions(iters, ttm, eig64, flags)
+    opt = B.FitOptions(iters, ttm, eig64, flags, 0)
     h = C.c_void_p()
     st = lib.gt_plan_create(arr, len(descs), C.byref(opt), C.byref(h))
     return st, h
@@ -134,3 +134,78 @@ def test_set_tuning_validation(lib):
     for v in ((3, 0, 0), (-1, 0, 0), (0, 2, 0), (0, 0, 2)):
         assert lib.gt_plan_set_tuning(h, *v) == 1, v   # GT_ERR_ARG
     lib.gt_plan_destroy(h)
+
+
+def test_set_tuning_rejects_fp32_variants_on_16bit_plans(lib):
+    # the prefetching / older B-step kernels and the vector-ALU T pass exist in FP32 only
+    st, h = _plan(lib, [(8, 64, 240, 12, 8, 16, 12, 4)] * 16, ttm=1)
+    assert st == 0
+    assert lib.gt_plan_set_tuning(h, 0, 0, 1) == 0
+    for v in ((1, 0, 1), (2, 0, 1), (0, 1, 1)):
+        assert lib.gt_plan_set_tuning(h, *v) == 5, v   # GT_ERR_UNSUPPORTED
+    lib.gt_plan_destroy(h)
+
+
+def _plan_dtype(lib, descs, dtype, ttm=0):
+    arr = (B.ChannelDesc * len(descs))(*[B.ChannelDesc(*d) for d in descs])
+    opt = B.FitOptions(3, ttm, 0, 0, dtype)
+    h = C.c_void_p()
+    return lib.gt_plan_create(arr, len(descs), C.byref(opt), C.byref(h)), h
+
+
+def test_c128_plans(lib):
+    d = (2, 8, 12, 12, 2, 4, 3, 2)
+    assert _plan_dtype(lib, [d], 2)[0] == 1                # unknown dtype: GT_ERR_ARG
+    assert _plan_dtype(lib, [d], B.GT_C128, ttm=1)[0] == 5  # 16-bit fit options: unsupported
+    st, h = _plan_dtype(lib, [d], B.GT_C128)
+    assert st == 0
+    st64, h64 = _plan_dtype(lib, [d], B.GT_C64)
+    w128, w64 = C.c_size_t(), C.c_size_t()
+    lib.gt_plan_workspace_bytes(h, C.byref(w128))
+    lib.gt_plan_workspace_bytes(h64, C.byref(w64))
+    assert w128.value > w64.value                          # FP64 gradient scratch
+    dummy = C.c_void_p(1 << 20)
+    # the fit, reconstruction and their adjoints are not provided in FP64: refused, no launch
+    assert lib.gt_tucker_fit(h, dummy, dummy, dummy, dummy, dummy, None, None, dummy,
+                             w128.value, None) == 5
+    assert lib.gt_tucker_reconstruct(h, dummy, dummy, dummy, dummy, dummy, dummy, dummy,
+                                     w128.value, None) == 5
+    assert lib.gt_tucker_reconstruct_backward(h, *([dummy] * 10), dummy, w128.value, None) == 5
+    lib.gt_plan_destroy(h)
+    lib.gt_plan_destroy(h64)
+
+
+def test_api_checks_every_buffer():
+    # the Python front end checks sizes and element types before any pointer reaches the
+    # library (a CPU plan: nothing is launched)
+    import torch
+
+    from paper_2401_09792_amd import api
+
+    d = dict(nr=4, nt=8, nsc=20, group_size=6, m=2, n=3, p=2, ns=2)
+    plan = api.Plan([d], iters=2, device="cpu")
+    t = plan.totals
+    C_ = torch.zeros(t.c, dtype=torch.complex64)
+    G = torch.zeros(t.g, dtype=torch.complex64)
+    with pytest.raises(ValueError, match="C has"):
+        plan.sinr(torch.zeros(t.c - 1, dtype=torch.complex64), G, [0.1])
+    with pytest.raises(TypeError, match="G must be"):
+        plan.sinr(C_, G.to(torch.complex128), [0.1])
+    with pytest.raises(ValueError, match="out has"):
+        plan.sinr(C_, G, [0.1, 1.0], out=torch.zeros((1, t.sc, plan.ns_max)))
+    with pytest.raises(TypeError, match="status must be"):
+        plan.sinr(C_, G, [0.1], status=torch.zeros(1, dtype=torch.int64))
+    with pytest.raises(ValueError, match="grad_sinr must have shape"):
+        plan.sinr_backward(C_, G, [0.1], torch.zeros((2, t.sc, plan.ns_max)))
+    with pytest.raises(ValueError, match="factors"):
+        f = plan.empty_factors()
+        f["B"] = f["B"][:-1]
+        plan.fit(torch.zeros(t.x, dtype=torch.complex64), factors=f)
+    with pytest.raises(ValueError, match="grad_Ht has"):
+        A, Bm = (torch.zeros(k, dtype=torch.complex64) for k in (t.a, t.b))
+        plan.reconstruct_backward(A, Bm, C_, G, grad_Ht=torch.zeros(3, dtype=torch.complex64))
+    with pytest.raises(ValueError, match="X has"):
+        plan.sinr_full(torch.zeros(t.x + 1, dtype=torch.complex64), [0.1])
+    p128 = api.Plan([d], iters=2, device="cpu", dtype="c128")
+    with pytest.raises(TypeError, match="complex128"):
+        p128.sinr(C_, G, [0.1])

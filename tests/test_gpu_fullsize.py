@@ -1,0 +1,96 @@
+"""Full-size parity of the plain FP32 path with the FP64 oracle.
+
+The 8 x 64 x 3276 workload (273 groups of 12, ranks (8, 16, 12), 20 sweeps, Ns = 4 at
+-5/0/10/20 dB) and the 16 x 256 x 3276 workload (ranks (12, 32, 12), 20 sweeps, Ns = 8 at
+10 dB) are fitted on the GPU in FP32 and compared with the oracle's fit of the same channel:
+NMSE within 1e-5 relative plus 1e-10, X-hat within 1e-5 (exactly representable 8 x 64 case)
+or 1e-4 (lossy 16 x 256 case) of ||X||, the objective within 1e-5 of ||X||^2 after the
+initialisation and after every half-step, and compressed SINR within 0.05 dB on every stream
+(Sections 3.2 and 3.3).  The full-channel SINR is checked on 8 x 128 and 16 x 256 arrays.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import synthgen
+from oracle import metrics, sinr as osinr, tucker
+from tests.gpu_util import announce, db, dev_c64, host, unpack
+from tests.test_gpu_parity import _gpu_fit_and_check
+
+pytestmark = pytest.mark.gpu
+
+
+def test_rb273_fp32_fit_and_sinr_full_size(gpu_lib, rb273_oracle):
+    cfg, X, orc, ref, s2 = (rb273_oracle[k] for k in ("cfg", "X", "orc", "sinr", "s2"))
+    announce("full size 8x64x3276 FP32 fit + SINR")
+    plan, res, _ = _gpu_fit_and_check(gpu_lib, X, cfg.group_size, cfg.m, cfg.n, cfg.p, cfg.ns,
+                                      cfg.iters, orc=orc, xhat_tol=1e-5)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    sg = host(plan.sinr(res["C"], res["G"], s2, status=st))[:, :, :cfg.ns]
+    err = np.abs(db(sg) - db(ref))
+    print(f"[full size] 8x64x3276: max SINR error {err.max():.3e} dB, mean {err.mean():.3e} dB",
+          flush=True)
+    assert err.max() <= 0.05, err.max()
+    assert int(st.item()) == 0
+
+
+def test_rb273_reconstruct_and_sinr_of_oracle_factors(gpu_lib, rb273_oracle):
+    # the oracle's own (A, B, C, G) through the GPU reconstruction and compressed SINR
+    cfg, X, orc, Xh_o, ref, s2 = (rb273_oracle[k] for k in ("cfg", "X", "orc", "Xh", "sinr", "s2"))
+    announce("full size 8x64x3276 reconstruct + SINR of the oracle's factors")
+    plan = gpu_lib.Plan([gpu_lib.desc_from_config(cfg)], iters=cfg.iters)
+    Ht_o, _ = tucker.reconstruct(orc["A"], orc["B"], orc["C"], orc["G"], cfg.group_size)
+    A, Bm, C, G = (dev_c64(orc[k]) for k in ("A", "B", "C", "G"))
+    ht, xh = plan.reconstruct(A, Bm, C, G)
+    ht = unpack(plan, 0, host(ht), "ht")
+    xh = unpack(plan, 0, host(xh), "x")
+    e_ht = np.linalg.norm(ht - Ht_o) / np.linalg.norm(Ht_o)
+    e_xh = np.linalg.norm(xh - Xh_o) / np.linalg.norm(Xh_o)
+    sg = host(plan.sinr(C, G, s2))[:, :, :cfg.ns]
+    err = np.abs(db(sg) - db(ref))
+    print(f"[full size] oracle factors: Ht {e_ht:.3e}, X-hat {e_xh:.3e} relative; "
+          f"SINR max {err.max():.3e} dB", flush=True)
+    assert e_ht <= 1e-5 and e_xh <= 1e-5
+    assert err.max() <= 0.05
+
+
+@pytest.fixture(scope="module")
+def wide_full():
+    cfg = synthgen.CONFIGS["wide"]
+    X = synthgen.make_channel(cfg, 0)
+    orc = tucker.fit(X, cfg.group_size, cfg.m, cfg.n, cfg.p, cfg.iters)
+    Ht, _ = tucker.reconstruct(orc["A"], orc["B"], orc["C"], orc["G"], cfg.group_size)
+    s2 = synthgen.snr_to_sigma2(cfg.snr_db)
+    return cfg, X, orc, osinr.sinr(Ht, s2, cfg.ns), s2
+
+
+def test_wide_fp32_fit_and_sinr_full_size(gpu_lib, wide_full):
+    cfg, X, orc, ref, s2 = wide_full
+    announce("full size 16x256x3276 FP32 fit + SINR")
+    plan, res, _ = _gpu_fit_and_check(gpu_lib, X, cfg.group_size, cfg.m, cfg.n, cfg.p, cfg.ns,
+                                      cfg.iters, orc=orc, xhat_tol=1e-4)
+    sg = host(plan.sinr(res["C"], res["G"], s2))[:, :, :cfg.ns]
+    err = np.abs(db(sg) - db(ref))
+    _, xh = plan.reconstruct(res["A"], res["B"], res["C"], res["G"])
+    nm = metrics.nmse(X, unpack(plan, 0, host(xh), "x"))
+    print(f"[full size] 16x256x3276: NMSE {nm:.4e}, max SINR error {err.max():.3e} dB, "
+          f"mean {err.mean():.3e} dB", flush=True)
+    assert err.max() <= 0.05, err.max()
+
+
+@pytest.mark.parametrize("name", ["grad", "wide"])
+def test_sinr_full_wide_arrays_full_size(gpu_lib, name):
+    # the uncompressed-channel SINR (Section 2.2) on 8 x 128 x 1632 and 16 x 256 x 3276
+    cfg = synthgen.CONFIGS[name]
+    announce(f"full-channel SINR {cfg.nr}x{cfg.nt}x{cfg.nsc}")
+    X = synthgen.make_channel(cfg, 0)
+    s2 = synthgen.snr_to_sigma2((-5.0, 0.0, 10.0, 20.0))
+    plan = gpu_lib.Plan([gpu_lib.desc_from_config(cfg)], iters=1)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = host(plan.sinr_full(dev_c64(X), s2, status=st))[:, :, :cfg.ns]
+    ref = osinr.sinr(X, s2, cfg.ns)
+    err = np.abs(db(out) - db(ref))
+    print(f"[full size] full-channel SINR {name}: max error {err.max():.3e} dB", flush=True)
+    assert err.max() <= 0.05, err.max()
+    assert int(st.item()) & ~8 == 0

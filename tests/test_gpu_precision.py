@@ -20,19 +20,9 @@ pytestmark = pytest.mark.gpu
 TOL = {"bf16": (0.1, 2e-2), "fp16": (0.1, 5e-3), "split_bf16": (0.05, 1e-4)}
 
 
-@pytest.fixture(scope="module")
-def rb273_oracle():
-    cfg = synthgen.CONFIGS["rb273"]
-    X = synthgen.make_channel(cfg, 0)
-    orc = tucker.fit(X, cfg.group_size, cfg.m, cfg.n, cfg.p, cfg.iters)
-    Ht, _ = tucker.reconstruct(orc["A"], orc["B"], orc["C"], orc["G"], cfg.group_size)
-    s2 = synthgen.snr_to_sigma2(cfg.snr_db)
-    return cfg, X, orc, osinr.sinr(Ht, s2, cfg.ns), s2
-
-
 @pytest.mark.parametrize("prec", ["bf16", "fp16", "split_bf16"])
 def test_precision_rb273_sinr(gpu_lib, rb273_oracle, prec):
-    cfg, X, orc, ref, s2 = rb273_oracle
+    cfg, X, ref, s2 = (rb273_oracle[k] for k in ("cfg", "X", "sinr", "s2"))
     announce(f"precision {prec} rb273 fit + sinr")
     plan = gpu_lib.Plan([gpu_lib.desc_from_config(cfg)], iters=cfg.iters, ttm_prec=prec)
     res = plan.fit(dev_c64(X))

@@ -242,9 +242,26 @@ def test_table1_storage_ratios():
 
 
 def test_subcarrier_group_storage_ratio():
-    # one channel with groups: Nr Nt Nsc / (Nr m + Nt n + sum_g (m n p_g + size_g p_g))
-    val = metrics.storage_ratio_subcarrier_groups(4, 32, 64, 16, 4, 8, 4)
-    assert abs(val - 4 * 32 * 64 / (16 + 256 + 4 * (128 + 64))) < 1e-12
+    # Pinned through the Individual and Shared formulas, whose values the 12 rows of Table 1
+    # fix (test above).  One channel compressed as a single group of all its subcarriers is
+    # the Individual model with J = K = 1 and P = Nsc.
+    for nr, nt, nsc, m, n, p in ((4, 32, 64, 4, 8, 4), (8, 64, 12, 8, 16, 12), (16, 256, 401, 12, 32, 150)):
+        one = metrics.storage_ratio_subcarrier_groups(nr, nt, nsc, nsc, m, n, p)
+        assert abs(one - metrics.storage_ratio_individual(1, 1, nr, nt, nsc, m, n, p)) < 1e-12 * one
+    # Equal groups of gs subcarriers share A and B as the Shared model's K = Nsc / gs tensors
+    # of P = gs slices do (J = 1).
+    for nr, nt, gs, G, m, n, p in ((4, 32, 16, 4, 4, 8, 4), (8, 64, 12, 273, 8, 16, 12),
+                                   (16, 256, 12, 273, 12, 32, 12), (8, 128, 12, 136, 8, 24, 5)):
+        val = metrics.storage_ratio_subcarrier_groups(nr, nt, gs * G, gs, m, n, p)
+        ref = metrics.storage_ratio_shared(1, G, nr, nt, gs, m, n, p)
+        assert abs(val - ref) < 1e-12 * ref, (val, ref)
+    # a short last group keeps p_g = min(p, size) slices: 64 subcarriers in groups of 24 leave
+    # a group of 16, which with p = 20 keeps 16
+    val = metrics.storage_ratio_subcarrier_groups(4, 32, 64, 24, 4, 8, 20)
+    full = metrics.storage_ratio_shared(1, 2, 4, 32, 24, 4, 8, 20)  # the two whole groups
+    stored_two = 4 * 32 * 48 / full
+    last = 4 * 8 * 16 + 16 * 16
+    assert abs(val - 4 * 32 * 64 / (stored_two + last)) < 1e-12 * val
 
 
 # ----------------------------------------------------------------------------------------
