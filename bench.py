@@ -387,7 +387,7 @@ def main():
              "k_stepA_group", "k_S3", "k_core", "k_objC", "k_trace", "k_norm_total", "k_fused_t",
              "k_fused_t_mfma", "k_fused_z", "k_fused_b", "k_fused_b_mfma", "k_fused_b_mm",
              "k_eigB_sub", "k_sub_prod", "k_sub_rr", "k_sub_rot", "k_rows_times_b", "k_w_rows", "k_yh_from_t", "k_gram_rows_st",
-             "k_reduce_S2_st", "k_reconstruct", "k_sinr_lane", "k_sinr", "k_sinr_bwd_lane",
+             "k_reduce_S2_st", "k_reconstruct", "k_reconstruct_ht", "k_sinr_rows", "k_sinr_lane", "k_sinr", "k_sinr_bwd_lane",
              "k_sinr_bwd", "k_sinr_bwd_reduce"]
     kern = {}
     for nm in names:
@@ -419,6 +419,7 @@ def main():
         "k_fused_b_mm": B * ng * CMAC * (gs * m * nr * nt + p * gs * m * nt
                                          + p * m * nt * nt / 2),
         "k_sinr_lane": sinr_units * sinr_unit_flops(m, n, p, cfg.ns, n_snr),
+        "k_sinr_rows": sinr_units * sinr_unit_flops(m, n, p, cfg.ns, n_snr),
         "k_sinr": sinr_units * sinr_unit_flops(m, n, p, cfg.ns, n_snr),
         "k_gram_rows": B * gram_rows_flops(ng, p, m, nt),
     }
@@ -433,7 +434,7 @@ def main():
                     frac=ach / PEAK_FP32_TFLOPS, traffic=measured_traffic(dom, args.workload),
                     algorithmic_flops_per_launch=models[dom],
                     share_of_step=kern[dom]["total_ms"] / ms_step)
-    sinr_k = kern.get("k_sinr_lane") or kern.get("k_sinr")
+    sinr_k = kern.get("k_sinr_rows") or kern.get("k_sinr_lane") or kern.get("k_sinr")
     sinr_rate = sinr_units / (sinr_k["avg_us"] * 1e-6) if sinr_k else None
 
     # accuracy of this step's output on channel 0 against the oracle, and the CPU baseline

@@ -1353,8 +1353,12 @@ static gt_status sinr_lane_t(const LaunchCtx& L, const ScRange& R, int64_t total
   return GT_OK;
 }
 
-// One launch per non-empty SINR class: the per-lane kernel for m <= 8, the cooperative one
-// for larger m; the full-channel form runs one cooperative launch over every channel.
+gt_status launch_sinr_rows(const LaunchCtx& L, int k0, int k1, int mp, int nsm, int64_t total_sc,
+                           const float2* C, const float2* G, const float* s2, int n_snr,
+                           float* out, int ns_max, int32_t* status);
+
+// One launch per non-empty SINR class: the row-parallel kernel for m <= 8, the cooperative
+// one for larger m; the full-channel form runs one cooperative launch over every channel.
 gt_status launch_sinr(const LaunchCtx& L, int64_t total_sc, bool full, const float2* X,
                       const float2* C, const float2* G, const float* s2, int n_snr, float* out,
                       int ns_max, int32_t* status) {
@@ -1373,10 +1377,10 @@ gt_status launch_sinr(const LaunchCtx& L, int64_t total_sc, bool full, const flo
     if (R.count == 0) continue;
     gt_status st = GT_OK;
     switch (k) {
-      case SC_LANE4_2: st = sinr_lane_t<4, 2>(L, R, total_sc, C, G, a, out, ns_max, status); break;
-      case SC_LANE4_4: st = sinr_lane_t<4, 4>(L, R, total_sc, C, G, a, out, ns_max, status); break;
-      case SC_LANE8_4: st = sinr_lane_t<8, 4>(L, R, total_sc, C, G, a, out, ns_max, status); break;
-      case SC_LANE8_8: st = sinr_lane_t<8, 8>(L, R, total_sc, C, G, a, out, ns_max, status); break;
+      case SC_LANE4_2: st = launch_sinr_rows(L, k, k + 1, 4, 2, total_sc, C, G, s2, n_snr, out, ns_max, status); break;
+      case SC_LANE4_4: st = launch_sinr_rows(L, k, k + 1, 4, 4, total_sc, C, G, s2, n_snr, out, ns_max, status); break;
+      case SC_LANE8_4: st = launch_sinr_rows(L, k, k + 1, 8, 4, total_sc, C, G, s2, n_snr, out, ns_max, status); break;
+      case SC_LANE8_8: st = launch_sinr_rows(L, k, k + 1, 8, 8, total_sc, C, G, s2, n_snr, out, ns_max, status); break;
       case SC_COOP_32:
         st = sinr_launch_t<16, 32, false>(L, R, total_sc, X, C, G, a, out, ns_max, status);
         break;

@@ -1,0 +1,548 @@
+// Per-subcarrier SINR from the compressed form (Section 3.3), row-parallel form.
+//
+// MP lanes of one wave (an aligned group, MP = 4, 8 or 16 >= m) handle one subcarrier; lane r
+// owns row r of every m x m matrix of the chain and keeps it in registers:
+//   Ht_s = sum_q C[s,q] G_g[q]   (equation "compressed matrix SINR reduction"), row r formed
+//                                by lane r, kRowsChunk columns at a time;
+//   K = Ht Ht^H                  rows from the staged chunk of Ht rows in LDS;
+//   K = U diag(sigma^2) U^H      parallel two-sided Jacobi: in step t of a sweep lane r is
+//                                paired with lane r xor t (t = 1 .. MP-1, so every pair of
+//                                indices meets once per sweep); partner rows are exchanged with
+//                                ds_swizzle, and the column rotations of the other pairs read
+//                                their (c, s) from LDS;
+//   HV = U_ns Sigma_ns           precoder of equation "precoding matrix" (HV = Ht V_ns);
+//   Q = HV HV^H + s2 I = L L^H   left-looking Cholesky, row c published to LDS at step c;
+//   W = Q^{-1} HV                substitutions over the rows, one row's values published per
+//                                step;
+//   c_rk = w_r^H hv_k            per-row partial products summed over the group by swizzles;
+//   SINR_r = |c_rr|^2 / (s2 ||w_r||^2 + sum_{k != r} |c_rk|^2)   (equations "s_r^ij" and
+//                                "SINR formula"; the denominator equals w_r^H Q w_r - s_r).
+// Spreading a subcarrier over MP lanes gives a launch MP times as many waves as one lane per
+// subcarrier, so the long serial chain of each small eigenproblem overlaps with others.
+#include <hip/hip_runtime.h>
+
+#include "gt_device.h"
+#include "gt_internal.h"
+
+namespace gt {
+
+struct RowsSnr {
+  float s2[kMaxSnr];
+  int n;
+};
+
+// Channels of a compact subcarrier range (channels ordered by SINR kernel class).
+struct RowsRange {
+  const int32_t* ch;
+  const int64_t* off;
+  int n;
+  int64_t base;
+  int64_t count;
+};
+
+__device__ __forceinline__ int rows_locate(const RowsRange& R, const DevChan* chans, int64_t i,
+                                           int64_t& gsc) {
+  const int64_t pos = R.base + i;
+  int lo = 0, hi = R.n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (R.off[mid] <= pos)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int c = R.ch[lo];
+  gsc = chans[c].sc + (pos - R.off[lo]);
+  return c;
+}
+
+// Value of lane (this lane xor T) within the same 32 lanes (ds_swizzle bitmask mode: and
+// mask 0x1F, xor mask T).
+template <int T>
+__device__ __forceinline__ float xswz(float v) {
+  static_assert(T > 0 && T < 32, "xor distance");
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x1F | (T << 10)));
+}
+
+template <int MP>
+__device__ __forceinline__ float rows_sum(float v) {
+  if (MP > 1) v += xswz<1>(v);
+  if (MP > 2) v += xswz<2>(v);
+  if (MP > 4) v += xswz<4>(v);
+  if (MP > 8) v += xswz<8>(v);
+  return v;
+}
+
+template <int MP>
+__device__ __forceinline__ uint32_t rows_or(uint32_t v) {
+  if (MP > 1) v |= (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (1 << 10));
+  if (MP > 2) v |= (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (2 << 10));
+  if (MP > 4) v |= (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (4 << 10));
+  if (MP > 8) v |= (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (8 << 10));
+  return v;
+}
+
+constexpr int kRowsChunk = 16;  // Ht columns staged per pass of the Gram
+
+template <int MP, int NS>
+struct RowsLds {
+  union {
+    float2 ht[MP][kRowsChunk];  // chunk of the Ht rows (Gram stage)
+    struct {
+      float2 hv[MP][NS];        // rows of HV = U_ns Sigma_ns
+      float2 l[MP][MP];         // rows of the Cholesky factor
+      float2 y[MP][NS];         // rows of the substitution results
+    } m;
+  } u;
+  float4 rot[MP];               // (c, Re s, Im s, -) of lane r's Jacobi pair in this step
+  float lam[MP];                // eigenvalues (K's diagonal after the sweeps)
+};
+
+// Jacobi rotation of the pair (p, q) zeroing K[p][q] = (kr, ki), with a = K[p][p] and
+// b = K[q][q]: rows p' = cs p + s q and q' = -conj(s) p + cs q, columns likewise from the right;
+// the new diagonal entries are a + tac and b - tac.  Identity when !live (a converged matrix) or
+// when the entry is already negligible.
+__device__ __forceinline__ void rows_rot_params(float a, float b, float kr, float ki, bool live,
+                                                float& cs, float& sr, float& si, float& tac) {
+  const float eps = 5.9604645e-08f;
+  const float ac = __builtin_sqrtf(kr * kr + ki * ki);
+  cs = 1.f;
+  sr = si = tac = 0.f;
+  if (live && ac > 0.f && ac > eps * 0.5f * (__builtin_fabsf(a) + __builtin_fabsf(b))) {
+    const float z = (b - a) / (2.f * ac);
+    const float az = __builtin_fabsf(z);
+    float tt = (az > 1.0e18f) ? 0.5f / az : 1.f / (az + __builtin_sqrtf(1.f + az * az));
+    if (z >= 0.f) tt = -tt;
+    cs = 1.f / __builtin_sqrtf(1.f + tt * tt);
+    const float sn = tt * cs;
+    sr = sn * kr / ac;
+    si = sn * ki / ac;
+    tac = tt * ac;
+  }
+}
+
+// Step T of a sweep: pair (r, r ^ T).  Rows (kr, ki) of K and (vr, vi) of V in this lane.
+template <int MP, int T>
+__device__ __forceinline__ void rows_jacobi_step(float4* rot, int r, bool live, float (&kr)[MP],
+                                                 float (&ki)[MP], float (&vr)[MP],
+                                                 float (&vi)[MP]) {
+  const int partner = r ^ T;
+  const bool lo = r < partner;
+  float d_me = 0.f, e_r = 0.f, e_i = 0.f;
+#pragma unroll
+  for (int j = 0; j < MP; ++j) {
+    d_me = (j == r) ? kr[j] : d_me;
+    e_r = (j == partner) ? kr[j] : e_r;
+    e_i = (j == partner) ? ki[j] : e_i;
+  }
+  const float d_pa = xswz<T>(d_me);
+  const float f_r = xswz<T>(e_r), f_i = xswz<T>(e_i);
+  // both lanes of the pair use K[p][p], K[q][q] and K[p][q] as the lower lane p holds them
+  const float a = lo ? d_me : d_pa, b = lo ? d_pa : d_me;
+  const float pr = lo ? e_r : f_r, pi = lo ? e_i : f_i;
+  float cs, sr, si, tac;
+  rows_rot_params(a, b, pr, pi, live, cs, sr, si, tac);
+  rot[r] = make_float4(cs, sr, si, 0.f);
+  wave_sync();
+  // K <- K J and V <- V J on the columns (j, j ^ T) of every pair, j < (j ^ T):
+  // column j' = c col_j + conj(s) col_jq, column jq' = -s col_j + c col_jq
+#pragma unroll
+  for (int j = 0; j < MP; ++j) {
+    constexpr int unused = 0;
+    (void)unused;
+    if (j < (j ^ T)) {
+      const int jq = j ^ T;
+      const float4 pj = rot[j];
+      const float c = pj.x, s_r = pj.y, s_i = pj.z;
+      float xr = kr[j], xi = ki[j], yr = kr[jq], yi = ki[jq];
+      kr[j] = c * xr + (s_r * yr + s_i * yi);
+      ki[j] = c * xi + (s_r * yi - s_i * yr);
+      kr[jq] = c * yr - (s_r * xr - s_i * xi);
+      ki[jq] = c * yi - (s_r * xi + s_i * xr);
+      xr = vr[j];
+      xi = vi[j];
+      yr = vr[jq];
+      yi = vi[jq];
+      vr[j] = c * xr + (s_r * yr + s_i * yi);
+      vi[j] = c * xi + (s_r * yi - s_i * yr);
+      vr[jq] = c * yr - (s_r * xr - s_i * xi);
+      vi[jq] = c * yi - (s_r * xi + s_i * xr);
+    }
+  }
+  // K <- J^H K: the lower lane takes cs x + s y, the upper one cs x - conj(s) y (y the
+  // partner's row after the column rotations)
+  const float tr = lo ? sr : -sr;
+#pragma unroll
+  for (int j = 0; j < MP; ++j) {
+    const float yr = xswz<T>(kr[j]), yi = xswz<T>(ki[j]);
+    kr[j] = cs * kr[j] + (tr * yr - si * yi);
+    ki[j] = cs * ki[j] + (tr * yi + si * yr);
+  }
+  if (tac != 0.f || sr != 0.f || si != 0.f) {
+#pragma unroll
+    for (int j = 0; j < MP; ++j) {
+      if (j == partner) {
+        kr[j] = 0.f;
+        ki[j] = 0.f;
+      }
+      if (j == r) {
+        kr[j] = lo ? a + tac : b - tac;
+        ki[j] = 0.f;
+      }
+    }
+  }
+  wave_sync();
+}
+
+template <int MP, int T>
+struct RowsSweep {
+  static __device__ __forceinline__ void run(float4* rot, int r, bool live, float (&kr)[MP],
+                                             float (&ki)[MP], float (&vr)[MP], float (&vi)[MP]) {
+    rows_jacobi_step<MP, T>(rot, r, live, kr, ki, vr, vi);
+    RowsSweep<MP, T + 1>::run(rot, r, live, kr, ki, vr, vi);
+  }
+};
+template <int MP>
+struct RowsSweep<MP, MP> {
+  static __device__ __forceinline__ void run(float4*, int, bool, float (&)[MP], float (&)[MP],
+                                             float (&)[MP], float (&)[MP]) {}
+};
+
+// Compressed-channel SINR for channels with m <= MP and ns <= NS, 256 / MP subcarriers per
+// block of 256 lanes.
+template <int MP, int NS>
+__global__ void __launch_bounds__(256) k_sinr_rows(const DevChan* __restrict__ chans, RowsRange R,
+                                                    int64_t total_sc, const float2* __restrict__ C,
+                                                    const float2* __restrict__ G, RowsSnr snr,
+                                                    float* __restrict__ out, int ns_max,
+                                                    int32_t* status) {
+  constexpr int SPB = 256 / MP;
+  __shared__ RowsLds<MP, NS> lds[SPB];
+  const int sub = threadIdx.x / MP, r = threadIdx.x % MP;
+  RowsLds<MP, NS>& S = lds[sub];
+  const int64_t it = (int64_t)blockIdx.x * SPB + sub;
+  const bool valid = it < R.count;
+  int64_t gsc = 0;
+  const int c = valid ? rows_locate(R, chans, it, gsc) : R.ch[0];
+  const DevChan& ch = chans[c];
+  const int64_t s = valid ? gsc - ch.sc : 0;
+  const int m = valid ? ch.m : 0;
+  const int n = valid ? ch.n : 0;
+  const int ns = valid ? ch.ns : 0;
+  const int g = (int)(s / ch.gs);
+  const int pg = min(ch.p, min(ch.gs, ch.nsc - g * ch.gs));
+  const bool row = r < m;
+  // row r of G_g[q] (rows past m read row m - 1 and are zeroed by a select)
+  const int rr = min(r, max(ch.m - 1, 0));
+  const float2* Cs = C + ch.c + s * ch.p;
+  const float2* Gr = G + ch.g + ((int64_t)g * ch.p * ch.m + rr) * ch.n;
+  const int64_t gq = (int64_t)ch.m * ch.n;
+
+  // ---- K = Ht Ht^H, row r -----------------------------------------------------------
+  float kr[MP], ki[MP];
+#pragma unroll
+  for (int j = 0; j < MP; ++j) kr[j] = ki[j] = 0.f;
+  for (int j0 = 0; j0 < n; j0 += kRowsChunk) {
+    float hr[kRowsChunk], hi[kRowsChunk];
+#pragma unroll
+    for (int jj = 0; jj < kRowsChunk; ++jj) hr[jj] = hi[jj] = 0.f;
+    for (int q = 0; q < pg; ++q) {
+      const float2 cq = Cs[q];
+      const float2* Gq = Gr + q * gq;
+#pragma unroll
+      for (int jj = 0; jj < kRowsChunk; ++jj) {
+        const int j = min(j0 + jj, n - 1);
+        const float2 gv = Gq[j];
+        hr[jj] += cq.x * gv.x - cq.y * gv.y;
+        hi[jj] += cq.x * gv.y + cq.y * gv.x;
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < kRowsChunk; ++jj) {
+      const bool on = row && (j0 + jj < n);
+      S.u.ht[r][jj] = make_float2(on ? hr[jj] : 0.f, on ? hi[jj] : 0.f);
+    }
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < MP; ++k) {
+#pragma unroll
+      for (int jj = 0; jj < kRowsChunk; jj += 2) {
+        const float4 a = *reinterpret_cast<const float4*>(&S.u.ht[r][jj]);
+        const float4 b = *reinterpret_cast<const float4*>(&S.u.ht[k][jj]);
+        // h_r conj(h_k)
+        kr[k] += a.x * b.x + a.y * b.y + (a.z * b.z + a.w * b.w);
+        ki[k] += a.y * b.x - a.x * b.y + (a.w * b.z - a.z * b.w);
+      }
+    }
+    wave_sync();
+  }
+
+  // ---- Jacobi sweeps ------------------------------------------------------------------
+  float vr[MP], vi[MP];
+#pragma unroll
+  for (int j = 0; j < MP; ++j) {
+    vr[j] = (j == r) ? 1.f : 0.f;
+    vi[j] = 0.f;
+  }
+  const float eps = 5.9604645e-08f;
+  uint32_t bits = 0;
+  bool conv = false;
+  for (int sw = 0; sw <= 10; ++sw) {
+    float off = 0.f, dg = 0.f;
+#pragma unroll
+    for (int j = 0; j < MP; ++j) {
+      const float v = kr[j] * kr[j] + ki[j] * ki[j];
+      if (j == r)
+        dg += v;
+      else
+        off += v;
+    }
+    off = rows_sum<MP>(off);
+    dg = rows_sum<MP>(dg);
+    const bool gdone = off <= 4.f * eps * eps * dg;  // the same in every lane of the group
+    if (__all(gdone ? 1 : 0)) {
+      conv = true;
+      break;
+    }
+    if (sw == 10) {
+      conv = gdone;
+      break;
+    }
+    RowsSweep<MP, 1>::run(S.rot, r, !gdone, kr, ki, vr, vi);
+  }
+  if (!conv) bits |= GT_DEV_EIG_SWEEPS;
+
+  // ---- descending eigenvalues, HV = U_ns Sigma_ns ---------------------------------------
+  float lam_me = 0.f;
+#pragma unroll
+  for (int j = 0; j < MP; ++j) lam_me = (j == r) ? kr[j] : lam_me;
+  S.lam[r] = row ? lam_me : -3.0e38f;
+  wave_sync();
+  float lam[MP];
+#pragma unroll
+  for (int j = 0; j < MP; ++j) lam[j] = S.lam[j];
+  int src[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) src[k] = 0;
+#pragma unroll
+  for (int j = 0; j < MP; ++j) {
+    int rk = 0;
+#pragma unroll
+    for (int i = 0; i < MP; ++i) rk += (lam[i] > lam[j] || (lam[i] == lam[j] && i < j)) ? 1 : 0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) src[k] = (rk == k) ? j : src[k];
+  }
+  float sig[NS], hvr[NS], hvi[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    float l = 0.f, ur = 0.f, ui = 0.f;
+#pragma unroll
+    for (int j = 0; j < MP; ++j) {
+      l = (src[k] == j) ? lam[j] : l;
+      ur = (src[k] == j) ? vr[j] : ur;
+      ui = (src[k] == j) ? vi[j] : ui;
+    }
+    sig[k] = __builtin_sqrtf(l > 0.f ? l : 0.f);
+    const bool on = row && k < ns;
+    hvr[k] = on ? sig[k] * ur : 0.f;
+    hvi[k] = on ? sig[k] * ui : 0.f;
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k)
+    if (k < ns && !(sig[k] > 1.0e-3f * sig[0])) bits |= GT_DEV_ZERO_STREAM;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) S.u.m.hv[r][k] = make_float2(hvr[k], hvi[k]);
+  wave_sync();
+  // P = HV HV^H, row r
+  float pr[MP], pi[MP];
+#pragma unroll
+  for (int j = 0; j < MP; ++j) {
+    float ar = 0.f, ai = 0.f;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const float2 h = S.u.m.hv[j][k];
+      ar += hvr[k] * h.x + hvi[k] * h.y;
+      ai += hvi[k] * h.x - hvr[k] * h.y;
+    }
+    pr[j] = ar;
+    pi[j] = ai;
+  }
+
+  // ---- per noise level: Cholesky, W, SINR -------------------------------------------------
+  for (int kk = 0; kk < snr.n; ++kk) {
+    const float s2 = snr.s2[kk];
+    // L row r starts as Q row r; padding rows r >= m are the identity
+    float lr[MP], li[MP];
+#pragma unroll
+    for (int j = 0; j < MP; ++j) {
+      lr[j] = row ? pr[j] + ((j == r) ? s2 : 0.f) : ((j == r) ? 1.f : 0.f);
+      li[j] = row ? pi[j] : 0.f;
+    }
+    bool ok = true;
+#pragma unroll
+    for (int cc = 0; cc < MP; ++cc) {
+      if (r == cc) {
+        float d = lr[cc];
+#pragma unroll
+        for (int k = 0; k < cc; ++k) d -= lr[k] * lr[k] + li[k] * li[k];
+        ok = d > 0.f;
+        lr[cc] = __builtin_sqrtf(d > 0.f ? d : 1.f);
+        li[cc] = 0.f;
+#pragma unroll
+        for (int k = 0; k <= cc; ++k) S.u.m.l[cc][k] = make_float2(lr[k], li[k]);
+      }
+      wave_sync();
+      if (r > cc) {
+        float ar = lr[cc], ai = li[cc];
+#pragma unroll
+        for (int k = 0; k < cc; ++k) {  // L[r][k] conj(L[cc][k])
+          const float2 y = S.u.m.l[cc][k];
+          ar -= lr[k] * y.x + li[k] * y.y;
+          ai -= li[k] * y.x - lr[k] * y.y;
+        }
+        const float inv = 1.f / S.u.m.l[cc][cc].x;
+        lr[cc] = ar * inv;
+        li[cc] = ai * inv;
+      }
+    }
+    // forward substitution L Y = HV: row i of Y is final at step i and published
+    float yr[NS], yi[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      yr[k] = hvr[k];
+      yi[k] = hvi[k];
+    }
+#pragma unroll
+    for (int i = 0; i < MP; ++i) {
+      if (r == i) {
+        const float inv = 1.f / lr[i];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          yr[k] *= inv;
+          yi[k] *= inv;
+          S.u.m.y[i][k] = make_float2(yr[k], yi[k]);
+        }
+      }
+      wave_sync();
+      if (r > i) {
+        const float ar = lr[i], ai = li[i];  // L[r][i]
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          const float2 y = S.u.m.y[i][k];
+          yr[k] -= ar * y.x - ai * y.y;
+          yi[k] -= ar * y.y + ai * y.x;
+        }
+      }
+    }
+    wave_sync();
+    // back substitution L^H W = Y: row i of W is final at step i (descending); the other rows
+    // j < i subtract conj(L[i][j]) w_i, with L[i][j] from the published rows of L
+#pragma unroll
+    for (int i = MP - 1; i >= 0; --i) {
+      if (r == i) {
+        const float inv = 1.f / lr[i];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          yr[k] *= inv;
+          yi[k] *= inv;
+          S.u.m.y[i][k] = make_float2(yr[k], yi[k]);
+        }
+      }
+      wave_sync();
+      if (r < i) {
+        const float2 l = S.u.m.l[i][r];  // conj(L[i][r]) w_i
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          const float2 w = S.u.m.y[i][k];
+          yr[k] -= l.x * w.x + l.y * w.y;
+          yi[k] -= l.x * w.y - l.y * w.x;
+        }
+      }
+    }
+    // yr/yi now hold row r of W; c_jk = sum_i conj(W[i][j]) HV[i][k] and ||w_j||^2
+    float sinr_me = 0.f;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      float sig_p = 0.f, den = 0.f;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        float cr = yr[j] * hvr[k] + yi[j] * hvi[k];
+        float ci = yr[j] * hvi[k] - yi[j] * hvr[k];
+        cr = rows_sum<MP>(cr);
+        ci = rows_sum<MP>(ci);
+        const float pw = cr * cr + ci * ci;
+        if (k == j)
+          sig_p = pw;
+        else
+          den += pw;
+      }
+      const float nw = rows_sum<MP>(yr[j] * yr[j] + yi[j] * yi[j]);
+      den += s2 * nw;
+      float v = sig_p / den;
+      if (!(sig[j] > 1.0e-3f * sig[0])) v = 0.f;
+      sinr_me = (j == r) ? v : sinr_me;
+    }
+    const bool any_bad = rows_or<MP>(ok ? 0u : 1u) != 0u;
+    if (any_bad) bits |= GT_DEV_CHOLESKY;
+    float v = (r < ns && !any_bad) ? sinr_me : 0.f;
+    if (!(v == v) || v > 3.0e38f) {
+      v = 0.f;
+      bits |= GT_DEV_NONFINITE;
+    }
+    if (valid) {
+      float* o = out + ((int64_t)kk * total_sc + gsc) * ns_max;
+      for (int q = r; q < ns_max; q += MP) o[q] = (q == r) ? v : 0.f;
+    }
+    wave_sync();
+  }
+  bits = rows_or<MP>(bits);
+  if (valid && status && bits && r == 0) atomicOr(reinterpret_cast<unsigned int*>(status + c), bits);
+}
+
+// ---------------------------------------------------------------------------------------
+
+template <int MP, int NS>
+static gt_status rows_launch_t(const LaunchCtx& L, const RowsRange& R, int64_t total_sc,
+                               const float2* C, const float2* G, const RowsSnr& a, float* out,
+                               int ns_max, int32_t* status) {
+  constexpr int SPB = 256 / MP;
+  const unsigned grid = (unsigned)((R.count + SPB - 1) / SPB);
+  prof_begin("k_sinr_rows", L.stream);
+  hipLaunchKernelGGL((k_sinr_rows<MP, NS>), dim3(grid), dim3(256), 0, L.stream, L.d_chans, R,
+                     total_sc, C, G, a, out, ns_max, status);
+  prof_end(L.stream);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error_detail("k_sinr_rows", e);
+    return GT_ERR_HIP;
+  }
+  return GT_OK;
+}
+
+// The compressed SINR of the classes [k0, k1) on the row-parallel kernel (m <= mp, ns <= nsm).
+gt_status launch_sinr_rows(const LaunchCtx& L, int k0, int k1, int mp, int nsm, int64_t total_sc,
+                           const float2* C, const float2* G, const float* s2, int n_snr,
+                           float* out, int ns_max, int32_t* status) {
+  RowsRange R;
+  const int j0 = L.sc_j[k0], j1 = L.sc_j[k1];
+  R.ch = L.d_sc_ch + j0;
+  R.off = L.d_sc_off + j0;
+  R.n = j1 - j0;
+  R.base = L.sc_base[k0];
+  R.count = L.sc_base[k1] - L.sc_base[k0];
+  if (R.count == 0) return GT_OK;
+  RowsSnr a{};
+  a.n = n_snr;
+  for (int k = 0; k < n_snr; ++k) a.s2[k] = s2[k];
+  if (mp <= 4) {
+    if (nsm <= 2) return rows_launch_t<4, 2>(L, R, total_sc, C, G, a, out, ns_max, status);
+    return rows_launch_t<4, 4>(L, R, total_sc, C, G, a, out, ns_max, status);
+  }
+  if (mp <= 8) {
+    if (nsm <= 4) return rows_launch_t<8, 4>(L, R, total_sc, C, G, a, out, ns_max, status);
+    return rows_launch_t<8, 8>(L, R, total_sc, C, G, a, out, ns_max, status);
+  }
+  return rows_launch_t<16, 8>(L, R, total_sc, C, G, a, out, ns_max, status);
+}
+
+}  // namespace gt
