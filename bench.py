@@ -11,10 +11,16 @@ One step = one pass of the whole path over a batch of channels resident in HBM:
 Prints one JSON line.  `value` is Tucker fits/s of the whole step; the SINR-evaluation
 rate of the SINR kernel is reported beside it.
 
+The headline steps run with the library's kernel timing off; a second pass of the same steps
+brackets every kernel with HIP events on its own stream for the per-kernel durations behind
+the rooflines (the B-step on FP32 matrix cores, the SINR kernel on the vector ALU and in HBM
+bytes, reconstruction in HBM bytes).  The line also carries the single-channel latency, a
+256-channel batch, the oracle on the host (all BLAS threads and one thread) and, unless
+`--no-forms`, the precision, graph-replay, differentiation and heterogeneous-batch forms.
+
 `--workload wide` times the same step on channels of 16 x 256 x 3276 (16 paths, K = 3 dB,
 ranks (12, 32, 12), 8 streams at 10 dB), 8 channels per step, for the profiles of the
-wide-array passes; the default run is the workload above.  `--forms` adds the precision,
-graph-replay, differentiation and heterogeneous-batch forms to the default run's line.
+wide-array passes; the default run is the workload above.
 """
 
 from __future__ import annotations
@@ -34,6 +40,9 @@ import numpy as np  # noqa: E402
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
+# vector ALU without packed FP32 instructions (disabled in this build): 256 CUs x 4 SIMDs x
+# 16 lanes x 2 flops per FMA x 2.4 GHz
+PEAK_VALU_FP32_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 # algorithmic work per unit of each timed kernel: CMAC = 8 real flops
 CMAC = 8.0
@@ -90,6 +99,120 @@ def measured_traffic(kernel: str, workload: str = "rb273"):
         if hashlib.sha256(fh.read()).hexdigest() != fields.get("source_sha256"):
             return None
     return float(fields["traffic_bytes_per_launch"])
+
+
+KERNEL_NAMES = [
+    "k_eigA", "k_eigB", "k_eigC", "k_gram_rows", "k_reduce_S1", "k_reduce_S2", "k_reduce_S2_mfma",
+    "k_init_group", "k_init_group_lds", "k_stepA_group", "k_S3", "k_core", "k_objC", "k_trace",
+    "k_norm_total", "k_fused_t", "k_fused_t_mfma", "k_fused_z", "k_fused_b", "k_fused_b_mfma",
+    "k_fused_b_mm", "k_eigB_sub", "k_sub_prod", "k_sub_rr", "k_sub_rot", "k_rows_times_b",
+    "k_w_rows", "k_yh_from_t", "k_gram_rows_st", "k_reduce_S2_st", "k_reconstruct",
+    "k_reconstruct_ht", "k_sinr_rows", "k_sinr_lane", "k_sinr", "k_sinr_bwd_rows",
+    "k_sinr_bwd_lane", "k_sinr_bwd", "k_sinr_bwd_reduce"]
+
+
+def profile_steps(api, fn, steps):
+    """Runs fn `steps` times with every library kernel bracketed by HIP events on its own
+    stream; returns per-kernel totals per step, launches per step and average durations."""
+    import torch
+
+    torch.cuda.synchronize()
+    api.profile_enable(True)
+    api.profile_reset()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    kern = {}
+    for nm in KERNEL_NAMES:
+        ms, cnt = api.profile_query(nm)
+        if cnt:
+            kern[nm] = dict(total_ms=ms / steps, launches=cnt // steps, avg_us=1e3 * ms / cnt)
+    api.profile_enable(False)
+    api.profile_reset()
+    return kern
+
+
+def _channels(synthgen, cfg, count, dev, torch):
+    xs = []
+    for c in range(count):
+        pp = synthgen.draw_paths(synthgen.channel_rng(cfg.seed_index, c), cfg.n_paths, cfg.k_db)
+        xs.append(synthgen.build_channel_torch(pp, cfg.nr, cfg.nt, cfg.nsc, dev,
+                                               dtype=torch.complex64).reshape(-1))
+    return torch.cat(xs)
+
+
+def single_channel_latency(api, synthgen, cfg, s2, dev, torch, reps=10):
+    """Latency of one channel through the whole step (fit, Ht, SINR, adjoint), median of reps."""
+    X = _channels(synthgen, cfg, 1, dev, torch)
+    plan = api.Plan([api.desc_from_config(cfg)], iters=cfg.iters)
+    f = plan.empty_factors()
+    gs = torch.full((len(s2), plan.totals.sc, plan.ns_max), 1.0e-3, dtype=torch.float32, device=dev)
+
+    def one():
+        r = plan.fit(X, factors=f, trace=False)
+        plan.reconstruct(r["A"], r["B"], r["C"], r["G"], ht=True, xhat=False)
+        plan.sinr(r["C"], r["G"], s2)
+        plan.sinr_backward(r["C"], r["G"], s2, gs)
+
+    one()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        one()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    times.sort()
+    return dict(ms=times[len(times) // 2], ms_min=times[0], reps=reps,
+                what="one 8x64x3276 channel: fit + Ht + SINR at 4 SNRs + SINR adjoint")
+
+
+def batch_throughput(api, synthgen, cfg, s2, dev, torch, count, steps=3):
+    """The same step over `count` seeded channels (fits/s)."""
+    X = _channels(synthgen, cfg, count, dev, torch)
+    plan = api.Plan([api.desc_from_config(cfg)] * count, iters=cfg.iters)
+    f = plan.empty_factors()
+    gs = torch.full((len(s2), plan.totals.sc, plan.ns_max), 1.0e-3, dtype=torch.float32, device=dev)
+
+    def one():
+        r = plan.fit(X, factors=f, trace=False)
+        plan.reconstruct(r["A"], r["B"], r["C"], r["G"], ht=True, xhat=False)
+        plan.sinr(r["C"], r["G"], s2)
+        plan.sinr_backward(r["C"], r["G"], s2, gs)
+
+    one()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        one()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    del X, plan, f
+    return dict(channels=count, ms_per_step=ms, fits_per_s=count / (ms / 1e3),
+                sinr_evals_per_s_step=count * cfg.nsc * len(s2) / (ms / 1e3))
+
+
+def host_description():
+    """nproc and the CPU model of the host the oracle runs on."""
+    desc = dict(nproc=os.cpu_count())
+    try:
+        import subprocess
+
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            k, _, v = ln.partition(":")
+            if k.strip() in ("Model name", "CPU(s)", "Thread(s) per core", "Core(s) per socket",
+                             "Socket(s)"):
+                desc[k.strip()] = v.strip()
+    except Exception:  # lscpu missing: nproc alone
+        pass
+    return desc
 
 
 def copy_calibration(mib: int) -> None:
@@ -313,9 +436,10 @@ def main():
     ap.add_argument("--batch", type=int, default=0,
                     help="channels per step (default 64 for rb273, 8 for wide)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=4, help="channels timed on the oracle")
-    ap.add_argument("--forms", action="store_true",
-                    help="also time the precision, graph-replay and refinement forms")
+    ap.add_argument("--cpu-sample", type=int, default=3,
+                    help="channels timed on the oracle with all BLAS threads")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the precision, graph-replay, refinement and batch forms")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run three plain copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -365,8 +489,7 @@ def main():
         step()
     torch.cuda.synchronize()
 
-    api.profile_enable(True)
-    api.profile_reset()
+    # headline: the timed steps with the library's kernel timing off
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -381,22 +504,15 @@ def main():
     ms_total = e0.elapsed_time(e1)
     ms_step = ms_total / args.steps
 
-    # live per-kernel durations over the timed region
-    names = ["k_eigA", "k_eigB", "k_eigC", "k_gram_rows", "k_reduce_S1", "k_reduce_S2",
-             "k_reduce_S2_mfma", "k_init_group", "k_init_group_lds",
-             "k_stepA_group", "k_S3", "k_core", "k_objC", "k_trace", "k_norm_total", "k_fused_t",
-             "k_fused_t_mfma", "k_fused_z", "k_fused_b", "k_fused_b_mfma", "k_fused_b_mm",
-             "k_eigB_sub", "k_sub_prod", "k_sub_rr", "k_sub_rot", "k_rows_times_b", "k_w_rows", "k_yh_from_t", "k_gram_rows_st",
-             "k_reduce_S2_st", "k_reconstruct", "k_reconstruct_ht", "k_sinr_rows", "k_sinr_lane", "k_sinr", "k_sinr_bwd_lane",
-             "k_sinr_bwd", "k_sinr_bwd_reduce"]
-    kern = {}
-    for nm in names:
-        ms, cnt = api.profile_query(nm)
-        if cnt:
-            kern[nm] = dict(total_ms=ms / args.steps, launches=cnt // args.steps,
-                            avg_us=1e3 * ms / cnt)
-    api.profile_enable(False)
-    api.profile_reset()
+    # a second pass of the same steps with every kernel bracketed by HIP events on its own
+    # stream: live per-kernel durations for the rooflines
+    kern = profile_steps(api, step, args.steps)
+    # the T pass and the eigensolves also run once unsplit (one stream), so that their
+    # durations are their own and not shared with concurrent parts
+    plan.set_tuning(bstep=0, tpass=0, split=0)
+    kern_unsplit = profile_steps(api, lambda: plan.fit(X, factors=f, trace=False), 1)
+    plan.set_tuning(bstep=0, tpass=0, split=1)
+    torch.cuda.synchronize()
 
     fits_per_s = B * args.steps / (ms_total / 1e3)
     ng = -(-cfg.nsc // cfg.group_size)
@@ -405,6 +521,7 @@ def main():
     # dominant kernel with an algorithmic work model, and its roofline
     nr, nt, m, n, p, gs = cfg.nr, cfg.nt, cfg.m, cfg.n, cfg.p, cfg.group_size
     n_sweeps = cfg.iters
+    sinr_flops = sinr_units * sinr_unit_flops(m, n, p, cfg.ns, n_snr)
     models = {
         # wide path, per launch over the B channels: the mode-2 Gram (one launch on the rows of
         # X for the initialisation, one per sweep on the W rows: the average over the
@@ -418,9 +535,9 @@ def main():
                                            + p * m * nt * nt / 2),
         "k_fused_b_mm": B * ng * CMAC * (gs * m * nr * nt + p * gs * m * nt
                                          + p * m * nt * nt / 2),
-        "k_sinr_lane": sinr_units * sinr_unit_flops(m, n, p, cfg.ns, n_snr),
-        "k_sinr_rows": sinr_units * sinr_unit_flops(m, n, p, cfg.ns, n_snr),
-        "k_sinr": sinr_units * sinr_unit_flops(m, n, p, cfg.ns, n_snr),
+        "k_sinr_lane": sinr_flops,
+        "k_sinr_rows": sinr_flops,
+        "k_sinr": sinr_flops,
         "k_gram_rows": B * gram_rows_flops(ng, p, m, nt),
     }
     bounds = {"k_fused_b_mfma": "mfma", "k_fused_b_mm": "mfma", "k_gram_rows": "mfma",
@@ -430,12 +547,58 @@ def main():
     if ranked:
         dom = ranked[0][1]
         ach = models[dom] / (kern[dom]["avg_us"] * 1e-6) / 1e12
-        roof = dict(kernel=dom, bound=bounds.get(dom, "alu"), achieved=ach, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                    frac=ach / PEAK_FP32_TFLOPS, traffic=measured_traffic(dom, args.workload),
+        bound = bounds.get(dom, "alu")
+        peak = PEAK_FP32_TFLOPS if bound == "mfma" else PEAK_VALU_FP32_TFLOPS
+        roof = dict(kernel=dom, bound=bound, achieved=ach, peak=peak, unit="TFLOP/s",
+                    frac=ach / peak, traffic=measured_traffic(dom, args.workload),
                     algorithmic_flops_per_launch=models[dom],
                     share_of_step=kern[dom]["total_ms"] / ms_step)
-    sinr_k = kern.get("k_sinr_rows") or kern.get("k_sinr_lane") or kern.get("k_sinr")
-    sinr_rate = sinr_units / (sinr_k["avg_us"] * 1e-6) if sinr_k else None
+    sinr_name = next((k for k in ("k_sinr_rows", "k_sinr_lane", "k_sinr") if k in kern), None)
+    sinr_k = kern.get(sinr_name) if sinr_name else None
+    sinr_rate = sinr_units / (sinr_k["total_ms"] * 1e-3) if sinr_k else None
+    roof_sinr = None
+    if sinr_k:
+        t_s = sinr_k["total_ms"] * 1e-3
+        sinr_bytes = sinr_units * sinr_unit_bytes(m, n, p, gs, n_snr, cfg.ns)
+        roof_sinr = dict(kernel=sinr_name, bound="alu", achieved=sinr_flops / t_s / 1e12,
+                         peak=PEAK_VALU_FP32_TFLOPS, unit="TFLOP/s",
+                         frac=sinr_flops / t_s / 1e12 / PEAK_VALU_FP32_TFLOPS,
+                         algorithmic_flops_per_launch=sinr_flops,
+                         evals_per_launch=sinr_units, evals_per_s=sinr_rate,
+                         hbm_gb_s=sinr_bytes / t_s / 1e9,
+                         hbm_frac=sinr_bytes / t_s / 1e9 / PEAK_HBM_GBS,
+                         traffic=measured_traffic(sinr_name, args.workload),
+                         share_of_step=sinr_k["total_ms"] / ms_step)
+    roof_rec = None
+    if "k_reconstruct_ht" in kern:
+        # Ht written, each group's core and the C rows read once
+        rec_bytes = B * 8.0 * (cfg.nsc * m * n + ng * p * m * n + cfg.nsc * p)
+        t_r = kern["k_reconstruct_ht"]["avg_us"] * 1e-6
+        roof_rec = dict(kernel="k_reconstruct_ht", bound="hbm", achieved=rec_bytes / t_r / 1e9,
+                        peak=PEAK_HBM_GBS, unit="GB/s", frac=rec_bytes / t_r / 1e9 / PEAK_HBM_GBS,
+                        algorithmic_bytes_per_launch=rec_bytes,
+                        traffic=measured_traffic("k_reconstruct_ht", args.workload))
+    # the fit's other passes: the T pass on its work model (unsplit launch), the eigensolves
+    # as latency (iterative; their flops are not counted)
+    fit_parts = {}
+    t_pass = kern_unsplit.get("k_fused_t_mfma")
+    if t_pass:
+        t_flops = B * ng * CMAC * (gs * nr * nt * n + gs * m * nr * n)
+        fit_parts["k_fused_t_mfma_unsplit"] = dict(
+            avg_us=t_pass["avg_us"], algorithmic_flops_per_launch=t_flops,
+            achieved_tflops=t_flops / (t_pass["avg_us"] * 1e-6) / 1e12,
+            frac_mfma_fp32=t_flops / (t_pass["avg_us"] * 1e-6) / 1e12 / PEAK_FP32_TFLOPS)
+    for nm in ("k_eigA", "k_eigB", "k_eigC", "k_fused_z", "k_reduce_S1", "k_reduce_S2_mfma"):
+        if nm in kern_unsplit:
+            fit_parts[nm + "_unsplit"] = dict(avg_us=kern_unsplit[nm]["avg_us"],
+                                              launches_per_fit=kern_unsplit[nm]["launches"],
+                                              ms_per_fit=kern_unsplit[nm]["total_ms"])
+    fit_flops = B * CMAC * sum(sweep_cmacs(nr, nt, cfg.nsc, gs, m, n, p)) * cfg.iters
+    fit_parts["whole_step_sweep_mfma_frac"] = fit_flops / (ms_step * 1e-3) / 1e12 / PEAK_FP32_TFLOPS
+
+    # single-channel latency and a 256-channel batch of the same step
+    latency = single_channel_latency(api, synthgen, cfg, s2, dev, torch) if not wide else None
+    big = batch_throughput(api, synthgen, cfg, s2, dev, torch, 256) if not wide else None
 
     # accuracy of this step's output on channel 0 against the oracle, and the CPU baseline
     cpu = None
@@ -447,6 +610,7 @@ def main():
 
         info = threadpoolctl.threadpool_info()
         threads = max([i.get("num_threads", 1) for i in info] + [1])
+        host = host_description()
         if wide:
             # a bounded sample: the first 540 subcarriers (45 groups) of channel 0, scaled to
             # channels of 3276 subcarriers
@@ -462,38 +626,53 @@ def main():
             cpu = dict(value=(nsub / cfg.nsc) / cpu_s, unit="fits/s", cores=threads, kind="oracle",
                        sample=f"first {nsub} of {cfg.nsc} subcarriers of one channel: fit + Ht + "
                               f"SINR (no adjoint), {cpu_s:.1f} s, scaled by {nsub}/{cfg.nsc}; "
-                              "complex128 NumPy/LAPACK")
-        nsamp = 0 if wide else max(1, args.cpu_sample)
-        t = time.perf_counter()
-        orc0 = None
-        for c in range(nsamp):
-            Xc = synthgen.make_channel(cfg, c)
-            orc = tucker.fit(Xc, cfg.group_size, cfg.m, cfg.n, cfg.p, cfg.iters)
-            Ht_o, _ = tucker.reconstruct(orc["A"], orc["B"], orc["C"], orc["G"], cfg.group_size)
-            sg_o = osinr.sinr(Ht_o, s2, cfg.ns)
-            if orc0 is None:
-                orc0 = (Xc, orc, sg_o)
-        if not wide:
-            cpu_s = time.perf_counter() - t
-            cpu = dict(value=nsamp / cpu_s, unit="fits/s", cores=threads, kind="oracle",
+                              "complex128 NumPy/LAPACK", host=host)
+        else:
+            # all BLAS threads on args.cpu_sample channels, then one thread on one channel; the
+            # SINR part of each is also reported as evals/s
+            def oracle_channels(nch):
+                t_fit = t_sinr = 0.0
+                first = None
+                for c in range(nch):
+                    Xc = synthgen.make_channel(cfg, c)
+                    t = time.perf_counter()
+                    orc = tucker.fit(Xc, cfg.group_size, cfg.m, cfg.n, cfg.p, cfg.iters)
+                    Ht_o, _ = tucker.reconstruct(orc["A"], orc["B"], orc["C"], orc["G"],
+                                                 cfg.group_size)
+                    t_fit += time.perf_counter() - t
+                    t = time.perf_counter()
+                    sg_o = osinr.sinr(Ht_o, s2, cfg.ns)
+                    t_sinr += time.perf_counter() - t
+                    if first is None:
+                        first = (Xc, orc, sg_o)
+                return t_fit, t_sinr, first
+
+            nsamp = max(1, args.cpu_sample)
+            t_fit, t_sinr, orc0 = oracle_channels(nsamp)
+            with threadpoolctl.threadpool_limits(1):
+                t_fit1, t_sinr1, _ = oracle_channels(1)
+            evals = cfg.nsc * n_snr
+            cpu = dict(value=nsamp / (t_fit + t_sinr), unit="fits/s", cores=threads, kind="oracle",
                        sample=f"{nsamp} channel(s) of the workload: fit + Ht + SINR at 4 SNRs "
-                              f"(no adjoint), {cpu_s:.1f} s, complex128 NumPy/LAPACK")
+                              f"(no adjoint), {t_fit + t_sinr:.1f} s, complex128 NumPy/LAPACK",
+                       sinr_evals_per_s=nsamp * evals / t_sinr,
+                       single_thread=dict(value=1.0 / (t_fit1 + t_sinr1), unit="fits/s", cores=1,
+                                          sinr_evals_per_s=evals / t_sinr1,
+                                          sample=f"1 channel, {t_fit1 + t_sinr1:.1f} s"),
+                       host=host)
     if not args.no_cpu_baseline and not wide:
         from oracle import metrics
 
         Xc, orc, sg_o = orc0
         sg0 = sg[:, :cfg.nsc, :cfg.ns].cpu().numpy()
         err = metrics.db_error(sg0, sg_o)
-        o0 = plan.offsets(0)
-        htg = ht[o0.ht:o0.ht + cfg.nsc * cfg.m * cfg.n].cpu().numpy()
         _, xh = plan.reconstruct(res["A"], res["B"], res["C"], res["G"], ht=False, xhat=True)
         xh0 = xh[:cfg.nsc * cfg.nr * cfg.nt].cpu().numpy().reshape(Xc.shape)
         acc = dict(max_sinr_err_db=float(err.max()), mean_sinr_err_db=float(err.mean()),
                    nmse_gpu=metrics.nmse(Xc, xh0))
-        del htg
 
     forms = None
-    if args.forms and not wide:
+    if not args.no_forms and not wide:
         forms = time_forms(api, synthgen, cfg, X, B, s2, ms_step, sg, torch, max(args.steps, 2))
 
     line = {
@@ -516,9 +695,15 @@ def main():
                    "channels_per_step": B, "parallelism": "single GPU"},
         "sinr_evals_per_s": sinr_rate,
         "roofline": roof,
+        "roofline_sinr": roof_sinr,
+        "roofline_reconstruct": roof_rec,
+        "fit_parts": fit_parts,
+        "latency_1ch": latency,
+        "batch_256": big,
         "cpu_baseline": cpu,
         "accuracy": acc,
         "kernels": kern,
+        "kernels_unsplit_fit": kern_unsplit,
         "forms": forms,
         "wall_s": wall,
     }

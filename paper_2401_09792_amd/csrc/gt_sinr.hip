@@ -1416,7 +1416,11 @@ static gt_status sinr_bwd_lane_t(const LaunchCtx& L, const ScRange& R, int64_t t
   return GT_OK;
 }
 
-// The adjoint: the per-lane kernel for m <= 8 with ns <= 4, the cooperative one for the rest
+gt_status launch_sinr_bwd_rows(const LaunchCtx& L, int k0, int k1, int mp, int nsm,
+                               int64_t total_sc, const float2* C, const float2* G, const float* s2,
+                               int n_snr, const float* gsinr, int ns_max, int32_t* status);
+
+// The adjoint: the row-parallel kernel for m <= 8 with ns <= 4, the cooperative one for the rest
 // (m <= 8 with ns > 4 on 8-lane groups sized by n), one launch per non-empty class, then the
 // per-group reduction into dl/dC and dl/dG.
 gt_status launch_sinr_bwd(const LaunchCtx& L, int64_t total_sc, const float2* C, const float2* G,
@@ -1430,9 +1434,9 @@ gt_status launch_sinr_bwd(const LaunchCtx& L, int64_t total_sc, const float2* C,
     if (R.count == 0) continue;
     gt_status st = GT_OK;
     switch (k) {
-      case SC_LANE4_2: st = sinr_bwd_lane_t<4, 2>(L, R, total_sc, C, G, a, gsinr, ns_max, status); break;
-      case SC_LANE4_4: st = sinr_bwd_lane_t<4, 4>(L, R, total_sc, C, G, a, gsinr, ns_max, status); break;
-      case SC_LANE8_4: st = sinr_bwd_lane_t<8, 4>(L, R, total_sc, C, G, a, gsinr, ns_max, status); break;
+      case SC_LANE4_2: st = launch_sinr_bwd_rows(L, k, k + 1, 4, 2, total_sc, C, G, s2, n_snr, gsinr, ns_max, status); break;
+      case SC_LANE4_4: st = launch_sinr_bwd_rows(L, k, k + 1, 4, 4, total_sc, C, G, s2, n_snr, gsinr, ns_max, status); break;
+      case SC_LANE8_4: st = launch_sinr_bwd_rows(L, k, k + 1, 8, 4, total_sc, C, G, s2, n_snr, gsinr, ns_max, status); break;
       case SC_LANE8_8: {
         const int N = sc_maxn(L, k, k + 1);
         st = N <= 16 ? sinr_bwd_t<8, 16>(L, R, total_sc, C, G, a, gsinr, ns_max, status)

@@ -82,7 +82,7 @@ __device__ __forceinline__ uint32_t rows_or(uint32_t v) {
   return v;
 }
 
-constexpr int kRowsChunk = 16;  // Ht columns staged per pass of the Gram
+constexpr int kRowsChunk = 8;  // Ht columns staged per pass of the Gram
 
 template <int MP, int NS>
 struct RowsLds {
@@ -208,6 +208,265 @@ struct RowsSweep<MP, MP> {
                                              float (&)[MP], float (&)[MP]) {}
 };
 
+// ---- stages shared by the forward kernel and its adjoint ----------------------------------
+
+// Chunk [j0, j0 + kRowsChunk) of row r of Ht = sum_q C[s,q] G_g[q] (zero past n and for the
+// padding rows r >= m).
+template <int MP>
+__device__ __forceinline__ void rows_ht_chunk(bool row, int j0, int n, int pg,
+                                              const float2* __restrict__ Cs,
+                                              const float2* __restrict__ Gr, int64_t gq,
+                                              float (&hr)[kRowsChunk], float (&hi)[kRowsChunk]) {
+#pragma unroll
+  for (int jj = 0; jj < kRowsChunk; ++jj) hr[jj] = hi[jj] = 0.f;
+  for (int q = 0; q < pg; ++q) {
+    const float2 cq = Cs[q];
+    const float2* Gq = Gr + q * gq;
+#pragma unroll
+    for (int jj = 0; jj < kRowsChunk; ++jj) {
+      const int j = min(j0 + jj, n - 1);
+      const float2 gv = Gq[j];
+      hr[jj] += cq.x * gv.x - cq.y * gv.y;
+      hi[jj] += cq.x * gv.y + cq.y * gv.x;
+    }
+  }
+#pragma unroll
+  for (int jj = 0; jj < kRowsChunk; ++jj) {
+    const bool on = row && (j0 + jj < n);
+    hr[jj] = on ? hr[jj] : 0.f;
+    hi[jj] = on ? hi[jj] : 0.f;
+  }
+}
+
+// Row r of K = Ht Ht^H.
+template <int MP, int NS>
+__device__ __forceinline__ void rows_gram(RowsLds<MP, NS>& S, int r, bool row, int n, int pg,
+                                          const float2* __restrict__ Cs,
+                                          const float2* __restrict__ Gr, int64_t gq,
+                                          float (&kr)[MP], float (&ki)[MP]) {
+#pragma unroll
+  for (int j = 0; j < MP; ++j) kr[j] = ki[j] = 0.f;
+  for (int j0 = 0; j0 < n; j0 += kRowsChunk) {
+    float hr[kRowsChunk], hi[kRowsChunk];
+    rows_ht_chunk<MP>(row, j0, n, pg, Cs, Gr, gq, hr, hi);
+#pragma unroll
+    for (int jj = 0; jj < kRowsChunk; ++jj) S.u.ht[r][jj] = make_float2(hr[jj], hi[jj]);
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < MP; ++k) {
+#pragma unroll
+      for (int jj = 0; jj < kRowsChunk; jj += 2) {
+        const float4 b = *reinterpret_cast<const float4*>(&S.u.ht[k][jj]);
+        // h_r conj(h_k)
+        kr[k] += hr[jj] * b.x + hi[jj] * b.y + (hr[jj + 1] * b.z + hi[jj + 1] * b.w);
+        ki[k] += hi[jj] * b.x - hr[jj] * b.y + (hi[jj + 1] * b.z - hr[jj + 1] * b.w);
+      }
+    }
+    wave_sync();
+  }
+}
+
+// Jacobi sweeps on K until the off-diagonal part is below 2 eps of the diagonal (per matrix;
+// converged matrices take identity rotations while the others of the wave finish), at most 10.
+// Leaves the eigenvalues on K's diagonal and the eigenvectors in the columns of V (row r in
+// this lane).  Returns false if the sweep cap was reached.
+template <int MP>
+__device__ __forceinline__ bool rows_eig(float4* rot, int r, float (&kr)[MP], float (&ki)[MP],
+                                         float (&vr)[MP], float (&vi)[MP]) {
+#pragma unroll
+  for (int j = 0; j < MP; ++j) {
+    vr[j] = (j == r) ? 1.f : 0.f;
+    vi[j] = 0.f;
+  }
+  const float eps = 5.9604645e-08f;
+  for (int sw = 0; sw <= 10; ++sw) {
+    float off = 0.f, dg = 0.f;
+#pragma unroll
+    for (int j = 0; j < MP; ++j) {
+      const float v = kr[j] * kr[j] + ki[j] * ki[j];
+      if (j == r)
+        dg += v;
+      else
+        off += v;
+    }
+    off = rows_sum<MP>(off);
+    dg = rows_sum<MP>(dg);
+    const bool gdone = off <= 4.f * eps * eps * dg;  // the same in every lane of the group
+    if (__all(gdone ? 1 : 0)) return true;
+    if (sw == 10) return gdone;
+    RowsSweep<MP, 1>::run(rot, r, !gdone, kr, ki, vr, vi);
+  }
+  return false;
+}
+
+// Descending eigenvalues over the first m indices; singular values sig[k] and, in this lane,
+// row r of U_ns (ur, ui) and of HV = U_ns Sigma_ns (hvr, hvi), zero past ns and for padding
+// rows.  Publishes the HV rows to LDS.
+template <int MP, int NS>
+__device__ __forceinline__ void rows_hv(RowsLds<MP, NS>& S, int r, bool row, int ns,
+                                        const float (&kr)[MP], const float (&vr)[MP],
+                                        const float (&vi)[MP], float (&sig)[NS],
+                                        float (&ur)[NS], float (&ui)[NS], float (&hvr)[NS],
+                                        float (&hvi)[NS], uint32_t& bits) {
+  float lam_me = 0.f;
+#pragma unroll
+  for (int j = 0; j < MP; ++j) lam_me = (j == r) ? kr[j] : lam_me;
+  S.lam[r] = row ? lam_me : -3.0e38f;
+  wave_sync();
+  float lam[MP];
+#pragma unroll
+  for (int j = 0; j < MP; ++j) lam[j] = S.lam[j];
+  int src[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) src[k] = 0;
+#pragma unroll
+  for (int j = 0; j < MP; ++j) {
+    int rk = 0;
+#pragma unroll
+    for (int i = 0; i < MP; ++i) rk += (lam[i] > lam[j] || (lam[i] == lam[j] && i < j)) ? 1 : 0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) src[k] = (rk == k) ? j : src[k];
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    float l = 0.f, a = 0.f, b = 0.f;
+#pragma unroll
+    for (int j = 0; j < MP; ++j) {
+      l = (src[k] == j) ? lam[j] : l;
+      a = (src[k] == j) ? vr[j] : a;
+      b = (src[k] == j) ? vi[j] : b;
+    }
+    sig[k] = __builtin_sqrtf(l > 0.f ? l : 0.f);
+    const bool on = row && k < ns;
+    ur[k] = on ? a : 0.f;
+    ui[k] = on ? b : 0.f;
+    hvr[k] = sig[k] * ur[k];
+    hvi[k] = sig[k] * ui[k];
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k)
+    if (k < ns && !(sig[k] > 1.0e-3f * sig[0])) bits |= GT_DEV_ZERO_STREAM;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) S.u.m.hv[r][k] = make_float2(hvr[k], hvi[k]);
+  wave_sync();
+}
+
+// Row r of the Cholesky factor of Q = HV HV^H + s2 I (padding rows: the identity), left-looking
+// with row c of L published to LDS at step c.  ok is false if this lane's pivot was not positive.
+template <int MP, int NS>
+__device__ __forceinline__ void rows_chol(RowsLds<MP, NS>& S, int r, bool row, float s2,
+                                          const float (&hvr)[NS], const float (&hvi)[NS],
+                                          float (&lr)[MP], float (&li)[MP], bool& ok) {
+#pragma unroll
+  for (int j = 0; j < MP; ++j) {
+    float ar = 0.f, ai = 0.f;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {  // hv_r conj(hv_j)
+      const float2 h = S.u.m.hv[j][k];
+      ar += hvr[k] * h.x + hvi[k] * h.y;
+      ai += hvi[k] * h.x - hvr[k] * h.y;
+    }
+    lr[j] = row ? ar + ((j == r) ? s2 : 0.f) : ((j == r) ? 1.f : 0.f);
+    li[j] = row ? ai : 0.f;
+  }
+  ok = true;
+#pragma unroll
+  for (int cc = 0; cc < MP; ++cc) {
+    if (r == cc) {
+      float d = lr[cc];
+#pragma unroll
+      for (int k = 0; k < cc; ++k) d -= lr[k] * lr[k] + li[k] * li[k];
+      ok = d > 0.f;
+      lr[cc] = __builtin_sqrtf(d > 0.f ? d : 1.f);
+      li[cc] = 0.f;
+#pragma unroll
+      for (int k = 0; k <= cc; ++k) S.u.m.l[cc][k] = make_float2(lr[k], li[k]);
+    }
+    wave_sync();
+    if (r > cc) {
+      float ar = lr[cc], ai = li[cc];
+#pragma unroll
+      for (int k = 0; k < cc; ++k) {  // L[r][k] conj(L[cc][k])
+        const float2 y = S.u.m.l[cc][k];
+        ar -= lr[k] * y.x + li[k] * y.y;
+        ai -= li[k] * y.x - lr[k] * y.y;
+      }
+      const float inv = 1.f / S.u.m.l[cc][cc].x;
+      lr[cc] = ar * inv;
+      li[cc] = ai * inv;
+    }
+  }
+}
+
+// In place: row r of X <- row r of Q^{-1} X (NS columns) with Q = L L^H: forward substitution
+// (row i final at step i, published), then back substitution (row i final at step i,
+// descending; the rows j < i subtract conj(L[i][j]) x_i with L[i][j] from the published rows).
+template <int MP, int NS>
+__device__ __forceinline__ void rows_solve(RowsLds<MP, NS>& S, int r, const float (&lr)[MP],
+                                           const float (&li)[MP], float (&xr)[NS],
+                                           float (&xi)[NS]) {
+#pragma unroll
+  for (int i = 0; i < MP; ++i) {
+    if (r == i) {
+      const float inv = 1.f / lr[i];
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        xr[k] *= inv;
+        xi[k] *= inv;
+        S.u.m.y[i][k] = make_float2(xr[k], xi[k]);
+      }
+    }
+    wave_sync();
+    if (r > i) {
+      const float ar = lr[i], ai = li[i];  // L[r][i]
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const float2 y = S.u.m.y[i][k];
+        xr[k] -= ar * y.x - ai * y.y;
+        xi[k] -= ar * y.y + ai * y.x;
+      }
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int i = MP - 1; i >= 0; --i) {
+    if (r == i) {
+      const float inv = 1.f / lr[i];
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        xr[k] *= inv;
+        xi[k] *= inv;
+        S.u.m.y[i][k] = make_float2(xr[k], xi[k]);
+      }
+    }
+    wave_sync();
+    if (r < i) {
+      const float2 l = S.u.m.l[i][r];
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const float2 w = S.u.m.y[i][k];
+        xr[k] -= l.x * w.x + l.y * w.y;
+        xi[k] -= l.x * w.y - l.y * w.x;
+      }
+    }
+  }
+  wave_sync();
+}
+
+// P[j][k] = sum over the group's rows i of conj(A[i][j]) B[i][k] (the same in every lane).
+template <int MP, int NS>
+__device__ __forceinline__ void rows_inner(const float (&ar)[NS], const float (&ai)[NS],
+                                           const float (&br)[NS], const float (&bi)[NS],
+                                           float (&pr)[NS][NS], float (&pi)[NS][NS]) {
+#pragma unroll
+  for (int j = 0; j < NS; ++j)
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      pr[j][k] = rows_sum<MP>(ar[j] * br[k] + ai[j] * bi[k]);
+      pi[j][k] = rows_sum<MP>(ar[j] * bi[k] - ai[j] * br[k]);
+    }
+}
+
 // Compressed-channel SINR for channels with m <= MP and ns <= NS, 256 / MP subcarriers per
 // block of 256 lanes.
 template <int MP, int NS>
@@ -232,252 +491,46 @@ __global__ void __launch_bounds__(256) k_sinr_rows(const DevChan* __restrict__ c
   const int g = (int)(s / ch.gs);
   const int pg = min(ch.p, min(ch.gs, ch.nsc - g * ch.gs));
   const bool row = r < m;
-  // row r of G_g[q] (rows past m read row m - 1 and are zeroed by a select)
+  // row r of G_g[q] (padding rows read row m - 1 and are zeroed)
   const int rr = min(r, max(ch.m - 1, 0));
   const float2* Cs = C + ch.c + s * ch.p;
   const float2* Gr = G + ch.g + ((int64_t)g * ch.p * ch.m + rr) * ch.n;
   const int64_t gq = (int64_t)ch.m * ch.n;
 
-  // ---- K = Ht Ht^H, row r -----------------------------------------------------------
-  float kr[MP], ki[MP];
-#pragma unroll
-  for (int j = 0; j < MP; ++j) kr[j] = ki[j] = 0.f;
-  for (int j0 = 0; j0 < n; j0 += kRowsChunk) {
-    float hr[kRowsChunk], hi[kRowsChunk];
-#pragma unroll
-    for (int jj = 0; jj < kRowsChunk; ++jj) hr[jj] = hi[jj] = 0.f;
-    for (int q = 0; q < pg; ++q) {
-      const float2 cq = Cs[q];
-      const float2* Gq = Gr + q * gq;
-#pragma unroll
-      for (int jj = 0; jj < kRowsChunk; ++jj) {
-        const int j = min(j0 + jj, n - 1);
-        const float2 gv = Gq[j];
-        hr[jj] += cq.x * gv.x - cq.y * gv.y;
-        hi[jj] += cq.x * gv.y + cq.y * gv.x;
-      }
-    }
-#pragma unroll
-    for (int jj = 0; jj < kRowsChunk; ++jj) {
-      const bool on = row && (j0 + jj < n);
-      S.u.ht[r][jj] = make_float2(on ? hr[jj] : 0.f, on ? hi[jj] : 0.f);
-    }
-    wave_sync();
-#pragma unroll
-    for (int k = 0; k < MP; ++k) {
-#pragma unroll
-      for (int jj = 0; jj < kRowsChunk; jj += 2) {
-        const float4 a = *reinterpret_cast<const float4*>(&S.u.ht[r][jj]);
-        const float4 b = *reinterpret_cast<const float4*>(&S.u.ht[k][jj]);
-        // h_r conj(h_k)
-        kr[k] += a.x * b.x + a.y * b.y + (a.z * b.z + a.w * b.w);
-        ki[k] += a.y * b.x - a.x * b.y + (a.w * b.z - a.z * b.w);
-      }
-    }
-    wave_sync();
-  }
+  float kr[MP], ki[MP], vr[MP], vi[MP];
+  rows_gram<MP, NS>(S, r, row, n, pg, Cs, Gr, gq, kr, ki);
+  uint32_t bits = rows_eig<MP>(S.rot, r, kr, ki, vr, vi) ? 0u : GT_DEV_EIG_SWEEPS;
+  float sig[NS], ur[NS], ui[NS], hvr[NS], hvi[NS];
+  rows_hv<MP, NS>(S, r, row, ns, kr, vr, vi, sig, ur, ui, hvr, hvi, bits);
 
-  // ---- Jacobi sweeps ------------------------------------------------------------------
-  float vr[MP], vi[MP];
-#pragma unroll
-  for (int j = 0; j < MP; ++j) {
-    vr[j] = (j == r) ? 1.f : 0.f;
-    vi[j] = 0.f;
-  }
-  const float eps = 5.9604645e-08f;
-  uint32_t bits = 0;
-  bool conv = false;
-  for (int sw = 0; sw <= 10; ++sw) {
-    float off = 0.f, dg = 0.f;
-#pragma unroll
-    for (int j = 0; j < MP; ++j) {
-      const float v = kr[j] * kr[j] + ki[j] * ki[j];
-      if (j == r)
-        dg += v;
-      else
-        off += v;
-    }
-    off = rows_sum<MP>(off);
-    dg = rows_sum<MP>(dg);
-    const bool gdone = off <= 4.f * eps * eps * dg;  // the same in every lane of the group
-    if (__all(gdone ? 1 : 0)) {
-      conv = true;
-      break;
-    }
-    if (sw == 10) {
-      conv = gdone;
-      break;
-    }
-    RowsSweep<MP, 1>::run(S.rot, r, !gdone, kr, ki, vr, vi);
-  }
-  if (!conv) bits |= GT_DEV_EIG_SWEEPS;
-
-  // ---- descending eigenvalues, HV = U_ns Sigma_ns ---------------------------------------
-  float lam_me = 0.f;
-#pragma unroll
-  for (int j = 0; j < MP; ++j) lam_me = (j == r) ? kr[j] : lam_me;
-  S.lam[r] = row ? lam_me : -3.0e38f;
-  wave_sync();
-  float lam[MP];
-#pragma unroll
-  for (int j = 0; j < MP; ++j) lam[j] = S.lam[j];
-  int src[NS];
-#pragma unroll
-  for (int k = 0; k < NS; ++k) src[k] = 0;
-#pragma unroll
-  for (int j = 0; j < MP; ++j) {
-    int rk = 0;
-#pragma unroll
-    for (int i = 0; i < MP; ++i) rk += (lam[i] > lam[j] || (lam[i] == lam[j] && i < j)) ? 1 : 0;
-#pragma unroll
-    for (int k = 0; k < NS; ++k) src[k] = (rk == k) ? j : src[k];
-  }
-  float sig[NS], hvr[NS], hvi[NS];
-#pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    float l = 0.f, ur = 0.f, ui = 0.f;
-#pragma unroll
-    for (int j = 0; j < MP; ++j) {
-      l = (src[k] == j) ? lam[j] : l;
-      ur = (src[k] == j) ? vr[j] : ur;
-      ui = (src[k] == j) ? vi[j] : ui;
-    }
-    sig[k] = __builtin_sqrtf(l > 0.f ? l : 0.f);
-    const bool on = row && k < ns;
-    hvr[k] = on ? sig[k] * ur : 0.f;
-    hvi[k] = on ? sig[k] * ui : 0.f;
-  }
-#pragma unroll
-  for (int k = 0; k < NS; ++k)
-    if (k < ns && !(sig[k] > 1.0e-3f * sig[0])) bits |= GT_DEV_ZERO_STREAM;
-#pragma unroll
-  for (int k = 0; k < NS; ++k) S.u.m.hv[r][k] = make_float2(hvr[k], hvi[k]);
-  wave_sync();
-  // P = HV HV^H, row r
-  float pr[MP], pi[MP];
-#pragma unroll
-  for (int j = 0; j < MP; ++j) {
-    float ar = 0.f, ai = 0.f;
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      const float2 h = S.u.m.hv[j][k];
-      ar += hvr[k] * h.x + hvi[k] * h.y;
-      ai += hvi[k] * h.x - hvr[k] * h.y;
-    }
-    pr[j] = ar;
-    pi[j] = ai;
-  }
-
-  // ---- per noise level: Cholesky, W, SINR -------------------------------------------------
   for (int kk = 0; kk < snr.n; ++kk) {
     const float s2 = snr.s2[kk];
-    // L row r starts as Q row r; padding rows r >= m are the identity
     float lr[MP], li[MP];
-#pragma unroll
-    for (int j = 0; j < MP; ++j) {
-      lr[j] = row ? pr[j] + ((j == r) ? s2 : 0.f) : ((j == r) ? 1.f : 0.f);
-      li[j] = row ? pi[j] : 0.f;
-    }
-    bool ok = true;
-#pragma unroll
-    for (int cc = 0; cc < MP; ++cc) {
-      if (r == cc) {
-        float d = lr[cc];
-#pragma unroll
-        for (int k = 0; k < cc; ++k) d -= lr[k] * lr[k] + li[k] * li[k];
-        ok = d > 0.f;
-        lr[cc] = __builtin_sqrtf(d > 0.f ? d : 1.f);
-        li[cc] = 0.f;
-#pragma unroll
-        for (int k = 0; k <= cc; ++k) S.u.m.l[cc][k] = make_float2(lr[k], li[k]);
-      }
-      wave_sync();
-      if (r > cc) {
-        float ar = lr[cc], ai = li[cc];
-#pragma unroll
-        for (int k = 0; k < cc; ++k) {  // L[r][k] conj(L[cc][k])
-          const float2 y = S.u.m.l[cc][k];
-          ar -= lr[k] * y.x + li[k] * y.y;
-          ai -= li[k] * y.x - lr[k] * y.y;
-        }
-        const float inv = 1.f / S.u.m.l[cc][cc].x;
-        lr[cc] = ar * inv;
-        li[cc] = ai * inv;
-      }
-    }
-    // forward substitution L Y = HV: row i of Y is final at step i and published
-    float yr[NS], yi[NS];
+    bool ok;
+    rows_chol<MP, NS>(S, r, row, s2, hvr, hvi, lr, li, ok);
+    float wr[NS], wi[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      yr[k] = hvr[k];
-      yi[k] = hvi[k];
+      wr[k] = hvr[k];
+      wi[k] = hvi[k];
     }
-#pragma unroll
-    for (int i = 0; i < MP; ++i) {
-      if (r == i) {
-        const float inv = 1.f / lr[i];
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-          yr[k] *= inv;
-          yi[k] *= inv;
-          S.u.m.y[i][k] = make_float2(yr[k], yi[k]);
-        }
-      }
-      wave_sync();
-      if (r > i) {
-        const float ar = lr[i], ai = li[i];  // L[r][i]
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-          const float2 y = S.u.m.y[i][k];
-          yr[k] -= ar * y.x - ai * y.y;
-          yi[k] -= ar * y.y + ai * y.x;
-        }
-      }
-    }
-    wave_sync();
-    // back substitution L^H W = Y: row i of W is final at step i (descending); the other rows
-    // j < i subtract conj(L[i][j]) w_i, with L[i][j] from the published rows of L
-#pragma unroll
-    for (int i = MP - 1; i >= 0; --i) {
-      if (r == i) {
-        const float inv = 1.f / lr[i];
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-          yr[k] *= inv;
-          yi[k] *= inv;
-          S.u.m.y[i][k] = make_float2(yr[k], yi[k]);
-        }
-      }
-      wave_sync();
-      if (r < i) {
-        const float2 l = S.u.m.l[i][r];  // conj(L[i][r]) w_i
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-          const float2 w = S.u.m.y[i][k];
-          yr[k] -= l.x * w.x + l.y * w.y;
-          yi[k] -= l.x * w.y - l.y * w.x;
-        }
-      }
-    }
-    // yr/yi now hold row r of W; c_jk = sum_i conj(W[i][j]) HV[i][k] and ||w_j||^2
+    rows_solve<MP, NS>(S, r, lr, li, wr, wi);
+    // c_jk = w_j^H hv_k, ||w_j||^2, SINR_j
     float sinr_me = 0.f;
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
       float sig_p = 0.f, den = 0.f;
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
-        float cr = yr[j] * hvr[k] + yi[j] * hvi[k];
-        float ci = yr[j] * hvi[k] - yi[j] * hvr[k];
-        cr = rows_sum<MP>(cr);
-        ci = rows_sum<MP>(ci);
+        const float cr = rows_sum<MP>(wr[j] * hvr[k] + wi[j] * hvi[k]);
+        const float ci = rows_sum<MP>(wr[j] * hvi[k] - wi[j] * hvr[k]);
         const float pw = cr * cr + ci * ci;
         if (k == j)
           sig_p = pw;
         else
           den += pw;
       }
-      const float nw = rows_sum<MP>(yr[j] * yr[j] + yi[j] * yi[j]);
-      den += s2 * nw;
+      den += s2 * rows_sum<MP>(wr[j] * wr[j] + wi[j] * wi[j]);
       float v = sig_p / den;
       if (!(sig[j] > 1.0e-3f * sig[0])) v = 0.f;
       sinr_me = (j == r) ? v : sinr_me;
@@ -492,6 +545,236 @@ __global__ void __launch_bounds__(256) k_sinr_rows(const DevChan* __restrict__ c
     if (valid) {
       float* o = out + ((int64_t)kk * total_sc + gsc) * ns_max;
       for (int q = r; q < ns_max; q += MP) o[q] = (q == r) ? v : 0.f;
+    }
+  }
+  bits = rows_or<MP>(bits);
+  if (valid && status && bits && r == 0) atomicOr(reinterpret_cast<unsigned int*>(status + c), bits);
+}
+
+// Adjoint of k_sinr_rows: recomputes Ht, its eigendecomposition and, per noise level, L and W;
+// back-propagates dl/dSINR through SINR_j = s_j / d_j, s_j = |c_jj|^2,
+// d_j = s2 ||w_j||^2 + sum_{k != j} |c_jk|^2 with c_jk = w_j^H hv_k, W = Q^{-1} HV and
+// Q = HV HV^H + s2 I to dl/dHV:
+//   C-bar_jk = 2 (k == j ? g_j / d_j : -g_j s_j / d_j^2) c_jk,   N-bar_j = -s2 g_j s_j / d_j^2,
+//   W-bar = HV C-bar^H + 2 W diag(N-bar),   Lambda = Q^{-1} W-bar,
+//   dl/dHV += W C-bar + Lambda - Lambda (W^H HV) - W (Lambda^H HV);
+// then through HV = U_ns Sigma_ns with the kept-block singular-vector adjoint
+//   P = U_ns^H dl/dHV,  D_aa = Re P_aa,
+//   D_ab = (sigma_b^2 P_ab - sigma_a sigma_b conj(P_ba)) / (sigma_b^2 - sigma_a^2)  (a != b,
+//          zero for numerically equal sigma),
+//   dl/dHt = U_ns D V_ns^H = E Ht,  E = U_ns D Sigma^{-1} U_ns^H,
+// row i of dl/dHt from row i of E and the recomputed rows of Ht.  Streams forced to zero by
+// the zero-stream rule carry no gradient.  dl/dHt goes to the workspace; the per-group
+// reduction forms dl/dC and dl/dG.
+template <int MP, int NS>
+__global__ void __launch_bounds__(256) k_sinr_bwd_rows(const DevChan* __restrict__ chans,
+                                                        RowsRange R, int64_t total_sc,
+                                                        const float2* __restrict__ C,
+                                                        const float2* __restrict__ G, RowsSnr snr,
+                                                        const float* __restrict__ gsinr,
+                                                        int ns_max, char* ws, int32_t* status) {
+  constexpr int SPB = 256 / MP;
+  __shared__ RowsLds<MP, NS> lds[SPB];
+  const int sub = threadIdx.x / MP, r = threadIdx.x % MP;
+  RowsLds<MP, NS>& S = lds[sub];
+  const int64_t it = (int64_t)blockIdx.x * SPB + sub;
+  const bool valid = it < R.count;
+  int64_t gsc = 0;
+  const int c = valid ? rows_locate(R, chans, it, gsc) : R.ch[0];
+  const DevChan& ch = chans[c];
+  const int64_t s = valid ? gsc - ch.sc : 0;
+  const int m = valid ? ch.m : 0;
+  const int n = valid ? ch.n : 0;
+  const int ns = valid ? ch.ns : 0;
+  const int g = (int)(s / ch.gs);
+  const int pg = min(ch.p, min(ch.gs, ch.nsc - g * ch.gs));
+  const bool row = r < m;
+  const int rr = min(r, max(ch.m - 1, 0));
+  const float2* Cs = C + ch.c + s * ch.p;
+  const float2* Gr = G + ch.g + ((int64_t)g * ch.p * ch.m + rr) * ch.n;
+  const int64_t gq = (int64_t)ch.m * ch.n;
+
+  float kr[MP], ki[MP], vr[MP], vi[MP];
+  rows_gram<MP, NS>(S, r, row, n, pg, Cs, Gr, gq, kr, ki);
+  uint32_t bits = rows_eig<MP>(S.rot, r, kr, ki, vr, vi) ? 0u : GT_DEV_EIG_SWEEPS;
+  float sig[NS], ur[NS], ui[NS], hvr[NS], hvi[NS];
+  rows_hv<MP, NS>(S, r, row, ns, kr, vr, vi, sig, ur, ui, hvr, hvi, bits);
+  bool live[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) live[k] = k < ns && sig[k] > 1.0e-3f * sig[0];
+
+  float br[NS], bi[NS];  // row r of dl/dHV
+#pragma unroll
+  for (int k = 0; k < NS; ++k) br[k] = bi[k] = 0.f;
+  for (int kk = 0; kk < snr.n; ++kk) {
+    const float s2 = snr.s2[kk];
+    float lr[MP], li[MP];
+    bool ok;
+    rows_chol<MP, NS>(S, r, row, s2, hvr, hvi, lr, li, ok);
+    const bool any_bad = rows_or<MP>(ok ? 0u : 1u) != 0u;
+    if (any_bad) bits |= GT_DEV_CHOLESKY;
+    float wr[NS], wi[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      wr[k] = hvr[k];
+      wi[k] = hvi[k];
+    }
+    rows_solve<MP, NS>(S, r, lr, li, wr, wi);
+    float cr[NS][NS], ci[NS][NS];  // c_jk = w_j^H hv_k
+    rows_inner<MP, NS>(wr, wi, hvr, hvi, cr, ci);
+    // C-bar (in place of c) and N-bar
+    float nb[NS];
+    const float* gk = gsinr + ((int64_t)kk * total_sc + gsc) * ns_max;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const float nw = rows_sum<MP>(wr[j] * wr[j] + wi[j] * wi[j]);
+      float sv = 0.f, dv = s2 * nw;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const float pw = cr[j][k] * cr[j][k] + ci[j][k] * ci[j][k];
+        if (k == j)
+          sv = pw;
+        else
+          dv += pw;
+      }
+      // streams past ns (zero columns of W and HV, d_j = 0), zero streams and broken-down
+      // noise levels carry no gradient
+      const bool on = valid && live[j] && !any_bad;
+      const float gj = on ? gk[j] : 0.f;
+      const float sbar = on ? gj / dv : 0.f;
+      const float dbar = on ? -gj * sv / (dv * dv) : 0.f;
+      nb[j] = s2 * dbar;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const float f = (k == j) ? 2.f * sbar : 2.f * dbar;
+        cr[j][k] *= f;
+        ci[j][k] *= f;
+      }
+    }
+    // c (needed below) is recomputed from W and HV after W-bar: keep C-bar in cr/ci
+    // W-bar row r: sum_k hv[r][k] conj(Cbar[j][k]) + 2 nb_j w[r][j]
+    float lmr[NS], lmi[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      float ar = 2.f * nb[j] * wr[j], ai = 2.f * nb[j] * wi[j];
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        ar += hvr[k] * cr[j][k] + hvi[k] * ci[j][k];
+        ai += hvi[k] * cr[j][k] - hvr[k] * ci[j][k];
+      }
+      lmr[j] = ar;
+      lmi[j] = ai;
+    }
+    // dl/dHV += W C-bar
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {
+        br[k] += wr[j] * cr[j][k] - wi[j] * ci[j][k];
+        bi[k] += wr[j] * ci[j][k] + wi[j] * cr[j][k];
+      }
+    }
+    rows_solve<MP, NS>(S, r, lr, li, lmr, lmi);  // Lambda = Q^{-1} W-bar
+    // c again (C-bar overwrote it), then X = Lambda^H HV
+    rows_inner<MP, NS>(wr, wi, hvr, hvi, cr, ci);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      float ar = lmr[k], ai = lmi[k];
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {  // - Lambda[r][j] c_jk
+        ar -= lmr[j] * cr[j][k] - lmi[j] * ci[j][k];
+        ai -= lmr[j] * ci[j][k] + lmi[j] * cr[j][k];
+      }
+      br[k] += ar;
+      bi[k] += ai;
+    }
+    rows_inner<MP, NS>(lmr, lmi, hvr, hvi, cr, ci);  // X_jk = lambda_j^H hv_k
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {  // - W[r][j] X_jk
+        br[k] -= wr[j] * cr[j][k] - wi[j] * ci[j][k];
+        bi[k] -= wr[j] * ci[j][k] + wi[j] * cr[j][k];
+      }
+    }
+  }
+  // singular-vector stage: P = U_ns^H dl/dHV, D, E row r
+  float pr[NS][NS], pi[NS][NS];
+  rows_inner<MP, NS>(ur, ui, br, bi, pr, pi);
+  const float lam1 = sig[0] * sig[0];
+  float dr[NS][NS], di[NS][NS];
+#pragma unroll
+  for (int a = 0; a < NS; ++a)
+#pragma unroll
+    for (int b = 0; b < NS; ++b) {
+      const float sa = sig[a], sb = sig[b];
+      const float gap = sb * sb - sa * sa;
+      float xr = 0.f, xi = 0.f;
+      if (a == b) {
+        xr = pr[a][a];
+      } else if (__builtin_fabsf(gap) > 1e-5f * lam1) {
+        xr = (sb * sb * pr[a][b] - sa * sb * pr[b][a]) / gap;
+        xi = (sb * sb * pi[a][b] + sa * sb * pi[b][a]) / gap;
+      }
+      const float inv = (live[b] && sb > 0.f) ? 1.f / sb : 0.f;  // D Sigma^{-1}
+      dr[a][b] = (a < ns && b < ns) ? xr * inv : 0.f;
+      di[a][b] = (a < ns && b < ns) ? xi * inv : 0.f;
+    }
+  // row r of F = U_ns D Sigma^{-1}; E[r][j] = sum_b F[r][b] conj(U[j][b]) with the U rows in LDS
+  float fr[NS], fi[NS];
+#pragma unroll
+  for (int b = 0; b < NS; ++b) {
+    float ar = 0.f, ai = 0.f;
+#pragma unroll
+    for (int a = 0; a < NS; ++a) {
+      ar += ur[a] * dr[a][b] - ui[a] * di[a][b];
+      ai += ur[a] * di[a][b] + ui[a] * dr[a][b];
+    }
+    fr[b] = ar;
+    fi[b] = ai;
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k) S.u.m.hv[r][k] = make_float2(ur[k], ui[k]);
+  wave_sync();
+  float er[MP], ei[MP];
+#pragma unroll
+  for (int j = 0; j < MP; ++j) {
+    float ar = 0.f, ai = 0.f;
+#pragma unroll
+    for (int b = 0; b < NS; ++b) {  // F[r][b] conj(U[j][b])
+      const float2 u = S.u.m.hv[j][b];
+      ar += fr[b] * u.x + fi[b] * u.y;
+      ai += fi[b] * u.x - fr[b] * u.y;
+    }
+    er[j] = ar;
+    ei[j] = ai;
+  }
+  wave_sync();
+  // dl/dHt row r = sum_j E[r][j] Ht[j][:], chunk by chunk of recomputed Ht rows
+  float2* gH = reinterpret_cast<float2*>(ws + ch.w_gH) + (s * ch.m + rr) * ch.n;
+  for (int j0 = 0; j0 < n; j0 += kRowsChunk) {
+    float hr[kRowsChunk], hi[kRowsChunk];
+    rows_ht_chunk<MP>(row, j0, n, pg, Cs, Gr, gq, hr, hi);
+#pragma unroll
+    for (int jj = 0; jj < kRowsChunk; ++jj) S.u.ht[r][jj] = make_float2(hr[jj], hi[jj]);
+    wave_sync();
+#pragma unroll
+    for (int jj = 0; jj < kRowsChunk; ++jj) hr[jj] = hi[jj] = 0.f;
+#pragma unroll
+    for (int j = 0; j < MP; ++j) {
+#pragma unroll
+      for (int jj = 0; jj < kRowsChunk; jj += 2) {
+        const float4 h = *reinterpret_cast<const float4*>(&S.u.ht[j][jj]);
+        hr[jj] += er[j] * h.x - ei[j] * h.y;
+        hi[jj] += er[j] * h.y + ei[j] * h.x;
+        hr[jj + 1] += er[j] * h.z - ei[j] * h.w;
+        hi[jj + 1] += er[j] * h.w + ei[j] * h.z;
+      }
+    }
+    if (valid && row) {
+#pragma unroll
+      for (int jj = 0; jj < kRowsChunk; ++jj)
+        if (j0 + jj < n) gH[j0 + jj] = make_float2(hr[jj], hi[jj]);
     }
     wave_sync();
   }
@@ -519,7 +802,8 @@ static gt_status rows_launch_t(const LaunchCtx& L, const RowsRange& R, int64_t t
   return GT_OK;
 }
 
-// The compressed SINR of the classes [k0, k1) on the row-parallel kernel (m <= mp, ns <= nsm).
+// The compressed SINR of the classes [k0, k1) on the row-parallel kernel (m <= mp <= 8,
+// ns <= nsm).
 gt_status launch_sinr_rows(const LaunchCtx& L, int k0, int k1, int mp, int nsm, int64_t total_sc,
                            const float2* C, const float2* G, const float* s2, int n_snr,
                            float* out, int ns_max, int32_t* status) {
@@ -538,11 +822,51 @@ gt_status launch_sinr_rows(const LaunchCtx& L, int k0, int k1, int mp, int nsm, 
     if (nsm <= 2) return rows_launch_t<4, 2>(L, R, total_sc, C, G, a, out, ns_max, status);
     return rows_launch_t<4, 4>(L, R, total_sc, C, G, a, out, ns_max, status);
   }
-  if (mp <= 8) {
-    if (nsm <= 4) return rows_launch_t<8, 4>(L, R, total_sc, C, G, a, out, ns_max, status);
-    return rows_launch_t<8, 8>(L, R, total_sc, C, G, a, out, ns_max, status);
+  if (nsm <= 4) return rows_launch_t<8, 4>(L, R, total_sc, C, G, a, out, ns_max, status);
+  return rows_launch_t<8, 8>(L, R, total_sc, C, G, a, out, ns_max, status);
+}
+
+
+template <int MP, int NS>
+static gt_status rows_bwd_launch_t(const LaunchCtx& L, const RowsRange& R, int64_t total_sc,
+                                   const float2* C, const float2* G, const RowsSnr& a,
+                                   const float* gs, int ns_max, int32_t* status) {
+  constexpr int SPB = 256 / MP;
+  const unsigned grid = (unsigned)((R.count + SPB - 1) / SPB);
+  prof_begin("k_sinr_bwd_rows", L.stream);
+  hipLaunchKernelGGL((k_sinr_bwd_rows<MP, NS>), dim3(grid), dim3(256), 0, L.stream, L.d_chans, R,
+                     total_sc, C, G, a, gs, ns_max, L.ws, status);
+  prof_end(L.stream);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error_detail("k_sinr_bwd_rows", e);
+    return GT_ERR_HIP;
   }
-  return rows_launch_t<16, 8>(L, R, total_sc, C, G, a, out, ns_max, status);
+  return GT_OK;
+}
+
+// dl/dHt of the classes [k0, k1) on the row-parallel adjoint (m <= mp, ns <= nsm) into the
+// workspace.
+gt_status launch_sinr_bwd_rows(const LaunchCtx& L, int k0, int k1, int mp, int nsm,
+                               int64_t total_sc, const float2* C, const float2* G, const float* s2,
+                               int n_snr, const float* gsinr, int ns_max, int32_t* status) {
+  RowsRange R;
+  const int j0 = L.sc_j[k0], j1 = L.sc_j[k1];
+  R.ch = L.d_sc_ch + j0;
+  R.off = L.d_sc_off + j0;
+  R.n = j1 - j0;
+  R.base = L.sc_base[k0];
+  R.count = L.sc_base[k1] - L.sc_base[k0];
+  if (R.count == 0) return GT_OK;
+  RowsSnr a{};
+  a.n = n_snr;
+  for (int k = 0; k < n_snr; ++k) a.s2[k] = s2[k];
+  if (mp <= 4) {
+    if (nsm <= 2) return rows_bwd_launch_t<4, 2>(L, R, total_sc, C, G, a, gsinr, ns_max, status);
+    return rows_bwd_launch_t<4, 4>(L, R, total_sc, C, G, a, gsinr, ns_max, status);
+  }
+  if (nsm <= 4) return rows_bwd_launch_t<8, 4>(L, R, total_sc, C, G, a, gsinr, ns_max, status);
+  return rows_bwd_launch_t<8, 8>(L, R, total_sc, C, G, a, gsinr, ns_max, status);
 }
 
 }  // namespace gt
