@@ -177,6 +177,23 @@ gt_status gt_sinr_eval_backward(const gt_plan* plan, const void* C, const void* 
                                 void* grad_C, void* grad_G, int32_t* dev_status, void* ws,
                                 size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): gt_sinr_eval_backward without a workspace.  Its
+ * scratch -- the plan's device tables and the per-subcarrier dl/dHt -- lives in a static
+ * device array of 64 MiB that every GPU the library runs on holds from the first call on it
+ * until the process ends; the call itself allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine).  The tables are copied into the array from memory the plan owns
+ * (asynchronously on `stream`) at every call; dl/dHt needs no clearing.  A plan whose tables
+ * and dl/dHt need more than 64 MiB (for example 20 or more 8 x 64 x 3276 channels at ranks
+ * (8, 16, 12)) is refused with GT_ERR_WORKSPACE before anything is launched.  All calls on one
+ * GPU share that GPU's array and it keeps the last call's contents: calls that overlap on one
+ * GPU (on different streams or from different threads) race.  Arguments, outputs and errors
+ * are otherwise those of gt_sinr_eval_backward. */
+gt_status gt_sinr_eval_backward_static(const gt_plan* plan, const void* C, const void* G,
+                                       const float* sigma2, int32_t n_snr, const void* grad_sinr,
+                                       void* grad_C, void* grad_G, int32_t* dev_status,
+                                       void* stream);
+
 /* Adjoint of gt_tucker_reconstruct.  grad_Ht or grad_Xhat may be NULL (treated as zero).
  * Writes grad_A, grad_B, grad_C, grad_G (overwritten). */
 gt_status gt_tucker_reconstruct_backward(const gt_plan* plan, const void* A, const void* B,

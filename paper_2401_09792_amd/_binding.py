@@ -64,6 +64,9 @@ SIGNATURES = {
                                         C.POINTER(C.c_float), C.c_int32, C.c_void_p,
                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.c_size_t, C.c_void_p]),
+    "gt_sinr_eval_backward_static": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
+                                               C.POINTER(C.c_float), C.c_int32, C.c_void_p,
+                                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "gt_tucker_reconstruct_backward": (C.c_int, [C.c_void_p] * 11 + [C.c_void_p, C.c_size_t,
                                                                       C.c_void_p]),
     "gt_tucker_fit_backward": (C.c_int, [C.c_void_p]),

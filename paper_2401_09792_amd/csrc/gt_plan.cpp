@@ -121,6 +121,10 @@ struct gt_plan {
   hipEvent_t ev_fork = nullptr, ev_join[3] = {nullptr, nullptr, nullptr};
   // pass variants chosen by gt_plan_autotune
   int tune_bstep = 0, tune_tpass = 0, tune_split = 1;
+  // compact layout of the SINR adjoint's scratch alone (tables and dl/dHt), for the entry point
+  // that runs in the library's static scratch array; sblob holds its table bytes
+  WsLayout slay{};
+  std::vector<char> sblob;
   ~gt_plan();
 };
 
@@ -346,6 +350,37 @@ static gt_status plan_build(const gt_channel_desc* descs, int32_t n_channels,
     ch.w_gBp = take(c8 * ch.ngroups * ch.nt * ch.n);
   }
   p->lay.total = off;
+  {  // the SINR adjoint's scratch alone: tables, then dl/dHt per channel
+    int64_t so = 0;
+    p->slay.chans = so;
+    so = align256(so + (int64_t)sizeof(DevChan) * n_channels);
+    p->slay.groups = so;
+    so = align256(so + (int64_t)sizeof(GroupItem) * gfirst);
+    p->slay.sc_ch = so;
+    so = align256(so + (int64_t)sizeof(int32_t) * n_channels);
+    p->slay.sc_off = so;
+    so = align256(so + (int64_t)sizeof(int64_t) * (n_channels + 1));
+    const int64_t tables = so;
+    std::vector<DevChan> sc(p->chans);
+    const int64_t ce = o.dtype == GT_C128 ? 16 : 8;
+    for (int c = 0; c < n_channels; ++c) {
+      DevChan& ch = sc[c];
+      ch.w_W = ch.w_T = ch.w_Yh = ch.w_S1p = ch.w_S1 = ch.w_S2p = ch.w_S2 = ch.w_S3 = 0;
+      ch.w_VA = ch.w_VB = ch.w_VS = ch.w_SP = ch.w_Xq = ch.w_VC = ch.w_lamg = ch.w_scal = 0;
+      ch.w_gAp = ch.w_gBp = 0;
+      ch.w_gH = so;
+      so = align256(so + std::max<int64_t>(ce * ch.nsc * ch.m * ch.n, 8));
+    }
+    p->slay.groups_by_size = p->slay.groups;
+    p->slay.tiles = 0;
+    p->slay.total = so;
+    p->sblob.assign((size_t)tables, 0);
+    std::memcpy(p->sblob.data() + p->slay.chans, sc.data(), sizeof(DevChan) * n_channels);
+    std::memcpy(p->sblob.data() + p->slay.groups, p->groups.data(), sizeof(GroupItem) * gfirst);
+    std::memcpy(p->sblob.data() + p->slay.sc_ch, p->sc_ch.data(), sizeof(int32_t) * n_channels);
+    std::memcpy(p->sblob.data() + p->slay.sc_off, p->sc_off.data(),
+                sizeof(int64_t) * (n_channels + 1));
+  }
   p->blob.assign((size_t)p->lay.sc_off + sizeof(int64_t) * (n_channels + 1), 0);
   std::memcpy(p->blob.data() + p->lay.chans, p->chans.data(), sizeof(DevChan) * n_channels);
   std::memcpy(p->blob.data() + p->lay.groups, p->groups.data(), sizeof(GroupItem) * gfirst);
@@ -449,17 +484,18 @@ static gt_status check_ws(const gt_plan* plan, void* ws, size_t ws_bytes) {
   return GT_OK;
 }
 
-static LaunchCtx make_ctx(const gt_plan* p, void* ws, void* stream) {
+// Launch context over the tables of layout `lay` at device address `ws`.
+static LaunchCtx make_ctx_at(const gt_plan* p, const WsLayout& lay, void* ws, void* stream) {
   LaunchCtx L;
   L.stream = reinterpret_cast<hipStream_t>(stream);
   L.ws = reinterpret_cast<char*>(ws);
-  L.d_chans = reinterpret_cast<const DevChan*>(L.ws + p->lay.chans);
-  L.d_groups = reinterpret_cast<const GroupItem*>(L.ws + p->lay.groups);
-  L.d_groups_by_size = reinterpret_cast<const GroupItem*>(L.ws + p->lay.groups_by_size);
-  L.d_tiles = reinterpret_cast<const int32_t*>(L.ws + p->lay.tiles);
+  L.d_chans = reinterpret_cast<const DevChan*>(L.ws + lay.chans);
+  L.d_groups = reinterpret_cast<const GroupItem*>(L.ws + lay.groups);
+  L.d_groups_by_size = reinterpret_cast<const GroupItem*>(L.ws + lay.groups_by_size);
+  L.d_tiles = reinterpret_cast<const int32_t*>(L.ws + lay.tiles);
   if (!p->sc_ch.empty()) {  // split views run no SINR and carry no class tables
-    L.d_sc_ch = reinterpret_cast<const int32_t*>(L.ws + p->lay.sc_ch);
-    L.d_sc_off = reinterpret_cast<const int64_t*>(L.ws + p->lay.sc_off);
+    L.d_sc_ch = reinterpret_cast<const int32_t*>(L.ws + lay.sc_ch);
+    L.d_sc_off = reinterpret_cast<const int64_t*>(L.ws + lay.sc_off);
   }
   for (int k = 0; k <= SC_COUNT; ++k) {
     L.sc_j[k] = p->sc_j[k];
@@ -487,6 +523,10 @@ static LaunchCtx make_ctx(const gt_plan* p, void* ws, void* stream) {
   L.tune_bstep = p->tune_bstep;
   L.tune_tpass = p->tune_tpass;
   return L;
+}
+
+static LaunchCtx make_ctx(const gt_plan* p, void* ws, void* stream) {
+  return make_ctx_at(p, p->lay, ws, stream);
 }
 
 gt_status gt_workspace_init(const gt_plan* plan, void* ws, size_t ws_bytes, void* stream) {
@@ -708,6 +748,70 @@ gt_status gt_sinr_eval_backward(const gt_plan* plan, const void* C, const void* 
   if ((st = check_snr(sigma2, n_snr)) != GT_OK) return st;
   if (!C || !G || !grad_sinr || !grad_C || !grad_G) return GT_ERR_ARG;
   LaunchCtx L = make_ctx(plan, ws, stream);
+  if (plan->opt.dtype == GT_C128)
+    return launch_sinr_bwd_c128(L, plan->totals.sc, (const double2*)C, (const double2*)G, sigma2,
+                                n_snr, (const double*)grad_sinr, (double2*)grad_C, (double2*)grad_G,
+                                plan->ns_max, dev_status);
+  return launch_sinr_bwd(L, plan->totals.sc, (const float2*)C, (const float2*)G, sigma2, n_snr,
+                         (const float*)grad_sinr, (float2*)grad_C, (float2*)grad_G, plan->ns_max,
+                         dev_status);
+}
+
+// ---------------------------------------------------------------------------------------
+// The SINR adjoint in the library's static scratch, for callers that cannot allocate.  Each GPU
+// the library runs on holds its own copy of `scratch` (from the first call on that GPU until
+// the process ends); its device address is taken once per device with hipGetSymbolAddress and
+// only that address is passed to copies and kernels.
+
+static constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+static constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of the current device's scratch, looked up on the first call on that device.
+static gt_status static_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    set_error_detail("hipGetDevice", e);
+    return GT_ERR_HIP;
+  }
+  if (dev < 0 || dev >= kMaxScratchDevices) return GT_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      set_error_detail("hipGetSymbolAddress(scratch)", e != hipSuccess ? e : hipErrorInvalidSymbol);
+      return GT_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return GT_OK;
+}
+
+gt_status gt_sinr_eval_backward_static(const gt_plan* plan, const void* C, const void* G,
+                                       const float* sigma2, int32_t n_snr, const void* grad_sinr,
+                                       void* grad_C, void* grad_G, int32_t* dev_status,
+                                       void* stream) {
+  if (!plan) return GT_ERR_ARG;
+  gt_status st = check_snr(sigma2, n_snr);
+  if (st != GT_OK) return st;
+  if (!C || !G || !grad_sinr || !grad_C || !grad_G) return GT_ERR_ARG;
+  if ((size_t)plan->slay.total > kStaticScratchBytes) return GT_ERR_WORKSPACE;
+  void* ptr = nullptr;
+  if ((st = static_scratch(&ptr)) != GT_OK) return st;
+  // the plan's tables (with dl/dHt offsets in this layout) into the scratch, ordered on the
+  // stream before the kernels; dl/dHt needs no clearing (every entry read is written first)
+  hipError_t e = hipMemcpyAsync(ptr, plan->sblob.data(), plan->sblob.size(), hipMemcpyHostToDevice,
+                                reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) {
+    set_error_detail("gt_sinr_eval_backward_static", e);
+    return GT_ERR_HIP;
+  }
+  LaunchCtx L = make_ctx_at(plan, plan->slay, ptr, stream);
   if (plan->opt.dtype == GT_C128)
     return launch_sinr_bwd_c128(L, plan->totals.sc, (const double2*)C, (const double2*)G, sigma2,
                                 n_snr, (const double*)grad_sinr, (double2*)grad_C, (double2*)grad_G,
