@@ -440,6 +440,9 @@ def main():
                     help="channels timed on the oracle with all BLAS threads")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the precision, graph-replay, refinement and batch forms")
+    ap.add_argument("--steps-only", action="store_true",
+                    help="only the warm-up, timed and profiled steps of the workload (for profiler "
+                         "runs: every launch of a kernel then has the same size)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run three plain copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -509,9 +512,11 @@ def main():
     kern = profile_steps(api, step, args.steps)
     # the T pass and the eigensolves also run once unsplit (one stream), so that their
     # durations are their own and not shared with concurrent parts
-    plan.set_tuning(bstep=0, tpass=0, split=0)
-    kern_unsplit = profile_steps(api, lambda: plan.fit(X, factors=f, trace=False), 1)
-    plan.set_tuning(bstep=0, tpass=0, split=1)
+    kern_unsplit = {}
+    if not args.steps_only:
+        plan.set_tuning(bstep=0, tpass=0, split=0)
+        kern_unsplit = profile_steps(api, lambda: plan.fit(X, factors=f, trace=False), 1)
+        plan.set_tuning(bstep=0, tpass=0, split=1)
     torch.cuda.synchronize()
 
     fits_per_s = B * args.steps / (ms_total / 1e3)
@@ -597,8 +602,9 @@ def main():
     fit_parts["whole_step_sweep_mfma_frac"] = fit_flops / (ms_step * 1e-3) / 1e12 / PEAK_FP32_TFLOPS
 
     # single-channel latency and a 256-channel batch of the same step
-    latency = single_channel_latency(api, synthgen, cfg, s2, dev, torch) if not wide else None
-    big = batch_throughput(api, synthgen, cfg, s2, dev, torch, 256) if not wide else None
+    extras = not wide and not args.steps_only
+    latency = single_channel_latency(api, synthgen, cfg, s2, dev, torch) if extras else None
+    big = batch_throughput(api, synthgen, cfg, s2, dev, torch, 256) if extras else None
 
     # accuracy of this step's output on channel 0 against the oracle, and the CPU baseline
     cpu = None
@@ -672,7 +678,7 @@ def main():
                    nmse_gpu=metrics.nmse(Xc, xh0))
 
     forms = None
-    if not args.no_forms and not wide:
+    if not args.no_forms and not wide and not args.steps_only:
         forms = time_forms(api, synthgen, cfg, X, B, s2, ms_step, sg, torch, max(args.steps, 2))
 
     line = {

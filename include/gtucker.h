@@ -90,6 +90,14 @@ typedef struct {
   int32_t group_size;    /* subcarriers per group */
   int32_t m, n, p;       /* Tucker ranks: 1<=m<=nr, 1<=n<=nt, 1<=p<=group_size */
   int32_t ns;            /* SVD-precoded streams evaluated by the SINR calls, 1<=ns<=min(m,n) */
+  /* Factor sharing and the multi-cell system (equation "three matrix factorization"):
+   * channels with the same nonzero a_id share the mode-1 factor A (the channels of one UE from
+   * every BS), channels with the same nonzero b_id share the mode-2 factor B (every UE's channel
+   * from one BS); 0 gives the channel a factor of its own.  Sharing channels must agree on
+   * (nr, m) for A and (nt, n) for B.  For gt_sinr_eval_system, a_id labels the UE and b_id the BS
+   * of every channel, and serving = 1 marks each UE's link to the BS that serves it (one per
+   * UE). */
+  int32_t a_id, b_id, serving;
 } gt_channel_desc;
 
 /* Element offsets of one channel inside packed batch buffers. */
@@ -143,7 +151,9 @@ gt_status gt_workspace_init(const gt_plan* plan, void* ws, size_t ws_bytes, void
  * runs the fused per-group passes spreads parts of each sweep over up to three side streams
  * of its own (made on the plan's first fit, default priority), forked from and joined back
  * into `stream` by events, so the call stays ordered on `stream` and can be captured in a
- * graph; a channel's results do not depend on the batch it is fitted in. */
+ * graph; a channel's results do not depend on the batch it is fitted in.  A plan whose channels
+ * share factors (nonzero a_id or b_id) fits all of them together, without side streams, and
+ * returns GT_ERR_UNSUPPORTED for a non-NULL obj_trace. */
 gt_status gt_tucker_fit(const gt_plan* plan, const void* X, void* A, void* B, void* C, void* G,
                         double* obj_trace, int32_t* dev_status, void* ws, size_t ws_bytes,
                         void* stream);
@@ -163,6 +173,32 @@ gt_status gt_tucker_reconstruct(const gt_plan* plan, const void* A, const void* 
 gt_status gt_sinr_eval(const gt_plan* plan, const void* C, const void* G, const float* sigma2,
                        int32_t n_snr, void* sinr, int32_t* dev_status, void* ws, size_t ws_bytes,
                        void* stream);
+
+/* Interference seen by each UE in gt_sinr_eval_system (equation "signal receiving"):
+ *   GT_INTERF_NONE   its own link only;
+ *   GT_INTERF_PAPER  its own link and, from every other BS k, the transmission to the first UE
+ *                    of cell k (the UE with the lowest a_id among those BS k serves): inter-cell
+ *                    interference only, the protocol of the paper's experiments (Section 4);
+ *   GT_INTERF_ALL    every transmission of every BS to every other UE (intra- and inter-cell). */
+#define GT_INTERF_NONE 0
+#define GT_INTERF_PAPER 1
+#define GT_INTERF_ALL 2
+
+/* Per-subcarrier SINR of every UE of a multi-cell system from the compressed channels
+ * (Sections 2.2 and 3.3: equations "covariance matrix", "compressed pre", "Cov", "reduced
+ * inversion of interference matrix", "MMSE receive filter", "s_r^ij", "SINR formula").  The
+ * plan's channels are the links (UE a_id, BS b_id) of the system (see gt_channel_desc); every
+ * UE needs a channel from every BS whose transmissions it sees under `mode`, and all channels
+ * the same nsc and ns, with m <= 8 and ns <= 4.  Each serving link's precoder (the first ns
+ * right singular vectors of its compressed channel, equation "precoding matrix") is formed
+ * first, in the workspace; then, for UE u served by BS i, Q~ = sum over the transmissions t
+ * (BS k with the precoder V~_v of UE v) of (Ht_{u,k} V~_v)(Ht_{u,k} V~_v)^H + s2 I_m and the
+ * MMSE chain on it.  The UE's SINR is written at its serving channel's subcarriers (layout of
+ * gt_sinr_eval); the other channels' entries are written as 0.  GT_ERR_ARG: not a complete
+ * system or a bad mode; GT_ERR_UNSUPPORTED: shapes outside the limits above, or a GT_C128 plan. */
+gt_status gt_sinr_eval_system(const gt_plan* plan, const void* C, const void* G, const float* sigma2,
+                              int32_t n_snr, int32_t mode, void* sinr, int32_t* dev_status, void* ws,
+                              size_t ws_bytes, void* stream);
 
 /* The same chain on the uncompressed channel H_s (nr x nt) read from X (Section 2.2). */
 gt_status gt_sinr_eval_full(const gt_plan* plan, const void* X, const float* sigma2, int32_t n_snr,

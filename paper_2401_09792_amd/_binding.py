@@ -14,13 +14,15 @@ STATUS_NAMES = {0: "GT_OK", 1: "GT_ERR_ARG", 2: "GT_ERR_SHAPE", 3: "GT_ERR_RANK"
                 7: "GT_ERR_NO_DEVICE"}
 GT_FIT_WARM_START = 1
 GT_C64, GT_C128 = 0, 1
+GT_INTERF_NONE, GT_INTERF_PAPER, GT_INTERF_ALL = 0, 1, 2
 DEV_NONFINITE, DEV_EIG_SWEEPS, DEV_CHOLESKY, DEV_ZERO_STREAM = 1, 2, 4, 8
 
 
 class ChannelDesc(C.Structure):
     _fields_ = [("nr", C.c_int32), ("nt", C.c_int32), ("nsc", C.c_int32),
                 ("group_size", C.c_int32), ("m", C.c_int32), ("n", C.c_int32),
-                ("p", C.c_int32), ("ns", C.c_int32)]
+                ("p", C.c_int32), ("ns", C.c_int32), ("a_id", C.c_int32),
+                ("b_id", C.c_int32), ("serving", C.c_int32)]
 
 
 class Offsets(C.Structure):
@@ -57,6 +59,9 @@ SIGNATURES = {
     "gt_sinr_eval": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_float),
                                C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                                C.c_void_p]),
+    "gt_sinr_eval_system": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_float),
+                                      C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_size_t, C.c_void_p]),
     "gt_sinr_eval_full": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_float), C.c_int32,
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                                     C.c_void_p]),

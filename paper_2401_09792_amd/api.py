@@ -74,7 +74,9 @@ class Plan:
         arr = (ChannelDesc * len(self.descs))()
         for i, d in enumerate(self.descs):
             arr[i] = ChannelDesc(d["nr"], d["nt"], d["nsc"], d["group_size"], d["m"], d["n"],
-                                 d["p"], d["ns"])
+                                 d["p"], d["ns"], d.get("a_id", 0), d.get("b_id", 0),
+                                 d.get("serving", 0))
+        self.sharing = any(d.get("a_id", 0) or d.get("b_id", 0) for d in self.descs)
         opt = FitOptions(int(iters), self.TTM_PREC[ttm_prec], 1 if eig_fp64 else 0,
                          B.GT_FIT_WARM_START if warm_start else 0, code)
         h = C.c_void_p()
@@ -138,8 +140,11 @@ class Plan:
 
     # -- calls -----------------------------------------------------------------------
     def fit(self, X: torch.Tensor, factors: Optional[Dict[str, torch.Tensor]] = None,
-            trace: bool = True) -> Dict[str, torch.Tensor]:
-        """Groupwise Tucker compression of every channel in X (packed)."""
+            trace: Optional[bool] = None) -> Dict[str, torch.Tensor]:
+        """Groupwise Tucker compression of every channel in X (packed).  The objective trace is
+        returned by default, except for plans that share factors (which provide none)."""
+        if trace is None:
+            trace = not self.sharing
         self._cx(X, "x", "X")
         f = factors if factors is not None else self.empty_factors()
         for k in ("A", "B", "C", "G"):
@@ -200,6 +205,26 @@ class Plan:
         check("gt_sinr_eval", self.lib.gt_sinr_eval(
             self._h, _ptr(C_), _ptr(G), s2, k, _ptr(out), _ptr(status), _ptr(self.ws),
             self.ws_bytes, _stream()))
+        return out
+
+    INTERF = {"none": B.GT_INTERF_NONE, "paper": B.GT_INTERF_PAPER, "all": B.GT_INTERF_ALL}
+
+    def sinr_system(self, C_, G, sigma2: Sequence[float], mode: str = "paper",
+                    out: Optional[torch.Tensor] = None,
+                    status: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """SINR of every UE of a multi-cell system plan (channels labelled by a_id = UE,
+        b_id = BS, serving = 1 on each UE's serving link), with the interference of `mode`;
+        the UE's values sit at its serving channel's subcarriers."""
+        s2, k = self._sigma2(sigma2)
+        self._cx(C_, "c", "C")
+        self._cx(G, "g", "G")
+        self._status(status)
+        if out is None:
+            out = torch.empty(self._sinr_shape(k), dtype=self.rdtype, device=self.device)
+        self._real_out(out, k, "out")
+        check("gt_sinr_eval_system", self.lib.gt_sinr_eval_system(
+            self._h, _ptr(C_), _ptr(G), s2, k, self.INTERF[mode], _ptr(out), _ptr(status),
+            _ptr(self.ws), self.ws_bytes, _stream()))
         return out
 
     def sinr_full(self, X, sigma2: Sequence[float], out: Optional[torch.Tensor] = None,

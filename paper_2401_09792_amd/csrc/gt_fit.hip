@@ -747,16 +747,23 @@ __global__ void __launch_bounds__(256) k_core(const DevChan* __restrict__ chans,
 static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 gt_status launch_eigB_sub(const LaunchCtx& L, float2* B, int32_t* status, int warm);
+gt_status launch_share_gram(const LaunchCtx& L, int which);
 
+// The eigensolves of one half-step.  Channels that share a factor get the Gram summed over the
+// sharing channels first (equations "update A" and "update B" over the shared index sets).
 template <typename T>
 static gt_status eig_all(const LaunchCtx& L, int which, float2* A, float2* B, float2* C,
                          int32_t* status, int warm) {
   if (which == 0) {
     GT_LAUNCH(k_reduce_S1, dim3(1, L.n_channels), dim3(256), L.d_chans,
               L.ws);
+    gt_status st = launch_share_gram(L, 0);
+    if (st != GT_OK) return st;
     GT_LAUNCH((k_eigA<T, 16>), dim3(cdiv(L.n_channels, 4)), dim3(64), L.d_chans, L.n_channels,
               L.ws, A, status, warm);
   } else if (which == 1) {
+    gt_status sst = launch_share_gram(L, 1);
+    if (sst != GT_OK) return sst;
     constexpr int NW = sizeof(T) == 4 ? 4 : 8;
     if (L.min_nt <= 64)
       GT_LAUNCH((k_eigB<T, NW>), dim3(L.n_channels), dim3(64 * NW), L.d_chans, L.ws, B, status, warm);

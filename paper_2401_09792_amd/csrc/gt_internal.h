@@ -78,6 +78,11 @@ enum ScClass {
 
 // Workspace header: where the tables sit.
 struct WsLayout {
+  int64_t share_off[2] = {0, 0};  // int32[groups + 1] per shared factor
+  int64_t share_ch[2] = {0, 0};   // int32[members]
+  int64_t sys_serving = 0;        // int32[n_channels]
+  int64_t sys_terms_off[3] = {0, 0, 0};  // int32[n_channels + 1] per interference mode
+  int64_t sys_terms[3] = {0, 0, 0};      // int32[2 terms] per interference mode
   int64_t chans;   // DevChan[n_channels]
   int64_t groups;  // GroupItem[total_groups]
   int64_t groups_by_size;  // GroupItem[total_groups]: groups of size <= 16 first, then the rest
@@ -113,6 +118,13 @@ struct LaunchCtx {
   int sc_j[SC_COUNT + 1] = {};
   int64_t sc_base[SC_COUNT + 1] = {};
   int sc_maxn[SC_COUNT] = {};
+  // factor sharing (0: mode-1 factor A, 1: mode-2 factor B): groups of two or more channels
+  // with the same label, members d_share_ch[d_share_off[g] .. d_share_off[g + 1])
+  int n_share[2] = {0, 0};
+  const int32_t* d_share_off[2] = {nullptr, nullptr};
+  const int32_t* d_share_ch[2] = {nullptr, nullptr};
+  // multi-cell system: 1 for each UE's serving channel
+  const int32_t* d_sys_serving = nullptr;
 };
 
 // A fit whose batch is split into parts of consecutive channels: the parts' contexts (their

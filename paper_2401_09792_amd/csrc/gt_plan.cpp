@@ -31,6 +31,9 @@ gt_status launch_sinr(const LaunchCtx& L, int64_t total_sc, bool full, const flo
 gt_status launch_sinr_bwd(const LaunchCtx& L, int64_t total_sc, const float2* C, const float2* G,
                           const float* s2, int n_snr, const float* gsinr, float2* gC, float2* gG,
                           int ns_max, int32_t* status);
+gt_status launch_sinr_system(const LaunchCtx& L, int64_t total_sc, const int32_t* terms_off,
+                             const int32_t* terms, const float2* C, const float2* G,
+                             const float* s2, int n_snr, float* out, int ns_max, int32_t* status);
 gt_status launch_sinr_c128(const LaunchCtx& L, int64_t total_sc, bool full, const double2* X,
                            const double2* C, const double2* G, const float* s2, int n_snr,
                            double* out, int ns_max, int32_t* status);
@@ -125,6 +128,15 @@ struct gt_plan {
   // that runs in the library's static scratch array; sblob holds its table bytes
   WsLayout slay{};
   std::vector<char> sblob;
+  // factor sharing: groups of channels with the same nonzero a_id (0) or b_id (1)
+  std::vector<int32_t> share_off[2], share_ch[2];
+  bool sharing = false;
+  // multi-cell system: serving flags and, per interference mode, each serving channel's
+  // transmissions (channel Ht_{u,k}, serving channel of the precoder's UE)
+  bool system = false;
+  bool sys_uniform = false;
+  std::vector<int32_t> sys_serving;
+  std::vector<int32_t> sys_terms_off[3], sys_terms[3];
   ~gt_plan();
 };
 
@@ -170,6 +182,7 @@ static gt_status validate(const gt_channel_desc& d) {
   if (d.m < 1 || d.m > d.nr || d.n < 1 || d.n > d.nt || d.n > 64) return GT_ERR_RANK;
   if (d.p < 1 || d.p > d.group_size) return GT_ERR_RANK;
   if (d.ns < 1 || d.ns > std::min(d.m, d.n)) return GT_ERR_RANK;
+  if (d.a_id < 0 || d.b_id < 0 || d.serving < 0 || d.serving > 1) return GT_ERR_ARG;
   return GT_OK;
 }
 
@@ -253,6 +266,111 @@ static gt_status plan_build(const gt_channel_desc* descs, int32_t n_channels,
     p->max_nsplit = std::max(p->max_nsplit, ch.nsplit);
   }
   p->totals = gt_offsets{ox, oa, ob, oc, og, oht, osc, gfirst, 0};
+  {  // factor sharing: members of each label in channel order; groups of two or more
+    for (int f = 0; f < 2; ++f) {
+      std::vector<std::pair<int32_t, int32_t>> lab;
+      for (int c = 0; c < n_channels; ++c) {
+        const int32_t id = f == 0 ? descs[c].a_id : descs[c].b_id;
+        if (id > 0) lab.push_back({id, c});
+      }
+      std::sort(lab.begin(), lab.end());
+      p->share_off[f].assign(1, 0);
+      p->share_ch[f].clear();
+      for (size_t a = 0; a < lab.size();) {
+        size_t b = a;
+        while (b < lab.size() && lab[b].first == lab[a].first) ++b;
+        if (b - a >= 2) {
+          const gt_channel_desc& d0 = descs[lab[a].second];
+          for (size_t k = a; k < b; ++k) {
+            const gt_channel_desc& d = descs[lab[k].second];
+            const bool same = f == 0 ? (d.nr == d0.nr && d.m == d0.m) : (d.nt == d0.nt && d.n == d0.n);
+            if (!same) {
+              delete p;
+              return GT_ERR_SHAPE;
+            }
+            p->share_ch[f].push_back(lab[k].second);
+          }
+          p->share_off[f].push_back((int32_t)p->share_ch[f].size());
+          p->sharing = true;
+        }
+        a = b;
+      }
+    }
+    // a complete system: every channel labelled, one serving link per UE, at most one channel
+    // per (UE, BS); the transmissions each UE sees under the three interference modes
+    bool sys = true;
+    std::vector<int> ue_serv;   // serving channel per UE label (index label - 1)
+    int max_ue = 0, max_bs = 0;
+    for (int c = 0; c < n_channels; ++c) {
+      if (descs[c].a_id < 1 || descs[c].b_id < 1) sys = false;
+      max_ue = std::max(max_ue, descs[c].a_id);
+      max_bs = std::max(max_bs, descs[c].b_id);
+    }
+    std::vector<int> link;  // channel of (UE, BS), -1 if absent
+    if (sys) {
+      ue_serv.assign(max_ue, -1);
+      link.assign((size_t)max_ue * max_bs, -1);
+      for (int c = 0; c < n_channels; ++c) {
+        const int u = descs[c].a_id - 1, k = descs[c].b_id - 1;
+        if (link[(size_t)u * max_bs + k] >= 0) sys = false;
+        link[(size_t)u * max_bs + k] = c;
+        if (descs[c].serving) {
+          if (ue_serv[u] >= 0) sys = false;
+          ue_serv[u] = c;
+        }
+      }
+      for (int u = 0; u < max_ue && sys; ++u)
+        if (ue_serv[u] < 0 && std::any_of(link.begin() + (size_t)u * max_bs,
+                                          link.begin() + (size_t)(u + 1) * max_bs,
+                                          [](int v) { return v >= 0; }))
+          sys = false;
+    }
+    p->system = sys;
+    p->sys_serving.assign(n_channels, 0);
+    for (int f = 0; f < 3; ++f) {
+      p->sys_terms_off[f].assign(n_channels + 1, 0);
+      p->sys_terms[f].clear();
+    }
+    if (sys) {
+      bool uniform = true;
+      for (int c = 0; c < n_channels; ++c) {
+        p->sys_serving[c] = descs[c].serving;
+        uniform = uniform && descs[c].nsc == descs[0].nsc && descs[c].ns == descs[0].ns &&
+                  descs[c].m <= 8 && descs[c].ns <= 4;
+      }
+      // first UE of each cell: the lowest UE label among the serving links of that BS
+      std::vector<int> first(max_bs, -1);
+      for (int u = 0; u < max_ue; ++u)
+        if (ue_serv[u] >= 0) {
+          const int k = descs[ue_serv[u]].b_id - 1;
+          if (first[k] < 0) first[k] = u;
+        }
+      for (int f = 0; f < 3; ++f) {
+        for (int c = 0; c < n_channels; ++c) {
+          if (descs[c].serving) {
+            const int u = descs[c].a_id - 1, i = descs[c].b_id - 1;
+            p->sys_terms[f].push_back(c);
+            p->sys_terms[f].push_back(c);
+            for (int v = 0; v < max_ue; ++v) {
+              if (v == u || ue_serv[v] < 0) continue;
+              const int k = descs[ue_serv[v]].b_id - 1;
+              const bool seen = f == 2 || (f == 1 && k != i && first[k] == v);
+              if (!seen) continue;
+              const int ct = link[(size_t)u * max_bs + k];
+              if (ct < 0) {
+                uniform = false;  // the UE has no channel from that BS: this mode is not available
+                continue;
+              }
+              p->sys_terms[f].push_back(ct);
+              p->sys_terms[f].push_back(ue_serv[v]);
+            }
+          }
+          p->sys_terms_off[f][c + 1] = (int32_t)(p->sys_terms[f].size() / 2);
+        }
+      }
+      p->sys_uniform = uniform;
+    }
+  }
   p->ns_max = p->max_ns;
   // workspace: tables then per-channel scratch
   int64_t off = 0;
@@ -312,6 +430,21 @@ static gt_status plan_build(const gt_channel_desc* descs, int32_t n_channels,
   off = align256(off + (int64_t)sizeof(int32_t) * n_channels);
   p->lay.sc_off = off;
   off = align256(off + (int64_t)sizeof(int64_t) * (n_channels + 1));
+  for (int f = 0; f < 2; ++f) {
+    p->lay.share_off[f] = off;
+    off = align256(off + (int64_t)sizeof(int32_t) * p->share_off[f].size());
+    p->lay.share_ch[f] = off;
+    off = align256(off + (int64_t)sizeof(int32_t) * std::max<size_t>(p->share_ch[f].size(), 1));
+  }
+  p->lay.sys_serving = off;
+  off = align256(off + (int64_t)sizeof(int32_t) * n_channels);
+  for (int f = 0; f < 3; ++f) {
+    p->lay.sys_terms_off[f] = off;
+    off = align256(off + (int64_t)sizeof(int32_t) * (n_channels + 1));
+    p->lay.sys_terms[f] = off;
+    off = align256(off + (int64_t)sizeof(int32_t) * std::max<size_t>(p->sys_terms[f].size(), 1));
+  }
+  const int64_t tables_end = off;
   const int64_t c8 = 8;
   for (int c = 0; c < n_channels; ++c) {
     DevChan& ch = p->chans[c];
@@ -381,17 +514,32 @@ static gt_status plan_build(const gt_channel_desc* descs, int32_t n_channels,
     std::memcpy(p->sblob.data() + p->slay.sc_off, p->sc_off.data(),
                 sizeof(int64_t) * (n_channels + 1));
   }
-  p->blob.assign((size_t)p->lay.sc_off + sizeof(int64_t) * (n_channels + 1), 0);
+  p->blob.assign((size_t)tables_end, 0);
   std::memcpy(p->blob.data() + p->lay.chans, p->chans.data(), sizeof(DevChan) * n_channels);
   std::memcpy(p->blob.data() + p->lay.groups, p->groups.data(), sizeof(GroupItem) * gfirst);
   std::memcpy(p->blob.data() + p->lay.groups_by_size, p->groups_by_size.data(),
               sizeof(GroupItem) * gfirst);
   std::memcpy(p->blob.data() + p->lay.tiles, p->tiles.data(), sizeof(int32_t) * p->tiles.size());
   std::memcpy(p->blob.data() + p->lay.sc_ch, p->sc_ch.data(), sizeof(int32_t) * n_channels);
+  for (int f = 0; f < 2; ++f) {
+    std::memcpy(p->blob.data() + p->lay.share_off[f], p->share_off[f].data(),
+                sizeof(int32_t) * p->share_off[f].size());
+    if (!p->share_ch[f].empty())
+      std::memcpy(p->blob.data() + p->lay.share_ch[f], p->share_ch[f].data(),
+                  sizeof(int32_t) * p->share_ch[f].size());
+  }
+  std::memcpy(p->blob.data() + p->lay.sys_serving, p->sys_serving.data(), sizeof(int32_t) * n_channels);
+  for (int f = 0; f < 3; ++f) {
+    std::memcpy(p->blob.data() + p->lay.sys_terms_off[f], p->sys_terms_off[f].data(),
+                sizeof(int32_t) * (n_channels + 1));
+    if (!p->sys_terms[f].empty())
+      std::memcpy(p->blob.data() + p->lay.sys_terms[f], p->sys_terms[f].data(),
+                  sizeof(int32_t) * p->sys_terms[f].size());
+  }
   std::memcpy(p->blob.data() + p->lay.sc_off, p->sc_off.data(), sizeof(int64_t) * (n_channels + 1));
   p->ws_total = p->lay.total;
   // batch split of the fit (fused passes, 8 or more channels): views over parts
-  if (allow_split && n_channels >= 8 && fused_fit_ok(make_ctx(p, nullptr, nullptr))) {
+  if (allow_split && !p->sharing && n_channels >= 8 && fused_fit_ok(make_ctx(p, nullptr, nullptr))) {
     const int k = n_channels >= 16 ? 4 : 2;
     int64_t woff = align256(p->lay.total);
     for (int i = 0; i < k; ++i) {
@@ -522,6 +670,14 @@ static LaunchCtx make_ctx_at(const gt_plan* p, const WsLayout& lay, void* ws, vo
   L.eig_fp64 = p->opt.eig_fp64;
   L.tune_bstep = p->tune_bstep;
   L.tune_tpass = p->tune_tpass;
+  if (&lay == &p->lay && p->sharing) {
+    for (int f = 0; f < 2; ++f) {
+      L.n_share[f] = (int)p->share_off[f].size() - 1;
+      L.d_share_off[f] = reinterpret_cast<const int32_t*>(L.ws + lay.share_off[f]);
+      L.d_share_ch[f] = reinterpret_cast<const int32_t*>(L.ws + lay.share_ch[f]);
+    }
+  }
+  if (&lay == &p->lay) L.d_sys_serving = reinterpret_cast<const int32_t*>(L.ws + lay.sys_serving);
   return L;
 }
 
@@ -593,6 +749,7 @@ gt_status gt_tucker_fit(const gt_plan* plan, const void* X, void* A, void* B, vo
   if (st != GT_OK) return st;
   if (!X || !A || !B || !C || !G) return GT_ERR_ARG;
   if (plan->opt.dtype != GT_C64) return GT_ERR_UNSUPPORTED;
+  if (plan->sharing && obj_trace) return GT_ERR_UNSUPPORTED;
   // 16-bit contractions take K steps of 8 reals: every nt a multiple of 4
   if (plan->opt.ttm_prec != GT_TTM_FP32) {
     for (const auto& d : plan->desc)
@@ -722,6 +879,22 @@ gt_status gt_sinr_eval(const gt_plan* plan, const void* C, const void* G, const 
                             sigma2, n_snr, (double*)sinr, plan->ns_max, dev_status);
   return launch_sinr(L, plan->totals.sc, false, nullptr, (const float2*)C, (const float2*)G, sigma2,
                      n_snr, (float*)sinr, plan->ns_max, dev_status);
+}
+
+gt_status gt_sinr_eval_system(const gt_plan* plan, const void* C, const void* G, const float* sigma2,
+                              int32_t n_snr, int32_t mode, void* sinr, int32_t* dev_status, void* ws,
+                              size_t ws_bytes, void* stream) {
+  gt_status st = check_ws(plan, ws, ws_bytes);
+  if (st != GT_OK) return st;
+  if ((st = check_snr(sigma2, n_snr)) != GT_OK) return st;
+  if (!C || !G || !sinr) return GT_ERR_ARG;
+  if (mode < GT_INTERF_NONE || mode > GT_INTERF_ALL || !plan->system) return GT_ERR_ARG;
+  if (plan->opt.dtype != GT_C64 || !plan->sys_uniform) return GT_ERR_UNSUPPORTED;
+  LaunchCtx L = make_ctx(plan, ws, stream);
+  const int32_t* toff = reinterpret_cast<const int32_t*>(L.ws + plan->lay.sys_terms_off[mode]);
+  const int32_t* terms = reinterpret_cast<const int32_t*>(L.ws + plan->lay.sys_terms[mode]);
+  return launch_sinr_system(L, plan->totals.sc, toff, terms, (const float2*)C, (const float2*)G,
+                            sigma2, n_snr, (float*)sinr, plan->ns_max, dev_status);
 }
 
 gt_status gt_sinr_eval_full(const gt_plan* plan, const void* X, const float* sigma2, int32_t n_snr,

@@ -1,5 +1,8 @@
 // Per-subcarrier SINR from the compressed form (Section 3.3) or from the full channel
-// (Section 2.2), and its adjoint.
+// (Section 2.2), and its adjoint: the LDS-cooperative kernels (the full-channel SINR, compressed
+// channels with m > 8 or with more than 4 streams in the adjoint, and every FP64 call), the
+// per-group reduction of the adjoint, and the launchers of every SINR class (compressed channels
+// with m <= 8 run on the register-resident row-parallel kernels of gt_sinr_rows.hip).
 //
 // One aligned group of MP lanes handles one subcarrier; lane i owns row i of every small
 // matrix.  Chain for a channel matrix H (M x N; M = m, N = n for the compressed form):
@@ -318,617 +321,6 @@ __global__ void __launch_bounds__(64) k_sinr(const DevChan* __restrict__ chans, 
     if (valid && r < ns_max) out[((int64_t)k * total_sc + gsc) * ns_max + r] = (O)val;
   }
   if (valid && status && bits && r == 0) atomicOr(reinterpret_cast<unsigned int*>(status + c), bits);
-}
-
-// ---------------------------------------------------------------------------------------
-// Register-resident variant for compressed channels with m <= M (M = 4 or 8): one lane per
-// subcarrier, every matrix in registers with compile-time indices, cyclic Jacobi on the
-// m x m Gram, then the same MMSE chain.  Rows i >= m are zero and stay zero.
-
-template <int M>
-struct LaneHerm {  // Hermitian M x M: diagonal d[i], upper entries (ur[i][j], ui[i][j]), i < j
-  float d[M];
-  float ur[M][M], ui[M][M];
-};
-
-// Column j of the compressed channel, Ht[:, j] = sum_q C[s,q] G_g[q][:, j], rows i < m.
-template <int M>
-__device__ __forceinline__ void ht_column(const float2* __restrict__ Cs, const float2* __restrict__ Gg,
-                                          int pg, int m, int n, int j, float (&hr)[M], float (&hi)[M]) {
-#pragma unroll
-  for (int i = 0; i < M; ++i) hr[i] = hi[i] = 0.f;
-  for (int q = 0; q < pg; ++q) {
-    const float2 cq = Cs[q];
-    const float2* Gq = Gg + (int64_t)q * m * n + j;
-#pragma unroll
-    for (int i = 0; i < M; ++i) {
-      if (i < m) {
-        const float2 gv = Gq[(int64_t)i * n];
-        hr[i] += cq.x * gv.x - cq.y * gv.y;
-        hi[i] += cq.x * gv.y + cq.y * gv.x;
-      }
-    }
-  }
-}
-
-// Per-lane front end shared by the SINR kernel and its adjoint: Gram of Ht, cyclic Jacobi,
-// descending order, singular values sig[r] and HV = U_ns Sigma_ns (hvr/hvi), zero-stream and
-// convergence status bits.
-template <int M, int NS>
-__device__ __forceinline__ void lane_svd(bool valid, int m, int n, int ns, int pg,
-                                         const float2* __restrict__ Cs,
-                                         const float2* __restrict__ Gg, float (&sig)[NS],
-                                         float (&hvr)[M][NS], float (&hvi)[M][NS], uint32_t& bits) {
-
-  // K = Ht Ht^H, one column of Ht at a time
-  LaneHerm<M> K;
-#pragma unroll
-  for (int i = 0; i < M; ++i) {
-    K.d[i] = 0.f;
-#pragma unroll
-    for (int j = 0; j < M; ++j) K.ur[i][j] = K.ui[i][j] = 0.f;
-  }
-  if (valid) {
-    for (int j = 0; j < n; ++j) {
-      float hr[M], hi[M];
-      ht_column<M>(Cs, Gg, pg, m, n, j, hr, hi);
-#pragma unroll
-      for (int i = 0; i < M; ++i) {
-        K.d[i] += hr[i] * hr[i] + hi[i] * hi[i];
-#pragma unroll
-        for (int k = i + 1; k < M; ++k) {  // h_i conj(h_k)
-          K.ur[i][k] += hr[i] * hr[k] + hi[i] * hi[k];
-          K.ui[i][k] += hi[i] * hr[k] - hr[i] * hi[k];
-        }
-      }
-    }
-  }
-
-  // cyclic Jacobi with eigenvectors V (columns)
-  float vr[M][M], vi[M][M];
-#pragma unroll
-  for (int i = 0; i < M; ++i)
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-      vr[i][j] = (i == j) ? 1.f : 0.f;
-      vi[i][j] = 0.f;
-    }
-  const float eps = 5.9604645e-08f;
-  bool conv = false;
-  for (int sw = 0; sw <= 10; ++sw) {
-    float off = 0.f, dg = 0.f;
-#pragma unroll
-    for (int i = 0; i < M; ++i) {
-      dg += K.d[i] * K.d[i];
-#pragma unroll
-      for (int k = i + 1; k < M; ++k) off += K.ur[i][k] * K.ur[i][k] + K.ui[i][k] * K.ui[i][k];
-    }
-    if (__all((2.f * off <= 4.f * eps * eps * dg) ? 1 : 0)) {
-      conv = true;
-      break;
-    }
-    if (sw == 10) break;
-#pragma unroll
-    for (int p = 0; p < M - 1; ++p) {
-#pragma unroll
-      for (int q = p + 1; q < M; ++q) {
-        const float a = K.d[p], b = K.d[q];
-        const float cre = K.ur[p][q], cim = K.ui[p][q];
-        const float ac = __builtin_sqrtf(cre * cre + cim * cim);
-        float cs = 1.f, sre = 0.f, sim = 0.f, tac = 0.f;
-        if (ac > 0.f && ac > eps * 0.5f * (__builtin_fabsf(a) + __builtin_fabsf(b))) {
-          const float z = (b - a) / (2.f * ac);
-          const float az = __builtin_fabsf(z);
-          float tt = (az > 1.0e18f) ? 0.5f / az : 1.f / (az + __builtin_sqrtf(1.f + az * az));
-          if (z >= 0.f) tt = -tt;
-          cs = 1.f / __builtin_sqrtf(1.f + tt * tt);
-          const float sn = tt * cs;
-          sre = sn * cre / ac;
-          sim = sn * cim / ac;
-          tac = tt * ac;
-        }
-        // rows p and q against every other index k
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-          if (k == p || k == q) continue;
-          // K[p][k], K[q][k] from upper storage
-          float pkr, pki, qkr, qki;
-          if (p < k) { pkr = K.ur[p][k]; pki = K.ui[p][k]; } else { pkr = K.ur[k][p]; pki = -K.ui[k][p]; }
-          if (q < k) { qkr = K.ur[q][k]; qki = K.ui[q][k]; } else { qkr = K.ur[k][q]; qki = -K.ui[k][q]; }
-          // new row p: cs K[p][k] + s K[q][k];  new row q: -conj(s) K[p][k] + cs K[q][k]
-          const float npr = cs * pkr + (sre * qkr - sim * qki);
-          const float npi = cs * pki + (sre * qki + sim * qkr);
-          const float nqr = cs * qkr - (sre * pkr + sim * pki);
-          const float nqi = cs * qki - (sre * pki - sim * pkr);
-          if (p < k) { K.ur[p][k] = npr; K.ui[p][k] = npi; } else { K.ur[k][p] = npr; K.ui[k][p] = -npi; }
-          if (q < k) { K.ur[q][k] = nqr; K.ui[q][k] = nqi; } else { K.ur[k][q] = nqr; K.ui[k][q] = -nqi; }
-        }
-        K.d[p] = a + tac;
-        K.d[q] = b - tac;
-        K.ur[p][q] = 0.f;
-        K.ui[p][q] = 0.f;
-        // V <- V J: column p = V_p cs + V_q conj(s), column q = -V_p s + V_q cs
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-          const float xr = vr[k][p], xi = vi[k][p], yr = vr[k][q], yi = vi[k][q];
-          vr[k][p] = xr * cs + (yr * sre + yi * sim);
-          vi[k][p] = xi * cs + (yi * sre - yr * sim);
-          vr[k][q] = yr * cs - (xr * sre - xi * sim);
-          vi[k][q] = yi * cs - (xr * sim + xi * sre);
-        }
-      }
-    }
-  }
-  if (!conv) bits |= GT_DEV_EIG_SWEEPS;
-
-  // descending order over the first m eigenvalues; HV = U_ns Sigma_ns
-  int rank[M];
-#pragma unroll
-  for (int i = 0; i < M; ++i) {
-    const float li = (i < m) ? K.d[i] : -3.0e38f;
-    int rk = 0;
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-      const float lj = (j < m) ? K.d[j] : -3.0e38f;
-      rk += (lj > li || (lj == li && j < i)) ? 1 : 0;
-    }
-    rank[i] = rk;
-  }
-#pragma unroll
-  for (int r = 0; r < NS; ++r) {
-    float l = 0.f;
-#pragma unroll
-    for (int j = 0; j < M; ++j) l = (rank[j] == r) ? K.d[j] : l;
-    sig[r] = __builtin_sqrtf(l > 0.f ? l : 0.f);
-#pragma unroll
-    for (int i = 0; i < M; ++i) {
-      float ur = 0.f, ui = 0.f;
-#pragma unroll
-      for (int j = 0; j < M; ++j) {
-        ur = (rank[j] == r) ? vr[i][j] : ur;
-        ui = (rank[j] == r) ? vi[i][j] : ui;
-      }
-      const bool on = r < ns && i < m;
-      hvr[i][r] = on ? sig[r] * ur : 0.f;
-      hvi[i][r] = on ? sig[r] * ui : 0.f;
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < NS; ++r)
-    if (r < ns && !(sig[r] > 1.0e-3f * sig[0])) bits |= GT_DEV_ZERO_STREAM;
-}
-
-template <int M, int NS>
-__global__ void __launch_bounds__(64) k_sinr_lane(const DevChan* __restrict__ chans, ScRange R,
-                                                   int64_t total_sc, const float2* __restrict__ C,
-                                                   const float2* __restrict__ G, SnrArgs snr,
-                                                   float* __restrict__ out, int ns_max,
-                                                   int32_t* status) {
-  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = it < R.count;
-  int64_t gsc = 0;
-  const int c = valid ? locate_sc(R, chans, it, gsc) : 0;
-  const DevChan& ch = chans[c];
-  const int64_t s = valid ? gsc - ch.sc : 0;
-  const int m = ch.m, n = ch.n;
-  const int ns = valid ? ch.ns : 0;
-  const int g = (int)(s / ch.gs);
-  const int pg = min(ch.p, min(ch.gs, ch.nsc - g * ch.gs));
-  const float2* Cs = C + ch.c + s * ch.p;
-  const float2* Gg = G + ch.g + (int64_t)g * ch.p * m * n;
-  uint32_t bits = 0;
-  float sig[NS], hvr[M][NS], hvi[M][NS];
-  lane_svd<M, NS>(valid, m, n, ns, pg, Cs, Gg, sig, hvr, hvi, bits);
-
-  for (int kk = 0; kk < snr.n; ++kk) {
-    const float s2 = snr.s2[kk];
-    // Cholesky of Q = HV HV^H + s2 I (lower L, real diagonal)
-    float lr[M][M], li[M][M], ld_[M];
-    bool ok = true;
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-      float dj = s2;
-#pragma unroll
-      for (int r = 0; r < NS; ++r) dj += hvr[j][r] * hvr[j][r] + hvi[j][r] * hvi[j][r];
-#pragma unroll
-      for (int k = 0; k < j; ++k) dj -= lr[j][k] * lr[j][k] + li[j][k] * li[j][k];
-      ok = ok && (dj > 0.f);
-      const float djs = __builtin_sqrtf(dj > 0.f ? dj : 1.f);
-      ld_[j] = djs;
-      const float inv = 1.f / djs;
-#pragma unroll
-      for (int i = j + 1; i < M; ++i) {
-        // Q[i][j] = sum_r hv[i][r] conj(hv[j][r])
-        float qr = 0.f, qi = 0.f;
-#pragma unroll
-        for (int r = 0; r < NS; ++r) {
-          qr += hvr[i][r] * hvr[j][r] + hvi[i][r] * hvi[j][r];
-          qi += hvi[i][r] * hvr[j][r] - hvr[i][r] * hvi[j][r];
-        }
-#pragma unroll
-        for (int k = 0; k < j; ++k) {  // L[i][k] conj(L[j][k])
-          qr -= lr[i][k] * lr[j][k] + li[i][k] * li[j][k];
-          qi -= li[i][k] * lr[j][k] - lr[i][k] * li[j][k];
-        }
-        lr[i][j] = qr * inv;
-        li[i][j] = qi * inv;
-      }
-    }
-    // W = Q^{-1} HV, column by column
-    float wr[M][NS], wi[M][NS];
-#pragma unroll
-    for (int r = 0; r < NS; ++r) {
-#pragma unroll
-      for (int i = 0; i < M; ++i) {  // L y = hv_r
-        float ar = hvr[i][r], ai = hvi[i][r];
-#pragma unroll
-        for (int j = 0; j < i; ++j) {
-          ar -= lr[i][j] * wr[j][r] - li[i][j] * wi[j][r];
-          ai -= lr[i][j] * wi[j][r] + li[i][j] * wr[j][r];
-        }
-        wr[i][r] = ar / ld_[i];
-        wi[i][r] = ai / ld_[i];
-      }
-#pragma unroll
-      for (int i = M - 1; i >= 0; --i) {  // L^H w = y
-        float ar = wr[i][r], ai = wi[i][r];
-#pragma unroll
-        for (int j = i + 1; j < M; ++j) {
-          ar -= lr[j][i] * wr[j][r] + li[j][i] * wi[j][r];
-          ai -= lr[j][i] * wi[j][r] - li[j][i] * wr[j][r];
-        }
-        wr[i][r] = ar / ld_[i];
-        wi[i][r] = ai / ld_[i];
-      }
-    }
-    if (!ok) bits |= GT_DEV_CHOLESKY;
-    float res[NS];
-#pragma unroll
-    for (int r = 0; r < NS; ++r) {
-      float sig_p = 0.f, den = 0.f, nw = 0.f;
-#pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        float cr = 0.f, ci = 0.f;
-#pragma unroll
-        for (int i = 0; i < M; ++i) {
-          cr += wr[i][r] * hvr[i][k] + wi[i][r] * hvi[i][k];
-          ci += wr[i][r] * hvi[i][k] - wi[i][r] * hvr[i][k];
-        }
-        const float pw = cr * cr + ci * ci;
-        if (k == r)
-          sig_p = pw;
-        else
-          den += pw;
-      }
-#pragma unroll
-      for (int i = 0; i < M; ++i) nw += wr[i][r] * wr[i][r] + wi[i][r] * wi[i][r];
-      den += s2 * nw;
-      float v = sig_p / den;
-      if (!ok || r >= ns || !(sig[r] > 1.0e-3f * sig[0])) v = 0.f;
-      if (!(v == v) || v > 3.0e38f) {
-        v = 0.f;
-        bits |= GT_DEV_NONFINITE;
-      }
-      res[r] = v;
-    }
-    if (valid) {
-      float* o = out + ((int64_t)kk * total_sc + gsc) * ns_max;
-#pragma unroll
-      for (int r = 0; r < NS; ++r)
-        if (r < ns_max) o[r] = res[r];
-      for (int r = NS; r < ns_max; ++r) o[r] = 0.f;
-    }
-  }
-  if (valid && status && bits) atomicOr(reinterpret_cast<unsigned int*>(status + c), bits);
-}
-
-// Per-lane adjoint for m <= M (the chain and the adjoint formulas are those described for
-// k_sinr_bwd below).  With D the kept-block coefficient matrix and v_b = Ht^H u_b / sigma_b,
-//   dl/dHt = sum_{a,b} u_a D_ab v_b^H = E Ht,   E = U_ns D Sigma^{-1} U_ns^H   (m x m),
-// so the gradient is formed column by column from recomputed columns of Ht.
-template <int M, int NS>
-__global__ void __launch_bounds__(64) k_sinr_bwd_lane(const DevChan* __restrict__ chans,
-                                                       ScRange R, int64_t total_sc,
-                                                       const float2* __restrict__ C,
-                                                       const float2* __restrict__ G, SnrArgs snr,
-                                                       const float* __restrict__ gsinr, int ns_max,
-                                                       char* ws, int32_t* status) {
-  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = it < R.count;
-  int64_t gsc = 0;
-  const int c = valid ? locate_sc(R, chans, it, gsc) : 0;
-  const DevChan& ch = chans[c];
-  const int64_t s = valid ? gsc - ch.sc : 0;
-  const int m = ch.m, n = ch.n;
-  const int ns = valid ? ch.ns : 0;
-  const int g = (int)(s / ch.gs);
-  const int pg = min(ch.p, min(ch.gs, ch.nsc - g * ch.gs));
-  const float2* Cs = C + ch.c + s * ch.p;
-  const float2* Gg = G + ch.g + (int64_t)g * ch.p * m * n;
-  uint32_t bits = 0;
-  float sig[NS], hvr[M][NS], hvi[M][NS];
-  lane_svd<M, NS>(valid, m, n, ns, pg, Cs, Gg, sig, hvr, hvi, bits);
-  bool live[NS];  // streams that carry a gradient (requested and not numerically zero)
-#pragma unroll
-  for (int r = 0; r < NS; ++r) live[r] = r < ns && sig[r] > 1.0e-3f * sig[0];
-
-  float gbr[M][NS], gbi[M][NS];  // dl/dHV
-#pragma unroll
-  for (int i = 0; i < M; ++i)
-#pragma unroll
-    for (int k = 0; k < NS; ++k) gbr[i][k] = gbi[i][k] = 0.f;
-
-  for (int kk = 0; kk < snr.n; ++kk) {
-    const float s2 = snr.s2[kk];
-    float lr[M][M], li[M][M], ld_[M];
-    bool ok = true;
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-      float dj = s2;
-#pragma unroll
-      for (int r = 0; r < NS; ++r) dj += hvr[j][r] * hvr[j][r] + hvi[j][r] * hvi[j][r];
-#pragma unroll
-      for (int k = 0; k < j; ++k) dj -= lr[j][k] * lr[j][k] + li[j][k] * li[j][k];
-      ok = ok && (dj > 0.f);
-      const float djs = __builtin_sqrtf(dj > 0.f ? dj : 1.f);
-      ld_[j] = djs;
-      const float inv = 1.f / djs;
-#pragma unroll
-      for (int i = j + 1; i < M; ++i) {
-        float qr = 0.f, qi = 0.f;
-#pragma unroll
-        for (int r = 0; r < NS; ++r) {
-          qr += hvr[i][r] * hvr[j][r] + hvi[i][r] * hvi[j][r];
-          qi += hvi[i][r] * hvr[j][r] - hvr[i][r] * hvi[j][r];
-        }
-#pragma unroll
-        for (int k = 0; k < j; ++k) {
-          qr -= lr[i][k] * lr[j][k] + li[i][k] * li[j][k];
-          qi -= li[i][k] * lr[j][k] - lr[i][k] * li[j][k];
-        }
-        lr[i][j] = qr * inv;
-        li[i][j] = qi * inv;
-      }
-    }
-    if (!ok) {
-      bits |= GT_DEV_CHOLESKY;
-      continue;
-    }
-    // solve Q x = y in place (column of M complex values)
-    auto solve = [&](float (&xr)[M], float (&xi)[M]) {
-#pragma unroll
-      for (int i = 0; i < M; ++i) {
-        float ar = xr[i], ai = xi[i];
-#pragma unroll
-        for (int j = 0; j < i; ++j) {
-          ar -= lr[i][j] * xr[j] - li[i][j] * xi[j];
-          ai -= lr[i][j] * xi[j] + li[i][j] * xr[j];
-        }
-        xr[i] = ar / ld_[i];
-        xi[i] = ai / ld_[i];
-      }
-#pragma unroll
-      for (int i = M - 1; i >= 0; --i) {
-        float ar = xr[i], ai = xi[i];
-#pragma unroll
-        for (int j = i + 1; j < M; ++j) {
-          ar -= lr[j][i] * xr[j] + li[j][i] * xi[j];
-          ai -= lr[j][i] * xi[j] - li[j][i] * xr[j];
-        }
-        xr[i] = ar / ld_[i];
-        xi[i] = ai / ld_[i];
-      }
-    };
-    float wr[M][NS], wi[M][NS];
-#pragma unroll
-    for (int r = 0; r < NS; ++r) {
-      float xr[M], xi[M];
-#pragma unroll
-      for (int i = 0; i < M; ++i) {
-        xr[i] = hvr[i][r];
-        xi[i] = hvi[i][r];
-      }
-      solve(xr, xi);
-#pragma unroll
-      for (int i = 0; i < M; ++i) {
-        wr[i][r] = xr[i];
-        wi[i][r] = xi[i];
-      }
-    }
-    // c[r][k] = w_r^H hv_k, and the SINR adjoint seeds
-    float cr[NS][NS], ci[NS][NS];
-#pragma unroll
-    for (int r = 0; r < NS; ++r)
-#pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        float ar = 0.f, ai = 0.f;
-#pragma unroll
-        for (int i = 0; i < M; ++i) {
-          ar += wr[i][r] * hvr[i][k] + wi[i][r] * hvi[i][k];
-          ai += wr[i][r] * hvi[i][k] - wi[i][r] * hvr[i][k];
-        }
-        cr[r][k] = ar;
-        ci[r][k] = ai;
-      }
-    float cbr[NS][NS], cbi[NS][NS], nbar[NS];
-#pragma unroll
-    for (int r = 0; r < NS; ++r) {
-      float sv = cr[r][r] * cr[r][r] + ci[r][r] * ci[r][r];
-      float nw = 0.f, den = 0.f;
-#pragma unroll
-      for (int i = 0; i < M; ++i) nw += wr[i][r] * wr[i][r] + wi[i][r] * wi[i][r];
-#pragma unroll
-      for (int k = 0; k < NS; ++k)
-        if (k != r) den += cr[r][k] * cr[r][k] + ci[r][k] * ci[r][k];
-      den += s2 * nw;
-      float gr = 0.f, sbar = 0.f, dbar = 0.f;
-      if (valid && live[r]) {
-        gr = gsinr[((int64_t)kk * total_sc + gsc) * ns_max + r];
-        sbar = gr / den;
-        dbar = -gr * sv / (den * den);
-      }
-      nbar[r] = s2 * dbar;
-#pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        const float f = (k == r) ? 2.f * sbar : 2.f * dbar;
-        cbr[r][k] = (k < ns) ? f * cr[r][k] : 0.f;
-        cbi[r][k] = (k < ns) ? f * ci[r][k] : 0.f;
-      }
-    }
-    // Lambda = Q^{-1} (HV Cbar^H + 2 W diag(nbar)), column by column
-    float lamr[M][NS], lami[M][NS];
-#pragma unroll
-    for (int r = 0; r < NS; ++r) {
-      float xr[M], xi[M];
-#pragma unroll
-      for (int i = 0; i < M; ++i) {
-        float ar = 2.f * nbar[r] * wr[i][r], ai = 2.f * nbar[r] * wi[i][r];
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {  // hv[i][k] conj(cb[r][k])
-          ar += hvr[i][k] * cbr[r][k] + hvi[i][k] * cbi[r][k];
-          ai += hvi[i][k] * cbr[r][k] - hvr[i][k] * cbi[r][k];
-        }
-        xr[i] = ar;
-        xi[i] = ai;
-      }
-      solve(xr, xi);
-#pragma unroll
-      for (int i = 0; i < M; ++i) {
-        lamr[i][r] = xr[i];
-        lami[i][r] = xi[i];
-      }
-    }
-    // (Lambda^H HV)[r][k]
-    float lhr[NS][NS], lhi[NS][NS];
-#pragma unroll
-    for (int r = 0; r < NS; ++r)
-#pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        float ar = 0.f, ai = 0.f;
-#pragma unroll
-        for (int i = 0; i < M; ++i) {
-          ar += lamr[i][r] * hvr[i][k] + lami[i][r] * hvi[i][k];
-          ai += lamr[i][r] * hvi[i][k] - lami[i][r] * hvr[i][k];
-        }
-        lhr[r][k] = ar;
-        lhi[r][k] = ai;
-      }
-    // dl/dHV += W Cbar + Lambda - Lambda c - W (Lambda^H HV)
-#pragma unroll
-    for (int i = 0; i < M; ++i)
-#pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        float ar = lamr[i][k], ai = lami[i][k];
-#pragma unroll
-        for (int r = 0; r < NS; ++r) {
-          ar += wr[i][r] * cbr[r][k] - wi[i][r] * cbi[r][k];
-          ai += wr[i][r] * cbi[r][k] + wi[i][r] * cbr[r][k];
-          ar -= lamr[i][r] * cr[r][k] - lami[i][r] * ci[r][k];
-          ai -= lamr[i][r] * ci[r][k] + lami[i][r] * cr[r][k];
-          ar -= wr[i][r] * lhr[r][k] - wi[i][r] * lhi[r][k];
-          ai -= wr[i][r] * lhi[r][k] + wi[i][r] * lhr[r][k];
-        }
-        if (k < ns) {
-          gbr[i][k] += ar;
-          gbi[i][k] += ai;
-        }
-      }
-  }
-
-  // singular-vector stage: P = U^H dl/dHV (u_a = hv_a / sigma_a), kept-block D, then
-  // E = sum_{a,b} u_a D_ab sigma_b^{-1} u_b^H
-  float inv[NS];
-#pragma unroll
-  for (int a = 0; a < NS; ++a) inv[a] = live[a] ? 1.f / sig[a] : 0.f;
-  float pr[NS][NS], pi[NS][NS];
-#pragma unroll
-  for (int a = 0; a < NS; ++a)
-#pragma unroll
-    for (int b = 0; b < NS; ++b) {
-      float ar = 0.f, ai = 0.f;
-#pragma unroll
-      for (int i = 0; i < M; ++i) {  // conj(u_a[i]) gb[i][b]
-        ar += hvr[i][a] * gbr[i][b] + hvi[i][a] * gbi[i][b];
-        ai += hvr[i][a] * gbi[i][b] - hvi[i][a] * gbr[i][b];
-      }
-      pr[a][b] = ar * inv[a];
-      pi[a][b] = ai * inv[a];
-    }
-  const float lam1 = sig[0] * sig[0];
-  float dr[NS][NS], di[NS][NS];
-#pragma unroll
-  for (int a = 0; a < NS; ++a)
-#pragma unroll
-    for (int b = 0; b < NS; ++b) {
-      if (!live[a] || !live[b]) {
-        dr[a][b] = di[a][b] = 0.f;
-      } else if (a == b) {
-        dr[a][b] = pr[a][a];
-        di[a][b] = 0.f;
-      } else {
-        const float la = sig[a] * sig[a], lb = sig[b] * sig[b];
-        const float gap = lb - la;
-        if (__builtin_fabsf(gap) > 1.0e-5f * lam1) {
-          dr[a][b] = (lb * pr[a][b] - sig[a] * sig[b] * pr[b][a]) / gap;
-          di[a][b] = (lb * pi[a][b] + sig[a] * sig[b] * pi[b][a]) / gap;
-        } else {
-          dr[a][b] = di[a][b] = 0.f;
-        }
-      }
-    }
-  // E[i][k] = sum_{a,b} u_a[i] D_ab inv_b conj(u_b[k])
-  float er[M][M], ei[M][M];
-  {
-    float tr_[M][NS], ti_[M][NS];  // (U D)[i][b] inv_b
-#pragma unroll
-    for (int i = 0; i < M; ++i)
-#pragma unroll
-      for (int b = 0; b < NS; ++b) {
-        float ar = 0.f, ai = 0.f;
-#pragma unroll
-        for (int a = 0; a < NS; ++a) {
-          const float ur = hvr[i][a] * inv[a], ui = hvi[i][a] * inv[a];
-          ar += ur * dr[a][b] - ui * di[a][b];
-          ai += ur * di[a][b] + ui * dr[a][b];
-        }
-        tr_[i][b] = ar * inv[b];
-        ti_[i][b] = ai * inv[b];
-      }
-#pragma unroll
-    for (int i = 0; i < M; ++i)
-#pragma unroll
-      for (int k = 0; k < M; ++k) {
-        float ar = 0.f, ai = 0.f;
-#pragma unroll
-        for (int b = 0; b < NS; ++b) {  // t[i][b] conj(u_b[k])
-          const float ur = hvr[k][b] * inv[b], ui = hvi[k][b] * inv[b];
-          ar += tr_[i][b] * ur + ti_[i][b] * ui;
-          ai += ti_[i][b] * ur - tr_[i][b] * ui;
-        }
-        er[i][k] = ar;
-        ei[i][k] = ai;
-      }
-  }
-  if (valid) {
-    float2* gH = reinterpret_cast<float2*>(ws + ch.w_gH) + s * m * n;
-    for (int j = 0; j < n; ++j) {
-      float hr[M], hi[M];
-      ht_column<M>(Cs, Gg, pg, m, n, j, hr, hi);
-#pragma unroll
-      for (int i = 0; i < M; ++i) {
-        if (i < m) {
-          float ar = 0.f, ai = 0.f;
-#pragma unroll
-          for (int k = 0; k < M; ++k) {
-            ar += er[i][k] * hr[k] - ei[i][k] * hi[k];
-            ai += er[i][k] * hi[k] + ei[i][k] * hr[k];
-          }
-          gH[(int64_t)i * n + j] = make_float2(ar, ai);
-        }
-      }
-    }
-  }
-  if (valid && status && bits) atomicOr(reinterpret_cast<unsigned int*>(status + c), bits);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1343,16 +735,6 @@ static gt_status sinr_launch_t(const LaunchCtx& L, const ScRange& R, int64_t tot
   return GT_OK;
 }
 
-template <int M, int NS>
-static gt_status sinr_lane_t(const LaunchCtx& L, const ScRange& R, int64_t total_sc,
-                             const float2* C, const float2* G, const SnrArgs& a, float* out,
-                             int ns_max, int32_t* status) {
-  const unsigned grid = (unsigned)((R.count + 63) / 64);
-  GT_LAUNCH((k_sinr_lane<M, NS>), dim3(grid), dim3(64), L.d_chans, R, total_sc, C, G, a, out, ns_max,
-            status);
-  return GT_OK;
-}
-
 gt_status launch_sinr_rows(const LaunchCtx& L, int k0, int k1, int mp, int nsm, int64_t total_sc,
                            const float2* C, const float2* G, const float* s2, int n_snr,
                            float* out, int ns_max, int32_t* status);
@@ -1402,16 +784,6 @@ static gt_status sinr_bwd_t(const LaunchCtx& L, const ScRange& R, int64_t total_
   constexpr int SPB = 64 / MP;
   const unsigned grid = (unsigned)((R.count + SPB - 1) / SPB);
   GT_LAUNCH((k_sinr_bwd<float, MP, NMAX>), dim3(grid), dim3(64), L.d_chans, R, total_sc, C, G, a, gs,
-            ns_max, L.ws, status);
-  return GT_OK;
-}
-
-template <int M, int NS>
-static gt_status sinr_bwd_lane_t(const LaunchCtx& L, const ScRange& R, int64_t total_sc,
-                                 const float2* C, const float2* G, const SnrArgs& a, const float* gs,
-                                 int ns_max, int32_t* status) {
-  const unsigned grid = (unsigned)((R.count + 63) / 64);
-  GT_LAUNCH((k_sinr_bwd_lane<M, NS>), dim3(grid), dim3(64), L.d_chans, R, total_sc, C, G, a, gs,
             ns_max, L.ws, status);
   return GT_OK;
 }

@@ -21,451 +21,9 @@
 // subcarrier, so the long serial chain of each small eigenproblem overlaps with others.
 #include <hip/hip_runtime.h>
 
-#include "gt_device.h"
-#include "gt_internal.h"
+#include "gt_rows.h"
 
 namespace gt {
-
-struct RowsSnr {
-  float s2[kMaxSnr];
-  int n;
-};
-
-// Channels of a compact subcarrier range (channels ordered by SINR kernel class).
-struct RowsRange {
-  const int32_t* ch;
-  const int64_t* off;
-  int n;
-  int64_t base;
-  int64_t count;
-};
-
-__device__ __forceinline__ int rows_locate(const RowsRange& R, const DevChan* chans, int64_t i,
-                                           int64_t& gsc) {
-  const int64_t pos = R.base + i;
-  int lo = 0, hi = R.n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (R.off[mid] <= pos)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  const int c = R.ch[lo];
-  gsc = chans[c].sc + (pos - R.off[lo]);
-  return c;
-}
-
-// Value of lane (this lane xor T) within the same 32 lanes (ds_swizzle bitmask mode: and
-// mask 0x1F, xor mask T).
-template <int T>
-__device__ __forceinline__ float xswz(float v) {
-  static_assert(T > 0 && T < 32, "xor distance");
-  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x1F | (T << 10)));
-}
-
-template <int MP>
-__device__ __forceinline__ float rows_sum(float v) {
-  if (MP > 1) v += xswz<1>(v);
-  if (MP > 2) v += xswz<2>(v);
-  if (MP > 4) v += xswz<4>(v);
-  if (MP > 8) v += xswz<8>(v);
-  return v;
-}
-
-template <int MP>
-__device__ __forceinline__ uint32_t rows_or(uint32_t v) {
-  if (MP > 1) v |= (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (1 << 10));
-  if (MP > 2) v |= (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (2 << 10));
-  if (MP > 4) v |= (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (4 << 10));
-  if (MP > 8) v |= (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (8 << 10));
-  return v;
-}
-
-constexpr int kRowsChunk = 8;  // Ht columns staged per pass of the Gram
-
-template <int MP, int NS>
-struct RowsLds {
-  union {
-    float2 ht[MP][kRowsChunk];  // chunk of the Ht rows (Gram stage)
-    struct {
-      float2 hv[MP][NS];        // rows of HV = U_ns Sigma_ns
-      float2 l[MP][MP];         // rows of the Cholesky factor
-      float2 y[MP][NS];         // rows of the substitution results
-    } m;
-  } u;
-  float4 rot[MP];               // (c, Re s, Im s, -) of lane r's Jacobi pair in this step
-  float lam[MP];                // eigenvalues (K's diagonal after the sweeps)
-};
-
-// Jacobi rotation of the pair (p, q) zeroing K[p][q] = (kr, ki), with a = K[p][p] and
-// b = K[q][q]: rows p' = cs p + s q and q' = -conj(s) p + cs q, columns likewise from the right;
-// the new diagonal entries are a + tac and b - tac.  Identity when !live (a converged matrix) or
-// when the entry is already negligible.
-__device__ __forceinline__ void rows_rot_params(float a, float b, float kr, float ki, bool live,
-                                                float& cs, float& sr, float& si, float& tac) {
-  const float eps = 5.9604645e-08f;
-  const float ac = __builtin_sqrtf(kr * kr + ki * ki);
-  cs = 1.f;
-  sr = si = tac = 0.f;
-  if (live && ac > 0.f && ac > eps * 0.5f * (__builtin_fabsf(a) + __builtin_fabsf(b))) {
-    const float z = (b - a) / (2.f * ac);
-    const float az = __builtin_fabsf(z);
-    float tt = (az > 1.0e18f) ? 0.5f / az : 1.f / (az + __builtin_sqrtf(1.f + az * az));
-    if (z >= 0.f) tt = -tt;
-    cs = 1.f / __builtin_sqrtf(1.f + tt * tt);
-    const float sn = tt * cs;
-    sr = sn * kr / ac;
-    si = sn * ki / ac;
-    tac = tt * ac;
-  }
-}
-
-// Step T of a sweep: pair (r, r ^ T).  Rows (kr, ki) of K and (vr, vi) of V in this lane.
-template <int MP, int T>
-__device__ __forceinline__ void rows_jacobi_step(float4* rot, int r, bool live, float (&kr)[MP],
-                                                 float (&ki)[MP], float (&vr)[MP],
-                                                 float (&vi)[MP]) {
-  const int partner = r ^ T;
-  const bool lo = r < partner;
-  float d_me = 0.f, e_r = 0.f, e_i = 0.f;
-#pragma unroll
-  for (int j = 0; j < MP; ++j) {
-    d_me = (j == r) ? kr[j] : d_me;
-    e_r = (j == partner) ? kr[j] : e_r;
-    e_i = (j == partner) ? ki[j] : e_i;
-  }
-  const float d_pa = xswz<T>(d_me);
-  const float f_r = xswz<T>(e_r), f_i = xswz<T>(e_i);
-  // both lanes of the pair use K[p][p], K[q][q] and K[p][q] as the lower lane p holds them
-  const float a = lo ? d_me : d_pa, b = lo ? d_pa : d_me;
-  const float pr = lo ? e_r : f_r, pi = lo ? e_i : f_i;
-  float cs, sr, si, tac;
-  rows_rot_params(a, b, pr, pi, live, cs, sr, si, tac);
-  rot[r] = make_float4(cs, sr, si, 0.f);
-  wave_sync();
-  // K <- K J and V <- V J on the columns (j, j ^ T) of every pair, j < (j ^ T):
-  // column j' = c col_j + conj(s) col_jq, column jq' = -s col_j + c col_jq
-#pragma unroll
-  for (int j = 0; j < MP; ++j) {
-    constexpr int unused = 0;
-    (void)unused;
-    if (j < (j ^ T)) {
-      const int jq = j ^ T;
-      const float4 pj = rot[j];
-      const float c = pj.x, s_r = pj.y, s_i = pj.z;
-      float xr = kr[j], xi = ki[j], yr = kr[jq], yi = ki[jq];
-      kr[j] = c * xr + (s_r * yr + s_i * yi);
-      ki[j] = c * xi + (s_r * yi - s_i * yr);
-      kr[jq] = c * yr - (s_r * xr - s_i * xi);
-      ki[jq] = c * yi - (s_r * xi + s_i * xr);
-      xr = vr[j];
-      xi = vi[j];
-      yr = vr[jq];
-      yi = vi[jq];
-      vr[j] = c * xr + (s_r * yr + s_i * yi);
-      vi[j] = c * xi + (s_r * yi - s_i * yr);
-      vr[jq] = c * yr - (s_r * xr - s_i * xi);
-      vi[jq] = c * yi - (s_r * xi + s_i * xr);
-    }
-  }
-  // K <- J^H K: the lower lane takes cs x + s y, the upper one cs x - conj(s) y (y the
-  // partner's row after the column rotations)
-  const float tr = lo ? sr : -sr;
-#pragma unroll
-  for (int j = 0; j < MP; ++j) {
-    const float yr = xswz<T>(kr[j]), yi = xswz<T>(ki[j]);
-    kr[j] = cs * kr[j] + (tr * yr - si * yi);
-    ki[j] = cs * ki[j] + (tr * yi + si * yr);
-  }
-  if (tac != 0.f || sr != 0.f || si != 0.f) {
-#pragma unroll
-    for (int j = 0; j < MP; ++j) {
-      if (j == partner) {
-        kr[j] = 0.f;
-        ki[j] = 0.f;
-      }
-      if (j == r) {
-        kr[j] = lo ? a + tac : b - tac;
-        ki[j] = 0.f;
-      }
-    }
-  }
-  wave_sync();
-}
-
-template <int MP, int T>
-struct RowsSweep {
-  static __device__ __forceinline__ void run(float4* rot, int r, bool live, float (&kr)[MP],
-                                             float (&ki)[MP], float (&vr)[MP], float (&vi)[MP]) {
-    rows_jacobi_step<MP, T>(rot, r, live, kr, ki, vr, vi);
-    RowsSweep<MP, T + 1>::run(rot, r, live, kr, ki, vr, vi);
-  }
-};
-template <int MP>
-struct RowsSweep<MP, MP> {
-  static __device__ __forceinline__ void run(float4*, int, bool, float (&)[MP], float (&)[MP],
-                                             float (&)[MP], float (&)[MP]) {}
-};
-
-// ---- stages shared by the forward kernel and its adjoint ----------------------------------
-
-// Chunk [j0, j0 + kRowsChunk) of row r of Ht = sum_q C[s,q] G_g[q] (zero past n and for the
-// padding rows r >= m).
-template <int MP>
-__device__ __forceinline__ void rows_ht_chunk(bool row, int j0, int n, int pg,
-                                              const float2* __restrict__ Cs,
-                                              const float2* __restrict__ Gr, int64_t gq,
-                                              float (&hr)[kRowsChunk], float (&hi)[kRowsChunk]) {
-#pragma unroll
-  for (int jj = 0; jj < kRowsChunk; ++jj) hr[jj] = hi[jj] = 0.f;
-  for (int q = 0; q < pg; ++q) {
-    const float2 cq = Cs[q];
-    const float2* Gq = Gr + q * gq;
-#pragma unroll
-    for (int jj = 0; jj < kRowsChunk; ++jj) {
-      const int j = min(j0 + jj, n - 1);
-      const float2 gv = Gq[j];
-      hr[jj] += cq.x * gv.x - cq.y * gv.y;
-      hi[jj] += cq.x * gv.y + cq.y * gv.x;
-    }
-  }
-#pragma unroll
-  for (int jj = 0; jj < kRowsChunk; ++jj) {
-    const bool on = row && (j0 + jj < n);
-    hr[jj] = on ? hr[jj] : 0.f;
-    hi[jj] = on ? hi[jj] : 0.f;
-  }
-}
-
-// Row r of K = Ht Ht^H.
-template <int MP, int NS>
-__device__ __forceinline__ void rows_gram(RowsLds<MP, NS>& S, int r, bool row, int n, int pg,
-                                          const float2* __restrict__ Cs,
-                                          const float2* __restrict__ Gr, int64_t gq,
-                                          float (&kr)[MP], float (&ki)[MP]) {
-#pragma unroll
-  for (int j = 0; j < MP; ++j) kr[j] = ki[j] = 0.f;
-  for (int j0 = 0; j0 < n; j0 += kRowsChunk) {
-    float hr[kRowsChunk], hi[kRowsChunk];
-    rows_ht_chunk<MP>(row, j0, n, pg, Cs, Gr, gq, hr, hi);
-#pragma unroll
-    for (int jj = 0; jj < kRowsChunk; ++jj) S.u.ht[r][jj] = make_float2(hr[jj], hi[jj]);
-    wave_sync();
-#pragma unroll
-    for (int k = 0; k < MP; ++k) {
-#pragma unroll
-      for (int jj = 0; jj < kRowsChunk; jj += 2) {
-        const float4 b = *reinterpret_cast<const float4*>(&S.u.ht[k][jj]);
-        // h_r conj(h_k)
-        kr[k] += hr[jj] * b.x + hi[jj] * b.y + (hr[jj + 1] * b.z + hi[jj + 1] * b.w);
-        ki[k] += hi[jj] * b.x - hr[jj] * b.y + (hi[jj + 1] * b.z - hr[jj + 1] * b.w);
-      }
-    }
-    wave_sync();
-  }
-}
-
-// Jacobi sweeps on K until the off-diagonal part is below 2 eps of the diagonal (per matrix;
-// converged matrices take identity rotations while the others of the wave finish), at most 10.
-// Leaves the eigenvalues on K's diagonal and the eigenvectors in the columns of V (row r in
-// this lane).  Returns false if the sweep cap was reached.
-template <int MP>
-__device__ __forceinline__ bool rows_eig(float4* rot, int r, float (&kr)[MP], float (&ki)[MP],
-                                         float (&vr)[MP], float (&vi)[MP]) {
-#pragma unroll
-  for (int j = 0; j < MP; ++j) {
-    vr[j] = (j == r) ? 1.f : 0.f;
-    vi[j] = 0.f;
-  }
-  const float eps = 5.9604645e-08f;
-  for (int sw = 0; sw <= 10; ++sw) {
-    float off = 0.f, dg = 0.f;
-#pragma unroll
-    for (int j = 0; j < MP; ++j) {
-      const float v = kr[j] * kr[j] + ki[j] * ki[j];
-      if (j == r)
-        dg += v;
-      else
-        off += v;
-    }
-    off = rows_sum<MP>(off);
-    dg = rows_sum<MP>(dg);
-    const bool gdone = off <= 4.f * eps * eps * dg;  // the same in every lane of the group
-    if (__all(gdone ? 1 : 0)) return true;
-    if (sw == 10) return gdone;
-    RowsSweep<MP, 1>::run(rot, r, !gdone, kr, ki, vr, vi);
-  }
-  return false;
-}
-
-// Descending eigenvalues over the first m indices; singular values sig[k] and, in this lane,
-// row r of U_ns (ur, ui) and of HV = U_ns Sigma_ns (hvr, hvi), zero past ns and for padding
-// rows.  Publishes the HV rows to LDS.
-template <int MP, int NS>
-__device__ __forceinline__ void rows_hv(RowsLds<MP, NS>& S, int r, bool row, int ns,
-                                        const float (&kr)[MP], const float (&vr)[MP],
-                                        const float (&vi)[MP], float (&sig)[NS],
-                                        float (&ur)[NS], float (&ui)[NS], float (&hvr)[NS],
-                                        float (&hvi)[NS], uint32_t& bits) {
-  float lam_me = 0.f;
-#pragma unroll
-  for (int j = 0; j < MP; ++j) lam_me = (j == r) ? kr[j] : lam_me;
-  S.lam[r] = row ? lam_me : -3.0e38f;
-  wave_sync();
-  float lam[MP];
-#pragma unroll
-  for (int j = 0; j < MP; ++j) lam[j] = S.lam[j];
-  int src[NS];
-#pragma unroll
-  for (int k = 0; k < NS; ++k) src[k] = 0;
-#pragma unroll
-  for (int j = 0; j < MP; ++j) {
-    int rk = 0;
-#pragma unroll
-    for (int i = 0; i < MP; ++i) rk += (lam[i] > lam[j] || (lam[i] == lam[j] && i < j)) ? 1 : 0;
-#pragma unroll
-    for (int k = 0; k < NS; ++k) src[k] = (rk == k) ? j : src[k];
-  }
-#pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    float l = 0.f, a = 0.f, b = 0.f;
-#pragma unroll
-    for (int j = 0; j < MP; ++j) {
-      l = (src[k] == j) ? lam[j] : l;
-      a = (src[k] == j) ? vr[j] : a;
-      b = (src[k] == j) ? vi[j] : b;
-    }
-    sig[k] = __builtin_sqrtf(l > 0.f ? l : 0.f);
-    const bool on = row && k < ns;
-    ur[k] = on ? a : 0.f;
-    ui[k] = on ? b : 0.f;
-    hvr[k] = sig[k] * ur[k];
-    hvi[k] = sig[k] * ui[k];
-  }
-#pragma unroll
-  for (int k = 0; k < NS; ++k)
-    if (k < ns && !(sig[k] > 1.0e-3f * sig[0])) bits |= GT_DEV_ZERO_STREAM;
-#pragma unroll
-  for (int k = 0; k < NS; ++k) S.u.m.hv[r][k] = make_float2(hvr[k], hvi[k]);
-  wave_sync();
-}
-
-// Row r of the Cholesky factor of Q = HV HV^H + s2 I (padding rows: the identity), left-looking
-// with row c of L published to LDS at step c.  ok is false if this lane's pivot was not positive.
-template <int MP, int NS>
-__device__ __forceinline__ void rows_chol(RowsLds<MP, NS>& S, int r, bool row, float s2,
-                                          const float (&hvr)[NS], const float (&hvi)[NS],
-                                          float (&lr)[MP], float (&li)[MP], bool& ok) {
-#pragma unroll
-  for (int j = 0; j < MP; ++j) {
-    float ar = 0.f, ai = 0.f;
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {  // hv_r conj(hv_j)
-      const float2 h = S.u.m.hv[j][k];
-      ar += hvr[k] * h.x + hvi[k] * h.y;
-      ai += hvi[k] * h.x - hvr[k] * h.y;
-    }
-    lr[j] = row ? ar + ((j == r) ? s2 : 0.f) : ((j == r) ? 1.f : 0.f);
-    li[j] = row ? ai : 0.f;
-  }
-  ok = true;
-#pragma unroll
-  for (int cc = 0; cc < MP; ++cc) {
-    if (r == cc) {
-      float d = lr[cc];
-#pragma unroll
-      for (int k = 0; k < cc; ++k) d -= lr[k] * lr[k] + li[k] * li[k];
-      ok = d > 0.f;
-      lr[cc] = __builtin_sqrtf(d > 0.f ? d : 1.f);
-      li[cc] = 0.f;
-#pragma unroll
-      for (int k = 0; k <= cc; ++k) S.u.m.l[cc][k] = make_float2(lr[k], li[k]);
-    }
-    wave_sync();
-    if (r > cc) {
-      float ar = lr[cc], ai = li[cc];
-#pragma unroll
-      for (int k = 0; k < cc; ++k) {  // L[r][k] conj(L[cc][k])
-        const float2 y = S.u.m.l[cc][k];
-        ar -= lr[k] * y.x + li[k] * y.y;
-        ai -= li[k] * y.x - lr[k] * y.y;
-      }
-      const float inv = 1.f / S.u.m.l[cc][cc].x;
-      lr[cc] = ar * inv;
-      li[cc] = ai * inv;
-    }
-  }
-}
-
-// In place: row r of X <- row r of Q^{-1} X (NS columns) with Q = L L^H: forward substitution
-// (row i final at step i, published), then back substitution (row i final at step i,
-// descending; the rows j < i subtract conj(L[i][j]) x_i with L[i][j] from the published rows).
-template <int MP, int NS>
-__device__ __forceinline__ void rows_solve(RowsLds<MP, NS>& S, int r, const float (&lr)[MP],
-                                           const float (&li)[MP], float (&xr)[NS],
-                                           float (&xi)[NS]) {
-#pragma unroll
-  for (int i = 0; i < MP; ++i) {
-    if (r == i) {
-      const float inv = 1.f / lr[i];
-#pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        xr[k] *= inv;
-        xi[k] *= inv;
-        S.u.m.y[i][k] = make_float2(xr[k], xi[k]);
-      }
-    }
-    wave_sync();
-    if (r > i) {
-      const float ar = lr[i], ai = li[i];  // L[r][i]
-#pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        const float2 y = S.u.m.y[i][k];
-        xr[k] -= ar * y.x - ai * y.y;
-        xi[k] -= ar * y.y + ai * y.x;
-      }
-    }
-  }
-  wave_sync();
-#pragma unroll
-  for (int i = MP - 1; i >= 0; --i) {
-    if (r == i) {
-      const float inv = 1.f / lr[i];
-#pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        xr[k] *= inv;
-        xi[k] *= inv;
-        S.u.m.y[i][k] = make_float2(xr[k], xi[k]);
-      }
-    }
-    wave_sync();
-    if (r < i) {
-      const float2 l = S.u.m.l[i][r];
-#pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        const float2 w = S.u.m.y[i][k];
-        xr[k] -= l.x * w.x + l.y * w.y;
-        xi[k] -= l.x * w.y - l.y * w.x;
-      }
-    }
-  }
-  wave_sync();
-}
-
-// P[j][k] = sum over the group's rows i of conj(A[i][j]) B[i][k] (the same in every lane).
-template <int MP, int NS>
-__device__ __forceinline__ void rows_inner(const float (&ar)[NS], const float (&ai)[NS],
-                                           const float (&br)[NS], const float (&bi)[NS],
-                                           float (&pr)[NS][NS], float (&pi)[NS][NS]) {
-#pragma unroll
-  for (int j = 0; j < NS; ++j)
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      pr[j][k] = rows_sum<MP>(ar[j] * br[k] + ai[j] * bi[k]);
-      pi[j][k] = rows_sum<MP>(ar[j] * bi[k] - ai[j] * br[k]);
-    }
-}
 
 // Compressed-channel SINR for channels with m <= MP and ns <= NS, 256 / MP subcarriers per
 // block of 256 lanes.
@@ -476,9 +34,9 @@ __global__ void __launch_bounds__(256) k_sinr_rows(const DevChan* __restrict__ c
                                                     float* __restrict__ out, int ns_max,
                                                     int32_t* status) {
   constexpr int SPB = 256 / MP;
-  __shared__ RowsLds<MP, NS> lds[SPB];
+  __shared__ RowsLds<MP, NS, 16> lds[SPB];
   const int sub = threadIdx.x / MP, r = threadIdx.x % MP;
-  RowsLds<MP, NS>& S = lds[sub];
+  RowsLds<MP, NS, 16>& S = lds[sub];
   const int64_t it = (int64_t)blockIdx.x * SPB + sub;
   const bool valid = it < R.count;
   int64_t gsc = 0;
@@ -754,7 +312,7 @@ __global__ void __launch_bounds__(256) k_sinr_bwd_rows(const DevChan* __restrict
   float2* gH = reinterpret_cast<float2*>(ws + ch.w_gH) + (s * ch.m + rr) * ch.n;
   for (int j0 = 0; j0 < n; j0 += kRowsChunk) {
     float hr[kRowsChunk], hi[kRowsChunk];
-    rows_ht_chunk<MP>(row, j0, n, pg, Cs, Gr, gq, hr, hi);
+    rows_ht_chunk<MP, kRowsChunk>(row, j0, n, pg, Cs, Gr, gq, hr, hi);
 #pragma unroll
     for (int jj = 0; jj < kRowsChunk; ++jj) S.u.ht[r][jj] = make_float2(hr[jj], hi[jj]);
     wave_sync();

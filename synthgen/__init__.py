@@ -18,4 +18,6 @@ from .channels import (  # noqa: F401
     planted_tucker,
     heterogeneous_batch,
     snr_to_sigma2,
+    system_links,
+    make_system,
 )

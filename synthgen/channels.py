@@ -195,6 +195,23 @@ def heterogeneous_batch(n_channels: int = 512, seed_index: int = 3) -> List[dict
     return out
 
 
+def system_links(J: int, K: int) -> List[tuple]:
+    """Links (u, k) of a system of J base stations with K UEs per cell, UE u = i K + j served by
+    BS i, in the order the channels of a system plan are laid out (UE-major)."""
+    return [(u, k) for u in range(J * K) for k in range(J)]
+
+
+def make_system(J: int, K: int, nr: int, nt: int, nsc: int, n_paths: int, k_db: float,
+                seed_index: int = 5) -> dict:
+    """Channel tensors [nsc][nr][nt] of every link (u, k) of a J-cell system, each from its own
+    seeded paths (child seed = the link's position in system_links)."""
+    out = {}
+    for idx, lk in enumerate(system_links(J, K)):
+        pp = draw_paths(channel_rng(seed_index, idx), n_paths, k_db)
+        out[lk] = build_channel(pp, nr, nt, nsc)
+    return out
+
+
 def snr_to_sigma2(snr_db: Sequence[float]) -> np.ndarray:
     """Noise variance for unit average channel gain and unit power per stream."""
     return 10.0 ** (-np.asarray(snr_db, dtype=np.float64) / 10.0)

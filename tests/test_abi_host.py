@@ -209,3 +209,54 @@ def test_api_checks_every_buffer():
     p128 = api.Plan([d], iters=2, device="cpu", dtype="c128")
     with pytest.raises(TypeError, match="complex128"):
         p128.sinr(C_, G, [0.1])
+
+
+def _plan_descs(lib, descs):
+    arr = (B.ChannelDesc * len(descs))(*[B.ChannelDesc(*d) for d in descs])
+    opt = B.FitOptions(3, 0, 0, 0, 0)
+    h = C.c_void_p()
+    return lib.gt_plan_create(arr, len(descs), C.byref(opt), C.byref(h)), h
+
+
+def test_sharing_labels_are_validated(lib):
+    base = (4, 16, 24, 8, 2, 4, 3, 2)
+    # channels that share A must agree on (nr, m); those that share B on (nt, n)
+    assert _plan_descs(lib, [base + (1, 0, 0), (6, 16, 24, 8, 2, 4, 3, 2, 1, 0, 0)])[0] == 2
+    assert _plan_descs(lib, [base + (0, 1, 0), (4, 32, 24, 8, 2, 4, 3, 2, 0, 1, 0)])[0] == 2
+    assert _plan_descs(lib, [base + (0, 1, 0), (4, 16, 24, 8, 2, 5, 3, 2, 0, 1, 0)])[0] == 2
+    # labels must be >= 0 and the serving flag 0 or 1
+    assert _plan_descs(lib, [base + (-1, 0, 0)])[0] == 1
+    assert _plan_descs(lib, [base + (0, 0, 2)])[0] == 1
+    st, h = _plan_descs(lib, [base + (1, 0, 0), (4, 32, 24, 8, 2, 6, 3, 2, 1, 0, 0)])
+    assert st == 0
+    wsb = C.c_size_t()
+    lib.gt_plan_workspace_bytes(h, C.byref(wsb))
+    dummy = C.c_void_p(1 << 20)
+    # a plan that shares factors provides no objective trace: refused before any launch
+    assert lib.gt_tucker_fit(h, dummy, dummy, dummy, dummy, dummy, dummy, None, dummy,
+                             wsb.value, None) == 5
+    # and it is not a multi-cell system (unlabelled BSs, no serving links)
+    s2 = (C.c_float * 1)(0.1)
+    assert lib.gt_sinr_eval_system(h, dummy, dummy, s2, 1, 1, dummy, None, dummy, wsb.value,
+                                   None) == 1
+    lib.gt_plan_destroy(h)
+
+
+def test_system_plan_detection(lib):
+    # 2 BSs x 1 UE: links (u, k) labelled a_id = u + 1, b_id = k + 1, serving where k == u
+    d = lambda u, k, serving: (4, 16, 24, 8, 2, 4, 3, 2, u + 1, k + 1, serving)  # noqa: E731
+    st, h = _plan_descs(lib, [d(0, 0, 1), d(0, 1, 0), d(1, 0, 0), d(1, 1, 1)])
+    assert st == 0
+    wsb = C.c_size_t()
+    lib.gt_plan_workspace_bytes(h, C.byref(wsb))
+    dummy = C.c_void_p(1 << 20)
+    s2 = (C.c_float * 1)(0.1)
+    assert lib.gt_sinr_eval_system(h, dummy, dummy, s2, 1, 3, dummy, None, dummy, wsb.value,
+                                   None) == 1      # unknown interference mode
+    lib.gt_plan_destroy(h)
+    # two serving links for one UE: not a system
+    st, h = _plan_descs(lib, [d(0, 0, 1), d(0, 1, 1), d(1, 0, 0), d(1, 1, 1)])
+    assert st == 0
+    assert lib.gt_sinr_eval_system(h, dummy, dummy, s2, 1, 1, dummy, None, dummy, wsb.value,
+                                   None) == 1
+    lib.gt_plan_destroy(h)
