@@ -229,6 +229,108 @@ def copy_calibration(mib: int) -> None:
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "copies": 3}))
 
 
+def time_models(api, synthgen, torch, dev, reps=5):
+    """The paper's three compression models on a synthetic multi-cell system (the layout of its
+    table of compression results): 3 base stations with 2 UEs each, links of 8 x 64 x 624
+    (8 paths, K 6 dB), groups of 12, ranks (8, 16, 6), 20 sweeps, 2 streams at 10 dB with the
+    paper's inter-cell protocol.  Per model: R_s (equation "compression ratio" for this
+    structure), R_t = SINR time of the uncompressed channels / SINR time from the compressed form
+    (both on this GPU; the Individual model's factors do not cancel, so its SINR runs on the
+    reconstructed channels), e_c (equation "SINR error"); then a rank sweep of the groupwise
+    model (R_s and e_c against n and p)."""
+    import numpy as np
+
+    J, K, nr, nt, nsc, gs = 3, 2, 8, 64, 624, 12
+    m, n, p, ns, iters = 8, 16, 6, 2, 20
+    s2 = [0.1]
+    links = synthgen.system_links(J, K)
+    Xs = synthgen.make_system(J, K, nr, nt, nsc, 8, 6.0)
+
+    def descs(mm, nn, gg, pp, model):
+        out = []
+        for u, k in links:
+            if model == "individual":
+                a, b = 0, 0
+            elif model == "shared":
+                a, b = 1, 1
+            else:
+                a, b = u + 1, k + 1
+            out.append(dict(nr=nr, nt=nt, nsc=nsc, group_size=gg, m=mm, n=nn, p=pp, ns=ns, a_id=a,
+                            b_id=b, serving=int(u // K == k and model == "groupwise")))
+        return out
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            out = fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ts.sort()
+        return ts[len(ts) // 2], out
+
+    def ue_values(plan, out):
+        o = out.cpu().numpy()
+        vals = []
+        for c, (u, k) in enumerate(links):
+            if u // K == k:
+                sc = plan.offsets(c).sc
+                vals.append(o[:, sc:sc + nsc, :ns].astype(np.float64))
+        return np.stack(vals)
+
+    exact = api.Plan(descs(nr, nt, 1, 1, "groupwise"), iters=1)
+    X = torch.cat([torch.as_tensor(Xs[lk].reshape(-1), dtype=torch.complex64) for lk in links]).to(dev)
+    ones = torch.ones(exact.totals.c, dtype=torch.complex64, device=dev)
+    ms_full, out_full = timed(lambda: exact.sinr_system(ones, X, s2, mode="paper"))
+    full = ue_values(exact, out_full)
+    sysplan = api.Plan(descs(m, n, gs, p, "groupwise"), iters=iters)
+    ng = -(-nsc // gs)
+    per_link = sum(m * n * min(p, min(gs, nsc - g * gs)) + min(gs, nsc - g * gs) * min(p, gs)
+                   for g in range(ng))
+    orig = J * J * K * nr * nt * nsc
+    stored = {"individual": J * J * K * (per_link + nr * m + nt * n),
+              "shared": J * J * K * per_link + nr * m + nt * n,
+              "groupwise": J * J * K * per_link + J * K * nr * m + J * nt * n}
+    res = {}
+    for model in ("individual", "shared", "groupwise"):
+        fplan = api.Plan(descs(m, n, gs, p, model), iters=iters)
+        f = fplan.empty_factors()
+        ms_fit, r = timed(lambda: fplan.fit(X, factors=f, trace=False))
+        if model == "individual":
+            def comp_fn():
+                _, xh = fplan.reconstruct(f["A"], f["B"], f["C"], f["G"], ht=False, xhat=True)
+                return exact.sinr_system(ones, xh, s2, mode="paper")
+            ms_sinr, out = timed(comp_fn)
+            comp = ue_values(exact, out)
+        else:
+            ms_sinr, out = timed(lambda: sysplan.sinr_system(f["C"], f["G"], s2, mode="paper"))
+            comp = ue_values(sysplan, out)
+        res[model] = dict(R_s=orig / stored[model], R_t=ms_full / ms_sinr,
+                          e_c=float(np.mean(np.abs((full - comp) / full))),
+                          ms_fit=ms_fit, ms_sinr=ms_sinr, status_ok=bool((r["status"] == 0).all()))
+        del fplan, f
+    sweep = []
+    for nn, pp in ((4, 3), (8, 3), (8, 6), (16, 6), (16, 12), (32, 12)):
+        plan = api.Plan(descs(m, nn, gs, pp, "groupwise"), iters=iters)
+        f = plan.empty_factors()
+        plan.fit(X, factors=f, trace=False)
+        comp = ue_values(plan, plan.sinr_system(f["C"], f["G"], s2, mode="paper"))
+        pl = sum(m * nn * min(pp, min(gs, nsc - g * gs)) + min(gs, nsc - g * gs) * min(pp, gs)
+                 for g in range(ng))
+        sweep.append(dict(m=m, n=nn, p=pp, R_s=orig / (J * J * K * pl + J * K * nr * m + J * nt * nn),
+                          e_c=float(np.mean(np.abs((full - comp) / full)))))
+        del plan, f
+    return dict(workload="3 BS x 2 UE, 18 links of 8 x 64 x 624 (8 paths, K 6 dB), groups of 12, "
+                         "ranks (8, 16, 6), 20 sweeps, Ns 2 at 10 dB, inter-cell from the first UE "
+                         "of each other cell", ms_sinr_uncompressed=ms_full, models=res,
+                rank_sweep_groupwise=sweep)
+
+
 def time_forms(api, synthgen, cfg, X, B, s2, ms_fp32, sg_fp32, torch, steps):
     """The precision, batched (graph replay) and differentiation forms on the same GPU:
     throughput of fit + SINR (eager FP32 first, as the reference) and SINR error against the
@@ -680,6 +782,7 @@ def main():
     forms = None
     if not args.no_forms and not wide and not args.steps_only:
         forms = time_forms(api, synthgen, cfg, X, B, s2, ms_step, sg, torch, max(args.steps, 2))
+        forms["compression_models"] = time_models(api, synthgen, torch, dev)
 
     line = {
         "metric": "subcarrier SINR evals/sec + Tucker fits/sec at <=0.1 dB err vs FP64 oracle",
