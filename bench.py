@@ -95,9 +95,15 @@ def measured_traffic(kernel: str, workload: str = "rb273"):
     src = fields.get("source")
     if not src or "traffic_bytes_per_launch" not in fields:
         return None
-    with open(os.path.join(ROOT, src), "rb") as fh:
-        if hashlib.sha256(fh.read()).hexdigest() != fields.get("source_sha256"):
-            return None
+    # one or more source files (comma-separated) with their hashes in the same order
+    files = [f.strip() for f in src.split(",")]
+    hashes = [h.strip() for h in fields.get("source_sha256", "").split(",")]
+    if len(files) != len(hashes):
+        return None
+    for f, h in zip(files, hashes):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != h:
+                return None
     return float(fields["traffic_bytes_per_launch"])
 
 
