@@ -108,7 +108,7 @@ def measured_traffic(kernel: str, workload: str = "rb273"):
 
 
 KERNEL_NAMES = [
-    "k_eigA", "k_eigB", "k_eigC", "k_gram_rows", "k_reduce_S1", "k_reduce_S2", "k_reduce_S2_mfma",
+    "k_eigA", "k_eigB", "k_eigC", "k_eigA_rows", "k_eigC_rows", "k_gram_rows", "k_reduce_S1", "k_reduce_S2", "k_reduce_S2_mfma",
     "k_init_group", "k_init_group_lds", "k_stepA_group", "k_S3", "k_core", "k_objC", "k_trace",
     "k_norm_total", "k_fused_t", "k_fused_t_mfma", "k_fused_z", "k_fused_b", "k_fused_b_mfma",
     "k_fused_b_mm", "k_eigB_sub", "k_sub_prod", "k_sub_rr", "k_sub_rot", "k_rows_times_b",
@@ -624,7 +624,7 @@ def main():
     if not args.steps_only:
         plan.set_tuning(bstep=0, tpass=0, split=0)
         kern_unsplit = profile_steps(api, lambda: plan.fit(X, factors=f, trace=False), 1)
-        plan.set_tuning(bstep=0, tpass=0, split=1)
+        plan.set_tuning(bstep=0, tpass=0, split=2)
     torch.cuda.synchronize()
 
     fits_per_s = B * args.steps / (ms_total / 1e3)
@@ -701,7 +701,8 @@ def main():
             avg_us=t_pass["avg_us"], algorithmic_flops_per_launch=t_flops,
             achieved_tflops=t_flops / (t_pass["avg_us"] * 1e-6) / 1e12,
             frac_mfma_fp32=t_flops / (t_pass["avg_us"] * 1e-6) / 1e12 / PEAK_FP32_TFLOPS)
-    for nm in ("k_eigA", "k_eigB", "k_eigC", "k_fused_z", "k_reduce_S1", "k_reduce_S2_mfma"):
+    for nm in ("k_eigA", "k_eigA_rows", "k_eigB", "k_eigC", "k_eigC_rows", "k_fused_z",
+               "k_reduce_S1", "k_reduce_S2_mfma"):
         if nm in kern_unsplit:
             fit_parts[nm + "_unsplit"] = dict(avg_us=kern_unsplit[nm]["avg_us"],
                                               launches_per_fit=kern_unsplit[nm]["launches"],

@@ -244,7 +244,10 @@ gt_status gt_tucker_reconstruct_backward(const gt_plan* plan, const void* A, con
  *   bstep  B-step pass: 0 matrix-core kernel, 1 the same with the next group's operands
  *          prefetched during the current group's Gram, 2 the older matrix-core kernel;
  *   tpass  T pass: 0 matrix cores, 1 vector ALU;
- *   split  fits of 8 or more channels split over concurrent streams: 0 off, 1 on.
+ *   split  fits of 8 or more channels split into parts on concurrent streams: 0 off, 1 the
+ *          B-step pass over the whole batch and the rest of each sweep per part, 2 every part
+ *          runs whole sweeps on its own stream (pipelined: one part's matrix-core passes
+ *          overlap another's eigensolves).  The results are the same in every mode.
  * Each configuration is timed as the faster of two fits of min(iters, 8) sweeps after an
  * untimed one, and a choice replaces the current one only when it is more than 2 % faster.
  * Choices that do not apply to the plan (no fused passes, 16-bit contractions for the

@@ -172,7 +172,7 @@ class Plan:
             _ptr(self.ws), self.ws_bytes, _stream(), C.byref(res)))
         return dict(bstep=res.bstep, tpass=res.tpass, split=res.split, probe_ms=res.probe_ms)
 
-    def set_tuning(self, bstep: int = 0, tpass: int = 0, split: int = 1) -> None:
+    def set_tuning(self, bstep: int = 0, tpass: int = 0, split: int = 2) -> None:
         """Sets the fit's pass variants (the choices autotune makes)."""
         check("gt_plan_set_tuning", self.lib.gt_plan_set_tuning(self._h, bstep, tpass, split))
 

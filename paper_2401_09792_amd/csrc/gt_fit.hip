@@ -14,6 +14,7 @@
 
 #include "gt_device.h"
 #include "gt_internal.h"
+#include "gt_rows.h"
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -487,6 +488,93 @@ __global__ void __launch_bounds__(64, (sizeof(T) == 4 && MP == 16) ? 2 : 1) k_ei
   }
 }
 
+// FP32 register-row variants of the two kernels above (MP lanes per matrix, row r of the Gram
+// and of the eigenvector matrix in lane r; Jacobi pairs r with r xor t, as in the SINR kernels):
+// the same outputs, warm starts and convergence test (squared off-diagonal norm below 64 eps^2
+// times the squared diagonal norm, at most 12 sweeps) without the LDS round trips of every
+// rotation step.
+
+// mode-1: one MP-lane group per channel (nr <= MP)
+template <int MP>
+__global__ void __launch_bounds__(64) k_eigA_rows(const DevChan* __restrict__ chans, int n_channels,
+                                                  char* ws, float2* A, int32_t* status, int warm) {
+  constexpr int GPW = 64 / MP;
+  __shared__ RowsEigLds<MP> lds[GPW];
+  const int grp = threadIdx.x / MP, r = threadIdx.x % MP;
+  const int c = blockIdx.x * GPW + grp;
+  RowsEigLds<MP>& S = lds[grp];
+  const bool live = c < n_channels;
+  const DevChan* chp = live ? &chans[c] : nullptr;
+  const int d = live ? chp->nr : 0;
+  float kr[MP], ki[MP], vr[MP], vi[MP];
+  const float2* Sg = live ? wsp(ws, chp->w_S1) : nullptr;
+  const float2* VA = live ? wsp(ws, chp->w_VA) : nullptr;
+#pragma unroll
+  for (int j = 0; j < MP; ++j) {
+    float2 v = make_float2(0.f, 0.f);
+    if (r < d && j < d) v = Sg[(int64_t)r * d + j];
+    kr[j] = v.x;
+    ki[j] = v.y;
+    float2 b = make_float2(j == r ? 1.f : 0.f, 0.f);
+    if (live && warm) b = VA[r * MP + j];
+    vr[j] = b.x;
+    vi[j] = b.y;
+  }
+  if (warm) rows_warm<MP>(S, r, kr, ki, vr, vi);
+  const bool conv = rows_eig<MP>(S.rot, r, kr, ki, vr, vi, true, 64.f, 12);
+  if (live) {
+    float2* VAw = wsp(ws, chp->w_VA);
+#pragma unroll
+    for (int j = 0; j < MP; ++j) VAw[r * MP + j] = make_float2(vr[j], vi[j]);
+  }
+  rows_eig_finish<MP>(S, r, live, d, live ? chp->m : 0, live ? A + chp->a : nullptr,
+                      live ? chp->m : 0, live ? chp->m : 0,
+                      live ? wsd(ws, chp->w_scal) + 1 : nullptr, live && status ? status + c : nullptr,
+                      conv, kr, vr, vi);
+}
+
+// mode-3: one 16-lane group per subcarrier group of up to 16 subcarriers
+__global__ void __launch_bounds__(64) k_eigC_rows(const DevChan* __restrict__ chans,
+                                                  const GroupItem* __restrict__ items,
+                                                  int total_groups, char* ws, float2* C,
+                                                  int32_t* status, int warm) {
+  constexpr int MP = 16, GPW = 4;
+  __shared__ RowsEigLds<MP> lds[GPW];
+  const int grp = threadIdx.x / MP, r = threadIdx.x % MP;
+  const int gi = blockIdx.x * GPW + grp;
+  RowsEigLds<MP>& S = lds[grp];
+  const bool live = gi < total_groups;
+  GroupItem it{0, 0};
+  if (live) it = items[gi];
+  const DevChan& ch = chans[it.ch];
+  const int s0 = it.g * ch.gs;
+  const int d = live ? min(ch.gs, ch.nsc - s0) : 0;
+  const float2* Sg = wsp(ws, ch.w_S3) + (int64_t)it.g * ch.gs * ch.gs;
+  float2* VC = wsp(ws, ch.w_VC) + (int64_t)it.g * MP * MP;
+  float kr[MP], ki[MP], vr[MP], vi[MP];
+#pragma unroll
+  for (int j = 0; j < MP; ++j) {
+    float2 v = make_float2(0.f, 0.f);
+    if (r < d && j < d) v = Sg[r * ch.gs + j];
+    kr[j] = v.x;
+    ki[j] = v.y;
+    float2 b = make_float2(j == r ? 1.f : 0.f, 0.f);
+    if (live && warm) b = VC[r * MP + j];
+    vr[j] = b.x;
+    vi[j] = b.y;
+  }
+  if (warm) rows_warm<MP>(S, r, kr, ki, vr, vi);
+  const bool conv = rows_eig<MP>(S.rot, r, kr, ki, vr, vi, true, 64.f, 12);
+  if (live) {
+#pragma unroll
+    for (int j = 0; j < MP; ++j) VC[r * MP + j] = make_float2(vr[j], vi[j]);
+  }
+  const int pg = min(ch.p, d);
+  rows_eig_finish<MP>(S, r, live, d, pg, C + ch.c + (int64_t)s0 * ch.p, ch.p, ch.p,
+                      wsd(ws, ch.w_lamg) + it.g, live && status ? status + it.ch : nullptr, conv,
+                      kr, vr, vi);
+}
+
 // ---------------------------------------------------------------------------------------
 // Mode-n products of the sweep.
 
@@ -759,8 +847,15 @@ static gt_status eig_all(const LaunchCtx& L, int which, float2* A, float2* B, fl
               L.ws);
     gt_status st = launch_share_gram(L, 0);
     if (st != GT_OK) return st;
-    GT_LAUNCH((k_eigA<T, 16>), dim3(cdiv(L.n_channels, 4)), dim3(64), L.d_chans, L.n_channels,
-              L.ws, A, status, warm);
+    if (sizeof(T) == 4 && L.max_nr <= 8)
+      GT_LAUNCH((k_eigA_rows<8>), dim3(cdiv(L.n_channels, 8)), dim3(64), L.d_chans, L.n_channels,
+                L.ws, A, status, warm);
+    else if (sizeof(T) == 4)
+      GT_LAUNCH((k_eigA_rows<16>), dim3(cdiv(L.n_channels, 4)), dim3(64), L.d_chans,
+                L.n_channels, L.ws, A, status, warm);
+    else
+      GT_LAUNCH((k_eigA<T, 16>), dim3(cdiv(L.n_channels, 4)), dim3(64), L.d_chans, L.n_channels,
+                L.ws, A, status, warm);
   } else if (which == 1) {
     gt_status sst = launch_share_gram(L, 1);
     if (sst != GT_OK) return sst;
@@ -774,7 +869,10 @@ static gt_status eig_all(const LaunchCtx& L, int which, float2* A, float2* B, fl
   } else {
     // groups of up to 16 subcarriers on 16-lane solvers, larger ones on 32-lane solvers
     const int ns = L.n_small_groups, nl = L.total_groups - L.n_small_groups;
-    if (ns > 0)
+    if (ns > 0 && sizeof(T) == 4)
+      GT_LAUNCH(k_eigC_rows, dim3(cdiv(ns, 4)), dim3(64), L.d_chans, L.d_groups_by_size, ns,
+                L.ws, C, status, warm);
+    else if (ns > 0)
       GT_LAUNCH((k_eigC<T, 16>), dim3(cdiv(ns, 4)), dim3(64), L.d_chans, L.d_groups_by_size, ns,
                 L.ws, C, status, warm);
     if (nl > 0)
@@ -867,8 +965,23 @@ gt_status launch_fit(const LaunchCtx& L, const SplitCtx* split, const float2* X,
     // per sweep: eigA, [W + Gram], eigB, [T, Yh, S3], eigC, [Z + S1 or cores]; the first
     // A-step Gram comes from [T] and [Z] with the starting factors
     gt_status st;
-    if ((st = launch_fused_t(L, X, A, B, 0)) != GT_OK) return st;
-    if ((st = launch_fused_z(L, C, G, iters > 0 ? 1 : 0, 0)) != GT_OK) return st;
+    // With m == nr in every channel A is square and unitary once an eigensolve has made it,
+    // so the B- and C-step Grams do not depend on it (W^H W = Hc^H A A^H Hc = Hc^H Hc, and
+    // likewise for Yh): only the last A-step, whose A the outputs and cores use, runs (and the
+    // first one when A comes from the caller), unless the objective trace asks for every
+    // half-step.
+    const bool skip_a = L.full_mode1 && !trace;
+    auto a_step = [&](int na) { return !skip_a || na == iters - 1 || (warm && na == 0); };
+    // T pass of sweep it: T is stored only for a following A-step; channels with m == nr take
+    // the mode-3 Gram of T
+    auto t_flags = [&](int it) {
+      const bool last = it == iters - 1;
+      return (last ? 2 : 1) | ((!last && a_step(it + 1)) ? 0 : T_NO_STORE) | T_GRAM_OF_T;
+    };
+    if (iters == 0 || a_step(0)) {
+      if ((st = launch_fused_t(L, X, A, B, 0)) != GT_OK) return st;
+      if ((st = launch_fused_z(L, C, G, iters > 0 ? 1 : 0, 0)) != GT_OK) return st;
+    }
     if (iters == 0) {
       if ((st = launch_fused_t(L, X, A, B, 2)) != GT_OK) return st;
       return launch_fused_z(L, C, G, 0, 1);
@@ -893,16 +1006,18 @@ gt_status launch_fit(const LaunchCtx& L, const SplitCtx* split, const float2* X,
             if (pt)
               GT_LAUNCH2(P, k_trace, dim3(cdiv(pn, 64)), dim3(64), P.d_chans, pn, P.ws, pt,
                          stride, 2 + 3 * it, 1);
-            if ((s2 = launch_fused_t(P, X, A, B, last ? 2 : 1)) != GT_OK) return s2;
+            if ((s2 = launch_fused_t(P, X, A, B, t_flags(it))) != GT_OK) return s2;
             if ((s2 = eig_dispatch(P, 2, A, B, C, ps, w)) != GT_OK) return s2;
             if (pt)
               GT_LAUNCH2(P, k_trace, dim3(cdiv(pn, 64)), dim3(64), P.d_chans, pn, P.ws, pt,
                          stride, 3 + 3 * it, 2);
-            if ((s2 = launch_fused_z(P, C, G, last ? 0 : 1, last ? 1 : 0)) != GT_OK) return s2;
+            const int za = (!last && a_step(it + 1)) ? 1 : 0;
+            if ((za || last) && (s2 = launch_fused_z(P, C, G, za, last ? 1 : 0)) != GT_OK)
+              return s2;
           }
           // mode-1 eigensolve of the next sweep (of sweep 0 when called before the loop)
           const int na = with_bc ? it + 1 : 0;
-          if (na < iters) {
+          if (na < iters && a_step(na)) {
             const int wa = (warm && na == 0) ? 0 : 1;
             if ((s2 = eig_dispatch(P, 0, A, B, C, ps, wa)) != GT_OK) return s2;
             if (pt)
@@ -912,6 +1027,51 @@ gt_status launch_fit(const LaunchCtx& L, const SplitCtx* split, const float2* X,
         }
         return split_join(L, *split);
       };
+      if (split->mode == 2) {
+        // pipelined parts: every part runs its own sweeps, B-step included, so that one part's
+        // matrix-core passes overlap another part's eigensolves; the parts only meet at the end
+        if ((st = split_fork(L, *split)) != GT_OK) return st;
+        for (int it = -1; it < iters; ++it) {
+          for (int k = 0; k < split->n; ++k) {
+            const LaunchCtx& P = split->parts[k];
+            const int pn = P.n_channels;
+            int32_t* ps = status ? status + P.c0 : nullptr;
+            double* pt = trace ? trace + (int64_t)P.c0 * stride : nullptr;
+            const int w = (warm && it <= 0) ? 0 : 1;
+            if (it >= 0) {
+              const bool last = it == iters - 1;
+              if (it == 0 && k > 0 &&
+                  hipStreamWaitEvent(P.stream, split->stag[k - 1], 0) != hipSuccess)
+                return GT_ERR_HIP;
+              if ((st = launch_fused_b(P, X, A, C)) != GT_OK) return st;
+              if (it == 0 && k + 1 < split->n &&
+                  hipEventRecord(split->stag[k], P.stream) != hipSuccess)
+                return GT_ERR_HIP;
+              if ((st = eig_dispatch(P, 1, A, B, C, ps, w)) != GT_OK) return st;
+              if (pt)
+                GT_LAUNCH2(P, k_trace, dim3(cdiv(pn, 64)), dim3(64), P.d_chans, pn, P.ws, pt,
+                           stride, 2 + 3 * it, 1);
+              if ((st = launch_fused_t(P, X, A, B, t_flags(it))) != GT_OK) return st;
+              if ((st = eig_dispatch(P, 2, A, B, C, ps, w)) != GT_OK) return st;
+              if (pt)
+                GT_LAUNCH2(P, k_trace, dim3(cdiv(pn, 64)), dim3(64), P.d_chans, pn, P.ws, pt,
+                           stride, 3 + 3 * it, 2);
+              const int za = (!last && a_step(it + 1)) ? 1 : 0;
+              if ((za || last) && (st = launch_fused_z(P, C, G, za, last ? 1 : 0)) != GT_OK)
+                return st;
+            }
+            const int na = it + 1;  // mode-1 eigensolve of the next sweep
+            if (na < iters && a_step(na)) {
+              const int wa = (warm && na == 0) ? 0 : 1;
+              if ((st = eig_dispatch(P, 0, A, B, C, ps, wa)) != GT_OK) return st;
+              if (pt)
+                GT_LAUNCH2(P, k_trace, dim3(cdiv(pn, 64)), dim3(64), P.d_chans, pn, P.ws, pt,
+                           stride, 1 + 3 * na, 0);
+            }
+          }
+        }
+        return split_join(L, *split);
+      }
       if ((st = part_sweep(0, false)) != GT_OK) return st;
       for (int it = 0; it < iters; ++it) {
         if ((st = launch_fused_b(L, X, A, C)) != GT_OK) return st;
@@ -921,7 +1081,7 @@ gt_status launch_fit(const LaunchCtx& L, const SplitCtx* split, const float2* X,
     }
     for (int it = 0; it < iters; ++it) {
       const int w = (warm && it == 0) ? 0 : 1;
-      if ((st = eig_dispatch(L, 0, A, B, C, status, w)) != GT_OK) return st;
+      if (a_step(it) && (st = eig_dispatch(L, 0, A, B, C, status, w)) != GT_OK) return st;
       if (trace)
         GT_LAUNCH(k_trace, dim3(cdiv(nch, 64)), dim3(64), L.d_chans, nch, L.ws, trace, stride,
                   1 + 3 * it, 0);
@@ -932,12 +1092,13 @@ gt_status launch_fit(const LaunchCtx& L, const SplitCtx* split, const float2* X,
                   2 + 3 * it, 1);
       const bool last = it == iters - 1;
       // the C-step pass of the last sweep also keeps Yh for the cores
-      if ((st = launch_fused_t(L, X, A, B, last ? 2 : 1)) != GT_OK) return st;
+      if ((st = launch_fused_t(L, X, A, B, t_flags(it))) != GT_OK) return st;
       if ((st = eig_dispatch(L, 2, A, B, C, status, w)) != GT_OK) return st;
       if (trace)
         GT_LAUNCH(k_trace, dim3(cdiv(nch, 64)), dim3(64), L.d_chans, nch, L.ws, trace, stride,
                   3 + 3 * it, 2);
-      if ((st = launch_fused_z(L, C, G, last ? 0 : 1, last ? 1 : 0)) != GT_OK) return st;
+      const int za = (!last && a_step(it + 1)) ? 1 : 0;
+      if ((za || last) && (st = launch_fused_z(L, C, G, za, last ? 1 : 0)) != GT_OK) return st;
     }
     return GT_OK;
   }

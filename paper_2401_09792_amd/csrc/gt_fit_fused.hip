@@ -151,10 +151,12 @@ __device__ __forceinline__ void fused_t_finish(const DevChan& ch, const GroupIte
                                                f32x16 (&acc)[TPW], int wave, int half, int col,
                                                int tid) {
   const int nr = ch.nr, m = ch.m, n = ch.n;
+  const int mode = do_c & T_MODE;
   // accumulator element (row 8 (r / 4) + 4 half + r % 4, column col) of tile -> T
   float2* Tg = wsp2(ws, ch.w_T) + (int64_t)s0 * nr * n;
   float* Tsf = reinterpret_cast<float*>(Ts);
   float* Tgf = reinterpret_cast<float*>(Tg);
+  const bool keep_t = (do_c & T_NO_STORE) == 0;
 #pragma unroll
   for (int u = 0; u < TPW; ++u) {
     const int tile = wave + 4 * u;
@@ -166,16 +168,24 @@ __device__ __forceinline__ void fused_t_finish(const DevChan& ch, const GroupIte
         const int row = tile * 32 + 8 * (r / 4) + 4 * half + (r % 4);
         if (row < rows) {
           Tsf[2 * (row * n + c) + part] = acc[u][r];
-          Tgf[2 * (row * n + c) + part] = acc[u][r];
+          if (keep_t) Tgf[2 * (row * n + c) + part] = acc[u][r];
         }
       }
     }
   }
-  if (!do_c) return;
+  if (!mode) return;
   __syncthreads();
   float2* Yg = wsp2(ws, ch.w_Yh) + (int64_t)s0 * m * n;
   const int ys = m * n + 2;  // LDS stride of Yh_s (complex): consecutive subcarriers 4 banks apart
-  if (m <= 8 && n <= 16 && nr <= 16) {
+  if ((do_c & T_GRAM_OF_T) && mode == 1 && m == nr) {
+    // A square and unitary: <Yh_s, Yh_t> = <T_s, T_t>, so the Gram is taken of T itself
+    // (copied to the padded Yh layout) and Yh is not formed
+    const int mn = m * n;
+    for (int e = tid; e < sz * mn; e += 256) {
+      const int s = e / mn;
+      Yh[s * ys + (e - s * mn)] = Ts[e];
+    }
+  } else if (m <= 8 && n <= 16 && nr <= 16) {
     // Yh_s = A^H T_s on 16 x 16 x 4 matrix cores, one subcarrier per wave at a time: rows
     // (a, re/im), columns b, K = (i, re/im) in steps of 4 (lane l: row / column l % 16,
     // k' = 4 t + l / 16); the A operand is the sign-arranged real form of A^H
@@ -209,7 +219,7 @@ __device__ __forceinline__ void fused_t_finish(const DevChan& ch, const GroupIte
         if (a < m && r16 < n) {
           const int o = 2 * ((s * m + a) * n + r16) + (row & 1);
           Yhf[2 * s * ys + o - 2 * s * m * n] = acc4[r];
-          if (do_c == 2) Ygf[o] = acc4[r];
+          if (mode == 2) Ygf[o] = acc4[r];
         }
       }
     }
@@ -233,7 +243,7 @@ __device__ __forceinline__ void fused_t_finish(const DevChan& ch, const GroupIte
         }
         const int o = (s * m + a) * n + b;
         Yh[s * ys + a * n + b] = make_float2(yr, yi);
-        if (do_c == 2) Yg[o] = make_float2(yr, yi);
+        if (mode == 2) Yg[o] = make_float2(yr, yi);
       }
     }
   }
@@ -985,6 +995,20 @@ __device__ __forceinline__ void bmm_prefetch_lp(uint2 (&xq)[PREC == 3 ? 2 : 1][(
   }
 }
 
+// Step-1 output (re, im) of Hc_q at column c = i nt + j into the q slot: interleaved for step 2,
+// or, when step 2 is skipped (m == nr), in the layout step 2 would write (real parts of the m
+// rows of 64 columns, then the imaginary parts).
+__device__ __forceinline__ void bmm_store_hc(float* slot, int c, int nt, int m, bool skip2,
+                                             float re, float im) {
+  if (skip2) {
+    const int i = c / nt, j = c - i * nt;
+    slot[i * 64 + j] = re;
+    slot[m * 64 + i * 64 + j] = im;
+  } else {
+    *reinterpret_cast<float2*>(slot + 2 * c) = make_float2(re, im);
+  }
+}
+
 // PF: the next group's step-1 operands are loaded while the current group's steps 2 and 3
 // run (more registers, one block per CU); otherwise they are loaded at the start of step 1
 // and latency is hidden by a second resident block.  SLC: the per-q LDS slot stride in
@@ -1012,7 +1036,18 @@ __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* _
   // holds row l % 16 = (a, re/im) and k' = 4 t + l / 16 = (i, re/im).  Otherwise 32 x 32 x 2:
   // lane l at K step i holds row l % 32 = (a, re/im) and k = (i, l / 32).
   const bool w16 = m <= 8;
-  for (int e = tid; e < nr * 64; e += 512) {
+  // m == nr: A is square and unitary (every B-step follows an eigensolve of the mode-1 Gram),
+  // so W_q^H W_q = Hc_q^H A A^H Hc_q = Hc_q^H Hc_q: step 1 writes Hc in the layout step 3
+  // reads and step 2 is skipped
+  const bool skip2 = m == nr;
+  if (skip2 && nt < 64) {  // the Gram reads 64 columns; those past nt stay zero
+    const int per = 2 * m * 64;
+    for (int e = tid; e < (SLC ? 16 : p) * per; e += 512) {
+      const int q = e / per, o = e - q * per;
+      if ((o & 63) >= nt) smf[q * SL + o] = 0.f;
+    }
+  }
+  for (int e = tid; e < (skip2 ? 0 : nr * 64); e += 512) {
     const int st = e / 64, l = e % 64;
     int a, part, i, kp;
     if (w16) {
@@ -1080,8 +1115,7 @@ __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* _
 #pragma unroll
           for (int r = 0; r < 16; r += 2) {
             const int q = 4 * (r / 4) + 2 * h + ((r % 4) >> 1);
-            if (SLC || q < pg)
-              *reinterpret_cast<float2*>(smf + q * SL + 2 * c) = make_float2(acc1[r], acc1[r + 1]);
+            if (SLC || q < pg) bmm_store_hc(smf + q * SL, c, nt, m, skip2, acc1[r], acc1[r + 1]);
           }
       }
     } else {
@@ -1104,15 +1138,15 @@ __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* _
 #pragma unroll
           for (int r = 0; r < 16; r += 2) {
             const int q = 4 * (r / 4) + 2 * h + ((r % 4) >> 1);
-            if (SLC || q < pg)
-              *reinterpret_cast<float2*>(smf + q * SL + 2 * c) = make_float2(acc1[r], acc1[r + 1]);
+            if (SLC || q < pg) bmm_store_hc(smf + q * SL, c, nt, m, skip2, acc1[r], acc1[r + 1]);
           }
       }
     }
     if (PF && g + 1 < g1) bmm_prefetch<NT1W, SMAX>(xp, cp, X, C, ch, g + 1, nrnt, wave, col, h);
     }
     __syncthreads();
-    // 2. W_q = A^H Hc_q, in place
+    // 2. W_q = A^H Hc_q, in place (skipped for m == nr)
+    if (!skip2) {
     // both column tiles are read before either is written back; loads are unconditional
     // (clamped) and out-of-range operands are zeroed by selects, four K steps per batch
     if (w16) {
@@ -1208,6 +1242,7 @@ __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* _
         }
     }
     __syncthreads();
+    }
     // 3. Gram over the rows (q, a) of W, q < p_g, two rows a0 + h of one q per step (an
     // odd m pads each q with a zero row); two steps per batch, loads unconditional
     {
@@ -2085,7 +2120,7 @@ gt_status launch_fused_t(const LaunchCtx& L, const float2* X, const float2* A, c
     return GT_OK;
   }
   GT_LAUNCH_SH(k_fused_t, dim3(L.total_groups), dim3(256), t_bytes(L), L.d_chans, L.d_groups, X, A, B,
-               L.ws, do_c);
+               L.ws, do_c & T_MODE);
   return GT_OK;
 }
 

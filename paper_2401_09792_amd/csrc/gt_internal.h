@@ -106,6 +106,9 @@ struct LaunchCtx {
   int n_small_groups;         // groups of size <= 16
   int max_nr, max_nt, max_nsc, max_gs, max_m, max_n, max_p, max_ns, max_groups, max_nsplit;
   int min_nt;
+  // every channel has m == nr: A is square and unitary, so A A^H = I and the B- and C-step
+  // Grams do not depend on it (the fit then runs only the last A-step, see launch_fit)
+  int full_mode1 = 0;
   int eig_fp64;
   int ttm_prec;  // gt_ttm_prec of the plan
   int c0 = 0;    // first channel of this context in the caller's channel numbering
@@ -127,6 +130,13 @@ struct LaunchCtx {
   const int32_t* d_sys_serving = nullptr;
 };
 
+// Bits of the T pass's do_c argument: the mode (0 = T only; 1 = also the group's mode-3 Gram;
+// 2 = as 1 and Yh to the workspace for the cores), T_NO_STORE (T is not stored to the
+// workspace: no A-step reads it) and T_GRAM_OF_T (a channel with m == nr has a square unitary
+// A, so its Gram may be taken of T instead of Yh = A^H T).  The vector-ALU kernel uses the mode
+// only.
+constexpr int T_MODE = 3, T_NO_STORE = 4, T_GRAM_OF_T = 8;
+
 // A fit whose batch is split into parts of consecutive channels: the parts' contexts (their
 // own tables over the same per-channel workspace, part 0 on the caller's stream) and the
 // events that fork the side streams from the caller's stream and join them back.
@@ -135,6 +145,11 @@ struct SplitCtx {
   const LaunchCtx* parts;
   hipEvent_t fork;
   hipEvent_t join[3];
+  // 1: the B-step pass runs over the whole batch and the parts meet after every sweep;
+  // 2: every part runs whole sweeps on its own stream, part k starting its first B-step after
+  //    part k-1's (stag[k-1])
+  int mode;
+  hipEvent_t stag[3];
 };
 
 // kernel timing hooks (no-ops unless profiling is on)

@@ -99,6 +99,7 @@ struct gt_plan {
   gt_offsets totals;
   int ns_max;
   int max_nr, max_nt, max_nsc, max_gs, max_m, max_n, max_p, max_ns, max_groups, max_nsplit;
+  int full_mode1 = 1;  // every channel keeps its full mode-1 rank (m == nr)
   int min_nt;
   std::vector<GroupItem> groups_by_size;
   int n_small_groups;
@@ -122,8 +123,9 @@ struct gt_plan {
   bool side_tried = false, side_ok = false;
   hipStream_t side[3] = {nullptr, nullptr, nullptr};
   hipEvent_t ev_fork = nullptr, ev_join[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev_stag[3] = {nullptr, nullptr, nullptr};
   // pass variants chosen by gt_plan_autotune
-  int tune_bstep = 0, tune_tpass = 0, tune_split = 1;
+  int tune_bstep = 0, tune_tpass = 0, tune_split = 2;
   // compact layout of the SINR adjoint's scratch alone (tables and dl/dHt), for the entry point
   // that runs in the library's static scratch array; sblob holds its table bytes
   WsLayout slay{};
@@ -145,6 +147,8 @@ gt_plan::~gt_plan() {
   for (hipStream_t& st : side)
     if (st) (void)hipStreamDestroy(st);
   if (ev_fork) (void)hipEventDestroy(ev_fork);
+  for (hipEvent_t& e : ev_stag)
+    if (e) (void)hipEventDestroy(e);
   for (hipEvent_t& e : ev_join)
     if (e) (void)hipEventDestroy(e);
 }
@@ -259,6 +263,7 @@ static gt_status plan_build(const gt_channel_desc* descs, int32_t n_channels,
     p->max_nsc = std::max(p->max_nsc, d.nsc);
     p->max_gs = std::max(p->max_gs, d.group_size);
     p->max_m = std::max(p->max_m, d.m);
+    if (d.m != d.nr) p->full_mode1 = 0;
     p->max_n = std::max(p->max_n, d.n);
     p->max_p = std::max(p->max_p, d.p);
     p->max_ns = std::max(p->max_ns, d.ns);
@@ -571,6 +576,7 @@ static gt_status plan_build(const gt_channel_desc* descs, int32_t n_channels,
       v->max_nsc = p->max_nsc;
       v->max_gs = p->max_gs;
       v->max_m = p->max_m;
+      v->full_mode1 = p->full_mode1;
       v->max_n = p->max_n;
       v->max_p = p->max_p;
       v->max_ns = p->max_ns;
@@ -660,6 +666,7 @@ static LaunchCtx make_ctx_at(const gt_plan* p, const WsLayout& lay, void* ws, vo
   L.max_nsc = p->max_nsc;
   L.max_gs = p->max_gs;
   L.max_m = p->max_m;
+  L.full_mode1 = p->full_mode1;
   L.max_n = p->max_n;
   L.max_p = p->max_p;
   L.max_ns = p->max_ns;
@@ -710,7 +717,8 @@ static bool side_ready(gt_plan* p) {
   bool ok = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) == hipSuccess;
   for (size_t i = 0; ok && i < ns; ++i)
     ok = hipStreamCreateWithFlags(&p->side[i], hipStreamNonBlocking) == hipSuccess &&
-         hipEventCreateWithFlags(&p->ev_join[i], hipEventDisableTiming) == hipSuccess;
+         hipEventCreateWithFlags(&p->ev_join[i], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&p->ev_stag[i], hipEventDisableTiming) == hipSuccess;
   p->side_ok = ok;
   return ok;
 }
@@ -731,12 +739,16 @@ static gt_status run_fit(const gt_plan* plan, const void* X, void* A, void* B, v
   S.n = (int)plan->parts.size();
   S.parts = P;
   S.fork = mp->ev_fork;
+  S.mode = plan->tune_split;
   for (int k = 0; k < S.n; ++k) {
     P[k] = make_ctx(plan->parts[k], ws, k == 0 ? stream : (void*)mp->side[k - 1]);
     P[k].c0 = plan->part_c0[k];
     P[k].tune_bstep = plan->tune_bstep;
     P[k].tune_tpass = plan->tune_tpass;
-    if (k > 0) S.join[k - 1] = mp->ev_join[k - 1];
+    if (k > 0) {
+      S.join[k - 1] = mp->ev_join[k - 1];
+      S.stag[k - 1] = mp->ev_stag[k - 1];
+    }
   }
   return launch_fit(L, &S, (const float2*)X, (float2*)A, (float2*)B, (float2*)C, (float2*)G,
                     obj_trace, dev_status, iters, warm);
@@ -759,7 +771,7 @@ gt_status gt_tucker_fit(const gt_plan* plan, const void* X, void* A, void* B, vo
 }
 
 gt_status gt_plan_set_tuning(gt_plan* plan, int32_t bstep, int32_t tpass, int32_t split) {
-  if (!plan || bstep < 0 || bstep > 2 || tpass < 0 || tpass > 1 || split < 0 || split > 1)
+  if (!plan || bstep < 0 || bstep > 2 || tpass < 0 || tpass > 1 || split < 0 || split > 2)
     return GT_ERR_ARG;
   // the prefetching and the older B-step kernels and the vector-ALU T pass are FP32-only: on a
   // 16-bit plan they would run the contraction on the FP32 X
@@ -817,7 +829,7 @@ gt_status gt_plan_autotune(gt_plan* plan, const void* X, void* A, void* B, void*
   if (fused) {
     knobs.push_back({&plan->tune_bstep, L0.ttm_prec == GT_TTM_FP32 ? 3 : 1});
     knobs.push_back({&plan->tune_tpass, L0.ttm_prec == GT_TTM_FP32 ? 2 : 1});
-    if (!plan->parts.empty()) knobs.push_back({&plan->tune_split, 2});
+    if (!plan->parts.empty()) knobs.push_back({&plan->tune_split, 3});
   }
   for (const Knob& k : knobs) {
     if (rc != GT_OK) break;

@@ -184,6 +184,11 @@ __device__ __forceinline__ void rows_jacobi_step(float4* rot, int r, bool live, 
     }
   }
   wave_sync();
+  // V's rotations feed nothing but later rotations of V, so the compiler would otherwise sink
+  // them to the end of the sweep and keep every step's (c, s) live (about 3 MP/2 registers per
+  // step); an empty asm that takes and returns the rows makes each step's V final here.
+#pragma unroll
+  for (int j = 0; j < MP; ++j) asm volatile("" : "+v"(vr[j]), "+v"(vi[j]));
 }
 
 template <int MP, int T>
@@ -258,20 +263,25 @@ __device__ __forceinline__ void rows_gram(RowsLds<MP, NS, CH>& S, int r, bool ro
   }
 }
 
-// Jacobi sweeps on K until the off-diagonal part is below 2 eps of the diagonal (per matrix;
-// converged matrices take identity rotations while the others of the wave finish), at most 10.
-// Leaves the eigenvalues on K's diagonal and the eigenvectors in the columns of V (row r in
-// this lane).  Returns false if the sweep cap was reached.
+// Jacobi sweeps on K until the squared off-diagonal norm is below tol eps^2 times the squared
+// diagonal norm (per matrix; converged matrices take identity rotations while the others of the
+// wave finish), at most max_sweeps.  V starts as the identity, or, with preset, as the basis the
+// caller holds in (vr, vi); the rotations accumulate onto it.  Leaves the eigenvalues on K's
+// diagonal and the eigenvectors in the columns of V (row r in this lane).  Returns false if
+// the sweep cap was reached.
 template <int MP>
 __device__ __forceinline__ bool rows_eig(float4* rot, int r, float (&kr)[MP], float (&ki)[MP],
-                                         float (&vr)[MP], float (&vi)[MP]) {
+                                         float (&vr)[MP], float (&vi)[MP], bool preset = false,
+                                         float tol = 4.f, int max_sweeps = 10) {
+  if (!preset) {
 #pragma unroll
-  for (int j = 0; j < MP; ++j) {
-    vr[j] = (j == r) ? 1.f : 0.f;
-    vi[j] = 0.f;
+    for (int j = 0; j < MP; ++j) {
+      vr[j] = (j == r) ? 1.f : 0.f;
+      vi[j] = 0.f;
+    }
   }
   const float eps = 5.9604645e-08f;
-  for (int sw = 0; sw <= 10; ++sw) {
+  for (int sw = 0; sw <= max_sweeps; ++sw) {
     float off = 0.f, dg = 0.f;
 #pragma unroll
     for (int j = 0; j < MP; ++j) {
@@ -283,9 +293,9 @@ __device__ __forceinline__ bool rows_eig(float4* rot, int r, float (&kr)[MP], fl
     }
     off = rows_sum<MP>(off);
     dg = rows_sum<MP>(dg);
-    const bool gdone = off <= 4.f * eps * eps * dg;  // the same in every lane of the group
+    const bool gdone = off <= tol * eps * eps * dg;  // the same in every lane of the group
     if (__all(gdone ? 1 : 0)) return true;
-    if (sw == 10) return gdone;
+    if (sw == max_sweeps) return gdone;
     RowsSweep<MP, 1>::run(rot, r, !gdone, kr, ki, vr, vi);
   }
   return false;
@@ -465,6 +475,177 @@ __device__ __forceinline__ void rows_inner(const float (&ar)[NS], const float (&
       pr[j][k] = rows_sum<MP>(ar[j] * br[k] + ai[j] * bi[k]);
       pi[j][k] = rows_sum<MP>(ar[j] * bi[k] - ai[j] * br[k]);
     }
+}
+
+// ---- Hermitian eigensolves of the fit (mode-1 and mode-3 Grams) -----------------------------
+
+template <int MP>
+struct RowsEigLds {
+  float2 w0[MP][MP];  // published rows of V, then of V after re-orthonormalisation
+  float2 w1[MP][MP];  // published rows of V^H V, then of K V
+  float4 rot[MP];
+  float lam[MP];
+  int src[MP];
+};
+
+template <int MP>
+__device__ __forceinline__ void rows_put(float2 (*W)[MP], int r, const float (&xr)[MP],
+                                         const float (&xi)[MP]) {
+#pragma unroll
+  for (int j = 0; j < MP; j += 2)
+    *reinterpret_cast<float4*>(&W[r][j]) = make_float4(xr[j], xi[j], xr[j + 1], xi[j + 1]);
+}
+
+// Row r of X^H Y for X, Y published in LDS: sum_k conj(X[k][r]) Y[k][j].
+template <int MP>
+__device__ __forceinline__ void rows_ah_b(const float2 (*X)[MP], const float2 (*Y)[MP], int r,
+                                          float (&o_r)[MP], float (&o_i)[MP]) {
+#pragma unroll
+  for (int j = 0; j < MP; ++j) o_r[j] = o_i[j] = 0.f;
+#pragma unroll
+  for (int k = 0; k < MP; ++k) {
+    const float2 a = X[k][r];
+#pragma unroll
+    for (int j = 0; j < MP; j += 2) {
+      const float4 b = *reinterpret_cast<const float4*>(&Y[k][j]);
+      o_r[j] += a.x * b.x + a.y * b.y;
+      o_i[j] += a.x * b.y - a.y * b.x;
+      o_r[j + 1] += a.x * b.z + a.y * b.w;
+      o_i[j + 1] += a.x * b.w - a.y * b.z;
+    }
+  }
+}
+
+// Row r of A Y with row r of A in registers and Y published in LDS: sum_k A[r][k] Y[k][j].
+template <int MP>
+__device__ __forceinline__ void rows_a_b(const float (&ar)[MP], const float (&ai)[MP],
+                                         const float2 (*Y)[MP], float (&o_r)[MP],
+                                         float (&o_i)[MP]) {
+#pragma unroll
+  for (int j = 0; j < MP; ++j) o_r[j] = o_i[j] = 0.f;
+#pragma unroll
+  for (int k = 0; k < MP; ++k) {
+    const float xr = ar[k], xi = ai[k];
+#pragma unroll
+    for (int j = 0; j < MP; j += 2) {
+      const float4 b = *reinterpret_cast<const float4*>(&Y[k][j]);
+      o_r[j] += xr * b.x - xi * b.y;
+      o_i[j] += xr * b.y + xi * b.x;
+      o_r[j + 1] += xr * b.z - xi * b.w;
+      o_i[j + 1] += xr * b.w + xi * b.z;
+    }
+  }
+}
+
+// Warm start of a Jacobi eigensolve from the basis V of an earlier solve on the same Gram
+// family: one Newton-Schulz step V <- V (3 I - V^H V) / 2 restores orthonormality lost to FP32
+// rounding, then K <- V^H K V, so that only the change since the earlier solve is left for the
+// sweeps (which then run with preset = true and accumulate onto V).
+template <int MP>
+__device__ __forceinline__ void rows_warm(RowsEigLds<MP>& S, int r, float (&kr)[MP],
+                                          float (&ki)[MP], float (&vr)[MP], float (&vi)[MP]) {
+  float tr[MP], ti[MP], er[MP], ei[MP];
+  rows_put<MP>(S.w0, r, vr, vi);
+  wave_sync();
+  rows_ah_b<MP>(S.w0, S.w0, r, er, ei);  // E = V^H V
+  rows_put<MP>(S.w1, r, er, ei);
+  wave_sync();
+  rows_a_b<MP>(vr, vi, S.w1, tr, ti);  // V E
+#pragma unroll
+  for (int j = 0; j < MP; ++j) {
+    vr[j] = 1.5f * vr[j] - 0.5f * tr[j];
+    vi[j] = 1.5f * vi[j] - 0.5f * ti[j];
+  }
+  rows_put<MP>(S.w0, r, vr, vi);  // every read of the old V ended before E was published
+  wave_sync();
+  rows_a_b<MP>(kr, ki, S.w0, tr, ti);  // K V
+  rows_put<MP>(S.w1, r, tr, ti);      // every read of E ended before V was republished
+  wave_sync();
+  rows_ah_b<MP>(S.w0, S.w1, r, kr, ki);  // V^H (K V)
+  wave_sync();
+}
+
+// Lane (of the group) holding the largest m (lowest index on ties), with its (a, b).
+template <int MP>
+__device__ __forceinline__ void rows_argmax(float& m, int& idx, float& a, float& b) {
+#define GT_ROWS_MAXSTEP(T)                                         \
+  if (MP > T) {                                                    \
+    const float om = xswz<T>(m), oa = xswz<T>(a), ob = xswz<T>(b); \
+    const int oi = __builtin_amdgcn_ds_swizzle(idx, 0x1F | (T << 10)); \
+    if (om > m || (om == m && oi < idx)) {                         \
+      m = om;                                                      \
+      idx = oi;                                                    \
+      a = oa;                                                      \
+      b = ob;                                                      \
+    }                                                              \
+  }
+  GT_ROWS_MAXSTEP(8)
+  GT_ROWS_MAXSTEP(4)
+  GT_ROWS_MAXSTEP(2)
+  GT_ROWS_MAXSTEP(1)
+#undef GT_ROWS_MAXSTEP
+}
+
+// Output of an eigensolve: the rk eigenvectors of the largest eigenvalues among the first d
+// indices, descending (lowest index on ties), each with the phase that makes its
+// largest-modulus entry (lowest row on ties) real positive, into rows r < d of dst (leading
+// dimension ld); columns rk .. rpad-1 are zeroed.  lamsum (if not NULL) receives the sum of
+// the rk eigenvalues in double; status (if not NULL) gets GT_DEV_EIG_SWEEPS when the sweeps
+// did not converge and GT_DEV_NONFINITE for a non-finite sum.  live: this group holds a matrix.
+template <int MP>
+__device__ __forceinline__ void rows_eig_finish(RowsEigLds<MP>& S, int r, bool live, int d, int rk,
+                                                float2* dst, int ld, int rpad, double* lamsum,
+                                                int32_t* status, bool conv, const float (&kr)[MP],
+                                                const float (&vr)[MP], const float (&vi)[MP]) {
+  float me = 0.f;
+#pragma unroll
+  for (int j = 0; j < MP; ++j) me = (j == r) ? kr[j] : me;
+  S.lam[r] = (r < d) ? me : -__builtin_huge_valf();
+  wave_sync();
+  {
+    const float mine = S.lam[r];
+    int rank = 0;
+#pragma unroll
+    for (int j = 0; j < MP; ++j) {
+      const float o = S.lam[j];
+      rank += (o > mine || (o == mine && j < r)) ? 1 : 0;
+    }
+    S.src[rank] = r;
+  }
+  wave_sync();
+  double ls = 0.0;
+  for (int jo = 0; jo < rpad; ++jo) {
+    if (jo < rk) {
+      const int col = S.src[jo] & (MP - 1);
+      float a = 0.f, b = 0.f;
+#pragma unroll
+      for (int j = 0; j < MP; ++j) {
+        a = (j == col) ? vr[j] : a;
+        b = (j == col) ? vi[j] : b;
+      }
+      float m = (r < d) ? a * a + b * b : -1.f, pa = a, pb = b;
+      int idx = r;
+      rows_argmax<MP>(m, idx, pa, pb);
+      const float mod = __builtin_sqrtf(pa * pa + pb * pb);
+      float phr = 1.f, phi = 0.f;
+      if (mod > 0.f) {
+        phr = pa / mod;
+        phi = -pb / mod;
+      }
+      if (live && r < d) dst[(int64_t)r * ld + jo] = make_float2(a * phr - b * phi, a * phi + b * phr);
+      ls += (double)S.lam[col];
+    } else if (live && r < d) {
+      dst[(int64_t)r * ld + jo] = make_float2(0.f, 0.f);
+    }
+  }
+  if (live && r == 0) {
+    if (lamsum) *lamsum = ls;
+    if (status) {
+      uint32_t bits = conv ? 0u : GT_DEV_EIG_SWEEPS;
+      if (!(ls == ls) || ls > 1e300 || ls < -1e300) bits |= GT_DEV_NONFINITE;
+      if (bits) atomicOr(reinterpret_cast<unsigned int*>(status), bits);
+    }
+  }
 }
 
 }  // namespace gt

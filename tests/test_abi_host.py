@@ -129,9 +129,9 @@ def test_status_strings(lib):
 def test_set_tuning_validation(lib):
     st, h = _plan(lib, [(8, 64, 240, 12, 8, 16, 12, 4)] * 16)
     assert st == 0
-    for v in ((0, 0, 0), (1, 1, 1), (2, 0, 1)):
+    for v in ((0, 0, 0), (1, 1, 1), (2, 0, 1), (0, 0, 2)):
         assert lib.gt_plan_set_tuning(h, *v) == 0, v
-    for v in ((3, 0, 0), (-1, 0, 0), (0, 2, 0), (0, 0, 2)):
+    for v in ((3, 0, 0), (-1, 0, 0), (0, 2, 0), (0, 0, 3)):
         assert lib.gt_plan_set_tuning(h, *v) == 1, v   # GT_ERR_ARG
     lib.gt_plan_destroy(h)
 

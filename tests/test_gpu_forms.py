@@ -12,14 +12,16 @@ from tests.gpu_util import announce, desc, dev_c64, host
 pytestmark = pytest.mark.gpu
 
 
-def test_fit_and_sinr_graph_replay(gpu_lib):
-    # eight 8 x 64 x 3276 channels (a batch the fit splits over concurrent streams): eager run,
-    # then a captured graph replayed three times with eager work in between; every replay must
-    # reproduce the eager outputs bit for bit
+@pytest.mark.parametrize("split", [1, 2])
+def test_fit_and_sinr_graph_replay(gpu_lib, split):
+    # eight 8 x 64 x 3276 channels (a batch the fit splits over concurrent streams, in both split
+    # modes): eager run, then a captured graph replayed three times with eager work in between;
+    # every replay must reproduce the eager outputs bit for bit
     cfg = synthgen.CONFIGS["rb273"]
-    announce("graph capture fit + sinr, 8 x rb273")
+    announce(f"graph capture fit + sinr, 8 x rb273, split mode {split}")
     X = torch.cat([dev_c64(synthgen.make_channel(cfg, c)) for c in range(8)])
     plan = gpu_lib.Plan([gpu_lib.desc_from_config(cfg)] * 8, iters=cfg.iters)
+    plan.set_tuning(split=split)
     s2 = [float(v) for v in synthgen.snr_to_sigma2(cfg.snr_db)]
     f_eager = plan.empty_factors()
     r = plan.fit(X, factors=f_eager, trace=False)
@@ -134,15 +136,18 @@ def test_heterogeneous_batch(gpu_lib):
         assert np.abs(tr[c] - orc["trace"]).max() <= 1e-5 * n2, c
 
 
-def test_split_batch_matches_single_channel_fits(gpu_lib):
-    # a batch of 16 channels runs as four parts on concurrent streams; every channel's factors,
-    # cores, objective trace and status must equal those of a plan holding that channel alone
-    announce("split batch of 16 vs single-channel plans")
+@pytest.mark.parametrize("split", [1, 2])
+def test_split_batch_matches_single_channel_fits(gpu_lib, split):
+    # a batch of 16 channels runs as four parts on concurrent streams (B-step over the batch, or
+    # pipelined parts); every channel's factors, cores, objective trace and status must equal
+    # those of a plan holding that channel alone
+    announce(f"split batch of 16 vs single-channel plans, split mode {split}")
     rng = np.random.default_rng(91)
     nr, nt, nsc = 8, 64, 240
     Xs = [synthgen.build_channel(synthgen.draw_paths(rng, 8, 6.0), nr, nt, nsc) for _ in range(16)]
     d = desc(nr, nt, nsc, 12, 8, 16, 12, 4)
     plan = gpu_lib.Plan([d] * 16, iters=8)
+    plan.set_tuning(split=split)
     res = plan.fit(torch.cat([dev_c64(x) for x in Xs]))
     torch.cuda.synchronize()
     for c, x in enumerate(Xs):
@@ -182,7 +187,7 @@ def test_autotune_keeps_a_valid_fit(gpu_lib):
     # every variant in turn gives the reference fit up to rounding
     for bstep in (0, 1, 2):
         for tpass in (0, 1):
-            for split in (0, 1):
+            for split in (0, 1, 2):
                 p = gpu_lib.Plan([d] * 16, iters=6)
                 p.set_tuning(bstep=bstep, tpass=tpass, split=split)
                 r = p.fit(X)
