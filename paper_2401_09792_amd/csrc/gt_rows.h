@@ -75,6 +75,11 @@ __device__ __forceinline__ uint32_t rows_or(uint32_t v) {
 
 constexpr int kRowsChunk = 8;  // default Ht columns staged per pass (CH)
 
+// Groups a wave's 64 / MP consecutive subcarriers may span and still have their cores staged:
+// two for 8 subcarriers (groups of 8 or more), four for 16.
+template <int MP>
+constexpr int kRowsMaxG = MP >= 8 ? 2 : 4;
+
 template <int MP, int NS, int CH = kRowsChunk>
 struct RowsLds {
   static constexpr int kChunk = CH;
@@ -216,15 +221,31 @@ __device__ __forceinline__ void rows_ht_chunk(bool row, int j0, int n, int pg,
                                               float (&hr)[CH], float (&hi)[CH]) {
 #pragma unroll
   for (int jj = 0; jj < CH; ++jj) hr[jj] = hi[jj] = 0.f;
-  for (int q = 0; q < pg; ++q) {
-    const float2 cq = Cs[q];
-    const float2* Gq = Gr + q * gq;
+  if (j0 + CH <= n && (gq & 1) == 0 && (reinterpret_cast<uintptr_t>(Gr + j0) & 15) == 0) {
+    // whole chunk, rows 16-byte aligned: two entries per load
+    for (int q = 0; q < pg; ++q) {
+      const float2 cq = Cs[q];
+      const float4* Gq = reinterpret_cast<const float4*>(Gr + q * gq + j0);
 #pragma unroll
-    for (int jj = 0; jj < CH; ++jj) {
-      const int j = min(j0 + jj, n - 1);
-      const float2 gv = Gq[j];
-      hr[jj] += cq.x * gv.x - cq.y * gv.y;
-      hi[jj] += cq.x * gv.y + cq.y * gv.x;
+      for (int jj = 0; jj < CH; jj += 2) {
+        const float4 gv = Gq[jj / 2];
+        hr[jj] += cq.x * gv.x - cq.y * gv.y;
+        hi[jj] += cq.x * gv.y + cq.y * gv.x;
+        hr[jj + 1] += cq.x * gv.z - cq.y * gv.w;
+        hi[jj + 1] += cq.x * gv.w + cq.y * gv.z;
+      }
+    }
+  } else {
+    for (int q = 0; q < pg; ++q) {
+      const float2 cq = Cs[q];
+      const float2* Gq = Gr + q * gq;
+#pragma unroll
+      for (int jj = 0; jj < CH; ++jj) {
+        const int j = min(j0 + jj, n - 1);
+        const float2 gv = Gq[j];
+        hr[jj] += cq.x * gv.x - cq.y * gv.y;
+        hi[jj] += cq.x * gv.y + cq.y * gv.x;
+      }
     }
   }
 #pragma unroll
@@ -235,17 +256,134 @@ __device__ __forceinline__ void rows_ht_chunk(bool row, int j0, int n, int pg,
   }
 }
 
-// Row r of K = Ht Ht^H.
-template <int MP, int NS, int CH>
+// The groups of a wave's subcarriers, for staging their cores in LDS: the 64 / MP subcarriers
+// of a wave are consecutive, so they fall in a few groups; slot k holds the k-th distinct
+// (channel, group) of the wave with the offset of G_g's first row, m, n and p_g (the same in
+// every lane), and gidx is the slot of this lane's subcarrier.  ngrp > MAXG: not staged.
+template <int MAXG>
+struct RowsWave {
+  int gidx, ngrp;
+  int64_t base[MAXG];
+  int mk[MAXG], nk[MAXG], pgk[MAXG];
+};
+
+template <int MP, int MAXG>
+__device__ __forceinline__ RowsWave<MAXG> rows_wave_groups(bool valid, int c, int g, int64_t goff,
+                                                          int m, int n, int pg) {
+  constexpr int MPW = 64 / MP;
+  RowsWave<MAXG> W;
+  const int lane = threadIdx.x % 64, me = lane / MP;
+  const int key = valid ? (c << 16) + g : -1;
+  int prev = -1, first[MAXG];
+  W.ngrp = 0;
+  W.gidx = 0;
+#pragma unroll
+  for (int k = 0; k < MAXG; ++k) first[k] = 0;
+#pragma unroll
+  for (int t = 0; t < MPW; ++t) {
+    const int kt = __shfl(key, t * MP, 64);
+    if (kt >= 0 && kt != prev) {
+#pragma unroll
+      for (int k = 0; k < MAXG; ++k)
+        if (k == W.ngrp) first[k] = t;
+      ++W.ngrp;
+      prev = kt;
+    }
+    if (t == me) W.gidx = W.ngrp > 0 ? W.ngrp - 1 : 0;
+  }
+  const int lo = (int)(goff & 0xffffffff), hi = (int)(goff >> 32);
+  // the slot values are the same in every lane: readfirstlane keeps them in scalar registers
+  W.ngrp = __builtin_amdgcn_readfirstlane(W.ngrp);
+#pragma unroll
+  for (int k = 0; k < MAXG; ++k) {
+    const int src = first[k] * MP;
+    const uint32_t blo = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl(lo, src, 64));
+    const int bhi = __builtin_amdgcn_readfirstlane(__shfl(hi, src, 64));
+    W.base[k] = ((int64_t)bhi << 32) | blo;
+    W.mk[k] = __builtin_amdgcn_readfirstlane(__shfl(m, src, 64));
+    W.nk[k] = __builtin_amdgcn_readfirstlane(__shfl(n, src, 64));
+    W.pgk[k] = (k < W.ngrp) ? __builtin_amdgcn_readfirstlane(__shfl(pg, src, 64)) : 0;
+  }
+  return W;
+}
+
+// rows_ht_chunk with the wave's group cores staged in LDS (stage: [MAXG][MP][CH] complex, free
+// for the wave): per q, the wave loads columns [j0, j0 + CH) of G_g[q] of each of its groups
+// with consecutive lanes on consecutive entries, then every lane forms its row from LDS.
+template <int MP, int CH, int MAXG>
+__device__ __forceinline__ void rows_ht_chunk_staged(float2* stage, const RowsWave<MAXG>& W,
+                                                     const float2* __restrict__ G, int r, bool row,
+                                                     int j0, int n, int pg,
+                                                     const float2* __restrict__ Cs,
+                                                     float (&hr)[CH], float (&hi)[CH]) {
+  const int lane = threadIdx.x % 64;
+  int pgmax = 0;
+#pragma unroll
+  for (int k = 0; k < MAXG; ++k) pgmax = max(pgmax, W.pgk[k]);
+#pragma unroll
+  for (int jj = 0; jj < CH; ++jj) hr[jj] = hi[jj] = 0.f;
+  const float2* my = stage + (W.gidx * MP + r) * CH;
+  for (int q = 0; q < pgmax; ++q) {
+#pragma unroll
+    for (int k = 0; k < MAXG; ++k) {
+      if (k < W.ngrp) {
+        const int mk = W.mk[k], nk = W.nk[k];
+        const float2* Gq = G + W.base[k] + (int64_t)q * mk * nk;
+#pragma unroll
+        for (int e0 = 0; e0 < MP * CH; e0 += 64) {
+          const int e = e0 + lane, rw = e / CH, j = j0 + e % CH;
+          float2 v = make_float2(0.f, 0.f);
+          if (e < MP * CH && rw < mk && j < nk && q < W.pgk[k]) v = Gq[rw * nk + j];
+          if (e < MP * CH) stage[k * MP * CH + e] = v;
+        }
+      }
+    }
+    wave_sync();
+    const float2 cq = q < pg ? Cs[q] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int jj = 0; jj < CH; jj += 2) {
+      const float4 gv = *reinterpret_cast<const float4*>(my + jj);
+      hr[jj] += cq.x * gv.x - cq.y * gv.y;
+      hi[jj] += cq.x * gv.y + cq.y * gv.x;
+      hr[jj + 1] += cq.x * gv.z - cq.y * gv.w;
+      hi[jj + 1] += cq.x * gv.w + cq.y * gv.z;
+    }
+    wave_sync();
+  }
+#pragma unroll
+  for (int jj = 0; jj < CH; ++jj) {
+    const bool on = row && (j0 + jj < n);
+    hr[jj] = on ? hr[jj] : 0.f;
+    hi[jj] = on ? hi[jj] : 0.f;
+  }
+}
+
+// Row r of K = Ht Ht^H.  With W (and its stage) the Ht rows come from the staged cores when
+// the wave's subcarriers fall in at most MAXG groups.
+template <int MP, int NS, int CH, int MAXG = 1>
 __device__ __forceinline__ void rows_gram(RowsLds<MP, NS, CH>& S, int r, bool row, int n, int pg,
                                           const float2* __restrict__ Cs,
                                           const float2* __restrict__ Gr, int64_t gq,
-                                          float (&kr)[MP], float (&ki)[MP]) {
+                                          float (&kr)[MP], float (&ki)[MP],
+                                          const RowsWave<MAXG>* W = nullptr,
+                                          float2* stage = nullptr,
+                                          const float2* __restrict__ G = nullptr) {
 #pragma unroll
   for (int j = 0; j < MP; ++j) kr[j] = ki[j] = 0.f;
-  for (int j0 = 0; j0 < n; j0 += CH) {
+  const bool staged = W && W->ngrp <= MAXG;  // the same in every lane of the wave
+  int jend = n;
+  if (staged) {  // chunks over the widest group of the wave
+    jend = 0;
+#pragma unroll
+    for (int k = 0; k < MAXG; ++k)
+      if (k < W->ngrp) jend = max(jend, W->nk[k]);
+  }
+  for (int j0 = 0; j0 < jend; j0 += CH) {
     float hr[CH], hi[CH];
-    rows_ht_chunk<MP, CH>(row, j0, n, pg, Cs, Gr, gq, hr, hi);
+    if (staged)
+      rows_ht_chunk_staged<MP, CH, MAXG>(stage, *W, G, r, row, j0, n, pg, Cs, hr, hi);
+    else
+      rows_ht_chunk<MP, CH>(row, j0, n, pg, Cs, Gr, gq, hr, hi);
 #pragma unroll
     for (int jj = 0; jj < CH; ++jj) S.u.ht[r][jj] = make_float2(hr[jj], hi[jj]);
     wave_sync();

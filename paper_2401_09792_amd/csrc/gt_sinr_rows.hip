@@ -56,7 +56,14 @@ __global__ void __launch_bounds__(256) k_sinr_rows(const DevChan* __restrict__ c
   const int64_t gq = (int64_t)ch.m * ch.n;
 
   float kr[MP], ki[MP], vr[MP], vi[MP];
-  rows_gram<MP, NS>(S, r, row, n, pg, Cs, Gr, gq, kr, ki);
+  {
+    // the cores of the wave's groups staged in the wave's own (not yet used) part of lds
+    constexpr int MAXG = kRowsMaxG<MP>;
+    const RowsWave<MAXG> W = rows_wave_groups<MP, MAXG>(
+        valid, c, g, ch.g + (int64_t)g * ch.p * ch.m * ch.n, m, n, pg);
+    float2* stage = reinterpret_cast<float2*>(&lds[(threadIdx.x / 64) * (64 / MP)]);
+    rows_gram<MP, NS>(S, r, row, n, pg, Cs, Gr, gq, kr, ki, &W, stage, G);
+  }
   uint32_t bits = rows_eig<MP>(S.rot, r, kr, ki, vr, vi) ? 0u : GT_DEV_EIG_SWEEPS;
   float sig[NS], ur[NS], ui[NS], hvr[NS], hvi[NS];
   rows_hv<MP, NS>(S, r, row, ns, kr, vr, vi, sig, ur, ui, hvr, hvi, bits);
@@ -153,7 +160,12 @@ __global__ void __launch_bounds__(256) k_sinr_bwd_rows(const DevChan* __restrict
   const int64_t gq = (int64_t)ch.m * ch.n;
 
   float kr[MP], ki[MP], vr[MP], vi[MP];
-  rows_gram<MP, NS>(S, r, row, n, pg, Cs, Gr, gq, kr, ki);
+  // the cores of the wave's groups staged in the wave's own part of lds (while it is free)
+  constexpr int MAXG = kRowsMaxG<MP>;
+  const RowsWave<MAXG> W = rows_wave_groups<MP, MAXG>(
+      valid, c, g, ch.g + (int64_t)g * ch.p * ch.m * ch.n, m, n, pg);
+  float2* stage = reinterpret_cast<float2*>(&lds[(threadIdx.x / 64) * (64 / MP)]);
+  rows_gram<MP, NS>(S, r, row, n, pg, Cs, Gr, gq, kr, ki, &W, stage, G);
   uint32_t bits = rows_eig<MP>(S.rot, r, kr, ki, vr, vi) ? 0u : GT_DEV_EIG_SWEEPS;
   float sig[NS], ur[NS], ui[NS], hvr[NS], hvi[NS];
   rows_hv<MP, NS>(S, r, row, ns, kr, vr, vi, sig, ur, ui, hvr, hvi, bits);
@@ -310,9 +322,20 @@ __global__ void __launch_bounds__(256) k_sinr_bwd_rows(const DevChan* __restrict
   wave_sync();
   // dl/dHt row r = sum_j E[r][j] Ht[j][:], chunk by chunk of recomputed Ht rows
   float2* gH = reinterpret_cast<float2*>(ws + ch.w_gH) + (s * ch.m + rr) * ch.n;
-  for (int j0 = 0; j0 < n; j0 += kRowsChunk) {
+  const bool staged = W.ngrp <= MAXG;  // the same in every lane of the wave
+  int jend = n;
+  if (staged) {
+    jend = 0;
+#pragma unroll
+    for (int k = 0; k < MAXG; ++k)
+      if (k < W.ngrp) jend = max(jend, W.nk[k]);
+  }
+  for (int j0 = 0; j0 < jend; j0 += kRowsChunk) {
     float hr[kRowsChunk], hi[kRowsChunk];
-    rows_ht_chunk<MP, kRowsChunk>(row, j0, n, pg, Cs, Gr, gq, hr, hi);
+    if (staged)
+      rows_ht_chunk_staged<MP, kRowsChunk, MAXG>(stage, W, G, r, row, j0, n, pg, Cs, hr, hi);
+    else
+      rows_ht_chunk<MP, kRowsChunk>(row, j0, n, pg, Cs, Gr, gq, hr, hi);
 #pragma unroll
     for (int jj = 0; jj < kRowsChunk; ++jj) S.u.ht[r][jj] = make_float2(hr[jj], hi[jj]);
     wave_sync();

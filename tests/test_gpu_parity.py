@@ -66,10 +66,12 @@ def test_reconstruct_matches_oracle(gpu_lib, small_case):
     assert np.linalg.norm(xh - Xh) <= 1e-5 * np.linalg.norm(Xh)
 
 
-def _gpu_fit_and_check(api, X, gs, m, n, p, ns, iters, orc=None, xhat_tol=1e-4, **plan_kw):
+def _gpu_fit_and_check(api, X, gs, m, n, p, ns, iters, orc=None, xhat_tol=1e-4, trace=True,
+                       **plan_kw):
+    # trace=False fits without the objective trace: with m == nr that runs only the last A-step
     nsc, nr, nt = X.shape
     plan = _plan(api, [desc(nr, nt, nsc, gs, m, n, p, ns)], iters=iters, **plan_kw)
-    res = plan.fit(dev_c64(X))
+    res = plan.fit(dev_c64(X), trace=trace)
     torch.cuda.synchronize()
     ht, xh = plan.reconstruct(res["A"], res["B"], res["C"], res["G"])
     A = unpack(plan, 0, host(res["A"]), "a")
@@ -92,8 +94,11 @@ def _gpu_fit_and_check(api, X, gs, m, n, p, ns, iters, orc=None, xhat_tol=1e-4, 
     nm_o = metrics.nmse(X, Xh_o)
     assert abs(nm_g - nm_o) <= 1e-5 * nm_o + 1e-10, (nm_g, nm_o)
     assert np.linalg.norm(Xh - Xh_o) <= xhat_tol * np.sqrt(nx), np.linalg.norm(Xh - Xh_o) / np.sqrt(nx)
-    tr = host(res["trace"])[0]
-    assert np.abs(tr - orc["trace"]).max() <= 1e-5 * nx, np.abs(tr - orc["trace"]).max() / nx
+    if trace:
+        tr = host(res["trace"])[0]
+        assert np.abs(tr - orc["trace"]).max() <= 1e-5 * nx, np.abs(tr - orc["trace"]).max() / nx
+    else:
+        assert "trace" not in res
     assert int(res["status"].item()) == 0
     return plan, res, orc
 
@@ -229,6 +234,61 @@ def test_reconstruct_ht_only_matches(gpu_lib):
     err = np.abs(a - b).max() / np.abs(b).max()
     print(f"[reconstruct] Ht only vs with Xhat: {err:.3e} of max |Ht|", flush=True)
     assert err <= 1e-6, err
+
+
+@pytest.mark.parametrize("case", [
+    # (nsc, nr, nt, gs, m, n, p, iters, seed), all with m == nr: without the trace the fit runs
+    # only the last A-step, the B-step skips its A^H product and the T pass takes the mode-3
+    # Gram of T (A is square and unitary, so A A^H = I)
+    (40, 6, 16, 12, 6, 6, 6, 5, 41),      # nt < 64: the B-step's zero columns past nt
+    (70, 8, 32, 24, 8, 8, 10, 5, 43),     # groups of 24, short last group
+    (50, 8, 64, 12, 8, 16, 12, 6, 47),    # the 8 x 64 shape of the headline workload
+    (30, 4, 16, 8, 4, 4, 3, 1, 53),       # one sweep: its A-step is the last
+])
+def test_fit_full_mode1_untraced(gpu_lib, case):
+    nsc, nr, nt, gs, m, n, p, iters, seed = case
+    announce(f"fit m == nr without trace {case}")
+    rng = np.random.default_rng(seed)
+    X = crandn(rng, nsc, nr, nt)
+    X = X * (0.6 ** np.arange(nr))[None, :, None] * (0.8 ** np.arange(nt))[None, None, :]
+    orc = tucker.fit(X, gs, m, n, p, iters)
+    plan, res, _ = _gpu_fit_and_check(gpu_lib, X, gs, m, n, p, min(m, n, 2), iters, orc=orc,
+                                      xhat_tol=1e-4, trace=False)
+    # the same plan with the trace runs every A-step: the reconstructions agree
+    full = plan.fit(dev_c64(X), trace=True)
+    _, xa = plan.reconstruct(res["A"], res["B"], res["C"], res["G"])
+    _, xb = plan.reconstruct(full["A"], full["B"], full["C"], full["G"])
+    xa, xb = host(xa), host(xb)
+    rel = np.linalg.norm(xa - xb) / np.linalg.norm(xb)
+    print(f"[full mode 1] untraced vs traced X-hat {rel:.3e}", flush=True)
+    assert rel <= 1e-5, rel
+
+
+def test_fit_full_mode1_warm_start_non_unitary_a(gpu_lib):
+    # a caller's A need not be unitary: with m == nr and no trace the first A-step still runs
+    # before the first B-step, so the continuation matches the oracle's (whose A-step does not
+    # read A)
+    announce("fit m == nr warm start from a non-unitary A")
+    rng = np.random.default_rng(59)
+    nsc, nr, nt, gs, m, n, p = 40, 6, 16, 12, 6, 6, 6
+    X = crandn(rng, nsc, nr, nt)
+    X = X * (0.6 ** np.arange(nr))[None, :, None] * (0.8 ** np.arange(nt))[None, None, :]
+    d = desc(nr, nt, nsc, gs, m, n, p, 2)
+    r1 = _plan(gpu_lib, [d], iters=3).fit(dev_c64(X))
+    warm = _plan(gpu_lib, [d], iters=3, warm_start=True)
+    f = {k: r1[k].clone() for k in ("A", "B", "C", "G")}
+    f["A"] *= 2.0
+    r2 = warm.fit(dev_c64(X), factors=f, trace=False)
+    _, xh = warm.reconstruct(r2["A"], r2["B"], r2["C"], r2["G"])
+    Xh = unpack(warm, 0, host(xh), "x")
+    half = tucker.fit(X, gs, m, n, p, 3)
+    half["A"] = 2.0 * half["A"]
+    rest = tucker.fit(X, gs, m, n, p, 3, warm=half)
+    _, Xh_o = tucker.reconstruct(rest["A"], rest["B"], rest["C"], rest["G"], gs)
+    rel = np.linalg.norm(Xh - Xh_o) / np.linalg.norm(X)
+    print(f"[full mode 1 warm] X-hat {rel:.3e} of ||X||", flush=True)
+    assert int(r2["status"].item()) == 0
+    assert rel <= 1e-4, rel
 
 
 def test_fit_warm_start_resume(gpu_lib):
