@@ -210,6 +210,151 @@ struct RowsSweep<MP, MP> {
                                              float (&)[MP], float (&)[MP]) {}
 };
 
+// ---- Jacobi on K rows in xor-relative order ------------------------------------------------
+// Lane r holds row r of K with column r ^ k at position k: the diagonal sits at position 0 and,
+// in step t of a sweep, the entry K[r][r ^ t] of the lane's own pair at position t, so the
+// rotation parameters, the partner's entries of the row rotation (position k ^ t of lane
+// r ^ t) and the fix of the rotated pair all have compile-time positions.  V keeps the natural
+// column order.
+
+// Rotation zeroing K[p][q] = (kr, ki) with a = K[p][p], b = K[q][q] (as rows_rot_params), with
+// hardware reciprocals and reciprocal square roots and no branch.
+__device__ __forceinline__ void rows_rot_params_fast(float a, float b, float kr, float ki, bool live,
+                                                     float& cs, float& sr, float& si,
+                                                     float& tac) {
+  const float eps = 5.9604645e-08f;
+  const float ac = __builtin_sqrtf(kr * kr + ki * ki);
+  const bool on = live && ac > 0.f && ac > eps * 0.5f * (__builtin_fabsf(a) + __builtin_fabsf(b));
+  const float inv = on ? __builtin_amdgcn_rcpf(ac) : 0.f;
+  const float z = 0.5f * (b - a) * inv;
+  const float az = __builtin_fabsf(z);
+  float tt = az > 1.0e18f ? 0.5f * __builtin_amdgcn_rcpf(az)
+                          : __builtin_amdgcn_rcpf(az + __builtin_sqrtf(1.f + az * az));
+  tt = z >= 0.f ? -tt : tt;
+  tt = on ? tt : 0.f;
+  cs = __builtin_amdgcn_rsqf(1.f + tt * tt);
+  const float sn = tt * cs * inv;
+  sr = sn * kr;
+  si = sn * ki;
+  tac = tt * ac;
+}
+
+template <int MP, int T>
+__device__ __forceinline__ void rows_jacobi_step_x(float4* rot, int r, bool live, float (&kr)[MP],
+                                                   float (&ki)[MP], float (&vr)[MP],
+                                                   float (&vi)[MP]) {
+  const bool lo = (r ^ T) > r;
+  const float d_pa = xswz<T>(kr[0]);
+  const float f_r = xswz<T>(kr[T]), f_i = xswz<T>(ki[T]);
+  // both lanes of the pair use K[p][p], K[q][q] and K[p][q] as the lower lane p holds them
+  const float a = lo ? kr[0] : d_pa, b = lo ? d_pa : kr[0];
+  const float pr = lo ? kr[T] : f_r, pi = lo ? ki[T] : f_i;
+  float cs, sr, si, tac;
+  rows_rot_params_fast(a, b, pr, pi, live, cs, sr, si, tac);
+  rot[r] = make_float4(cs, sr, si, 0.f);
+  wave_sync();
+  // K <- K J: positions (k, k ^ T), k < k ^ T, hold columns j1 = k ^ r and j2 = j1 ^ T; j1 is
+  // the lower column of its pair exactly when bit b of r is clear (b the top bit of T), so with
+  // t = s-bar for a lower j1 and -s otherwise: x' = c x + t y, y' = c y - conj(t) x
+  constexpr int TB = T >= 8 ? 8 : (T >= 4 ? 4 : (T >= 2 ? 2 : 1));
+  const float sg = (r & TB) ? -1.f : 1.f;
+#pragma unroll
+  for (int k = 0; k < MP; ++k) {
+    if (k < (k ^ T)) {
+      const int kq = k ^ T;
+      const float4 pj = rot[k ^ r];
+      const float c = pj.x, tr = sg * pj.y, ti = -pj.z;
+      const float xr = kr[k], xi = ki[k], yr = kr[kq], yi = ki[kq];
+      kr[k] = c * xr + (tr * yr - ti * yi);
+      ki[k] = c * xi + (tr * yi + ti * yr);
+      kr[kq] = c * yr - (tr * xr + ti * xi);
+      ki[kq] = c * yi - (tr * xi - ti * xr);
+    }
+  }
+  // V <- V J in natural order: column j' = c col_j + conj(s) col_jq, jq' = -s col_j + c col_jq
+#pragma unroll
+  for (int j = 0; j < MP; ++j) {
+    if (j < (j ^ T)) {
+      const int jq = j ^ T;
+      const float4 pj = rot[j];
+      const float c = pj.x, s_r = pj.y, s_i = pj.z;
+      const float xr = vr[j], xi = vi[j], yr = vr[jq], yi = vi[jq];
+      vr[j] = c * xr + (s_r * yr + s_i * yi);
+      vi[j] = c * xi + (s_r * yi - s_i * yr);
+      vr[jq] = c * yr - (s_r * xr - s_i * xi);
+      vi[jq] = c * yi - (s_r * xi + s_i * xr);
+    }
+  }
+  // K <- J^H K: the lower lane takes c x + s y, the upper one c x - conj(s) y, y the partner's
+  // entry of the same column (its position k ^ T)
+  // (positions k and k ^ T read each other's partner entries: both are exchanged before either
+  // is overwritten)
+  const float ur = lo ? sr : -sr;
+#pragma unroll
+  for (int k = 0; k < MP; ++k) {
+    if (k < (k ^ T)) {
+      const int kq = k ^ T;
+      const float y1r = xswz<T>(kr[kq]), y1i = xswz<T>(ki[kq]);
+      const float y2r = xswz<T>(kr[k]), y2i = xswz<T>(ki[k]);
+      kr[k] = cs * kr[k] + (ur * y1r - si * y1i);
+      ki[k] = cs * ki[k] + (ur * y1i + si * y1r);
+      kr[kq] = cs * kr[kq] + (ur * y2r - si * y2i);
+      ki[kq] = cs * ki[kq] + (ur * y2i + si * y2r);
+    }
+  }
+  const bool rotd = tac != 0.f || sr != 0.f || si != 0.f;
+  kr[0] = rotd ? (lo ? a + tac : b - tac) : kr[0];
+  ki[0] = rotd ? 0.f : ki[0];
+  kr[T] = rotd ? 0.f : kr[T];
+  ki[T] = rotd ? 0.f : ki[T];
+  wave_sync();
+  // the V rotations feed nothing but later rotations of V: keep each step's V final here (the
+  // compiler would otherwise sink them and hold every step's (c, s) live)
+#pragma unroll
+  for (int j = 0; j < MP; ++j) asm volatile("" : "+v"(vr[j]), "+v"(vi[j]));
+}
+
+template <int MP, int T>
+struct RowsSweepX {
+  static __device__ __forceinline__ void run(float4* rot, int r, bool live, float (&kr)[MP],
+                                             float (&ki)[MP], float (&vr)[MP], float (&vi)[MP]) {
+    rows_jacobi_step_x<MP, T>(rot, r, live, kr, ki, vr, vi);
+    RowsSweepX<MP, T + 1>::run(rot, r, live, kr, ki, vr, vi);
+  }
+};
+template <int MP>
+struct RowsSweepX<MP, MP> {
+  static __device__ __forceinline__ void run(float4*, int, bool, float (&)[MP], float (&)[MP],
+                                             float (&)[MP], float (&)[MP]) {}
+};
+
+// rows_eig on K in xor-relative order (the eigenvalue of index r ends at position 0 of lane r).
+template <int MP>
+__device__ __forceinline__ bool rows_eig_x(float4* rot, int r, float (&kr)[MP], float (&ki)[MP],
+                                           float (&vr)[MP], float (&vi)[MP], bool preset = false,
+                                           float tol = 4.f, int max_sweeps = 10) {
+  if (!preset) {
+#pragma unroll
+    for (int j = 0; j < MP; ++j) {
+      vr[j] = (j == r) ? 1.f : 0.f;
+      vi[j] = 0.f;
+    }
+  }
+  const float eps = 5.9604645e-08f;
+  for (int sw = 0; sw <= max_sweeps; ++sw) {
+    float off = 0.f;
+#pragma unroll
+    for (int k = 1; k < MP; ++k) off += kr[k] * kr[k] + ki[k] * ki[k];
+    const float dg = rows_sum<MP>(kr[0] * kr[0] + ki[0] * ki[0]);
+    off = rows_sum<MP>(off);
+    const bool gdone = off <= tol * eps * eps * dg;  // the same in every lane of the group
+    if (__all(gdone ? 1 : 0)) return true;
+    if (sw == max_sweeps) return gdone;
+    RowsSweepX<MP, 1>::run(rot, r, !gdone, kr, ki, vr, vi);
+  }
+  return false;
+}
+
 // ---- stages shared by the forward kernel and its adjoint ----------------------------------
 
 // Chunk [j0, j0 + kRowsChunk) of row r of Ht = sum_q C[s,q] G_g[q] (zero past n and for the
@@ -358,9 +503,10 @@ __device__ __forceinline__ void rows_ht_chunk_staged(float2* stage, const RowsWa
   }
 }
 
-// Row r of K = Ht Ht^H.  With W (and its stage) the Ht rows come from the staged cores when
-// the wave's subcarriers fall in at most MAXG groups.
-template <int MP, int NS, int CH, int MAXG = 1>
+// Row r of K = Ht Ht^H (XOR: in xor-relative order, column r ^ k at position k).  With W (and
+// its stage) the Ht rows come from the staged cores when the wave's subcarriers fall in at
+// most MAXG groups.
+template <int MP, int NS, int CH, int MAXG = 1, bool XOR = false>
 __device__ __forceinline__ void rows_gram(RowsLds<MP, NS, CH>& S, int r, bool row, int n, int pg,
                                           const float2* __restrict__ Cs,
                                           const float2* __restrict__ Gr, int64_t gq,
@@ -391,7 +537,7 @@ __device__ __forceinline__ void rows_gram(RowsLds<MP, NS, CH>& S, int r, bool ro
     for (int k = 0; k < MP; ++k) {
 #pragma unroll
       for (int jj = 0; jj < CH; jj += 2) {
-        const float4 b = *reinterpret_cast<const float4*>(&S.u.ht[k][jj]);
+        const float4 b = *reinterpret_cast<const float4*>(&S.u.ht[XOR ? (k ^ r) : k][jj]);
         // h_r conj(h_k)
         kr[k] += hr[jj] * b.x + hi[jj] * b.y + (hr[jj + 1] * b.z + hi[jj + 1] * b.w);
         ki[k] += hi[jj] * b.x - hr[jj] * b.y + (hi[jj + 1] * b.z - hr[jj + 1] * b.w);
@@ -442,15 +588,17 @@ __device__ __forceinline__ bool rows_eig(float4* rot, int r, float (&kr)[MP], fl
 // Descending eigenvalues over the first m indices; singular values sig[k] and, in this lane,
 // row r of U_ns (ur, ui) and of HV = U_ns Sigma_ns (hvr, hvi), zero past ns and for padding
 // rows.  Publishes the HV rows to LDS.
-template <int MP, int NS, int CH>
+template <int MP, int NS, int CH, bool XOR = false>
 __device__ __forceinline__ void rows_hv(RowsLds<MP, NS, CH>& S, int r, bool row, int ns,
                                         const float (&kr)[MP], const float (&vr)[MP],
                                         const float (&vi)[MP], float (&sig)[NS],
                                         float (&ur)[NS], float (&ui)[NS], float (&hvr)[NS],
                                         float (&hvi)[NS], uint32_t& bits) {
-  float lam_me = 0.f;
+  float lam_me = XOR ? kr[0] : 0.f;
+  if (!XOR) {
 #pragma unroll
-  for (int j = 0; j < MP; ++j) lam_me = (j == r) ? kr[j] : lam_me;
+    for (int j = 0; j < MP; ++j) lam_me = (j == r) ? kr[j] : lam_me;
+  }
   S.lam[r] = row ? lam_me : -3.0e38f;
   wave_sync();
   float lam[MP];
@@ -493,11 +641,13 @@ __device__ __forceinline__ void rows_hv(RowsLds<MP, NS, CH>& S, int r, bool row,
 
 // Row r of the Cholesky factor of Q, left-looking, with row c of L published to LDS at step c;
 // (lr, li) hold row r of Q on entry (padding rows: the identity).  ok is false if this lane's
-// pivot was not positive.
+// pivot was not positive; rd receives 1 / L[r][r] (hardware reciprocal), which the published
+// diagonal entry carries in its imaginary slot (L's diagonal is real) for the rows below.
 template <int MP, int NS, int CH>
 __device__ __forceinline__ void rows_chol_factor(RowsLds<MP, NS, CH>& S, int r, float (&lr)[MP],
-                                                 float (&li)[MP], bool& ok) {
+                                                 float (&li)[MP], bool& ok, float& rd) {
   ok = true;
+  rd = 1.f;
 #pragma unroll
   for (int cc = 0; cc < MP; ++cc) {
     if (r == cc) {
@@ -507,8 +657,10 @@ __device__ __forceinline__ void rows_chol_factor(RowsLds<MP, NS, CH>& S, int r, 
       ok = d > 0.f;
       lr[cc] = __builtin_sqrtf(d > 0.f ? d : 1.f);
       li[cc] = 0.f;
+      rd = __builtin_amdgcn_rcpf(lr[cc]);
 #pragma unroll
-      for (int k = 0; k <= cc; ++k) S.u.m.l[cc][k] = make_float2(lr[k], li[k]);
+      for (int k = 0; k < cc; ++k) S.u.m.l[cc][k] = make_float2(lr[k], li[k]);
+      S.u.m.l[cc][cc] = make_float2(lr[cc], rd);
     }
     wave_sync();
     if (r > cc) {
@@ -519,7 +671,7 @@ __device__ __forceinline__ void rows_chol_factor(RowsLds<MP, NS, CH>& S, int r, 
         ar -= lr[k] * y.x + li[k] * y.y;
         ai -= li[k] * y.x - lr[k] * y.y;
       }
-      const float inv = 1.f / S.u.m.l[cc][cc].x;
+      const float inv = S.u.m.l[cc][cc].y;
       lr[cc] = ar * inv;
       li[cc] = ai * inv;
     }
@@ -530,7 +682,7 @@ __device__ __forceinline__ void rows_chol_factor(RowsLds<MP, NS, CH>& S, int r, 
 template <int MP, int NS, int CH>
 __device__ __forceinline__ void rows_chol(RowsLds<MP, NS, CH>& S, int r, bool row, float s2,
                                           const float (&hvr)[NS], const float (&hvi)[NS],
-                                          float (&lr)[MP], float (&li)[MP], bool& ok) {
+                                          float (&lr)[MP], float (&li)[MP], bool& ok, float& rd) {
 #pragma unroll
   for (int j = 0; j < MP; ++j) {
     float ar = 0.f, ai = 0.f;
@@ -543,20 +695,21 @@ __device__ __forceinline__ void rows_chol(RowsLds<MP, NS, CH>& S, int r, bool ro
     lr[j] = row ? ar + ((j == r) ? s2 : 0.f) : ((j == r) ? 1.f : 0.f);
     li[j] = row ? ai : 0.f;
   }
-  rows_chol_factor<MP, NS, CH>(S, r, lr, li, ok);
+  rows_chol_factor<MP, NS, CH>(S, r, lr, li, ok, rd);
 }
 
 // In place: row r of X <- row r of Q^{-1} X (NS columns) with Q = L L^H: forward substitution
 // (row i final at step i, published), then back substitution (row i final at step i,
 // descending; the rows j < i subtract conj(L[i][j]) x_i with L[i][j] from the published rows).
+// rd is 1 / L[r][r] from rows_chol_factor.
 template <int MP, int NS, int CH>
 __device__ __forceinline__ void rows_solve(RowsLds<MP, NS, CH>& S, int r, const float (&lr)[MP],
-                                           const float (&li)[MP], float (&xr)[NS],
+                                           const float (&li)[MP], float rd, float (&xr)[NS],
                                            float (&xi)[NS]) {
 #pragma unroll
   for (int i = 0; i < MP; ++i) {
     if (r == i) {
-      const float inv = 1.f / lr[i];
+      const float inv = rd;
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
         xr[k] *= inv;
@@ -579,7 +732,7 @@ __device__ __forceinline__ void rows_solve(RowsLds<MP, NS, CH>& S, int r, const 
 #pragma unroll
   for (int i = MP - 1; i >= 0; --i) {
     if (r == i) {
-      const float inv = 1.f / lr[i];
+      const float inv = rd;
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
         xr[k] *= inv;

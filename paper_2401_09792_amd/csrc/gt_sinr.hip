@@ -639,14 +639,20 @@ __global__ void __launch_bounds__(256) k_sinr_bwd_reduce(const DevChan* __restri
   E* gGg = gG + ch.g + (int64_t)it.g * ch.p * mn;
   const E* gH = gHm;
   const E* Gg = Ggm;
+  const E* Cg = C + ch.c + (int64_t)s0 * ch.p;  // the group's C rows (stride p)
   if (STAGE) {
+    // dl/dHt, the cores and the C rows of the group in LDS (every product below reads them
+    // many times)
     E* sH = sm;
     E* sG = sm + sz * mn;
+    E* sC = sG + pg * mn;
     for (int e = threadIdx.x; e < sz * mn; e += blockDim.x) sH[e] = gHm[e];
     for (int e = threadIdx.x; e < pg * mn; e += blockDim.x) sG[e] = Ggm[e];
+    for (int e = threadIdx.x; e < sz * ch.p; e += blockDim.x) sC[e] = Cg[e];
     __syncthreads();
     gH = sH;
     Gg = sG;
+    Cg = sC;
   }
   // dl/dG: a thread owns entry e for QC consecutive q, so each dl/dHt entry is read once per
   // chunk of q (rows q >= p_g are written as zero)
@@ -659,7 +665,7 @@ __global__ void __launch_bounds__(256) k_sinr_bwd_reduce(const DevChan* __restri
     for (int j = 0; j < QC; ++j) acc[j] = Cx<R>{R(0), R(0)};
     for (int i = 0; i < sz; ++i) {
       const Cx<R> h = ldc<R>(gH + (int64_t)i * mn + e);
-      const E* Ci = C + ch.c + (int64_t)(s0 + i) * ch.p + qc * QC;
+      const E* Ci = Cg + (int64_t)i * ch.p + qc * QC;
 #pragma unroll
       for (int j = 0; j < QC; ++j)
         if (qc * QC + j < pg) cfmac(acc[j], ldc<R>(Ci + j), h);
@@ -826,7 +832,8 @@ gt_status launch_sinr_bwd(const LaunchCtx& L, int64_t total_sc, const float2* C,
 
 template <typename E>
 static gt_status grad_cg_t(const LaunchCtx& L, const E* C, const E* G, E* gC, E* gG) {
-  const size_t sh = sizeof(E) * ((size_t)L.max_gs + L.max_p) * L.max_m * L.max_n;
+  const size_t sh = sizeof(E) * (((size_t)L.max_gs + L.max_p) * L.max_m * L.max_n +
+                                 (size_t)L.max_gs * L.max_p);
   if (sh <= 64 * 1024) {
     prof_begin("k_sinr_bwd_reduce", L.stream);
     hipLaunchKernelGGL((k_sinr_bwd_reduce<true, E>), dim3(L.total_groups), dim3(256), sh, L.stream,

@@ -28,7 +28,7 @@ namespace gt {
 // Compressed-channel SINR for channels with m <= MP and ns <= NS, 256 / MP subcarriers per
 // block of 256 lanes.
 template <int MP, int NS>
-__global__ void __launch_bounds__(256) k_sinr_rows(const DevChan* __restrict__ chans, RowsRange R,
+__global__ void __launch_bounds__(256, 4) k_sinr_rows(const DevChan* __restrict__ chans, RowsRange R,
                                                     int64_t total_sc, const float2* __restrict__ C,
                                                     const float2* __restrict__ G, RowsSnr snr,
                                                     float* __restrict__ out, int ns_max,
@@ -62,24 +62,25 @@ __global__ void __launch_bounds__(256) k_sinr_rows(const DevChan* __restrict__ c
     const RowsWave<MAXG> W = rows_wave_groups<MP, MAXG>(
         valid, c, g, ch.g + (int64_t)g * ch.p * ch.m * ch.n, m, n, pg);
     float2* stage = reinterpret_cast<float2*>(&lds[(threadIdx.x / 64) * (64 / MP)]);
-    rows_gram<MP, NS>(S, r, row, n, pg, Cs, Gr, gq, kr, ki, &W, stage, G);
+    rows_gram<MP, NS, 16, MAXG, true>(S, r, row, n, pg, Cs, Gr, gq, kr, ki, &W, stage, G);
   }
-  uint32_t bits = rows_eig<MP>(S.rot, r, kr, ki, vr, vi) ? 0u : GT_DEV_EIG_SWEEPS;
+  uint32_t bits = rows_eig_x<MP>(S.rot, r, kr, ki, vr, vi) ? 0u : GT_DEV_EIG_SWEEPS;
   float sig[NS], ur[NS], ui[NS], hvr[NS], hvi[NS];
-  rows_hv<MP, NS>(S, r, row, ns, kr, vr, vi, sig, ur, ui, hvr, hvi, bits);
+  rows_hv<MP, NS, 16, true>(S, r, row, ns, kr, vr, vi, sig, ur, ui, hvr, hvi, bits);
 
   for (int kk = 0; kk < snr.n; ++kk) {
     const float s2 = snr.s2[kk];
     float lr[MP], li[MP];
     bool ok;
-    rows_chol<MP, NS>(S, r, row, s2, hvr, hvi, lr, li, ok);
+    float rd;
+    rows_chol<MP, NS>(S, r, row, s2, hvr, hvi, lr, li, ok, rd);
     float wr[NS], wi[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       wr[k] = hvr[k];
       wi[k] = hvi[k];
     }
-    rows_solve<MP, NS>(S, r, lr, li, wr, wi);
+    rows_solve<MP, NS>(S, r, lr, li, rd, wr, wi);
     // c_jk = w_j^H hv_k, ||w_j||^2, SINR_j
     float sinr_me = 0.f;
 #pragma unroll
@@ -132,7 +133,7 @@ __global__ void __launch_bounds__(256) k_sinr_rows(const DevChan* __restrict__ c
 // the zero-stream rule carry no gradient.  dl/dHt goes to the workspace; the per-group
 // reduction forms dl/dC and dl/dG.
 template <int MP, int NS>
-__global__ void __launch_bounds__(256) k_sinr_bwd_rows(const DevChan* __restrict__ chans,
+__global__ void __launch_bounds__(256, 3) k_sinr_bwd_rows(const DevChan* __restrict__ chans,
                                                         RowsRange R, int64_t total_sc,
                                                         const float2* __restrict__ C,
                                                         const float2* __restrict__ G, RowsSnr snr,
@@ -165,10 +166,10 @@ __global__ void __launch_bounds__(256) k_sinr_bwd_rows(const DevChan* __restrict
   const RowsWave<MAXG> W = rows_wave_groups<MP, MAXG>(
       valid, c, g, ch.g + (int64_t)g * ch.p * ch.m * ch.n, m, n, pg);
   float2* stage = reinterpret_cast<float2*>(&lds[(threadIdx.x / 64) * (64 / MP)]);
-  rows_gram<MP, NS>(S, r, row, n, pg, Cs, Gr, gq, kr, ki, &W, stage, G);
-  uint32_t bits = rows_eig<MP>(S.rot, r, kr, ki, vr, vi) ? 0u : GT_DEV_EIG_SWEEPS;
+  rows_gram<MP, NS, kRowsChunk, MAXG, true>(S, r, row, n, pg, Cs, Gr, gq, kr, ki, &W, stage, G);
+  uint32_t bits = rows_eig_x<MP>(S.rot, r, kr, ki, vr, vi) ? 0u : GT_DEV_EIG_SWEEPS;
   float sig[NS], ur[NS], ui[NS], hvr[NS], hvi[NS];
-  rows_hv<MP, NS>(S, r, row, ns, kr, vr, vi, sig, ur, ui, hvr, hvi, bits);
+  rows_hv<MP, NS, kRowsChunk, true>(S, r, row, ns, kr, vr, vi, sig, ur, ui, hvr, hvi, bits);
   bool live[NS];
 #pragma unroll
   for (int k = 0; k < NS; ++k) live[k] = k < ns && sig[k] > 1.0e-3f * sig[0];
@@ -180,7 +181,8 @@ __global__ void __launch_bounds__(256) k_sinr_bwd_rows(const DevChan* __restrict
     const float s2 = snr.s2[kk];
     float lr[MP], li[MP];
     bool ok;
-    rows_chol<MP, NS>(S, r, row, s2, hvr, hvi, lr, li, ok);
+    float rd;
+    rows_chol<MP, NS>(S, r, row, s2, hvr, hvi, lr, li, ok, rd);
     const bool any_bad = rows_or<MP>(ok ? 0u : 1u) != 0u;
     if (any_bad) bits |= GT_DEV_CHOLESKY;
     float wr[NS], wi[NS];
@@ -189,7 +191,7 @@ __global__ void __launch_bounds__(256) k_sinr_bwd_rows(const DevChan* __restrict
       wr[k] = hvr[k];
       wi[k] = hvi[k];
     }
-    rows_solve<MP, NS>(S, r, lr, li, wr, wi);
+    rows_solve<MP, NS>(S, r, lr, li, rd, wr, wi);
     float cr[NS][NS], ci[NS][NS];  // c_jk = w_j^H hv_k
     rows_inner<MP, NS>(wr, wi, hvr, hvi, cr, ci);
     // C-bar (in place of c) and N-bar
@@ -244,7 +246,7 @@ __global__ void __launch_bounds__(256) k_sinr_bwd_rows(const DevChan* __restrict
         bi[k] += wr[j] * ci[j][k] + wi[j] * cr[j][k];
       }
     }
-    rows_solve<MP, NS>(S, r, lr, li, lmr, lmi);  // Lambda = Q^{-1} W-bar
+    rows_solve<MP, NS>(S, r, lr, li, rd, lmr, lmi);  // Lambda = Q^{-1} W-bar
     // c again (C-bar overwrote it), then X = Lambda^H HV
     rows_inner<MP, NS>(wr, wi, hvr, hvi, cr, ci);
 #pragma unroll

@@ -254,14 +254,15 @@ __global__ void __launch_bounds__(256) k_sys_sinr(const DevChan* __restrict__ ch
       li[j] = row ? pi[j] + qi[j] : 0.f;
     }
     bool ok;
-    rows_chol_factor<MP, NS>(S.b, r, lr, li, ok);
+    float rd;
+    rows_chol_factor<MP, NS>(S.b, r, lr, li, ok, rd);
     float wr[NS], wi[NS];
 #pragma unroll
     for (int a = 0; a < NS; ++a) {
       wr[a] = hvr[a];
       wi[a] = hvi[a];
     }
-    rows_solve<MP, NS>(S.b, r, lr, li, wr, wi);  // W rows; the y table holds all of them
+    rows_solve<MP, NS>(S.b, r, lr, li, rd, wr, wi);  // W rows; the y table holds all of them
     // z = R W, row r (W rows from the y table), then w_a^H R w_a summed over the rows
     float zr[NS], zi[NS];
 #pragma unroll
