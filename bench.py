@@ -568,8 +568,9 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the precision, graph-replay, refinement and batch forms")
     ap.add_argument("--steps-only", action="store_true",
-                    help="only the warm-up, timed and profiled steps of the workload (for profiler "
-                         "runs: every launch of a kernel then has the same size)")
+                    help="only the warm-up, timed and profiled steps of the workload and one "
+                         "single-stream fit (for profiler runs: the fit kernels' launches then have "
+                         "two sizes, a part of the pipelined fit and the whole batch)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run three plain copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -639,11 +640,10 @@ def main():
     kern = profile_steps(api, step, args.steps)
     # the T pass and the eigensolves also run once unsplit (one stream), so that their
     # durations are their own and not shared with concurrent parts
-    kern_unsplit = {}
-    if not args.steps_only:
-        plan.set_tuning(bstep=0, tpass=0, split=0)
-        kern_unsplit = profile_steps(api, lambda: plan.fit(X, factors=f, trace=False), 1)
-        plan.set_tuning(bstep=0, tpass=0, split=2)
+    # (also with --steps-only: the rooflines need the fit kernels' own durations)
+    plan.set_tuning(bstep=0, tpass=0, split=0)
+    kern_unsplit = profile_steps(api, lambda: plan.fit(X, factors=f, trace=False), 1)
+    plan.set_tuning(bstep=0, tpass=0, split=2)
     torch.cuda.synchronize()
 
     fits_per_s = B * args.steps / (ms_total / 1e3)
