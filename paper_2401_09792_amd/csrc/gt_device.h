@@ -451,130 +451,82 @@ __device__ __forceinline__ void reorthonormalize_r(EigLds<T, MP>& L, int r) {
   wave_sync();
 }
 
-// Block version for MP = 64 and 256 threads.
+// Block versions for MP = 64 and 256 threads (a 4 x 4 output tile per thread).  Each product is
+// formed in registers and written back over an operand after a barrier, so no scratch matrix is
+// needed: the kernel's LDS is the Jacobi's own K and V.
 template <typename T>
-__device__ __forceinline__ void reorthonormalize64(EigLds<T, 64>& L, T (*tr)[65], T (*ti)[65]) {
-  const int t = threadIdx.x;
-  const int bi = (t / 16) * 4, bj = (t % 16) * 4;
-  T ar[4][4], ai[4][4];
+__device__ __forceinline__ void tile_product64(const T (*xr)[65], const T (*xi)[65], bool xh,
+                                               const T (*yr)[65], const T (*yi)[65], int bi, int bj,
+                                               T (&ar)[4][4], T (&ai)[4][4]) {
+  // (X Y) or (X^H Y) on rows bi.., columns bj..
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) ar[a][b] = ai[a][b] = 0;
-  for (int k = 0; k < 64; ++k) {  // E = V^H V
-    T xr[4], xi[4], yr[4], yi[4];
+  for (int k = 0; k < 64; ++k) {
+    T pr[4], pi[4], qr[4], qi[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      xr[a] = L.vr[k][bi + a];
-      xi[a] = -L.vi[k][bi + a];
-      yr[a] = L.vr[k][bj + a];
-      yi[a] = L.vi[k][bj + a];
+      pr[a] = xh ? xr[k][bi + a] : xr[bi + a][k];
+      pi[a] = xh ? -xi[k][bi + a] : xi[bi + a][k];
+      qr[a] = yr[k][bj + a];
+      qi[a] = yi[k][bj + a];
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        ar[a][b] += xr[a] * yr[b] - xi[a] * yi[b];
-        ai[a][b] += xr[a] * yi[b] + xi[a] * yr[b];
+        ar[a][b] += pr[a] * qr[b] - pi[a] * qi[b];
+        ai[a][b] += pr[a] * qi[b] + pi[a] * qr[b];
       }
   }
+}
+
+// V <- V (3 I - V^H V) / 2 with E = V^H V held in K's arrays (K is loaded afterwards).
+template <typename T>
+__device__ __forceinline__ void reorthonormalize64(EigLds<T, 64>& L) {
+  const int t = threadIdx.x;
+  const int bi = (t / 16) * 4, bj = (t % 16) * 4;
+  T ar[4][4], ai[4][4];
+  tile_product64<T>(L.vr, L.vi, true, L.vr, L.vi, bi, bj, ar, ai);  // E = V^H V
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      tr[bi + a][bj + b] = ar[a][b];
-      ti[bi + a][bj + b] = ai[a][b];
-      ar[a][b] = ai[a][b] = 0;
+      L.kr[bi + a][bj + b] = ar[a][b];
+      L.ki[bi + a][bj + b] = ai[a][b];
     }
   __syncthreads();
-  for (int k = 0; k < 64; ++k) {  // V E
-    T xr[4], xi[4], yr[4], yi[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      xr[a] = L.vr[bi + a][k];
-      xi[a] = L.vi[bi + a][k];
-      yr[a] = tr[k][bj + a];
-      yi[a] = ti[k][bj + a];
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        ar[a][b] += xr[a] * yr[b] - xi[a] * yi[b];
-        ai[a][b] += xr[a] * yi[b] + xi[a] * yr[b];
-      }
-  }
+  tile_product64<T>(L.vr, L.vi, false, L.kr, L.ki, bi, bj, ar, ai);  // V E
+  __syncthreads();  // every read of V and E is done
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      L.kr[bi + a][bj + b] = T(1.5) * L.vr[bi + a][bj + b] - T(0.5) * ar[a][b];
-      L.ki[bi + a][bj + b] = T(1.5) * L.vi[bi + a][bj + b] - T(0.5) * ai[a][b];
-    }
-  __syncthreads();
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      L.vr[bi + a][bj + b] = L.kr[bi + a][bj + b];
-      L.vi[bi + a][bj + b] = L.ki[bi + a][bj + b];
+      L.vr[bi + a][bj + b] = T(1.5) * L.vr[bi + a][bj + b] - T(0.5) * ar[a][b];
+      L.vi[bi + a][bj + b] = T(1.5) * L.vi[bi + a][bj + b] - T(0.5) * ai[a][b];
     }
   __syncthreads();
 }
 
-// The same for MP = 64 shared by a block of 256 threads (4 x 4 output tile per thread).
+// K <- V^H K V, the intermediate K V held in K's arrays.
 template <typename T>
-__device__ __forceinline__ void rotate_into_basis64(EigLds<T, 64>& L, T (*tr)[65], T (*ti)[65]) {
+__device__ __forceinline__ void rotate_into_basis64(EigLds<T, 64>& L) {
   const int t = threadIdx.x;
   const int bi = (t / 16) * 4, bj = (t % 16) * 4;
   T ar[4][4], ai[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) ar[a][b] = ai[a][b] = 0;
-  for (int k = 0; k < 64; ++k) {
-    T xr[4], xi[4], yr[4], yi[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      xr[a] = L.kr[bi + a][k];
-      xi[a] = L.ki[bi + a][k];
-      yr[a] = L.vr[k][bj + a];
-      yi[a] = L.vi[k][bj + a];
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        ar[a][b] += xr[a] * yr[b] - xi[a] * yi[b];
-        ai[a][b] += xr[a] * yi[b] + xi[a] * yr[b];
-      }
-  }
+  tile_product64<T>(L.kr, L.ki, false, L.vr, L.vi, bi, bj, ar, ai);  // K V
+  __syncthreads();  // every read of K is done
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      tr[bi + a][bj + b] = ar[a][b];
-      ti[bi + a][bj + b] = ai[a][b];
-      ar[a][b] = ai[a][b] = 0;
+      L.kr[bi + a][bj + b] = ar[a][b];
+      L.ki[bi + a][bj + b] = ai[a][b];
     }
   __syncthreads();
-  for (int k = 0; k < 64; ++k) {
-    T xr[4], xi[4], yr[4], yi[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      xr[a] = L.vr[k][bi + a];  // conj(V[k][i])
-      xi[a] = -L.vi[k][bi + a];
-      yr[a] = tr[k][bj + a];
-      yi[a] = ti[k][bj + a];
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        ar[a][b] += xr[a] * yr[b] - xi[a] * yi[b];
-        ai[a][b] += xr[a] * yi[b] + xi[a] * yr[b];
-      }
-  }
+  tile_product64<T>(L.vr, L.vi, true, L.kr, L.ki, bi, bj, ar, ai);  // V^H (K V)
+  __syncthreads();  // every read of K V is done
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll

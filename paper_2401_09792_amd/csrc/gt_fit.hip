@@ -385,19 +385,210 @@ __global__ void __launch_bounds__(64, (sizeof(T) == 4 && MP == 16) ? 2 : 1) k_ei
   }
 }
 
+// Warm mode-2 solve by Rayleigh-Ritz on the previous call's top-n basis (FP32, nt <= 64,
+// n <= 16), one 256-thread block per channel.  With Bp the current B (the last solve's n leading
+// eigenvectors of this channel's Gram family): Y = S2 Bp, H = Bp^H Y, H = U diag(theta) U^H, the
+// residual R = Y - Bp H.  The Ritz pairs (Bp U, theta) are the n leading eigenpairs of S2 to FP32
+// accuracy when ||R||_F <= 5e-6 theta_max (Bp spans an invariant subspace) and the complement's
+// trace tr(S2) - sum(theta) does not exceed theta_min + 1e-5 tr(S2) (no eigenvalue outside that
+// subspace lies above the kept ones, up to the Gram's rounding); then B = Bp U (descending, each
+// column's largest-modulus entry real positive) and the call returns true.  Otherwise it returns
+// false and the caller runs the full Jacobi.  Run by the 256 threads of k_eigB's block, in its
+// LDS (before the Jacobi's own use of it).
+constexpr int kRitzN = 16;
+struct RitzLds {
+  float2 s[64][65];               // S2 (zero past nt)
+  float2 b[64][kRitzN];           // the previous basis
+  float2 y[64][kRitzN];           // S2 Bp
+  float2 h[kRitzN][kRitzN + 1];   // Bp^H Y, then U (rows)
+  float4 rot[kRitzN];
+  float lam[kRitzN];
+  int src[kRitzN];
+  float red[8];
+};
+
+__device__ __forceinline__ bool eigB_ritz(RitzLds& L, const DevChan& ch, int c, char* ws, float2* B,
+                                          int32_t* status) {
+  constexpr int NB = kRitzN;
+  const int t = threadIdx.x, lane = t % 64, wave = t / 64;
+  const int d = ch.nt, n = ch.n;
+  double* sc = wsd(ws, ch.w_scal);
+  if (d > 64 || n > NB) return false;
+  const float2* S = wsp(ws, ch.w_S2);
+  for (int e = t; e < 64 * 64; e += 256) {
+    const int i = e / 64, j = e % 64;
+    L.s[i][j] = (i < d && j < d) ? S[(int64_t)i * d + j] : make_float2(0.f, 0.f);
+  }
+  for (int e = t; e < 64 * NB; e += 256) {
+    const int i = e / NB, j = e % NB;
+    L.b[i][j] = (i < d && j < n) ? B[ch.b + (int64_t)i * n + j] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  // Y = S2 Bp: thread (i, four columns)
+  {
+    const int i = t / 4, j0 = 4 * (t % 4);
+    float yr[4] = {0.f, 0.f, 0.f, 0.f}, yi[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < 64; ++k) {
+      const float2 a = L.s[i][k];
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const float2 bv = L.b[k][j0 + jj];
+        yr[jj] += a.x * bv.x - a.y * bv.y;
+        yi[jj] += a.x * bv.y + a.y * bv.x;
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) L.y[i][j0 + jj] = make_float2(yr[jj], yi[jj]);
+  }
+  __syncthreads();
+  // H = Bp^H Y: thread (a, b)
+  {
+    const int a = t / NB, b = t % NB;
+    float hr = 0.f, hi = 0.f;
+    for (int k = 0; k < 64; ++k) {
+      const float2 x = L.b[k][a], y = L.y[k][b];
+      hr += x.x * y.x + x.y * y.y;
+      hi += x.x * y.y - x.y * y.x;
+    }
+    L.h[a][b] = make_float2(hr, hi);
+  }
+  __syncthreads();
+  // residual R = Y - Bp H and tr(S2) (all threads), while wave 0 diagonalises H on 16 lanes
+  float rr = 0.f;
+  {
+    const int i = t / 4, j0 = 4 * (t % 4);
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      float xr = L.y[i][j0 + jj].x, xi = L.y[i][j0 + jj].y;
+      for (int k = 0; k < NB; ++k) {
+        const float2 bv = L.b[i][k], hv = L.h[k][j0 + jj];
+        xr -= bv.x * hv.x - bv.y * hv.y;
+        xi -= bv.x * hv.y + bv.y * hv.x;
+      }
+      rr += xr * xr + xi * xi;
+    }
+  }
+  float trs = (t < 64 && t < d) ? L.s[t][t].x : 0.f;
+  bool conv = true;
+  float ur[NB], ui[NB];
+  __syncthreads();  // every read of H for the residual is done
+  if (wave == 0 && lane < NB) {
+    float kr[NB], ki[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const bool on = lane < n && j < n;
+      kr[j] = on ? L.h[lane][j].x : 0.f;
+      ki[j] = on ? L.h[lane][j].y : 0.f;
+    }
+    conv = rows_eig<NB>(L.rot, lane, kr, ki, ur, ui, false, 64.f, 12);
+    float me = 0.f;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) me = (j == lane) ? kr[j] : me;
+    L.lam[lane] = lane < n ? me : -__builtin_huge_valf();
+  }
+  // block sums: |R|^2 and tr(S2)
+  rr = group_sum<64>(rr);
+  trs = group_sum<64>(trs);
+  __syncthreads();
+  if (lane == 0) {
+    L.red[wave] = rr;
+    L.red[4 + wave] = trs;
+  }
+  if (wave == 0 && lane < NB) {
+    // U rows to LDS (row lane of U), and the descending order of theta
+#pragma unroll
+    for (int j = 0; j < NB; ++j) L.h[lane][j] = make_float2(ur[j], ui[j]);
+    const float mine = L.lam[lane];
+    int rank = 0;
+    for (int j = 0; j < NB; ++j) {
+      const float o = L.lam[j];
+      rank += (o > mine || (o == mine && j < lane)) ? 1 : 0;
+    }
+    L.src[rank] = lane;
+  }
+  __syncthreads();
+  const float r2 = (L.red[0] + L.red[1]) + (L.red[2] + L.red[3]);
+  const float tr_s = (L.red[4] + L.red[5]) + (L.red[6] + L.red[7]);
+  float th_max = L.lam[L.src[0]], th_min = L.lam[L.src[n - 1]];
+  float th_sum = 0.f;
+  for (int j = 0; j < n; ++j) th_sum += L.lam[j];
+  const int conv_all = __syncthreads_and(conv ? 1 : 0);
+  const bool ok = conv_all && th_max > 0.f && r2 <= 2.5e-11f * th_max * th_max &&
+                  tr_s - th_sum <= th_min + 1.0e-5f * tr_s;
+  if (!ok) {
+    __syncthreads();  // every read of the Ritz data is done before the Jacobi reuses the LDS
+    return false;
+  }
+  // B = Bp U, column j from Ritz vector src[j], with its phase: thread (column j = t / 16, rows
+  // (t % 16) + 16 k)
+  {
+    const int j = t / 16, l16 = t % 16;
+    const int col = L.src[j < n ? j : 0];
+    float vr[4], vi[4], mag = -1.f;
+    int idx = 1 << 30;
+    float pr = 0.f, pi = 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = l16 + 16 * k;
+      float ar = 0.f, ai = 0.f;
+      for (int q = 0; q < NB; ++q) {
+        const float2 bv = L.b[i][q], u = L.h[q][col];
+        ar += bv.x * u.x - bv.y * u.y;
+        ai += bv.x * u.y + bv.y * u.x;
+      }
+      vr[k] = ar;
+      vi[k] = ai;
+      const float mg = (i < d) ? ar * ar + ai * ai : -1.f;
+      if (mg > mag) {  // rows ascend with k: the first maximum is the lowest row
+        mag = mg;
+        idx = i;
+        pr = ar;
+        pi = ai;
+      }
+    }
+    rows_argmax<16>(mag, idx, pr, pi);
+    const float mod = __builtin_sqrtf(pr * pr + pi * pi);
+    float phr = 1.f, phi = 0.f;
+    if (mod > 0.f) {
+      phr = pr / mod;
+      phi = -pi / mod;
+    }
+    if (j < n) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int i = l16 + 16 * k;
+        if (i < d) B[ch.b + (int64_t)i * n + j] = make_float2(vr[k] * phr - vi[k] * phi, vr[k] * phi + vi[k] * phr);
+      }
+    }
+  }
+  if (t == 0) {
+    double ls = 0.0;
+    for (int j = 0; j < n; ++j) ls += (double)L.lam[L.src[j]];
+    sc[2] = ls;
+    uint32_t bits = 0u;
+    if (!(ls == ls) || ls > 1e300 || ls < -1e300) bits |= GT_DEV_NONFINITE;
+    if (bits && status) atomicOr(reinterpret_cast<unsigned int*>(status + c), bits);
+  }
+  return true;
+}
+
 // mode-2: one block of NW waves per channel, nt <= 64
 template <typename T, int NW>
 __global__ void __launch_bounds__(64 * NW) k_eigB(const DevChan* __restrict__ chans, char* ws,
-                                                  float2* B, int32_t* status, int warm) {
+                                                  float2* B, int32_t* status, int warm, int ritz) {
   constexpr int MP = 64;
   constexpr bool kWarmOk = sizeof(T) == 4 && NW == 4;
   __shared__ EigLds<T, MP> L;
-  __shared__ T tr[kWarmOk ? MP : 1][MP + 1], ti[kWarmOk ? MP : 1][MP + 1];
   const int r = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int c = blockIdx.x;
   const DevChan& ch = chans[c];
   const int d = ch.nt;
   if (d > MP) return;  // wide arrays: subspace-iteration kernel
+  if (kWarmOk && ritz && warm) {
+    // warm FP32 solve: the Rayleigh-Ritz step on the previous basis first, in this block's LDS
+    static_assert(sizeof(RitzLds) <= sizeof(EigLds<float, 64>), "Ritz data must fit the Jacobi LDS");
+    if (eigB_ritz(*reinterpret_cast<RitzLds*>(&L), ch, c, ws, B, status)) return;
+  }
   const float2* S = wsp(ws, ch.w_S2);
   float2* VB = wsp(ws, ch.w_VB);
   const bool use_warm = kWarmOk && warm;
@@ -408,7 +599,7 @@ __global__ void __launch_bounds__(64 * NW) k_eigB(const DevChan* __restrict__ ch
       L.vi[e / MP][e % MP] = (T)v.y;
     }
     __syncthreads();
-    if (kWarmOk) reorthonormalize64<T>(L, reinterpret_cast<T(*)[65]>(tr), reinterpret_cast<T(*)[65]>(ti));
+    if (kWarmOk) reorthonormalize64<T>(L);
   }
   for (int e = threadIdx.x; e < MP * MP; e += 64 * NW) {
     const int i = e / MP, j = e % MP;
@@ -422,8 +613,7 @@ __global__ void __launch_bounds__(64 * NW) k_eigB(const DevChan* __restrict__ ch
     L.ki[i][j] = si;
   }
   __syncthreads();
-  if (kWarmOk && use_warm) rotate_into_basis64<T>(L, reinterpret_cast<T(*)[65]>(tr),
-                                                  reinterpret_cast<T(*)[65]>(ti));
+  if (kWarmOk && use_warm) rotate_into_basis64<T>(L);
   bool conv = jacobi_herm<T, MP, NW>(L, r, wave, sizeof(T) == 4 ? 12 : 20, use_warm);
   if (sizeof(T) == 4)
     for (int e = threadIdx.x; e < MP * MP; e += 64 * NW)
@@ -860,8 +1050,13 @@ static gt_status eig_all(const LaunchCtx& L, int which, float2* A, float2* B, fl
     gt_status sst = launch_share_gram(L, 1);
     if (sst != GT_OK) return sst;
     constexpr int NW = sizeof(T) == 4 ? 4 : 8;
-    if (L.min_nt <= 64)
-      GT_LAUNCH((k_eigB<T, NW>), dim3(L.n_channels), dim3(64 * NW), L.d_chans, L.ws, B, status, warm);
+    if (L.min_nt <= 64) {
+      // warm FP32 solves try the Rayleigh-Ritz step on the previous basis first and run the
+      // Jacobi only for the channels it cannot settle
+      const int ritz = (sizeof(T) == 4 && warm) ? 1 : 0;
+      GT_LAUNCH((k_eigB<T, NW>), dim3(L.n_channels), dim3(64 * NW), L.d_chans, L.ws, B, status, warm,
+                ritz);
+    }
     if (L.max_nt > 64) {
       gt_status st = launch_eigB_sub(L, B, status, warm);
       if (st != GT_OK) return st;
