@@ -1094,7 +1094,8 @@ gt_status launch_eigB_sub(const LaunchCtx& L, float2* B, int32_t* status, int wa
 gt_status launch_fused_t(const LaunchCtx& L, const float2* X, const float2* A, const float2* B,
                          int do_c);
 gt_status launch_fused_z(const LaunchCtx& L, const float2* C, float2* G, int do_a, int do_core);
-gt_status launch_fused_b(const LaunchCtx& L, const float2* X, const float2* A, const float2* C);
+gt_status launch_fused_b(const LaunchCtx& L, const float2* X, const float2* A, const float2* C,
+                         hipEvent_t pre_reduce = nullptr, hipEvent_t after_pass = nullptr);
 
 static gt_status split_fork(const LaunchCtx& L, const SplitCtx& S) {
   if (hipEventRecord(S.fork, L.stream) != hipSuccess) return GT_ERR_HIP;
@@ -1122,6 +1123,35 @@ gt_status launch_fit(const LaunchCtx& L, const SplitCtx* split, const float2* X,
   const dim3 gGram(tiles * tiles, L.max_nsplit, nch);
   const dim3 gRed(cdiv((int64_t)L.max_nt * L.max_nt, 256), nch);
 
+  // the fused per-group passes need their own limits for 16-bit contractions; the generic
+  // row passes take any shape
+  const bool fused = fused_fit_ok(L) && (L.ttm_prec == GT_TTM_FP32 || fused_lowp_ok(L));
+  // With m == nr in every channel A is square and unitary once an eigensolve has made it,
+  // so the B- and C-step Grams do not depend on it (W^H W = Hc^H A A^H Hc = Hc^H Hc, and
+  // likewise for Yh): only the last A-step, whose A the outputs and cores use, runs (and the
+  // first one when A comes from the caller), unless the objective trace asks for every
+  // half-step.
+  const bool skip_a = L.full_mode1 && !trace;
+  auto a_step = [&](int na) { return !skip_a || na == iters - 1 || (warm && na == 0); };
+  // Pipelined parts whose first use of the starting B is the warm start of their first mode-2
+  // eigensolve (no A-step and no objective before it): the mode-2 Gram of X and its cold
+  // eigensolve run on the last part's stream, beside the other initial passes and the parts'
+  // first B-steps.  Those B-steps write the Gram's partials, so the caller's stream waits for
+  // the Gram before the parts start; each part's first B-step reduction overwrites the Gram,
+  // so it waits for the eigensolve.  Every cross-stream wait is on an event of the caller's
+  // stream or made by it, as for the fork and join of the parts: part 0 (the caller's stream)
+  // waits for the eigensolve and relays it to the middle parts through init[3]; the last part
+  // runs behind the eigensolve on its own stream.
+  const bool side_b0 = !warm && fused && split && split->mode == 2 && split->n > 1 && iters > 0 &&
+                       !a_step(0);
+  LaunchCtx LQ = L;
+  if (side_b0) {
+    LQ.stream = split->parts[split->n - 1].stream;
+    if (hipEventRecord(split->init[0], L.stream) != hipSuccess ||
+        hipStreamWaitEvent(LQ.stream, split->init[0], 0) != hipSuccess)
+      return GT_ERR_HIP;
+  }
+
   // initialisation: Grams of the unfoldings, norms
   if ((int64_t)L.max_gs * L.max_nr * L.max_nt <= 8192)
     GT_LAUNCH(k_init_group_lds, dim3(L.total_groups), dim3(512), L.d_chans, L.d_groups, X, L.ws);
@@ -1132,15 +1162,16 @@ gt_status launch_fit(const LaunchCtx& L, const SplitCtx* split, const float2* X,
     gt_status st;
     // mode-2 Gram of the rows of X in 128 x 128 super-tiles (LDS-staged row chunks); for
     // nt <= 64 one super-tile holds the whole real Gram
-    if ((st = launch_gram_rows_big(L, X, 0)) != GT_OK) return st;
+    if ((st = launch_gram_rows_big(LQ, X, 0)) != GT_OK) return st;
+    if (side_b0 && hipEventRecord(split->init[1], LQ.stream) != hipSuccess) return GT_ERR_HIP;
     if ((st = eig_dispatch(L, 0, A, B, C, status, 0)) != GT_OK) return st;
-    if ((st = eig_dispatch(L, 1, A, B, C, status, 0)) != GT_OK) return st;
+    if ((st = eig_dispatch(LQ, 1, A, B, C, status, 0)) != GT_OK) return st;
+    if (side_b0 && hipEventRecord(split->init[2], LQ.stream) != hipSuccess) return GT_ERR_HIP;
     if ((st = eig_dispatch(L, 2, A, B, C, status, 0)) != GT_OK) return st;
+    if (side_b0 && hipStreamWaitEvent(L.stream, split->init[1], 0) != hipSuccess)
+      return GT_ERR_HIP;
   }
   // objective of the starting factors (the generic path also needs Yh for the cores)
-  // the fused per-group passes need their own limits for 16-bit contractions; the generic
-  // row passes take any shape
-  const bool fused = fused_fit_ok(L) && (L.ttm_prec == GT_TTM_FP32 || fused_lowp_ok(L));
   if (L.ttm_prec != GT_TTM_FP32) {  // 16-bit copy of X for the contractions below
     gt_status st;
     if ((st = launch_convert_x(L, X)) != GT_OK) return st;
@@ -1160,13 +1191,6 @@ gt_status launch_fit(const LaunchCtx& L, const SplitCtx* split, const float2* X,
     // per sweep: eigA, [W + Gram], eigB, [T, Yh, S3], eigC, [Z + S1 or cores]; the first
     // A-step Gram comes from [T] and [Z] with the starting factors
     gt_status st;
-    // With m == nr in every channel A is square and unitary once an eigensolve has made it,
-    // so the B- and C-step Grams do not depend on it (W^H W = Hc^H A A^H Hc = Hc^H Hc, and
-    // likewise for Yh): only the last A-step, whose A the outputs and cores use, runs (and the
-    // first one when A comes from the caller), unless the objective trace asks for every
-    // half-step.
-    const bool skip_a = L.full_mode1 && !trace;
-    auto a_step = [&](int na) { return !skip_a || na == iters - 1 || (warm && na == 0); };
     // T pass of sweep it: T is stored only for a following A-step; channels with m == nr take
     // the mode-3 Gram of T
     auto t_flags = [&](int it) {
@@ -1238,9 +1262,13 @@ gt_status launch_fit(const LaunchCtx& L, const SplitCtx* split, const float2* X,
               if (it == 0 && k > 0 &&
                   hipStreamWaitEvent(P.stream, split->stag[k - 1], 0) != hipSuccess)
                 return GT_ERR_HIP;
-              if ((st = launch_fused_b(P, X, A, C)) != GT_OK) return st;
-              if (it == 0 && k + 1 < split->n &&
-                  hipEventRecord(split->stag[k], P.stream) != hipSuccess)
+              // the next part's first B-step follows this one's B-step kernel
+              hipEvent_t mm = (it == 0 && k + 1 < split->n) ? split->stag[k] : nullptr;
+              hipEvent_t pre = nullptr;
+              if (side_b0 && it == 0 && k + 1 < split->n) pre = split->init[k == 0 ? 2 : 3];
+              if ((st = launch_fused_b(P, X, A, C, pre, mm)) != GT_OK) return st;
+              if (side_b0 && it == 0 && k == 0 &&
+                  hipEventRecord(split->init[3], P.stream) != hipSuccess)
                 return GT_ERR_HIP;
               if ((st = eig_dispatch(P, 1, A, B, C, ps, w)) != GT_OK) return st;
               if (pt)

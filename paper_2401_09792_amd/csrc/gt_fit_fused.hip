@@ -2165,7 +2165,15 @@ static int bmm_variant(const LaunchCtx& L) {
   return 0;
 }
 
-gt_status launch_fused_b(const LaunchCtx& L, const float2* X, const float2* A, const float2* C) {
+gt_status launch_fused_b(const LaunchCtx& L, const float2* X, const float2* A, const float2* C,
+                         hipEvent_t pre_reduce, hipEvent_t after_pass) {
+  // after_pass, when set, is recorded behind the pass over X; the reduction overwrites the
+  // channel's mode-2 Gram, so with pre_reduce set it first waits for that event (an eigensolve
+  // of the previous Gram still running on another stream)
+  auto wait_pre = [&]() {
+    return (!after_pass || hipEventRecord(after_pass, L.stream) == hipSuccess) &&
+           (!pre_reduce || hipStreamWaitEvent(L.stream, pre_reduce, 0) == hipSuccess);
+  };
   const int v = (L.tune_bstep == 2 && fused_b_mfma_ok(L)) ? 0 : bmm_variant(L);
   if (v) {
     const dim3 grid(L.max_nsplit, L.n_channels);
@@ -2198,6 +2206,7 @@ gt_status launch_fused_b(const LaunchCtx& L, const float2* X, const float2* A, c
 #undef GT_BMM_PREC
 #undef GT_BMM
 #undef GT_BMM_S
+    if (!wait_pre()) return GT_ERR_HIP;
     GT_LAUNCH_SH(k_reduce_S2_mfma, dim3(3, L.n_channels), dim3(256), 0,
                  L.d_chans, L.ws);
     return GT_OK;
@@ -2215,12 +2224,14 @@ gt_status launch_fused_b(const LaunchCtx& L, const float2* X, const float2* A, c
     else
       GT_LAUNCH_SH((k_fused_b_mfma<2, 16>), dim3(L.max_nsplit, L.n_channels), dim3(256), bm_bytes(L),
                    L.d_chans, X, A, C, L.ws);
+    if (!wait_pre()) return GT_ERR_HIP;
     GT_LAUNCH_SH(k_reduce_S2_mfma, dim3(3, L.n_channels), dim3(256), 0,
                  L.d_chans, L.ws);
     return GT_OK;
   }
   GT_LAUNCH_SH(k_fused_b, dim3(L.max_nsplit, L.n_channels), dim3(256), b_bytes(L), L.d_chans, X, A, C,
                L.ws);
+  if (!wait_pre()) return GT_ERR_HIP;
   GT_LAUNCH_SH(k_reduce_S2, dim3((L.max_nt * L.max_nt + 255) / 256, L.n_channels), dim3(256), 0,
                L.d_chans, L.ws);
   return GT_OK;

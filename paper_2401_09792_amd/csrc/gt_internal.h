@@ -150,6 +150,10 @@ struct SplitCtx {
   //    part k-1's (stag[k-1])
   int mode;
   hipEvent_t stag[3];
+  // mode 2 with the starting mode-2 factor made on the last part's stream: [0] the start of the
+  // fit on the caller's stream, [1] the mode-2 Gram of X reduced, [2] its eigensolve done,
+  // [3] the same passed on by the caller's stream
+  hipEvent_t init[4];
 };
 
 // kernel timing hooks (no-ops unless profiling is on)

@@ -124,6 +124,7 @@ struct gt_plan {
   hipStream_t side[3] = {nullptr, nullptr, nullptr};
   hipEvent_t ev_fork = nullptr, ev_join[3] = {nullptr, nullptr, nullptr};
   hipEvent_t ev_stag[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev_init[4] = {nullptr, nullptr, nullptr, nullptr};
   // pass variants chosen by gt_plan_autotune
   int tune_bstep = 0, tune_tpass = 0, tune_split = 2;
   // compact layout of the SINR adjoint's scratch alone (tables and dl/dHt), for the entry point
@@ -148,6 +149,8 @@ gt_plan::~gt_plan() {
     if (st) (void)hipStreamDestroy(st);
   if (ev_fork) (void)hipEventDestroy(ev_fork);
   for (hipEvent_t& e : ev_stag)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t& e : ev_init)
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t& e : ev_join)
     if (e) (void)hipEventDestroy(e);
@@ -715,6 +718,8 @@ static bool side_ready(gt_plan* p) {
   p->side_tried = true;
   const size_t ns = p->parts.size() - 1;
   bool ok = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) == hipSuccess;
+  for (hipEvent_t& e : p->ev_init)
+    ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
   for (size_t i = 0; ok && i < ns; ++i)
     ok = hipStreamCreateWithFlags(&p->side[i], hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&p->ev_join[i], hipEventDisableTiming) == hipSuccess &&
@@ -740,6 +745,7 @@ static gt_status run_fit(const gt_plan* plan, const void* X, void* A, void* B, v
   S.parts = P;
   S.fork = mp->ev_fork;
   S.mode = plan->tune_split;
+  for (int i = 0; i < 4; ++i) S.init[i] = mp->ev_init[i];
   for (int k = 0; k < S.n; ++k) {
     P[k] = make_ctx(plan->parts[k], ws, k == 0 ? stream : (void*)mp->side[k - 1]);
     P[k].c0 = plan->part_c0[k];
