@@ -1015,7 +1015,12 @@ __device__ __forceinline__ void bmm_store_hc(float* slot, int c, int nt, int m, 
 // floats when every channel of the launch fits it (a compile-time stride turns the slot
 // offsets into instruction immediates instead of per-lane addresses held across the group
 // loop), or 0 for the channel's own stride.
-template <int NT1W, int SMAX, bool PF, int PREC, int SLC>
+// QL (every channel m == nr <= 8, SLC 1024): each q slot holds the 8 x 128 real rows of Hc in
+// row quads, element (a, c') at (a / 4) 512 + 4 c' + a % 4, rows m..7 and columns past nt zero.
+// A lane then reads the four rows a K quad needs as one 16-byte load: the Gram takes its K
+// steps in the order 4 h + v (lane half h, step v) over the rows of each q, so that one q is
+// four products per tile fed by two loads, with no per-step address or mask arithmetic.
+template <int NT1W, int SMAX, bool PF, int PREC, int SLC, bool QL = false>
 __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* __restrict__ chans,
                                                        const float2* __restrict__ X,
                                                        const float2* __restrict__ A,
@@ -1039,8 +1044,15 @@ __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* _
   // m == nr: A is square and unitary (every B-step follows an eigensolve of the mode-1 Gram),
   // so W_q^H W_q = Hc_q^H A A^H Hc_q = Hc_q^H Hc_q: step 1 writes Hc in the layout step 3
   // reads and step 2 is skipped
-  const bool skip2 = m == nr;
-  if (skip2 && nt < 64) {  // the Gram reads 64 columns; those past nt stay zero
+  const bool skip2 = QL || m == nr;
+  if (QL) {
+    // rows m..7 and columns past nt of every slot stay zero (the Gram reads them)
+    if (m < 8 || nt < 64)
+      for (int e = tid; e < 16 * 1024; e += 512) {
+        const int o = e & 1023, a = ((o >> 9) << 2) | (o & 3), cc = (o & 511) >> 2;
+        if (a >= m || (cc & 63) >= nt) smf[e] = 0.f;
+      }
+  } else if (skip2 && nt < 64) {  // the Gram reads 64 columns; those past nt stay zero
     const int per = 2 * m * 64;
     for (int e = tid; e < (SLC ? 16 : p) * per; e += 512) {
       const int q = e / per, o = e - q * per;
@@ -1079,6 +1091,14 @@ __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* _
     for (int r = 0; r < 16; ++r) gacc[t][r] = 0.f;
   const int g0 = (int)((int64_t)split * ch.ngroups / ch.nsplit);
   const int g1 = (int)((int64_t)(split + 1) * ch.ngroups / ch.nsplit);
+  // QL: offset of this lane's step-1 output (q = 2 h, row i, real column j) for each of its
+  // column tiles c = 32 (wave + 8 u) + col = i nt + j
+  int qo[NT1W];
+#pragma unroll
+  for (int u = 0; u < NT1W; ++u) {
+    const int c = 32 * (wave + 8 * u) + col, i = c / nt, j = c - i * nt;
+    qo[u] = QL ? h * 2 * 1024 + (i >> 2) * 512 + 4 * j + (i & 3) : 0;
+  }
   float xp[SMAX][NT1W], cp[SMAX];
   if (PF && g0 < g1) bmm_prefetch<NT1W, SMAX>(xp, cp, X, C, ch, g0, nrnt, wave, col, h);
   __syncthreads();
@@ -1115,7 +1135,13 @@ __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* _
 #pragma unroll
           for (int r = 0; r < 16; r += 2) {
             const int q = 4 * (r / 4) + 2 * h + ((r % 4) >> 1);
-            if (SLC || q < pg) bmm_store_hc(smf + q * SL, c, nt, m, skip2, acc1[r], acc1[r + 1]);
+            if (QL) {
+              float* d = smf + qo[u] + (4 * (r / 4) + ((r % 4) >> 1)) * 1024;
+              d[0] = acc1[r];
+              d[256] = acc1[r + 1];
+            } else if (SLC || q < pg) {
+              bmm_store_hc(smf + q * SL, c, nt, m, skip2, acc1[r], acc1[r + 1]);
+            }
           }
       }
     } else {
@@ -1138,7 +1164,13 @@ __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* _
 #pragma unroll
           for (int r = 0; r < 16; r += 2) {
             const int q = 4 * (r / 4) + 2 * h + ((r % 4) >> 1);
-            if (SLC || q < pg) bmm_store_hc(smf + q * SL, c, nt, m, skip2, acc1[r], acc1[r + 1]);
+            if (QL) {
+              float* d = smf + qo[u] + (4 * (r / 4) + ((r % 4) >> 1)) * 1024;
+              d[0] = acc1[r];
+              d[256] = acc1[r + 1];
+            } else if (SLC || q < pg) {
+              bmm_store_hc(smf + q * SL, c, nt, m, skip2, acc1[r], acc1[r + 1]);
+            }
           }
       }
     }
@@ -1243,9 +1275,58 @@ __global__ void __launch_bounds__(512, PF ? 2 : 4) k_fused_b_mm(const DevChan* _
     }
     __syncthreads();
     }
-    // 3. Gram over the rows (q, a) of W, q < p_g, two rows a0 + h of one q per step (an
-    // odd m pads each q with a zero row); two steps per batch, loads unconditional
-    {
+    // 3. Gram over the rows (q, a) of W, q < p_g
+    if constexpr (QL) {
+      // row quads: per q, lane half h supplies rows 4 h + v at step v, so each tile takes
+      // four products per q from one 16-byte load of each operand; two q per batch (the
+      // second clamped, its products skipped past p_g), all branches wave-uniform
+      const int wu = __builtin_amdgcn_readfirstlane(wave);
+      int ol = lane;
+      asm volatile("" : "+v"(ol));
+      const int base = (ol >> 5) * 512 + 4 * (ol & 31);
+      int I0, J0, I1, J1;
+      gram_tile(wu, I0, J0);
+      gram_tile(8 + (wu & 1), I1, J1);
+      const float* pa0 = smf + base + 128 * I0;
+      const float* pb0 = smf + base + 128 * J0;
+      const float* pa1 = smf + base + 128 * I1;
+      const float* pb1 = smf + base + 128 * J1;
+      const bool t2 = wu < 4;
+      const int par = (wu >> 1) & 1;
+      for (int q = 0; q < pg; q += 2) {
+        const bool more = q + 1 < pg;
+        const int q1 = more ? q + 1 : q;
+        const float4 x0 = *reinterpret_cast<const float4*>(pa0 + q * 1024);
+        const float4 y0 = *reinterpret_cast<const float4*>(pb0 + q * 1024);
+        const float4 x1 = *reinterpret_cast<const float4*>(pa0 + q1 * 1024);
+        const float4 y1 = *reinterpret_cast<const float4*>(pb0 + q1 * 1024);
+        // the shared tile on the q of this wave's parity (waves 0, 1 even q, waves 2, 3 odd)
+        const int qt = par ? q1 : q;
+        float4 u0, w0;  // read and used by waves 0..3 only
+        if (t2) {
+          u0 = *reinterpret_cast<const float4*>(pa1 + qt * 1024);
+          w0 = *reinterpret_cast<const float4*>(pb1 + qt * 1024);
+        }
+        gacc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.x, y0.x, gacc[0], 0, 0, 0);
+        gacc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.y, y0.y, gacc[0], 0, 0, 0);
+        gacc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.z, y0.z, gacc[0], 0, 0, 0);
+        gacc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.w, y0.w, gacc[0], 0, 0, 0);
+        if (t2 && (par == 0 || more)) {
+          gacc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(u0.x, w0.x, gacc[1], 0, 0, 0);
+          gacc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(u0.y, w0.y, gacc[1], 0, 0, 0);
+          gacc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(u0.z, w0.z, gacc[1], 0, 0, 0);
+          gacc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(u0.w, w0.w, gacc[1], 0, 0, 0);
+        }
+        if (more) {
+          gacc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.x, y1.x, gacc[0], 0, 0, 0);
+          gacc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.y, y1.y, gacc[0], 0, 0, 0);
+          gacc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.z, y1.z, gacc[0], 0, 0, 0);
+          gacc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.w, y1.w, gacc[0], 0, 0, 0);
+        }
+      }
+    } else {
+    // two rows a0 + h of one q per step (an odd m pads each q with a zero row); two steps per
+    // batch, loads unconditional
       // per-lane offsets are derived here from an opaque copy of the lane index, so that the
       // compiler recomputes them per group instead of holding them across steps 1 and 2
       int ol = lane;
@@ -2180,10 +2261,14 @@ gt_status launch_fused_b(const LaunchCtx& L, const float2* X, const float2* A, c
     const size_t sh = bmm_bytes(L);
     const bool pf = L.tune_bstep == 1 && L.ttm_prec == GT_TTM_FP32;
     const bool slc = bmm_slc(L) != 0;
-#define GT_BMM_S(NT1W, SMAX, PF, PREC)                                                                     \
-  if (slc)                                                                                                 \
-    GT_LAUNCH_SH((k_fused_b_mm<NT1W, SMAX, PF, PREC, 1024>), grid, dim3(512), sh, L.d_chans, X, A, C, L.ws); \
-  else                                                                                                     \
+    // row-quad layout: every channel m == nr <= 8 (one 8 x 128 slot per q)
+    const bool ql = slc && L.full_mode1 && L.max_nr <= 8;
+#define GT_BMM_S(NT1W, SMAX, PF, PREC)                                                                           \
+  if (ql)                                                                                                        \
+    GT_LAUNCH_SH((k_fused_b_mm<NT1W, SMAX, PF, PREC, 1024, true>), grid, dim3(512), sh, L.d_chans, X, A, C, L.ws); \
+  else if (slc)                                                                                                  \
+    GT_LAUNCH_SH((k_fused_b_mm<NT1W, SMAX, PF, PREC, 1024>), grid, dim3(512), sh, L.d_chans, X, A, C, L.ws);       \
+  else                                                                                                           \
     GT_LAUNCH_SH((k_fused_b_mm<NT1W, SMAX, PF, PREC, 0>), grid, dim3(512), sh, L.d_chans, X, A, C, L.ws)
 #define GT_BMM(NT1W, SMAX, PREC)   \
   if (PREC == 0 && pf) {           \
