@@ -200,6 +200,30 @@ gt_status gt_sinr_eval_system(const gt_plan* plan, const void* C, const void* G,
                               int32_t n_snr, int32_t mode, void* sinr, int32_t* dev_status, void* ws,
                               size_t ws_bytes, void* stream);
 
+/* Channel matrices at general coefficient vectors (Section 2.2, equations "channel submatrices"
+ * and "channel submatrices, tensor"; Section 3.3, equation "compressed matrix SINR reduction").
+ * Mode 3 of X holds P path / delay submatrices H_s (nsc = P), and the channel at a time or
+ * frequency point t is their combination by a row u_t of P complex weights: the row c*(t) of
+ * the tensor form (pass u_t = c(t) to combine with the unconjugated coefficients of the
+ * submatrix equation instead).  For every channel and each of its n_pts rows:
+ *   gt_combine_full:        H(t)  = sum_s u_t[s] H_s                          (nr x nt)
+ *   gt_combine_compressed:  Ht(t) = G x3 (u_t C) = sum_g sum_q w_g,q(t) G_g[q],
+ *                           w_g,q(t) = sum_{s in group g} u_t[s] C[s,q]       (m x n)
+ * with H(t) ~ A Ht(t) B^H.  u_t = e_s gives H_s and the Ht_s of gt_tucker_reconstruct.
+ * Layouts, complex row-major, channels packed in order:
+ *   U   [n_pts][nsc] per channel, channel c at n_pts * offsets.sc;
+ *   H   [n_pts][nr][nt] per channel, channel c at n_pts * (sum of nr nt over channels < c);
+ *   Ht  [n_pts][m][n] per channel, channel c at n_pts * (sum of m n over channels < c).
+ * These are the X layouts of a plan with the descriptors (nr, nt, nsc = n_pts) or
+ * (nr = m, nt = n, nsc = n_pts) and the same ns, so gt_sinr_eval_full on such a plan gives the
+ * SINR of every combined channel (the compressed SINR of Section 3.3 is the same chain on
+ * Ht(t)).  GT_ERR_ARG: null pointer or n_pts outside 1..2^20; GT_ERR_UNSUPPORTED: a GT_C128
+ * plan. */
+gt_status gt_combine_full(const gt_plan* plan, const void* X, const void* U, int32_t n_pts, void* H,
+                          void* ws, size_t ws_bytes, void* stream);
+gt_status gt_combine_compressed(const gt_plan* plan, const void* C, const void* G, const void* U,
+                                int32_t n_pts, void* Ht, void* ws, size_t ws_bytes, void* stream);
+
 /* The same chain on the uncompressed channel H_s (nr x nt) read from X (Section 2.2). */
 gt_status gt_sinr_eval_full(const gt_plan* plan, const void* X, const float* sigma2, int32_t n_snr,
                             void* sinr, int32_t* dev_status, void* ws, size_t ws_bytes,

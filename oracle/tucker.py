@@ -176,6 +176,34 @@ def compressed_channels(C: np.ndarray, G: np.ndarray, gs: int) -> np.ndarray:
     return Ht
 
 
+def combine_full(X: np.ndarray, U: np.ndarray) -> np.ndarray:
+    """Channel matrices at general coefficient vectors (Section 2.2, equation "channel
+    submatrices, tensor"): H(t) = X x3 u_t = sum_s U[t, s] X_s, with u_t the combining row
+    (the row c^*(t) of the tensor form).  X [P][nr][nt], U [T][P]; returns [T][nr][nt]."""
+    T = U.shape[0]
+    H = np.zeros((T,) + X.shape[1:], dtype=np.complex128)
+    for t in range(T):
+        for s in range(X.shape[0]):
+            H[t] += U[t, s] * X[s]
+    return H
+
+
+def combine_compressed(C: np.ndarray, G: np.ndarray, gs: int, U: np.ndarray) -> np.ndarray:
+    """Compressed channel matrices at general coefficient vectors (Section 3.3, equation
+    "compressed matrix SINR reduction"): with the groupwise model X_g ~ G_g x1 A x2 Bt x3 C_g,
+    the combination of X by the row u_t is A Ht(t) B^H with
+    Ht(t) = sum_g G_g x3 (u_t,g C_g), u_t,g the entries of u_t on group g's submatrices.
+    C [P][p], G [groups][p][m][n], U [T][P]; returns [T][m][n]."""
+    T, P = U.shape
+    starts, sizes = group_layout(P, gs)
+    Ht = np.zeros((T,) + G.shape[2:], dtype=np.complex128)
+    for t in range(T):
+        for g, (s0, sz) in enumerate(zip(starts, sizes)):
+            row = U[t, s0:s0 + sz] @ C[s0:s0 + sz]     # u_t,g C_g  (length p)
+            Ht[t] += np.tensordot(row, G[g], axes=(0, 0))
+    return Ht
+
+
 def reconstruct(A, B, C, G, gs) -> Tuple[np.ndarray, np.ndarray]:
     """Compressed channels Ht [nsc][m][n] and the full reconstruction
     Xhat_g = G_g x1 A x2 Bt x3 C_g (tensor form, Bt = conj(B)) as [nsc][nr][nt]."""

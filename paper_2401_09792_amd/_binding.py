@@ -65,6 +65,11 @@ SIGNATURES = {
     "gt_sinr_eval_full": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_float), C.c_int32,
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                                     C.c_void_p]),
+    "gt_combine_full": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                  C.c_void_p, C.c_size_t, C.c_void_p]),
+    "gt_combine_compressed": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t,
+                                        C.c_void_p]),
     "gt_sinr_eval_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.POINTER(C.c_float), C.c_int32, C.c_void_p,
                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,

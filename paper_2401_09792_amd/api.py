@@ -240,6 +240,45 @@ class Plan:
             _stream()))
         return out
 
+    # -- channels at general coefficient vectors (mode 3 = path / delay submatrices) ----
+    def _weights(self, U, n_pts: int):
+        _buf(U, n_pts * self.totals.sc, self.cdtype, "U")
+
+    def combine_full(self, X, U, n_pts: int) -> torch.Tensor:
+        """H(t) = sum_s U[t, s] H_s for the n_pts weight rows of every channel (U packed
+        [n_pts][nsc] per channel); returns the packed [n_pts][nr][nt] blocks, the X layout of
+        `combined_descs(..., compressed=False)`."""
+        self._cx(X, "x", "X")
+        self._weights(U, n_pts)
+        out = self._new(n_pts * sum(d["nr"] * d["nt"] for d in self.descs))
+        check("gt_combine_full", self.lib.gt_combine_full(
+            self._h, _ptr(X), _ptr(U), int(n_pts), _ptr(out), _ptr(self.ws), self.ws_bytes,
+            _stream()))
+        return out
+
+    def combine_compressed(self, C_, G, U, n_pts: int) -> torch.Tensor:
+        """Ht(t) = G x3 (U[t] C) for the n_pts weight rows of every channel; returns the
+        packed [n_pts][m][n] blocks, the X layout of `combined_descs(..., compressed=True)`."""
+        self._cx(C_, "c", "C")
+        self._cx(G, "g", "G")
+        self._weights(U, n_pts)
+        out = self._new(n_pts * sum(d["m"] * d["n"] for d in self.descs))
+        check("gt_combine_compressed", self.lib.gt_combine_compressed(
+            self._h, _ptr(C_), _ptr(G), _ptr(U), int(n_pts), _ptr(out), _ptr(self.ws),
+            self.ws_bytes, _stream()))
+        return out
+
+    def combined_descs(self, n_pts: int, compressed: bool) -> List[dict]:
+        """Descriptors of a plan whose X layout is the output of combine_compressed
+        (compressed=True: nr = m, nt = n) or combine_full, with nsc = n_pts and the same ns:
+        its sinr_full gives the SINR of every combined channel."""
+        out = []
+        for d in self.descs:
+            r, t = (d["m"], d["n"]) if compressed else (d["nr"], d["nt"])
+            out.append(dict(nr=r, nt=t, nsc=int(n_pts), group_size=1, m=d["ns"], n=d["ns"], p=1,
+                            ns=d["ns"]))
+        return out
+
     def sinr_backward(self, C_, G, sigma2, grad_sinr, status=None):
         s2, k = self._sigma2(sigma2)
         self._cx(C_, "c", "C")

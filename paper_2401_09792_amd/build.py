@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT_DIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(OUT_DIR, "libgtucker.so")
-SOURCES = ["gt_plan.cpp", "gt_fit.hip", "gt_fit_fused.hip", "gt_eig_sub.hip", "gt_sinr.hip", "gt_sinr_rows.hip", "gt_system.hip", "gt_rec.hip"]
+SOURCES = ["gt_plan.cpp", "gt_fit.hip", "gt_fit_fused.hip", "gt_eig_sub.hip", "gt_sinr.hip", "gt_sinr_rows.hip", "gt_system.hip", "gt_rec.hip", "gt_combine.hip"]
 
 ARCH = os.environ.get("GT_OFFLOAD_ARCH", "gfx950")
 FLAGS = [

@@ -13,6 +13,7 @@ constexpr int kMaxNr = 16;        // receive antennas, also bounds m
 constexpr int kMaxNt = 64;        // transmit antennas handled by the Jacobi mode-2 eigensolver
 constexpr int kMaxGroup = 32;     // subcarriers per group, also bounds p
 constexpr int kMaxSnr = 16;
+constexpr int kMaxCombinePts = 1 << 20;  // points per call of the coefficient-vector combinations
 
 // Per-channel descriptor as the kernels see it (lives in the workspace).
 struct DevChan {
@@ -44,6 +45,9 @@ struct DevChan {
   int64_t w_gH;    // [nsc][m][n]         c64   per-subcarrier gradient of Ht
   int64_t w_gAp;   // [ngroups][nr][m]    c64   per-group partial gradient of A
   int64_t w_gBp;   // [ngroups][nt][n]    c64   per-group partial gradient of B
+  // prefix sums over the preceding channels of m n and nr nt: a channel's block in the
+  // combined-matrix layouts starts at n_pts times these
+  int64_t mn_off, rt_off;
 };
 
 struct GroupItem {

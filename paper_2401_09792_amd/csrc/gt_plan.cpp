@@ -34,6 +34,10 @@ gt_status launch_sinr_bwd(const LaunchCtx& L, int64_t total_sc, const float2* C,
 gt_status launch_sinr_system(const LaunchCtx& L, int64_t total_sc, const int32_t* terms_off,
                              const int32_t* terms, const float2* C, const float2* G,
                              const float* s2, int n_snr, float* out, int ns_max, int32_t* status);
+gt_status launch_combine_core(const LaunchCtx& L, int n_pts, const float2* C, const float2* G,
+                              const float2* U, float2* Ht);
+gt_status launch_combine_full(const LaunchCtx& L, int n_pts, const float2* X, const float2* U,
+                              float2* H);
 gt_status launch_sinr_c128(const LaunchCtx& L, int64_t total_sc, bool full, const double2* X,
                            const double2* C, const double2* G, const float* s2, int n_snr,
                            double* out, int ns_max, int32_t* status);
@@ -224,7 +228,7 @@ static gt_status plan_build(const gt_channel_desc* descs, int32_t n_channels,
   p->desc.assign(descs, descs + n_channels);
   p->opt = o;
   p->chans.resize(n_channels);
-  int64_t ox = 0, oa = 0, ob = 0, oc = 0, og = 0, oht = 0, osc = 0;
+  int64_t ox = 0, oa = 0, ob = 0, oc = 0, og = 0, oht = 0, osc = 0, omn = 0, ort = 0;
   int gfirst = 0;
   p->max_nr = p->max_nt = p->max_nsc = p->max_gs = p->max_m = p->max_n = p->max_p = p->max_ns = 0;
   p->max_groups = p->max_nsplit = 0;
@@ -251,6 +255,10 @@ static gt_status plan_build(const gt_channel_desc* descs, int32_t n_channels,
     ch.g = og;
     ch.ht = oht;
     ch.sc = osc;
+    ch.mn_off = omn;
+    ch.rt_off = ort;
+    omn += (int64_t)d.m * d.n;
+    ort += (int64_t)d.nr * d.nt;
     ox += (int64_t)d.nsc * d.nr * d.nt;
     oa += (int64_t)d.nr * d.m;
     ob += (int64_t)d.nt * d.n;
@@ -913,6 +921,27 @@ gt_status gt_sinr_eval_system(const gt_plan* plan, const void* C, const void* G,
   const int32_t* terms = reinterpret_cast<const int32_t*>(L.ws + plan->lay.sys_terms[mode]);
   return launch_sinr_system(L, plan->totals.sc, toff, terms, (const float2*)C, (const float2*)G,
                             sigma2, n_snr, (float*)sinr, plan->ns_max, dev_status);
+}
+
+gt_status gt_combine_compressed(const gt_plan* plan, const void* C, const void* G, const void* U,
+                                int32_t n_pts, void* Ht, void* ws, size_t ws_bytes, void* stream) {
+  gt_status st = check_ws(plan, ws, ws_bytes);
+  if (st != GT_OK) return st;
+  if (!C || !G || !U || !Ht || n_pts < 1 || n_pts > kMaxCombinePts) return GT_ERR_ARG;
+  if (plan->opt.dtype != GT_C64) return GT_ERR_UNSUPPORTED;
+  LaunchCtx L = make_ctx(plan, ws, stream);
+  return launch_combine_core(L, n_pts, (const float2*)C, (const float2*)G, (const float2*)U,
+                             (float2*)Ht);
+}
+
+gt_status gt_combine_full(const gt_plan* plan, const void* X, const void* U, int32_t n_pts, void* H,
+                          void* ws, size_t ws_bytes, void* stream) {
+  gt_status st = check_ws(plan, ws, ws_bytes);
+  if (st != GT_OK) return st;
+  if (!X || !U || !H || n_pts < 1 || n_pts > kMaxCombinePts) return GT_ERR_ARG;
+  if (plan->opt.dtype != GT_C64) return GT_ERR_UNSUPPORTED;
+  LaunchCtx L = make_ctx(plan, ws, stream);
+  return launch_combine_full(L, n_pts, (const float2*)X, (const float2*)U, (float2*)H);
 }
 
 gt_status gt_sinr_eval_full(const gt_plan* plan, const void* X, const float* sigma2, int32_t n_snr,

@@ -20,4 +20,7 @@ from .channels import (  # noqa: F401
     snr_to_sigma2,
     system_links,
     make_system,
+    draw_submatrix_paths,
+    build_submatrices,
+    submatrix_weights,
 )

@@ -212,6 +212,63 @@ def make_system(J: int, K: int, nr: int, nt: int, nsc: int, n_paths: int, k_db: 
     return out
 
 
+def draw_submatrix_paths(rng: np.random.Generator, n_clusters: int = 20, rays: int = 20,
+                         k_db: float = 6.0, spread_deg: float = 2.0,
+                         max_delay: float = 16.0) -> PathParams:
+    """Rays of a clustered multipath channel, one channel submatrix per ray (the structure of
+    the paper's channel-submatrix equation, Section 2.2, with P = n_clusters * rays + 1; the
+    paper's 3GPP channels have P = 401, which the defaults give).  Stand-in for TR 38.901:
+    cluster angles U(-60 deg, 60 deg), ray angles the cluster's plus N(0, spread_deg), cluster
+    delays U(0, max_delay) samples with ray jitter U(0, 0.5), cluster powers proportional to
+    exp(-delay / 4) summing to 1/(K+1), ray gains CN(0, cluster power / rays), and the LOS ray
+    (gain sqrt(K/(K+1)) e^{j psi}, delay 0) last.  Ray l of cluster k sits at index k rays + l,
+    so that groups of `rays` consecutive submatrices are the clusters.
+
+    Draw order: cluster theta, phi, delay [n_clusters]; ray theta and phi offsets and delay
+    jitter [n_clusters * rays]; psi, LOS theta, LOS phi; then the ray gains' real and
+    imaginary parts."""
+    nc, nrays = int(n_clusters), int(rays)
+    lim = math.radians(60.0)
+    sp = math.radians(spread_deg)
+    ct = rng.uniform(-lim, lim, size=nc)
+    cp = rng.uniform(-lim, lim, size=nc)
+    cd = rng.uniform(0.0, max_delay, size=nc)
+    dt = rng.standard_normal(nc * nrays) * sp
+    dp = rng.standard_normal(nc * nrays) * sp
+    dj = rng.uniform(0.0, 0.5, size=nc * nrays)
+    psi = rng.uniform(0.0, 2.0 * math.pi)
+    los_t = rng.uniform(-lim, lim)
+    los_p = rng.uniform(-lim, lim)
+    re = rng.standard_normal(nc * nrays)
+    im = rng.standard_normal(nc * nrays)
+    kf = 10.0 ** (k_db / 10.0)
+    pw = np.exp(-cd / 4.0)
+    pw = pw / pw.sum() / (kf + 1.0)
+    ray_pw = np.repeat(pw / nrays, nrays)
+    theta = np.concatenate([np.repeat(ct, nrays) + dt, [los_t]])
+    phi = np.concatenate([np.repeat(cp, nrays) + dp, [los_p]])
+    tau = np.concatenate([np.repeat(cd, nrays) + dj, [0.0]])
+    alpha = np.concatenate([np.sqrt(ray_pw / 2.0) * (re + 1j * im),
+                            [math.sqrt(kf / (kf + 1.0)) * np.exp(1j * psi)]])
+    return PathParams(theta, phi, tau, alpha)
+
+
+def build_submatrices(pp: PathParams, nr: int, nt: int) -> np.ndarray:
+    """Channel submatrices at the reference time, one per ray: X_l = alpha_l a_r(theta_l)
+    a_t(phi_l)^H, laid out [P][nr][nt] (mode 3 = submatrices), complex128."""
+    ar = _steering(nr, pp.theta)
+    at = _steering(nt, pp.phi)
+    return np.einsum("l,il,jl->lij", pp.alpha, ar, at.conj(), optimize=True)
+
+
+def submatrix_weights(pp: PathParams, n_pts: int, n_fft: int) -> np.ndarray:
+    """Combining rows u_t[l] = exp(-j 2 pi t tau_l / n_fft) for the points t = 0..n_pts-1 of an
+    n_fft-point OFDM grid, [n_pts][P]: combining the submatrices with them gives the channel
+    at subcarrier t."""
+    t = np.arange(int(n_pts))[:, None]
+    return np.exp(-2j * math.pi * t * pp.tau[None, :] / float(n_fft))
+
+
 def snr_to_sigma2(snr_db: Sequence[float]) -> np.ndarray:
     """Noise variance for unit average channel gain and unit power per stream."""
     return 10.0 ** (-np.asarray(snr_db, dtype=np.float64) / 10.0)

@@ -117,6 +117,13 @@ def test_calls_reject_bad_workspace_without_launching(lib):
     neg = (C.c_float * 1)(-1.0)
     assert lib.gt_sinr_eval(h, dummy, dummy, neg, 1, dummy, None, dummy, wsb.value, None) == 1
     assert lib.gt_tucker_fit_backward(h) == 5
+    # the coefficient-vector combinations check the workspace, the pointers and n_pts first
+    assert lib.gt_combine_full(h, dummy, dummy, 4, dummy, None, 0, None) == 4
+    assert lib.gt_combine_compressed(h, dummy, dummy, dummy, 4, dummy, None, 0, None) == 4
+    assert lib.gt_combine_full(h, dummy, dummy, 0, dummy, dummy, wsb.value, None) == 1
+    assert lib.gt_combine_full(h, None, dummy, 4, dummy, dummy, wsb.value, None) == 1
+    assert lib.gt_combine_compressed(h, dummy, dummy, dummy, (1 << 20) + 1, dummy, dummy,
+                                     wsb.value, None) == 1
     lib.gt_plan_destroy(h)
 
 

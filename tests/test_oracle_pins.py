@@ -384,3 +384,48 @@ def test_generator_torch_matches_numpy():
     a = synthgen.build_channel(pp, cfg.nr, cfg.nt, cfg.nsc)
     b = synthgen.build_channel_torch(pp, cfg.nr, cfg.nt, cfg.nsc, "cpu").numpy()
     np.testing.assert_allclose(a, b, atol=1e-12)
+
+
+# ----------------------------------------------------------------------------------------
+# Channels at general coefficient vectors (mode 3 = path / delay submatrices)
+
+
+def test_combine_selector_rows_give_slices_and_compressed_channels():
+    # u_t = e_s picks the slice H_s (equation "channel submatrices, tensor") and the compressed
+    # channel Ht_s of equation "compressed matrix SINR reduction" with a selector c
+    rng = np.random.default_rng(71)
+    X, A, B, C, G = synthgen.planted_tucker(rng, 4, 6, 11, 4, 3, 4, 3)
+    eye = np.eye(11, dtype=np.complex128)
+    np.testing.assert_array_equal(tucker.combine_full(X, eye), X)
+    np.testing.assert_allclose(tucker.combine_compressed(C, G, 4, eye),
+                               tucker.compressed_channels(C, G, 4), rtol=0, atol=1e-14)
+
+
+def test_combine_exact_model_factors_cancel():
+    # on a tensor that the groupwise model holds exactly (built slice by slice by the
+    # generator), combining the submatrices by any rows equals A Ht(t) B^H with Ht(t) combined
+    # from the factors: the identity behind equation "compressed matrix SINR reduction"
+    rng = np.random.default_rng(72)
+    X, A, B, C, G = synthgen.planted_tucker(rng, 5, 7, 23, 6, 3, 4, 4)  # ragged last group
+    U = crandn(rng, 9, 23)
+    H = tucker.combine_full(X, U)
+    Ht = tucker.combine_compressed(C, G, 6, U)
+    assert Ht.shape == (9, 3, 4)
+    for t in range(9):
+        np.testing.assert_allclose(A @ Ht[t] @ B.conj().T, H[t], rtol=0,
+                                   atol=1e-12 * np.abs(H[t]).max())
+    # and the combination is linear in the rows
+    U2 = crandn(rng, 9, 23)
+    np.testing.assert_allclose(tucker.combine_compressed(C, G, 6, U + 2j * U2),
+                               Ht + 2j * tucker.combine_compressed(C, G, 6, U2), atol=1e-12)
+
+
+def test_submatrix_weights_rebuild_the_ofdm_channel():
+    # combining the ray submatrices with u_t[l] = exp(-j 2 pi t tau_l / N) gives the channel
+    # at subcarrier t of the same rays (the channel-submatrix equation of Section 2.2), which
+    # build_channel assembles independently
+    pp = synthgen.draw_submatrix_paths(synthgen.channel_rng(9, 0), n_clusters=3, rays=4)
+    X = synthgen.build_submatrices(pp, 4, 8)
+    assert X.shape == (13, 4, 8)
+    H = tucker.combine_full(X, synthgen.submatrix_weights(pp, 16, 16))
+    np.testing.assert_allclose(H, synthgen.build_channel(pp, 4, 8, 16), atol=1e-12)
