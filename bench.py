@@ -356,6 +356,69 @@ def time_models(api, synthgen, torch, dev, reps=5):
                 rank_sweep_groupwise=sweep)
 
 
+def time_submatrix(api, synthgen, torch, dev, reps=5):
+    """The paper's 8 x 256 x 401 shape with mode 3 = path / delay submatrices (Section 2.2):
+    8 channels of clustered rays (20 clusters x 20 rays + LOS, one submatrix per ray), groups of
+    20 (one cluster each, the LOS alone), ranks (8, 48, 12), 10 sweeps, Ns 4 at 10 dB.  The
+    channels are evaluated at 512 OFDM points (combining rows exp(-j 2 pi t tau_l / 512)):
+    compressed = combine the factors (equation "compressed matrix SINR reduction") + the SINR
+    chain on the m x n channels; full = combine the submatrices + the chain on the nr x nt
+    channels.  R_t = full time / compressed time, e_c = mean relative SINR error of the
+    compressed evaluation (equation "SINR error"), R_s = stored elements of X / of the
+    factors and cores (equation "compression ratio" for one link)."""
+    import numpy as np
+
+    nch, nr, nt, gs, m, n, p, ns, iters, n_pts = 8, 8, 256, 20, 8, 48, 12, 4, 10, 512
+    s2 = [float(v) for v in synthgen.snr_to_sigma2([10.0])]
+    pps = [synthgen.draw_submatrix_paths(synthgen.channel_rng(12, c)) for c in range(nch)]
+    X = torch.cat([torch.as_tensor(synthgen.build_submatrices(pp, nr, nt).reshape(-1),
+                                   dtype=torch.complex64) for pp in pps]).to(dev)
+    U = torch.cat([torch.as_tensor(synthgen.submatrix_weights(pp, n_pts, 512).reshape(-1),
+                                   dtype=torch.complex64) for pp in pps]).to(dev)
+    P = 20 * 20 + 1
+    plan = api.Plan([dict(nr=nr, nt=nt, nsc=P, group_size=gs, m=m, n=n, p=p, ns=ns)] * nch,
+                    iters=iters)
+    f = plan.empty_factors()
+    comp_plan = api.Plan(plan.combined_descs(n_pts, compressed=True), iters=0)
+    full_plan = api.Plan(plan.combined_descs(n_pts, compressed=False), iters=0)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            out = fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ts.sort()
+        return ts[len(ts) // 2], out
+
+    ms_fit, r = timed(lambda: plan.fit(X, factors=f, trace=False))
+    ms_comb_c, Ht = timed(lambda: plan.combine_compressed(f["C"], f["G"], U, n_pts))
+    ms_comb_f, H = timed(lambda: plan.combine_full(X, U, n_pts))
+    ms_sinr_c, sc = timed(lambda: comp_plan.sinr_full(Ht, s2))
+    ms_sinr_f, sf = timed(lambda: full_plan.sinr_full(H, s2))
+    a, b = sc.cpu().numpy().astype(np.float64), sf.cpu().numpy().astype(np.float64)
+    live = (a > 0) & (b > 0)
+    ng = -(-P // gs)
+    stored = nr * m + nt * n + sum(min(gs, P - g * gs) * min(p, min(gs, P - g * gs))
+                                   + m * n * min(p, min(gs, P - g * gs)) for g in range(ng))
+    ms_c, ms_f = ms_comb_c + ms_sinr_c, ms_comb_f + ms_sinr_f
+    return dict(
+        workload="8 x (8 x 256 x 401) submatrix tensors (20 clusters x 20 rays + LOS), groups of "
+                 "20, ranks (8, 48, 12), 10 sweeps, 512 OFDM points, Ns 4 at 10 dB",
+        fits_per_s=nch / (ms_fit / 1e3), ms_fit=ms_fit,
+        ms_compressed=ms_c, ms_combine_compressed=ms_comb_c, ms_sinr_compressed=ms_sinr_c,
+        ms_full=ms_f, ms_combine_full=ms_comb_f, ms_sinr_full=ms_sinr_f,
+        R_t=ms_f / ms_c, R_s=P * nr * nt / stored, e_c=float(np.mean(np.abs(a[live] - b[live]) / b[live])),
+        evals_per_s_compressed=nch * n_pts / (ms_c / 1e3),
+        status_ok=bool((r["status"] == 0).all()))
+
+
 def time_forms(api, synthgen, cfg, X, B, s2, ms_fp32, sg_fp32, torch, steps):
     """The precision, batched (graph replay) and differentiation forms on the same GPU:
     throughput of fit + SINR (eager FP32 first, as the reference) and SINR error against the
@@ -816,6 +879,7 @@ def main():
     if not args.no_forms and not wide and not args.steps_only:
         forms = time_forms(api, synthgen, cfg, X, B, s2, ms_step, sg, torch, max(args.steps, 2))
         forms["compression_models"] = time_models(api, synthgen, torch, dev)
+        forms["paper_submatrix_8x256x401"] = time_submatrix(api, synthgen, torch, dev)
 
     line = {
         "metric": "subcarrier SINR evals/sec + Tucker fits/sec at <=0.1 dB err vs FP64 oracle",

@@ -23,65 +23,76 @@ __device__ __forceinline__ void cfma2(float2& acc, float2 a, float2 b) {
   acc.y += a.x * b.y + a.y * b.x;
 }
 
-// Compressed combination: one block per (tile of kCombPts points, channel).  Per group the
-// block forms w_g(t) for its points in LDS (one (t, q) per thread, a dot product over the
-// group's rows), then every thread adds, for its entries e of the m x n matrix,
-// sum_q w_g,q(t) G_g[q][e] to its kCombPts accumulators: each core entry is read once per
-// tile of points.
-constexpr int kCombPts = 8;
-constexpr int kCombEnt = (kMaxNr * 64 + 255) / 256;  // entries per thread (m n <= 16 x 64)
-
+// Compressed combination, a product per channel Ht (n_pts x m n) = W (n_pts x groups p) times
+// the stacked cores (groups p x m n), with W's columns of group g, w_g(t) = u_t,g C_g, formed
+// per group in LDS: block tile 32 points x 64 entries; per group the block stages its 32 rows
+// of U on the group (up to 32 submatrices) and C_g, forms the 32 x p_g weights (a dot product
+// over the group per weight), stages G_g's p_g x 64 tile and accumulates.  Thread (ty, tx)
+// owns points ty, ty + 16 and entries tx + 16 j.
 __global__ void __launch_bounds__(256) k_combine_core(const DevChan* __restrict__ chans, int n_pts,
                                                       const float2* __restrict__ C,
                                                       const float2* __restrict__ G,
                                                       const float2* __restrict__ U,
                                                       float2* __restrict__ Ht) {
-  const DevChan& ch = chans[blockIdx.y];
-  const int t0 = blockIdx.x * kCombPts;
-  if (t0 >= n_pts) return;
-  __shared__ float2 w[kCombPts][kMaxGroup];
-  const int tid = threadIdx.x;
+  const DevChan& ch = chans[blockIdx.z];
   const int mn = ch.m * ch.n, p = ch.p, nsc = ch.nsc;
+  const int e0 = blockIdx.x * 64, t0 = blockIdx.y * 32;
+  if (e0 >= mn || t0 >= n_pts) return;
+  __shared__ float2 us[32][kMaxGroup + 1];
+  __shared__ float2 cs[kMaxGroup][kMaxGroup + 1];
+  __shared__ float2 ws[32][kMaxGroup + 1];
+  __shared__ float2 gs_[kMaxGroup][64];
+  const int tid = threadIdx.x, ty = tid / 16, tx = tid % 16;
   const float2* Uc = U + (int64_t)ch.sc * n_pts;
-  const float2* Cc = C + ch.c;
-  float2 acc[kCombEnt][kCombPts];
+  float2 acc[2][4];
 #pragma unroll
-  for (int k = 0; k < kCombEnt; ++k)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int t = 0; t < kCombPts; ++t) acc[k][t] = make_float2(0.f, 0.f);
+    for (int j = 0; j < 4; ++j) acc[i][j] = make_float2(0.f, 0.f);
   for (int g = 0; g < ch.ngroups; ++g) {
     const int s0 = g * ch.gs, sz = min(ch.gs, nsc - s0), pg = min(p, sz);
-    if (tid < kCombPts * pg) {
-      const int t = tid / pg, q = tid - t * pg;
-      float2 v = make_float2(0.f, 0.f);
-      if (t0 + t < n_pts) {
-        const float2* ur = Uc + (int64_t)(t0 + t) * nsc + s0;
-        for (int s = 0; s < sz; ++s) cfma2(v, ur[s], Cc[(int64_t)(s0 + s) * p + q]);
-      }
-      w[t][q] = v;
+    for (int idx = tid; idx < 32 * sz; idx += 256) {
+      const int r = idx / sz, k = idx - r * sz;
+      us[r][k] = t0 + r < n_pts ? Uc[(int64_t)(t0 + r) * nsc + s0 + k] : make_float2(0.f, 0.f);
+    }
+    for (int idx = tid; idx < sz * pg; idx += 256) {
+      const int k = idx / pg, q = idx - k * pg;
+      cs[k][q] = C[ch.c + (int64_t)(s0 + k) * p + q];
+    }
+    const float2* Gg = G + ch.g + (int64_t)g * p * mn;
+    for (int idx = tid; idx < pg * 64; idx += 256) {
+      const int q = idx / 64, c = idx % 64;
+      gs_[q][c] = e0 + c < mn ? Gg[(int64_t)q * mn + e0 + c] : make_float2(0.f, 0.f);
     }
     __syncthreads();
-    const float2* Gg = G + ch.g + (int64_t)g * p * mn;
+    for (int idx = tid; idx < 32 * pg; idx += 256) {
+      const int r = idx / pg, q = idx - r * pg;
+      float2 v = make_float2(0.f, 0.f);
+      for (int k = 0; k < sz; ++k) cfma2(v, us[r][k], cs[k][q]);
+      ws[r][q] = v;
+    }
+    __syncthreads();
+    for (int q = 0; q < pg; ++q) {
+      const float2 w0 = ws[ty][q], w1 = ws[ty + 16][q];
 #pragma unroll
-    for (int k = 0; k < kCombEnt; ++k) {
-      const int e = tid + 256 * k;
-      if (e < mn)
-        for (int q = 0; q < pg; ++q) {
-          const float2 gv = Gg[(int64_t)q * mn + e];
-#pragma unroll
-          for (int t = 0; t < kCombPts; ++t) cfma2(acc[k][t], w[t][q], gv);
-        }
+      for (int j = 0; j < 4; ++j) {
+        const float2 gv = gs_[q][tx + 16 * j];
+        cfma2(acc[0][j], w0, gv);
+        cfma2(acc[1][j], w1, gv);
+      }
     }
     __syncthreads();
   }
   float2* out = Ht + ch.mn_off * n_pts;
 #pragma unroll
-  for (int k = 0; k < kCombEnt; ++k) {
-    const int e = tid + 256 * k;
-    if (e < mn)
+  for (int i = 0; i < 2; ++i) {
+    const int t = t0 + ty + 16 * i;
+    if (t < n_pts)
 #pragma unroll
-      for (int t = 0; t < kCombPts; ++t)
-        if (t0 + t < n_pts) out[(int64_t)(t0 + t) * mn + e] = acc[k][t];
+      for (int j = 0; j < 4; ++j) {
+        const int e = e0 + tx + 16 * j;
+        if (e < mn) out[(int64_t)t * mn + e] = acc[i][j];
+      }
   }
 }
 
@@ -159,8 +170,8 @@ __global__ void __launch_bounds__(256) k_combine_full(const DevChan* __restrict_
 
 gt_status launch_combine_core(const LaunchCtx& L, int n_pts, const float2* C, const float2* G,
                               const float2* U, float2* Ht) {
-  const unsigned nb = (unsigned)((n_pts + kCombPts - 1) / kCombPts);
-  GT_LAUNCH(k_combine_core, dim3(nb, L.n_channels), dim3(256), L.d_chans, n_pts, C, G, U, Ht);
+  const unsigned ex = (unsigned)((L.max_m * L.max_n + 63) / 64), ty = (unsigned)((n_pts + 31) / 32);
+  GT_LAUNCH(k_combine_core, dim3(ex, ty, L.n_channels), dim3(256), L.d_chans, n_pts, C, G, U, Ht);
   return GT_OK;
 }
 
