@@ -141,13 +141,52 @@ __global__ void __launch_bounds__(256) k_fused_t(const DevChan* __restrict__ cha
   group_gram_s3(Yh, wsp2(ws, ch.w_S3) + (int64_t)it.g * ch.gs * ch.gs, ch.gs, sz, m * n, tid);
 }
 
+// The group's mode-3 Gram on matrix cores, for gs <= 16 and m n a multiple of 8, by four waves:
+// the real Gram P = R^T R of the mn x 32 matrix R[e][c] = Re Yh_c[e] (c < gs), Im Yh_{c-gs}[e]
+// (gs <= c < 2 gs), zero for other c and for subcarriers past the group, with the mn entries
+// split over the waves (32 x 32 x 2 products, one operand register for both sides).  The
+// waves' partials go through `part` (4 x 1024 floats, which may alias Yh: the waves are past
+// their reads of Yh before it is written), then S3[s][t] = sum_e Yh_s[e] conj(Yh_t[e]) =
+// (P[s][t] + P[gs+s][gs+t]) + i (P[gs+s][t] - P[s][gs+t]).  Yh rows start ys apart.
+__device__ __forceinline__ void group_gram_s3_mfma(const float2* Yh, int ys, float* part, float2* S3,
+                                                   int gs, int sz, int mn, int tid) {
+  const int wave = tid / 64, lane = tid % 64, c = lane % 32, h = lane / 32;
+  const int sl = c < gs ? c : c - gs;
+  const bool live = c < 2 * gs && sl < sz;
+  const float* yb = reinterpret_cast<const float*>(Yh + (live ? sl : 0) * ys) + (c < gs ? 0 : 1);
+  const int kq = mn / 4, e0 = wave * kq;
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+  for (int k = 0; k < kq; k += 2) {
+    const float v0 = yb[2 * (e0 + k + h)];
+    const float v = live ? v0 : 0.f;
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(v, v, acc, 0, 0, 0);
+  }
+  __syncthreads();  // every wave has read its entries of Yh
+  // accumulator layout: lane l, register r -> row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32
+#pragma unroll
+  for (int r = 0; r < 16; ++r) part[wave * 1024 + (8 * (r / 4) + 4 * h + (r % 4)) * 32 + c] = acc[r];
+  __syncthreads();
+  auto P = [&](int i, int j) {
+    const int o = i * 32 + j;
+    return (part[o] + part[1024 + o]) + (part[2048 + o] + part[3072 + o]);
+  };
+  for (int o = tid; o < gs * gs; o += 256) {
+    const int s = o / gs, t = o - s * gs;
+    S3[o] = make_float2(P(s, t) + P(gs + s, gs + t), P(gs + s, t) - P(s, gs + t));
+  }
+}
+
 // The part of the T pass after the product: T (accumulators of 32 x 32 tiles over rows (s, i)
 // and the 2 n real columns) to LDS and the workspace, then for a C-step Yh = A^H T and the
 // group's mode-3 Gram.
+// yh_cap: complex elements of LDS from Yh on that the caller owns (the matrix-core Gram writes
+// its partials there).
 template <int TPW>
 __device__ __forceinline__ void fused_t_finish(const DevChan& ch, const GroupItem& it, int s0, int sz,
                                                int rows, int ntile, float2* Ts, float2* Yh,
-                                               const float2* As, char* ws, int do_c,
+                                               int yh_cap, const float2* As, char* ws, int do_c,
                                                f32x16 (&acc)[TPW], int wave, int half, int col,
                                                int tid) {
   const int nr = ch.nr, m = ch.m, n = ch.n;
@@ -248,12 +287,14 @@ __device__ __forceinline__ void fused_t_finish(const DevChan& ch, const GroupIte
     }
   }
   __syncthreads();
-  // S3[s][t] = <Yh_s, Yh_t> on the upper triangle (16 lanes per entry), mirrored below (zero
-  // where t is past the group).  On matrix cores this Gram used two waves of the four and made
-  // the split fit slower; the vector form keeps all four busy.
+  // S3[s][t] = <Yh_s, Yh_t>: on matrix cores split over the four waves where the shapes allow
+  // (Yh sits in region 0, which also holds the waves' partials), else on the vector ALU on the
+  // upper triangle (16 lanes per entry), mirrored below (zero where t is past the group)
   const int gs = ch.gs, mn = m * n;
   float2* S3 = wsp2(ws, ch.w_S3) + (int64_t)it.g * gs * gs;
-  {
+  if (gs <= 16 && (mn & 7) == 0 && yh_cap >= 2048) {
+    group_gram_s3_mfma(Yh, ys, reinterpret_cast<float*>(Yh), S3, gs, sz, mn, tid);
+  } else {
     const int l16 = tid % 16;
     for (int k = tid / 16; k < gs * (gs + 1) / 2; k += 16) {
       int s = 0, rem = k;
@@ -411,7 +452,8 @@ __global__ void __launch_bounds__(256, 4) k_fused_t_mfma(const DevChan* __restri
       }
     }
   }
-  fused_t_finish<TPW>(ch, it, s0, sz, rows, ntile, Ts, Yh, As, ws, do_c, acc, wave, half, col, tid);
+  fused_t_finish<TPW>(ch, it, s0, sz, rows, ntile, Ts, Yh, reg0, As, ws, do_c, acc, wave, half, col,
+                      tid);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -544,7 +586,8 @@ __global__ void __launch_bounds__(256) k_fused_t_lp(const DevChan* __restrict__ 
       }
     }
   }
-  fused_t_finish<1>(ch, it, s0, sz, rows, ntile, Ts, Yh, As, ws, do_c, acc, wave, half, col, tid);
+  fused_t_finish<1>(ch, it, s0, sz, rows, ntile, Ts, Yh, ch.gs * (m * n + 2), As, ws, do_c, acc, wave,
+                    half, col, tid);
 }
 
 // k_fused_z, one block per group, after the mode-3 eigensolve: the A-step partial Gram
