@@ -387,11 +387,15 @@ __global__ void __launch_bounds__(64, (sizeof(T) == 4 && MP == 16) ? 2 : 1) k_ei
   }
 }
 
-// Warm mode-2 solve by Rayleigh-Ritz on the previous call's top-n basis (FP32, nt <= 64,
-// n <= 16), one 256-thread block per channel.  With Bp the current B (the last solve's n leading
-// eigenvectors of this channel's Gram family): Y = S2 Bp, H = Bp^H Y, H = U diag(theta) U^H, the
+// Mode-2 solve by Rayleigh-Ritz (FP32, nt <= 64, n <= 16), one 256-thread block per channel, on
+// the previous call's top-n basis (warm: Bp the current B, the last solve's n leading
+// eigenvectors of this channel's Gram family) or on an orthonormal basis of S2 Omega (cold, see
+// eigB_cold_block): Y = S2 Bp, H = Bp^H Y, H = U diag(theta) U^H, the
 // residual R = Y - Bp H.  The Ritz pairs (Bp U, theta) are the n leading eigenpairs of S2 to FP32
-// accuracy when ||R||_F <= 5e-6 theta_max (Bp spans an invariant subspace) and the complement's
+// accuracy when every Ritz vector z_j = Bp U[:, j] has ||S2 z_j - theta_j z_j|| <= 1e-5 theta_max
+// (Bp spans an invariant subspace of a Gram within that distance of S2, which is about the
+// rounding S2 itself carries after its FP32 accumulation over every subcarrier; the residual of
+// z_j is the norm of R U[:, j]) and the complement's
 // trace tr(S2) - sum(theta) does not exceed theta_min + 1e-5 tr(S2) (no eigenvalue outside that
 // subspace lies above the kept ones, up to the Gram's rounding); then B = Bp U (descending, each
 // column's largest-modulus entry real positive) and the call returns true.  Otherwise it returns
@@ -403,14 +407,138 @@ struct RitzLds {
   float2 b[64][kRitzN];           // the previous basis
   float2 y[64][kRitzN];           // S2 Bp
   float2 h[kRitzN][kRitzN + 1];   // Bp^H Y, then U (rows)
+  float2 g[kRitzN][kRitzN + 1];   // R^H R
+  float res[kRitzN];              // ||S2 z_j - theta_j z_j||^2 per Ritz vector
   float4 rot[kRitzN];
   float lam[kRitzN];
   int src[kRitzN];
-  float red[8];
+  float red[4];
+  int cold_ok;
 };
 
+// Cold start of the Rayleigh-Ritz step: Bp = an orthonormal basis of S2 (S2 Omega), two steps
+// of subspace iteration from a fixed pseudo-random d x n block Omega of (+-1) + i (+-1)
+// entries.  When S2 has rank r <= n (a channel with at most n paths), S2 Omega already spans
+// its range, but the rounding of Y = S2 Omega leaves the directions of the smallest nonzero
+// eigenvalues tilted by about eps theta_max / theta_r; the second product removes that tilt.
+// A column that vanishes under the orthogonalisation (rank below n) is replaced by a unit
+// vector made orthogonal to the others, which then lies in the numerical null space.  Channels
+// of higher rank fail the Ritz acceptance test and go to the Jacobi.
+//
+// Wave 0 orthonormalises the rows in L.y (row i in lane i) into L.b by classical Gram-Schmidt
+// applied twice per column; returns false (in every thread) if a column could not be completed.
+__device__ __forceinline__ bool eigB_cold_orth(RitzLds& L, int d, int n) {
+  constexpr int NB = kRitzN;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  if (wave == 0) {
+    float br[NB], bi[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      br[j] = lane < d ? L.y[lane][j].x : 0.f;
+      bi[j] = lane < d ? L.y[lane][j].y : 0.f;
+    }
+    float scale = 0.f;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) scale = fmaxf(scale, group_sum<64>(br[j] * br[j] + bi[j] * bi[j]));
+    // a column is kept when its norm after the projections is above 1e-6 of the largest column's:
+    // directions of eigenvalues down to about 1e-6 theta_max survive the products, rounding noise
+    // does not
+    const float tol2 = 1e-12f * scale;
+    int u = 0;  // next unit-vector candidate
+    bool good = scale > 0.f;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      if (k < n) {
+        float nrm2 = 0.f;
+        bool found = false;
+        for (int attempt = 0; attempt <= d; ++attempt) {
+#pragma unroll
+          for (int pass = 0; pass < 2; ++pass) {
+            // classical Gram-Schmidt, twice: the k projections b_j^H b_k reduce independently
+            float dr[NB], di[NB];
+#pragma unroll
+            for (int j = 0; j < k; ++j) {
+              dr[j] = group_sum<64>(br[j] * br[k] + bi[j] * bi[k]);
+              di[j] = group_sum<64>(br[j] * bi[k] - bi[j] * br[k]);
+            }
+#pragma unroll
+            for (int j = 0; j < k; ++j) {
+              br[k] -= dr[j] * br[j] - di[j] * bi[j];
+              bi[k] -= dr[j] * bi[j] + di[j] * br[j];
+            }
+          }
+          nrm2 = group_sum<64>(br[k] * br[k] + bi[k] * bi[k]);
+          if (nrm2 > (attempt == 0 ? tol2 : 0.05f)) {
+            found = true;
+            break;
+          }
+          if (u >= d) break;
+          br[k] = lane == u ? 1.f : 0.f;  // replace by e_u, orthogonalised on the next pass
+          bi[k] = 0.f;
+          ++u;
+        }
+        good = good && found;
+        const float inv = found ? __builtin_amdgcn_rsqf(nrm2) : 0.f;
+        br[k] *= inv;
+        bi[k] *= inv;
+      } else {
+        br[k] = bi[k] = 0.f;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) L.b[lane][j] = make_float2(lane < d ? br[j] : 0.f, lane < d ? bi[j] : 0.f);
+    if (lane == 0) L.cold_ok = good ? 1 : 0;
+  }
+  __syncthreads();
+  return L.cold_ok != 0;
+}
+
+// Y = S2 Bp into L.y: thread (row i, four columns)
+__device__ __forceinline__ void eigB_s_times_b(RitzLds& L) {
+  const int t = threadIdx.x, i = t / 4, j0 = 4 * (t % 4);
+  float yr[4] = {0.f, 0.f, 0.f, 0.f}, yi[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int k = 0; k < 64; ++k) {
+    const float2 a = L.s[i][k];
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const float2 bv = L.b[k][j0 + jj];
+      yr[jj] += a.x * bv.x - a.y * bv.y;
+      yi[jj] += a.x * bv.y + a.y * bv.x;
+    }
+  }
+#pragma unroll
+  for (int jj = 0; jj < 4; ++jj) L.y[i][j0 + jj] = make_float2(yr[jj], yi[jj]);
+}
+
+__device__ __forceinline__ bool eigB_cold_block(RitzLds& L, int d, int n) {
+  {
+    // Y = S2 Omega, Omega[k][j] = (+-1) + i (+-1), the signs two bits of a multiplicative hash
+    // of (k, j)
+    const int t = threadIdx.x, i = t / 4, j0 = 4 * (t % 4);
+    float yr[4] = {0.f, 0.f, 0.f, 0.f}, yi[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < d; ++k) {
+      const float2 a = L.s[i][k];
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const unsigned hsh = ((unsigned)k * 2654435761u) ^ ((unsigned)(j0 + jj + 1) * 40503u);
+        const float cs = (hsh & 0x10000u) ? 1.f : -1.f, sn = (hsh & 0x20000u) ? 1.f : -1.f;
+        yr[jj] += a.x * cs - a.y * sn;
+        yi[jj] += a.x * sn + a.y * cs;
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj)
+      L.y[i][j0 + jj] = (j0 + jj < n) ? make_float2(yr[jj], yi[jj]) : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  if (!eigB_cold_orth(L, d, n)) return false;
+  eigB_s_times_b(L);
+  __syncthreads();
+  return eigB_cold_orth(L, d, n);
+}
+
 __device__ __forceinline__ bool eigB_ritz(RitzLds& L, const DevChan& ch, int c, char* ws, float2* B,
-                                          int32_t* status) {
+                                          int32_t* status, bool cold) {
   constexpr int NB = kRitzN;
   const int t = threadIdx.x, lane = t % 64, wave = t / 64;
   const int d = ch.nt, n = ch.n;
@@ -421,27 +549,20 @@ __device__ __forceinline__ bool eigB_ritz(RitzLds& L, const DevChan& ch, int c, 
     const int i = e / 64, j = e % 64;
     L.s[i][j] = (i < d && j < d) ? S[(int64_t)i * d + j] : make_float2(0.f, 0.f);
   }
-  for (int e = t; e < 64 * NB; e += 256) {
-    const int i = e / NB, j = e % NB;
-    L.b[i][j] = (i < d && j < n) ? B[ch.b + (int64_t)i * n + j] : make_float2(0.f, 0.f);
-  }
-  __syncthreads();
-  // Y = S2 Bp: thread (i, four columns)
-  {
-    const int i = t / 4, j0 = 4 * (t % 4);
-    float yr[4] = {0.f, 0.f, 0.f, 0.f}, yi[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int k = 0; k < 64; ++k) {
-      const float2 a = L.s[i][k];
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const float2 bv = L.b[k][j0 + jj];
-        yr[jj] += a.x * bv.x - a.y * bv.y;
-        yi[jj] += a.x * bv.y + a.y * bv.x;
-      }
+  if (!cold)
+    for (int e = t; e < 64 * NB; e += 256) {
+      const int i = e / NB, j = e % NB;
+      L.b[i][j] = (i < d && j < n) ? B[ch.b + (int64_t)i * n + j] : make_float2(0.f, 0.f);
     }
-#pragma unroll
-    for (int jj = 0; jj < 4; ++jj) L.y[i][j0 + jj] = make_float2(yr[jj], yi[jj]);
+  __syncthreads();
+  // a starting block that is not orthonormal (a column could not be completed) goes to the
+  // Jacobi; the barrier keeps every read of cold_ok before the LDS is reused
+  if (cold && !eigB_cold_block(L, d, n)) {
+    __syncthreads();
+    return false;
   }
+  // Y = S2 Bp
+  eigB_s_times_b(L);
   __syncthreads();
   // H = Bp^H Y: thread (a, b)
   {
@@ -455,8 +576,8 @@ __device__ __forceinline__ bool eigB_ritz(RitzLds& L, const DevChan& ch, int c, 
     L.h[a][b] = make_float2(hr, hi);
   }
   __syncthreads();
-  // residual R = Y - Bp H and tr(S2) (all threads), while wave 0 diagonalises H on 16 lanes
-  float rr = 0.f;
+  // residual R = Y - Bp H into L.y (all threads), then its Gram R^H R (waves 1-3) while wave 0
+  // diagonalises H on 16 lanes
   {
     const int i = t / 4, j0 = 4 * (t % 4);
 #pragma unroll
@@ -467,13 +588,25 @@ __device__ __forceinline__ bool eigB_ritz(RitzLds& L, const DevChan& ch, int c, 
         xr -= bv.x * hv.x - bv.y * hv.y;
         xi -= bv.x * hv.y + bv.y * hv.x;
       }
-      rr += xr * xr + xi * xi;
+      L.y[i][j0 + jj] = make_float2(xr, xi);
     }
   }
   float trs = (t < 64 && t < d) ? L.s[t][t].x : 0.f;
   bool conv = true;
   float ur[NB], ui[NB];
-  __syncthreads();  // every read of H for the residual is done
+  __syncthreads();  // every read of H and every entry of R are done
+  if (wave > 0) {
+    for (int e = t - 64; e < NB * NB; e += 192) {
+      const int a = e / NB, b = e % NB;
+      float gr = 0.f, gi = 0.f;
+      for (int k = 0; k < 64; ++k) {
+        const float2 x = L.y[k][a], y = L.y[k][b];
+        gr += x.x * y.x + x.y * y.y;
+        gi += x.x * y.y - x.y * y.x;
+      }
+      L.g[a][b] = make_float2(gr, gi);
+    }
+  }
   if (wave == 0 && lane < NB) {
     float kr[NB], ki[NB];
 #pragma unroll
@@ -488,14 +621,10 @@ __device__ __forceinline__ bool eigB_ritz(RitzLds& L, const DevChan& ch, int c, 
     for (int j = 0; j < NB; ++j) me = (j == lane) ? kr[j] : me;
     L.lam[lane] = lane < n ? me : -__builtin_huge_valf();
   }
-  // block sums: |R|^2 and tr(S2)
-  rr = group_sum<64>(rr);
+  // block sum: tr(S2)
   trs = group_sum<64>(trs);
   __syncthreads();
-  if (lane == 0) {
-    L.red[wave] = rr;
-    L.red[4 + wave] = trs;
-  }
+  if (lane == 0) L.red[wave] = trs;
   if (wave == 0 && lane < NB) {
     // U rows to LDS (row lane of U), and the descending order of theta
 #pragma unroll
@@ -509,13 +638,30 @@ __device__ __forceinline__ bool eigB_ritz(RitzLds& L, const DevChan& ch, int c, 
     L.src[rank] = lane;
   }
   __syncthreads();
-  const float r2 = (L.red[0] + L.red[1]) + (L.red[2] + L.red[3]);
-  const float tr_s = (L.red[4] + L.red[5]) + (L.red[6] + L.red[7]);
+  if (t < NB) {
+    // residual of Ritz vector z_t = Bp U[:, t]: U[:, t]^H (R^H R) U[:, t]
+    float acc = 0.f;
+    if (t < n)
+      for (int a = 0; a < NB; ++a) {
+        float vr = 0.f, vi = 0.f;  // (G U[:, t])_a
+        for (int b = 0; b < NB; ++b) {
+          const float2 gv = L.g[a][b], uv = L.h[b][t];
+          vr += gv.x * uv.x - gv.y * uv.y;
+          vi += gv.x * uv.y + gv.y * uv.x;
+        }
+        const float2 ua = L.h[a][t];
+        acc += ua.x * vr + ua.y * vi;
+      }
+    L.res[t] = acc;
+  }
+  const float tr_s = (L.red[0] + L.red[1]) + (L.red[2] + L.red[3]);
   float th_max = L.lam[L.src[0]], th_min = L.lam[L.src[n - 1]];
   float th_sum = 0.f;
   for (int j = 0; j < n; ++j) th_sum += L.lam[j];
   const int conv_all = __syncthreads_and(conv ? 1 : 0);
-  const bool ok = conv_all && th_max > 0.f && r2 <= 2.5e-11f * th_max * th_max &&
+  float r2 = 0.f;
+  for (int j = 0; j < n; ++j) r2 = fmaxf(r2, L.res[j]);
+  const bool ok = conv_all && th_max > 0.f && r2 <= 1.0e-10f * th_max * th_max &&
                   tr_s - th_sum <= th_min + 1.0e-5f * tr_s;
   if (!ok) {
     __syncthreads();  // every read of the Ritz data is done before the Jacobi reuses the LDS
@@ -586,10 +732,20 @@ __global__ void __launch_bounds__(64 * NW) k_eigB(const DevChan* __restrict__ ch
   const DevChan& ch = chans[c];
   const int d = ch.nt;
   if (d > MP) return;  // wide arrays: subspace-iteration kernel
-  if (kWarmOk && ritz && warm) {
-    // warm FP32 solve: the Rayleigh-Ritz step on the previous basis first, in this block's LDS
+  if (kWarmOk && ritz) {
+    // FP32 solve: the Rayleigh-Ritz step first, in this block's LDS, on the previous basis
+    // (warm) or on a basis of S2 Omega (cold)
     static_assert(sizeof(RitzLds) <= sizeof(EigLds<float, 64>), "Ritz data must fit the Jacobi LDS");
-    if (eigB_ritz(*reinterpret_cast<RitzLds*>(&L), ch, c, ws, B, status)) return;
+    if (eigB_ritz(*reinterpret_cast<RitzLds*>(&L), ch, c, ws, B, status, !warm)) {
+      // after a cold start the stored basis is set to the identity, a valid start for a later
+      // warm Jacobi that the Ritz step cannot settle
+      if (!warm) {
+        float2* VBw = wsp(ws, ch.w_VB);
+        for (int e = threadIdx.x; e < MP * MP; e += 64 * NW)
+          VBw[e] = make_float2(e / MP == e % MP ? 1.f : 0.f, 0.f);
+      }
+      return;
+    }
   }
   const float2* S = wsp(ws, ch.w_S2);
   float2* VB = wsp(ws, ch.w_VB);
@@ -1053,9 +1209,9 @@ static gt_status eig_all(const LaunchCtx& L, int which, float2* A, float2* B, fl
     if (sst != GT_OK) return sst;
     constexpr int NW = sizeof(T) == 4 ? 4 : 8;
     if (L.min_nt <= 64) {
-      // warm FP32 solves try the Rayleigh-Ritz step on the previous basis first and run the
-      // Jacobi only for the channels it cannot settle
-      const int ritz = (sizeof(T) == 4 && warm) ? 1 : 0;
+      // FP32 solves try the Rayleigh-Ritz step first (on the previous basis, or cold on S2 Omega)
+      // and run the Jacobi only for the channels it cannot settle
+      const int ritz = sizeof(T) == 4 ? 1 : 0;
       GT_LAUNCH((k_eigB<T, NW>), dim3(L.n_channels), dim3(64 * NW), L.d_chans, L.ws, B, status, warm,
                 ritz);
     }

@@ -454,7 +454,8 @@ __device__ __forceinline__ RowsWave<MAXG> rows_wave_groups(bool valid, int c, in
 
 // rows_ht_chunk with the wave's group cores staged in LDS (stage: [MAXG][MP][CH] complex, free
 // for the wave): per q, the wave loads columns [j0, j0 + CH) of G_g[q] of each of its groups
-// with consecutive lanes on consecutive entries, then every lane forms its row from LDS.
+// with consecutive lanes on consecutive entries (one q ahead, in registers), then every lane
+// forms its row from LDS.
 template <int MP, int CH, int MAXG>
 __device__ __forceinline__ void rows_ht_chunk_staged(float2* stage, const RowsWave<MAXG>& W,
                                                      const float2* __restrict__ G, int r, bool row,
@@ -468,23 +469,40 @@ __device__ __forceinline__ void rows_ht_chunk_staged(float2* stage, const RowsWa
 #pragma unroll
   for (int jj = 0; jj < CH; ++jj) hr[jj] = hi[jj] = 0.f;
   const float2* my = stage + (W.gidx * MP + r) * CH;
-  for (int q = 0; q < pgmax; ++q) {
+  // software pipeline: the entries (and the C entry) of q + 1 are loaded into registers while
+  // the wave forms its rows from those of q in LDS
+  constexpr int NE = (MP * CH + 63) / 64;
+  float2 nxt[MAXG][NE];
+  auto fetch = [&](int q) {
 #pragma unroll
     for (int k = 0; k < MAXG; ++k) {
-      if (k < W.ngrp) {
-        const int mk = W.mk[k], nk = W.nk[k];
-        const float2* Gq = G + W.base[k] + (int64_t)q * mk * nk;
+      const int mk = W.mk[k], nk = W.nk[k];
+      const float2* Gq = G + W.base[k] + (int64_t)q * mk * nk;
 #pragma unroll
-        for (int e0 = 0; e0 < MP * CH; e0 += 64) {
-          const int e = e0 + lane, rw = e / CH, j = j0 + e % CH;
-          float2 v = make_float2(0.f, 0.f);
-          if (e < MP * CH && rw < mk && j < nk && q < W.pgk[k]) v = Gq[rw * nk + j];
-          if (e < MP * CH) stage[k * MP * CH + e] = v;
-        }
+      for (int u = 0; u < NE; ++u) {
+        const int e = 64 * u + lane, rw = e / CH, j = j0 + e % CH;
+        float2 v = make_float2(0.f, 0.f);
+        if (k < W.ngrp && e < MP * CH && rw < mk && j < nk && q < W.pgk[k]) v = Gq[rw * nk + j];
+        nxt[k][u] = v;
       }
     }
+  };
+  if (pgmax > 0) fetch(0);
+  float2 cn = 0 < pg ? Cs[0] : make_float2(0.f, 0.f);
+  for (int q = 0; q < pgmax; ++q) {
+#pragma unroll
+    for (int k = 0; k < MAXG; ++k)
+#pragma unroll
+      for (int u = 0; u < NE; ++u) {
+        const int e = 64 * u + lane;
+        if (k < W.ngrp && e < MP * CH) stage[k * MP * CH + e] = nxt[k][u];
+      }
+    const float2 cq = cn;
+    if (q + 1 < pgmax) {
+      fetch(q + 1);
+      cn = q + 1 < pg ? Cs[q + 1] : make_float2(0.f, 0.f);
+    }
     wave_sync();
-    const float2 cq = q < pg ? Cs[q] : make_float2(0.f, 0.f);
 #pragma unroll
     for (int jj = 0; jj < CH; jj += 2) {
       const float4 gv = *reinterpret_cast<const float4*>(my + jj);
