@@ -11,12 +11,19 @@
 //                                ds_swizzle, and the column rotations of the other pairs read
 //                                their (c, s) from LDS;
 //   HV = U_ns Sigma_ns           precoder of equation "precoding matrix" (HV = Ht V_ns);
-//   Q = HV HV^H + s2 I = L L^H   left-looking Cholesky, row c published to LDS at step c;
-//   W = Q^{-1} HV                substitutions over the rows, one row's values published per
-//                                step;
-//   c_rk = w_r^H hv_k            per-row partial products summed over the group by swizzles;
-//   SINR_r = |c_rr|^2 / (s2 ||w_r||^2 + sum_{k != r} |c_rk|^2)   (equations "s_r^ij" and
-//                                "SINR formula"; the denominator equals w_r^H Q w_r - s_r).
+//   M = HV^H HV                  ns x ns, summed over the group by swizzles, held by every lane;
+//   W = Q^{-1} HV = HV P^{-1}    the MMSE filter with Q = HV HV^H + s2 I_m (equation "MMSE
+//                                receive filter"), through the push-through identity with
+//                                P = M + s2 I_ns: the ns x ns system replaces the m x m one, as
+//                                the Woodbury step of Section 3.3 replaces M x M by m x m;
+//   c_jk = w_j^H hv_k = (P^{-1} M)_jk,   ||w_j||^2 = (P^{-1} M P^{-1})_jj: lane j factors P by
+//                                Cholesky, solves P y = e_j and forms z = M y, so c_jk = conj(z_k)
+//                                and ||w_j||^2 = y^H z;
+//   SINR_j = |c_jj|^2 / (s2 ||w_j||^2 + sum_{k != j} |c_jk|^2)   (equations "s_r^ij" and
+//                                "SINR formula"; the denominator equals w_j^H Q w_j - s_j).
+// Instantiations with NS = MP, and the adjoint kernel (whose back-propagation runs through it),
+// keep the m x m chain: Q = HV HV^H + s2 I = L L^H by a left-looking Cholesky over the rows,
+// W = Q^{-1} HV by substitutions, c_jk = w_j^H hv_k summed over the group by swizzles.
 // Spreading a subcarrier over MP lanes gives a launch MP times as many waves as one lane per
 // subcarrier, so the long serial chain of each small eigenproblem overlaps with others.
 #include <hip/hip_runtime.h>
@@ -24,6 +31,80 @@
 #include "gt_rows.h"
 
 namespace gt {
+
+// SINR of stream j of the MMSE filter from M = HV^H HV (NS x NS Hermitian, zero past ns) and the
+// noise level s2: P = M + s2 I = L L^H (Cholesky, real diagonal), y = P^{-1} e_j by forward and
+// back substitution, z = M y; c_jk = conj(z_k), ||w_j||^2 = y^H z.  ok turns false if a pivot of
+// P is not positive.
+template <int NS>
+__device__ __forceinline__ float pt_stream_sinr(const float (&mr)[NS][NS], const float (&mi)[NS][NS],
+                                                float s2, int j, bool& ok) {
+  float lr[NS][NS], li[NS][NS], dinv[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+#pragma unroll
+    for (int k = 0; k <= i; ++k) {
+      float sr = mr[i][k] + (i == k ? s2 : 0.f), si = (i == k) ? 0.f : mi[i][k];
+#pragma unroll
+      for (int l = 0; l < k; ++l) {  // - L[i][l] conj(L[k][l])
+        sr -= lr[i][l] * lr[k][l] + li[i][l] * li[k][l];
+        si -= li[i][l] * lr[k][l] - lr[i][l] * li[k][l];
+      }
+      if (i == k) {
+        ok = ok && sr > 0.f;
+        const float dd = sr > 0.f ? sr : 1.f;
+        dinv[i] = __builtin_amdgcn_rsqf(dd);
+      } else {
+        lr[i][k] = sr * dinv[k];
+        li[i][k] = si * dinv[k];
+      }
+    }
+  }
+  // L u = e_j
+  float ur[NS], ui[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    float sr = (i == j) ? 1.f : 0.f, si = 0.f;
+#pragma unroll
+    for (int l = 0; l < i; ++l) {
+      sr -= lr[i][l] * ur[l] - li[i][l] * ui[l];
+      si -= lr[i][l] * ui[l] + li[i][l] * ur[l];
+    }
+    ur[i] = sr * dinv[i];
+    ui[i] = si * dinv[i];
+  }
+  // L^H y = u
+  float yr[NS], yi[NS];
+#pragma unroll
+  for (int i = NS - 1; i >= 0; --i) {
+    float sr = ur[i], si = ui[i];
+#pragma unroll
+    for (int l = i + 1; l < NS; ++l) {  // - conj(L[l][i]) y[l]
+      sr -= lr[l][i] * yr[l] + li[l][i] * yi[l];
+      si -= lr[l][i] * yi[l] - li[l][i] * yr[l];
+    }
+    yr[i] = sr * dinv[i];
+    yi[i] = si * dinv[i];
+  }
+  // z = M y; signal |z_j|^2, interference sum_{k != j} |z_k|^2, ||w_j||^2 = Re(y^H z)
+  float sig_p = 0.f, den = 0.f, wn = 0.f;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    float zr = 0.f, zi = 0.f;
+#pragma unroll
+    for (int l = 0; l < NS; ++l) {
+      zr += mr[k][l] * yr[l] - mi[k][l] * yi[l];
+      zi += mr[k][l] * yi[l] + mi[k][l] * yr[l];
+    }
+    const float pw = zr * zr + zi * zi;
+    if (k == j)
+      sig_p = pw;
+    else
+      den += pw;
+    wn += yr[k] * zr + yi[k] * zi;
+  }
+  return sig_p / (den + s2 * wn);
+}
 
 // Compressed-channel SINR for channels with m <= MP and ns <= NS, 256 / MP subcarriers per
 // block of 256 lanes.
@@ -68,38 +149,67 @@ __global__ void __launch_bounds__(256, 4) k_sinr_rows(const DevChan* __restrict_
   float sig[NS], ur[NS], ui[NS], hvr[NS], hvi[NS];
   rows_hv<MP, NS, 16, true>(S, r, row, ns, kr, vr, vi, sig, ur, ui, hvr, hvi, bits);
 
+  // with ns < m the ns x ns push-through form of the MMSE filter; with ns = m the m x m chain
+  constexpr bool kPT = NS < MP;
+  float mr[kPT ? NS : 1][kPT ? NS : 1], mi[kPT ? NS : 1][kPT ? NS : 1];
+  bool live = true;
+  int js = 0;
+  if constexpr (kPT) {
+    // M = HV^H HV, the same in every lane of the group
+#pragma unroll
+    for (int i = 0; i < NS; ++i)
+#pragma unroll
+      for (int k = i; k < NS; ++k) {
+        const float re = rows_sum<MP>(hvr[i] * hvr[k] + hvi[i] * hvi[k]);
+        const float im = (k == i) ? 0.f : rows_sum<MP>(hvr[i] * hvi[k] - hvi[i] * hvr[k]);
+        mr[i][k] = re;
+        mi[i][k] = im;
+        mr[k][i] = re;
+        mi[k][i] = -im;
+      }
+    js = min(r, NS - 1);  // this lane's stream
+    float sig_me = sig[0];
+#pragma unroll
+    for (int k = 1; k < NS; ++k) sig_me = (k == js) ? sig[k] : sig_me;
+    live = sig_me > 1.0e-3f * sig[0];  // zero-stream rule
+  }
   for (int kk = 0; kk < snr.n; ++kk) {
     const float s2 = snr.s2[kk];
-    float lr[MP], li[MP];
-    bool ok;
-    float rd;
-    rows_chol<MP, NS>(S, r, row, s2, hvr, hvi, lr, li, ok, rd);
-    float wr[NS], wi[NS];
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      wr[k] = hvr[k];
-      wi[k] = hvi[k];
-    }
-    rows_solve<MP, NS>(S, r, lr, li, rd, wr, wi);
-    // c_jk = w_j^H hv_k, ||w_j||^2, SINR_j
+    bool ok = true;
     float sinr_me = 0.f;
-#pragma unroll
-    for (int j = 0; j < NS; ++j) {
-      float sig_p = 0.f, den = 0.f;
+    if constexpr (kPT) {
+      sinr_me = pt_stream_sinr<NS>(mr, mi, s2, js, ok);
+      if (!live) sinr_me = 0.f;
+    } else {
+      float lr[MP], li[MP];
+      float rd;
+      rows_chol<MP, NS>(S, r, row, s2, hvr, hvi, lr, li, ok, rd);
+      float wr[NS], wi[NS];
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
-        const float cr = rows_sum<MP>(wr[j] * hvr[k] + wi[j] * hvi[k]);
-        const float ci = rows_sum<MP>(wr[j] * hvi[k] - wi[j] * hvr[k]);
-        const float pw = cr * cr + ci * ci;
-        if (k == j)
-          sig_p = pw;
-        else
-          den += pw;
+        wr[k] = hvr[k];
+        wi[k] = hvi[k];
       }
-      den += s2 * rows_sum<MP>(wr[j] * wr[j] + wi[j] * wi[j]);
-      float v = sig_p / den;
-      if (!(sig[j] > 1.0e-3f * sig[0])) v = 0.f;
-      sinr_me = (j == r) ? v : sinr_me;
+      rows_solve<MP, NS>(S, r, lr, li, rd, wr, wi);
+      // c_jk = w_j^H hv_k, ||w_j||^2, SINR_j
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {
+        float sig_p = 0.f, den = 0.f;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          const float cr = rows_sum<MP>(wr[j] * hvr[k] + wi[j] * hvi[k]);
+          const float ci = rows_sum<MP>(wr[j] * hvi[k] - wi[j] * hvr[k]);
+          const float pw = cr * cr + ci * ci;
+          if (k == j)
+            sig_p = pw;
+          else
+            den += pw;
+        }
+        den += s2 * rows_sum<MP>(wr[j] * wr[j] + wi[j] * wi[j]);
+        float v = sig_p / den;
+        if (!(sig[j] > 1.0e-3f * sig[0])) v = 0.f;
+        sinr_me = (j == r) ? v : sinr_me;
+      }
     }
     const bool any_bad = rows_or<MP>(ok ? 0u : 1u) != 0u;
     if (any_bad) bits |= GT_DEV_CHOLESKY;
