@@ -646,9 +646,28 @@ __global__ void __launch_bounds__(256) k_sinr_bwd_reduce(const DevChan* __restri
     E* sH = sm;
     E* sG = sm + sz * mn;
     E* sC = sG + pg * mn;
-    for (int e = threadIdx.x; e < sz * mn; e += blockDim.x) sH[e] = gHm[e];
-    for (int e = threadIdx.x; e < pg * mn; e += blockDim.x) sG[e] = Ggm[e];
-    for (int e = threadIdx.x; e < sz * ch.p; e += blockDim.x) sC[e] = Cg[e];
+    // every thread issues its loads of the three arrays (up to B of each) before its LDS
+    // stores, so one memory latency covers the copy of a group
+    constexpr int B = 8;
+    const int nH = sz * mn, nG = pg * mn, nC = sz * ch.p;
+    const int nmax = max(nH, max(nG, nC));
+    for (int e0 = threadIdx.x; e0 < nmax; e0 += B * blockDim.x) {
+      E vh[B], vg[B], vc[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int e = e0 + u * (int)blockDim.x;
+        if (e < nH) vh[u] = gHm[e];
+        if (e < nG) vg[u] = Ggm[e];
+        if (e < nC) vc[u] = Cg[e];
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int e = e0 + u * (int)blockDim.x;
+        if (e < nH) sH[e] = vh[u];
+        if (e < nG) sG[e] = vg[u];
+        if (e < nC) sC[e] = vc[u];
+      }
+    }
     __syncthreads();
     gH = sH;
     Gg = sG;

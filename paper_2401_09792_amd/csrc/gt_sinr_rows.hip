@@ -32,14 +32,30 @@
 
 namespace gt {
 
-// SINR of stream j of the MMSE filter from M = HV^H HV (NS x NS Hermitian, zero past ns) and the
-// noise level s2: P = M + s2 I = L L^H (Cholesky, real diagonal), y = P^{-1} e_j by forward and
-// back substitution, z = M y; c_jk = conj(z_k), ||w_j||^2 = y^H z.  ok turns false if a pivot of
-// P is not positive.
+// M = HV^H HV from the rows of HV held by the MP lanes of a group (ns x ns, zero past ns), the
+// same in every lane.
+template <int MP, int NS>
+__device__ __forceinline__ void pt_gram(const float (&hvr)[NS], const float (&hvi)[NS],
+                                        float (&mr)[NS][NS], float (&mi)[NS][NS]) {
+#pragma unroll
+  for (int i = 0; i < NS; ++i)
+#pragma unroll
+    for (int k = i; k < NS; ++k) {
+      const float re = rows_sum<MP>(hvr[i] * hvr[k] + hvi[i] * hvi[k]);
+      const float im = (k == i) ? 0.f : rows_sum<MP>(hvr[i] * hvi[k] - hvi[i] * hvr[k]);
+      mr[i][k] = re;
+      mi[i][k] = im;
+      mr[k][i] = re;
+      mi[k][i] = -im;
+    }
+}
+
+// P = M + s2 I = L L^H (Cholesky, lower, in registers); dinv[i] = 1 / L[i][i].  ok turns false
+// if a pivot is not positive.
 template <int NS>
-__device__ __forceinline__ float pt_stream_sinr(const float (&mr)[NS][NS], const float (&mi)[NS][NS],
-                                                float s2, int j, bool& ok) {
-  float lr[NS][NS], li[NS][NS], dinv[NS];
+__device__ __forceinline__ void pt_chol(const float (&mr)[NS][NS], const float (&mi)[NS][NS],
+                                        float s2, float (&lr)[NS][NS], float (&li)[NS][NS],
+                                        float (&dinv)[NS], bool& ok) {
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
 #pragma unroll
@@ -52,18 +68,23 @@ __device__ __forceinline__ float pt_stream_sinr(const float (&mr)[NS][NS], const
       }
       if (i == k) {
         ok = ok && sr > 0.f;
-        const float dd = sr > 0.f ? sr : 1.f;
-        dinv[i] = __builtin_amdgcn_rsqf(dd);
+        dinv[i] = __builtin_amdgcn_rsqf(sr > 0.f ? sr : 1.f);
       } else {
         lr[i][k] = sr * dinv[k];
         li[i][k] = si * dinv[k];
       }
     }
   }
-  // L u = e_j
-  float ur[NS], ui[NS];
+}
+
+// y = P^{-1} e_j = L^{-H} L^{-1} e_j; returns P^{-1}_jj = ||L^{-1} e_j||^2 (real by construction).
+template <int NS>
+__device__ __forceinline__ float pt_solve(const float (&lr)[NS][NS], const float (&li)[NS][NS],
+                                          const float (&dinv)[NS], int j, float (&yr)[NS],
+                                          float (&yi)[NS]) {
+  float ur[NS], ui[NS], xjj = 0.f;
 #pragma unroll
-  for (int i = 0; i < NS; ++i) {
+  for (int i = 0; i < NS; ++i) {  // L u = e_j
     float sr = (i == j) ? 1.f : 0.f, si = 0.f;
 #pragma unroll
     for (int l = 0; l < i; ++l) {
@@ -72,11 +93,10 @@ __device__ __forceinline__ float pt_stream_sinr(const float (&mr)[NS][NS], const
     }
     ur[i] = sr * dinv[i];
     ui[i] = si * dinv[i];
+    xjj += ur[i] * ur[i] + ui[i] * ui[i];
   }
-  // L^H y = u
-  float yr[NS], yi[NS];
 #pragma unroll
-  for (int i = NS - 1; i >= 0; --i) {
+  for (int i = NS - 1; i >= 0; --i) {  // L^H y = u
     float sr = ur[i], si = ui[i];
 #pragma unroll
     for (int l = i + 1; l < NS; ++l) {  // - conj(L[l][i]) y[l]
@@ -86,6 +106,18 @@ __device__ __forceinline__ float pt_stream_sinr(const float (&mr)[NS][NS], const
     yr[i] = sr * dinv[i];
     yi[i] = si * dinv[i];
   }
+  return xjj;
+}
+
+// SINR of stream j of the MMSE filter from M = HV^H HV (NS x NS Hermitian, zero past ns) and the
+// noise level s2: y = P^{-1} e_j, z = M y; c_jk = conj(z_k), ||w_j||^2 = y^H z.  ok turns false
+// if a pivot of P is not positive.
+template <int NS>
+__device__ __forceinline__ float pt_stream_sinr(const float (&mr)[NS][NS], const float (&mi)[NS][NS],
+                                                float s2, int j, bool& ok) {
+  float lr[NS][NS], li[NS][NS], dinv[NS], yr[NS], yi[NS];
+  pt_chol<NS>(mr, mi, s2, lr, li, dinv, ok);
+  pt_solve<NS>(lr, li, dinv, j, yr, yi);
   // z = M y; signal |z_j|^2, interference sum_{k != j} |z_k|^2, ||w_j||^2 = Re(y^H z)
   float sig_p = 0.f, den = 0.f, wn = 0.f;
 #pragma unroll
@@ -155,18 +187,7 @@ __global__ void __launch_bounds__(256, 4) k_sinr_rows(const DevChan* __restrict_
   bool live = true;
   int js = 0;
   if constexpr (kPT) {
-    // M = HV^H HV, the same in every lane of the group
-#pragma unroll
-    for (int i = 0; i < NS; ++i)
-#pragma unroll
-      for (int k = i; k < NS; ++k) {
-        const float re = rows_sum<MP>(hvr[i] * hvr[k] + hvi[i] * hvi[k]);
-        const float im = (k == i) ? 0.f : rows_sum<MP>(hvr[i] * hvi[k] - hvi[i] * hvr[k]);
-        mr[i][k] = re;
-        mi[i][k] = im;
-        mr[k][i] = re;
-        mi[k][i] = -im;
-      }
+    pt_gram<MP, NS>(hvr, hvi, mr, mi);  // M = HV^H HV
     js = min(r, NS - 1);  // this lane's stream
     float sig_me = sig[0];
 #pragma unroll
@@ -227,8 +248,9 @@ __global__ void __launch_bounds__(256, 4) k_sinr_rows(const DevChan* __restrict_
   if (valid && status && bits && r == 0) atomicOr(reinterpret_cast<unsigned int*>(status + c), bits);
 }
 
-// Adjoint of k_sinr_rows: recomputes Ht, its eigendecomposition and, per noise level, L and W;
-// back-propagates dl/dSINR through SINR_j = s_j / d_j, s_j = |c_jj|^2,
+// Adjoint of k_sinr_rows: recomputes Ht, its eigendecomposition and, per noise level, the MMSE
+// chain.  With ns < m it runs in the ns x ns push-through form (see the loop); otherwise it
+// recomputes L and W and back-propagates dl/dSINR through SINR_j = s_j / d_j, s_j = |c_jj|^2,
 // d_j = s2 ||w_j||^2 + sum_{k != j} |c_jk|^2 with c_jk = w_j^H hv_k, W = Q^{-1} HV and
 // Q = HV HV^H + s2 I to dl/dHV:
 //   C-bar_jk = 2 (k == j ? g_j / d_j : -g_j s_j / d_j^2) c_jk,   N-bar_j = -s2 g_j s_j / d_j^2,
@@ -287,96 +309,144 @@ __global__ void __launch_bounds__(256, 3) k_sinr_bwd_rows(const DevChan* __restr
   float br[NS], bi[NS];  // row r of dl/dHV
 #pragma unroll
   for (int k = 0; k < NS; ++k) br[k] = bi[k] = 0.f;
-  for (int kk = 0; kk < snr.n; ++kk) {
-    const float s2 = snr.s2[kk];
-    float lr[MP], li[MP];
-    bool ok;
-    float rd;
-    rows_chol<MP, NS>(S, r, row, s2, hvr, hvi, lr, li, ok, rd);
-    const bool any_bad = rows_or<MP>(ok ? 0u : 1u) != 0u;
-    if (any_bad) bits |= GT_DEV_CHOLESKY;
-    float wr[NS], wi[NS];
+  if constexpr (NS < MP) {
+    // ns < m: with X = P^{-1}, P = HV^H HV + s2 I_ns, the SINR of the MMSE filter is
+    // SINR_j = 1 / (s2 X_jj) - 1 (the chain's c and ||w_j||^2 in terms of X), so
+    // dl/dM = sum_j g_j / (s2 X_jj^2) x_j x_j^H (x_j = X e_j) and dl/dHV = 2 HV dl/dM
+    float mr[NS][NS], mi[NS][NS], gmr[NS][NS], gmi[NS][NS];
+    pt_gram<MP, NS>(hvr, hvi, mr, mi);
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      wr[k] = hvr[k];
-      wi[k] = hvi[k];
-    }
-    rows_solve<MP, NS>(S, r, lr, li, rd, wr, wi);
-    float cr[NS][NS], ci[NS][NS];  // c_jk = w_j^H hv_k
-    rows_inner<MP, NS>(wr, wi, hvr, hvi, cr, ci);
-    // C-bar (in place of c) and N-bar
-    float nb[NS];
-    const float* gk = gsinr + ((int64_t)kk * total_sc + gsc) * ns_max;
+    for (int k = 0; k < NS; ++k)
 #pragma unroll
-    for (int j = 0; j < NS; ++j) {
-      const float nw = rows_sum<MP>(wr[j] * wr[j] + wi[j] * wi[j]);
-      float sv = 0.f, dv = s2 * nw;
-#pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        const float pw = cr[j][k] * cr[j][k] + ci[j][k] * ci[j][k];
-        if (k == j)
-          sv = pw;
-        else
-          dv += pw;
-      }
-      // streams past ns (zero columns of W and HV, d_j = 0), zero streams and broken-down
-      // noise levels carry no gradient
-      const bool on = valid && live[j] && !any_bad;
-      const float gj = on ? gk[j] : 0.f;
-      const float sbar = on ? gj / dv : 0.f;
-      const float dbar = on ? -gj * sv / (dv * dv) : 0.f;
-      nb[j] = s2 * dbar;
-#pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        const float f = (k == j) ? 2.f * sbar : 2.f * dbar;
-        cr[j][k] *= f;
-        ci[j][k] *= f;
-      }
-    }
-    // c (needed below) is recomputed from W and HV after W-bar: keep C-bar in cr/ci
-    // W-bar row r: sum_k hv[r][k] conj(Cbar[j][k]) + 2 nb_j w[r][j]
-    float lmr[NS], lmi[NS];
-#pragma unroll
-    for (int j = 0; j < NS; ++j) {
-      float ar = 2.f * nb[j] * wr[j], ai = 2.f * nb[j] * wi[j];
-#pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        ar += hvr[k] * cr[j][k] + hvi[k] * ci[j][k];
-        ai += hvi[k] * cr[j][k] - hvr[k] * ci[j][k];
-      }
-      lmr[j] = ar;
-      lmi[j] = ai;
-    }
-    // dl/dHV += W C-bar
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
+      for (int l = 0; l < NS; ++l) gmr[k][l] = gmi[k][l] = 0.f;
+    for (int kk = 0; kk < snr.n; ++kk) {
+      const float s2 = snr.s2[kk];
+      float lr[NS][NS], li[NS][NS], dinv[NS];
+      bool ok = true;
+      pt_chol<NS>(mr, mi, s2, lr, li, dinv, ok);
+      const bool any_bad = rows_or<MP>(ok ? 0u : 1u) != 0u;
+      if (any_bad) bits |= GT_DEV_CHOLESKY;
+      const float* gk = gsinr + ((int64_t)kk * total_sc + gsc) * ns_max;
 #pragma unroll
       for (int j = 0; j < NS; ++j) {
-        br[k] += wr[j] * cr[j][k] - wi[j] * ci[j][k];
-        bi[k] += wr[j] * ci[j][k] + wi[j] * cr[j][k];
+        // streams past ns, zero streams and broken-down noise levels carry no gradient
+        const bool on = valid && live[j] && !any_bad;
+        const float gj = on ? gk[j] : 0.f;
+        float yr[NS], yi[NS];
+        const float xjj = pt_solve<NS>(lr, li, dinv, j, yr, yi);
+        const float aj = on ? gj / (s2 * xjj * xjj) : 0.f;
+#pragma unroll
+        for (int k = 0; k < NS; ++k)
+#pragma unroll
+          for (int l = 0; l < NS; ++l) {  // a_j y_k conj(y_l)
+            gmr[k][l] += aj * (yr[k] * yr[l] + yi[k] * yi[l]);
+            gmi[k][l] += aj * (yi[k] * yr[l] - yr[k] * yi[l]);
+          }
       }
     }
-    rows_solve<MP, NS>(S, r, lr, li, rd, lmr, lmi);  // Lambda = Q^{-1} W-bar
-    // c again (C-bar overwrote it), then X = Lambda^H HV
-    rows_inner<MP, NS>(wr, wi, hvr, hvi, cr, ci);
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      float ar = lmr[k], ai = lmi[k];
+    for (int k = 0; k < NS; ++k) {  // row r of 2 HV dl/dM
+      float ar = 0.f, ai = 0.f;
 #pragma unroll
-      for (int j = 0; j < NS; ++j) {  // - Lambda[r][j] c_jk
-        ar -= lmr[j] * cr[j][k] - lmi[j] * ci[j][k];
-        ai -= lmr[j] * ci[j][k] + lmi[j] * cr[j][k];
+      for (int l = 0; l < NS; ++l) {
+        ar += hvr[l] * gmr[l][k] - hvi[l] * gmi[l][k];
+        ai += hvr[l] * gmi[l][k] + hvi[l] * gmr[l][k];
       }
-      br[k] += ar;
-      bi[k] += ai;
+      br[k] = 2.f * ar;
+      bi[k] = 2.f * ai;
     }
-    rows_inner<MP, NS>(lmr, lmi, hvr, hvi, cr, ci);  // X_jk = lambda_j^H hv_k
+  } else {
+    for (int kk = 0; kk < snr.n; ++kk) {
+      const float s2 = snr.s2[kk];
+      float lr[MP], li[MP];
+      bool ok;
+      float rd;
+      rows_chol<MP, NS>(S, r, row, s2, hvr, hvi, lr, li, ok, rd);
+      const bool any_bad = rows_or<MP>(ok ? 0u : 1u) != 0u;
+      if (any_bad) bits |= GT_DEV_CHOLESKY;
+      float wr[NS], wi[NS];
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
+      for (int k = 0; k < NS; ++k) {
+        wr[k] = hvr[k];
+        wi[k] = hvi[k];
+      }
+      rows_solve<MP, NS>(S, r, lr, li, rd, wr, wi);
+      float cr[NS][NS], ci[NS][NS];  // c_jk = w_j^H hv_k
+      rows_inner<MP, NS>(wr, wi, hvr, hvi, cr, ci);
+      // C-bar (in place of c) and N-bar
+      float nb[NS];
+      const float* gk = gsinr + ((int64_t)kk * total_sc + gsc) * ns_max;
 #pragma unroll
-      for (int j = 0; j < NS; ++j) {  // - W[r][j] X_jk
-        br[k] -= wr[j] * cr[j][k] - wi[j] * ci[j][k];
-        bi[k] -= wr[j] * ci[j][k] + wi[j] * cr[j][k];
+      for (int j = 0; j < NS; ++j) {
+        const float nw = rows_sum<MP>(wr[j] * wr[j] + wi[j] * wi[j]);
+        float sv = 0.f, dv = s2 * nw;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          const float pw = cr[j][k] * cr[j][k] + ci[j][k] * ci[j][k];
+          if (k == j)
+            sv = pw;
+          else
+            dv += pw;
+        }
+        // streams past ns (zero columns of W and HV, d_j = 0), zero streams and broken-down
+        // noise levels carry no gradient
+        const bool on = valid && live[j] && !any_bad;
+        const float gj = on ? gk[j] : 0.f;
+        const float sbar = on ? gj / dv : 0.f;
+        const float dbar = on ? -gj * sv / (dv * dv) : 0.f;
+        nb[j] = s2 * dbar;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          const float f = (k == j) ? 2.f * sbar : 2.f * dbar;
+          cr[j][k] *= f;
+          ci[j][k] *= f;
+        }
+      }
+      // c (needed below) is recomputed from W and HV after W-bar: keep C-bar in cr/ci
+      // W-bar row r: sum_k hv[r][k] conj(Cbar[j][k]) + 2 nb_j w[r][j]
+      float lmr[NS], lmi[NS];
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {
+        float ar = 2.f * nb[j] * wr[j], ai = 2.f * nb[j] * wi[j];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          ar += hvr[k] * cr[j][k] + hvi[k] * ci[j][k];
+          ai += hvi[k] * cr[j][k] - hvr[k] * ci[j][k];
+        }
+        lmr[j] = ar;
+        lmi[j] = ai;
+      }
+      // dl/dHV += W C-bar
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+          br[k] += wr[j] * cr[j][k] - wi[j] * ci[j][k];
+          bi[k] += wr[j] * ci[j][k] + wi[j] * cr[j][k];
+        }
+      }
+      rows_solve<MP, NS>(S, r, lr, li, rd, lmr, lmi);  // Lambda = Q^{-1} W-bar
+      // c again (C-bar overwrote it), then X = Lambda^H HV
+      rows_inner<MP, NS>(wr, wi, hvr, hvi, cr, ci);
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        float ar = lmr[k], ai = lmi[k];
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {  // - Lambda[r][j] c_jk
+          ar -= lmr[j] * cr[j][k] - lmi[j] * ci[j][k];
+          ai -= lmr[j] * ci[j][k] + lmi[j] * cr[j][k];
+        }
+        br[k] += ar;
+        bi[k] += ai;
+      }
+      rows_inner<MP, NS>(lmr, lmi, hvr, hvi, cr, ci);  // X_jk = lambda_j^H hv_k
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {  // - W[r][j] X_jk
+          br[k] -= wr[j] * cr[j][k] - wi[j] * ci[j][k];
+          bi[k] -= wr[j] * ci[j][k] + wi[j] * cr[j][k];
+        }
       }
     }
   }
