@@ -677,6 +677,10 @@ __global__ void __launch_bounds__(256) k_sinr_bwd_reduce(const DevChan* __restri
   // chunk of q (rows q >= p_g are written as zero)
   constexpr int QC = 8;
   const int nqc = (ch.p + QC - 1) / QC;
+  // (with FP32 elements, an even p and the C rows 16-byte aligned, the C entries are read two
+  // per 16-byte load)
+  const bool c_pairs =
+      sizeof(E) == 8 && (ch.p % 2) == 0 && (reinterpret_cast<uintptr_t>(Cg) & 15) == 0;
   for (int o = threadIdx.x; o < nqc * mn; o += blockDim.x) {
     const int qc = o / mn, e = o - qc * mn;
     Cx<R> acc[QC];
@@ -685,34 +689,71 @@ __global__ void __launch_bounds__(256) k_sinr_bwd_reduce(const DevChan* __restri
     for (int i = 0; i < sz; ++i) {
       const Cx<R> h = ldc<R>(gH + (int64_t)i * mn + e);
       const E* Ci = Cg + (int64_t)i * ch.p + qc * QC;
+      if (c_pairs) {
 #pragma unroll
-      for (int j = 0; j < QC; ++j)
-        if (qc * QC + j < pg) cfmac(acc[j], ldc<R>(Ci + j), h);
+        for (int j = 0; j < QC; j += 2) {
+          if (qc * QC + j < pg) {
+            const float4 cv = *reinterpret_cast<const float4*>(Ci + j);
+            cfmac(acc[j], Cx<R>{R(cv.x), R(cv.y)}, h);
+            if (qc * QC + j + 1 < pg) cfmac(acc[j + 1], Cx<R>{R(cv.z), R(cv.w)}, h);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < QC; ++j)
+          if (qc * QC + j < pg) cfmac(acc[j], ldc<R>(Ci + j), h);
+      }
     }
 #pragma unroll
     for (int j = 0; j < QC; ++j)
       if (qc * QC + j < ch.p) gGg[(int64_t)(qc * QC + j) * mn + e] = Elem<E>::make(acc[j].re, acc[j].im);
   }
-  // dl/dC: 16 lanes per (s, q) split the m n entries and reduce by shuffles; the 16 lanes of an
-  // output are aligned and run the same passes
+  // dl/dC: 16 lanes per 2 x 2 tile of (s, q) split the m n entries and reduce by shuffles (each
+  // loaded entry of dl/dHt and of a core serves two outputs); the 16 lanes of a tile are aligned
+  // and run the same passes
   const int l16 = threadIdx.x % 16;
-  for (int o = threadIdx.x / 16; o < sz * ch.p; o += blockDim.x / 16) {
-    const int i = o / ch.p, q = o % ch.p;
-    R ar = 0, ai = 0;
-    if (q < pg) {
-#pragma unroll 8
-      for (int e = l16; e < mn; e += 16) {
-        const E g = Gg[(int64_t)q * mn + e], h = gH[(int64_t)i * mn + e];
-        ar += g.x * h.x + g.y * h.y;  // conj(g) h
-        ai += g.x * h.y - g.y * h.x;
-      }
+  const int ti = (sz + 1) / 2, tq = (ch.p + 1) / 2;
+  for (int o = threadIdx.x / 16; o < ti * tq; o += blockDim.x / 16) {
+    const int i0 = 2 * (o / tq), q0 = 2 * (o % tq);
+    const bool i1 = i0 + 1 < sz, g0 = q0 < pg, g1 = q0 + 1 < pg;
+    R ar[2][2], ai[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) ar[a][b] = ai[a][b] = R(0);
+    const E zero = Elem<E>::make(R(0), R(0));
+#pragma unroll 4
+    for (int e = l16; e < mn; e += 16) {
+      E h[2], g[2];
+      h[0] = gH[(int64_t)i0 * mn + e];
+      h[1] = i1 ? gH[(int64_t)(i0 + 1) * mn + e] : zero;
+      g[0] = g0 ? Gg[(int64_t)q0 * mn + e] : zero;
+      g[1] = g1 ? Gg[(int64_t)(q0 + 1) * mn + e] : zero;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {  // conj(g_b) h_a
+          ar[a][b] += g[b].x * h[a].x + g[b].y * h[a].y;
+          ai[a][b] += g[b].x * h[a].y - g[b].y * h[a].x;
+        }
     }
 #pragma unroll
-    for (int d = 8; d > 0; d >>= 1) {
-      ar += __shfl_xor(ar, d, 64);
-      ai += __shfl_xor(ai, d, 64);
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int d = 8; d > 0; d >>= 1) {
+          ar[a][b] += __shfl_xor(ar[a][b], d, 64);
+          ai[a][b] += __shfl_xor(ai[a][b], d, 64);
+        }
+    if (l16 == 0) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          if (i0 + a < sz && q0 + b < ch.p)
+            gC[ch.c + (int64_t)(s0 + i0 + a) * ch.p + q0 + b] = Elem<E>::make(ar[a][b], ai[a][b]);
     }
-    if (l16 == 0) gC[ch.c + (int64_t)(s0 + i) * ch.p + q] = Elem<E>::make(ar, ai);
   }
 }
 
