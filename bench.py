@@ -84,11 +84,18 @@ def bstep_group_cmacs(nr, nt, gs, m, p):
 
 def sinr_unit_flops(m, n, p, ns, n_snr):
     """Flops of one (subcarrier, SNR) SINR evaluation from the compressed form: Ht (m n p),
-    its Gram (m^2 n / 2) amortised over the SNRs, then per SNR the covariance (m^2 ns / 2),
-    Cholesky (m^3 / 6), two triangular solves (m^2 ns) and the stream products (m ns^2 + m ns).
+    its Gram (m^2 n / 2) amortised over the SNRs, then the MMSE chain.  With ns < m the chain
+    runs in the ns x ns push-through form: M = HV^H HV (m ns^2 / 2) once per subcarrier, and per
+    SNR the Cholesky of M + s2 I (ns^3 / 6) and, per stream, two triangular solves and z = M y
+    (2 ns^2).  With ns = m it is the m x m chain: the covariance (m^2 ns / 2), Cholesky
+    (m^3 / 6), two triangular solves (m^2 ns) and the stream products (m ns^2 + m ns).
     Iterative eigensolver sweeps are excluded."""
     per_sub = m * n * p + m * m * n / 2
-    per_snr = m * m * ns / 2 + m ** 3 / 6 + m * m * ns + m * ns * ns + m * ns
+    if ns < m:
+        per_sub += m * ns * ns / 2
+        per_snr = ns ** 3 / 6 + 2 * ns ** 3
+    else:
+        per_snr = m * m * ns / 2 + m ** 3 / 6 + m * m * ns + m * ns * ns + m * ns
     return CMAC * (per_sub / n_snr + per_snr)
 
 
