@@ -168,7 +168,10 @@ gt_status gt_tucker_reconstruct(const gt_plan* plan, const void* A, const void* 
 /* Per-subcarrier SINR from the compressed form (Section 3.3): Ht_s from (C, G); SVD precoder
  * (equation "precoding matrix"); covariance, MMSE filter and per-stream SINR (equations
  * "covariance matrix", "MMSE receive filter", "s_r^ij", "SINR formula") on the m x m
- * compressed covariance.  sigma2: host array of n_snr noise variances (1 <= n_snr <= 16).
+ * compressed covariance; with Ns < m the FP32 row kernels form the same filter through the
+ * push-through identity W = HV (HV^H HV + sigma2 I_Ns)^{-1}, an Ns x Ns Cholesky solve.
+ * sigma2: host array of n_snr noise variances, each > 0 and finite (1 <= n_snr <= 16); any
+ * other value is GT_ERR_ARG before a launch.
  * Output layout as above: float32 on a GT_C64 plan, float64 on a GT_C128 plan. */
 gt_status gt_sinr_eval(const gt_plan* plan, const void* C, const void* G, const float* sigma2,
                        int32_t n_snr, void* sinr, int32_t* dev_status, void* ws, size_t ws_bytes,

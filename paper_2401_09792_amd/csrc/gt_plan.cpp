@@ -888,7 +888,7 @@ gt_status gt_tucker_reconstruct(const gt_plan* plan, const void* A, const void* 
 static gt_status check_snr(const float* sigma2, int32_t n_snr) {
   if (!sigma2 || n_snr < 1 || n_snr > kMaxSnr) return GT_ERR_ARG;
   for (int k = 0; k < n_snr; ++k)
-    if (!(sigma2[k] >= 0.f) || sigma2[k] > 3e38f) return GT_ERR_ARG;
+    if (!(sigma2[k] > 0.f) || sigma2[k] > 3e38f) return GT_ERR_ARG;
   return GT_OK;
 }
 

@@ -116,6 +116,9 @@ def test_calls_reject_bad_workspace_without_launching(lib):
     assert lib.gt_sinr_eval(h, dummy, dummy, s2, 0, dummy, None, dummy, wsb.value, None) == 1
     neg = (C.c_float * 1)(-1.0)
     assert lib.gt_sinr_eval(h, dummy, dummy, neg, 1, dummy, None, dummy, wsb.value, None) == 1
+    # the MMSE filter needs a positive noise variance (the covariance is singular without it)
+    zero = (C.c_float * 1)(0.0)
+    assert lib.gt_sinr_eval(h, dummy, dummy, zero, 1, dummy, None, dummy, wsb.value, None) == 1
     assert lib.gt_tucker_fit_backward(h) == 5
     # the coefficient-vector combinations check the workspace, the pointers and n_pts first
     assert lib.gt_combine_full(h, dummy, dummy, 4, dummy, None, 0, None) == 4
