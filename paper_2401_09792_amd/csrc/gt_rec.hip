@@ -85,30 +85,53 @@ __global__ void __launch_bounds__(256) k_reconstruct(const DevChan* __restrict__
 
 // Ht only (no Xhat): one block per group; a thread owns entry e of Ht_s for SC consecutive
 // subcarriers, so each entry of G_g is read once per chunk of subcarriers rather than once per
-// subcarrier.  The sum over q runs in the same order as in stage_ht.
+// subcarrier.  The group's C rows are staged in LDS (every thread of a chunk reads the same
+// entry), and the cores are read four q at a time with their loads issued before the products.
+// The sum over q runs in the same order as in stage_ht.
 __global__ void __launch_bounds__(256) k_reconstruct_ht(const DevChan* __restrict__ chans,
                                                         const GroupItem* __restrict__ items,
                                                         const float2* __restrict__ C,
                                                         const float2* __restrict__ G, float2* Ht) {
+  __shared__ float2 cs[kMaxGroup * kMaxGroup];
   const GroupItem it = items[blockIdx.x];
   const DevChan& ch = chans[it.ch];
   const int s0 = it.g * ch.gs;
   const int sz = min(ch.gs, ch.nsc - s0);
-  const int pg = min(ch.p, sz);
+  const int p = ch.p, pg = min(p, sz);
   const int mn = ch.m * ch.n;
-  const float2* Gg = G + ch.g + (int64_t)it.g * ch.p * mn;
-  constexpr int SC = 8;
+  const float2* Gg = G + ch.g + (int64_t)it.g * p * mn;
+  for (int e = threadIdx.x; e < sz * p; e += blockDim.x) cs[e] = C[ch.c + (int64_t)s0 * p + e];
+  __syncthreads();
+  constexpr int SC = 6, QU = 4;
   const int nch = (sz + SC - 1) / SC;
   for (int o = threadIdx.x; o < nch * mn; o += blockDim.x) {
     const int sc = o / mn, e = o - sc * mn;
+    const float2* cr = cs + sc * SC * p;  // C row of this chunk's first subcarrier
     Cx<float> acc[SC];
 #pragma unroll
     for (int j = 0; j < SC; ++j) acc[j] = Cx<float>{0.f, 0.f};
-    for (int q = 0; q < pg; ++q) {
+    int q = 0;
+    for (; q + QU <= pg; q += QU) {
+      Cx<float> gv[QU];
+#pragma unroll
+      for (int u = 0; u < QU; ++u) gv[u] = ld(Gg + (int64_t)(q + u) * mn + e);
+#pragma unroll
+      for (int u = 0; u < QU; ++u)
+#pragma unroll
+        for (int j = 0; j < SC; ++j)
+          if (sc * SC + j < sz) {
+            const float2 cv = cr[j * p + q + u];
+            cfma(acc[j], Cx<float>{cv.x, cv.y}, gv[u]);
+          }
+    }
+    for (; q < pg; ++q) {
       const Cx<float> gv = ld(Gg + (int64_t)q * mn + e);
 #pragma unroll
       for (int j = 0; j < SC; ++j)
-        if (sc * SC + j < sz) cfma(acc[j], ld(C + ch.c + (int64_t)(s0 + sc * SC + j) * ch.p + q), gv);
+        if (sc * SC + j < sz) {
+          const float2 cv = cr[j * p + q];
+          cfma(acc[j], Cx<float>{cv.x, cv.y}, gv);
+        }
     }
 #pragma unroll
     for (int j = 0; j < SC; ++j)
