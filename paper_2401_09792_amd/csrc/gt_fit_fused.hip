@@ -620,7 +620,20 @@ __global__ void __launch_bounds__(256) k_fused_z(const DevChan* __restrict__ cha
       Cx<float> z[QC];
 #pragma unroll
       for (int j = 0; j < QC; ++j) z[j] = Cx<float>{0.f, 0.f};
-      for (int s = 0; s < sz; ++s) {
+      // the T entries of four subcarriers are loaded before their products
+      constexpr int SU = 4;
+      int s = 0;
+      for (; s + SU <= sz; s += SU) {
+        Cx<float> tv[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) tv[u] = ld(Tg + (s + u) * nrn + e);
+#pragma unroll
+        for (int u = 0; u < SU; ++u)
+#pragma unroll
+          for (int j = 0; j < QC; ++j)
+            if (qc * QC + j < pg) cfmac(z[j], ld(Cs + (s + u) * p + qc * QC + j), tv[u]);
+      }
+      for (; s < sz; ++s) {
         const Cx<float> tv = ld(Tg + s * nrn + e);
 #pragma unroll
         for (int j = 0; j < QC; ++j)
@@ -654,14 +667,39 @@ __global__ void __launch_bounds__(256) k_fused_z(const DevChan* __restrict__ cha
     }
   }
   if (do_core) {
+    // a thread owns entry e of G_g[q] for QC consecutive q (each Yh entry is read once per
+    // chunk of q) and loads the Yh entries of four subcarriers before their products; rows
+    // q >= p_g are written as zero
     const int mn = m * n;
     const float2* Yg = wsp2(ws, ch.w_Yh) + (int64_t)s0 * mn;
-    for (int o = tid; o < p * mn; o += 256) {
-      const int q = o / mn, e = o % mn;
-      Cx<float> acc{0.f, 0.f};
-      if (q < pg)
-        for (int s = 0; s < sz; ++s) cfmac(acc, ld(Cs + s * p + q), ld(Yg + s * mn + e));
-      G[ch.g + (int64_t)it.g * p * mn + o] = make_float2(acc.re, acc.im);
+    float2* Gg = G + ch.g + (int64_t)it.g * p * mn;
+    constexpr int QC = 6, SU = 4;
+    const int nqc = (p + QC - 1) / QC;
+    for (int o = tid; o < nqc * mn; o += 256) {
+      const int qc = o / mn, e = o - qc * mn;
+      Cx<float> acc[QC];
+#pragma unroll
+      for (int j = 0; j < QC; ++j) acc[j] = Cx<float>{0.f, 0.f};
+      int s = 0;
+      for (; s + SU <= sz; s += SU) {
+        Cx<float> yv[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) yv[u] = ld(Yg + (s + u) * mn + e);
+#pragma unroll
+        for (int u = 0; u < SU; ++u)
+#pragma unroll
+          for (int j = 0; j < QC; ++j)
+            if (qc * QC + j < pg) cfmac(acc[j], ld(Cs + (s + u) * p + qc * QC + j), yv[u]);
+      }
+      for (; s < sz; ++s) {
+        const Cx<float> yv = ld(Yg + s * mn + e);
+#pragma unroll
+        for (int j = 0; j < QC; ++j)
+          if (qc * QC + j < pg) cfmac(acc[j], ld(Cs + s * p + qc * QC + j), yv);
+      }
+#pragma unroll
+      for (int j = 0; j < QC; ++j)
+        if (qc * QC + j < p) Gg[(int64_t)(qc * QC + j) * mn + e] = make_float2(acc[j].re, acc[j].im);
     }
   }
 }
