@@ -116,10 +116,23 @@ __global__ void __launch_bounds__(512) k_init_group_lds(const DevChan* __restric
   const float2* Xg = X + ch.x + (int64_t)s0 * slice;
   const int tid = threadIdx.x, l16 = tid % 16;
   double nrm = 0.0;
-  for (int e = tid; e < tot; e += 512) {
-    const float2 v = Xg[e];
-    xs[e] = v;
-    nrm += (double)v.x * v.x + (double)v.y * v.y;
+  // each thread issues up to 12 loads before its LDS stores: one memory latency per pass
+  constexpr int B = 12;
+  for (int e0 = tid; e0 < tot; e0 += B * 512) {
+    float2 v[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int e = e0 + 512 * u;
+      v[u] = e < tot ? Xg[e] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int e = e0 + 512 * u;
+      if (e < tot) {
+        xs[e] = v[u];
+        nrm += (double)v[u].x * v[u].x + (double)v[u].y * v[u].y;
+      }
+    }
   }
   __syncthreads();
   const int n1 = want_s1 ? nr * (nr + 1) / 2 : 0, n3 = gs * (gs + 1) / 2;
