@@ -323,6 +323,35 @@ def test_mmse_identity_any_precoder():
     np.testing.assert_allclose(got, 1.0 / np.real(np.diagonal(E)) - 1.0, rtol=1e-10)
 
 
+def test_push_through_sinr_gradient_against_finite_differences():
+    # with X = (HV^H HV + s2 I)^{-1}, SINR_j = 1 / (s2 X_jj) - 1 (the identity above), so the
+    # gradient of sum_j g_j SINR_j in HV (convention dl = Re sum conj(Gbar) dHV) is
+    # 2 HV sum_j g_j / (s2 X_jj^2) x_j x_j^H, x_j = X e_j: checked by central differences of the
+    # oracle's MMSE chain with the identity precoder (so that H P = HV)
+    rng = np.random.default_rng(23)
+    m, ns, s2 = 6, 3, 0.4
+    HV = crandn(rng, m, ns)
+    g = rng.standard_normal(ns)
+    P = np.eye(ns)
+
+    def loss(h):
+        return float(g @ sinr.mmse_sinr(h, P, s2))
+
+    X = np.linalg.inv(HV.conj().T @ HV + s2 * np.eye(ns))
+    gm = sum(g[j] / (s2 * np.real(X[j, j]) ** 2) * np.outer(X[:, j], X[:, j].conj())
+             for j in range(ns))
+    grad = 2.0 * HV @ gm
+    fd = np.zeros_like(HV)
+    eps = 1e-6
+    for a in range(m):
+        for b in range(ns):
+            for unit in (1.0, 1j):
+                d = np.zeros_like(HV)
+                d[a, b] = eps * unit
+                fd[a, b] += unit * (loss(HV + d) - loss(HV - d)) / (2 * eps)
+    np.testing.assert_allclose(fd, grad, rtol=0, atol=1e-6 * np.abs(grad).max())
+
+
 def test_factor_cancellation_compressed_equals_full():
     # SINR of A Ht B^* with orthonormal A, B equals the SINR of Ht (Section 3.3)
     rng = np.random.default_rng(12)
