@@ -26,6 +26,8 @@
 
 namespace gt {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 struct SnrArgs {
   float s2[kMaxSnr];
   int n;
@@ -640,12 +642,17 @@ __global__ void __launch_bounds__(256) k_sinr_bwd_reduce(const DevChan* __restri
   const E* gH = gHm;
   const E* Gg = Ggm;
   const E* Cg = C + ch.c + (int64_t)s0 * ch.p;  // the group's C rows (stride p)
+  // matrix-core form (FP32, groups of at most 16 subcarriers, p <= 16, m n a multiple of 16):
+  // the staged rows of dl/dHt and of the cores take a stride of m n + 1 so that the 16 rows a
+  // product operand spans fall in distinct LDS banks
+  const bool mf = STAGE && sizeof(E) == 8 && ch.gs <= 16 && ch.p <= 16 && (mn % 16) == 0;
+  const int ld = mf ? mn + 1 : mn;
   if (STAGE) {
     // dl/dHt, the cores and the C rows of the group in LDS (every product below reads them
     // many times)
     E* sH = sm;
-    E* sG = sm + sz * mn;
-    E* sC = sG + pg * mn;
+    E* sG = sm + sz * ld;
+    E* sC = sG + pg * ld;
     // every thread issues its loads of the three arrays (up to B of each) before its LDS
     // stores, so one memory latency covers the copy of a group
     constexpr int B = 8;
@@ -663,8 +670,8 @@ __global__ void __launch_bounds__(256) k_sinr_bwd_reduce(const DevChan* __restri
 #pragma unroll
       for (int u = 0; u < B; ++u) {
         const int e = e0 + u * (int)blockDim.x;
-        if (e < nH) sH[e] = vh[u];
-        if (e < nG) sG[e] = vg[u];
+        if (e < nH) sH[mf ? (e / mn) * ld + e % mn : e] = vh[u];
+        if (e < nG) sG[mf ? (e / mn) * ld + e % mn : e] = vg[u];
         if (e < nC) sC[e] = vc[u];
       }
     }
@@ -672,6 +679,84 @@ __global__ void __launch_bounds__(256) k_sinr_bwd_reduce(const DevChan* __restri
     gH = sH;
     Gg = sG;
     Cg = sC;
+  }
+  if constexpr (sizeof(E) == 8) {
+    if (mf) {
+      // 16 x 16 x 4 FP32 matrix-core products on the real forms, lane l holding operand row
+      // (or column) l % 16 and K index 4 t + l / 16; K runs over (subcarrier or entry, re/im):
+      //   dl/dG[q][e] = sum_s conj(C[s,q]) dHt_s[e]: Re = sum (cr hr + ci hi), Im = sum (cr hi - ci hr)
+      //   dl/dC[s][q] = sum_e conj(G_q[e]) dHt_s[e]: Re = sum (hr gr + hi gi), Im = sum (hi gr - hr gi)
+      const float* sHf = reinterpret_cast<const float*>(gH);
+      const float* sGf = reinterpret_cast<const float*>(Gg);
+      const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, l16 = lane % 16, kq = lane / 16;
+      const int ksteps = (2 * sz + 3) / 4;
+      for (int Et = wave; Et < mn / 16; Et += 4) {
+        const int e = 16 * Et + l16;
+        f32x4 are = {0.f, 0.f, 0.f, 0.f}, aim = {0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < ksteps; ++t) {
+          const int k = 4 * t + kq, sk = k >> 1, part = k & 1;
+          float cr = 0.f, ci = 0.f, hr = 0.f, hi = 0.f;
+          if (sk < sz) {
+            if (l16 < pg) {
+              const E cv = Cg[sk * ch.p + l16];
+              cr = cv.x;
+              ci = cv.y;
+            }
+            hr = sHf[2 * (sk * ld + e)];
+            hi = sHf[2 * (sk * ld + e) + 1];
+          }
+          are = __builtin_amdgcn_mfma_f32_16x16x4f32(part ? ci : cr, part ? hi : hr, are, 0, 0, 0);
+          aim = __builtin_amdgcn_mfma_f32_16x16x4f32(part ? -ci : cr, part ? hr : hi, aim, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int q = 4 * kq + v;
+          if (q < ch.p) gGg[(int64_t)q * mn + e] = Elem<E>::make(are[v], aim[v]);
+        }
+      }
+      // dl/dC: the four waves split the entries, then their 16 x 16 partial tiles are summed
+      f32x4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
+      {
+        const int ew = mn / 4, e0w = wave * ew;  // this wave's entries
+        for (int t = 0; t < ew / 2; ++t) {
+          const int k = 4 * t + kq, e = e0w + (k >> 1), part = k & 1;
+          float hr = 0.f, hi = 0.f, gr = 0.f, gi = 0.f;
+          if (l16 < sz) {
+            hr = sHf[2 * (l16 * ld + e)];
+            hi = sHf[2 * (l16 * ld + e) + 1];
+          }
+          if (l16 < pg) {
+            gr = sGf[2 * (l16 * ld + e)];
+            gi = sGf[2 * (l16 * ld + e) + 1];
+          }
+          cre = __builtin_amdgcn_mfma_f32_16x16x4f32(part ? hi : hr, part ? gi : gr, cre, 0, 0, 0);
+          cim = __builtin_amdgcn_mfma_f32_16x16x4f32(part ? hr : hi, part ? -gi : gr, cim, 0, 0, 0);
+        }
+      }
+      __syncthreads();  // every read of the staged rows is done: the partials reuse that LDS
+      float* red = reinterpret_cast<float*>(sm);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        red[(wave * 4 + v) * 128 + lane] = cre[v];
+        red[(wave * 4 + v) * 128 + 64 + lane] = cim[v];
+      }
+      __syncthreads();
+      if (wave == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          float xr = 0.f, xi = 0.f;
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            xr += red[(w * 4 + v) * 128 + lane];
+            xi += red[(w * 4 + v) * 128 + 64 + lane];
+          }
+          const int si = 4 * kq + v;  // output row (subcarrier), column q = l16
+          if (si < sz && l16 < ch.p)
+            gC[ch.c + (int64_t)(s0 + si) * ch.p + l16] = Elem<E>::make(xr, xi);
+        }
+      }
+      return;
+    }
   }
   // dl/dG: a thread owns entry e for QC consecutive q, so each dl/dHt entry is read once per
   // chunk of q (rows q >= p_g are written as zero)
@@ -892,8 +977,11 @@ gt_status launch_sinr_bwd(const LaunchCtx& L, int64_t total_sc, const float2* C,
 
 template <typename E>
 static gt_status grad_cg_t(const LaunchCtx& L, const E* C, const E* G, E* gC, E* gG) {
-  const size_t sh = sizeof(E) * (((size_t)L.max_gs + L.max_p) * L.max_m * L.max_n +
-                                 (size_t)L.max_gs * L.max_p);
+  // (the staged rows may take a stride of m n + 1, and the matrix-core form reuses at least 8 KB
+  // of the block's LDS for the four waves' partial dl/dC tiles)
+  const size_t sh = std::max<size_t>(
+      8192, sizeof(E) * (((size_t)L.max_gs + L.max_p) * ((size_t)L.max_m * L.max_n + 1) +
+                         (size_t)L.max_gs * L.max_p));
   if (sh <= 64 * 1024) {
     prof_begin("k_sinr_bwd_reduce", L.stream);
     hipLaunchKernelGGL((k_sinr_bwd_reduce<true, E>), dim3(L.total_groups), dim3(256), sh, L.stream,
